@@ -1,0 +1,296 @@
+"""Python face of the FP64 CPU oracle (``omnigs_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline leg
+of the benchmark may call this module; the product path never does.  It shares
+no code with the HIP implementation.  Inputs are the same float32 arrays the
+GPU path receives, widened exactly to float64.
+
+What each function computes, with the paper passages it follows, is stated in
+``omnigs_oracle.c``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "omnigs_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libomnigs_oracle.so")
+
+# margins used to flag near-threshold discrete decisions (see DESIGN notes):
+# relative for alpha and T decisions and for depth ties, absolute pixels for
+# the rect bounds.
+DEFAULT_FLAGS = dict(flag_rel_alpha=1e-5, flag_rel_T=1e-4, flag_rel_depth=2.0**-21, flag_abs_rect=1e-6)
+
+DEFAULT_SETTINGS = dict(alpha_min=1.0 / 255.0, alpha_max=0.99, T_min=1e-4, dilation=0.3, near_plane=0.2,
+                        bg=(0.0, 0.0, 0.0))
+
+REC = 48  # doubles per projection record
+REC_FIELDS = dict(visible=0, t=slice(1, 4), t_r=4, lon=5, lat=6, px=7, py=8, J=slice(9, 15), cov2d=slice(15, 18),
+                  conic=slice(18, 21), ex=21, ey=22, xs=23, xe=24, ys=25, ye=26, full_x=27, tx0=28, ntx=29, ty0=30,
+                  nty=31, ntiles=32, rgb=slice(33, 36), clamp=slice(36, 39), flag=39, dir=slice(40, 43), det=43)
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (FP64, no fast-math, no FP contraction)."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
+               "-fno-fast-math", "-Wall", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Scene(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64),
+        ("means", ctypes.c_void_p),
+        ("scales", ctypes.c_void_p),
+        ("quats", ctypes.c_void_p),
+        ("opac", ctypes.c_void_p),
+        ("sh", ctypes.c_void_p),
+        ("sh_degree", ctypes.c_int32),
+        ("sh_coeffs", ctypes.c_int32),
+        ("width", ctypes.c_int32),
+        ("height", ctypes.c_int32),
+        ("R", ctypes.c_double * 9),
+        ("t", ctypes.c_double * 3),
+        ("alpha_min", ctypes.c_double),
+        ("alpha_max", ctypes.c_double),
+        ("T_min", ctypes.c_double),
+        ("dilation", ctypes.c_double),
+        ("near_plane", ctypes.c_double),
+        ("bg", ctypes.c_double * 3),
+        ("flag_rel_alpha", ctypes.c_double),
+        ("flag_rel_T", ctypes.c_double),
+        ("flag_rel_depth", ctypes.c_double),
+        ("flag_abs_rect", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        _lib = ctypes.CDLL(build())
+        P = ctypes.POINTER
+        _lib.orc_project.argtypes = [P(_Scene), ctypes.c_void_p]
+        _lib.orc_project.restype = ctypes.c_int
+        _lib.orc_tile_lists.argtypes = [P(_Scene), ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        _lib.orc_tile_lists.restype = ctypes.c_int64
+        _lib.orc_render.argtypes = [P(_Scene)] + [ctypes.c_void_p] * 5
+        _lib.orc_render.restype = ctypes.c_int
+        _lib.orc_l1_tiles.argtypes = [P(_Scene), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        _lib.orc_l1_tiles.restype = ctypes.c_int
+        _lib.orc_backward.argtypes = [P(_Scene)] + [ctypes.c_void_p] * 14
+        _lib.orc_backward.restype = ctypes.c_int
+        _lib.orc_l1.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        _lib.orc_l1.restype = ctypes.c_double
+        _lib.orc_sh_eval.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        _lib.orc_sh_eval.restype = None
+        _lib.orc_num_threads.argtypes = []
+        _lib.orc_num_threads.restype = ctypes.c_int
+    return _lib
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+class Scene:
+    """A Gaussian set, a camera and the raster settings, held in float64.
+
+    ``gaussians``: dict with means [N,3], scales [N,3] (activated), quats
+    [N,4] (w,x,y,z), opacities [N] (activated), sh [N,K,3], sh_degree.
+    ``camera``: dict with R [3,3] (world -> camera rotation), t [3], width,
+    height.
+    """
+
+    def __init__(self, gaussians, camera, settings=None, flags=None):
+        st = dict(DEFAULT_SETTINGS)
+        st.update(settings or {})
+        fl = dict(DEFAULT_FLAGS)
+        fl.update(flags or {})
+        self.means = _f64(gaussians["means"]).reshape(-1, 3)
+        self.n = self.means.shape[0]
+        self.scales = _f64(gaussians["scales"]).reshape(self.n, 3)
+        self.quats = _f64(gaussians["quats"]).reshape(self.n, 4)
+        self.opac = _f64(gaussians["opacities"]).reshape(self.n)
+        sh = _f64(gaussians["sh"])
+        self.sh = sh.reshape(self.n, -1, 3)
+        self.sh_coeffs = self.sh.shape[1]
+        self.sh_degree = int(gaussians["sh_degree"])
+        self.width = int(camera["width"])
+        self.height = int(camera["height"])
+        self.R = _f64(camera["R"]).reshape(3, 3)
+        self.t = _f64(camera["t"]).reshape(3)
+        self.settings = st
+        self.flags = fl
+
+    @property
+    def tiles_x(self):
+        return self.width // 16
+
+    @property
+    def tiles_y(self):
+        return (self.height + 15) // 16
+
+    def _struct(self):
+        s = _Scene()
+        s.n = self.n
+        s.means = self.means.ctypes.data
+        s.scales = self.scales.ctypes.data
+        s.quats = self.quats.ctypes.data
+        s.opac = self.opac.ctypes.data
+        s.sh = self.sh.ctypes.data
+        s.sh_degree = self.sh_degree
+        s.sh_coeffs = self.sh_coeffs
+        s.width = self.width
+        s.height = self.height
+        for k in range(9):
+            s.R[k] = float(self.R.reshape(-1)[k])
+        for k in range(3):
+            s.t[k] = float(self.t[k])
+        st = self.settings
+        s.alpha_min = st["alpha_min"]
+        s.alpha_max = st["alpha_max"]
+        s.T_min = st["T_min"]
+        s.dilation = st["dilation"]
+        s.near_plane = st["near_plane"]
+        for k in range(3):
+            s.bg[k] = float(st["bg"][k])
+        for k, v in self.flags.items():
+            setattr(s, k, float(v))
+        return s
+
+    def with_params(self, **kw):
+        """Copy with some parameter arrays replaced (float64)."""
+        g = dict(means=self.means, scales=self.scales, quats=self.quats, opacities=self.opac, sh=self.sh,
+                 sh_degree=self.sh_degree)
+        g.update(kw)
+        cam = dict(R=self.R, t=self.t, width=self.width, height=self.height)
+        return Scene(g, cam, self.settings, self.flags)
+
+    def with_camera(self, R=None, t=None):
+        g = dict(means=self.means, scales=self.scales, quats=self.quats, opacities=self.opac, sh=self.sh,
+                 sh_degree=self.sh_degree)
+        cam = dict(R=self.R if R is None else R, t=self.t if t is None else t, width=self.width,
+                   height=self.height)
+        return Scene(g, cam, self.settings, self.flags)
+
+
+def project(scene: Scene) -> np.ndarray:
+    """Per-Gaussian projection records, [N, REC] float64 (fields: REC_FIELDS)."""
+    lib = _load()
+    rec = np.zeros((scene.n, REC), dtype=np.float64)
+    s = scene._struct()
+    if lib.orc_project(ctypes.byref(s), rec.ctypes.data) != 0:
+        raise ValueError("oracle: invalid scene")
+    return rec
+
+
+def tile_lists(scene: Scene):
+    """Sorted instances: (tile_id int32 [M], gaussian_id int32 [M], t_r float64 [M])."""
+    lib = _load()
+    s = scene._struct()
+    m = lib.orc_tile_lists(ctypes.byref(s), 0, None, None, None)
+    if m < 0:
+        raise ValueError("oracle: invalid scene")
+    tile = np.zeros(max(m, 1), dtype=np.int32)
+    gid = np.zeros(max(m, 1), dtype=np.int32)
+    tr = np.zeros(max(m, 1), dtype=np.float64)
+    m2 = lib.orc_tile_lists(ctypes.byref(s), m, tile.ctypes.data, gid.ctypes.data, tr.ctypes.data)
+    assert m2 == m
+    return tile[:m], gid[:m], tr[:m]
+
+
+def render(scene: Scene, alt: bool = True):
+    """Forward render: dict(image [3,H,W], final_T [H,W], n_contrib [H,W],
+    n_flags [H,W], alt [3,H,W] or None)."""
+    lib = _load()
+    H, W = scene.height, scene.width
+    image = np.zeros((3, H, W))
+    T = np.zeros((H, W))
+    nc = np.zeros((H, W), dtype=np.int32)
+    nf = np.zeros((H, W), dtype=np.int32)
+    altimg = np.zeros((3, H, W)) if alt else None
+    s = scene._struct()
+    rc = lib.orc_render(ctypes.byref(s), image.ctypes.data, T.ctypes.data, nc.ctypes.data, nf.ctypes.data,
+                        altimg.ctypes.data if alt else None)
+    if rc != 0:
+        raise ValueError("oracle: invalid scene")
+    return dict(image=image, final_T=T, n_contrib=nc, n_flags=nf, alt=altimg)
+
+
+def l1(image, target):
+    """L1 term of Eq. 17 (mean over all entries) and its gradient."""
+    lib = _load()
+    im = _f64(image)
+    tg = _f64(target)
+    g = np.zeros_like(im)
+    loss = lib.orc_l1(im.size, im.ctypes.data, tg.ctypes.data, g.ctypes.data)
+    return loss, g
+
+
+def l1_tiles(scene: Scene, target, tile_mask):
+    """(sum over the masked tiles' pixels of |C - target| / (3HW), decision hash)."""
+    lib = _load()
+    tg = _f64(target)
+    mask = np.ascontiguousarray(np.asarray(tile_mask, dtype=np.uint8).reshape(-1))
+    assert mask.size == scene.tiles_x * scene.tiles_y
+    loss = ctypes.c_double(0.0)
+    sig = ctypes.c_uint64(0)
+    s = scene._struct()
+    if lib.orc_l1_tiles(ctypes.byref(s), tg.ctypes.data, mask.ctypes.data, ctypes.byref(loss),
+                        ctypes.byref(sig)) != 0:
+        raise ValueError("oracle: invalid scene")
+    return loss.value, sig.value
+
+
+def backward(scene: Scene, dL_dimage, with_abs: bool = True):
+    """Analytic gradient of <dL_dimage, render(scene)> w.r.t. the parameters.
+
+    Returns dict(means, scales, quats, opacities, sh, screen, acc) and, with
+    ``with_abs``, the same keys prefixed ``abs_``: sums of |per-pixel
+    contributions| pushed through |chain| (the scale FP32 sums are judged
+    against).
+    """
+    lib = _load()
+    n, K = scene.n, scene.sh_coeffs
+    g = _f64(dL_dimage).reshape(3, scene.height, scene.width)
+    out = dict(means=np.zeros((n, 3)), scales=np.zeros((n, 3)), quats=np.zeros((n, 4)), opacities=np.zeros(n),
+               sh=np.zeros((n, K, 3)), screen=np.zeros((n, 2)), acc=np.zeros((n, 9)))
+    names = ["means", "scales", "quats", "opacities", "sh", "screen"]
+    if with_abs:
+        for k in names:
+            out["abs_" + k] = np.zeros_like(out[k])
+    s = scene._struct()
+    args = [out[k].ctypes.data for k in names] + [out["acc"].ctypes.data]
+    args += [out["abs_" + k].ctypes.data for k in names] if with_abs else [None] * 6
+    if lib.orc_backward(ctypes.byref(s), g.ctypes.data, *args) != 0:
+        raise ValueError("oracle: invalid scene")
+    return out
+
+
+def sh_eval(degree: int, direction):
+    """Real SH basis values Y[(D+1)^2] and their derivatives dY/d(x,y,z)."""
+    lib = _load()
+    d = _f64(direction).reshape(3)
+    K = (degree + 1) ** 2
+    Y = np.zeros(K)
+    dY = np.zeros((K, 3))
+    lib.orc_sh_eval(degree, d.ctypes.data, Y.ctypes.data, dY.ctypes.data)
+    return Y, dY
+
+
+def num_threads() -> int:
+    return int(_load().orc_num_threads())
