@@ -1,0 +1,208 @@
+/*
+ * omnigs.h -- C ABI of libomnigs.so, the MI355X (gfx950) rasterizer that
+ * splats 3D Gaussians onto an equirectangular (ERP) image through the
+ * spherical camera model of OmniGS (arXiv 2404.03202, Sec. 3), and its
+ * backward pass.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Pointers documented "device" are HIP device addresses; "host" are
+ *   ordinary CPU pointers read during the call only.
+ * - `stream` is a hipStream_t passed as void*; NULL means the legacy default
+ *   stream.  All GPU work is enqueued on it.  Calls do not synchronise the
+ *   stream except where stated (the instance-count readback of
+ *   omnigs_forward).
+ * - The caller owns every buffer.  Device memory the library needs beyond
+ *   the caller's inputs and outputs is obtained through the caller's
+ *   allocator callback and never freed by the library:
+ *     OMNIGS_MEM_SCRATCH allocations are dead once every kernel the call
+ *       enqueued has run (a stream-ordered caching allocator may recycle
+ *       them as soon as the call returns);
+ *     OMNIGS_MEM_STATE allocations back an omnigs_state and must stay alive
+ *       until the last omnigs_backward that uses that state has run.
+ * - Errors: every entry point returns an omnigs_status.  On a non-OK status
+ *   nothing valid was produced, and omnigs_last_error() returns a
+ *   thread-local message.  No exception crosses the ABI.
+ * - Image layout is planar [3][H][W] float32, row-major, pixel (x, y) sampled
+ *   at the continuous ERP coordinate (x + 1/2, y + 1/2) (Eq. 5).
+ * - Requirements: width % 16 == 0 (16x16 tiles that wrap across the
+ *   longitude seam), width <= 65520 and height >= 1.
+ */
+#ifndef OMNIGS_H
+#define OMNIGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    OMNIGS_OK = 0,
+    OMNIGS_ERR_INVALID = 1,  /* bad argument (null pointer, size, degree, non-finite camera, ...) */
+    OMNIGS_ERR_ALLOC = 2,    /* the allocator callback returned NULL */
+    OMNIGS_ERR_HIP = 3,      /* a HIP runtime call or kernel launch failed */
+    OMNIGS_ERR_CAPACITY = 4  /* more tile instances than the caller's capacity */
+} omnigs_status;
+
+enum { OMNIGS_MEM_SCRATCH = 0, OMNIGS_MEM_STATE = 1 };
+
+/* Device allocator: returns `bytes` of device memory aligned to 256 bytes,
+ * or NULL.  `kind` is OMNIGS_MEM_SCRATCH or OMNIGS_MEM_STATE. */
+typedef void *(*omnigs_alloc_fn)(void *user, size_t bytes, int32_t kind);
+typedef struct {
+    omnigs_alloc_fn alloc;
+    void *user;
+} omnigs_allocator;
+
+/* The Gaussian set (Sec. 3.1): centre m, scale S, rotation q, opacity o and
+ * SH colour coefficients.  All device, float32, densely packed. */
+typedef struct {
+    const float *means;     /* [n][3] world positions m                              */
+    const float *scales;    /* [n][3] activated (positive) scales S                  */
+    const float *quats;     /* [n][4] rotation q = (w, x, y, z); normalised inside   */
+    const float *opacities; /* [n]    activated opacity o in (0, 1)                  */
+    const float *sh;        /* [n][sh_coeffs][3] real SH, index l*l+l+m, RGB last     */
+    int64_t n;              /* 0 <= n < 2^31                                          */
+    int32_t sh_degree;      /* active degree D, 0..3                                  */
+    int32_t sh_coeffs;      /* stored coefficients per Gaussian: (D+1)^2 <= it <= 16 */
+} omnigs_gaussians;
+
+/* Camera pose T_cw of Eq. 1 (host, float64): t = R_cw m + t_cw, camera axes
+ * +X right, +Y down, +Z forward (Fig. 2); the X-Z plane is the equator. */
+typedef struct {
+    double R_cw[9]; /* row-major rotation W of Eq. 1 */
+    double t_cw[3];
+    int32_t width;  /* ERP image W, multiple of 16 */
+    int32_t height; /* ERP image H */
+} omnigs_camera;
+
+/* Rasterisation settings (host).  The paper fixes the stop threshold (Sec.
+ * 3.3, "alpha = 0.9999", i.e. T_min = 1e-4); the others are this library's
+ * readings, with the defaults given by omnigs_default_settings():
+ *   alpha_min 1/255, alpha_max 0.99, T_min 1e-4, dilation 0.3 px^2,
+ *   near_plane 0.2, bg = 0. */
+typedef struct {
+    double alpha_min;  /* instances with alpha < alpha_min are skipped                 */
+    double alpha_max;  /* alpha is clamped to alpha_max                                  */
+    double T_min;      /* stop before an instance that would bring T below T_min        */
+    double dilation;   /* added to the diagonal of the 2D covariance (px^2)             */
+    double near_plane; /* Gaussians with t_r <= near_plane are culled                    */
+    double bg[3];      /* background colour seen through the final transmittance       */
+} omnigs_settings;
+
+/* Per-pixel outputs of the forward pass (device, caller-allocated). */
+typedef struct {
+    float *image;       /* [3][H][W]  C + T_final * bg  (Eq. 6)                   */
+    float *final_T;     /* [H][W]     transmittance after the last blended one   */
+    int32_t *n_contrib; /* [H][W]     1 + tile-list position of the last blended */
+} omnigs_image_out;
+
+/* Saved forward state (filled by omnigs_forward, read by omnigs_backward).
+ * The buffers are OMNIGS_MEM_STATE allocations from the caller's allocator;
+ * the typed views below point into them. */
+typedef struct {
+    int64_t n;           /* Gaussians                                    */
+    int64_t n_instances; /* M: (Gaussian, covered tile) instances         */
+    int32_t width, height, tiles_x, tiles_y;
+    const void *records;         /* [n] 48-byte blend records (opaque)              */
+    const uint32_t *n_tiles;     /* [n] tiles covered per Gaussian, 0 when culled    */
+    const uint32_t *depth_order; /* [n] Gaussian ids sorted by (t_r, id), culled last */
+    const uint32_t *inst_tile;   /* [M] tile id of each sorted instance             */
+    const uint32_t *inst_gauss;  /* [M] Gaussian id of each sorted instance         */
+    const uint32_t *tile_range;  /* [tiles][2] [start, end) into the sorted list    */
+} omnigs_state;
+
+/* Parameter gradients (device, caller-allocated, overwritten). */
+typedef struct {
+    float *dmeans;     /* [n][3]                                                  */
+    float *dscales;    /* [n][3]  w.r.t. the activated scales                     */
+    float *dquats;     /* [n][4]  w.r.t. the raw quaternion                       */
+    float *dopacities; /* [n]     w.r.t. the activated opacity                    */
+    float *dsh;        /* [n][sh_coeffs][3]; coefficients above degree D are 0    */
+    float *dscreen;    /* [n][2]  dL/ds, s the uniform screen coordinate (Eq. 4) */
+} omnigs_grads;
+
+/* Default settings (see omnigs_settings). */
+omnigs_settings omnigs_default_settings(void);
+
+/* Forward render of the ERP image (Sec. 3.3).
+ * Stages, each a HIP kernel on `stream`:
+ *   1. project: Eq. 1 (world -> camera), Eq. 3-5 (ERP pixel), Eq. 9-16
+ *      (2D covariance through the spherical Jacobian), SH colour, and the
+ *      radius of influence (the box of the alpha = alpha_min iso-ellipse),
+ *      with its tile span wrapped across the longitude seam;
+ *   2. depth sort of the Gaussians by t_r (Sec. 3.3: ERP sorts by distance,
+ *      not t_z), then one instance per (Gaussian, covered tile) emitted in
+ *      depth order and stably sorted by tile: each tile's list is in
+ *      (t_r, id) order; per-tile [start, end) ranges;
+ *   3. front-to-back alpha blending of Eq. 6-8, one 16x16 tile per
+ *      workgroup, stopping per pixel before T would drop below T_min.
+ * The instance count M is read back to size the instance buffers: this is
+ * the only host synchronisation of the call.
+ * Inputs: g (device arrays), cam and s (host).  Outputs: out (device,
+ * caller-allocated) and *state (host struct; device buffers from `alloc`).
+ * Returns OMNIGS_ERR_INVALID for null pointers, n < 0, sh_degree outside
+ * 0..3, sh_coeffs out of range, width % 16 != 0, height < 1 or a non-finite
+ * camera; OMNIGS_ERR_ALLOC if `alloc` fails; OMNIGS_ERR_HIP on a runtime
+ * failure. */
+omnigs_status omnigs_forward(const omnigs_gaussians *g, const omnigs_camera *cam, const omnigs_settings *s,
+                             omnigs_allocator alloc, omnigs_image_out *out, omnigs_state *state, void *stream);
+
+/* Backward pass of the render (Sec. 3.4, Eq. 18-20) for an image-space
+ * cotangent dL_dimage [3][H][W] (device).  Re-walks each pixel's tile list
+ * back to front from the saved final T and n_contrib (recomputing alpha and
+ * T rather than reading stored per-pixel lists), accumulates per-Gaussian
+ * dL/dp, dL/dSigma2D^-1, dL/do, dL/dcolour with one atomic per field per
+ * (tile, Gaussian), then chains them per Gaussian through the omnidirectional
+ * terms dSigma2D/dSigma, dJ/dt, dp/ds, ds/dt to means, scales, quaternions,
+ * opacities and SH.  g, cam and s must be those of the forward call that
+ * produced `state` and `fwd`.  Gradients are overwritten.  Zero gradient
+ * flows through the alpha_max clamp and through colour channels clamped at 0.
+ * Scratch (the accumulators) comes from `alloc`.  Errors as omnigs_forward. */
+omnigs_status omnigs_backward(const omnigs_gaussians *g, const omnigs_camera *cam, const omnigs_settings *s,
+                              const omnigs_state *state, const omnigs_image_out *fwd, const float *dL_dimage,
+                              omnigs_grads *grads, omnigs_allocator alloc, void *stream);
+
+/* L1 photometric term of Eq. 17 (lambda = 0): *loss = mean |image - target|
+ * over `count` float32 entries, and dL_dimage = sign(image - target) / count
+ * with sign(0) = 0.  image, target, dL_dimage (may be NULL) and loss are
+ * device pointers; the sum is reduced in a fixed order (deterministic).
+ * Scratch comes from `alloc`. */
+omnigs_status omnigs_l1_loss(const float *image, const float *target, int64_t count, float *dL_dimage, float *loss,
+                             omnigs_allocator alloc, void *stream);
+
+/* Batched forward of `batch` cameras of mixed resolution over one resident
+ * Gaussian set (K1 reads each Gaussian once for all cameras; one instance
+ * sort and one blend launch over the concatenated tile space of all
+ * cameras).  Every image equals the one omnigs_forward renders for that
+ * camera alone, bit for bit.  cams[b] (host) and outs[b] (device buffers)
+ * per camera.  instance_capacity > 0 sizes the instance buffers without the
+ * readback; then, if more instances are needed, the call still runs without
+ * writing out of bounds but *overflow (device int32, may be NULL) is set to 1
+ * and the images are invalid.  instance_capacity == 0 reads the count back
+ * (one host synchronisation).  No backward state is kept. */
+omnigs_status omnigs_forward_batch(const omnigs_gaussians *g, const omnigs_camera *cams, int32_t batch,
+                                   const omnigs_settings *s, omnigs_allocator alloc, omnigs_image_out *outs,
+                                   int64_t instance_capacity, int32_t *overflow, void *stream);
+
+/* Thread-local message describing the last non-OK status of this thread. */
+const char *omnigs_last_error(void);
+
+/* Stage timing.  When enabled, each stage is bracketed with HIP events on
+ * the call's stream and its GPU time is accumulated per stage until
+ * omnigs_profile_read (which synchronises the recorded events, then resets
+ * the accumulators).  Stages: see omnigs_profile_stage_name. */
+omnigs_status omnigs_profile_enable(int32_t on);
+int32_t omnigs_profile_num_stages(void);
+const char *omnigs_profile_stage_name(int32_t stage);
+/* ms[k] = total ms of stage k since the last read, launches[k] = number of
+ * timed launches; arrays of omnigs_profile_num_stages() entries (host). */
+omnigs_status omnigs_profile_read(double *ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OMNIGS_H */

@@ -604,14 +604,17 @@ int64_t orc_tile_lists(const orc_scene *s, int64_t cap, int32_t *tile_out, int32
     return M;
 }
 
-/* Forward render.  image [3][H][W], final_T [H][W], n_contrib [H][W],
+/* Forward render of the tiles set in tile_mask (NULL: all tiles; pixels of
+ * other tiles are left untouched).  image [3][H][W], final_T [H][W], n_contrib [H][W],
  * n_flags [H][W]; alt (may be NULL) receives, for pixels with exactly one
- * flagged decision, the value with that decision inverted (else the value). */
-int orc_render(const orc_scene *s, double *image, double *final_T, int32_t *n_contrib, int32_t *n_flags,
-               double *alt) {
+ * flagged decision, the value with that decision inverted (else the value);
+ * n_grad_flags (may be NULL) also counts alpha_max-clamp near-ties, where
+ * the gradient (not the value) changes. */
+int orc_render(const orc_scene *s, const uint8_t *tile_mask, double *image, double *final_T, int32_t *n_contrib,
+               int32_t *n_flags, double *alt, int32_t *n_grad_flags) {
     if (s->width % ORC_TILE != 0 || s->height < 1) return -1;
     orc_lists L;
-    if (build_lists(s, NULL, &L) != 0) {
+    if (build_lists(s, tile_mask, &L) != 0) {
         lists_free(&L);
         return -1;
     }
@@ -621,12 +624,14 @@ int orc_render(const orc_scene *s, double *image, double *final_T, int32_t *n_co
     for (int64_t p = 0; p < HW; ++p) {
         const int x = (int)(p % Wd), y = (int)(p / Wd);
         const int64_t t = tile_of_pixel(&L, x, y);
+        if (tile_mask && !tile_mask[t]) continue;
         orc_pixel px;
         render_pixel(s, &L, L.tstart[t], L.tend[t], x, y, -1, &px, NULL);
         for (int ch = 0; ch < 3; ++ch) image[ch * HW + p] = px.C[ch];
         final_T[p] = px.T;
         n_contrib[p] = px.n_contrib;
         n_flags[p] = px.n_flags;
+        if (n_grad_flags) n_grad_flags[p] = px.n_grad_flags;
         if (alt) {
             if (px.n_flags == 1) {
                 orc_pixel q;
@@ -641,11 +646,12 @@ int orc_render(const orc_scene *s, double *image, double *final_T, int32_t *n_co
     return 0;
 }
 
-/* L1 loss sum over the pixels of the masked tiles: sum |C - target| / (3HW),
+/* L1 loss sum over the pixels of the masked tiles: sum w |C - target| / (3HW)
+ * (w = weight[H][W], or 1 when weight is NULL),
  * plus a hash of every discrete decision taken there (for finite-difference
  * validity checks). */
-int orc_l1_tiles(const orc_scene *s, const double *target, const uint8_t *tile_mask, double *loss,
-                 uint64_t *signature) {
+int orc_l1_tiles(const orc_scene *s, const double *target, const double *weight, const uint8_t *tile_mask,
+                 double *loss, uint64_t *signature) {
     if (s->width % ORC_TILE != 0 || s->height < 1) return -1;
     orc_lists L;
     if (build_lists(s, tile_mask, &L) != 0) {
@@ -667,7 +673,7 @@ int orc_l1_tiles(const orc_scene *s, const double *target, const uint8_t *tile_m
                 sig = fnv(sig, px.sig);
                 for (int ch = 0; ch < 3; ++ch) {
                     const double r = px.C[ch] - target[ch * HW + p];
-                    total += fabs(r);
+                    total += (weight ? weight[p] : 1.0) * fabs(r);
                     sig = fnv(sig, (uint64_t)(r > 0.0 ? 1 : (r < 0.0 ? 2 : 0)));
                 }
             }
@@ -829,18 +835,20 @@ static void chain_one(const orc_scene *s, int64_t i, const orc_proj *P, const do
     dscreen[1] = gp[1] * H / 2.0;
 }
 
-/* Backward of image = render(params) for a given dL/dimage [3][H][W].
+/* Backward of image = render(params) for a given dL/dimage [3][H][W],
+ * restricted to the tiles set in tile_mask (NULL: all); exact when dL/dimage
+ * vanishes outside them.
  * Gradient outputs are overwritten: dmeans [n][3], dscales [n][3],
  * dquats [n][4], dopac [n], dsh [n][sh_coeffs][3], dscreen [n][2].
  * acc_out (may be NULL): [n][9] screen-space accumulators.
  * abs_* (may all be NULL): sums of |per-pixel contributions| propagated
  * through |chain|, the scale against which FP32 sums are judged. */
-int orc_backward(const orc_scene *s, const double *dLdC, double *dmeans, double *dscales, double *dquats,
-                 double *dopac, double *dsh, double *dscreen, double *acc_out, double *abs_means, double *abs_scales,
-                 double *abs_quats, double *abs_opac, double *abs_sh, double *abs_screen) {
+int orc_backward(const orc_scene *s, const uint8_t *tile_mask, const double *dLdC, double *dmeans, double *dscales,
+                 double *dquats, double *dopac, double *dsh, double *dscreen, double *acc_out, double *abs_means,
+                 double *abs_scales, double *abs_quats, double *abs_opac, double *abs_sh, double *abs_screen) {
     if (s->width % ORC_TILE != 0 || s->height < 1) return -1;
     orc_lists L;
-    if (build_lists(s, NULL, &L) != 0) {
+    if (build_lists(s, tile_mask, &L) != 0) {
         lists_free(&L);
         return -1;
     }
@@ -871,6 +879,7 @@ int orc_backward(const orc_scene *s, const double *dLdC, double *dmeans, double 
         orc_contrib *con = (orc_contrib *)malloc(sizeof(orc_contrib) * (size_t)maxlen);
 #pragma omp for schedule(dynamic, 4)
         for (int64_t t = 0; t < ntiles; ++t) {
+            if (tile_mask && !tile_mask[t]) continue;
             const int tx = (int)(t % L.tiles_x), ty = (int)(t / L.tiles_x);
             for (int y = ty * ORC_TILE; y < ty * ORC_TILE + ORC_TILE && y < Hd; ++y)
                 for (int x = tx * ORC_TILE; x < tx * ORC_TILE + ORC_TILE; ++x) {

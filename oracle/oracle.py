@@ -23,7 +23,7 @@ _LIB_PATH = os.path.join(_HERE, "libomnigs_oracle.so")
 # margins used to flag near-threshold discrete decisions (see DESIGN notes):
 # relative for alpha and T decisions and for depth ties, absolute pixels for
 # the rect bounds.
-DEFAULT_FLAGS = dict(flag_rel_alpha=1e-5, flag_rel_T=1e-4, flag_rel_depth=2.0**-21, flag_abs_rect=1e-6)
+DEFAULT_FLAGS = dict(flag_rel_alpha=1e-5, flag_rel_T=1e-4, flag_rel_depth=2.0**-22, flag_abs_rect=1e-6)
 
 DEFAULT_SETTINGS = dict(alpha_min=1.0 / 255.0, alpha_max=0.99, T_min=1e-4, dilation=0.3, near_plane=0.2,
                         bg=(0.0, 0.0, 0.0))
@@ -84,11 +84,11 @@ def _load():
         _lib.orc_project.restype = ctypes.c_int
         _lib.orc_tile_lists.argtypes = [P(_Scene), ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         _lib.orc_tile_lists.restype = ctypes.c_int64
-        _lib.orc_render.argtypes = [P(_Scene)] + [ctypes.c_void_p] * 5
+        _lib.orc_render.argtypes = [P(_Scene)] + [ctypes.c_void_p] * 7
         _lib.orc_render.restype = ctypes.c_int
-        _lib.orc_l1_tiles.argtypes = [P(_Scene), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        _lib.orc_l1_tiles.argtypes = [P(_Scene)] + [ctypes.c_void_p] * 5
         _lib.orc_l1_tiles.restype = ctypes.c_int
-        _lib.orc_backward.argtypes = [P(_Scene)] + [ctypes.c_void_p] * 14
+        _lib.orc_backward.argtypes = [P(_Scene)] + [ctypes.c_void_p] * 15
         _lib.orc_backward.restype = ctypes.c_int
         _lib.orc_l1.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         _lib.orc_l1.restype = ctypes.c_double
@@ -213,9 +213,19 @@ def tile_lists(scene: Scene):
     return tile[:m], gid[:m], tr[:m]
 
 
-def render(scene: Scene, alt: bool = True):
+def _mask(scene, tile_mask):
+    if tile_mask is None:
+        return None
+    m = np.ascontiguousarray(np.asarray(tile_mask, dtype=np.uint8).reshape(-1))
+    assert m.size == scene.tiles_x * scene.tiles_y
+    return m
+
+
+def render(scene: Scene, alt: bool = True, tile_mask=None):
     """Forward render: dict(image [3,H,W], final_T [H,W], n_contrib [H,W],
-    n_flags [H,W], alt [3,H,W] or None)."""
+    n_flags [H,W], alt [3,H,W] or None, n_grad_flags [H,W]).  With
+    ``tile_mask`` ([tiles] bool) only those tiles are rendered (the other
+    pixels stay zero)."""
     lib = _load()
     H, W = scene.height, scene.width
     image = np.zeros((3, H, W))
@@ -223,12 +233,14 @@ def render(scene: Scene, alt: bool = True):
     nc = np.zeros((H, W), dtype=np.int32)
     nf = np.zeros((H, W), dtype=np.int32)
     altimg = np.zeros((3, H, W)) if alt else None
+    ngf = np.zeros((H, W), dtype=np.int32)
     s = scene._struct()
-    rc = lib.orc_render(ctypes.byref(s), image.ctypes.data, T.ctypes.data, nc.ctypes.data, nf.ctypes.data,
-                        altimg.ctypes.data if alt else None)
+    m = _mask(scene, tile_mask)
+    rc = lib.orc_render(ctypes.byref(s), m.ctypes.data if m is not None else None, image.ctypes.data, T.ctypes.data,
+                        nc.ctypes.data, nf.ctypes.data, altimg.ctypes.data if alt else None, ngf.ctypes.data)
     if rc != 0:
         raise ValueError("oracle: invalid scene")
-    return dict(image=image, final_T=T, n_contrib=nc, n_flags=nf, alt=altimg)
+    return dict(image=image, final_T=T, n_contrib=nc, n_flags=nf, alt=altimg, n_grad_flags=ngf)
 
 
 def l1(image, target):
@@ -241,28 +253,31 @@ def l1(image, target):
     return loss, g
 
 
-def l1_tiles(scene: Scene, target, tile_mask):
-    """(sum over the masked tiles' pixels of |C - target| / (3HW), decision hash)."""
+def l1_tiles(scene: Scene, target, tile_mask, weight=None):
+    """(sum over the masked tiles' pixels of w |C - target| / (3HW), decision
+    hash); ``weight`` [H,W] or None (all ones)."""
     lib = _load()
     tg = _f64(target)
+    w = None if weight is None else _f64(weight).reshape(scene.height, scene.width)
     mask = np.ascontiguousarray(np.asarray(tile_mask, dtype=np.uint8).reshape(-1))
     assert mask.size == scene.tiles_x * scene.tiles_y
     loss = ctypes.c_double(0.0)
     sig = ctypes.c_uint64(0)
     s = scene._struct()
-    if lib.orc_l1_tiles(ctypes.byref(s), tg.ctypes.data, mask.ctypes.data, ctypes.byref(loss),
-                        ctypes.byref(sig)) != 0:
+    if lib.orc_l1_tiles(ctypes.byref(s), tg.ctypes.data, w.ctypes.data if w is not None else None, mask.ctypes.data,
+                        ctypes.byref(loss), ctypes.byref(sig)) != 0:
         raise ValueError("oracle: invalid scene")
     return loss.value, sig.value
 
 
-def backward(scene: Scene, dL_dimage, with_abs: bool = True):
+def backward(scene: Scene, dL_dimage, with_abs: bool = True, tile_mask=None):
     """Analytic gradient of <dL_dimage, render(scene)> w.r.t. the parameters.
 
     Returns dict(means, scales, quats, opacities, sh, screen, acc) and, with
     ``with_abs``, the same keys prefixed ``abs_``: sums of |per-pixel
     contributions| pushed through |chain| (the scale FP32 sums are judged
-    against).
+    against).  With ``tile_mask`` only those tiles are walked (exact when
+    dL_dimage vanishes elsewhere).
     """
     lib = _load()
     n, K = scene.n, scene.sh_coeffs
@@ -276,7 +291,8 @@ def backward(scene: Scene, dL_dimage, with_abs: bool = True):
     s = scene._struct()
     args = [out[k].ctypes.data for k in names] + [out["acc"].ctypes.data]
     args += [out["abs_" + k].ctypes.data for k in names] if with_abs else [None] * 6
-    if lib.orc_backward(ctypes.byref(s), g.ctypes.data, *args) != 0:
+    m = _mask(scene, tile_mask)
+    if lib.orc_backward(ctypes.byref(s), m.ctypes.data if m is not None else None, g.ctypes.data, *args) != 0:
         raise ValueError("oracle: invalid scene")
     return out
 

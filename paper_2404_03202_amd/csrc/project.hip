@@ -1,0 +1,448 @@
+// project.hip -- per-Gaussian projection onto the ERP screen (forward) and
+// its chain rule back to the Gaussian parameters (backward).
+//
+// Both kernels are one thread per Gaussian and bandwidth-bound (236 B of
+// parameters in per Gaussian).  CDNA4 runs FP64 vector math at the FP32
+// non-packed rate, so the whole projection is done in double precision at no
+// measurable cost; only the 48-byte blend record is rounded to float.
+//
+// Forward (Sec. 3.2-3.3):
+//   t = W m + t_cw                                   (Eq. 1)
+//   lon = atan2(t_x, t_z), lat = asin(t_y / t_r)     (Eq. 3)
+//   s = (lon / pi, 2 lat / pi), p = (s + 1) (W, H)/2  (Eq. 4, 5)
+//   J = dp/dt                                        (Eq. 10-16)
+//   Sigma2D = (J W) Sigma (J W)^T + dilation I        (Eq. 9)
+// computed as V V^T with V = J W R(q) diag(S), which is exactly Eq. 9 for
+// Sigma = R diag(S)^2 R^T and keeps the 2x2 covariance positive in floating
+// point.  The radius of influence is the axis-aligned box of the
+// alpha = alpha_min iso-ellipse; its pixel columns wrap across the seam.
+//
+// Backward (Sec. 3.4, Eq. 18-20): from the per-Gaussian accumulators
+// dL/dp, dL/dQ (Q = Sigma2D^-1), dL/do, dL/drgb to dL/dm, dL/dS, dL/dq,
+// dL/do, dL/dSH and dL/ds, through the replaced omnidirectional terms
+// dSigma2D/dSigma, dJ/dt, dp/ds and ds/dt.
+#include "internal.h"
+
+#include <cmath>
+
+namespace omnigs {
+namespace {
+
+constexpr double kPi = 3.141592653589793238462643383279502884;
+
+// Real SH basis constants (Condon-Shortley phase, index l*l + l + m,
+// z polar axis), from N_l^m = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!):
+constexpr double kSH0 = 0.28209479177387814;   // 1 / (2 sqrt(pi))
+constexpr double kSH1 = 0.48860251190291992;   // sqrt(3 / (4 pi))
+constexpr double kSH2a = 1.0925484305920792;   // sqrt(15 / (4 pi))
+constexpr double kSH2b = 0.31539156525252005;  // sqrt(5 / (16 pi))
+constexpr double kSH2c = 0.54627421529603959;  // sqrt(15 / (16 pi))
+constexpr double kSH3a = 0.59004358992664352;  // sqrt(35 / (32 pi))
+constexpr double kSH3b = 2.8906114426405538;   // sqrt(105 / (4 pi))
+constexpr double kSH3c = 0.45704579946446572;  // sqrt(21 / (32 pi))
+constexpr double kSH3d = 0.37317633259011540;  // sqrt(7 / (16 pi))
+constexpr double kSH3e = 1.4453057213202769;   // sqrt(105 / (16 pi))
+
+template <int D>
+__device__ inline void sh_basis(double x, double y, double z, double *Y) {
+    Y[0] = kSH0;
+    if (D >= 1) {
+        Y[1] = -kSH1 * y;
+        Y[2] = kSH1 * z;
+        Y[3] = -kSH1 * x;
+    }
+    if (D >= 2) {
+        const double xx = x * x, yy = y * y, zz = z * z;
+        Y[4] = kSH2a * x * y;
+        Y[5] = -kSH2a * y * z;
+        Y[6] = kSH2b * (2.0 * zz - xx - yy);
+        Y[7] = -kSH2a * x * z;
+        Y[8] = kSH2c * (xx - yy);
+        if (D >= 3) {
+            Y[9] = -kSH3a * y * (3.0 * xx - yy);
+            Y[10] = kSH3b * x * y * z;
+            Y[11] = -kSH3c * y * (4.0 * zz - xx - yy);
+            Y[12] = kSH3d * z * (2.0 * zz - 3.0 * xx - 3.0 * yy);
+            Y[13] = -kSH3c * x * (4.0 * zz - xx - yy);
+            Y[14] = kSH3e * z * (xx - yy);
+            Y[15] = -kSH3a * x * (xx - 3.0 * yy);
+        }
+    }
+}
+
+// Gradient of each basis polynomial w.r.t. (x, y, z): dY[k][0..2].
+template <int D>
+__device__ inline void sh_basis_grad(double x, double y, double z, double (*dY)[3]) {
+    dY[0][0] = dY[0][1] = dY[0][2] = 0.0;
+    if (D >= 1) {
+        dY[1][0] = 0.0;   dY[1][1] = -kSH1; dY[1][2] = 0.0;
+        dY[2][0] = 0.0;   dY[2][1] = 0.0;   dY[2][2] = kSH1;
+        dY[3][0] = -kSH1; dY[3][1] = 0.0;   dY[3][2] = 0.0;
+    }
+    if (D >= 2) {
+        dY[4][0] = kSH2a * y;          dY[4][1] = kSH2a * x;          dY[4][2] = 0.0;
+        dY[5][0] = 0.0;                dY[5][1] = -kSH2a * z;         dY[5][2] = -kSH2a * y;
+        dY[6][0] = -2.0 * kSH2b * x;   dY[6][1] = -2.0 * kSH2b * y;   dY[6][2] = 4.0 * kSH2b * z;
+        dY[7][0] = -kSH2a * z;         dY[7][1] = 0.0;                dY[7][2] = -kSH2a * x;
+        dY[8][0] = 2.0 * kSH2c * x;    dY[8][1] = -2.0 * kSH2c * y;   dY[8][2] = 0.0;
+        if (D >= 3) {
+            const double xx = x * x, yy = y * y, zz = z * z;
+            dY[9][0] = -kSH3a * 6.0 * x * y;
+            dY[9][1] = -kSH3a * 3.0 * (xx - yy);
+            dY[9][2] = 0.0;
+            dY[10][0] = kSH3b * y * z;
+            dY[10][1] = kSH3b * x * z;
+            dY[10][2] = kSH3b * x * y;
+            dY[11][0] = kSH3c * 2.0 * x * y;
+            dY[11][1] = -kSH3c * (4.0 * zz - xx - 3.0 * yy);
+            dY[11][2] = -kSH3c * 8.0 * y * z;
+            dY[12][0] = -kSH3d * 6.0 * x * z;
+            dY[12][1] = -kSH3d * 6.0 * y * z;
+            dY[12][2] = kSH3d * (6.0 * zz - 3.0 * xx - 3.0 * yy);
+            dY[13][0] = -kSH3c * (4.0 * zz - 3.0 * xx - yy);
+            dY[13][1] = kSH3c * 2.0 * x * y;
+            dY[13][2] = -kSH3c * 8.0 * x * z;
+            dY[14][0] = kSH3e * 2.0 * x * z;
+            dY[14][1] = -kSH3e * 2.0 * y * z;
+            dY[14][2] = kSH3e * (xx - yy);
+            dY[15][0] = -kSH3a * 3.0 * (xx - yy);
+            dY[15][1] = kSH3a * 6.0 * x * y;
+            dY[15][2] = 0.0;
+        }
+    }
+}
+
+// Everything the forward computes for one Gaussian, in double precision.
+struct Proj {
+    double t[3], tr, rho;
+    double px, py;
+    double J[6];   // dp/dt, 2x3 row-major
+    double M[6];   // J W
+    double qn[4], qnorm, Rq[9];
+    double S[3];
+    double V[6];   // M Rq diag(S)
+    double a, b, c, det;  // Sigma2D = [[a, b], [b, c]]
+    double dir[3], vnorm; // unit direction camera centre -> m (world frame)
+};
+
+// Eq. 1, 3-5, 9-16.  Returns false when the Gaussian is culled (t_r below the
+// near plane, opacity that can never pass alpha_min, on the polar axis, or a
+// degenerate 2D covariance).
+__device__ inline bool project_core(const ProjectArgs &A, int64_t i, double o, Proj &P) {
+    const double m0 = A.means[3 * i], m1 = A.means[3 * i + 1], m2 = A.means[3 * i + 2];
+    for (int r = 0; r < 3; ++r) P.t[r] = A.R[3 * r] * m0 + A.R[3 * r + 1] * m1 + A.R[3 * r + 2] * m2 + A.t[r];
+    const double tx = P.t[0], ty = P.t[1], tz = P.t[2];
+    const double rho2 = tx * tx + tz * tz;
+    P.rho = sqrt(rho2);
+    P.tr = sqrt(rho2 + ty * ty);
+    if (!(P.tr > A.near_plane) || !(o > A.alpha_min) || !(P.rho > 1e-6 * P.tr)) return false;
+    double lon = atan2(tx, tz);
+    if (lon >= kPi) lon = -kPi;
+    const double lat = asin(ty / P.tr);
+    P.px = (lon / kPi + 1.0) * (0.5 * A.width);
+    P.py = (2.0 * lat / kPi + 1.0) * (0.5 * A.height);
+    const double kx = A.width / (2.0 * kPi), ky = A.height / kPi;
+    const double r2 = P.tr * P.tr;
+    P.J[0] = kx * tz / rho2;
+    P.J[1] = 0.0;
+    P.J[2] = -kx * tx / rho2;
+    P.J[3] = -ky * tx * ty / (r2 * P.rho);
+    P.J[4] = ky * P.rho / r2;
+    P.J[5] = -ky * tz * ty / (r2 * P.rho);
+    for (int a = 0; a < 2; ++a)
+        for (int k = 0; k < 3; ++k)
+            P.M[3 * a + k] = P.J[3 * a] * A.R[k] + P.J[3 * a + 1] * A.R[3 + k] + P.J[3 * a + 2] * A.R[6 + k];
+    const float4 q = reinterpret_cast<const float4 *>(A.quats)[i];
+    P.qnorm = sqrt((double)q.x * q.x + (double)q.y * q.y + (double)q.z * q.z + (double)q.w * q.w);
+    if (!(P.qnorm > 0.0)) return false;
+    const double w = q.x / P.qnorm, x = q.y / P.qnorm, y = q.z / P.qnorm, z = q.w / P.qnorm;
+    P.qn[0] = w; P.qn[1] = x; P.qn[2] = y; P.qn[3] = z;
+    double *R = P.Rq;
+    R[0] = 1.0 - 2.0 * (y * y + z * z); R[1] = 2.0 * (x * y - w * z);       R[2] = 2.0 * (x * z + w * y);
+    R[3] = 2.0 * (x * y + w * z);       R[4] = 1.0 - 2.0 * (x * x + z * z); R[5] = 2.0 * (y * z - w * x);
+    R[6] = 2.0 * (x * z - w * y);       R[7] = 2.0 * (y * z + w * x);       R[8] = 1.0 - 2.0 * (x * x + y * y);
+    for (int k = 0; k < 3; ++k) P.S[k] = A.scales[3 * i + k];
+    for (int a = 0; a < 2; ++a)
+        for (int k = 0; k < 3; ++k)
+            P.V[3 * a + k] = (P.M[3 * a] * R[k] + P.M[3 * a + 1] * R[3 + k] + P.M[3 * a + 2] * R[6 + k]) * P.S[k];
+    const double *V0 = P.V, *V1 = P.V + 3;
+    P.a = V0[0] * V0[0] + V0[1] * V0[1] + V0[2] * V0[2] + A.dilation;
+    P.b = V0[0] * V1[0] + V0[1] * V1[1] + V0[2] * V1[2];
+    P.c = V1[0] * V1[0] + V1[1] * V1[1] + V1[2] * V1[2] + A.dilation;
+    P.det = P.a * P.c - P.b * P.b;
+    if (!(P.det > 0.0)) return false;
+    const double v0 = m0 - A.campos[0], v1 = m1 - A.campos[1], v2 = m2 - A.campos[2];
+    P.vnorm = sqrt(v0 * v0 + v1 * v1 + v2 * v2);
+    P.dir[0] = v0 / P.vnorm;
+    P.dir[1] = v1 / P.vnorm;
+    P.dir[2] = v2 / P.vnorm;
+    return true;
+}
+
+template <int D>
+__device__ inline void load_sh(const ProjectArgs &A, int64_t i, double (*sh)[3]) {
+    constexpr int K = (D + 1) * (D + 1);
+    const float *p = A.sh + i * (int64_t)A.sh_coeffs * 3;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) sh[k][ch] = p[3 * k + ch];
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_project(ProjectArgs A, BlendRecord *rec, uint32_t *depth_key,
+                                                 uint32_t *n_tiles, uint2 *rect) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    const double o = A.opacities[i];
+    Proj P;
+    bool vis = project_core(A, i, o, P);
+    uint32_t ntx = 0, nty = 0, tx0 = 0, ty0 = 0;
+    if (vis) {
+        const double kcut = 2.0 * log(o / A.alpha_min);
+        const double ex = sqrt(kcut * P.a), ey = sqrt(kcut * P.c);
+        const double xs = ceil(P.px - ex - 0.5), xe = floor(P.px + ex - 0.5);
+        double ys = ceil(P.py - ey - 0.5), ye = floor(P.py + ey - 0.5);
+        ys = fmax(ys, 0.0);
+        ye = fmin(ye, (double)(A.height - 1));
+        const bool full = (xe - xs + 1.0) >= (double)A.width;
+        if ((!full && xe < xs) || ye < ys) {
+            vis = false;
+        } else {
+            if (full) {
+                tx0 = 0;
+                ntx = A.tiles_x;
+            } else {
+                // xs, xe lie within (-W, 2W): exact in int
+                const int t0 = (int)floor(xs / kTile), t1 = (int)floor(xe / kTile);
+                const int cnt = t1 - t0 + 1;
+                if (cnt >= A.tiles_x) {
+                    tx0 = 0;
+                    ntx = A.tiles_x;
+                } else {
+                    tx0 = (uint32_t)(((t0 % A.tiles_x) + A.tiles_x) % A.tiles_x);
+                    ntx = (uint32_t)cnt;
+                }
+            }
+            ty0 = (uint32_t)((int)ys / kTile);
+            nty = (uint32_t)((int)ye / kTile) - ty0 + 1;
+        }
+    }
+    if (!vis) {
+        depth_key[i] = kCulledKey;
+        n_tiles[i] = 0;
+        rect[i] = make_uint2(0, 0);
+        return;
+    }
+    constexpr int K = (D + 1) * (D + 1);
+    double Y[16];
+    sh_basis<D>(P.dir[0], P.dir[1], P.dir[2], Y);
+    double sh[K][3];
+    load_sh<D>(A, i, sh);
+    float rgb[3];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        double v = 0.5;
+#pragma unroll
+        for (int k = 0; k < K; ++k) v += Y[k] * sh[k][ch];
+        rgb[ch] = v < 0.0 ? 0.0f : (float)v;
+    }
+    BlendRecord r;
+    r.px_hi = (float)P.px;
+    r.px_lo = (float)(P.px - (double)r.px_hi);
+    r.py_hi = (float)P.py;
+    r.py_lo = (float)(P.py - (double)r.py_hi);
+    const double inv_det = 1.0 / P.det;
+    r.q00 = (float)(P.c * inv_det);
+    r.q01 = (float)(-P.b * inv_det);
+    r.q11 = (float)(P.a * inv_det);
+    r.opacity = (float)o;
+    r.r = rgb[0];
+    r.g = rgb[1];
+    r.b = rgb[2];
+    r.pad = 0.0f;
+    float4 *dst = reinterpret_cast<float4 *>(rec + i);
+    dst[0] = make_float4(r.px_hi, r.px_lo, r.py_hi, r.py_lo);
+    dst[1] = make_float4(r.q00, r.q01, r.q11, r.opacity);
+    dst[2] = make_float4(r.r, r.g, r.b, r.pad);
+    depth_key[i] = __float_as_uint((float)P.tr);
+    n_tiles[i] = ntx * nty;
+    rect[i] = make_uint2(tx0 | (ntx << 16), ty0 | (nty << 16));
+}
+
+// dJ/dt for the spherical Jacobian: dJ[e][n] = d J_e / d t_n, e = 3a + j.
+__device__ inline void jacobian_grad(const Proj &P, double kx, double ky, double (*dJ)[3]) {
+    const double tx = P.t[0], ty = P.t[1], tz = P.t[2];
+    const double rho = P.rho, rho2 = rho * rho, rho4 = rho2 * rho2;
+    const double r2 = P.tr * P.tr, r4 = r2 * r2;
+    const double rho3 = rho2 * rho;
+    const double txx_tzz = tx * tx - tz * tz;
+    dJ[0][0] = -2.0 * kx * tx * tz / rho4;
+    dJ[0][1] = 0.0;
+    dJ[0][2] = kx * txx_tzz / rho4;
+    dJ[1][0] = dJ[1][1] = dJ[1][2] = 0.0;
+    dJ[2][0] = kx * txx_tzz / rho4;
+    dJ[2][1] = 0.0;
+    dJ[2][2] = 2.0 * kx * tx * tz / rho4;
+    const double q = 2.0 * rho2 + r2;
+    const double u = ty * ty - rho2;
+    dJ[3][0] = -ky * ty * (r2 * rho2 - tx * tx * q) / (r4 * rho3);
+    dJ[3][1] = ky * tx * u / (r4 * rho);
+    dJ[3][2] = ky * tx * ty * tz * q / (r4 * rho3);
+    dJ[4][0] = ky * tx * u / (rho * r4);
+    dJ[4][1] = -2.0 * ky * rho * ty / r4;
+    dJ[4][2] = ky * tz * u / (rho * r4);
+    dJ[5][0] = ky * tx * ty * tz * q / (r4 * rho3);
+    dJ[5][1] = ky * tz * u / (r4 * rho);
+    dJ[5][2] = -ky * ty * (r2 * rho2 - tz * tz * q) / (r4 * rho3);
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_project_backward(ProjectArgs A, const uint32_t *n_tiles, const float *acc,
+                                                          omnigs_grads G) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    const int K = A.sh_coeffs;
+    float *dsh = G.dsh + i * (int64_t)K * 3;
+    constexpr int KD = (D + 1) * (D + 1);
+    for (int k = KD; k < K; ++k) dsh[3 * k] = dsh[3 * k + 1] = dsh[3 * k + 2] = 0.0f;
+    const double o = A.opacities[i];
+    Proj P;
+    if (n_tiles[i] == 0 || !project_core(A, i, o, P)) {
+        for (int k = 0; k < 3; ++k) G.dmeans[3 * i + k] = G.dscales[3 * i + k] = 0.0f;
+        reinterpret_cast<float4 *>(G.dquats)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        G.dopacities[i] = 0.0f;
+        for (int k = 0; k < KD; ++k) dsh[3 * k] = dsh[3 * k + 1] = dsh[3 * k + 2] = 0.0f;
+        G.dscreen[2 * i] = G.dscreen[2 * i + 1] = 0.0f;
+        return;
+    }
+    double g[kAcc];
+#pragma unroll
+    for (int k = 0; k < kAcc; ++k) g[k] = acc[i * kAcc + k];
+    // Q = Sigma2D^-1; the blend's dL/dQ treats q01 as one variable used in
+    // both off-diagonal entries: the symmetric gradient is [[g00, g01/2], ...].
+    const double id = 1.0 / P.det;
+    const double Q00 = P.c * id, Q01 = -P.b * id, Q11 = P.a * id;
+    const double G00 = g[2], G01 = 0.5 * g[3], G11 = g[4];
+    // dL/dSigma2D = -Q G Q (symmetric)
+    const double A00 = Q00 * G00 + Q01 * G01, A01 = Q00 * G01 + Q01 * G11;
+    const double A10 = Q01 * G00 + Q11 * G01, A11 = Q01 * G01 + Q11 * G11;
+    const double S00 = -(A00 * Q00 + A01 * Q01);
+    const double S01 = -(A00 * Q01 + A01 * Q11);
+    const double S11 = -(A10 * Q01 + A11 * Q11);
+    // a = V0.V0, b = V0.V1, c = V1.V1 (b used twice in the symmetric matrix)
+    const double ga = S00, gb = 2.0 * S01, gc = S11;
+    double dV[6];
+    for (int k = 0; k < 3; ++k) {
+        dV[k] = 2.0 * ga * P.V[k] + gb * P.V[3 + k];
+        dV[3 + k] = gb * P.V[k] + 2.0 * gc * P.V[3 + k];
+    }
+    // V = M B, B = Rq diag(S)
+    double dM[6], dB[9];
+    for (int a = 0; a < 2; ++a)
+        for (int j = 0; j < 3; ++j) {
+            double v = 0.0;
+            for (int k = 0; k < 3; ++k) v += dV[3 * a + k] * P.Rq[3 * j + k] * P.S[k];
+            dM[3 * a + j] = v;
+        }
+    for (int j = 0; j < 3; ++j)
+        for (int k = 0; k < 3; ++k) dB[3 * j + k] = P.M[j] * dV[k] + P.M[3 + j] * dV[3 + k];
+    double dS[3], dR[9];
+    for (int k = 0; k < 3; ++k) {
+        dS[k] = dB[k] * P.Rq[k] + dB[3 + k] * P.Rq[3 + k] + dB[6 + k] * P.Rq[6 + k];
+        for (int j = 0; j < 3; ++j) dR[3 * j + k] = dB[3 * j + k] * P.S[k];
+    }
+    // R(q) for the unit quaternion (w, x, y, z)
+    const double w = P.qn[0], x = P.qn[1], y = P.qn[2], z = P.qn[3];
+    double dqn[4];
+    dqn[0] = 2.0 * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+    dqn[1] = 2.0 * (y * dR[1] + z * dR[2] + y * dR[3] - 2.0 * x * dR[4] - w * dR[5] + z * dR[6] + w * dR[7] -
+                    2.0 * x * dR[8]);
+    dqn[2] = 2.0 * (-2.0 * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] + z * dR[7] -
+                    2.0 * y * dR[8]);
+    dqn[3] = 2.0 * (-2.0 * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.0 * z * dR[4] + y * dR[5] +
+                    x * dR[6] + y * dR[7]);
+    const double qd = w * dqn[0] + x * dqn[1] + y * dqn[2] + z * dqn[3];
+    float4 dq;
+    dq.x = (float)((dqn[0] - w * qd) / P.qnorm);
+    dq.y = (float)((dqn[1] - x * qd) / P.qnorm);
+    dq.z = (float)((dqn[2] - y * qd) / P.qnorm);
+    dq.w = (float)((dqn[3] - z * qd) / P.qnorm);
+    // M = J W: dJ = dM W^T
+    double dJ[6];
+    for (int a = 0; a < 2; ++a)
+        for (int j = 0; j < 3; ++j)
+            dJ[3 * a + j] = dM[3 * a] * A.R[3 * j] + dM[3 * a + 1] * A.R[3 * j + 1] + dM[3 * a + 2] * A.R[3 * j + 2];
+    const double kx = A.width / (2.0 * kPi), ky = A.height / kPi;
+    double dJdt[6][3];
+    jacobian_grad(P, kx, ky, dJdt);
+    double dt[3];
+    for (int nn = 0; nn < 3; ++nn) {
+        double v = P.J[nn] * g[0] + P.J[3 + nn] * g[1];
+        for (int e = 0; e < 6; ++e) v += dJ[e] * dJdt[e][nn];
+        dt[nn] = v;
+    }
+    double dm[3];
+    for (int k = 0; k < 3; ++k) dm[k] = A.R[k] * dt[0] + A.R[3 + k] * dt[1] + A.R[6 + k] * dt[2];
+    // SH colour
+    double Y[16], dY[16][3], sh[KD][3];
+    sh_basis<D>(P.dir[0], P.dir[1], P.dir[2], Y);
+    sh_basis_grad<D>(P.dir[0], P.dir[1], P.dir[2], dY);
+    load_sh<D>(A, i, sh);
+    double grgb[3];
+    for (int ch = 0; ch < 3; ++ch) {
+        double v = 0.5;
+        for (int k = 0; k < KD; ++k) v += Y[k] * sh[k][ch];
+        grgb[ch] = v < 0.0 ? 0.0 : g[6 + ch];
+    }
+    double gdir[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < KD; ++k) {
+        const double s = sh[k][0] * grgb[0] + sh[k][1] * grgb[1] + sh[k][2] * grgb[2];
+        gdir[0] += s * dY[k][0];
+        gdir[1] += s * dY[k][1];
+        gdir[2] += s * dY[k][2];
+        dsh[3 * k] = (float)(Y[k] * grgb[0]);
+        dsh[3 * k + 1] = (float)(Y[k] * grgb[1]);
+        dsh[3 * k + 2] = (float)(Y[k] * grgb[2]);
+    }
+    const double pd = P.dir[0] * gdir[0] + P.dir[1] * gdir[1] + P.dir[2] * gdir[2];
+    for (int k = 0; k < 3; ++k) dm[k] += (gdir[k] - P.dir[k] * pd) / P.vnorm;
+    for (int k = 0; k < 3; ++k) {
+        G.dmeans[3 * i + k] = (float)dm[k];
+        G.dscales[3 * i + k] = (float)dS[k];
+    }
+    reinterpret_cast<float4 *>(G.dquats)[i] = dq;
+    G.dopacities[i] = (float)g[5];
+    G.dscreen[2 * i] = (float)(g[0] * (0.5 * A.width));
+    G.dscreen[2 * i + 1] = (float)(g[1] * (0.5 * A.height));
+}
+
+}  // namespace
+
+hipError_t launch_project(const ProjectArgs &a, BlendRecord *rec, uint32_t *depth_key, uint32_t *n_tiles,
+                          uint2 *rect, hipStream_t st) {
+    if (a.n == 0) return hipSuccess;
+    const dim3 grid((unsigned)((a.n + 255) / 256));
+    switch (a.sh_degree) {
+        case 0: hipLaunchKernelGGL(k_project<0>, grid, dim3(256), 0, st, a, rec, depth_key, n_tiles, rect); break;
+        case 1: hipLaunchKernelGGL(k_project<1>, grid, dim3(256), 0, st, a, rec, depth_key, n_tiles, rect); break;
+        case 2: hipLaunchKernelGGL(k_project<2>, grid, dim3(256), 0, st, a, rec, depth_key, n_tiles, rect); break;
+        default: hipLaunchKernelGGL(k_project<3>, grid, dim3(256), 0, st, a, rec, depth_key, n_tiles, rect); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_project_backward(const ProjectArgs &a, const uint32_t *n_tiles, const float *acc,
+                                   const omnigs_grads &gr, hipStream_t st) {
+    if (a.n == 0) return hipSuccess;
+    const dim3 grid((unsigned)((a.n + 255) / 256));
+    switch (a.sh_degree) {
+        case 0: hipLaunchKernelGGL(k_project_backward<0>, grid, dim3(256), 0, st, a, n_tiles, acc, gr); break;
+        case 1: hipLaunchKernelGGL(k_project_backward<1>, grid, dim3(256), 0, st, a, n_tiles, acc, gr); break;
+        case 2: hipLaunchKernelGGL(k_project_backward<2>, grid, dim3(256), 0, st, a, n_tiles, acc, gr); break;
+        default: hipLaunchKernelGGL(k_project_backward<3>, grid, dim3(256), 0, st, a, n_tiles, acc, gr); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace omnigs

@@ -1,0 +1,355 @@
+"""Thin ctypes binding of libomnigs.so (include/omnigs.h).
+
+Argument marshalling only: every step of the render and its backward runs in
+the HIP kernels of the library.  PyTorch provides the device memory (the
+library's allocator callback hands out torch CUDA tensors, so the caching
+allocator recycles them) and the stream (the current HIP stream of the
+tensors' device).
+
+The names mirror the C entry points: ``omnigs_forward``, ``omnigs_backward``,
+``omnigs_l1_loss``, ``omnigs_forward_batch``, ``omnigs_last_error``,
+``omnigs_default_settings`` and the ``omnigs_profile_*`` calls.  Loading
+fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import threading
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libomnigs.so")
+
+OMNIGS_OK, OMNIGS_ERR_INVALID, OMNIGS_ERR_ALLOC, OMNIGS_ERR_HIP, OMNIGS_ERR_CAPACITY = 0, 1, 2, 3, 4
+OMNIGS_MEM_SCRATCH, OMNIGS_MEM_STATE = 0, 1
+STATUS_NAMES = {0: "OK", 1: "ERR_INVALID", 2: "ERR_ALLOC", 3: "ERR_HIP", 4: "ERR_CAPACITY"}
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32)
+
+
+class OmnigsError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"omnigs {STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class c_allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("user", ctypes.c_void_p)]
+
+
+class c_gaussians(ctypes.Structure):
+    _fields_ = [("means", ctypes.c_void_p), ("scales", ctypes.c_void_p), ("quats", ctypes.c_void_p),
+                ("opacities", ctypes.c_void_p), ("sh", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("sh_degree", ctypes.c_int32), ("sh_coeffs", ctypes.c_int32)]
+
+
+class c_camera(ctypes.Structure):
+    _fields_ = [("R_cw", ctypes.c_double * 9), ("t_cw", ctypes.c_double * 3), ("width", ctypes.c_int32),
+                ("height", ctypes.c_int32)]
+
+
+class c_settings(ctypes.Structure):
+    _fields_ = [("alpha_min", ctypes.c_double), ("alpha_max", ctypes.c_double), ("T_min", ctypes.c_double),
+                ("dilation", ctypes.c_double), ("near_plane", ctypes.c_double), ("bg", ctypes.c_double * 3)]
+
+
+class c_image_out(ctypes.Structure):
+    _fields_ = [("image", ctypes.c_void_p), ("final_T", ctypes.c_void_p), ("n_contrib", ctypes.c_void_p)]
+
+
+class c_state(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("n_instances", ctypes.c_int64), ("width", ctypes.c_int32),
+                ("height", ctypes.c_int32), ("tiles_x", ctypes.c_int32), ("tiles_y", ctypes.c_int32),
+                ("records", ctypes.c_void_p), ("n_tiles", ctypes.c_void_p), ("depth_order", ctypes.c_void_p),
+                ("inst_tile", ctypes.c_void_p), ("inst_gauss", ctypes.c_void_p), ("tile_range", ctypes.c_void_p)]
+
+
+class c_grads(ctypes.Structure):
+    _fields_ = [("dmeans", ctypes.c_void_p), ("dscales", ctypes.c_void_p), ("dquats", ctypes.c_void_p),
+                ("dopacities", ctypes.c_void_p), ("dsh", ctypes.c_void_p), ("dscreen", ctypes.c_void_p)]
+
+
+EXPORTS = ("omnigs_default_settings", "omnigs_forward", "omnigs_backward", "omnigs_l1_loss", "omnigs_forward_batch",
+           "omnigs_last_error", "omnigs_profile_enable", "omnigs_profile_num_stages", "omnigs_profile_stage_name",
+           "omnigs_profile_read")
+
+_lib = None
+_lib_lock = threading.Lock()
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libomnigs.so (raises if it has not been built)."""
+    global _lib
+    with _lib_lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(path):
+            raise RuntimeError(f"libomnigs.so not found at {path}: build it with "
+                               "`python -m paper_2404_03202_amd.build` (there is no CPU fallback)")
+        lib = ctypes.CDLL(path)
+        P = ctypes.POINTER
+        vp = ctypes.c_void_p
+        lib.omnigs_default_settings.argtypes = []
+        lib.omnigs_default_settings.restype = c_settings
+        lib.omnigs_forward.argtypes = [P(c_gaussians), P(c_camera), P(c_settings), c_allocator, P(c_image_out),
+                                       P(c_state), vp]
+        lib.omnigs_forward.restype = ctypes.c_int
+        lib.omnigs_backward.argtypes = [P(c_gaussians), P(c_camera), P(c_settings), P(c_state), P(c_image_out), vp,
+                                        P(c_grads), c_allocator, vp]
+        lib.omnigs_backward.restype = ctypes.c_int
+        lib.omnigs_l1_loss.argtypes = [vp, vp, ctypes.c_int64, vp, vp, c_allocator, vp]
+        lib.omnigs_l1_loss.restype = ctypes.c_int
+        lib.omnigs_forward_batch.argtypes = [P(c_gaussians), P(c_camera), ctypes.c_int32, P(c_settings), c_allocator,
+                                             P(c_image_out), ctypes.c_int64, vp, vp]
+        lib.omnigs_forward_batch.restype = ctypes.c_int
+        lib.omnigs_last_error.argtypes = []
+        lib.omnigs_last_error.restype = ctypes.c_char_p
+        lib.omnigs_profile_enable.argtypes = [ctypes.c_int32]
+        lib.omnigs_profile_enable.restype = ctypes.c_int
+        lib.omnigs_profile_num_stages.argtypes = []
+        lib.omnigs_profile_num_stages.restype = ctypes.c_int32
+        lib.omnigs_profile_stage_name.argtypes = [ctypes.c_int32]
+        lib.omnigs_profile_stage_name.restype = ctypes.c_char_p
+        lib.omnigs_profile_read.argtypes = [vp, vp]
+        lib.omnigs_profile_read.restype = ctypes.c_int
+        _lib = lib
+        return lib
+
+
+def omnigs_last_error() -> str:
+    return load_library().omnigs_last_error().decode(errors="replace")
+
+
+def _check(status):
+    if status != OMNIGS_OK:
+        raise OmnigsError(status, omnigs_last_error())
+
+
+# ------------------------------------------------------------------ marshal
+def omnigs_default_settings() -> dict:
+    s = load_library().omnigs_default_settings()
+    return dict(alpha_min=s.alpha_min, alpha_max=s.alpha_max, T_min=s.T_min, dilation=s.dilation,
+                near_plane=s.near_plane, bg=tuple(s.bg))
+
+
+def make_settings(settings: dict | None) -> c_settings:
+    d = omnigs_default_settings()
+    d.update(settings or {})
+    s = c_settings()
+    for k in ("alpha_min", "alpha_max", "T_min", "dilation", "near_plane"):
+        setattr(s, k, float(d[k]))
+    for k in range(3):
+        s.bg[k] = float(d["bg"][k])
+    return s
+
+
+def make_camera(camera: dict) -> c_camera:
+    """camera: R [3,3] world->camera rotation, t [3], width, height."""
+    c = c_camera()
+    R = np.asarray(camera["R"], dtype=np.float64).reshape(9)
+    t = np.asarray(camera["t"], dtype=np.float64).reshape(3)
+    for k in range(9):
+        c.R_cw[k] = float(R[k])
+    for k in range(3):
+        c.t_cw[k] = float(t[k])
+    c.width = int(camera["width"])
+    c.height = int(camera["height"])
+    return c
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def make_gaussians(g: dict) -> c_gaussians:
+    """g: means [N,3], scales [N,3], quats [N,4], opacities [N], sh [N,K,3]
+    (contiguous float32 CUDA tensors), sh_degree."""
+    sh = g["sh"]
+    n = int(g["means"].shape[0])
+    for k in ("means", "scales", "quats", "opacities", "sh"):
+        t = g[k]
+        if t.dtype != torch.float32 or not t.is_contiguous() or t.device.type != "cuda":
+            raise ValueError(f"{k} must be a contiguous float32 CUDA tensor")
+    c = c_gaussians()
+    c.means, c.scales, c.quats = _ptr(g["means"]), _ptr(g["scales"]), _ptr(g["quats"])
+    c.opacities, c.sh = _ptr(g["opacities"]), _ptr(sh)
+    c.n = n
+    c.sh_degree = int(g["sh_degree"])
+    c.sh_coeffs = int(sh.shape[1]) if sh.dim() == 3 else int(sh.numel() // max(n, 1) // 3)
+    return c
+
+
+class Allocator:
+    """Allocator callback backed by torch's caching allocator.  Scratch
+    allocations are dropped when the call returns (stream-ordered reuse);
+    state allocations stay referenced by the returned state."""
+
+    def __init__(self, device, fail=False):
+        self.device = device
+        self.fail = fail
+        self.scratch = []
+        self.state = []
+        self._cb = ALLOC_FN(self._alloc)
+        self.c = c_allocator(self._cb, None)
+
+    def _alloc(self, user, nbytes, kind):
+        if self.fail:
+            return None
+        try:
+            t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        except Exception:  # out of memory: reported as OMNIGS_ERR_ALLOC
+            return None
+        (self.state if kind == OMNIGS_MEM_STATE else self.scratch).append(t)
+        return t.data_ptr()
+
+
+def _stream_ptr(device):
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class ForwardResult:
+    """Outputs of omnigs_forward plus the saved state for omnigs_backward."""
+
+    def __init__(self, image, final_T, n_contrib, state: c_state, keepalive):
+        self.image = image
+        self.final_T = final_T
+        self.n_contrib = n_contrib
+        self.state = state
+        self._keep = keepalive
+
+    @property
+    def n_instances(self):
+        return int(self.state.n_instances)
+
+    def _view(self, ptr, count, dtype):
+        """View a state buffer as a tensor (for tests / debugging)."""
+        for t in self._keep:
+            base = t.data_ptr()
+            if base <= ptr < base + t.numel():
+                off = ptr - base
+                esz = torch.empty((), dtype=dtype).element_size()
+                return t[off:off + count * esz].view(dtype)
+        raise KeyError("pointer not in state buffers")
+
+    def instance_lists(self):
+        """(tile id [M] int32, Gaussian id [M] int32, tile ranges [tiles, 2] int32) as device tensors."""
+        M = self.n_instances
+        tiles = self.state.tiles_x * self.state.tiles_y
+        return (self._view(self.state.inst_tile, M, torch.int32), self._view(self.state.inst_gauss, M, torch.int32),
+                self._view(self.state.tile_range, 2 * tiles, torch.int32).view(tiles, 2))
+
+    def depth_order(self):
+        return self._view(self.state.depth_order, int(self.state.n), torch.int32)
+
+    def n_tiles(self):
+        return self._view(self.state.n_tiles, int(self.state.n), torch.int32)
+
+
+def omnigs_forward(g: dict, camera: dict, settings: dict | None = None, allocator: Allocator | None = None,
+                   out: dict | None = None) -> ForwardResult:
+    lib = load_library()
+    dev = g["means"].device
+    cg, cc, cs = make_gaussians(g), make_camera(camera), make_settings(settings)
+    H, W = cc.height, cc.width
+    if out is None:
+        out = dict(image=torch.empty((3, H, W), dtype=torch.float32, device=dev),
+                   final_T=torch.empty((H, W), dtype=torch.float32, device=dev),
+                   n_contrib=torch.empty((H, W), dtype=torch.int32, device=dev))
+    co = c_image_out(_ptr(out["image"]), _ptr(out["final_T"]), _ptr(out["n_contrib"]))
+    st = c_state()
+    al = allocator or Allocator(dev)
+    _check(lib.omnigs_forward(ctypes.byref(cg), ctypes.byref(cc), ctypes.byref(cs), al.c, ctypes.byref(co),
+                              ctypes.byref(st), ctypes.c_void_p(_stream_ptr(dev))))
+    keep = list(al.state)
+    al.scratch.clear()
+    al.state.clear()
+    return ForwardResult(out["image"], out["final_T"], out["n_contrib"], st, keep)
+
+
+def omnigs_backward(g: dict, camera: dict, settings: dict | None, fwd: ForwardResult, dL_dimage: torch.Tensor,
+                    allocator: Allocator | None = None, grads: dict | None = None) -> dict:
+    lib = load_library()
+    dev = g["means"].device
+    n = int(g["means"].shape[0])
+    cg, cc, cs = make_gaussians(g), make_camera(camera), make_settings(settings)
+    if dL_dimage.dtype != torch.float32 or not dL_dimage.is_contiguous():
+        raise ValueError("dL_dimage must be a contiguous float32 tensor")
+    if grads is None:
+        z = lambda *shape: torch.empty(shape, dtype=torch.float32, device=dev)
+        grads = dict(means=z(n, 3), scales=z(n, 3), quats=z(n, 4), opacities=z(n), sh=torch.empty_like(g["sh"]),
+                     screen=z(n, 2))
+    cgr = c_grads(_ptr(grads["means"]), _ptr(grads["scales"]), _ptr(grads["quats"]), _ptr(grads["opacities"]),
+                  _ptr(grads["sh"]), _ptr(grads["screen"]))
+    co = c_image_out(_ptr(fwd.image), _ptr(fwd.final_T), _ptr(fwd.n_contrib))
+    al = allocator or Allocator(dev)
+    _check(lib.omnigs_backward(ctypes.byref(cg), ctypes.byref(cc), ctypes.byref(cs), ctypes.byref(fwd.state),
+                               ctypes.byref(co), ctypes.c_void_p(dL_dimage.data_ptr()), ctypes.byref(cgr), al.c,
+                               ctypes.c_void_p(_stream_ptr(dev))))
+    al.scratch.clear()
+    return grads
+
+
+def omnigs_l1_loss(image: torch.Tensor, target: torch.Tensor, grad: bool = True, allocator: Allocator | None = None):
+    """(loss [1] float32, dL/dimage or None): mean |image - target| and sign/count."""
+    lib = load_library()
+    if image.shape != target.shape or image.dtype != torch.float32 or target.dtype != torch.float32:
+        raise ValueError("image and target must be float32 tensors of one shape")
+    image, target = image.contiguous(), target.contiguous()
+    dev = image.device
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    g = torch.empty_like(image) if grad else None
+    al = allocator or Allocator(dev)
+    _check(lib.omnigs_l1_loss(ctypes.c_void_p(image.data_ptr()), ctypes.c_void_p(target.data_ptr()), image.numel(),
+                              ctypes.c_void_p(_ptr(g)), ctypes.c_void_p(loss.data_ptr()), al.c,
+                              ctypes.c_void_p(_stream_ptr(dev))))
+    al.scratch.clear()
+    return loss, g
+
+
+def omnigs_forward_batch(g: dict, cameras: list, settings: dict | None = None, instance_capacity: int = 0,
+                         allocator: Allocator | None = None, outs: list | None = None):
+    """Render several cameras in one batched launch sequence.  Returns
+    (list of dict(image, final_T, n_contrib), overflow flag tensor)."""
+    lib = load_library()
+    dev = g["means"].device
+    B = len(cameras)
+    cg, cs = make_gaussians(g), make_settings(settings)
+    cams = (c_camera * B)(*[make_camera(c) for c in cameras])
+    if outs is None:
+        outs = []
+        for c in cameras:
+            H, W = int(c["height"]), int(c["width"])
+            outs.append(dict(image=torch.empty((3, H, W), dtype=torch.float32, device=dev),
+                             final_T=torch.empty((H, W), dtype=torch.float32, device=dev),
+                             n_contrib=torch.empty((H, W), dtype=torch.int32, device=dev)))
+    couts = (c_image_out * B)(*[c_image_out(_ptr(o["image"]), _ptr(o["final_T"]), _ptr(o["n_contrib"])) for o in outs])
+    overflow = torch.zeros(1, dtype=torch.int32, device=dev)
+    al = allocator or Allocator(dev)
+    _check(lib.omnigs_forward_batch(ctypes.byref(cg), cams, B, ctypes.byref(cs), al.c, couts, int(instance_capacity),
+                                    ctypes.c_void_p(overflow.data_ptr()), ctypes.c_void_p(_stream_ptr(dev))))
+    al.scratch.clear()
+    return outs, overflow
+
+
+# ---------------------------------------------------------------- profiling
+def omnigs_profile_enable(on: bool = True):
+    _check(load_library().omnigs_profile_enable(1 if on else 0))
+
+
+def omnigs_profile_read() -> dict:
+    """{stage name: (total ms, launches)} since the last read (synchronises)."""
+    lib = load_library()
+    n = lib.omnigs_profile_num_stages()
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int64 * n)()
+    _check(lib.omnigs_profile_read(ms, cnt))
+    return {lib.omnigs_profile_stage_name(k).decode(): (ms[k], int(cnt[k])) for k in range(n)}
+
+
+def tile_sort_bits(width: int, height: int) -> int:
+    tiles = (width // 16) * ((height + 15) // 16)
+    return max(1, math.ceil(math.log2(max(tiles, 2))))

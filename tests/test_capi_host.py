@@ -1,0 +1,124 @@
+"""Host-side contract of the C ABI (no GPU needed): the library loads, exports
+every entry point include/omnigs.h declares, and rejects bad arguments and
+allocator failures before any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2404_03202_amd import omnigs as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    hdr = open(os.path.join(ROOT, "include", "omnigs.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    return sorted(set(re.findall(r"\b(omnigs_\w+)\s*\(", hdr)) - {"omnigs_alloc_fn"})
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB_PATH):
+        pytest.fail("libomnigs.so is not built: run `python -m paper_2404_03202_amd.build`")
+    return B.load_library()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), f"{name} declared in omnigs.h but not exported"
+    assert set(names) == set(B.EXPORTS)
+
+
+def test_default_settings(lib):
+    s = B.omnigs_default_settings()
+    assert s["alpha_min"] == pytest.approx(1 / 255)
+    assert s["alpha_max"] == 0.99 and s["T_min"] == 1e-4 and s["dilation"] == 0.3 and s["near_plane"] == 0.2
+    assert tuple(s["bg"]) == (0.0, 0.0, 0.0)
+
+
+def _fake_args(n=10, width=64, height=32, degree=3, coeffs=16):
+    # non-null, 16-byte aligned fake device addresses: validation and
+    # allocation failures are reported before any pointer is dereferenced
+    g = B.c_gaussians(0x10000, 0x20000, 0x30000, 0x40000, 0x50000, n, degree, coeffs)
+    c = B.c_camera()
+    for k in range(9):
+        c.R_cw[k] = 1.0 if k in (0, 4, 8) else 0.0
+    c.width, c.height = width, height
+    s = B.make_settings(None)
+    out = B.c_image_out(0x60000, 0x70000, 0x80000)
+    return g, c, s, out
+
+
+def _alloc(fail):
+    calls = []
+
+    def cb(user, nbytes, kind):
+        calls.append((nbytes, kind))
+        return None if fail else None
+
+    f = B.ALLOC_FN(cb)
+    return B.c_allocator(f, None), calls, f
+
+
+def _forward(lib, g, c, s, out, alloc):
+    st = B.c_state()
+    return lib.omnigs_forward(ctypes.byref(g), ctypes.byref(c), ctypes.byref(s), alloc, ctypes.byref(out),
+                              ctypes.byref(st), None)
+
+
+@pytest.mark.parametrize("mutate,needle", [
+    (lambda g, c, s, o: setattr(c, "width", 100), "multiple of 16"),
+    (lambda g, c, s, o: setattr(c, "height", 0), "height"),
+    (lambda g, c, s, o: setattr(g, "sh_degree", 4), "sh_degree"),
+    (lambda g, c, s, o: setattr(g, "sh_coeffs", 4), "sh_coeffs"),
+    (lambda g, c, s, o: setattr(g, "n", -1), "out of range"),
+    (lambda g, c, s, o: setattr(g, "means", None), "NULL"),
+    (lambda g, c, s, o: setattr(g, "quats", 0x30004), "aligned"),
+    (lambda g, c, s, o: c.R_cw.__setitem__(3, float("nan")), "non-finite"),
+    (lambda g, c, s, o: setattr(s, "alpha_min", 0.0), "alpha_min"),
+    (lambda g, c, s, o: setattr(s, "T_min", 1.5), "T_min"),
+    (lambda g, c, s, o: setattr(o, "image", None), "NULL"),
+])
+def test_invalid_arguments(lib, mutate, needle):
+    g, c, s, out = _fake_args()
+    mutate(g, c, s, out)
+    alloc, calls, keep = _alloc(fail=True)
+    rc = _forward(lib, g, c, s, out, alloc)
+    assert rc == B.OMNIGS_ERR_INVALID
+    assert needle in B.omnigs_last_error()
+    assert calls == []  # rejected before allocating
+
+
+def test_allocator_failure_reports_err_alloc(lib):
+    g, c, s, out = _fake_args(n=1000)
+    alloc, calls, keep = _alloc(fail=True)
+    rc = _forward(lib, g, c, s, out, alloc)
+    assert rc == B.OMNIGS_ERR_ALLOC
+    assert "allocator returned NULL" in B.omnigs_last_error()
+    assert len(calls) == 1 and calls[0][1] == B.OMNIGS_MEM_STATE and calls[0][0] >= 1000 * 48
+
+
+def test_l1_and_backward_argument_checks(lib):
+    alloc, calls, keep = _alloc(fail=True)
+    assert lib.omnigs_l1_loss(None, None, 10, None, None, alloc, None) == B.OMNIGS_ERR_INVALID
+    assert lib.omnigs_l1_loss(0x1000, 0x2000, 0, None, 0x3000, alloc, None) == B.OMNIGS_ERR_INVALID
+    assert lib.omnigs_l1_loss(0x1000, 0x2000, 10, None, 0x3000, alloc, None) == B.OMNIGS_ERR_ALLOC
+    g, c, s, out = _fake_args()
+    st = B.c_state()
+    st.n, st.width, st.height = 5, 64, 32  # does not match n = 10
+    gr = B.c_grads(0x1000, 0x2000, 0x3000, 0x4000, 0x5000, 0x6000)
+    rc = lib.omnigs_backward(ctypes.byref(g), ctypes.byref(c), ctypes.byref(s), ctypes.byref(st), ctypes.byref(out),
+                             0x9000, ctypes.byref(gr), alloc, None)
+    assert rc == B.OMNIGS_ERR_INVALID and "state does not match" in B.omnigs_last_error()
+
+
+def test_profile_stage_names(lib):
+    n = lib.omnigs_profile_num_stages()
+    names = [lib.omnigs_profile_stage_name(k).decode() for k in range(n)]
+    assert names[:6] == ["project", "depth_sort", "emit", "tile_sort", "tile_ranges", "blend_fwd"]
+    assert "blend_bwd" in names and "project_bwd" in names
+    assert lib.omnigs_profile_stage_name(n).decode() == ""

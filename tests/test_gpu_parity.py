@@ -1,0 +1,263 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Same seeded inputs on both sides; comparison rules in ``parity.py``.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2404_03202_amd import omnigs as B
+from paper_2404_03202_amd import scenes
+from paper_2404_03202_amd.raster import rasterize
+
+import parity
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def to_dev(g):
+    d = {k: torch.from_numpy(np.ascontiguousarray(v, dtype=np.float32)).to(DEV)
+         for k, v in g.items() if k != "sh_degree"}
+    d["sh_degree"] = g["sh_degree"]
+    return d
+
+
+def gpu_forward(g, cam, settings=None):
+    r = B.omnigs_forward(to_dev(g), cam, settings)
+    torch.cuda.synchronize()
+    return r
+
+
+def np_(t):
+    return t.detach().cpu().numpy()
+
+
+def flagged_gaussians(sc):
+    rec = O.project(sc)
+    return np.nonzero(rec[:, O.REC_FIELDS["flag"]] > 0)[0]
+
+
+def compare_forward(g, cam, settings=None, lists=True, what="", max_excluded=1e-3):
+    sc = O.Scene(g, cam, settings)
+    orc = O.render(sc)
+    r = gpu_forward(g, cam, settings)
+    rep = parity.check_image(np_(r.image), orc, what=what, max_excluded=max_excluded)
+    parity.check_transmittance(np_(r.final_T), np_(r.n_contrib), orc)
+    if lists:
+        t, gid, tr = O.tile_lists(sc)
+        it, ig, rng = (np_(x) for x in r.instance_lists())
+        rep.update(parity.check_tile_lists(it, ig, t, gid, tr, flagged_gaussians(sc)))
+        # per-tile ranges agree with the sorted ids
+        ntiles = sc.tiles_x * sc.tiles_y
+        counts = np.bincount(t, minlength=ntiles)
+        np.testing.assert_array_equal(rng[:, 1] - rng[:, 0], counts)
+    return r, orc, rep
+
+
+# ---------------------------------------------------------------- forward
+def test_forward_config0():
+    g, cam = scenes.config0()
+    r, orc, rep = compare_forward(g, cam, what="config0")
+    assert rep["M"] == r.n_instances > 1000
+    assert rep["excluded"] == 0.0
+    # depth order of the Gaussians: by (t_r, id), culled last
+    rec = O.project(O.Scene(g, cam))
+    vis = rec[:, 0] > 0
+    ids = np.arange(len(vis))
+    expect = np.concatenate([ids[vis][np.lexsort((ids[vis], rec[vis, 4].astype(np.float32)))], ids[~vis]])
+    np.testing.assert_array_equal(np_(r.depth_order()), expect)
+
+
+def test_forward_config1_image():
+    g, cam, _ = scenes.config1()
+    r, orc, rep = compare_forward(g, cam, what="config1")
+    print("config1 forward", rep)
+
+
+EDGE = {
+    "ragged_height": lambda: (scenes.shell_scene(50, 3000), scenes.camera(96, 40)),
+    "seam_straddlers": lambda: (scenes.room_scene(51, 4000, seam_fraction=0.5), scenes.camera(256, 128)),
+    "near_pole_full_rows": lambda: (scenes.shell_scene(52, 500, r0=0.5, r1=1.5, scale_lo=0.1, scale_hi=0.4),
+                                    scenes.camera(128, 64, scenes.rot_y(0.2).T @ np.array(
+                                        [[1, 0, 0], [0, 0, -1], [0, 1, 0]]))),
+    "long_lists": lambda: (scenes.shell_scene(53, 6000, r0=2, r1=4, scale_lo=0.1, scale_hi=0.6), scenes.camera(64, 32)),
+    "single_tile_image": lambda: (scenes.shell_scene(54, 300), scenes.camera(16, 16)),
+    "odd_n": lambda: (scenes.shell_scene(55, 4097), scenes.camera(128, 64, scenes.rot_y(2.0).T, [0.3, -0.4, 0.2])),
+}
+
+
+@pytest.mark.parametrize("case", sorted(EDGE))
+def test_forward_edge_cases(case):
+    g, cam = EDGE[case]()
+    # near-ties grow with the number of decisions per pixel: ~800 in long_lists
+    compare_forward(g, cam, settings=dict(bg=(0.1, 0.3, 0.2)), what=case,
+                    max_excluded=2e-2 if case == "long_lists" else 1e-3)
+
+
+@pytest.mark.parametrize("degree,coeffs", [(0, 1), (1, 4), (2, 9), (2, 16), (3, 16)])
+def test_forward_sh_degrees(degree, coeffs):
+    g = scenes.shell_scene(60 + degree, 2000)
+    g = dict(g, sh_degree=degree, sh=np.ascontiguousarray(g["sh"][:, :coeffs, :]))
+    compare_forward(g, scenes.camera(128, 64, scenes.rot_y(0.5).T, [0.2, 0.1, 0.0]), what=f"sh{degree}")
+
+
+def test_forward_empty_and_culled():
+    cam = scenes.camera(64, 32)
+    bg = (0.25, 0.5, 0.75)
+    empty = dict(means=np.zeros((0, 3)), scales=np.zeros((0, 3)), quats=np.zeros((0, 4)), opacities=np.zeros(0),
+                 sh=np.zeros((0, 16, 3)), sh_degree=3)
+    r = gpu_forward(empty, cam, dict(bg=bg))
+    assert r.n_instances == 0
+    np.testing.assert_array_equal(np_(r.image), np.broadcast_to(np.array(bg, np.float32)[:, None, None], (3, 32, 64)))
+    assert (np_(r.final_T) == 1.0).all() and (np_(r.n_contrib) == 0).all()
+    g = scenes.shell_scene(70, 500)
+    g["opacities"][:] = 1.0 / 300.0        # below alpha_min: never visible
+    g["means"][:250] *= 0.01               # inside the near sphere
+    r = gpu_forward(g, cam, dict(bg=bg))
+    assert r.n_instances == 0
+    assert (np_(r.n_tiles()) == 0).all()
+
+
+def test_forward_deterministic():
+    g, cam, _ = scenes.config1()
+    a = gpu_forward(g, cam)
+    b = gpu_forward(g, cam)
+    assert torch.equal(a.image, b.image) and torch.equal(a.n_contrib, b.n_contrib)
+
+
+def test_seam_roll_symmetry_gpu():
+    """Yawing by 2 pi k / W rolls the image by k columns (Gaussians across
+    the seam included)."""
+    W, H = 256, 128
+    g = scenes.room_scene(80, 20000, seam_fraction=0.3)
+    base = np_(gpu_forward(g, scenes.camera(W, H)).image)
+    for k in (1, 37, 128):
+        R = scenes.rot_y(2 * np.pi * k / W)
+        img = np_(gpu_forward(g, dict(R=R, t=np.zeros(3), width=W, height=H)).image)
+        assert np.abs(img - np.roll(base, k, axis=2)).max() <= 1e-4
+
+
+def test_l1_loss_kernel():
+    rng = np.random.default_rng(3)
+    a = rng.normal(size=(3, 100, 64)).astype(np.float32)
+    b = rng.normal(size=(3, 100, 64)).astype(np.float32)
+    b[0, 0, :7] = a[0, 0, :7]
+    loss, grad = B.omnigs_l1_loss(torch.from_numpy(a).to(DEV), torch.from_numpy(b).to(DEV))
+    ref, gref = O.l1(a, b)
+    assert float(loss) == pytest.approx(ref, rel=1e-6)
+    np.testing.assert_array_equal(np_(grad), gref.astype(np.float32))
+
+
+# --------------------------------------------------------------- backward
+def _oracle_cotangent(sc, orc, target):
+    """dL/dC of the oracle's L1 loss, zeroed at pixels with a near-tie
+    decision (where the blend itself, hence its gradient, may differ)."""
+    _, dl = O.l1(orc["image"], target)
+    dl[:, orc["n_grad_flags"] > 0] = 0.0
+    return dl
+
+
+def compare_backward(g, cam, target_g=None, settings=None, names=("means", "scales", "quats", "opacities", "sh",
+                                                                  "screen")):
+    sc = O.Scene(g, cam, settings)
+    orc = O.render(sc)
+    if target_g is None:
+        target = np.zeros_like(orc["image"]) + 0.3
+    else:
+        target = O.render(O.Scene(target_g, cam, settings), alt=False)["image"]
+    dl = _oracle_cotangent(sc, orc, target)
+    ob = O.backward(sc, dl)
+    gd = to_dev(g)
+    fwd = B.omnigs_forward(gd, cam, settings)
+    grads = B.omnigs_backward(gd, cam, settings, fwd, torch.from_numpy(dl.astype(np.float32)).to(DEV))
+    torch.cuda.synchronize()
+    gg = {k: np_(v) for k, v in grads.items()}
+    return parity.check_grads(gg, ob, names, skip_rows=flagged_gaussians(sc))
+
+
+@pytest.mark.parametrize("degree", [0, 1, 3])
+def test_backward_small(degree):
+    g = scenes.shell_scene(90 + degree, 3000, r0=1.0, r1=5.0, scale_lo=0.02, scale_hi=0.4)
+    g = dict(g, sh_degree=degree)
+    cam = scenes.camera(128, 64, scenes.rot_y(0.8).T, [0.2, -0.1, 0.3])
+    rep = compare_backward(g, cam, scenes.perturbed(90 + degree, g), settings=dict(bg=(0.1, 0.2, 0.3)))
+    print("backward small", degree, rep)
+
+
+def test_backward_config1():
+    g, cam, gt = scenes.config1()
+    rep = compare_backward(g, cam, gt)
+    print("backward config1", rep)
+
+
+def test_autograd_matches_finite_differences_config1():
+    """The autograd.Function gradients of the L1 loss (through PyTorch's own
+    exp / sigmoid activations of log-scales and opacity logits) match central
+    differences (h = 1e-3, FP64 oracle) on 64 random raw parameters whose
+    perturbation flips no discrete decision."""
+    g, cam, gt = scenes.config1()
+    sc = O.Scene(g, cam)
+    orc = O.render(sc)
+    target = O.render(O.Scene(gt, cam), alt=False)["image"]
+    dl = _oracle_cotangent(sc, orc, target)
+    # raw optimiser parameters
+    raw = dict(means=g["means"].astype(np.float64), log_scales=np.log(g["scales"].astype(np.float64)),
+               quats=g["quats"].astype(np.float64),
+               logits=np.log(g["opacities"].astype(np.float64) / (1 - g["opacities"].astype(np.float64))),
+               sh=g["sh"].astype(np.float64))
+    t = {k: torch.tensor(v, dtype=torch.float32, device=DEV, requires_grad=True) for k, v in raw.items()}
+    img, _, _ = rasterize(t["means"], torch.exp(t["log_scales"]), t["quats"], torch.sigmoid(t["logits"]), t["sh"],
+                          cam, sh_degree=3)
+    (img * torch.from_numpy(dl.astype(np.float32)).to(DEV)).sum().backward()
+    grad = {k: np_(v.grad).astype(np.float64) for k, v in t.items()}
+    # |contribution| scales of the activated parameters, chained to the raw ones
+    ob = O.backward(sc, dl)
+    sc_ = g["scales"].astype(np.float64)
+    op_ = g["opacities"].astype(np.float64)
+    A = dict(means=ob["abs_means"], log_scales=ob["abs_scales"] * sc_, quats=ob["abs_quats"],
+             logits=(ob["abs_opacities"] * op_ * (1 - op_))[:, None], sh=ob["abs_sh"].reshape(sc.n, -1))
+    weight = (orc["n_grad_flags"] == 0).astype(np.float64)
+
+    def scene_of(p):
+        return sc.with_params(means=p["means"], scales=np.exp(p["log_scales"]), quats=p["quats"],
+                              opacities=1 / (1 + np.exp(-p["logits"])), sh=p["sh"])
+
+    rec = O.project(sc)
+    rng = scenes.rng_for(1, scenes.STREAM_FD)
+    ntx, nty = sc.tiles_x, sc.tiles_y
+    checked = rejected = 0
+    widths = dict(means=3, log_scales=3, quats=4, logits=1, sh=48)
+    names = sorted(widths)
+    while checked < 64 and rejected < 400:
+        name = names[rng.integers(len(names))]
+        i = int(rng.integers(sc.n))
+        k = int(rng.integers(widths[name]))
+        if rec[i, 0] == 0 or rec[i, 32] > 64:
+            continue
+        h = 1e-3
+        # tiles the Gaussian can touch at +-h: its rect grown by a margin
+        mask = np.zeros((nty, ntx), np.uint8)
+        ty0, nty_i, tx0, ntx_i = int(rec[i, 30]), int(rec[i, 31]), int(rec[i, 28]), int(rec[i, 29])
+        for ty in range(max(0, ty0 - 1), min(nty, ty0 + nty_i + 1)):
+            for dx in range(-1, ntx_i + 1):
+                mask[ty, (tx0 + dx) % ntx] = 1
+        vals, sigs = {}, set()
+        for d in (h, -h, h / 2, -h / 2):
+            p = {kk: vv.copy() for kk, vv in raw.items()}
+            p[name].reshape(sc.n, -1)[i, k] += d
+            # L1 against the oracle target, restricted to the masked tiles;
+            # the cotangent's zeroed (flagged) pixels are excluded likewise
+            vals[d], s = O.l1_tiles(scene_of(p), target, mask, weight)
+            sigs.add(s)
+        if len(sigs) != 1:
+            rejected += 1
+            continue
+        fd = (4 * (vals[h / 2] - vals[-h / 2]) / h - (vals[h] - vals[-h]) / (2 * h)) / 3
+        an = grad[name].reshape(sc.n, -1)[i, k]
+        a_ik = A[name].reshape(sc.n, -1)[i, k]
+        assert abs(an - fd) <= parity.GRAD_REL * max(abs(fd), parity.GRAD_FLOOR * a_ik), (name, i, k, an, fd, a_ik)
+        checked += 1
+    assert checked == 64, (checked, rejected)
