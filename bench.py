@@ -1,0 +1,143 @@
+#!/usr/bin/env python
+"""ERP rasterizer benchmark: forward + L1 + backward iterations per second.
+
+Workload: 1M Gaussians in the indoor room layout (70% on the faces of an
+axis-aligned box, 30% in a shell, 20% moved across the +-pi seam), SH degree
+3, 2048x1024 ERP images, 200 seeded poses (centre in the unit ball, random
+yaw).  One step = one pose: omnigs_forward (project, depth sort, emit, tile
+sort, ranges, blend), omnigs_l1_loss against a per-pose target image (the
+render of a perturbed copy of the scene, prepared before timing), and
+omnigs_backward (reverse blend, projection chain).  Inputs are resident in
+HBM when timing starts.
+
+Prints one JSON line (stdout) with the throughput, the roofline of the
+dominant kernel (from HIP-event timings of every stage taken during the timed
+region) and the FP64 CPU oracle timed on one pose of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_VECTOR = 157.3e12   # FLOP/s, MI355X published dense FP32 vector
+PEAK_HBM = 8.0e12             # B/s
+
+# Algorithmic FP32 work per (pixel, instance) pair of the blend (FMA = 2):
+# evaluating alpha (offsets, quadratic form, exp2, opacity, clamp) = 12;
+# the backward's gradient terms for a pair that was blended = 24.
+FLOP_ALPHA = 12
+FLOP_GRAD = 24
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(g, pose, gt_image):
+    """FP64 oracle, one pose (forward + L1 + backward) on the host cores."""
+    from oracle import oracle as O
+    sc = O.Scene(g, pose)
+    t0 = time.perf_counter()
+    r = O.render(sc, alt=False)
+    _, dl = O.l1(r["image"], gt_image)
+    O.backward(sc, dl, with_abs=False)
+    dt = time.perf_counter() - t0
+    return dict(value=1.0 / dt, unit="iters/s", cores=O.num_threads(), kind="oracle",
+                sample=f"1 of 200 poses (pose 0), full 1M Gaussians at 2048x1024: forward + L1 + backward, "
+                       f"{dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--poses", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only (the rasterizer has no multi-GPU path); "
+              "use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2404_03202_amd import omnigs as B
+    from paper_2404_03202_amd import scenes
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    g, poses, gt = scenes.config2(n_poses=args.poses)
+    log(f"scene: {g['means'].shape[0]} Gaussians, {len(poses)} poses ({time.perf_counter() - t0:.1f} s)")
+    gd = {k: (torch.from_numpy(v).to(dev) if k != "sh_degree" else v) for k, v in g.items()}
+    gtd = {k: (torch.from_numpy(v).to(dev) if k != "sh_degree" else v) for k, v in gt.items()}
+    targets = []
+    for p in poses:
+        targets.append(B.omnigs_forward(gtd, p).image.clone())
+    del gtd
+    torch.cuda.synchronize()
+    log("targets rendered")
+
+    def step(k):
+        p = poses[k % len(poses)]
+        fwd = B.omnigs_forward(gd, p)
+        loss, dl = B.omnigs_l1_loss(fwd.image, targets[k % len(poses)])
+        B.omnigs_backward(gd, p, None, fwd, dl)
+        return fwd
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    B.omnigs_profile_read()
+    B.omnigs_profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.warmup, args.warmup + args.steps):
+        step(k)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    B.omnigs_profile_enable(False)
+    prof = B.omnigs_profile_read()
+    log("stages (ms per step): " + ", ".join(f"{k} {v[0] / args.steps:.3f}" for k, v in prof.items() if v[1]))
+
+    # pairs walked / blended by the timed steps (deterministic re-render)
+    walked = blended = 0
+    for k in range(args.warmup, args.warmup + args.steps):
+        f = B.omnigs_forward(gd, poses[k % len(poses)], with_blended=True)
+        walked += int(f.n_contrib.sum(dtype=torch.int64))
+        blended += int(f.n_blended.sum(dtype=torch.int64))
+    bwd_ms, bwd_n = prof["blend_bwd"]
+    flops = FLOP_ALPHA * walked + FLOP_GRAD * blended
+    achieved = flops / (bwd_ms * 1e-3)
+    dominant = max(((k, v[0]) for k, v in prof.items()), key=lambda kv: kv[1])[0]
+    roofline = dict(kernel="blend_bwd", bound="alu", achieved=achieved / 1e12, peak=PEAK_FP32_VECTOR / 1e12,
+                    unit="TFLOP/s", frac=achieved / PEAK_FP32_VECTOR, traffic=None,
+                    avg_launch_ms=bwd_ms / max(bwd_n, 1), pairs_walked_per_launch=walked / max(bwd_n, 1),
+                    pairs_blended_per_launch=blended / max(bwd_n, 1), dominant_stage=dominant)
+
+    out = dict(metric="ERP fwd+bwd iters/s @1M Gaussians 2048x1024", value=args.steps / dt, unit="iters/s",
+               n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=dt * 1e3 / args.steps,
+               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
+               config=dict(workload="1M Gaussians, room layout with 20% across the seam, SH degree 3, "
+                                    "2048x1024 ERP, 200 poses, forward + L1 + backward per pose",
+                           gaussians=int(g["means"].shape[0]), width=2048, height=1024, poses=len(poses)),
+               stage_ms={k: v[0] / args.steps for k, v in prof.items() if v[1]},
+               roofline=roofline)
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, one pose)...")
+        out["cpu_baseline"] = cpu_baseline(g, poses[0], targets[0].cpu().numpy().astype(np.float64))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -97,6 +97,8 @@ typedef struct {
     float *image;       /* [3][H][W]  C + T_final * bg  (Eq. 6)                   */
     float *final_T;     /* [H][W]     transmittance after the last blended one   */
     int32_t *n_contrib; /* [H][W]     1 + tile-list position of the last blended */
+    int32_t *n_blended; /* [H][W]     instances blended (alpha >= alpha_min);
+                           optional: NULL skips it                              */
 } omnigs_image_out;
 
 /* Saved forward state (filled by omnigs_forward, read by omnigs_backward).
@@ -112,6 +114,8 @@ typedef struct {
     const uint32_t *inst_tile;   /* [M] tile id of each sorted instance             */
     const uint32_t *inst_gauss;  /* [M] Gaussian id of each sorted instance         */
     const uint32_t *tile_range;  /* [tiles][2] [start, end) into the sorted list    */
+    const uint32_t *tile_work;   /* [tiles] largest n_contrib of the tile (the
+                                    backward's walk length)                        */
 } omnigs_state;
 
 /* Parameter gradients (device, caller-allocated, overwritten). */

@@ -609,9 +609,10 @@ int64_t orc_tile_lists(const orc_scene *s, int64_t cap, int32_t *tile_out, int32
  * n_flags [H][W]; alt (may be NULL) receives, for pixels with exactly one
  * flagged decision, the value with that decision inverted (else the value);
  * n_grad_flags (may be NULL) also counts alpha_max-clamp near-ties, where
- * the gradient (not the value) changes. */
+ * the gradient (not the value) changes; n_blended (may be NULL) counts the
+ * instances blended into each pixel. */
 int orc_render(const orc_scene *s, const uint8_t *tile_mask, double *image, double *final_T, int32_t *n_contrib,
-               int32_t *n_flags, double *alt, int32_t *n_grad_flags) {
+               int32_t *n_flags, double *alt, int32_t *n_grad_flags, int32_t *n_blended) {
     if (s->width % ORC_TILE != 0 || s->height < 1) return -1;
     orc_lists L;
     if (build_lists(s, tile_mask, &L) != 0) {
@@ -632,6 +633,7 @@ int orc_render(const orc_scene *s, const uint8_t *tile_mask, double *image, doub
         n_contrib[p] = px.n_contrib;
         n_flags[p] = px.n_flags;
         if (n_grad_flags) n_grad_flags[p] = px.n_grad_flags;
+        if (n_blended) n_blended[p] = px.n_blended;
         if (alt) {
             if (px.n_flags == 1) {
                 orc_pixel q;

@@ -84,7 +84,7 @@ def _load():
         _lib.orc_project.restype = ctypes.c_int
         _lib.orc_tile_lists.argtypes = [P(_Scene), ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         _lib.orc_tile_lists.restype = ctypes.c_int64
-        _lib.orc_render.argtypes = [P(_Scene)] + [ctypes.c_void_p] * 7
+        _lib.orc_render.argtypes = [P(_Scene)] + [ctypes.c_void_p] * 8
         _lib.orc_render.restype = ctypes.c_int
         _lib.orc_l1_tiles.argtypes = [P(_Scene)] + [ctypes.c_void_p] * 5
         _lib.orc_l1_tiles.restype = ctypes.c_int
@@ -223,7 +223,7 @@ def _mask(scene, tile_mask):
 
 def render(scene: Scene, alt: bool = True, tile_mask=None):
     """Forward render: dict(image [3,H,W], final_T [H,W], n_contrib [H,W],
-    n_flags [H,W], alt [3,H,W] or None, n_grad_flags [H,W]).  With
+    n_flags [H,W], alt [3,H,W] or None, n_grad_flags [H,W], n_blended [H,W]).  With
     ``tile_mask`` ([tiles] bool) only those tiles are rendered (the other
     pixels stay zero)."""
     lib = _load()
@@ -234,13 +234,15 @@ def render(scene: Scene, alt: bool = True, tile_mask=None):
     nf = np.zeros((H, W), dtype=np.int32)
     altimg = np.zeros((3, H, W)) if alt else None
     ngf = np.zeros((H, W), dtype=np.int32)
+    nbl = np.zeros((H, W), dtype=np.int32)
     s = scene._struct()
     m = _mask(scene, tile_mask)
     rc = lib.orc_render(ctypes.byref(s), m.ctypes.data if m is not None else None, image.ctypes.data, T.ctypes.data,
-                        nc.ctypes.data, nf.ctypes.data, altimg.ctypes.data if alt else None, ngf.ctypes.data)
+                        nc.ctypes.data, nf.ctypes.data, altimg.ctypes.data if alt else None, ngf.ctypes.data,
+                        nbl.ctypes.data)
     if rc != 0:
         raise ValueError("oracle: invalid scene")
-    return dict(image=image, final_T=T, n_contrib=nc, n_flags=nf, alt=altimg, n_grad_flags=ngf)
+    return dict(image=image, final_T=T, n_contrib=nc, n_flags=nf, alt=altimg, n_grad_flags=ngf, n_blended=nbl)
 
 
 def l1(image, target):

@@ -1,28 +1,54 @@
 // blend.hip -- front-to-back alpha blending of the sorted tile lists (Eq. 6-8,
 // Sec. 3.3) and its reverse-order backward (Sec. 3.4).
 //
-// One workgroup of 256 lanes (four wave64s) per 16x16 tile, one lane per
-// pixel.  The workgroup stages the next 256 instances of its tile list in
-// LDS (each lane gathers one 48-byte record), then every lane walks the
-// staged batch.  Positions are made tile-relative when staged, from the
-// record's hi/lo split, so per-pixel offsets keep full precision at any
-// image width; the x offset is then wrapped to the shortest signed offset
-// on the circle of circumference W (the longitude seam).
+// One workgroup per 16x16 tile, of kW wave64s (1, 2 or 4; a template
+// parameter, chosen separately for the two kernels).  The tile's four 8x8
+// quadrants are split between the waves; each lane owns one pixel of each
+// quadrant of its wave (4 / kW pixels).  More waves shorten the longest
+// per-wave walk (a tile's list is split by quadrant); more pixels per lane
+// amortise the backward's cross-lane reduction over more pixels.
 //
-// alpha = min(alpha_max, o * exp(-1/2 d^T Q d)) is evaluated by one inline
-// function in both kernels, with explicit FMAs, so that the backward re-walk
-// takes exactly the forward's decisions (skip below alpha_min, stop before
-// T < T_min) from the saved final T and contributor count.
+// The workgroup stages the next kBatch = 64 kW instances of its tile list in
+// LDS (each lane gathers one 48-byte record); positions are made
+// tile-relative from the record's hi/lo split, so pixel offsets keep full
+// precision at any width.  The x offset is the shortest signed offset on the
+// circle of circumference W (the longitude seam).
 //
-// The backward reduces each instance's nine per-pixel gradient terms over
-// the wave (DPP row sums plus two cross-row shuffles) and over the four
-// waves (LDS), then issues one float atomic per field per (tile, instance).
+// The lane that stages an instance also tests which quadrants its
+// alpha >= alpha_min ellipse can reach (the exact minimum of the quadratic
+// form over each quadrant's pixel-centre rectangle, with a safety margin).
+// Each wave then compacts, in order, the staged instances that reach one of
+// its quadrants and walks only those, skipping unreached quadrants with a
+// uniform branch: a skipped instance holds no pixel of the quadrant whose
+// alpha could pass alpha_min, so the image is unchanged.
+//
+// alpha = min(alpha_max, o * exp(-1/2 d^T Q d)) is evaluated per pixel by the
+// same inline function in both kernels, with explicit FMAs (the library is
+// built without FP contraction), and both use the same quadrant test, so the
+// backward re-walk takes exactly the forward's decisions (skip below
+// alpha_min, stop before T < T_min) from the saved final T and contributor
+// count, whatever the wave layout of each kernel.
+//
+// Backward reduction: a wave sums an instance's nine gradient terms to lane
+// 63 with DPP (quad permutes, row rotations, row broadcasts: no LDS traffic)
+// and adds them into the instance's LDS slot; after the batch, the lane that
+// staged the instance converts the sums and issues the float atomics to
+// global memory (one per nonzero field per (tile, instance)).
 #include "internal.h"
+
+#ifndef OMNIGS_FWD_WAVES
+#define OMNIGS_FWD_WAVES 4
+#endif
+#ifndef OMNIGS_BWD_WAVES
+#define OMNIGS_BWD_WAVES 2
+#endif
 
 namespace omnigs {
 namespace {
 
 constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.69314718055994531f;
+constexpr int kQuads = 4;  // 8x8 quadrants per tile
 
 struct BlendFrame {
     int width, height, tiles_x, tiles_y;
@@ -30,7 +56,8 @@ struct BlendFrame {
     float *image;
     float *final_T;
     int32_t *n_contrib;
-    const float *dL;  // backward only
+    int32_t *n_blended;  // forward only, may be null
+    const float *dL;     // backward only
 };
 
 constexpr int kMaxFrames = 32;
@@ -46,259 +73,464 @@ __device__ inline int find_frame(const FrameTable &T, uint32_t tile) {
     return f;
 }
 
-// Stage one instance in LDS: position relative to the tile origin, conic
-// pre-scaled so that the exponent is evaluated in base 2:
-//   p2 = c00 dx^2 + c01 dx dy + c11 dy^2 = log2(e) * (-1/2 d^T Q d).
-__device__ inline void stage(const BlendRecord *rec, uint32_t gid, float X0, float Y0, float W, float *sx,
-                             float *sy, float4 *sc, float4 *scol, int slot) {
+// Staged instances (LDS):
+//   a = (x, y, c00, c01), b = (c11, o, r, g), c = b, quad = quadrant mask
+// with (x, y) the centre relative to the tile origin and the conic
+// pre-scaled for a base-2 exponent: c00 dx^2 + c01 dx dy + c11 dy^2 =
+// log2(e) * (-1/2 d^T Q d).  list[w] holds, for wave w, the staged slots
+// that reach one of its quadrants, in order, as slot | (wave mask << 8).
+template <int kW>
+struct Stage {
+    static constexpr int kBatch = kWave * kW;
+    float4 a[kBatch], b[kBatch];
+    float c[kBatch];
+    uint32_t quad[kBatch];
+    uint32_t gid[kBatch];
+    uint16_t list[kW][kBatch];
+};
+
+// Minimum of q(u, v) = qa u^2 + 2 qb u v + qc v^2 (positive definite) over
+// the rectangle [u0, u1] x [v0, v1]: zero if it holds the origin, else the
+// least of the four edges' clamped one-dimensional minima (ra = 1/qa,
+// rc = 1/qc).
+__device__ inline float rect_min_quadratic(float qa, float qb, float qc, float ra, float rc, float u0, float u1,
+                                           float v0, float v1) {
+    if (u0 <= 0.0f && u1 >= 0.0f && v0 <= 0.0f && v1 >= 0.0f) return 0.0f;
+    float best = __builtin_huge_valf();
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const float u = e ? u1 : u0;
+        const float v = fminf(fmaxf(-qb * u * rc, v0), v1);
+        best = fminf(best, qa * u * u + 2.0f * qb * u * v + qc * v * v);
+    }
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const float v = e ? v1 : v0;
+        const float u = fminf(fmaxf(-qb * v * ra, u0), u1);
+        best = fminf(best, qa * u * u + 2.0f * qb * u * v + qc * v * v);
+    }
+    return best;
+}
+
+// Stage the record of Gaussian gid in slot `slot`.
+template <int kW>
+__device__ inline void stage(const BlendRecord *rec, uint32_t gid, float X0, float Y0, float W, Stage<kW> &S,
+                             int slot) {
     const float4 *p = reinterpret_cast<const float4 *>(rec + gid);
-    const float4 a = p[0], b = p[1], c = p[2];
-    float x = (a.x - X0) + a.y;  // px_hi - X0 is exact near the tile
-    const float y = (a.z - Y0) + a.w;
+    const float4 ra4 = p[0], rb4 = p[1], rc4 = p[2];
+    float x = (ra4.x - X0) + ra4.y;  // px_hi - X0 is exact near the tile
+    const float y = (ra4.z - Y0) + ra4.w;
     // bring the centre within half a turn of the tile's middle column
     const float half = 0.5f * W;
     if (x - 8.0f >= half) x -= W;
     if (x - 8.0f < -half) x += W;
-    sx[slot] = x;
-    sy[slot] = y;
-    sc[slot] = make_float4(-0.5f * kLog2e * b.x, -kLog2e * b.y, -0.5f * kLog2e * b.z, b.w);
-    scol[slot] = c;
+    const float c00 = -0.5f * kLog2e * rb4.x, c01 = -kLog2e * rb4.y, c11 = -0.5f * kLog2e * rb4.z;
+    // quadrants the alpha >= alpha_min region can reach:
+    // -(c00 u^2 + c01 u v + c11 v^2) <= log2(o / alpha_min), with a margin;
+    // the clamped edge minima only need to be near-exact: a slightly wrong
+    // clamp point still bounds the minimum over an edge from above, and the
+    // margin absorbs the rounding
+    const float reach = rc4.w + 1e-3f * (1.0f + fabsf(rc4.w));
+    const float qa = -c00, qb = -0.5f * c01, qc = -c11;
+    const float ra = __builtin_amdgcn_rcpf(qa), rc = __builtin_amdgcn_rcpf(qc);
+    uint32_t quad = 0;
+#pragma unroll
+    for (int k = 0; k < kQuads; ++k) {
+        const float qx = (float)((k & 1) * 8), qy = (float)((k >> 1) * 8);
+        const float u0 = qx + 0.5f - x, u1 = qx + 7.5f - x;
+        const float v0 = qy + 0.5f - y, v1 = qy + 7.5f - y;
+        // offsets that the seam wrap may shift: keep the quadrant
+        const bool wraps = u0 < -half || u1 >= half;
+        if (wraps || rect_min_quadratic(qa, qb, qc, ra, rc, u0, u1, v0, v1) <= reach) quad |= 1u << k;
+    }
+    S.a[slot] = make_float4(x, y, c00, c01);
+    S.b[slot] = make_float4(c11, rb4.w, rc4.x, rc4.y);
+    S.c[slot] = rc4.z;
+    S.quad[slot] = quad;
+    S.gid[slot] = gid;
 }
 
-// alpha of one staged instance at pixel centre (fx, fy) (tile-relative);
-// returns the unclamped alpha, writes the clamped one and the pixel offset.
-__device__ __forceinline__ float eval_alpha(float fx, float fy, float x, float y, float4 conic, float W, float half,
-                                            float alpha_max, float &alpha, float &dx, float &dy, float &G) {
-    float d = fx - x;
+// Wave w lists, in order, the staged slots in [lo, nb) that reach one of its
+// quadrants; returns the count (uniform).
+template <int kW>
+__device__ inline int compact(Stage<kW> &S, int w, int lo, int nb) {
+    constexpr int kPPL = kQuads / kW;
+    const int lane = __lane_id();
+    int n = 0;
+    for (int c = 0; c < Stage<kW>::kBatch; c += kWave) {
+        const int slot = c + lane;
+        const uint32_t m = (slot >= lo && slot < nb) ? (S.quad[slot] >> (w * kPPL)) & ((1u << kPPL) - 1u) : 0u;
+        const uint64_t hits = __ballot(m != 0u);
+        if (m) S.list[w][n + __popcll(hits & ((1ull << lane) - 1ull))] = (uint16_t)(slot | (m << 8));
+        n += __popcll(hits);
+    }
+    return n;
+}
+
+// alpha at one pixel: returns the unclamped alpha, writes the clamped one,
+// G = exp(-1/2 d^T Q d) and the pixel offset (x wrapped across the seam).
+__device__ __forceinline__ float pixel_alpha(float fx, float fy, float4 a, float c11, float o, float W, float half,
+                                             float alpha_max, float &alpha, float &G, float &dx, float &dy) {
+    float d = fx - a.x;
     d = (d >= half) ? d - W : d;
     d = (d < -half) ? d + W : d;
     dx = d;
-    dy = fy - y;
-    const float t = __builtin_fmaf(conic.y, dy, conic.x * dx);
-    const float p2 = __builtin_fmaf(conic.z * dy, dy, dx * t);
+    dy = fy - a.y;
+    const float t = __builtin_fmaf(a.w, dy, a.z * dx);
+    const float p2 = __builtin_fmaf(c11 * dy, dy, dx * t);
     G = __builtin_amdgcn_exp2f(p2);
-    const float araw = conic.w * G;
+    const float araw = o * G;
     alpha = araw < alpha_max ? araw : alpha_max;
     return araw;
 }
 
-template <bool kBatched>
-__global__ __launch_bounds__(kBlendThreads) void k_blend_forward(FrameTable FT, const BlendRecord *rec,
-                                                                  const uint32_t *inst_gauss, const uint2 *ranges,
-                                                                  BlendSettings s) {
-    __shared__ float sx[kBlendThreads], sy[kBlendThreads];
-    __shared__ float4 sc[kBlendThreads], scol[kBlendThreads];
-    const uint32_t tile = blockIdx.x;
+// Pixel (inside the tile) of slot s of wave w, lane (lx, ly) of an 8x8 block.
+template <int kW>
+__device__ __forceinline__ int slot_px(int w, int s, int lx) { return (((w * (kQuads / kW)) + s) & 1) * 8 + lx; }
+template <int kW>
+__device__ __forceinline__ int slot_py(int w, int s, int ly) { return (((w * (kQuads / kW)) + s) >> 1) * 8 + ly; }
+
+template <int kW, bool kBatched>
+__global__ __launch_bounds__(kWave * kW) void k_blend_forward(FrameTable FT, const BlendRecord *rec,
+                                                               const uint32_t *inst_gauss, const uint2 *ranges,
+                                                               BlendSettings s, const uint32_t *order,
+                                                               uint32_t *tile_work) {
+    constexpr int kNT = kWave * kW, kPPL = kQuads / kW, kBatch = Stage<kW>::kBatch;
+    constexpr uint32_t kAll = (1u << kPPL) - 1u;
+    __shared__ Stage<kW> S;
+    __shared__ int s_wmax[kW];
+    const uint32_t tile = order ? order[blockIdx.x] : blockIdx.x;
     const int fi = kBatched ? find_frame(FT, tile) : 0;
     const BlendFrame &F = FT.f[fi];
     const uint32_t lt = tile - F.tile_base;
     const int tx = lt % F.tiles_x, ty = lt / F.tiles_x;
-    const int lx = threadIdx.x % kTile, ly = threadIdx.x / kTile;
-    const int x = tx * kTile + lx, y = ty * kTile + ly;
-    const bool inside = y < F.height;
+    const int w = threadIdx.x / kWave, lane = __lane_id();
+    const int lx = lane & 7, ly = lane >> 3;
     const float W = (float)F.width, half = 0.5f * W;
     const float X0 = (float)(tx * kTile), Y0 = (float)(ty * kTile);
-    const float fx = lx + 0.5f, fy = ly + 0.5f;
     const uint2 range = ranges[tile];
     const int count = (int)(range.y - range.x);
-    float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
-    int last = 0;
-    bool done = !inside;
-    for (int base = 0; base < count; base += kBlendThreads) {
-        if (__syncthreads_count(done) == kBlendThreads) break;
-        const int k = base + threadIdx.x;
-        if (k < count) stage(rec, inst_gauss[range.x + k], X0, Y0, W, sx, sy, sc, scol, threadIdx.x);
+    float T[kPPL], C0[kPPL], C1[kPPL], C2[kPPL];
+    int last[kPPL], blended[kPPL];
+    uint32_t done = 0;
+#pragma unroll
+    for (int k = 0; k < kPPL; ++k) {
+        T[k] = 1.0f;
+        C0[k] = C1[k] = C2[k] = 0.0f;
+        last[k] = blended[k] = 0;
+        if (ty * kTile + slot_py<kW>(w, k, ly) >= F.height) done |= 1u << k;
+    }
+    for (int base = 0; base < count; base += kBatch) {
+        if (__syncthreads_count(done == kAll) == kNT) break;
+        const int nb = min(kBatch, count - base);
+        if ((int)threadIdx.x < nb) stage(rec, inst_gauss[range.x + base + threadIdx.x], X0, Y0, W, S, threadIdx.x);
         __syncthreads();
-        const int nb = min(kBlendThreads, count - base);
-        for (int j = 0; !done && j < nb; ++j) {
-            float alpha, dx, dy, G;
-            eval_alpha(fx, fy, sx[j], sy[j], sc[j], W, half, s.alpha_max, alpha, dx, dy, G);
-            if (alpha < s.alpha_min) continue;
-            const float Tn = T * (1.0f - alpha);
-            if (Tn < s.T_min) {
-                done = true;
-                break;
+        if (__ballot(done != kAll) == 0ull) continue;  // this wave is finished: keep staging with the others
+        const int n = compact(S, w, 0, nb);
+        for (int t = 0; t < n; ++t) {
+            const uint32_t e = __builtin_amdgcn_readfirstlane(S.list[w][t]);
+            const int j = e & 0xff;
+            const uint32_t m = e >> 8;
+            const float4 a = S.a[j], b = S.b[j];
+            const float cb = S.c[j];
+#pragma unroll
+            for (int k = 0; k < kPPL; ++k) {
+                if (!(m & (1u << k))) continue;  // uniform
+                float alpha, G, dx, dy;
+                pixel_alpha(slot_px<kW>(w, k, lx) + 0.5f, slot_py<kW>(w, k, ly) + 0.5f, a, b.x, b.y, W, half,
+                            s.alpha_max, alpha, G, dx, dy);
+                const float Tn = T[k] * (1.0f - alpha);
+                const bool live = !(done & (1u << k)) && alpha >= s.alpha_min;
+                const bool stop = live && Tn < s.T_min;
+                const bool take = live && !stop;
+                done |= stop ? (1u << k) : 0u;
+                const float wgt = take ? alpha * T[k] : 0.0f;
+                C0[k] = __builtin_fmaf(b.z, wgt, C0[k]);
+                C1[k] = __builtin_fmaf(b.w, wgt, C1[k]);
+                C2[k] = __builtin_fmaf(cb, wgt, C2[k]);
+                T[k] = take ? Tn : T[k];
+                last[k] = take ? base + j + 1 : last[k];
+                blended[k] += take ? 1 : 0;
             }
-            const float wgt = alpha * T;
-            const float4 col = scol[j];
-            C0 = __builtin_fmaf(col.x, wgt, C0);
-            C1 = __builtin_fmaf(col.y, wgt, C1);
-            C2 = __builtin_fmaf(col.z, wgt, C2);
-            T = Tn;
-            last = base + j + 1;
+            if ((t & 15) == 15 && __ballot(done != kAll) == 0ull) break;
         }
     }
-    if (inside) {
-        const int64_t HW = (int64_t)F.width * F.height;
-        const int64_t p = (int64_t)y * F.width + x;
-        F.image[p] = __builtin_fmaf(T, s.bg[0], C0);
-        F.image[HW + p] = __builtin_fmaf(T, s.bg[1], C1);
-        F.image[2 * HW + p] = __builtin_fmaf(T, s.bg[2], C2);
-        F.final_T[p] = T;
-        F.n_contrib[p] = last;
+    // the tile's backward walk length: its largest contributor count
+    int wmax = 0;
+#pragma unroll
+    for (int k = 0; k < kPPL; ++k) wmax = max(wmax, last[k]);
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) wmax = max(wmax, __shfl_xor(wmax, off, kWave));
+    if (lane == 0) s_wmax[w] = wmax;
+    __syncthreads();
+    if (threadIdx.x == 0 && tile_work) {
+        int m = 0;
+#pragma unroll
+        for (int k = 0; k < kW; ++k) m = max(m, s_wmax[k]);
+        tile_work[tile] = (uint32_t)m;
+    }
+    const int64_t HW = (int64_t)F.width * F.height;
+#pragma unroll
+    for (int k = 0; k < kPPL; ++k) {
+        const int y = ty * kTile + slot_py<kW>(w, k, ly);
+        if (y >= F.height) continue;
+        const int64_t p = (int64_t)y * F.width + tx * kTile + slot_px<kW>(w, k, lx);
+        F.image[p] = __builtin_fmaf(T[k], s.bg[0], C0[k]);
+        F.image[HW + p] = __builtin_fmaf(T[k], s.bg[1], C1[k]);
+        F.image[2 * HW + p] = __builtin_fmaf(T[k], s.bg[2], C2[k]);
+        F.final_T[p] = T[k];
+        F.n_contrib[p] = last[k];
+        if (F.n_blended) F.n_blended[p] = blended[k];
     }
 }
 
-// Sum over the 64 lanes of the wave; every lane receives the total.
-__device__ __forceinline__ float wave_sum(float v) {
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));  // xor 1
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));  // xor 2
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x124, 0xF, 0xF, false)); // ror 4
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x128, 0xF, 0xF, false)); // ror 8
-    v += __shfl_xor(v, 16, kWave);
-    v += __shfl_xor(v, 32, kWave);
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ float dpp_add(float v) {
+    return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kCtrl, kRowMask, 0xF, false));
+}
+
+// Sum over the 64 lanes of the wave, valid in lane 63: quad sums (quad_perm
+// [1,0,3,2], [2,3,0,1]), row sums (row_ror 4, 8), then row_bcast 15 folds
+// row 0 into row 1 and row 2 into row 3, and row_bcast 31 folds rows 0-1
+// into row 3.
+__device__ __forceinline__ float wave_sum_to_last(float v) {
+    v = dpp_add<0xB1, 0xF>(v);
+    v = dpp_add<0x4E, 0xF>(v);
+    v = dpp_add<0x124, 0xF>(v);
+    v = dpp_add<0x128, 0xF>(v);
+    v = dpp_add<0x142, 0xA>(v);
+    v = dpp_add<0x143, 0xC>(v);
     return v;
 }
 
-template <bool kBatched>
-__global__ __launch_bounds__(kBlendThreads) void k_blend_backward(FrameTable FT, const BlendRecord *rec,
-                                                                   const uint32_t *inst_gauss, const uint2 *ranges,
-                                                                   BlendSettings s, float *acc) {
-    constexpr int kW = kBlendThreads / kWave;
-    __shared__ float sx[kBlendThreads], sy[kBlendThreads];
-    __shared__ float4 sc[kBlendThreads], scol[kBlendThreads];
-    __shared__ uint32_t sgid[kBlendThreads];
-    __shared__ float part[kBlendThreads][kW][kAcc];
-    __shared__ int s_max_last;
-    const uint32_t tile = blockIdx.x;
+template <int kW, bool kBatched>
+__global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, const BlendRecord *rec,
+                                                                const uint32_t *inst_gauss, const uint2 *ranges,
+                                                                BlendSettings s, float *acc, const uint32_t *order) {
+    constexpr int kNT = kWave * kW, kPPL = kQuads / kW, kBatch = Stage<kW>::kBatch;
+    __shared__ Stage<kW> S;
+    __shared__ float part[kBatch][kAcc];
+    __shared__ int s_max[kW];
+    const uint32_t tile = order ? order[blockIdx.x] : blockIdx.x;
     const int fi = kBatched ? find_frame(FT, tile) : 0;
     const BlendFrame &F = FT.f[fi];
     const uint32_t lt = tile - F.tile_base;
     const int tx = lt % F.tiles_x, ty = lt / F.tiles_x;
-    const int lx = threadIdx.x % kTile, ly = threadIdx.x / kTile;
-    const int x = tx * kTile + lx, y = ty * kTile + ly;
-    const bool inside = y < F.height;
+    const int w = threadIdx.x / kWave, lane = __lane_id();
+    const int lx = lane & 7, ly = lane >> 3;
     const float W = (float)F.width, half = 0.5f * W;
     const float X0 = (float)(tx * kTile), Y0 = (float)(ty * kTile);
-    const float fx = lx + 0.5f, fy = ly + 0.5f;
     const uint2 range = ranges[tile];
-    const int wave = threadIdx.x / kWave;
-    float T = 1.0f, dL0 = 0.0f, dL1 = 0.0f, dL2 = 0.0f;
-    int last = 0;
-    if (inside) {
-        const int64_t HW = (int64_t)F.width * F.height;
-        const int64_t p = (int64_t)y * F.width + x;
-        T = F.final_T[p];
-        last = F.n_contrib[p];
-        dL0 = F.dL[p];
-        dL1 = F.dL[HW + p];
-        dL2 = F.dL[2 * HW + p];
+    const int64_t HW = (int64_t)F.width * F.height;
+    float T[kPPL], dLS[kPPL], dL0[kPPL], dL1[kPPL], dL2[kPPL];
+    int last[kPPL];
+    int wmax = 0;
+#pragma unroll
+    for (int k = 0; k < kPPL; ++k) {
+        const int y = ty * kTile + slot_py<kW>(w, k, ly);
+        T[k] = 1.0f;
+        dL0[k] = dL1[k] = dL2[k] = 0.0f;
+        last[k] = 0;
+        if (y < F.height) {
+            const int64_t p = (int64_t)y * F.width + tx * kTile + slot_px<kW>(w, k, lx);
+            T[k] = F.final_T[p];
+            last[k] = F.n_contrib[p];
+            dL0[k] = F.dL[p];
+            dL1[k] = F.dL[HW + p];
+            dL2[k] = F.dL[2 * HW + p];
+        }
+        // dL . (colour blended behind the current instance + T_final bg)
+        dLS[k] = T[k] * (dL0[k] * s.bg[0] + dL1[k] * s.bg[1] + dL2[k] * s.bg[2]);
+        wmax = max(wmax, last[k]);
     }
-    // dL . (colour blended behind the current instance + T_final bg)
-    float dLS = T * (dL0 * s.bg[0] + dL1 * s.bg[1] + dL2 * s.bg[2]);
-    if (threadIdx.x == 0) s_max_last = 0;
+    // per-wave and per-tile maxima of the contributor counts
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) wmax = max(wmax, __shfl_xor(wmax, off, kWave));
+    if (lane == 0) s_max[w] = wmax;
     __syncthreads();
-    atomicMax(&s_max_last, last);
-    __syncthreads();
-    const int max_last = s_max_last;
-    for (int hi = max_last; hi > 0; hi -= kBlendThreads) {
-        const int lo = hi - kBlendThreads > 0 ? hi - kBlendThreads : 0;
-        const int nb = hi - lo;
+    int max_last = 0;
+#pragma unroll
+    for (int k = 0; k < kW; ++k) max_last = max(max_last, s_max[k]);
+    for (int hi = max_last; hi > 0; hi -= kBatch) {
+        const int nb = min(kBatch, hi);
         __syncthreads();
-        if (threadIdx.x < nb) {
-            const int pos = hi - 1 - threadIdx.x;  // slot j holds list position hi-1-j
-            const uint32_t g = inst_gauss[range.x + pos];
-            sgid[threadIdx.x] = g;
-            stage(rec, g, X0, Y0, W, sx, sy, sc, scol, threadIdx.x);
+        if ((int)threadIdx.x < nb) {
+            // slot i holds list position hi-1-i
+            stage(rec, inst_gauss[range.x + hi - 1 - threadIdx.x], X0, Y0, W, S, threadIdx.x);
+#pragma unroll
+            for (int f = 0; f < kAcc; ++f) part[threadIdx.x][f] = 0.0f;
         }
         __syncthreads();
-        for (int j = 0; j < nb; ++j) {
+        // positions at or past this wave's largest contributor count (slots
+        // below hi - wmax) are never blended by its pixels
+        const int n = compact(S, w, hi - wmax, nb);
+        for (int t = 0; t < n; ++t) {
+            const uint32_t e = __builtin_amdgcn_readfirstlane(S.list[w][t]);
+            const int j = e & 0xff;
+            const uint32_t m = e >> 8;
             const int pos = hi - 1 - j;
+            const float4 a = S.a[j], b = S.b[j];
+            const float cb = S.c[j];
             float v[kAcc];
 #pragma unroll
-            for (int k = 0; k < kAcc; ++k) v[k] = 0.0f;
+            for (int f = 0; f < kAcc; ++f) v[f] = 0.0f;
             bool any = false;
-            if (pos < last) {
-                float alpha, dx, dy, G;
-                const float4 conic = sc[j];
-                const float araw = eval_alpha(fx, fy, sx[j], sy[j], conic, W, half, s.alpha_max, alpha, dx, dy, G);
-                if (alpha >= s.alpha_min) {
-                    any = true;
-                    const float one_m = 1.0f - alpha;
-                    const float inv = 1.0f / one_m;
-                    T = T * inv;  // transmittance in front of this instance
-                    const float wgt = alpha * T;
-                    const float4 col = scol[j];
-                    const float dLc = dL0 * col.x + dL1 * col.y + dL2 * col.z;
-                    const float dalpha = dLc * T - dLS * inv;
-                    dLS = __builtin_fmaf(dLc, wgt, dLS);
-                    v[6] = dL0 * wgt;
-                    v[7] = dL1 * wgt;
-                    v[8] = dL2 * wgt;
-                    if (araw < s.alpha_max) {
-                        const float gp = araw * dalpha;  // dL/d(-1/2 d^T Q d)
-                        v[0] = dx * gp;
-                        v[1] = dy * gp;
-                        v[2] = dx * v[0];
-                        v[3] = dx * v[1];
-                        v[4] = dy * v[1];
-                        v[5] = G * dalpha;
+#pragma unroll
+            for (int k = 0; k < kPPL; ++k) {
+                if (!(m & (1u << k))) continue;  // uniform
+                float alpha, G, dx, dy;
+                const float araw = pixel_alpha(slot_px<kW>(w, k, lx) + 0.5f, slot_py<kW>(w, k, ly) + 0.5f, a, b.x,
+                                               b.y, W, half, s.alpha_max, alpha, G, dx, dy);
+                const bool valid = pos < last[k] && alpha >= s.alpha_min;
+                if (__ballot(valid) == 0ull) continue;  // uniform: nothing blended in this quadrant
+                any |= valid;
+                const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
+                const float Tf = T[k] * inv;  // transmittance in front of this instance
+                T[k] = valid ? Tf : T[k];
+                const float wgt = valid ? alpha * Tf : 0.0f;
+                const float dLc = dL0[k] * b.z + dL1[k] * b.w + dL2[k] * cb;
+                const float dalpha = dLc * Tf - dLS[k] * inv;
+                dLS[k] = __builtin_fmaf(dLc, wgt, dLS[k]);
+                v[6] = __builtin_fmaf(dL0[k], wgt, v[6]);
+                v[7] = __builtin_fmaf(dL1[k], wgt, v[7]);
+                v[8] = __builtin_fmaf(dL2[k], wgt, v[8]);
+                // dL/dalpha through an unclamped alpha only
+                const float da = (valid && araw < s.alpha_max) ? dalpha : 0.0f;
+                // moments of gp = dL/d(-1/2 d^T Q d) = alpha * dL/dalpha
+                const float gp = araw * da;
+                const float gx = dx * gp, gy = dy * gp;
+                v[0] += gx;
+                v[1] += gy;
+                v[2] = __builtin_fmaf(dx, gx, v[2]);
+                v[3] = __builtin_fmaf(dx, gy, v[3]);
+                v[4] = __builtin_fmaf(dy, gy, v[4]);
+                v[5] = __builtin_fmaf(G, da, v[5]);
+            }
+            if (__ballot(any) != 0ull) {
+#pragma unroll
+                for (int f = 0; f < kAcc; ++f) v[f] = wave_sum_to_last(v[f]);
+                if (lane == kWave - 1) {
+#pragma unroll
+                    for (int f = 0; f < kAcc; ++f) {
+                        if (kW == 1) part[j][f] = v[f];
+                        else atomicAdd(&part[j][f], v[f]);  // the waves of this instance meet here
                     }
                 }
             }
-            const bool wave_any = __ballot(any) != 0ull;
-            if (wave_any) {
-#pragma unroll
-                for (int k = 0; k < kAcc; ++k) v[k] = wave_sum(v[k]);
-            }
-            if (__lane_id() == 0) {
-#pragma unroll
-                for (int k = 0; k < kAcc; ++k) part[j][wave][k] = v[k];
-            }
         }
         __syncthreads();
-        // fold the four waves' partial sums; moments -> screen-space gradients
-        for (int j = threadIdx.x; j < nb; j += kBlendThreads) {
-            float m[kAcc];
+        // moments -> screen-space gradients: the staging lane of each slot
+        if ((int)threadIdx.x < nb && S.quad[threadIdx.x]) {
+            const int j = threadIdx.x;
+            float mo[kAcc];
 #pragma unroll
-            for (int k = 0; k < kAcc; ++k) m[k] = part[j][0][k] + part[j][1][k] + part[j][2][k] + part[j][3][k];
+            for (int f = 0; f < kAcc; ++f) mo[f] = part[j][f];
             // conic back to Q: q00 = -2 ln2 c00, q01 = -ln2 c01, q11 = -2 ln2 c11
-            const float4 c = sc[j];
-            const float q00 = -2.0f * c.x / kLog2e, q01 = -c.y / kLog2e, q11 = -2.0f * c.z / kLog2e;
+            const float4 a = S.a[j], b = S.b[j];
+            const float q00 = -2.0f * kLn2 * a.z, q01 = -kLn2 * a.w, q11 = -2.0f * kLn2 * b.x;
             float out[kAcc];
-            out[0] = q00 * m[0] + q01 * m[1];  // dL/dp_x
-            out[1] = q01 * m[0] + q11 * m[1];  // dL/dp_y
-            out[2] = -0.5f * m[2];             // dL/dq00
-            out[3] = -m[3];                    // dL/dq01
-            out[4] = -0.5f * m[4];             // dL/dq11
-            out[5] = m[5];                     // dL/do
-            out[6] = m[6];
-            out[7] = m[7];
-            out[8] = m[8];
-            float *dst = acc + (int64_t)sgid[j] * kAcc;
+            out[0] = q00 * mo[0] + q01 * mo[1];  // dL/dp_x
+            out[1] = q01 * mo[0] + q11 * mo[1];  // dL/dp_y
+            out[2] = -0.5f * mo[2];              // dL/dq00
+            out[3] = -mo[3];                     // dL/dq01
+            out[4] = -0.5f * mo[4];              // dL/dq11
+            out[5] = mo[5];                      // dL/do
+            out[6] = mo[6];
+            out[7] = mo[7];
+            out[8] = mo[8];
+            float *dst = acc + (int64_t)S.gid[j] * kAcc;
 #pragma unroll
-            for (int k = 0; k < kAcc; ++k)
-                if (out[k] != 0.0f) atomicAdd(dst + k, out[k]);
+            for (int f = 0; f < kAcc; ++f)
+                if (out[f] != 0.0f) atomicAdd(dst + f, out[f]);
         }
     }
+}
+
+// Launch order, longest first: tiles bucketed by descending work (work
+// clamped to kOrderBuckets - 1) in one workgroup (LDS counting sort), so the
+// longest walks start first and do not trail the kernel.  Work is the list
+// length (ranges, forward) or the walk length recorded by the forward
+// (work, backward).
+constexpr int kOrderBuckets = 4096;
+constexpr int kOrderThreads = 1024;
+
+__global__ __launch_bounds__(kOrderThreads) void k_tile_order(const uint2 *ranges, const uint32_t *work,
+                                                              uint32_t ntiles, uint32_t *order) {
+    __shared__ uint32_t cnt[kOrderBuckets];
+    __shared__ uint32_t wave_tot[kOrderThreads / kWave];
+    for (int b = threadIdx.x; b < kOrderBuckets; b += kOrderThreads) cnt[b] = 0;
+    __syncthreads();
+    auto bucket = [&](uint32_t t) {
+        const uint32_t wk = work ? work[t] : ranges[t].y - ranges[t].x;
+        return (uint32_t)(kOrderBuckets - 1) - min(wk, (uint32_t)(kOrderBuckets - 1));
+    };
+    for (uint32_t t = threadIdx.x; t < ntiles; t += kOrderThreads) atomicAdd(&cnt[bucket(t)], 1u);
+    __syncthreads();
+    // exclusive scan of the bucket counts: 4 per thread, then across waves
+    constexpr int kPer = kOrderBuckets / kOrderThreads;
+    uint32_t v[kPer], sum = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        v[k] = cnt[threadIdx.x * kPer + k];
+        sum += v[k];
+    }
+    const int lane = __lane_id(), wv = threadIdx.x / kWave;
+    uint32_t x = sum;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off, kWave);
+        if (lane >= off) x += y;
+    }
+    if (lane == kWave - 1) wave_tot[wv] = x;
+    __syncthreads();
+    uint32_t run = x - sum;
+    for (int k = 0; k < wv; ++k) run += wave_tot[k];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        cnt[threadIdx.x * kPer + k] = run;
+        run += v[k];
+    }
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < ntiles; t += kOrderThreads) order[atomicAdd(&cnt[bucket(t)], 1u)] = t;
 }
 
 }  // namespace
 
+hipError_t launch_tile_order(const uint2 *ranges, const uint32_t *work, uint32_t ntiles, uint32_t *order,
+                             hipStream_t st) {
+    if (ntiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, st, ranges, work, ntiles, order);
+    return hipGetLastError();
+}
+
 hipError_t launch_blend_forward(const FrameGeom &f, const BlendRecord *rec, const uint32_t *inst_gauss,
                                 const uint2 *ranges, const BlendSettings &s, float *image, float *final_T,
-                                int32_t *n_contrib, hipStream_t st) {
+                                int32_t *n_contrib, int32_t *n_blended, const uint32_t *order, uint32_t *tile_work,
+                                hipStream_t st) {
     FrameTable T{};
     T.n = 1;
-    T.f[0] = BlendFrame{f.width, f.height, f.tiles_x, f.tiles_y, f.tile_base, image, final_T, n_contrib, nullptr};
+    T.f[0] = BlendFrame{f.width, f.height, f.tiles_x, f.tiles_y, 0u, image, final_T, n_contrib, n_blended, nullptr};
     const unsigned tiles = (unsigned)(f.tiles_x * f.tiles_y);
     if (tiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_blend_forward<false>, dim3(tiles), dim3(kBlendThreads), 0, st, T, rec, inst_gauss,
-                       ranges + f.tile_base, s);
+    constexpr int kW = OMNIGS_FWD_WAVES;
+    hipLaunchKernelGGL((k_blend_forward<kW, false>), dim3(tiles), dim3(kWave * kW), 0, st, T, rec, inst_gauss,
+                       ranges + f.tile_base, s, order, tile_work);
     return hipGetLastError();
 }
 
 hipError_t launch_blend_backward(const FrameGeom &f, const BlendRecord *rec, const uint32_t *inst_gauss,
                                  const uint2 *ranges, const BlendSettings &s, const float *final_T,
-                                 const int32_t *n_contrib, const float *dL_dimage, float *acc, hipStream_t st) {
+                                 const int32_t *n_contrib, const float *dL_dimage, float *acc, const uint32_t *order,
+                                 hipStream_t st) {
     FrameTable T{};
     T.n = 1;
-    T.f[0] = BlendFrame{f.width, f.height, f.tiles_x, f.tiles_y, f.tile_base, nullptr, const_cast<float *>(final_T),
-                        const_cast<int32_t *>(n_contrib), dL_dimage};
+    T.f[0] = BlendFrame{f.width, f.height, f.tiles_x, f.tiles_y, 0u, nullptr, const_cast<float *>(final_T),
+                        const_cast<int32_t *>(n_contrib), nullptr, dL_dimage};
     const unsigned tiles = (unsigned)(f.tiles_x * f.tiles_y);
     if (tiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_blend_backward<false>, dim3(tiles), dim3(kBlendThreads), 0, st, T, rec, inst_gauss,
-                       ranges + f.tile_base, s, acc);
+    constexpr int kW = OMNIGS_BWD_WAVES;
+    hipLaunchKernelGGL((k_blend_backward<kW, false>), dim3(tiles), dim3(kWave * kW), 0, st, T, rec, inst_gauss,
+                       ranges + f.tile_base, s, acc, order);
     return hipGetLastError();
 }
 

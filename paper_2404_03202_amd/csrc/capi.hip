@@ -39,17 +39,21 @@ omnigs_status fail(omnigs_status st, const char *fmt, ...) {
 enum Stage {
     kStProject = 0,
     kStDepthSort,
+    kStEmitCount,
     kStEmit,
     kStTileSort,
     kStRanges,
+    kStTileOrder,
     kStBlendFwd,
     kStL1,
+    kStBwdClear,
     kStBlendBwd,
     kStProjectBwd,
     kStCount
 };
-const char *kStageNames[kStCount] = {"project",   "depth_sort", "emit",          "tile_sort",  "tile_ranges",
-                                     "blend_fwd", "l1_loss",    "blend_bwd",     "project_bwd"};
+const char *kStageNames[kStCount] = {"project",    "depth_sort", "emit_count", "emit",      "tile_sort",
+                                     "tile_ranges", "tile_order", "blend_fwd",  "l1_loss",   "bwd_clear",
+                                     "blend_bwd",  "project_bwd"};
 
 struct Profiler {
     std::mutex mu;
@@ -219,25 +223,23 @@ struct GeomState {
     }
 };
 struct GeomScratch {
-    uint32_t *depth_key, *iota, *keys_tmp, *vals_tmp, *keys_sorted, *chunk_tot, *chunk_base;
+    uint32_t *depth_key, *iota, *keys_tmp, *vals_tmp, *keys_sorted, *offs;
     void *sort_tmp, *scan_tmp;
     void carve(Arena &a, int64_t n) {
         const size_t m = (size_t)(n > 0 ? n : 1);
-        const size_t nc = (size_t)((m + kEmitChunk - 1) / kEmitChunk);
         depth_key = a.take<uint32_t>(m);
         iota = a.take<uint32_t>(m);
         keys_tmp = a.take<uint32_t>(m);
         vals_tmp = a.take<uint32_t>(m);
         keys_sorted = a.take<uint32_t>(m);
-        chunk_tot = a.take<uint32_t>(nc + 1);
-        chunk_base = a.take<uint32_t>(nc + 1);
+        offs = a.take<uint32_t>(m + 1);
         sort_tmp = a.take_bytes(sort_scratch_bytes((int64_t)m));
-        scan_tmp = a.take_bytes(scan_scratch_bytes((int64_t)nc + 1));
+        scan_tmp = a.take_bytes(scan_scratch_bytes((int64_t)m));
     }
 };
 
-// Projection, depth sort and per-chunk instance totals of one camera.
-// Leaves the instance total in gs.chunk_base[n_chunks].
+// Projection, depth sort and per-rank instance offsets of one camera.
+// Leaves the instance total M in gs.offs[n].
 omnigs_status run_geometry(const ProjectArgs &pa, GeomState &gst, GeomScratch &gs, hipStream_t st) {
     const int64_t n = pa.n;
     {
@@ -251,14 +253,8 @@ omnigs_status run_geometry(const ProjectArgs &pa, GeomState &gst, GeomScratch &g
                                  gs.sort_tmp, st));
     }
     {
-        StageTimer t(st, kStEmit);
-        const int64_t nc = (n + kEmitChunk - 1) / kEmitChunk;
-        if (n > 0) {
-            HIP_TRY(launch_emit_counts(gst.order, gst.n_tiles, n, gs.chunk_tot, st));
-            HIP_TRY(scan_exclusive(gs.chunk_tot, gs.chunk_base, nc, gs.chunk_base + nc, gs.scan_tmp, st));
-        } else {
-            HIP_TRY(launch_fill_u32(gs.chunk_base, 0u, 1, st));
-        }
+        StageTimer t(st, kStEmitCount);
+        HIP_TRY(scan_exclusive(gst.n_tiles, gs.offs, n, gs.offs + n, gs.scan_tmp, st, gst.order));
     }
     return OMNIGS_OK;
 }
@@ -312,9 +308,8 @@ omnigs_status omnigs_forward(const omnigs_gaussians *g, const omnigs_camera *cam
     if ((rc = run_geometry(pa, gst, gs, st)) != OMNIGS_OK) return rc;
 
     // instance count: the one host synchronisation
-    const int64_t nc = (n + kEmitChunk - 1) / kEmitChunk;
     uint32_t m32 = 0;
-    HIP_TRY(hipMemcpyAsync(&m32, gs.chunk_base + (n > 0 ? nc : 0), sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&m32, gs.offs + n, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     const int64_t M = m32;
 
@@ -322,20 +317,25 @@ omnigs_status omnigs_forward(const omnigs_gaussians *g, const omnigs_camera *cam
     const int bits = bits_for(ntiles);
     const int passes = (bits + 7) / 8;
     Arena ia, ja;
+    uint32_t *tile_work;
     auto carve_inst = [&](Arena &a, uint32_t *&tile, uint32_t *&gauss, uint2 *&ranges) {
         tile = a.take<uint32_t>((size_t)(M > 0 ? M : 1));
         gauss = a.take<uint32_t>((size_t)(M > 0 ? M : 1));
         ranges = a.take<uint2>(ntiles);
+        tile_work = a.take<uint32_t>(ntiles);
     };
     uint32_t *inst_tile, *inst_gauss, *tmp_tile, *tmp_gauss;
     uint2 *ranges;
     void *sort_tmp;
     carve_inst(ia, inst_tile, inst_gauss, ranges);
     const size_t inst_state_bytes = ia.off;
+    uint32_t *part, *order;
     auto carve_tmp = [&](Arena &a) {
         tmp_tile = a.take<uint32_t>((size_t)(M > 0 ? M : 1));
         tmp_gauss = a.take<uint32_t>((size_t)(M > 0 ? M : 1));
         sort_tmp = a.take_bytes(sort_scratch_bytes(M));
+        part = a.take<uint32_t>((size_t)emit_blocks((uint64_t)M) + 1);
+        order = a.take<uint32_t>(ntiles);
     };
     carve_tmp(ja);
     const size_t inst_scratch_bytes = ja.off;
@@ -351,8 +351,8 @@ omnigs_status omnigs_forward(const omnigs_gaussians *g, const omnigs_camera *cam
         // last pass lands in the state buffers
         uint32_t *et = (passes % 2) ? tmp_tile : inst_tile;
         uint32_t *eg = (passes % 2) ? tmp_gauss : inst_gauss;
-        HIP_TRY(launch_emit(gst.order, gst.n_tiles, gst.rect, n, gs.chunk_base, pa.tiles_x, 0u, (uint64_t)M, et, eg,
-                            nullptr, st));
+        HIP_TRY(launch_emit(gst.order, gst.n_tiles, gst.rect, gs.offs, n, part, gs.offs + n, pa.tiles_x, 0u,
+                            (uint64_t)M, et, eg, nullptr, st));
     }
     {
         StageTimer t(st, kStTileSort);
@@ -365,13 +365,17 @@ omnigs_status omnigs_forward(const omnigs_gaussians *g, const omnigs_camera *cam
     {
         StageTimer t(st, kStRanges);
         HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), 0u, 2 * (int64_t)ntiles, st));
-        HIP_TRY(launch_tile_ranges(inst_tile, gs.chunk_base + (n > 0 ? nc : 0), (uint64_t)M, ranges, ntiles, st));
+        HIP_TRY(launch_tile_ranges(inst_tile, gs.offs + n, (uint64_t)M, ranges, ntiles, st));
+    }
+    {
+        StageTimer t(st, kStTileOrder);
+        HIP_TRY(launch_tile_order(ranges, nullptr, ntiles, order, st));
     }
     {
         StageTimer t(st, kStBlendFwd);
         FrameGeom f{cam->width, cam->height, pa.tiles_x, pa.tiles_y, 0u};
         HIP_TRY(launch_blend_forward(f, gst.rec, inst_gauss, ranges, make_blend_settings(s), out->image, out->final_T,
-                                     out->n_contrib, st));
+                                     out->n_contrib, out->n_blended, order, tile_work, st));
     }
     state->n = n;
     state->n_instances = M;
@@ -385,6 +389,7 @@ omnigs_status omnigs_forward(const omnigs_gaussians *g, const omnigs_camera *cam
     state->inst_tile = inst_tile;
     state->inst_gauss = inst_gauss;
     state->tile_range = reinterpret_cast<const uint32_t *>(ranges);
+    state->tile_work = tile_work;
     return OMNIGS_OK;
 }
 
@@ -405,24 +410,35 @@ omnigs_status omnigs_backward(const omnigs_gaussians *g, const omnigs_camera *ca
         return fail(OMNIGS_ERR_INVALID, "dquats must be 16-byte aligned");
     if (state->n != g->n || state->width != cam->width || state->height != cam->height)
         return fail(OMNIGS_ERR_INVALID, "state does not match the Gaussians / camera");
-    if (g->n > 0 && (!state->records || !state->n_tiles || !state->inst_gauss || !state->tile_range))
+    if (g->n > 0 && (!state->records || !state->n_tiles || !state->inst_gauss || !state->tile_range ||
+                     !state->tile_work))
         return fail(OMNIGS_ERR_INVALID, "state buffers are NULL");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t n = g->n;
     if (n == 0) return OMNIGS_OK;
     const ProjectArgs pa = make_project_args(g, cam, s);
+    const uint32_t ntiles = (uint32_t)(pa.tiles_x * pa.tiles_y);
     Arena a;
     a.take<float>((size_t)n * kAcc);
+    a.take<uint32_t>(ntiles);
     if ((rc = alloc_arena(alloc, a.off, OMNIGS_MEM_SCRATCH, a, "gradient accumulators")) != OMNIGS_OK) return rc;
     float *acc = a.take<float>((size_t)n * kAcc);
+    uint32_t *order = a.take<uint32_t>(ntiles);
     const auto *rec = static_cast<const BlendRecord *>(state->records);
     const auto *ranges = reinterpret_cast<const uint2 *>(state->tile_range);
     {
-        StageTimer t(st, kStBlendBwd);
+        StageTimer t(st, kStBwdClear);
         HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(acc), 0u, n * kAcc, st));
-        FrameGeom f{cam->width, cam->height, pa.tiles_x, pa.tiles_y, 0u};
+    }
+    const FrameGeom f{cam->width, cam->height, pa.tiles_x, pa.tiles_y, 0u};
+    {
+        StageTimer t(st, kStTileOrder);
+        HIP_TRY(launch_tile_order(ranges, state->tile_work, ntiles, order, st));
+    }
+    {
+        StageTimer t(st, kStBlendBwd);
         HIP_TRY(launch_blend_backward(f, rec, state->inst_gauss, ranges, make_blend_settings(s), fwd->final_T,
-                                      fwd->n_contrib, dL_dimage, acc, st));
+                                      fwd->n_contrib, dL_dimage, acc, order, st));
     }
     {
         StageTimer t(st, kStProjectBwd);

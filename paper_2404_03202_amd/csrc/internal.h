@@ -21,7 +21,9 @@ constexpr int kWave = 64;            // CDNA wavefront
 struct alignas(16) BlendRecord {
     float px_hi, px_lo, py_hi, py_lo;  // ERP pixel position of the centre (Eq. 5)
     float q00, q01, q11, opacity;      // inverse 2D covariance (Eq. 8), opacity
-    float r, g, b, pad;                // SH colour, clamped at 0
+    float r, g, b;                     // SH colour, clamped at 0
+    float reach;                       // log2(opacity / alpha_min): alpha >= alpha_min
+                                       // iff -log2(e)/2 d^T Q d >= -reach
 };
 static_assert(sizeof(BlendRecord) == 48, "record layout");
 
@@ -60,18 +62,21 @@ hipError_t radix_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in, ui
                             void *scratch, hipStream_t st);
 hipError_t launch_iota(uint32_t *v, int64_t n, hipStream_t st);
 
-// Instance emission in depth order.  `chunk_base` [n_chunks + 1] = exclusive
-// scan of per-chunk instance totals (last entry = M).
-constexpr int kEmitChunk = 1024;
-size_t emit_scratch_bytes(int64_t n);
-hipError_t launch_emit_counts(const uint32_t *order, const uint32_t *n_tiles, int64_t n, uint32_t *chunk_tot,
-                              hipStream_t st);
-hipError_t scan_exclusive(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *total, void *scratch,
-                          hipStream_t st);
+// Exclusive scan of u32 (optionally of in[gather[i]]); *total (device, may be
+// null) receives the sum.  `scratch` from scan_scratch_bytes.
 size_t scan_scratch_bytes(int64_t n);
-hipError_t launch_emit(const uint32_t *order, const uint32_t *n_tiles, const uint2 *rect, int64_t n,
-                       const uint32_t *chunk_base, int tiles_x, uint32_t tile_base, uint64_t capacity,
-                       uint32_t *inst_tile, uint32_t *inst_gauss, int32_t *overflow, hipStream_t st);
+hipError_t scan_exclusive(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *total, void *scratch,
+                          hipStream_t st, const uint32_t *gather);
+
+// Instance emission in depth order: offs[r] = exclusive scan of the tile
+// counts in depth order (offs[n] = M at *m_dev).  Writes min(M, capacity)
+// instances; sets *overflow when M > capacity.  `part` holds
+// emit_blocks(capacity) entries of scratch.
+uint64_t emit_blocks(uint64_t capacity);
+hipError_t launch_emit(const uint32_t *order, const uint32_t *n_tiles, const uint2 *rect, const uint32_t *offs,
+                       int64_t n, uint32_t *part, const uint32_t *m_dev, int tiles_x, uint32_t tile_base,
+                       uint64_t capacity, uint32_t *inst_tile, uint32_t *inst_gauss, int32_t *overflow,
+                       hipStream_t st);
 hipError_t launch_tile_ranges(const uint32_t *inst_tile, const uint32_t *m_dev, uint64_t capacity,
                               uint2 *ranges, uint32_t n_tiles_total, hipStream_t st);
 
@@ -82,12 +87,21 @@ struct BlendSettings {
     float alpha_min, alpha_max, T_min;
     float bg[3];
 };
+// `order` (device, may be null): launch order of the tiles (a permutation).
+// The forward writes each tile's largest contributor count (the backward's
+// walk length) to tile_work (may be null).
 hipError_t launch_blend_forward(const FrameGeom &f, const BlendRecord *rec, const uint32_t *inst_gauss,
                                 const uint2 *ranges, const BlendSettings &s, float *image, float *final_T,
-                                int32_t *n_contrib, hipStream_t st);
+                                int32_t *n_contrib, int32_t *n_blended, const uint32_t *order, uint32_t *tile_work,
+                                hipStream_t st);
 hipError_t launch_blend_backward(const FrameGeom &f, const BlendRecord *rec, const uint32_t *inst_gauss,
                                  const uint2 *ranges, const BlendSettings &s, const float *final_T,
-                                 const int32_t *n_contrib, const float *dL_dimage, float *acc, hipStream_t st);
+                                 const int32_t *n_contrib, const float *dL_dimage, float *acc, const uint32_t *order,
+                                 hipStream_t st);
+// Longest-first tile order from the list lengths (work == null) or from a
+// per-tile work array.  One workgroup; ntiles unbounded.
+hipError_t launch_tile_order(const uint2 *ranges, const uint32_t *work, uint32_t ntiles, uint32_t *order,
+                             hipStream_t st);
 
 // L1 loss.
 size_t l1_scratch_bytes();

@@ -260,11 +260,11 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs A, BlendRecord *rec
     r.r = rgb[0];
     r.g = rgb[1];
     r.b = rgb[2];
-    r.pad = 0.0f;
+    r.reach = (float)(log2(o / A.alpha_min));
     float4 *dst = reinterpret_cast<float4 *>(rec + i);
     dst[0] = make_float4(r.px_hi, r.px_lo, r.py_hi, r.py_lo);
     dst[1] = make_float4(r.q00, r.q01, r.q11, r.opacity);
-    dst[2] = make_float4(r.r, r.g, r.b, r.pad);
+    dst[2] = make_float4(r.r, r.g, r.b, r.reach);
     depth_key[i] = __float_as_uint((float)P.tr);
     n_tiles[i] = ntx * nty;
     rect[i] = make_uint2(tx0 | (ntx << 16), ty0 | (nty << 16));

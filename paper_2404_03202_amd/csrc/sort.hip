@@ -7,8 +7,8 @@
 // order is built in two narrow stable sorts:
 //   1. the N Gaussians are sorted by the float bits of t_r (4 passes over N);
 //   2. instances are emitted in that depth order (a scan of tiles-per-
-//      Gaussian gives each chunk of Gaussians its output range, and every
-//      lane of a block writes consecutive instances: coalesced stores), then
+//      Gaussian in depth order gives each Gaussian its output range; every
+//      block writes a fixed span of consecutive outputs, coalesced), then
 //      stably radix-sorted on the tile id alone (ceil(log2 tiles / 8)
 //      passes over M).
 // The result is each tile's list in (t_r, Gaussian id) order, identical to a
@@ -33,6 +33,8 @@ constexpr int kRadixBits = 8;
 constexpr int kBins = 1 << kRadixBits;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kThreads * kScanItems;
+constexpr int kEmitItems = 8;
+constexpr int kEmitSpan = kThreads * kEmitItems;  // outputs per emit block
 
 __device__ inline uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
 
@@ -177,7 +179,16 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t *keys
 }
 
 // ------------------------------------------------------------------- scans
-__global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t *in, int64_t n, uint32_t *block_sums) {
+// Element idx of a scan input: in[idx], or in[gather[idx]] (gathered
+// indices past n read as 0).
+__device__ inline uint32_t scan_input(const uint32_t *in, const uint32_t *gather, int64_t idx, int64_t n) {
+    if (!gather) return in[idx];
+    const uint32_t g = gather[idx];
+    return g < (uint64_t)n ? in[g] : 0u;
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t *in, const uint32_t *gather, int64_t n,
+                                                           uint32_t *block_sums) {
     __shared__ uint32_t wave_tot[kWaves];
     __shared__ uint32_t total;
     const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x;
@@ -185,7 +196,7 @@ __global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t *in, in
 #pragma unroll
     for (int it = 0; it < kScanItems; ++it) {
         const int64_t idx = base + (int64_t)it * kThreads;
-        if (idx < n) s += in[idx];
+        if (idx < n) s += scan_input(in, gather, idx, n);
     }
     block_exclusive_scan(s, wave_tot, &total);
     if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
@@ -193,15 +204,16 @@ __global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t *in, in
 
 // exclusive scan of a tile with a per-block offset; blocked arrangement:
 // thread t owns items [t*kScanItems, (t+1)*kScanItems)
-__global__ __launch_bounds__(kThreads) void k_scan_tile(const uint32_t *in, uint32_t *out, int64_t n,
-                                                         const uint32_t *block_offsets, uint32_t *grand_total) {
+__global__ __launch_bounds__(kThreads) void k_scan_tile(const uint32_t *in, const uint32_t *gather, uint32_t *out,
+                                                         int64_t n, const uint32_t *block_offsets,
+                                                         uint32_t *grand_total) {
     __shared__ uint32_t wave_tot[kWaves];
     __shared__ uint32_t total;
     __shared__ uint32_t s_data[kScanTile];
     const int64_t block0 = (int64_t)blockIdx.x * kScanTile;
     for (int k = threadIdx.x; k < kScanTile; k += kThreads) {
         const int64_t idx = block0 + k;
-        s_data[k] = idx < n ? in[idx] : 0u;
+        s_data[k] = idx < n ? scan_input(in, gather, idx, n) : 0u;
     }
     __syncthreads();
     uint32_t v[kScanItems], s = 0;
@@ -226,88 +238,71 @@ __global__ __launch_bounds__(kThreads) void k_scan_tile(const uint32_t *in, uint
 }
 
 // ---------------------------------------------------------------- emission
-// Per chunk of kEmitChunk depth-ordered Gaussians: total instance count.
-__global__ __launch_bounds__(kThreads) void k_emit_counts(const uint32_t *order, const uint32_t *n_tiles, int64_t n,
-                                                           uint32_t *chunk_tot) {
-    __shared__ uint32_t wave_tot[kWaves];
-    __shared__ uint32_t total;
-    const int64_t base = (int64_t)blockIdx.x * kEmitChunk;
-    uint32_t s = 0;
-    for (int k = threadIdx.x; k < kEmitChunk; k += kThreads) {
-        const int64_t r = base + k;
-        if (r < n) {
-            const uint32_t g = order[r];
-            if (g < (uint64_t)n) s += n_tiles[g];
-        }
-    }
-    block_exclusive_scan(s, wave_tot, &total);
-    if (threadIdx.x == 0) chunk_tot[blockIdx.x] = total;
+// Instances are emitted in depth order: rank r of the depth order owns the
+// output range [offs[r], offs[r] + n_tiles(r)).  Every emit block writes a
+// fixed span of kEmitSpan consecutive outputs, whatever the tile counts of the
+// Gaussians behind them (the nearest Gaussians, which come first, cover up to
+// thousands of tiles each).  part[b] = the rank owning output b * kEmitSpan.
+__global__ __launch_bounds__(kThreads) void k_emit_partition(const uint32_t *order, const uint32_t *n_tiles,
+                                                              const uint32_t *offs, int64_t n,
+                                                              uint64_t part_blocks, uint32_t *part) {
+    const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (r >= n) return;
+    const uint32_t g = order[r];
+    const uint32_t c = g < (uint64_t)n ? n_tiles[g] : 0u;
+    if (c == 0) return;
+    const uint64_t o = offs[r];
+    const uint64_t b1 = (o + c - 1) / kEmitSpan;
+    for (uint64_t b = (o + kEmitSpan - 1) / kEmitSpan; b <= b1 && b < part_blocks; ++b) part[b] = (uint32_t)r;
 }
 
-// One block per chunk: local exclusive scan of tiles-per-Gaussian, then each
-// lane emits instances j = lane, lane + 256, ... of the chunk, finding its
-// Gaussian by binary search over the local prefix (coalesced stores).
 __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *order, const uint32_t *n_tiles, const uint2 *rect,
-                                                    int64_t n, const uint32_t *chunk_base, int tiles_x,
-                                                    uint32_t tile_base, uint64_t capacity, uint32_t *inst_tile,
-                                                    uint32_t *inst_gauss, int32_t *overflow) {
-    constexpr int kPer = kEmitChunk / kThreads;
-    __shared__ uint32_t s_pre[kEmitChunk + 1];
-    __shared__ uint32_t s_gid[kEmitChunk];
-    __shared__ uint2 s_rect[kEmitChunk];
-    __shared__ uint32_t wave_tot[kWaves];
-    __shared__ uint32_t total;
-    const int64_t base = (int64_t)blockIdx.x * kEmitChunk;
-    uint32_t cnt[kPer], s = 0;
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-        const int li = threadIdx.x * kPer + k;
-        const int64_t r = base + li;
-        uint32_t g = 0, c = 0;
-        uint2 rc = make_uint2(0, 0);
-        if (r < n) {
-            g = order[r];
-            if (g < (uint64_t)n) {
-                c = n_tiles[g];
-                if (c) rc = rect[g];
-            }
-        }
-        s_gid[li] = g;
-        s_rect[li] = rc;
-        cnt[k] = c;
-        s += c;
+                                                    const uint32_t *offs, int64_t n, const uint32_t *part,
+                                                    const uint32_t *m_dev, int tiles_x, uint32_t tile_base,
+                                                    uint64_t capacity, uint32_t *inst_tile, uint32_t *inst_gauss,
+                                                    int32_t *overflow) {
+    __shared__ uint32_t s_off[kEmitSpan + 1];
+    __shared__ uint32_t s_gid[kEmitSpan + 1];
+    __shared__ uint2 s_rect[kEmitSpan + 1];
+    const uint64_t M = *m_dev;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && M > capacity && overflow) *overflow = 1;
+    const uint64_t j0 = (uint64_t)blockIdx.x * kEmitSpan;
+    if (j0 >= M || j0 >= capacity) return;
+    const uint64_t nblocks = (M + kEmitSpan - 1) / kEmitSpan;
+    const uint32_t r0 = part[blockIdx.x];
+    // ranks of this span: r0 .. r1 (each visible rank owns >= 1 output, so a
+    // span of kEmitSpan outputs touches at most kEmitSpan + 1 ranks)
+    uint64_t r1 = blockIdx.x + 1 < nblocks ? part[blockIdx.x + 1] : (uint64_t)r0 + kEmitSpan;
+    if (r1 > (uint64_t)n - 1) r1 = n - 1;
+    if (r1 > (uint64_t)r0 + kEmitSpan) r1 = (uint64_t)r0 + kEmitSpan;
+    const int cnt = (int)(r1 - r0) + 1;
+    for (int i = threadIdx.x; i < cnt; i += kThreads) {
+        const uint32_t r = r0 + i;
+        const uint32_t g = order[r];
+        s_off[i] = offs[r];
+        s_gid[i] = g;
+        s_rect[i] = (g < (uint64_t)n && n_tiles[g]) ? rect[g] : make_uint2(0, 0);
     }
-    uint32_t run = block_exclusive_scan(s, wave_tot, &total);
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-        s_pre[threadIdx.x * kPer + k] = run;
-        run += cnt[k];
-    }
-    if (threadIdx.x == 0) s_pre[kEmitChunk] = total;
     __syncthreads();
-    const uint64_t out0 = chunk_base[blockIdx.x];
-    const uint32_t tot = total;
-    if (out0 + tot > capacity) {
-        if (threadIdx.x == 0 && overflow) *overflow = 1;
-    }
-    for (uint32_t j = threadIdx.x; j < tot; j += kThreads) {
-        // largest li with s_pre[li] <= j (and a nonzero count)
-        int lo = 0, hi = kEmitChunk;
+    uint64_t jend = j0 + kEmitSpan;
+    if (jend > M) jend = M;
+    if (jend > capacity) jend = capacity;
+    for (uint64_t j = j0 + threadIdx.x; j < jend; j += kThreads) {
+        // last rank i with s_off[i] <= j
+        int lo = 0, hi = cnt;
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
-            if (s_pre[mid] <= j) lo = mid; else hi = mid;
+            if (s_off[mid] <= j) lo = mid; else hi = mid;
         }
-        const uint32_t k = j - s_pre[lo];
+        const uint32_t k = (uint32_t)(j - s_off[lo]);
         const uint2 rc = s_rect[lo];
         const uint32_t ntx = rc.x >> 16, tx0 = rc.x & 0xffffu, ty0 = rc.y & 0xffffu;
+        if (ntx == 0) continue;
         const uint32_t ty = ty0 + k / ntx;
         uint32_t tx = tx0 + k % ntx;
         if (tx >= (uint32_t)tiles_x) tx -= tiles_x;
-        const uint64_t dst = out0 + j;
-        if (dst < capacity) {
-            inst_tile[dst] = tile_base + ty * (uint32_t)tiles_x + tx;
-            inst_gauss[dst] = s_gid[lo];
-        }
+        inst_tile[j] = tile_base + ty * (uint32_t)tiles_x + tx;
+        inst_gauss[j] = s_gid[lo];
     }
 }
 
@@ -351,23 +346,23 @@ size_t scan_scratch_bytes(int64_t n) {
 }
 
 hipError_t scan_exclusive(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *total, void *scratch,
-                          hipStream_t st) {
+                          hipStream_t st, const uint32_t *gather) {
     if (n <= 0) {
         if (total) hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, total, 0u, (int64_t)1);
         return hipGetLastError();
     }
     const int64_t nb = blocks_for(n, kScanTile);
     if (nb == 1) {
-        hipLaunchKernelGGL(k_scan_tile, dim3(1), dim3(kThreads), 0, st, in, out, n, (const uint32_t *)nullptr,
-                           total);
+        hipLaunchKernelGGL(k_scan_tile, dim3(1), dim3(kThreads), 0, st, in, gather, out, n,
+                           (const uint32_t *)nullptr, total);
         return hipGetLastError();
     }
     uint32_t *sums = static_cast<uint32_t *>(scratch);
     void *next = static_cast<char *>(scratch) + (((size_t)nb * 4 + 255) & ~(size_t)255);
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kThreads), 0, st, in, n, sums);
-    hipError_t e = scan_exclusive(sums, sums, nb, nullptr, next, st);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kThreads), 0, st, in, gather, n, sums);
+    hipError_t e = scan_exclusive(sums, sums, nb, nullptr, next, st, nullptr);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_scan_tile, dim3((unsigned)nb), dim3(kThreads), 0, st, in, out, n, sums, total);
+    hipLaunchKernelGGL(k_scan_tile, dim3((unsigned)nb), dim3(kThreads), 0, st, in, gather, out, n, sums, total);
     return hipGetLastError();
 }
 
@@ -402,7 +397,7 @@ hipError_t radix_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in, ui
         hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kThreads), 0, st, src_k, n, shift, pbits, counts,
                            (int)nb);
         // only (1 << pbits) digit rows are used: scan that prefix of the matrix
-        hipError_t e = scan_exclusive(counts, offsets, (int64_t)(1 << pbits) * nb, nullptr, scan_tmp, st);
+        hipError_t e = scan_exclusive(counts, offsets, (int64_t)(1 << pbits) * nb, nullptr, scan_tmp, st, nullptr);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kThreads), 0, st, src_k, src_v, dk, dv, n,
                            shift, pbits, offsets, (int)nb);
@@ -424,25 +419,18 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st) {
     return hipGetLastError();
 }
 
-size_t emit_scratch_bytes(int64_t n) {
-    const int64_t nc = blocks_for(n > 0 ? n : 1, kEmitChunk);
-    return (((size_t)(nc + 1) * 4 + 255) & ~(size_t)255) * 2 + scan_scratch_bytes(nc + 1);
-}
+uint64_t emit_blocks(uint64_t capacity) { return (capacity + kEmitSpan - 1) / kEmitSpan; }
 
-hipError_t launch_emit_counts(const uint32_t *order, const uint32_t *n_tiles, int64_t n, uint32_t *chunk_tot,
-                              hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_emit_counts, dim3((unsigned)blocks_for(n, kEmitChunk)), dim3(kThreads), 0, st, order,
-                       n_tiles, n, chunk_tot);
-    return hipGetLastError();
-}
-
-hipError_t launch_emit(const uint32_t *order, const uint32_t *n_tiles, const uint2 *rect, int64_t n,
-                       const uint32_t *chunk_base, int tiles_x, uint32_t tile_base, uint64_t capacity,
-                       uint32_t *inst_tile, uint32_t *inst_gauss, int32_t *overflow, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)blocks_for(n, kEmitChunk)), dim3(kThreads), 0, st, order, n_tiles,
-                       rect, n, chunk_base, tiles_x, tile_base, capacity, inst_tile, inst_gauss, overflow);
+hipError_t launch_emit(const uint32_t *order, const uint32_t *n_tiles, const uint2 *rect, const uint32_t *offs,
+                       int64_t n, uint32_t *part, const uint32_t *m_dev, int tiles_x, uint32_t tile_base,
+                       uint64_t capacity, uint32_t *inst_tile, uint32_t *inst_gauss, int32_t *overflow,
+                       hipStream_t st) {
+    if (n <= 0 || capacity == 0) return hipSuccess;
+    const uint64_t nb = emit_blocks(capacity);
+    hipLaunchKernelGGL(k_emit_partition, dim3((unsigned)blocks_for(n, kThreads)), dim3(kThreads), 0, st, order,
+                       n_tiles, offs, n, nb, part);
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)nb), dim3(kThreads), 0, st, order, n_tiles, rect, offs, n,
+                       (const uint32_t *)part, m_dev, tiles_x, tile_base, capacity, inst_tile, inst_gauss, overflow);
     return hipGetLastError();
 }
 

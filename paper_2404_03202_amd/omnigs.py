@@ -58,14 +58,16 @@ class c_settings(ctypes.Structure):
 
 
 class c_image_out(ctypes.Structure):
-    _fields_ = [("image", ctypes.c_void_p), ("final_T", ctypes.c_void_p), ("n_contrib", ctypes.c_void_p)]
+    _fields_ = [("image", ctypes.c_void_p), ("final_T", ctypes.c_void_p), ("n_contrib", ctypes.c_void_p),
+                ("n_blended", ctypes.c_void_p)]
 
 
 class c_state(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("n_instances", ctypes.c_int64), ("width", ctypes.c_int32),
                 ("height", ctypes.c_int32), ("tiles_x", ctypes.c_int32), ("tiles_y", ctypes.c_int32),
                 ("records", ctypes.c_void_p), ("n_tiles", ctypes.c_void_p), ("depth_order", ctypes.c_void_p),
-                ("inst_tile", ctypes.c_void_p), ("inst_gauss", ctypes.c_void_p), ("tile_range", ctypes.c_void_p)]
+                ("inst_tile", ctypes.c_void_p), ("inst_gauss", ctypes.c_void_p), ("tile_range", ctypes.c_void_p),
+                ("tile_work", ctypes.c_void_p)]
 
 
 class c_grads(ctypes.Structure):
@@ -214,10 +216,11 @@ def _stream_ptr(device):
 class ForwardResult:
     """Outputs of omnigs_forward plus the saved state for omnigs_backward."""
 
-    def __init__(self, image, final_T, n_contrib, state: c_state, keepalive):
+    def __init__(self, image, final_T, n_contrib, state: c_state, keepalive, n_blended=None):
         self.image = image
         self.final_T = final_T
         self.n_contrib = n_contrib
+        self.n_blended = n_blended
         self.state = state
         self._keep = keepalive
 
@@ -250,7 +253,7 @@ class ForwardResult:
 
 
 def omnigs_forward(g: dict, camera: dict, settings: dict | None = None, allocator: Allocator | None = None,
-                   out: dict | None = None) -> ForwardResult:
+                   out: dict | None = None, with_blended: bool = False) -> ForwardResult:
     lib = load_library()
     dev = g["means"].device
     cg, cc, cs = make_gaussians(g), make_camera(camera), make_settings(settings)
@@ -259,7 +262,9 @@ def omnigs_forward(g: dict, camera: dict, settings: dict | None = None, allocato
         out = dict(image=torch.empty((3, H, W), dtype=torch.float32, device=dev),
                    final_T=torch.empty((H, W), dtype=torch.float32, device=dev),
                    n_contrib=torch.empty((H, W), dtype=torch.int32, device=dev))
-    co = c_image_out(_ptr(out["image"]), _ptr(out["final_T"]), _ptr(out["n_contrib"]))
+        if with_blended:
+            out["n_blended"] = torch.empty((H, W), dtype=torch.int32, device=dev)
+    co = c_image_out(_ptr(out["image"]), _ptr(out["final_T"]), _ptr(out["n_contrib"]), _ptr(out.get("n_blended")))
     st = c_state()
     al = allocator or Allocator(dev)
     _check(lib.omnigs_forward(ctypes.byref(cg), ctypes.byref(cc), ctypes.byref(cs), al.c, ctypes.byref(co),
@@ -267,7 +272,7 @@ def omnigs_forward(g: dict, camera: dict, settings: dict | None = None, allocato
     keep = list(al.state)
     al.scratch.clear()
     al.state.clear()
-    return ForwardResult(out["image"], out["final_T"], out["n_contrib"], st, keep)
+    return ForwardResult(out["image"], out["final_T"], out["n_contrib"], st, keep, out.get("n_blended"))
 
 
 def omnigs_backward(g: dict, camera: dict, settings: dict | None, fwd: ForwardResult, dL_dimage: torch.Tensor,
@@ -284,7 +289,7 @@ def omnigs_backward(g: dict, camera: dict, settings: dict | None, fwd: ForwardRe
                      screen=z(n, 2))
     cgr = c_grads(_ptr(grads["means"]), _ptr(grads["scales"]), _ptr(grads["quats"]), _ptr(grads["opacities"]),
                   _ptr(grads["sh"]), _ptr(grads["screen"]))
-    co = c_image_out(_ptr(fwd.image), _ptr(fwd.final_T), _ptr(fwd.n_contrib))
+    co = c_image_out(_ptr(fwd.image), _ptr(fwd.final_T), _ptr(fwd.n_contrib), None)
     al = allocator or Allocator(dev)
     _check(lib.omnigs_backward(ctypes.byref(cg), ctypes.byref(cc), ctypes.byref(cs), ctypes.byref(fwd.state),
                                ctypes.byref(co), ctypes.c_void_p(dL_dimage.data_ptr()), ctypes.byref(cgr), al.c,
@@ -326,7 +331,8 @@ def omnigs_forward_batch(g: dict, cameras: list, settings: dict | None = None, i
             outs.append(dict(image=torch.empty((3, H, W), dtype=torch.float32, device=dev),
                              final_T=torch.empty((H, W), dtype=torch.float32, device=dev),
                              n_contrib=torch.empty((H, W), dtype=torch.int32, device=dev)))
-    couts = (c_image_out * B)(*[c_image_out(_ptr(o["image"]), _ptr(o["final_T"]), _ptr(o["n_contrib"])) for o in outs])
+    couts = (c_image_out * B)(*[c_image_out(_ptr(o["image"]), _ptr(o["final_T"]), _ptr(o["n_contrib"]),
+                                            _ptr(o.get("n_blended"))) for o in outs])
     overflow = torch.zeros(1, dtype=torch.int32, device=dev)
     al = allocator or Allocator(dev)
     _check(lib.omnigs_forward_batch(ctypes.byref(cg), cams, B, ctypes.byref(cs), al.c, couts, int(instance_capacity),

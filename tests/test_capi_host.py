@@ -49,7 +49,7 @@ def _fake_args(n=10, width=64, height=32, degree=3, coeffs=16):
         c.R_cw[k] = 1.0 if k in (0, 4, 8) else 0.0
     c.width, c.height = width, height
     s = B.make_settings(None)
-    out = B.c_image_out(0x60000, 0x70000, 0x80000)
+    out = B.c_image_out(0x60000, 0x70000, 0x80000, None)
     return g, c, s, out
 
 
@@ -119,6 +119,7 @@ def test_l1_and_backward_argument_checks(lib):
 def test_profile_stage_names(lib):
     n = lib.omnigs_profile_num_stages()
     names = [lib.omnigs_profile_stage_name(k).decode() for k in range(n)]
-    assert names[:6] == ["project", "depth_sort", "emit", "tile_sort", "tile_ranges", "blend_fwd"]
+    assert names[:8] == ["project", "depth_sort", "emit_count", "emit", "tile_sort", "tile_ranges", "tile_order",
+                         "blend_fwd"]
     assert "blend_bwd" in names and "project_bwd" in names
     assert lib.omnigs_profile_stage_name(n).decode() == ""

@@ -26,7 +26,7 @@ def to_dev(g):
 
 
 def gpu_forward(g, cam, settings=None):
-    r = B.omnigs_forward(to_dev(g), cam, settings)
+    r = B.omnigs_forward(to_dev(g), cam, settings, with_blended=True)
     torch.cuda.synchronize()
     return r
 
@@ -46,6 +46,8 @@ def compare_forward(g, cam, settings=None, lists=True, what="", max_excluded=1e-
     r = gpu_forward(g, cam, settings)
     rep = parity.check_image(np_(r.image), orc, what=what, max_excluded=max_excluded)
     parity.check_transmittance(np_(r.final_T), np_(r.n_contrib), orc)
+    sel = orc["n_flags"] == 0
+    assert (np_(r.n_blended)[sel] == orc["n_blended"][sel]).all(), "n_blended differs at unflagged pixels"
     if lists:
         t, gid, tr = O.tile_lists(sc)
         it, ig, rng = (np_(x) for x in r.instance_lists())
