@@ -31,6 +31,9 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32_VECTOR = 157.3e12   # FLOP/s, MI355X published dense FP32 vector
 PEAK_HBM = 8.0e12             # B/s
+COPY_BYTES = 256 << 20        # plain copy used to calibrate the HBM counters
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "blend_bwd_1M_2048x1024_traffic.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2404_03202_amd", "csrc", "blend.hip")
 
 # Algorithmic FP32 work per (pixel, instance) pair of the blend (FMA = 2):
 # evaluating alpha (offsets, quadratic form, exp2, opacity, clamp) = 12;
@@ -41,6 +44,26 @@ FLOP_GRAD = 24
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def measured_traffic():
+    """HBM bytes per blend_bwd launch from the committed counter summary, or
+    None when the kernel source changed since the counters were taken."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    digest = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if kv.get("source_sha256") != digest:
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(g, pose, gt_image):
@@ -64,6 +87,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--poses", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run plain 256 MiB device copies (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (the rasterizer has no multi-GPU path); "
@@ -76,6 +101,14 @@ def main():
 
     dev = "cuda:0"
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(copy_bytes=COPY_BYTES, copies=5)))
+        return
     t0 = time.perf_counter()
     g, poses, gt = scenes.config2(n_poses=args.poses)
     log(f"scene: {g['means'].shape[0]} Gaussians, {len(poses)} poses ({time.perf_counter() - t0:.1f} s)")
@@ -121,7 +154,7 @@ def main():
     achieved = flops / (bwd_ms * 1e-3)
     dominant = max(((k, v[0]) for k, v in prof.items()), key=lambda kv: kv[1])[0]
     roofline = dict(kernel="blend_bwd", bound="alu", achieved=achieved / 1e12, peak=PEAK_FP32_VECTOR / 1e12,
-                    unit="TFLOP/s", frac=achieved / PEAK_FP32_VECTOR, traffic=None,
+                    unit="TFLOP/s", frac=achieved / PEAK_FP32_VECTOR, traffic=measured_traffic(),
                     avg_launch_ms=bwd_ms / max(bwd_n, 1), pairs_walked_per_launch=walked / max(bwd_n, 1),
                     pairs_blended_per_launch=blended / max(bwd_n, 1), dominant_stage=dominant)
 
