@@ -26,7 +26,7 @@
  * - Image layout is planar [3][H][W] float32, row-major, pixel (x, y) sampled
  *   at the continuous ERP coordinate (x + 1/2, y + 1/2) (Eq. 5).
  * - Requirements: width % 16 == 0 (16x16 tiles that wrap across the
- *   longitude seam), width <= 65520 and height >= 1.
+ *   longitude seam), width <= 65520 and 1 <= height <= 65520.
  */
 #ifndef OMNIGS_H
 #define OMNIGS_H
@@ -148,7 +148,7 @@ omnigs_settings omnigs_default_settings(void);
  * Inputs: g (device arrays), cam and s (host).  Outputs: out (device,
  * caller-allocated) and *state (host struct; device buffers from `alloc`).
  * Returns OMNIGS_ERR_INVALID for null pointers, n < 0, sh_degree outside
- * 0..3, sh_coeffs out of range, width % 16 != 0, height < 1 or a non-finite
+ * 0..3, sh_coeffs out of range, width % 16 != 0, height outside [1, 65520] or a non-finite
  * camera; OMNIGS_ERR_ALLOC if `alloc` fails; OMNIGS_ERR_HIP on a runtime
  * failure. */
 omnigs_status omnigs_forward(const omnigs_gaussians *g, const omnigs_camera *cam, const omnigs_settings *s,
@@ -177,19 +177,32 @@ omnigs_status omnigs_backward(const omnigs_gaussians *g, const omnigs_camera *ca
 omnigs_status omnigs_l1_loss(const float *image, const float *target, int64_t count, float *dL_dimage, float *loss,
                              omnigs_allocator alloc, void *stream);
 
-/* Batched forward of `batch` cameras of mixed resolution over one resident
- * Gaussian set (K1 reads each Gaussian once for all cameras; one instance
- * sort and one blend launch over the concatenated tile space of all
- * cameras).  Every image equals the one omnigs_forward renders for that
- * camera alone, bit for bit.  cams[b] (host) and outs[b] (device buffers)
- * per camera.  instance_capacity > 0 sizes the instance buffers without the
- * readback; then, if more instances are needed, the call still runs without
- * writing out of bounds but *overflow (device int32, may be NULL) is set to 1
- * and the images are invalid.  instance_capacity == 0 reads the count back
- * (one host synchronisation).  No backward state is kept. */
+/* Batched forward render of `batch` cameras (1 <= batch <= OMNIGS_MAX_BATCH,
+ * mixed resolutions) over one resident Gaussian set: the path of
+ * omnigs_forward (Sec. 3.2-3.3) run once for all of them.  One projection
+ * launch covers every (camera, Gaussian) pair; one depth sort orders all of
+ * them; instances are emitted into the concatenation of the cameras' tile
+ * spaces (camera b's tiles follow those of cameras 0..b-1), so one tile sort
+ * and one blend launch serve the whole batch.  A tile's list holds the same
+ * records in the same order as when its camera is rendered alone, so every
+ * output equals that of omnigs_forward for the camera, bit for bit.
+ * cams[b] (host) and outs[b] (device, caller-allocated) per camera.
+ * instance_capacity == 0: the total instance count M is read back to size
+ *   the instance buffers (one host synchronisation of `stream`).
+ * instance_capacity > 0: the instance buffers hold that many instances and
+ *   nothing is read back (no host synchronisation: the call only enqueues);
+ *   if M exceeds it, the call still stays within its buffers, but the
+ *   outputs are invalid and *overflow is 1.
+ * overflow (device int32, may be NULL) is set to 0 or 1 on `stream`.
+ * n_instances (host, may be NULL) receives M when it was read back, else -1.
+ * M must stay below 2^32.  No backward state is kept; all memory beyond the
+ * outputs is OMNIGS_MEM_SCRATCH.  Errors as omnigs_forward, plus
+ * OMNIGS_ERR_INVALID for batch out of range or batch * n >= 2^32. */
+#define OMNIGS_MAX_BATCH 16
 omnigs_status omnigs_forward_batch(const omnigs_gaussians *g, const omnigs_camera *cams, int32_t batch,
                                    const omnigs_settings *s, omnigs_allocator alloc, omnigs_image_out *outs,
-                                   int64_t instance_capacity, int32_t *overflow, void *stream);
+                                   int64_t instance_capacity, int32_t *overflow, int64_t *n_instances,
+                                   void *stream);
 
 /* Thread-local message describing the last non-OK status of this thread. */
 const char *omnigs_last_error(void);

@@ -60,10 +60,9 @@ struct BlendFrame {
     const float *dL;     // backward only
 };
 
-constexpr int kMaxFrames = 32;
 struct FrameTable {
     int n;
-    BlendFrame f[kMaxFrames];
+    BlendFrame f[kMaxBatch];
 };
 
 __device__ inline int find_frame(const FrameTable &T, uint32_t tile) {
@@ -515,6 +514,25 @@ hipError_t launch_blend_forward(const FrameGeom &f, const BlendRecord *rec, cons
     constexpr int kW = OMNIGS_FWD_WAVES;
     hipLaunchKernelGGL((k_blend_forward<kW, false>), dim3(tiles), dim3(kWave * kW), 0, st, T, rec, inst_gauss,
                        ranges + f.tile_base, s, order, tile_work);
+    return hipGetLastError();
+}
+
+hipError_t launch_blend_forward_frames(const FrameGeom *frames, const omnigs_image_out *outs, int count,
+                                       const BlendRecord *rec, const uint32_t *inst_gauss, const uint2 *ranges,
+                                       const BlendSettings &s, const uint32_t *order, uint32_t total_tiles,
+                                       hipStream_t st) {
+    if (count < 1 || count > kMaxBatch) return hipErrorInvalidValue;
+    if (total_tiles == 0) return hipSuccess;
+    FrameTable T{};
+    T.n = count;
+    for (int k = 0; k < count; ++k) {
+        const FrameGeom &f = frames[k];
+        T.f[k] = BlendFrame{f.width, f.height, f.tiles_x, f.tiles_y, f.tile_base, outs[k].image, outs[k].final_T,
+                            outs[k].n_contrib, outs[k].n_blended, nullptr};
+    }
+    constexpr int kW = OMNIGS_FWD_WAVES;
+    hipLaunchKernelGGL((k_blend_forward<kW, true>), dim3(total_tiles), dim3(kWave * kW), 0, st, T, rec, inst_gauss,
+                       ranges, s, order, (uint32_t *)nullptr);
     return hipGetLastError();
 }
 

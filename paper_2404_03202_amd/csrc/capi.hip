@@ -149,7 +149,7 @@ omnigs_status check_camera(const omnigs_camera *c) {
     if (!c) return fail(OMNIGS_ERR_INVALID, "camera is NULL");
     if (c->width <= 0 || c->width % kTile != 0 || c->width > 65520)
         return fail(OMNIGS_ERR_INVALID, "width %d must be a positive multiple of 16, <= 65520", c->width);
-    if (c->height < 1 || c->height > (1 << 20)) return fail(OMNIGS_ERR_INVALID, "height %d out of range", c->height);
+    if (c->height < 1 || c->height > 65520) return fail(OMNIGS_ERR_INVALID, "height %d not in [1, 65520]", c->height);
     for (int k = 0; k < 9; ++k)
         if (!std::isfinite(c->R_cw[k])) return fail(OMNIGS_ERR_INVALID, "non-finite camera rotation");
     for (int k = 0; k < 3; ++k)
@@ -351,8 +351,13 @@ omnigs_status omnigs_forward(const omnigs_gaussians *g, const omnigs_camera *cam
         // last pass lands in the state buffers
         uint32_t *et = (passes % 2) ? tmp_tile : inst_tile;
         uint32_t *eg = (passes % 2) ? tmp_gauss : inst_gauss;
-        HIP_TRY(launch_emit(gst.order, gst.n_tiles, gst.rect, gs.offs, n, part, gs.offs + n, pa.tiles_x, 0u,
-                            (uint64_t)M, et, eg, nullptr, st));
+        EmitFrames ef{};
+        ef.n_per = n > 0 ? n : 1;
+        ef.count = 1;
+        ef.tiles_x[0] = pa.tiles_x;
+        ef.tile_base[0] = 0u;
+        HIP_TRY(launch_emit(gst.order, gst.n_tiles, gst.rect, gs.offs, n, part, gs.offs + n, ef, (uint64_t)M, et, eg,
+                            nullptr, st));
     }
     {
         StageTimer t(st, kStTileSort);
@@ -464,10 +469,138 @@ omnigs_status omnigs_l1_loss(const float *image, const float *target, int64_t co
 
 omnigs_status omnigs_forward_batch(const omnigs_gaussians *g, const omnigs_camera *cams, int32_t batch,
                                    const omnigs_settings *s, omnigs_allocator alloc, omnigs_image_out *outs,
-                                   int64_t instance_capacity, int32_t *overflow, void *stream) {
-    (void)g; (void)cams; (void)batch; (void)s; (void)alloc; (void)outs; (void)instance_capacity; (void)overflow;
-    (void)stream;
-    return fail(OMNIGS_ERR_INVALID, "omnigs_forward_batch: not available in this build");
+                                   int64_t instance_capacity, int32_t *overflow, int64_t *n_instances,
+                                   void *stream) {
+    omnigs_status rc;
+    if (n_instances) *n_instances = -1;
+    if ((rc = check_gaussians(g)) != OMNIGS_OK) return rc;
+    if ((rc = check_settings(s)) != OMNIGS_OK) return rc;
+    if (batch < 1 || batch > kMaxBatch) return fail(OMNIGS_ERR_INVALID, "batch %d not in [1, %d]", batch, kMaxBatch);
+    if (!cams || !outs) return fail(OMNIGS_ERR_INVALID, "cameras or outputs is NULL");
+    if (!alloc.alloc) return fail(OMNIGS_ERR_INVALID, "allocator callback is NULL");
+    if (instance_capacity < 0 || instance_capacity >= (int64_t(1) << 32))
+        return fail(OMNIGS_ERR_INVALID, "instance_capacity %lld out of range", (long long)instance_capacity);
+    const int64_t n = g->n;
+    const int64_t nrec = n * batch;  // record b * n + i: camera b, Gaussian i
+    if (nrec >= (int64_t(1) << 32) - 1) return fail(OMNIGS_ERR_INVALID, "batch * n must stay below 2^32");
+    uint64_t total_tiles = 0;
+    FrameGeom frames[kMaxBatch];
+    CamTable ct{};
+    ct.count = batch;
+    EmitFrames ef{};
+    ef.n_per = n > 0 ? n : 1;
+    ef.count = batch;
+    for (int b = 0; b < batch; ++b) {
+        if ((rc = check_camera(&cams[b])) != OMNIGS_OK) return rc;
+        if (!outs[b].image || !outs[b].final_T || !outs[b].n_contrib)
+            return fail(OMNIGS_ERR_INVALID, "output pointer of camera %d is NULL", b);
+        const ProjectArgs pb = make_project_args(g, &cams[b], s);
+        CamGeom &cg = ct.c[b];
+        for (int k = 0; k < 9; ++k) cg.R[k] = pb.R[k];
+        for (int k = 0; k < 3; ++k) {
+            cg.t[k] = pb.t[k];
+            cg.campos[k] = pb.campos[k];
+        }
+        cg.width = pb.width;
+        cg.height = pb.height;
+        cg.tiles_x = pb.tiles_x;
+        cg.tiles_y = pb.tiles_y;
+        frames[b] = FrameGeom{pb.width, pb.height, pb.tiles_x, pb.tiles_y, (uint32_t)total_tiles};
+        ef.tiles_x[b] = pb.tiles_x;
+        ef.tile_base[b] = (uint32_t)total_tiles;
+        total_tiles += (uint64_t)pb.tiles_x * pb.tiles_y;
+    }
+    // the last id is kept free so that bits_for always has room
+    if (total_tiles >= (uint64_t(1) << 31)) return fail(OMNIGS_ERR_INVALID, "too many tiles in the batch");
+    const ProjectArgs pa = make_project_args(g, &cams[0], s);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const uint32_t ntiles = (uint32_t)total_tiles;
+
+    // per-record buffers (all scratch: no backward state is kept)
+    Arena ra;
+    GeomState gst;
+    GeomScratch gs;
+    auto carve_geom = [&](Arena &a) {
+        gst.carve(a, nrec);
+        gs.carve(a, nrec);
+    };
+    carve_geom(ra);
+    if ((rc = alloc_arena(alloc, ra.off, OMNIGS_MEM_SCRATCH, ra, "per-record scratch")) != OMNIGS_OK) return rc;
+    carve_geom(ra);
+    if (overflow) HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(overflow), 0u, 1, st));
+    {
+        StageTimer t(st, kStProject);
+        HIP_TRY(launch_project_batch(pa, ct, gst.rec, gs.depth_key, gst.n_tiles, gst.rect, st));
+    }
+    {
+        StageTimer t(st, kStDepthSort);
+        HIP_TRY(launch_iota(gs.iota, nrec, st));
+        HIP_TRY(radix_sort_pairs(gs.depth_key, gs.iota, gs.keys_tmp, gs.vals_tmp, gs.keys_sorted, gst.order, nrec,
+                                 32, gs.sort_tmp, st));
+    }
+    uint32_t *m_dev = gs.offs + nrec;
+    {
+        StageTimer t(st, kStEmitCount);
+        HIP_TRY(scan_exclusive(gst.n_tiles, gs.offs, nrec, m_dev, gs.scan_tmp, st, gst.order));
+    }
+    int64_t cap = instance_capacity;
+    if (cap == 0) {
+        uint32_t m32 = 0;
+        HIP_TRY(hipMemcpyAsync(&m32, m_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        cap = m32;
+        if (n_instances) *n_instances = m32;
+    }
+    const int bits = bits_for(total_tiles);
+    const int passes = (bits + 7) / 8;
+    const size_t mc = (size_t)(cap > 0 ? cap : 1);
+    Arena ia;
+    uint32_t *inst_tile, *inst_gauss, *tmp_tile, *tmp_gauss, *part, *order;
+    uint2 *ranges;
+    void *sort_tmp;
+    auto carve_inst = [&](Arena &a) {
+        inst_tile = a.take<uint32_t>(mc);
+        inst_gauss = a.take<uint32_t>(mc);
+        tmp_tile = a.take<uint32_t>(mc);
+        tmp_gauss = a.take<uint32_t>(mc);
+        sort_tmp = a.take_bytes(sort_scratch_bytes((int64_t)mc));
+        part = a.take<uint32_t>((size_t)emit_blocks((uint64_t)cap) + 1);
+        ranges = a.take<uint2>(ntiles);
+        order = a.take<uint32_t>(ntiles);
+    };
+    carve_inst(ia);
+    if ((rc = alloc_arena(alloc, ia.off, OMNIGS_MEM_SCRATCH, ia, "instance lists")) != OMNIGS_OK) return rc;
+    carve_inst(ia);
+    // with a capacity, the counts the kernels use are min(M, capacity),
+    // read on the device
+    const uint32_t *count_dev = instance_capacity > 0 ? m_dev : nullptr;
+    {
+        StageTimer t(st, kStEmit);
+        const bool odd = passes % 2;
+        HIP_TRY(launch_emit(gst.order, gst.n_tiles, gst.rect, gs.offs, nrec, part, m_dev, ef, (uint64_t)cap,
+                            odd ? tmp_tile : inst_tile, odd ? tmp_gauss : inst_gauss, overflow, st));
+    }
+    {
+        StageTimer t(st, kStTileSort);
+        const bool odd = passes % 2;
+        HIP_TRY(radix_sort_pairs(odd ? tmp_tile : inst_tile, odd ? tmp_gauss : inst_gauss, tmp_tile, tmp_gauss,
+                                 inst_tile, inst_gauss, cap, bits, sort_tmp, st, count_dev));
+    }
+    {
+        StageTimer t(st, kStRanges);
+        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), 0u, 2 * (int64_t)ntiles, st));
+        HIP_TRY(launch_tile_ranges(inst_tile, m_dev, (uint64_t)cap, ranges, ntiles, st));
+    }
+    {
+        StageTimer t(st, kStTileOrder);
+        HIP_TRY(launch_tile_order(ranges, nullptr, ntiles, order, st));
+    }
+    {
+        StageTimer t(st, kStBlendFwd);
+        HIP_TRY(launch_blend_forward_frames(frames, outs, batch, gst.rec, inst_gauss, ranges, make_blend_settings(s),
+                                            order, ntiles, st));
+    }
+    return OMNIGS_OK;
 }
 
 omnigs_status omnigs_profile_enable(int32_t on) {

@@ -13,6 +13,7 @@ constexpr int kTile = 16;            // tile edge in pixels
 constexpr int kTilePixels = kTile * kTile;
 constexpr int kBlendThreads = 256;   // one lane per pixel of a 16x16 tile
 constexpr int kWave = 64;            // CDNA wavefront
+constexpr int kMaxBatch = OMNIGS_MAX_BATCH;  // cameras per batched launch
 
 // Blend record of one Gaussian, 48 bytes: what the blend kernels gather per
 // (tile, instance).  The pixel position is split into a float hi part and a
@@ -48,18 +49,43 @@ struct FrameGeom {  // one camera's image inside a (possibly batched) launch
     uint32_t tile_base;  // first global tile id of this image
 };
 
+// Camera-dependent part of ProjectArgs, one entry per camera of a batch.
+struct CamGeom {
+    double R[9], t[3], campos[3];
+    int width, height, tiles_x, tiles_y;
+};
+struct CamTable {
+    int count;
+    CamGeom c[kMaxBatch];
+};
+
+// Tile geometry of the cameras behind record index g = b * n_per + i.
+struct EmitFrames {
+    int64_t n_per;  // records per camera
+    int count;
+    int tiles_x[kMaxBatch];
+    uint32_t tile_base[kMaxBatch];
+};
+
 // Host-side launchers (each .hip file owns its kernels).
 hipError_t launch_project(const ProjectArgs &a, BlendRecord *rec, uint32_t *depth_key, uint32_t *n_tiles,
                           uint2 *rect, hipStream_t st);
+// All cameras of `cams` in one launch: the outputs of camera b for Gaussian i
+// land at index b * a.n + i, bit-identical to launch_project of that camera
+// (a's camera fields are ignored).
+hipError_t launch_project_batch(const ProjectArgs &a, const CamTable &cams, BlendRecord *rec, uint32_t *depth_key,
+                                uint32_t *n_tiles, uint2 *rect, hipStream_t st);
 hipError_t launch_project_backward(const ProjectArgs &a, const uint32_t *n_tiles, const float *acc,
                                    const omnigs_grads &gr, hipStream_t st);
 
 // radix sort of (u32 key, u32 value) pairs on the low `bits` bits of the key;
 // stable.  Result lands in keys_out/vals_out.  `scratch` from sort_scratch_bytes.
+// n_dev (device, may be null): the element count is min(n, *n_dev), read on
+// the device (n then only bounds the buffers and the grid).
 size_t sort_scratch_bytes(int64_t n);
 hipError_t radix_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_tmp,
                             uint32_t *vals_tmp, uint32_t *keys_out, uint32_t *vals_out, int64_t n, int bits,
-                            void *scratch, hipStream_t st);
+                            void *scratch, hipStream_t st, const uint32_t *n_dev = nullptr);
 hipError_t launch_iota(uint32_t *v, int64_t n, hipStream_t st);
 
 // Exclusive scan of u32 (optionally of in[gather[i]]); *total (device, may be
@@ -70,11 +96,12 @@ hipError_t scan_exclusive(const uint32_t *in, uint32_t *out, int64_t n, uint32_t
 
 // Instance emission in depth order: offs[r] = exclusive scan of the tile
 // counts in depth order (offs[n] = M at *m_dev).  Writes min(M, capacity)
-// instances; sets *overflow when M > capacity.  `part` holds
-// emit_blocks(capacity) entries of scratch.
+// instances, with global tile ids (frames.tile_base of the record's camera
+// plus the tile inside its image); sets *overflow when M > capacity.  `part`
+// holds emit_blocks(capacity) entries of scratch.
 uint64_t emit_blocks(uint64_t capacity);
 hipError_t launch_emit(const uint32_t *order, const uint32_t *n_tiles, const uint2 *rect, const uint32_t *offs,
-                       int64_t n, uint32_t *part, const uint32_t *m_dev, int tiles_x, uint32_t tile_base,
+                       int64_t n, uint32_t *part, const uint32_t *m_dev, const EmitFrames &frames,
                        uint64_t capacity, uint32_t *inst_tile, uint32_t *inst_gauss, int32_t *overflow,
                        hipStream_t st);
 hipError_t launch_tile_ranges(const uint32_t *inst_tile, const uint32_t *m_dev, uint64_t capacity,
@@ -94,6 +121,12 @@ hipError_t launch_blend_forward(const FrameGeom &f, const BlendRecord *rec, cons
                                 const uint2 *ranges, const BlendSettings &s, float *image, float *final_T,
                                 int32_t *n_contrib, int32_t *n_blended, const uint32_t *order, uint32_t *tile_work,
                                 hipStream_t st);
+// Forward blend of several images in one launch over their concatenated
+// tile space (frames[k].tile_base ascending, total_tiles in all).
+hipError_t launch_blend_forward_frames(const FrameGeom *frames, const omnigs_image_out *outs, int count,
+                                       const BlendRecord *rec, const uint32_t *inst_gauss, const uint2 *ranges,
+                                       const BlendSettings &s, const uint32_t *order, uint32_t total_tiles,
+                                       hipStream_t st);
 hipError_t launch_blend_backward(const FrameGeom &f, const BlendRecord *rec, const uint32_t *inst_gauss,
                                  const uint2 *ranges, const BlendSettings &s, const float *final_T,
                                  const int32_t *n_contrib, const float *dL_dimage, float *acc, const uint32_t *order,

@@ -189,11 +189,11 @@ __device__ inline void load_sh(const ProjectArgs &A, int64_t i, double (*sh)[3])
         for (int ch = 0; ch < 3; ++ch) sh[k][ch] = p[3 * k + ch];
 }
 
+// Projection of Gaussian i for the camera of A; the outputs go to index
+// `slot` of the output arrays.
 template <int D>
-__global__ __launch_bounds__(256) void k_project(ProjectArgs A, BlendRecord *rec, uint32_t *depth_key,
-                                                 uint32_t *n_tiles, uint2 *rect) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= A.n) return;
+__device__ inline void project_one(const ProjectArgs &A, int64_t i, int64_t slot, BlendRecord *rec,
+                                   uint32_t *depth_key, uint32_t *n_tiles, uint2 *rect) {
     const double o = A.opacities[i];
     Proj P;
     bool vis = project_core(A, i, o, P);
@@ -229,9 +229,9 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs A, BlendRecord *rec
         }
     }
     if (!vis) {
-        depth_key[i] = kCulledKey;
-        n_tiles[i] = 0;
-        rect[i] = make_uint2(0, 0);
+        depth_key[slot] = kCulledKey;
+        n_tiles[slot] = 0;
+        rect[slot] = make_uint2(0, 0);
         return;
     }
     constexpr int K = (D + 1) * (D + 1);
@@ -261,13 +261,44 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs A, BlendRecord *rec
     r.g = rgb[1];
     r.b = rgb[2];
     r.reach = (float)(log2(o / A.alpha_min));
-    float4 *dst = reinterpret_cast<float4 *>(rec + i);
+    float4 *dst = reinterpret_cast<float4 *>(rec + slot);
     dst[0] = make_float4(r.px_hi, r.px_lo, r.py_hi, r.py_lo);
     dst[1] = make_float4(r.q00, r.q01, r.q11, r.opacity);
     dst[2] = make_float4(r.r, r.g, r.b, r.reach);
-    depth_key[i] = __float_as_uint((float)P.tr);
-    n_tiles[i] = ntx * nty;
-    rect[i] = make_uint2(tx0 | (ntx << 16), ty0 | (nty << 16));
+    depth_key[slot] = __float_as_uint((float)P.tr);
+    n_tiles[slot] = ntx * nty;
+    rect[slot] = make_uint2(tx0 | (ntx << 16), ty0 | (nty << 16));
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_project(ProjectArgs A, BlendRecord *rec, uint32_t *depth_key,
+                                                 uint32_t *n_tiles, uint2 *rect) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    project_one<D>(A, i, i, rec, depth_key, n_tiles, rect);
+}
+
+// Every camera of a batch for Gaussian i in turn: the Gaussian's parameters
+// are fetched from HBM once and re-read from cache for the later cameras.
+template <int D>
+__global__ __launch_bounds__(256) void k_project_batch(ProjectArgs A, CamTable T, BlendRecord *rec,
+                                                       uint32_t *depth_key, uint32_t *n_tiles, uint2 *rect) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    for (int b = 0; b < T.count; ++b) {
+        ProjectArgs C = A;
+        const CamGeom &g = T.c[b];
+        for (int k = 0; k < 9; ++k) C.R[k] = g.R[k];
+        for (int k = 0; k < 3; ++k) {
+            C.t[k] = g.t[k];
+            C.campos[k] = g.campos[k];
+        }
+        C.width = g.width;
+        C.height = g.height;
+        C.tiles_x = g.tiles_x;
+        C.tiles_y = g.tiles_y;
+        project_one<D>(C, i, (int64_t)b * A.n + i, rec, depth_key, n_tiles, rect);
+    }
 }
 
 // dJ/dt for the spherical Jacobian: dJ[e][n] = d J_e / d t_n, e = 3a + j.
@@ -428,6 +459,19 @@ hipError_t launch_project(const ProjectArgs &a, BlendRecord *rec, uint32_t *dept
         case 1: hipLaunchKernelGGL(k_project<1>, grid, dim3(256), 0, st, a, rec, depth_key, n_tiles, rect); break;
         case 2: hipLaunchKernelGGL(k_project<2>, grid, dim3(256), 0, st, a, rec, depth_key, n_tiles, rect); break;
         default: hipLaunchKernelGGL(k_project<3>, grid, dim3(256), 0, st, a, rec, depth_key, n_tiles, rect); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_project_batch(const ProjectArgs &a, const CamTable &cams, BlendRecord *rec, uint32_t *depth_key,
+                                uint32_t *n_tiles, uint2 *rect, hipStream_t st) {
+    if (a.n == 0 || cams.count == 0) return hipSuccess;
+    const dim3 grid((unsigned)((a.n + 255) / 256));
+    switch (a.sh_degree) {
+        case 0: hipLaunchKernelGGL(k_project_batch<0>, grid, dim3(256), 0, st, a, cams, rec, depth_key, n_tiles, rect); break;
+        case 1: hipLaunchKernelGGL(k_project_batch<1>, grid, dim3(256), 0, st, a, cams, rec, depth_key, n_tiles, rect); break;
+        case 2: hipLaunchKernelGGL(k_project_batch<2>, grid, dim3(256), 0, st, a, cams, rec, depth_key, n_tiles, rect); break;
+        default: hipLaunchKernelGGL(k_project_batch<3>, grid, dim3(256), 0, st, a, cams, rec, depth_key, n_tiles, rect); break;
     }
     return hipGetLastError();
 }

@@ -74,9 +74,17 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *wave_tot, 
 }
 
 // ---------------------------------------------------------------- radix pass
-__global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t *keys, int64_t n, int shift, int bits,
-                                                          uint32_t *counts, int nblocks) {
+// Element count of a sort: n, or min(n, *n_dev) when counted on the device.
+__device__ inline int64_t sort_count(int64_t n, const uint32_t *n_dev) {
+    if (!n_dev) return n;
+    const int64_t m = *n_dev;
+    return m < n ? m : n;
+}
+
+__global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t *keys, int64_t n_max, const uint32_t *n_dev,
+                                                          int shift, int bits, uint32_t *counts, int nblocks) {
     __shared__ uint32_t hist[kWaves][kBins];
+    const int64_t n = sort_count(n_max, n_dev);
     const int w = threadIdx.x / kWave, lane = __lane_id();
     for (int k = threadIdx.x; k < kWaves * kBins; k += kThreads) (&hist[0][0])[k] = 0;
     __syncthreads();
@@ -101,9 +109,9 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t *keys, i
 }
 
 __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t *keys_in, const uint32_t *vals_in,
-                                                             uint32_t *keys_out, uint32_t *vals_out, int64_t n,
-                                                             int shift, int bits, const uint32_t *offsets,
-                                                             int nblocks) {
+                                                             uint32_t *keys_out, uint32_t *vals_out, int64_t n_max,
+                                                             const uint32_t *n_dev, int shift, int bits,
+                                                             const uint32_t *offsets, int nblocks) {
     __shared__ uint32_t s_keys[kTileKeys];
     __shared__ uint32_t s_vals[kTileKeys];
     __shared__ uint32_t cnt[kWaves][kBins];
@@ -111,6 +119,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t *keys
     __shared__ uint32_t gbase[kBins];
     __shared__ uint32_t wave_tot[kWaves];
     __shared__ uint32_t total;
+    const int64_t n = sort_count(n_max, n_dev);
     const int w = threadIdx.x / kWave, lane = __lane_id();
     const uint32_t mask = (1u << bits) - 1u;
     const int64_t block0 = (int64_t)blockIdx.x * kTileKeys;
@@ -166,7 +175,8 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t *keys
         s_vals[pos] = val[it];
     }
     __syncthreads();
-    const int64_t nvalid = n - block0 < kTileKeys ? n - block0 : kTileKeys;
+    int64_t nvalid = n - block0 < kTileKeys ? n - block0 : kTileKeys;
+    if (nvalid < 0) nvalid = 0;
     for (int p = threadIdx.x; p < nvalid; p += kThreads) {
         const uint32_t k = s_keys[p];
         const uint32_t dg = (k >> shift) & mask;
@@ -258,23 +268,27 @@ __global__ __launch_bounds__(kThreads) void k_emit_partition(const uint32_t *ord
 
 __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *order, const uint32_t *n_tiles, const uint2 *rect,
                                                     const uint32_t *offs, int64_t n, const uint32_t *part,
-                                                    const uint32_t *m_dev, int tiles_x, uint32_t tile_base,
-                                                    uint64_t capacity, uint32_t *inst_tile, uint32_t *inst_gauss,
-                                                    int32_t *overflow) {
+                                                    const uint32_t *m_dev, EmitFrames F, uint64_t capacity,
+                                                    uint32_t *inst_tile, uint32_t *inst_gauss, int32_t *overflow) {
     __shared__ uint32_t s_off[kEmitSpan + 1];
     __shared__ uint32_t s_gid[kEmitSpan + 1];
     __shared__ uint2 s_rect[kEmitSpan + 1];
+    __shared__ uint8_t s_cam[kEmitSpan + 1];
     const uint64_t M = *m_dev;
     if (blockIdx.x == 0 && threadIdx.x == 0 && M > capacity && overflow) *overflow = 1;
     const uint64_t j0 = (uint64_t)blockIdx.x * kEmitSpan;
     if (j0 >= M || j0 >= capacity) return;
-    const uint64_t nblocks = (M + kEmitSpan - 1) / kEmitSpan;
+    // spans that start below min(M, capacity): the grid covers the capacity,
+    // and part[] is written for exactly these
+    uint64_t nblocks = (M + kEmitSpan - 1) / kEmitSpan;
+    if (nblocks > gridDim.x) nblocks = gridDim.x;
     const uint32_t r0 = part[blockIdx.x];
     // ranks of this span: r0 .. r1 (each visible rank owns >= 1 output, so a
     // span of kEmitSpan outputs touches at most kEmitSpan + 1 ranks)
     uint64_t r1 = blockIdx.x + 1 < nblocks ? part[blockIdx.x + 1] : (uint64_t)r0 + kEmitSpan;
     if (r1 > (uint64_t)n - 1) r1 = n - 1;
     if (r1 > (uint64_t)r0 + kEmitSpan) r1 = (uint64_t)r0 + kEmitSpan;
+    if (r1 < r0) r1 = r0;
     const int cnt = (int)(r1 - r0) + 1;
     for (int i = threadIdx.x; i < cnt; i += kThreads) {
         const uint32_t r = r0 + i;
@@ -282,6 +296,8 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *order, const 
         s_off[i] = offs[r];
         s_gid[i] = g;
         s_rect[i] = (g < (uint64_t)n && n_tiles[g]) ? rect[g] : make_uint2(0, 0);
+        // camera of record g = b * n_per + i
+        s_cam[i] = (uint8_t)(F.count > 1 && g < (uint64_t)n ? min((int64_t)g / F.n_per, (int64_t)F.count - 1) : 0);
     }
     __syncthreads();
     uint64_t jend = j0 + kEmitSpan;
@@ -298,10 +314,12 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *order, const 
         const uint2 rc = s_rect[lo];
         const uint32_t ntx = rc.x >> 16, tx0 = rc.x & 0xffffu, ty0 = rc.y & 0xffffu;
         if (ntx == 0) continue;
+        const int cam = s_cam[lo];
+        const uint32_t tiles_x = (uint32_t)F.tiles_x[cam];
         const uint32_t ty = ty0 + k / ntx;
         uint32_t tx = tx0 + k % ntx;
-        if (tx >= (uint32_t)tiles_x) tx -= tiles_x;
-        inst_tile[j] = tile_base + ty * (uint32_t)tiles_x + tx;
+        if (tx >= tiles_x) tx -= tiles_x;
+        inst_tile[j] = F.tile_base[cam] + ty * tiles_x + tx;
         inst_gauss[j] = s_gid[lo];
     }
 }
@@ -374,7 +392,7 @@ size_t sort_scratch_bytes(int64_t n) {
 
 hipError_t radix_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_tmp,
                             uint32_t *vals_tmp, uint32_t *keys_out, uint32_t *vals_out, int64_t n, int bits,
-                            void *scratch, hipStream_t st) {
+                            void *scratch, hipStream_t st, const uint32_t *n_dev) {
     if (n <= 0) return hipSuccess;
     const int64_t nb = blocks_for(n, kTileKeys);
     const int64_t cells = nb * kBins;
@@ -394,13 +412,13 @@ hipError_t radix_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in, ui
         uint32_t *dk = to_out ? keys_out : keys_tmp;
         uint32_t *dv = to_out ? vals_out : vals_tmp;
         (void)last;
-        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kThreads), 0, st, src_k, n, shift, pbits, counts,
-                           (int)nb);
+        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kThreads), 0, st, src_k, n, n_dev, shift, pbits,
+                           counts, (int)nb);
         // only (1 << pbits) digit rows are used: scan that prefix of the matrix
         hipError_t e = scan_exclusive(counts, offsets, (int64_t)(1 << pbits) * nb, nullptr, scan_tmp, st, nullptr);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kThreads), 0, st, src_k, src_v, dk, dv, n,
-                           shift, pbits, offsets, (int)nb);
+                           n_dev, shift, pbits, offsets, (int)nb);
         src_k = dk;
         src_v = dv;
     }
@@ -422,7 +440,7 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st) {
 uint64_t emit_blocks(uint64_t capacity) { return (capacity + kEmitSpan - 1) / kEmitSpan; }
 
 hipError_t launch_emit(const uint32_t *order, const uint32_t *n_tiles, const uint2 *rect, const uint32_t *offs,
-                       int64_t n, uint32_t *part, const uint32_t *m_dev, int tiles_x, uint32_t tile_base,
+                       int64_t n, uint32_t *part, const uint32_t *m_dev, const EmitFrames &frames,
                        uint64_t capacity, uint32_t *inst_tile, uint32_t *inst_gauss, int32_t *overflow,
                        hipStream_t st) {
     if (n <= 0 || capacity == 0) return hipSuccess;
@@ -430,7 +448,7 @@ hipError_t launch_emit(const uint32_t *order, const uint32_t *n_tiles, const uin
     hipLaunchKernelGGL(k_emit_partition, dim3((unsigned)blocks_for(n, kThreads)), dim3(kThreads), 0, st, order,
                        n_tiles, offs, n, nb, part);
     hipLaunchKernelGGL(k_emit, dim3((unsigned)nb), dim3(kThreads), 0, st, order, n_tiles, rect, offs, n,
-                       (const uint32_t *)part, m_dev, tiles_x, tile_base, capacity, inst_tile, inst_gauss, overflow);
+                       (const uint32_t *)part, m_dev, frames, capacity, inst_tile, inst_gauss, overflow);
     return hipGetLastError();
 }
 

@@ -106,7 +106,7 @@ def load_library(path: str = LIB_PATH):
         lib.omnigs_l1_loss.argtypes = [vp, vp, ctypes.c_int64, vp, vp, c_allocator, vp]
         lib.omnigs_l1_loss.restype = ctypes.c_int
         lib.omnigs_forward_batch.argtypes = [P(c_gaussians), P(c_camera), ctypes.c_int32, P(c_settings), c_allocator,
-                                             P(c_image_out), ctypes.c_int64, vp, vp]
+                                             P(c_image_out), ctypes.c_int64, vp, P(ctypes.c_int64), vp]
         lib.omnigs_forward_batch.restype = ctypes.c_int
         lib.omnigs_last_error.argtypes = []
         lib.omnigs_last_error.restype = ctypes.c_char_p
@@ -315,30 +315,59 @@ def omnigs_l1_loss(image: torch.Tensor, target: torch.Tensor, grad: bool = True,
     return loss, g
 
 
+OMNIGS_MAX_BATCH = 16
+
+
+class BatchResult:
+    """Outputs of omnigs_forward_batch: one dict(image, final_T, n_contrib
+    [, n_blended]) per camera, the device overflow flag and the instance
+    count (-1 when it was not read back)."""
+
+    def __init__(self, outs, overflow, n_instances, keepalive):
+        self.outs = outs
+        self.overflow = overflow
+        self.n_instances = n_instances
+        self._keep = keepalive
+
+
 def omnigs_forward_batch(g: dict, cameras: list, settings: dict | None = None, instance_capacity: int = 0,
-                         allocator: Allocator | None = None, outs: list | None = None):
-    """Render several cameras in one batched launch sequence.  Returns
-    (list of dict(image, final_T, n_contrib), overflow flag tensor)."""
+                         allocator: Allocator | None = None, outs: list | None = None,
+                         with_blended: bool = False) -> BatchResult:
+    """Render up to OMNIGS_MAX_BATCH cameras (mixed resolutions) in one
+    batched launch sequence on the current stream.  instance_capacity 0 reads
+    the instance count back (one host sync); > 0 enqueues only and flags
+    overflow on the device."""
     lib = load_library()
     dev = g["means"].device
     B = len(cameras)
     cg, cs = make_gaussians(g), make_settings(settings)
-    cams = (c_camera * B)(*[make_camera(c) for c in cameras])
+    cams = (c_camera * max(B, 1))(*[make_camera(c) for c in cameras])
     if outs is None:
         outs = []
         for c in cameras:
             H, W = int(c["height"]), int(c["width"])
-            outs.append(dict(image=torch.empty((3, H, W), dtype=torch.float32, device=dev),
-                             final_T=torch.empty((H, W), dtype=torch.float32, device=dev),
-                             n_contrib=torch.empty((H, W), dtype=torch.int32, device=dev)))
-    couts = (c_image_out * B)(*[c_image_out(_ptr(o["image"]), _ptr(o["final_T"]), _ptr(o["n_contrib"]),
-                                            _ptr(o.get("n_blended"))) for o in outs])
-    overflow = torch.zeros(1, dtype=torch.int32, device=dev)
+            o = dict(image=torch.empty((3, H, W), dtype=torch.float32, device=dev),
+                     final_T=torch.empty((H, W), dtype=torch.float32, device=dev),
+                     n_contrib=torch.empty((H, W), dtype=torch.int32, device=dev))
+            if with_blended:
+                o["n_blended"] = torch.empty((H, W), dtype=torch.int32, device=dev)
+            outs.append(o)
+    couts = (c_image_out * max(B, 1))(*[c_image_out(_ptr(o["image"]), _ptr(o["final_T"]), _ptr(o["n_contrib"]),
+                                                    _ptr(o.get("n_blended"))) for o in outs])
+    overflow = torch.empty(1, dtype=torch.int32, device=dev)
+    m = ctypes.c_int64(-1)
     al = allocator or Allocator(dev)
-    _check(lib.omnigs_forward_batch(ctypes.byref(cg), cams, B, ctypes.byref(cs), al.c, couts, int(instance_capacity),
-                                    ctypes.c_void_p(overflow.data_ptr()), ctypes.c_void_p(_stream_ptr(dev))))
-    al.scratch.clear()
-    return outs, overflow
+    try:
+        _check(lib.omnigs_forward_batch(ctypes.byref(cg), cams, B, ctypes.byref(cs), al.c, couts,
+                                        int(instance_capacity), ctypes.c_void_p(overflow.data_ptr()),
+                                        ctypes.byref(m), ctypes.c_void_p(_stream_ptr(dev))))
+    finally:
+        keep = list(al.scratch)
+        al.scratch.clear()
+    # scratch tensors go back to the caching allocator here; their reuse is
+    # ordered after the enqueued kernels on this stream
+    del keep
+    return BatchResult(outs, overflow, int(m.value), [])
 
 
 # ---------------------------------------------------------------- profiling

@@ -146,20 +146,27 @@ def poses(config: int, count: int, width: int, height: int, radius=1.0, yaw_zero
 SERVE_RESOLUTIONS = ((512, 256), (1024, 512), (2048, 1024), (3840, 1920))
 
 
-def request_stream(config: int, count: int, rate_hz: float, resolutions=SERVE_RESOLUTIONS):
-    """Poisson arrivals at ``rate_hz``: list of (arrival_s, camera)."""
-    rng = rng_for(config, STREAM_REQUESTS, int(rate_hz * 1000))
-    t = 0.0
+def serve_cameras(config: int, count: int, resolutions=SERVE_RESOLUTIONS):
+    """Cameras of a request stream: resolution uniform over `resolutions`,
+    centre uniform in the unit ball, random yaw (the same sequence whatever
+    the arrival rate)."""
+    rng = rng_for(config, STREAM_REQUESTS)
     out = []
     for _ in range(count):
-        t += rng.exponential(1.0 / rate_hz)
         w, h = resolutions[rng.integers(len(resolutions))]
         d = rng.normal(size=3)
         d /= np.linalg.norm(d)
         c = d * rng.uniform() ** (1.0 / 3.0)
         yaw = rng.uniform(-np.pi, np.pi)
-        out.append((t, camera(w, h, rot_y(yaw).T, c)))
+        out.append(camera(int(w), int(h), rot_y(yaw).T, c))
     return out
+
+
+def arrival_times(config: int, count: int, rate_hz: float, run: int = 0):
+    """Poisson arrivals: cumulative exponential gaps of mean 1 / rate_hz
+    (seconds), seeded per run."""
+    rng = rng_for(config, STREAM_REQUESTS, 1 + run)
+    return np.cumsum(rng.exponential(1.0 / rate_hz, size=count))
 
 
 # the workloads' scene definitions

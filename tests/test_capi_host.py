@@ -123,3 +123,58 @@ def test_profile_stage_names(lib):
                          "blend_fwd"]
     assert "blend_bwd" in names and "project_bwd" in names
     assert lib.omnigs_profile_stage_name(n).decode() == ""
+
+
+def _forward_batch(lib, g, cams, s, outs, alloc, batch=None, capacity=0):
+    B_ = len(cams) if batch is None else batch
+    ca = (B.c_camera * max(len(cams), 1))(*cams)
+    oa = (B.c_image_out * max(len(outs), 1))(*outs)
+    m = ctypes.c_int64(7)
+    rc = lib.omnigs_forward_batch(ctypes.byref(g), ca, B_, ctypes.byref(s), alloc, oa, capacity, None,
+                                  ctypes.byref(m), None)
+    return rc, m.value
+
+
+@pytest.mark.parametrize("case,needle", [
+    ("batch0", "batch 0"),
+    ("batch17", "batch 17"),
+    ("bad_width", "multiple of 16"),
+    ("null_out", "camera 1 is NULL"),
+    ("capacity", "instance_capacity"),
+    ("too_many_records", "below 2^32"),
+])
+def test_forward_batch_invalid_arguments(lib, case, needle):
+    g, c, s, out = _fake_args()
+    cams = [B.c_camera.from_buffer_copy(c) for _ in range(3)]
+    outs = [B.c_image_out(0x60000, 0x70000, 0x80000, None) for _ in range(3)]
+    batch, cap = None, 0
+    if case == "batch0":
+        batch = 0
+    elif case == "batch17":
+        batch = 17
+        cams = cams * 6
+        outs = outs * 6
+    elif case == "bad_width":
+        cams[2].width = 72 + 4
+    elif case == "null_out":
+        outs[1].final_T = None
+    elif case == "capacity":
+        cap = -5
+    elif case == "too_many_records":
+        g.n = (1 << 31) - 1
+    alloc, calls, keep = _alloc(fail=True)
+    rc, m = _forward_batch(lib, g, cams, s, outs, alloc, batch=batch, capacity=cap)
+    assert rc == B.OMNIGS_ERR_INVALID
+    assert needle in B.omnigs_last_error()
+    assert m == -1 and calls == []
+
+
+def test_forward_batch_allocator_failure(lib):
+    g, c, s, out = _fake_args(n=1000)
+    cams = [B.c_camera.from_buffer_copy(c) for _ in range(2)]
+    outs = [B.c_image_out(0x60000, 0x70000, 0x80000, None) for _ in range(2)]
+    alloc, calls, keep = _alloc(fail=True)
+    rc, m = _forward_batch(lib, g, cams, s, outs, alloc)
+    assert rc == B.OMNIGS_ERR_ALLOC
+    # one scratch allocation holding the records of both cameras
+    assert len(calls) == 1 and calls[0][1] == B.OMNIGS_MEM_SCRATCH and calls[0][0] >= 2 * 1000 * 48
