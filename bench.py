@@ -12,9 +12,12 @@ HBM when timing starts.
 
 Prints one JSON line (stdout) with the throughput, the roofline of the
 dominant kernel (from HIP-event timings of every stage taken during the timed
-region) and the FP64 CPU oracle timed on one pose of the same workload.
+region), the serving measurement (continuous batching vs one request at a
+time on the same resident scene: renders/s and p50/p99 latency at Poisson
+arrival rates of 0.5, 1 and 2 times the one-at-a-time capacity) and the FP64
+CPU oracle timed on one pose of the training workload.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-serve]
 """
 from __future__ import annotations
 
@@ -80,6 +83,57 @@ def cpu_baseline(g, pose, gt_image):
                        f"{dt:.1f} s")
 
 
+def serving_bench(gd, n_requests, slots, max_batch, log):
+    """Continuous-batching server vs one-request-at-a-time on the resident
+    1M-Gaussian scene: resolutions uniform over 512x256 .. 3840x1920, forward
+    only.  mu1 = the one-at-a-time capacity (all requests queued at once);
+    then Poisson arrivals at 0.5, 1 and 2 x mu1, the same requests for both."""
+    import torch
+    from paper_2404_03202_amd import omnigs as B
+    from paper_2404_03202_amd import scenes, serve
+
+    res = scenes.SERVE_RESOLUTIONS
+    cams = scenes.serve_cameras(4, n_requests)
+
+    def server(batched):
+        srv = serve.Server(gd, slots=slots if batched else 1, max_batch=max_batch if batched else 1,
+                           hbm_budget=32 << 30, keep_images=False)
+        srv.calibrate([scenes.camera(w, h) for (w, h) in res])
+        return srv
+
+    # warm the caching allocator and the code paths
+    for batched in (False, True):
+        server(batched).run(serve.make_requests(cams[:64]))
+    torch.cuda.synchronize()
+    sat = {}
+    for name, batched in (("one_at_a_time", False), ("batched", True)):
+        sat[name] = server(batched).run(serve.make_requests(cams))
+        log(f"serving saturated {name}: {sat[name]}")
+    mu1 = sat["one_at_a_time"]["renders_per_s"]
+    rates = []
+    for k, mult in enumerate((0.5, 1.0, 2.0)):
+        arr = scenes.arrival_times(4, n_requests, mult * mu1, run=k)
+        row = dict(multiplier=mult, rate_hz=mult * mu1)
+        for name, batched in (("one_at_a_time", False), ("batched", True)):
+            srv = server(batched)
+            keep = set(range(0, n_requests, max(1, n_requests // 24))) if (batched and mult == 2.0) else False
+            srv.keep_images = keep
+            reqs = serve.make_requests(cams, arr)
+            row[name] = srv.run(reqs)
+            log(f"serving {mult} x mu1 {name}: {row[name]}")
+            if keep:
+                # every kept result equals the render of that request alone
+                same = 0
+                for r in reqs:
+                    if r.image is not None:
+                        same += int(torch.equal(r.image, B.omnigs_forward(gd, r.camera).image))
+                row["identical_alone"] = f"{same}/{len(keep)}"
+        rates.append(row)
+    return dict(workload=f"resident 1M-Gaussian room scene, {n_requests} requests, resolution uniform over "
+                         + ", ".join(f"{w}x{h}" for w, h in res) + ", forward only",
+                slots=slots, max_batch=max_batch, mu1_renders_per_s=mu1, saturated=sat, poisson=rates)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +141,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--poses", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-requests", type=int, default=800)
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-max-batch", type=int, default=4)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run plain 256 MiB device copies (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -166,6 +224,8 @@ def main():
                            gaussians=int(g["means"].shape[0]), width=2048, height=1024, poses=len(poses)),
                stage_ms={k: v[0] / args.steps for k, v in prof.items() if v[1]},
                roofline=roofline)
+    if not args.no_serve:
+        out["serving"] = serving_bench(gd, args.serve_requests, args.serve_slots, args.serve_max_batch, log)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, one pose)...")
         out["cpu_baseline"] = cpu_baseline(g, poses[0], targets[0].cpu().numpy().astype(np.float64))

@@ -3,8 +3,10 @@
 Requests (an ERP camera pose and resolution) arrive over time.  The server
 keeps `slots` batches in flight, each on its own HIP stream (default
 priority).  Whenever a slot is free, it forms a batch from the requests that
-have arrived (FIFO, at most `max_batch`, and only while the estimated HBM
-footprint of everything in flight stays within `hbm_budget`), and enqueues it
+have arrived (FIFO, at most `max_batch`, at most `max_tiles` 16x16 tiles in
+all -- 2^16 keeps the batch's tile ids to two 8-bit radix passes -- and only
+while the estimated HBM footprint of everything in flight stays within
+`hbm_budget`), and enqueues it
 with one omnigs_forward_batch call in capacity mode: the instance buffers are
 sized from a running per-resolution estimate, so the call never waits on the
 device and the scheduler goes straight back to admitting and polling.
@@ -58,6 +60,10 @@ class Request:
         return int(self.camera["width"]) * int(self.camera["height"])
 
 
+def _tiles(camera) -> int:
+    return (int(camera["width"]) // 16) * ((int(camera["height"]) + 15) // 16)
+
+
 def footprint(n_gaussians: int, width: int, height: int, instances: int) -> int:
     tiles = (width // 16) * ((height + 15) // 16)
     return (n_gaussians * BYTES_PER_RECORD + instances * BYTES_PER_INSTANCE + width * height * BYTES_PER_PIXEL
@@ -77,11 +83,12 @@ class _Slot:
 class Server:
     """Continuous-batching server.  `instance_estimate` maps (width, height)
     to an instance count used to size capacities (learned upwards on
-    overflow); `margin` scales it."""
+    overflow); `margin` scales it.  `keep_images`: True, False, or a set of
+    request ids whose images are kept."""
 
     def __init__(self, gaussians: dict, settings: dict | None = None, slots: int = 2, max_batch: int = 8,
                  hbm_budget: int = 16 << 30, instance_estimate: dict | None = None, margin: float = 1.25,
-                 keep_images: bool = True):
+                 keep_images=True, max_tiles: int = 1 << 16):
         if not 1 <= max_batch <= B.OMNIGS_MAX_BATCH:
             raise ValueError(f"max_batch must be in [1, {B.OMNIGS_MAX_BATCH}]")
         self.g = gaussians
@@ -94,6 +101,7 @@ class Server:
         self.est = dict(instance_estimate or {})
         self.margin = margin
         self.keep_images = keep_images
+        self.max_tiles = max_tiles
         self.overflows = 0
         self.batches = 0
 
@@ -153,7 +161,8 @@ class Server:
             return
         for r, o in zip(batch, res.outs):
             r.done = now
-            r.image = o["image"] if self.keep_images else None
+            keep = self.keep_images is True or (self.keep_images and r.rid in self.keep_images)
+            r.image = o["image"] if keep else None
             done.append(r)
 
     def run(self, requests: list, clock=time.perf_counter, idle_sleep: float = 0.0) -> dict:
@@ -176,13 +185,17 @@ class Server:
                     continue
                 # admit while the footprint fits; a request larger than the
                 # whole budget still runs, alone, when nothing else is in flight
-                batch, need = [], 0
+                batch, need, tiles = [], 0, 0
                 while queue and len(batch) < self.max_batch:
                     b = self.request_bytes(queue[0])
                     if in_flight + need + b > self.budget and (batch or in_flight > 0):
                         break
+                    t = _tiles(queue[0].camera)
+                    if batch and tiles + t > self.max_tiles:
+                        break
                     batch.append(queue.popleft())
                     need += b
+                    tiles += t
                 if not batch:
                     break
                 self._launch(s, batch, clock() - t0)
