@@ -585,12 +585,13 @@ int orc_project(const orc_scene *s, double *rec) {
     return 0;
 }
 
-/* Sorted instance list.  Returns M, or -1 on error; writes at most cap
- * entries. */
-int64_t orc_tile_lists(const orc_scene *s, int64_t cap, int32_t *tile_out, int32_t *gid_out, double *tr_out) {
+/* Sorted instance list of the tiles set in tile_mask (NULL: all tiles).
+ * Returns M, or -1 on error; writes at most cap entries. */
+int64_t orc_tile_lists(const orc_scene *s, const uint8_t *tile_mask, int64_t cap, int32_t *tile_out, int32_t *gid_out,
+                       double *tr_out) {
     if (s->width % ORC_TILE != 0 || s->height < 1) return -1;
     orc_lists L;
-    if (build_lists(s, NULL, &L) != 0) {
+    if (build_lists(s, tile_mask, &L) != 0) {
         lists_free(&L);
         return -1;
     }
@@ -843,8 +844,9 @@ static void chain_one(const orc_scene *s, int64_t i, const orc_proj *P, const do
  * Gradient outputs are overwritten: dmeans [n][3], dscales [n][3],
  * dquats [n][4], dopac [n], dsh [n][sh_coeffs][3], dscreen [n][2].
  * acc_out (may be NULL): [n][9] screen-space accumulators.
- * abs_* (may all be NULL): sums of |per-pixel contributions| propagated
- * through |chain|, the scale against which FP32 sums are judged. */
+ * abs_* (may all be NULL): sums of |per-pixel contributions|, each weighted
+ * by 1 + the pixel's optical depth ln(1 / T_final), propagated through
+ * |chain|: the scale against which float32 sums are judged. */
 int orc_backward(const orc_scene *s, const uint8_t *tile_mask, const double *dLdC, double *dmeans, double *dscales,
                  double *dquats, double *dopac, double *dsh, double *dscreen, double *acc_out, double *abs_means,
                  double *abs_scales, double *abs_quats, double *abs_opac, double *abs_sh, double *abs_screen) {
@@ -890,6 +892,14 @@ int orc_backward(const orc_scene *s, const uint8_t *tile_mask, const double *dLd
                     render_pixel(s, &L, L.tstart[t], L.tend[t], x, y, -1, &px, con);
                     const int ncon = px.n_blended;
                     const double g[3] = {dLdC[p], dLdC[HW + p], dLdC[2 * HW + p]};
+                    /* weight of this pixel's |contributions| in the abs
+                     * sums: 1 + its optical depth ln(1 / T_final).  A float32
+                     * alpha carries a relative error of ~1e-6 and the
+                     * transmittance in front of or behind an instance is a
+                     * product over the pixel's blended instances, so a float32
+                     * contribution's relative error grows with the optical
+                     * depth (at most ln(1 / T_min)). */
+                    const double wd = 1.0 + log(1.0 / px.T);
                     /* S = colour blended behind the current instance, plus
                      * the background seen through the final transmittance */
                     double Sb[3];
@@ -903,7 +913,7 @@ int orc_backward(const orc_scene *s, const uint8_t *tile_mask, const double *dLd
                         for (int ch = 0; ch < 3; ++ch) {
                             const double term = g[ch] * c->alpha * c->T;
                             a[6 + ch] += term;
-                            aa[6 + ch] += fabs(term);
+                            aa[6 + ch] += fabs(term) * wd;
                             dalpha += g[ch] * (P->rgb[ch] * c->T - Sb[ch] / (1.0 - c->alpha));
                         }
                         for (int ch = 0; ch < 3; ++ch) Sb[ch] += P->rgb[ch] * c->alpha * c->T;
@@ -916,12 +926,12 @@ int orc_backward(const orc_scene *s, const uint8_t *tile_mask, const double *dLd
                         /* power depends on p through dx = x + 1/2 - p_x */
                         const double tpx = (P->Q[0] * c->dx + P->Q[1] * c->dy) * gpow;
                         const double tpy = (P->Q[1] * c->dx + P->Q[2] * c->dy) * gpow;
-                        a[0] += tpx; aa[0] += fabs(tpx);
-                        a[1] += tpy; aa[1] += fabs(tpy);
-                        a[2] += t0;  aa[2] += fabs(t0);
-                        a[3] += t1;  aa[3] += fabs(t1);
-                        a[4] += t2;  aa[4] += fabs(t2);
-                        a[5] += gO;  aa[5] += fabs(gO);
+                        a[0] += tpx; aa[0] += fabs(tpx) * wd;
+                        a[1] += tpy; aa[1] += fabs(tpy) * wd;
+                        a[2] += t0;  aa[2] += fabs(t0) * wd;
+                        a[3] += t1;  aa[3] += fabs(t1) * wd;
+                        a[4] += t2;  aa[4] += fabs(t2) * wd;
+                        a[5] += gO;  aa[5] += fabs(gO) * wd;
                     }
                 }
         }

@@ -82,7 +82,8 @@ def _load():
         P = ctypes.POINTER
         _lib.orc_project.argtypes = [P(_Scene), ctypes.c_void_p]
         _lib.orc_project.restype = ctypes.c_int
-        _lib.orc_tile_lists.argtypes = [P(_Scene), ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        _lib.orc_tile_lists.argtypes = [P(_Scene), ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p]
         _lib.orc_tile_lists.restype = ctypes.c_int64
         _lib.orc_render.argtypes = [P(_Scene)] + [ctypes.c_void_p] * 8
         _lib.orc_render.restype = ctypes.c_int
@@ -198,17 +199,20 @@ def project(scene: Scene) -> np.ndarray:
     return rec
 
 
-def tile_lists(scene: Scene):
-    """Sorted instances: (tile_id int32 [M], gaussian_id int32 [M], t_r float64 [M])."""
+def tile_lists(scene: Scene, tile_mask=None):
+    """Sorted instances: (tile_id int32 [M], gaussian_id int32 [M], t_r float64 [M]),
+    of the tiles set in ``tile_mask`` ([tiles] bool; None: all)."""
     lib = _load()
     s = scene._struct()
-    m = lib.orc_tile_lists(ctypes.byref(s), 0, None, None, None)
+    mk = _mask(scene, tile_mask)
+    mp = mk.ctypes.data if mk is not None else None
+    m = lib.orc_tile_lists(ctypes.byref(s), mp, 0, None, None, None)
     if m < 0:
         raise ValueError("oracle: invalid scene")
     tile = np.zeros(max(m, 1), dtype=np.int32)
     gid = np.zeros(max(m, 1), dtype=np.int32)
     tr = np.zeros(max(m, 1), dtype=np.float64)
-    m2 = lib.orc_tile_lists(ctypes.byref(s), m, tile.ctypes.data, gid.ctypes.data, tr.ctypes.data)
+    m2 = lib.orc_tile_lists(ctypes.byref(s), mp, m, tile.ctypes.data, gid.ctypes.data, tr.ctypes.data)
     assert m2 == m
     return tile[:m], gid[:m], tr[:m]
 
@@ -277,8 +281,10 @@ def backward(scene: Scene, dL_dimage, with_abs: bool = True, tile_mask=None):
 
     Returns dict(means, scales, quats, opacities, sh, screen, acc) and, with
     ``with_abs``, the same keys prefixed ``abs_``: sums of |per-pixel
-    contributions| pushed through |chain| (the scale FP32 sums are judged
-    against).  With ``tile_mask`` only those tiles are walked (exact when
+    contributions|, each weighted by 1 + the pixel's optical depth
+    ln(1 / T_final), pushed through |chain| (the scale float32 sums are judged
+    against: a float32 contribution's relative error grows with the optical
+    depth through the transmittance products).  With ``tile_mask`` only those tiles are walked (exact when
     dL_dimage vanishes elsewhere).
     """
     lib = _load()

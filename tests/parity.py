@@ -7,8 +7,11 @@
 * Tile lists: bit-exact, except that instances of one tile whose t_r agree to
   within the float32 resolution of the depth key may appear in any order.
 * Gradients: |g - g_o| <= 1e-3 max(|g_o|, 1e-2 A), where A is the oracle's sum
-  of |per-pixel contributions| to that entry (float32 atomic sums of terms of
-  both signs are judged against that scale), and per-group relative L2 <= 1e-3.
+  of |per-pixel contributions| to that entry, each weighted by 1 + the pixel's
+  optical depth ln(1 / T_final) (float32 sums of terms of both signs are
+  judged against that scale; a float32 alpha is accurate to ~1e-6 relative,
+  and the transmittance products carry that error through every instance of
+  the pixel), and per-group relative L2 <= 1e-3.
 """
 import numpy as np
 

@@ -1,0 +1,161 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py
+times (omnigs_forward / omnigs_backward, default settings):
+
+* 1M Gaussians in the room layout at 2048x1024 (a benchmark pose and a yaw-0
+  pose where the seam wedge straddles the +-pi seam);
+* 3M Gaussians with scales log-uniform [0.002, 0.5] at 3840x1920.
+
+The GPU renders and back-propagates the whole image; the FP64 oracle computes
+a sample of tiles one by one (seeded random tiles, the longest lists by the
+oracle's own projection, seam columns and pole rows): images, transmittance,
+contributor counts and tile lists on those tiles, and all gradients for a
+seeded cotangent that is zero outside them.  Properties that hold at any size
+are checked on every pixel.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2404_03202_amd import omnigs as B
+from paper_2404_03202_amd import scenes
+
+import parity
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+DEV = "cuda:0"
+NAMES = ["means", "scales", "quats", "opacities", "sh", "screen"]
+
+
+def to_dev(g):
+    d = {k: torch.from_numpy(np.ascontiguousarray(v, dtype=np.float32)).to(DEV)
+         for k, v in g.items() if k != "sh_degree"}
+    d["sh_degree"] = g["sh_degree"]
+    return d
+
+
+def tile_counts(rec, tiles_x, tiles_y, rows=None):
+    """Instances per tile from the oracle's projection records (each visible
+    Gaussian covers a rectangle of tiles, columns wrapping at the seam),
+    by a 2D difference array."""
+    F = O.REC_FIELDS
+    r = rec[rec[:, F["visible"]] > 0] if rows is None else rec[rows]
+    tx0, ntx = r[:, F["tx0"]].astype(np.int64), r[:, F["ntx"]].astype(np.int64)
+    ty0, nty = r[:, F["ty0"]].astype(np.int64), r[:, F["nty"]].astype(np.int64)
+    D = np.zeros((tiles_y + 1, tiles_x + 1), np.int64)
+    c1 = tx0 + ntx
+    wrap = c1 > tiles_x
+    for c0, c1_, rr in ((tx0, np.minimum(c1, tiles_x), np.ones(len(r), bool)), (np.zeros_like(tx0), c1 - tiles_x, wrap)):
+        np.add.at(D, (ty0[rr], c0[rr]), 1)
+        np.add.at(D, (ty0[rr], c1_[rr]), -1)
+        np.add.at(D, (ty0[rr] + nty[rr], c0[rr]), -1)
+        np.add.at(D, (ty0[rr] + nty[rr], c1_[rr]), 1)
+    return D.cumsum(0).cumsum(1)[:tiles_y, :tiles_x].reshape(-1)
+
+
+def sample_tiles(sc, counts, rng, n_random=32, n_longest=6):
+    """Tile mask: random tiles, the longest lists, seam columns and the pole
+    rows."""
+    tx_n, ty_n = sc.tiles_x, sc.tiles_y
+    mask = np.zeros(tx_n * ty_n, bool)
+    mask[rng.choice(tx_n * ty_n, n_random, replace=False)] = True
+    mask[np.argsort(counts, kind="stable")[-n_longest:]] = True
+    for ty in rng.choice(ty_n, 3, replace=False):
+        mask[ty * tx_n] = mask[ty * tx_n + tx_n - 1] = True        # both sides of the seam
+    mask[rng.choice(tx_n, 2, replace=False)] = True                   # top row
+    mask[(ty_n - 1) * tx_n + rng.choice(tx_n, 2, replace=False)] = True  # bottom row
+    return mask
+
+
+def tile_pixels(sc, mask):
+    pm = mask.reshape(sc.tiles_y, sc.tiles_x).repeat(16, 0).repeat(16, 1)[:sc.height, :sc.width]
+    return np.nonzero(pm)
+
+
+def check_fullsize(g, cam, seed, n_random=32):
+    sc = O.Scene(g, cam)
+    rng = np.random.default_rng([seed, scenes.STREAM_FD])
+    rec = O.project(sc)
+    flagged = np.nonzero(rec[:, O.REC_FIELDS["flag"]] > 0)[0]
+    counts = tile_counts(rec, sc.tiles_x, sc.tiles_y)
+    mask = sample_tiles(sc, counts, rng, n_random=n_random)
+    print(f"sampled {mask.sum()} tiles; longest list {counts.max()}", flush=True)
+    gd = to_dev(g)
+    fwd = B.omnigs_forward(gd, cam, with_blended=True)
+    torch.cuda.synchronize()
+    img, T, nc = (x.cpu().numpy() for x in (fwd.image, fwd.final_T, fwd.n_contrib))
+
+    # properties at every pixel
+    assert np.isfinite(img).all() and (img >= 0).all()
+    assert (T >= np.float32(1e-4)).all() and (T <= 1.0).all()
+    it, ig, rng_t = (x.cpu().numpy() for x in fwd.instance_lists())
+    lens = (rng_t[:, 1] - rng_t[:, 0]).reshape(sc.tiles_y, sc.tiles_x)
+    per_pix = lens.repeat(16, 0).repeat(16, 1)[:sc.height, :sc.width]
+    assert (nc >= 0).all() and (nc <= per_pix).all()
+    assert (np.diff(it.astype(np.int64)) >= 0).all(), "instances not sorted by tile"
+    # per-tile counts on every tile, except tiles within one tile of a
+    # Gaussian with a near-tie rect bound
+    near = tile_counts(rec, sc.tiles_x, sc.tiles_y, rows=flagged).reshape(sc.tiles_y, sc.tiles_x) > 0
+    near = near | np.roll(near, 1, 1) | np.roll(near, -1, 1)
+    near[1:] |= near[:-1].copy()
+    near[:-1] |= near[1:].copy()
+    ok = ~near.reshape(-1)
+    np.testing.assert_array_equal(lens.reshape(-1)[ok], counts[ok])
+    print(f"tile counts equal on {ok.sum()} of {ok.size} tiles; {len(flagged)} flagged Gaussians", flush=True)
+
+    # sampled tiles against the oracle
+    orc = O.render(sc, tile_mask=mask)
+    ys, xs = tile_pixels(sc, mask)
+    sub = lambda a: a[..., ys, xs][..., None, :]
+    osub = {k: (sub(v) if v is not None else None) for k, v in orc.items()}
+    rep = parity.check_image(sub(img), osub, what="full-size sampled tiles")
+    parity.check_transmittance(sub(T), sub(nc), osub)
+    sel = osub["n_flags"] == 0
+    assert (sub(fwd.n_blended.cpu().numpy())[sel] == osub["n_blended"][sel]).all()
+    ot, og, otr = O.tile_lists(sc, tile_mask=mask)
+    gpu_t, gpu_g = [], []
+    for t in np.nonzero(mask)[0]:
+        a, b = rng_t[t]
+        gpu_t.append(it[a:b])
+        gpu_g.append(ig[a:b])
+    rep.update(parity.check_tile_lists(np.concatenate(gpu_t), np.concatenate(gpu_g), ot, og, otr, flagged))
+
+    # backward: seeded cotangent on the sampled tiles, zero elsewhere and at
+    # pixels with a near-threshold decision
+    G = np.zeros((3, sc.height, sc.width))
+    G[:, ys, xs] = rng.normal(size=(3, len(ys))) / len(ys)
+    G *= (orc["n_grad_flags"] == 0)[None]
+    Gd = torch.from_numpy(G.astype(np.float32)).to(DEV)
+    grads = B.omnigs_backward(gd, cam, None, fwd, Gd)
+    torch.cuda.synchronize()
+    ob = O.backward(sc, G.astype(np.float32).astype(np.float64), tile_mask=mask)
+    gg = {k: v.cpu().numpy() for k, v in grads.items()}
+    touched = np.unique(og)
+    untouched = np.setdiff1d(np.arange(sc.n), np.union1d(touched, flagged))
+    for k in NAMES:
+        assert (gg[k][untouched] == 0).all(), f"grad {k} nonzero for a Gaussian outside the sampled tiles"
+    rep.update(parity.check_grads(gg, ob, NAMES, skip_rows=flagged))
+    print("full-size parity", rep, flush=True)
+    return rep
+
+
+@pytest.fixture(scope="module")
+def room1m():
+    return scenes.room_scene(2, 1_000_000)
+
+
+def test_fullsize_1m_2048x1024_bench_pose(room1m):
+    cam = scenes.poses(2, 200, 2048, 1024)[0]
+    check_fullsize(room1m, cam, seed=200)
+
+
+def test_fullsize_1m_2048x1024_seam_pose(room1m):
+    # yaw 0: the wedge at world longitude pi straddles the seam
+    cam = scenes.camera(2048, 1024, np.eye(3), [0.2, -0.1, 0.15])
+    check_fullsize(room1m, cam, seed=201)
+
+
+def test_fullsize_3m_3840x1920():
+    g, poses, _ = scenes.config3(n_poses=1)
+    check_fullsize(g, poses[0], seed=300, n_random=24)

@@ -191,6 +191,28 @@ def test_blend_invariants_random_scene():
         assert np.all(np.diff(tr[sel]) >= 0)
 
 
+def test_masked_tile_lists_and_render_are_restrictions():
+    """A tile mask only selects tiles: the masked lists are the full lists
+    filtered, and a masked render equals the full render on those tiles."""
+    g = scenes.room_scene(31, 3000, seam_fraction=0.4)
+    sc = O.Scene(g, scenes.camera(256, 128, np.eye(3), [0.1, 0.0, -0.2]))
+    rng = np.random.default_rng(5)
+    mask = rng.uniform(size=sc.tiles_x * sc.tiles_y) < 0.2
+    mask[0] = mask[sc.tiles_x - 1] = True          # both sides of the seam
+    t, gi, tr = O.tile_lists(sc)
+    tm, gm, trm = O.tile_lists(sc, tile_mask=mask)
+    keep = mask[t]
+    np.testing.assert_array_equal(tm, t[keep])
+    np.testing.assert_array_equal(gm, gi[keep])
+    np.testing.assert_array_equal(trm, tr[keep])
+    full = O.render(sc)
+    part = O.render(sc, tile_mask=mask)
+    pix = mask.reshape(sc.tiles_y, sc.tiles_x).repeat(16, 0).repeat(16, 1)[:sc.height, :sc.width]
+    for k in ("final_T", "n_contrib", "n_flags", "n_blended"):
+        np.testing.assert_array_equal(part[k][pix], full[k][pix])
+    np.testing.assert_array_equal(part["image"][:, pix], full["image"][:, pix])
+
+
 def test_transmittance_monotone_along_list():
     """Rendering with only the first k Gaussians of the depth order never
     raises T (Eq. 6: T = prod (1 - alpha_j))."""
