@@ -29,11 +29,13 @@
 // alpha_min, stop before T < T_min) from the saved final T and contributor
 // count, whatever the wave layout of each kernel.
 //
-// Backward reduction: a wave sums an instance's nine gradient terms to lane
-// 63 with DPP (quad permutes, row rotations, row broadcasts: no LDS traffic)
-// and adds them into the instance's LDS slot; after the batch, the lane that
-// staged the instance converts the sums and issues the float atomics to
-// global memory (one per nonzero field per (tile, instance)).
+// Backward reduction: a wave reduce-scatters an instance's nine gradient
+// terms across its lanes (gfx950 permlane swaps between wave halves and
+// between rows pair two fields per exchange, DPP finishes inside the rows: no
+// LDS traffic), and one lane per row adds up to three of the sums into the
+// instance's LDS slot; after the batch, the lane that staged the instance
+// converts the sums and issues the float atomics to global memory (one per
+// nonzero field per (tile, instance)).
 #include "internal.h"
 
 #ifndef OMNIGS_FWD_WAVES
@@ -288,18 +290,43 @@ __device__ __forceinline__ float dpp_add(float v) {
     return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kCtrl, kRowMask, 0xF, false));
 }
 
-// Sum over the 64 lanes of the wave, valid in lane 63: quad sums (quad_perm
-// [1,0,3,2], [2,3,0,1]), row sums (row_ror 4, 8), then row_bcast 15 folds
-// row 0 into row 1 and row 2 into row 3, and row_bcast 31 folds rows 0-1
-// into row 3.
-__device__ __forceinline__ float wave_sum_to_last(float v) {
-    v = dpp_add<0xB1, 0xF>(v);
-    v = dpp_add<0x4E, 0xF>(v);
-    v = dpp_add<0x124, 0xF>(v);
-    v = dpp_add<0x128, 0xF>(v);
-    v = dpp_add<0x142, 0xA>(v);
-    v = dpp_add<0x143, 0xC>(v);
+// Reduce-scatter of ten per-lane values over the wave: permlane32_swap
+// pairs the wave halves (two fields per swap + add), permlane16_swap pairs
+// the rows, and four DPP steps (row rotations, quad permutes) finish the sums
+// inside each 16-lane row.  Afterwards every lane of row r holds, in o[k],
+// the wave-wide sum of field kFieldOf[k][r] (o[2] rows 1-3: padding).
+__device__ __forceinline__ void swap_add(float &x, float &y, bool half32) {
+    const auto r = half32 ? __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false)
+                          : __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+    x = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float row_sum(float v) {
+    v = dpp_add<0x128, 0xF>(v);  // row_ror 8
+    v = dpp_add<0x124, 0xF>(v);  // row_ror 4
+    v = dpp_add<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+    v = dpp_add<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
     return v;
+}
+// field held by row r of output k: after the 32-lane step, register p holds
+// field 2p in lanes 0-31 and 2p+1 in lanes 32-63; the 16-lane step of
+// (p, q) leaves rows (2p, 2q, 2p+1, 2q+1)
+__device__ __forceinline__ int field_of(int k, int row) { return 4 * k + ((row & 1) << 1) + (row >> 1); }
+
+__device__ __forceinline__ void wave_reduce_scatter(const float (&v)[kAcc], float (&o)[3]) {
+    float a0 = v[0], a1 = v[2], a2 = v[4], a3 = v[6], a4 = v[8];
+    float b0 = v[1], b1 = v[3], b2 = v[5], b3 = v[7], b4 = 0.0f;
+    swap_add(a0, b0, true);
+    swap_add(a1, b1, true);
+    swap_add(a2, b2, true);
+    swap_add(a3, b3, true);
+    swap_add(a4, b4, true);
+    float z = 0.0f;
+    swap_add(a0, a1, false);
+    swap_add(a2, a3, false);
+    swap_add(a4, z, false);
+    o[0] = row_sum(a0);
+    o[1] = row_sum(a2);
+    o[2] = row_sum(a4);
 }
 
 template <int kW, bool kBatched>
@@ -406,13 +433,16 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, co
                 v[5] = __builtin_fmaf(G, da, v[5]);
             }
             if (__ballot(any) != 0ull) {
+                float o[3];
+                wave_reduce_scatter(v, o);
+                if ((lane & 15) == 15) {
+                    const int row = lane >> 4;
 #pragma unroll
-                for (int f = 0; f < kAcc; ++f) v[f] = wave_sum_to_last(v[f]);
-                if (lane == kWave - 1) {
-#pragma unroll
-                    for (int f = 0; f < kAcc; ++f) {
-                        if (kW == 1) part[j][f] = v[f];
-                        else atomicAdd(&part[j][f], v[f]);  // the waves of this instance meet here
+                    for (int k = 0; k < 3; ++k) {
+                        const int f = field_of(k, row);
+                        if (f >= kAcc) continue;
+                        if (kW == 1) part[j][f] = o[k];
+                        else atomicAdd(&part[j][f], o[k]);  // the waves of this instance meet here
                     }
                 }
             }
