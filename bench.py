@@ -134,6 +134,71 @@ def serving_bench(gd, n_requests, slots, max_batch, log):
                 slots=slots, max_batch=max_batch, mu1_renders_per_s=mu1, saturated=sat, poisson=rates)
 
 
+def stress_bench(steps, log):
+    """Large scene: 3M Gaussians (room layout, scales log-uniform [0.002,
+    0.5]) at 3840x1920, forward + L1 + backward per pose.  Reports stage
+    times, the algorithmic HBM rate of the sort and binning stages and the
+    algorithmic FP32 rate of the two blends."""
+    import torch
+    from paper_2404_03202_amd import omnigs as B
+    from paper_2404_03202_amd import scenes
+
+    g, poses, gt = scenes.config3(n_poses=4)
+    dev = "cuda:0"
+    gd = {k: (torch.from_numpy(v).to(dev) if k != "sh_degree" else v) for k, v in g.items()}
+    gtd = {k: (torch.from_numpy(v).to(dev) if k != "sh_degree" else v) for k, v in gt.items()}
+    targets = [B.omnigs_forward(gtd, p).image.clone() for p in poses]
+    del gtd
+    n = int(g["means"].shape[0])
+    W, H = 3840, 1920
+    tiles = (W // 16) * (H // 16)
+    inst = []
+
+    def step(k):
+        p = poses[k % len(poses)]
+        fwd = B.omnigs_forward(gd, p)
+        inst.append(fwd.n_instances)
+        _, dl = B.omnigs_l1_loss(fwd.image, targets[k % len(poses)])
+        B.omnigs_backward(gd, p, None, fwd, dl)
+
+    step(0)
+    torch.cuda.synchronize()
+    inst.clear()
+    B.omnigs_profile_read()
+    B.omnigs_profile_enable(True)
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(k)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    B.omnigs_profile_enable(False)
+    prof = B.omnigs_profile_read()
+    ms = {k: v[0] / steps for k, v in prof.items() if v[1]}
+    M = float(np.mean(inst))
+    walked = blended = 0
+    for k in range(steps):
+        f = B.omnigs_forward(gd, poses[k % len(poses)], with_blended=True)
+        walked += int(f.n_contrib.sum(dtype=torch.int64))
+        blended += int(f.n_blended.sum(dtype=torch.int64))
+    walked /= steps
+    blended /= steps
+    passes = -(-max(1, int(np.ceil(np.log2(tiles)))) // 8)
+    # algorithmic bytes per stage (u32 keys and values; each radix pass reads
+    # the keys for its histogram, then reads and writes key + value)
+    algo = dict(depth_sort=4 * 20 * n + 4 * n, emit_count=12 * n, emit=8 * M + 20 * n,
+                tile_sort=passes * 20 * M, tile_ranges=4 * M + 8 * tiles)
+    rates = {k: algo[k] / (ms[k] * 1e-3) / 1e9 for k in algo if k in ms}
+    out = dict(workload="3M Gaussians, room layout, scales log-uniform [0.002, 0.5], SH degree 3, 3840x1920 ERP, "
+                        f"{len(poses)} poses, forward + L1 + backward per pose",
+               steps=steps, ms_per_step=dt * 1e3 / steps, iters_per_s=steps / dt, instances_per_step=M,
+               tile_sort_passes=passes, stage_ms=ms, sort_binning_GBps=rates,
+               blend_pairs=dict(walked=walked, blended=blended),
+               blend_fwd_TFLOPs=FLOP_ALPHA * walked / (ms["blend_fwd"] * 1e-3) / 1e12,
+               blend_bwd_TFLOPs=(FLOP_ALPHA * walked + FLOP_GRAD * blended) / (ms["blend_bwd"] * 1e-3) / 1e12)
+    log(f"stress: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,6 +207,8 @@ def main():
     ap.add_argument("--poses", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--stress", action="store_true", help="also measure the 3M-Gaussian 3840x1920 workload")
+    ap.add_argument("--stress-steps", type=int, default=8)
     ap.add_argument("--serve-requests", type=int, default=800)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-max-batch", type=int, default=4)
@@ -224,6 +291,8 @@ def main():
                            gaussians=int(g["means"].shape[0]), width=2048, height=1024, poses=len(poses)),
                stage_ms={k: v[0] / args.steps for k, v in prof.items() if v[1]},
                roofline=roofline)
+    if args.stress:
+        out["stress"] = stress_bench(args.stress_steps, log)
     if not args.no_serve:
         out["serving"] = serving_bench(gd, args.serve_requests, args.serve_slots, args.serve_max_batch, log)
     if not args.no_cpu_baseline:
