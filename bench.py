@@ -151,19 +151,20 @@ def stress_bench(steps, log):
     del gtd
     n = int(g["means"].shape[0])
     W, H = 3840, 1920
-    tiles = (W // 16) * (H // 16)
-    inst = []
+    inst, entries = [], []
 
     def step(k):
         p = poses[k % len(poses)]
         fwd = B.omnigs_forward(gd, p)
         inst.append(fwd.n_instances)
+        entries.append(fwd.n_entries)
         _, dl = B.omnigs_l1_loss(fwd.image, targets[k % len(poses)])
         B.omnigs_backward(gd, p, None, fwd, dl)
 
     step(0)
     torch.cuda.synchronize()
     inst.clear()
+    entries.clear()
     B.omnigs_profile_read()
     B.omnigs_profile_enable(True)
     t0 = time.perf_counter()
@@ -175,6 +176,7 @@ def stress_bench(steps, log):
     prof = B.omnigs_profile_read()
     ms = {k: v[0] / steps for k, v in prof.items() if v[1]}
     M = float(np.mean(inst))
+    S = float(np.mean(entries))
     walked = blended = 0
     for k in range(steps):
         f = B.omnigs_forward(gd, poses[k % len(poses)], with_blended=True)
@@ -182,16 +184,20 @@ def stress_bench(steps, log):
         blended += int(f.n_blended.sum(dtype=torch.int64))
     walked /= steps
     blended /= steps
-    passes = -(-max(1, int(np.ceil(np.log2(tiles)))) // 8)
+    supers = ((W // 16 + 7) // 8) * ((H // 16 + 7) // 8)
+    passes = -(-max(1, int(np.ceil(np.log2(supers)))) // 8)
     # algorithmic bytes per stage (u32 keys and values; each radix pass reads
-    # the keys for its histogram, then reads and writes key + value)
-    algo = dict(depth_sort=4 * 20 * n + 4 * n, emit_count=12 * n, emit=8 * M + 20 * n,
-                tile_sort=passes * 20 * M, tile_ranges=4 * M + 8 * tiles)
+    # the keys for its histogram, then reads and writes key + value):
+    # depth sort over N; scans of the block and tile counts; block entries
+    # (S) emitted, sorted by block and ranged; the expansion reads every entry
+    # and its rectangle twice (count, write) and writes each instance once
+    algo = dict(depth_sort=4 * 20 * n + 4 * n, emit_count=20 * n, super_emit=8 * S + 20 * n,
+                super_sort=passes * 20 * S + 4 * S, tile_bin=24 * S + 4 * M)
     rates = {k: algo[k] / (ms[k] * 1e-3) / 1e9 for k in algo if k in ms}
     out = dict(workload="3M Gaussians, room layout, scales log-uniform [0.002, 0.5], SH degree 3, 3840x1920 ERP, "
                         f"{len(poses)} poses, forward + L1 + backward per pose",
                steps=steps, ms_per_step=dt * 1e3 / steps, iters_per_s=steps / dt, instances_per_step=M,
-               tile_sort_passes=passes, stage_ms=ms, sort_binning_GBps=rates,
+               block_entries_per_step=S, block_sort_passes=passes, stage_ms=ms, sort_binning_GBps=rates,
                blend_pairs=dict(walked=walked, blended=blended),
                blend_fwd_TFLOPs=FLOP_ALPHA * walked / (ms["blend_fwd"] * 1e-3) / 1e12,
                blend_bwd_TFLOPs=(FLOP_ALPHA * walked + FLOP_GRAD * blended) / (ms["blend_bwd"] * 1e-3) / 1e12)

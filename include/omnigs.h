@@ -107,13 +107,16 @@ typedef struct {
 typedef struct {
     int64_t n;           /* Gaussians                                    */
     int64_t n_instances; /* M: (Gaussian, covered tile) instances         */
+    int64_t n_entries;   /* S: (Gaussian, touched 8x8-tile block) entries  */
     int32_t width, height, tiles_x, tiles_y;
     const void *records;         /* [n] 48-byte blend records (opaque)              */
     const uint32_t *n_tiles;     /* [n] tiles covered per Gaussian, 0 when culled    */
     const uint32_t *depth_order; /* [n] Gaussian ids sorted by (t_r, id), culled last */
-    const uint32_t *inst_tile;   /* [M] tile id of each sorted instance             */
-    const uint32_t *inst_gauss;  /* [M] Gaussian id of each sorted instance         */
-    const uint32_t *tile_range;  /* [tiles][2] [start, end) into the sorted list    */
+    const uint32_t *inst_gauss;  /* [M] Gaussian ids: each tile's list contiguous,
+                                    in (t_r, id) order; tiles stored 8x8 block
+                                    by 8x8 block                                    */
+    const uint32_t *tile_range;  /* [tiles][2] [start, end) of tile ty*tiles_x+tx
+                                    in inst_gauss                                   */
     const uint32_t *tile_work;   /* [tiles] largest n_contrib of the tile (the
                                     backward's walk length)                        */
 } omnigs_state;
@@ -138,12 +141,14 @@ omnigs_settings omnigs_default_settings(void);
  *      radius of influence (the box of the alpha = alpha_min iso-ellipse),
  *      with its tile span wrapped across the longitude seam;
  *   2. depth sort of the Gaussians by t_r (Sec. 3.3: ERP sorts by distance,
- *      not t_z), then one instance per (Gaussian, covered tile) emitted in
- *      depth order and stably sorted by tile: each tile's list is in
- *      (t_r, id) order; per-tile [start, end) ranges;
+ *      not t_z), then one instance per (Gaussian, covered tile), in two
+ *      levels: an entry per touched block of 8x8 tiles, emitted in depth
+ *      order and stably sorted by block, then each block's list expanded
+ *      into its tiles' lists (each instance written once): each tile's list
+ *      is in (t_r, id) order; per-tile [start, end) ranges;
  *   3. front-to-back alpha blending of Eq. 6-8, one 16x16 tile per
  *      workgroup, stopping per pixel before T would drop below T_min.
- * The instance count M is read back to size the instance buffers: this is
+ * The instance counts are read back to size the instance buffers: this is
  * the only host synchronisation of the call.
  * Inputs: g (device arrays), cam and s (host).  Outputs: out (device,
  * caller-allocated) and *state (host struct; device buffers from `alloc`).

@@ -1,0 +1,241 @@
+// bin.hip -- second level of the tile binning (Sec. 3.3: one instance per
+// (Gaussian, covered tile), each tile's list ordered by t_r).
+//
+// The first level (sort.hip) leaves, for every super-tile of 8x8 tiles, the
+// list of records whose tile rectangle touches it, in depth order.  Here each
+// list is cut into chunks of kChunk entries.  For an entry, the 64 tiles of
+// its super-tile that the record covers form a 64-bit mask (its rectangle,
+// columns wrapping across the seam, clipped to the super-tile).  Per chunk,
+// 64 wave ballots (one per tile) give each tile's instance count and, in the
+// expansion, each entry's rank among the chunk's entries that cover the
+// tile, in list order.  Counts are laid out per super-tile as [tile][chunk],
+// super-tiles one after another, so that one exclusive scan yields at once
+// the start of every tile's list (tiles are stored super-tile by super-tile,
+// each tile's list contiguous) and the offset of every chunk inside it.
+// Every instance is then written once, to its final position: each tile's
+// list comes out in depth order, as a stable sort on the tile id would give.
+#include "internal.h"
+
+#include <algorithm>
+
+namespace omnigs {
+namespace {
+
+constexpr int kChunk = 256;  // super-list entries per chunk (one per thread)
+constexpr int kThreads = kChunk;
+constexpr int kWaves = kThreads / kWave;
+constexpr int kTilesPer = kSuper * kSuper;  // 64 tiles per super-tile
+
+__device__ inline int find_super_frame(const SuperTable &T, uint32_t s) {
+    int f = 0;
+    for (int k = 1; k < T.count; ++k)
+        if (s >= T.f[k].super_base) f = k;
+    return f;
+}
+
+// Tiles of super-tile (sx, sy) covered by the tile rectangle r: bit
+// 8 * (row in super-tile) + (column in super-tile).
+__device__ inline uint64_t cover_mask(uint2 r, int tiles_x, int sx, int sy) {
+    const int ntx = (int)(r.x >> 16), tx0 = (int)(r.x & 0xffffu), nty = (int)(r.y >> 16), ty0 = (int)(r.y & 0xffffu);
+    const int y_lo = max(ty0, sy * kSuper) - sy * kSuper, y_hi = min(ty0 + nty, sy * kSuper + kSuper) - sy * kSuper;
+    if (ntx == 0 || y_hi <= y_lo) return 0ull;
+    uint32_t cols = 0;
+#pragma unroll
+    for (int c = 0; c < kSuper; ++c) {
+        const int tx = sx * kSuper + c;
+        int d = tx - tx0;
+        d += d < 0 ? tiles_x : 0;  // offset from the rectangle's first column, modulo tiles_x
+        cols |= (tx < tiles_x && d < ntx) ? (1u << c) : 0u;
+    }
+    uint64_t m = 0;
+#pragma unroll
+    for (int k = 0; k < kSuper; ++k)
+        if (k >= y_lo && k < y_hi) m |= (uint64_t)cols << (kSuper * k);
+    return m;
+}
+
+// Position of (super-tile s, tile j, chunk c) in the count layout.
+__device__ inline uint64_t layout(uint32_t choff_s, uint32_t nch_s, int j, uint32_t c) {
+    return (uint64_t)kTilesPer * choff_s + (uint64_t)j * nch_s + c;
+}
+
+// Chunks of each super-tile's list.
+__global__ __launch_bounds__(256) void k_bin_chunks(const uint2 *sranges, uint32_t n_super, uint32_t *nch) {
+    const uint32_t s = blockIdx.x * 256u + threadIdx.x;
+    if (s >= n_super) return;
+    const uint32_t len = sranges[s].y - sranges[s].x;
+    nch[s] = (len + kChunk - 1) / kChunk;
+}
+
+// desc[k] = super-tile of chunk k.
+__global__ __launch_bounds__(256) void k_bin_desc(const uint32_t *choff, const uint32_t *nch, uint32_t n_super,
+                                                  uint64_t max_chunks, uint32_t *desc) {
+    const uint32_t s = blockIdx.x * 256u + threadIdx.x;
+    if (s >= n_super) return;
+    const uint32_t o = choff[s], n = nch[s];
+    for (uint32_t c = 0; c < n && (uint64_t)o + c < max_chunks; ++c) desc[o + c] = s;
+}
+
+__global__ __launch_bounds__(kThreads) void k_bin_count(SuperTable T, const uint2 *rect, const uint32_t *sinst_gauss,
+                                                        const uint2 *sranges, const uint32_t *choff,
+                                                        const uint32_t *nch, const uint32_t *desc, uint32_t n_super,
+                                                        uint32_t *counts) {
+    __shared__ uint32_t wcnt[kWaves][kTilesPer];
+    const uint32_t k = blockIdx.x;
+    const uint32_t K = choff[n_super];  // chunks in all (device)
+    const int w = threadIdx.x / kWave, lane = __lane_id();
+    if (k >= K) {
+        // slots past the last chunk: zero, so that the scan over the whole
+        // (capacity-sized) layout leaves every valid position exact
+        if (threadIdx.x < kTilesPer) counts[(uint64_t)kTilesPer * k + threadIdx.x] = 0u;
+        return;
+    }
+    const uint32_t s = desc[k], o = choff[s], n = nch[s], c = k - o;
+    const SuperFrame &F = T.f[find_super_frame(T, s)];
+    const uint32_t ls = s - F.super_base;
+    const int sx = (int)(ls % (uint32_t)F.super_x), sy = (int)(ls / (uint32_t)F.super_x);
+    const uint32_t e = sranges[s].x + c * kChunk + threadIdx.x;
+    uint64_t mask = 0ull;
+    if (e < sranges[s].y) mask = cover_mask(rect[sinst_gauss[e]], F.tiles_x, sx, sy);
+    uint32_t mine = 0;
+    for (int j = 0; j < kTilesPer; ++j) {
+        const uint32_t cnt = (uint32_t)__popcll(__ballot((mask >> j) & 1ull));
+        mine = (lane == j) ? cnt : mine;
+    }
+    wcnt[w][lane] = mine;
+    __syncthreads();
+    if (threadIdx.x < kTilesPer) {
+        uint32_t t = 0;
+#pragma unroll
+        for (int q = 0; q < kWaves; ++q) t += wcnt[q][threadIdx.x];
+        counts[layout(o, n, threadIdx.x, c)] = t;
+    }
+}
+
+// [start, end) of every tile, from the scanned counts.
+__global__ __launch_bounds__(256) void k_bin_ranges(SuperTable T, uint32_t n_super, const uint32_t *choff,
+                                                    const uint32_t *nch, const uint32_t *scanned, uint64_t inst_cap,
+                                                    uint2 *ranges) {
+    const uint64_t id = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+    if (id >= (uint64_t)n_super * kTilesPer) return;
+    const uint32_t s = (uint32_t)(id / kTilesPer);
+    const int j = (int)(id % kTilesPer);
+    const SuperFrame &F = T.f[find_super_frame(T, s)];
+    const uint32_t ls = s - F.super_base;
+    const int tx = (int)(ls % (uint32_t)F.super_x) * kSuper + j % kSuper;
+    const int ty = (int)(ls / (uint32_t)F.super_x) * kSuper + j / kSuper;
+    if (tx >= F.tiles_x || ty >= F.tiles_y) return;
+    const uint32_t o = choff[s], n = nch[s];
+    uint64_t a = scanned[layout(o, n, j, 0)], b = scanned[layout(o, n, j + 1, 0)];
+    a = a < inst_cap ? a : inst_cap;
+    b = b < inst_cap ? b : inst_cap;
+    ranges[F.tile_base + (uint32_t)ty * (uint32_t)F.tiles_x + (uint32_t)tx] = make_uint2((uint32_t)a, (uint32_t)b);
+}
+
+// Every instance of the chunk to its final position.
+__global__ __launch_bounds__(kThreads) void k_bin_expand(SuperTable T, const uint2 *rect, const uint32_t *sinst_gauss,
+                                                         const uint2 *sranges, const uint32_t *choff,
+                                                         const uint32_t *nch, const uint32_t *desc, uint32_t n_super,
+                                                         const uint32_t *scanned, uint64_t inst_cap,
+                                                         uint32_t *inst_gauss, int32_t *overflow) {
+    __shared__ uint64_t wball[kWaves][kTilesPer];
+    __shared__ uint32_t wpre[kWaves][kTilesPer];
+    const uint32_t k = blockIdx.x;
+    if (k >= choff[n_super]) return;
+    const int w = threadIdx.x / kWave, lane = __lane_id();
+    const uint32_t s = desc[k], o = choff[s], n = nch[s], c = k - o;
+    const SuperFrame &F = T.f[find_super_frame(T, s)];
+    const uint32_t ls = s - F.super_base;
+    const int sx = (int)(ls % (uint32_t)F.super_x), sy = (int)(ls / (uint32_t)F.super_x);
+    const uint32_t e = sranges[s].x + c * kChunk + threadIdx.x;
+    uint64_t mask = 0ull;
+    uint32_t g = 0;
+    if (e < sranges[s].y) {
+        g = sinst_gauss[e];
+        mask = cover_mask(rect[g], F.tiles_x, sx, sy);
+    }
+    uint64_t mine = 0;
+    for (int j = 0; j < kTilesPer; ++j) {
+        const uint64_t b = __ballot((mask >> j) & 1ull);
+        mine = (lane == j) ? b : mine;
+    }
+    wball[w][lane] = mine;
+    __syncthreads();
+    if (threadIdx.x < kTilesPer) {
+        // start of this chunk's instances in tile j, plus the entries of the
+        // earlier waves that cover the tile
+        const int j = threadIdx.x;
+        uint32_t run = scanned[layout(o, n, j, c)];
+#pragma unroll
+        for (int q = 0; q < kWaves; ++q) {
+            wpre[q][j] = run;
+            run += (uint32_t)__popcll(wball[q][j]);
+        }
+    }
+    __syncthreads();
+    const uint64_t below = (1ull << lane) - 1ull;
+    bool dropped = false;
+    for (int j = 0; j < kTilesPer; ++j) {
+        const uint64_t b = wball[w][j];
+        if (b == 0ull) continue;  // uniform
+        if ((mask >> j) & 1ull) {
+            const uint64_t pos = (uint64_t)wpre[w][j] + (uint64_t)__popcll(b & below);
+            if (pos < inst_cap) inst_gauss[pos] = g;
+            else dropped = true;
+        }
+    }
+    if (dropped && overflow) *overflow = 1;
+}
+
+int64_t blocks_for(int64_t n, int64_t per) { return (n + per - 1) / per; }
+
+uint64_t max_chunks(uint64_t super_cap, uint32_t n_super_total) {
+    return (super_cap + kChunk - 1) / kChunk + n_super_total;
+}
+
+}  // namespace
+
+size_t binning_scratch_bytes(uint64_t super_cap, uint32_t n_super_total) {
+    const uint64_t K = max_chunks(super_cap, n_super_total);
+    const uint64_t cells = (uint64_t)kTilesPer * K;
+    auto al = [](uint64_t b) { return (size_t)((b + 255) & ~(uint64_t)255); };
+    return al(4ull * n_super_total) + al(4ull * (n_super_total + 1)) + al(4ull * K) + al(4ull * cells) +
+           al(4ull * (cells + 1)) + scan_scratch_bytes((int64_t)std::max<uint64_t>(cells, n_super_total)) + 256;
+}
+
+hipError_t launch_binning(const SuperTable &T, uint32_t n_super_total, const uint2 *rect, const uint32_t *sinst_gauss,
+                          const uint2 *sranges, uint64_t super_cap, uint64_t inst_cap, void *scratch, uint2 *ranges,
+                          uint32_t *inst_gauss, int32_t *overflow, hipStream_t st) {
+    if (n_super_total == 0) return hipSuccess;
+    const uint64_t K = max_chunks(super_cap, n_super_total);
+    const uint64_t cells = (uint64_t)kTilesPer * K;
+    auto al = [](uint64_t b) { return (size_t)((b + 255) & ~(uint64_t)255); };
+    char *p = static_cast<char *>(scratch);
+    uint32_t *nch = reinterpret_cast<uint32_t *>(p);
+    p += al(4ull * n_super_total);
+    uint32_t *choff = reinterpret_cast<uint32_t *>(p);
+    p += al(4ull * (n_super_total + 1));
+    uint32_t *desc = reinterpret_cast<uint32_t *>(p);
+    p += al(4ull * K);
+    uint32_t *counts = reinterpret_cast<uint32_t *>(p);
+    p += al(4ull * cells);
+    uint32_t *scanned = reinterpret_cast<uint32_t *>(p);
+    p += al(4ull * (cells + 1));
+    void *scan_tmp = p;
+    const unsigned sb = (unsigned)blocks_for(n_super_total, 256);
+    hipLaunchKernelGGL(k_bin_chunks, dim3(sb), dim3(256), 0, st, sranges, n_super_total, nch);
+    hipError_t e = scan_exclusive(nch, choff, n_super_total, choff + n_super_total, scan_tmp, st, nullptr);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bin_desc, dim3(sb), dim3(256), 0, st, choff, nch, n_super_total, K, desc);
+    hipLaunchKernelGGL(k_bin_count, dim3((unsigned)K), dim3(kThreads), 0, st, T, rect, sinst_gauss, sranges, choff, nch,
+                       desc, n_super_total, counts);
+    e = scan_exclusive(counts, scanned, (int64_t)cells, scanned + cells, scan_tmp, st, nullptr);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bin_ranges, dim3((unsigned)blocks_for((int64_t)n_super_total * kTilesPer, 256)), dim3(256), 0,
+                       st, T, n_super_total, choff, nch, scanned, inst_cap, ranges);
+    hipLaunchKernelGGL(k_bin_expand, dim3((unsigned)K), dim3(kThreads), 0, st, T, rect, sinst_gauss, sranges, choff,
+                       nch, desc, n_super_total, scanned, inst_cap, inst_gauss, overflow);
+    return hipGetLastError();
+}
+
+}  // namespace omnigs

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -40,9 +41,9 @@ enum Stage {
     kStProject = 0,
     kStDepthSort,
     kStEmitCount,
-    kStEmit,
-    kStTileSort,
-    kStRanges,
+    kStSuperEmit,
+    kStSuperSort,
+    kStTileBin,
     kStTileOrder,
     kStBlendFwd,
     kStL1,
@@ -51,8 +52,8 @@ enum Stage {
     kStProjectBwd,
     kStCount
 };
-const char *kStageNames[kStCount] = {"project",    "depth_sort", "emit_count", "emit",      "tile_sort",
-                                     "tile_ranges", "tile_order", "blend_fwd",  "l1_loss",   "bwd_clear",
+const char *kStageNames[kStCount] = {"project",    "depth_sort", "emit_count", "super_emit", "super_sort",
+                                     "tile_bin",   "tile_order", "blend_fwd",  "l1_loss",    "bwd_clear",
                                      "blend_bwd",  "project_bwd"};
 
 struct Profiler {
@@ -209,7 +210,7 @@ int bits_for(uint64_t count) {
     return b;
 }
 
-// N-sized buffers of one forward: persistent part (state) and scratch.
+// Per-record buffers of one forward: persistent part (state) and scratch.
 struct GeomState {
     BlendRecord *rec;
     uint32_t *n_tiles, *order;
@@ -223,7 +224,8 @@ struct GeomState {
     }
 };
 struct GeomScratch {
-    uint32_t *depth_key, *iota, *keys_tmp, *vals_tmp, *keys_sorted, *offs;
+    uint32_t *depth_key, *iota, *keys_tmp, *vals_tmp, *keys_sorted, *offs, *n_super;
+    uint32_t *totals;  // [0] super entries S, [1] tile instances M (adjacent: one readback)
     void *sort_tmp, *scan_tmp;
     void carve(Arena &a, int64_t n) {
         const size_t m = (size_t)(n > 0 ? n : 1);
@@ -233,19 +235,17 @@ struct GeomScratch {
         vals_tmp = a.take<uint32_t>(m);
         keys_sorted = a.take<uint32_t>(m);
         offs = a.take<uint32_t>(m + 1);
+        n_super = a.take<uint32_t>(m);
+        totals = a.take<uint32_t>(2);
         sort_tmp = a.take_bytes(sort_scratch_bytes((int64_t)m));
         scan_tmp = a.take_bytes(scan_scratch_bytes((int64_t)m));
     }
 };
 
-// Projection, depth sort and per-rank instance offsets of one camera.
-// Leaves the instance total M in gs.offs[n].
-omnigs_status run_geometry(const ProjectArgs &pa, GeomState &gst, GeomScratch &gs, hipStream_t st) {
-    const int64_t n = pa.n;
-    {
-        StageTimer t(st, kStProject);
-        HIP_TRY(launch_project(pa, gst.rec, gs.depth_key, gst.n_tiles, gst.rect, st));
-    }
+// Depth sort and per-rank super-entry offsets of n records (projected
+// already): gs.offs, S at gs.totals[0], M = total tile instances at
+// gs.totals[1].
+omnigs_status sort_and_count(int64_t n, GeomState &gst, GeomScratch &gs, hipStream_t st) {
     {
         StageTimer t(st, kStDepthSort);
         HIP_TRY(launch_iota(gs.iota, n, st));
@@ -254,7 +254,76 @@ omnigs_status run_geometry(const ProjectArgs &pa, GeomState &gst, GeomScratch &g
     }
     {
         StageTimer t(st, kStEmitCount);
-        HIP_TRY(scan_exclusive(gst.n_tiles, gs.offs, n, gs.offs + n, gs.scan_tmp, st, gst.order));
+        HIP_TRY(scan_exclusive(gs.n_super, gs.offs, n, gs.totals, gs.scan_tmp, st, gst.order));
+        // the sort's key scratch is free again: it takes the (unused) scan of
+        // the tile counts whose total is M
+        HIP_TRY(scan_exclusive(gst.n_tiles, gs.keys_tmp, n, gs.totals + 1, gs.scan_tmp, st, nullptr));
+    }
+    return OMNIGS_OK;
+}
+
+// Grids of the images of a launch.
+struct Grids {
+    EmitFrames ef{};   // super-tile emission
+    SuperTable sup{};  // super-tile and tile grids
+    uint32_t n_super = 0, n_tiles = 0;
+    void add(int b, int tiles_x, int tiles_y) {
+        const int sx = (tiles_x + kSuper - 1) / kSuper, sy = (tiles_y + kSuper - 1) / kSuper;
+        ef.tiles_x[b] = tiles_x;
+        ef.cols[b] = sx;
+        ef.base[b] = n_super;
+        sup.f[b] = SuperFrame{n_super, n_tiles, sx, sy, tiles_x, tiles_y};
+        n_super += (uint32_t)(sx * sy);
+        n_tiles += (uint32_t)(tiles_x * tiles_y);
+    }
+};
+
+// Scratch of the two-level binning for super_cap super entries.
+struct BinScratch {
+    uint32_t *stile, *sgauss, *stile_tmp, *sgauss_tmp, *part;
+    uint2 *sranges;
+    void *sort_tmp, *bin_tmp;
+    void carve(Arena &a, uint64_t super_cap, uint32_t n_super) {
+        const size_t m = (size_t)(super_cap > 0 ? super_cap : 1);
+        stile = a.take<uint32_t>(m);
+        sgauss = a.take<uint32_t>(m);
+        stile_tmp = a.take<uint32_t>(m);
+        sgauss_tmp = a.take<uint32_t>(m);
+        part = a.take<uint32_t>((size_t)emit_blocks(super_cap) + 1);
+        sranges = a.take<uint2>(n_super > 0 ? n_super : 1);
+        sort_tmp = a.take_bytes(sort_scratch_bytes((int64_t)m));
+        bin_tmp = a.take_bytes(binning_scratch_bytes(super_cap, n_super));
+    }
+};
+
+// Two-level binning of nrec depth-sorted records into per-tile lists:
+// super-tile entries in depth order (emission), a stable sort by super-tile,
+// and the expansion into the lists of the tiles (bin.hip).  With counted ==
+// true the entry count is read on the device (min(S, super_cap)).
+omnigs_status run_binning(int64_t nrec, const GeomState &gst, const GeomScratch &gs, const Grids &G,
+                          uint64_t super_cap, uint64_t inst_cap, bool counted, BinScratch &bs, uint2 *ranges,
+                          uint32_t *inst_gauss, int32_t *overflow, hipStream_t st) {
+    const int bits = bits_for(G.n_super);
+    const bool odd = ((bits + 7) / 8) % 2;
+    uint32_t *et = odd ? bs.stile_tmp : bs.stile, *eg = odd ? bs.sgauss_tmp : bs.sgauss;
+    {
+        StageTimer t(st, kStSuperEmit);
+        // emit where the sort's ping-pong starts, so that the last pass lands
+        // in stile / sgauss
+        HIP_TRY(launch_emit(gst.order, gs.n_super, gst.rect, gs.offs, nrec, bs.part, gs.totals, G.ef, super_cap, et,
+                            eg, overflow, st));
+    }
+    {
+        StageTimer t(st, kStSuperSort);
+        HIP_TRY(radix_sort_pairs(et, eg, bs.stile_tmp, bs.sgauss_tmp, bs.stile, bs.sgauss, (int64_t)super_cap, bits,
+                                 bs.sort_tmp, st, counted ? gs.totals : nullptr));
+        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(bs.sranges), 0u, 2 * (int64_t)G.n_super, st));
+        HIP_TRY(launch_tile_ranges(bs.stile, gs.totals, super_cap, bs.sranges, G.n_super, st));
+    }
+    {
+        StageTimer t(st, kStTileBin);
+        HIP_TRY(launch_binning(G.sup, G.n_super, gst.rect, bs.sgauss, bs.sranges, super_cap, inst_cap, bs.bin_tmp,
+                               ranges, inst_gauss, overflow, st));
     }
     return OMNIGS_OK;
 }
@@ -305,73 +374,48 @@ omnigs_status omnigs_forward(const omnigs_gaussians *g, const omnigs_camera *cam
         return rc;
     gs.carve(ta, n);
 
-    if ((rc = run_geometry(pa, gst, gs, st)) != OMNIGS_OK) return rc;
+    {
+        StageTimer t(st, kStProject);
+        HIP_TRY(launch_project(pa, gst.rec, gs.depth_key, gst.n_tiles, gst.rect, gs.n_super, st));
+    }
+    if ((rc = sort_and_count(n, gst, gs, st)) != OMNIGS_OK) return rc;
 
-    // instance count: the one host synchronisation
-    uint32_t m32 = 0;
-    HIP_TRY(hipMemcpyAsync(&m32, gs.offs + n, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    // super entries S and tile instances M: the one host synchronisation
+    uint32_t tot[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(tot, gs.totals, sizeof(tot), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    const int64_t M = m32;
+    const int64_t S = tot[0], M = tot[1];
 
-    // M-sized buffers
-    const int bits = bits_for(ntiles);
-    const int passes = (bits + 7) / 8;
+    Grids G;
+    G.ef.n_per = n > 0 ? n : 1;
+    G.ef.count = 1;
+    G.ef.super = 1;
+    G.sup.count = 1;
+    G.add(0, pa.tiles_x, pa.tiles_y);
+    // M-sized state and S-sized scratch
     Arena ia, ja;
-    uint32_t *tile_work;
-    auto carve_inst = [&](Arena &a, uint32_t *&tile, uint32_t *&gauss, uint2 *&ranges) {
-        tile = a.take<uint32_t>((size_t)(M > 0 ? M : 1));
-        gauss = a.take<uint32_t>((size_t)(M > 0 ? M : 1));
+    uint32_t *inst_gauss, *tile_work, *order;
+    uint2 *ranges;
+    BinScratch bs;
+    auto carve_state = [&](Arena &a) {
+        inst_gauss = a.take<uint32_t>((size_t)(M > 0 ? M : 1));
         ranges = a.take<uint2>(ntiles);
         tile_work = a.take<uint32_t>(ntiles);
     };
-    uint32_t *inst_tile, *inst_gauss, *tmp_tile, *tmp_gauss;
-    uint2 *ranges;
-    void *sort_tmp;
-    carve_inst(ia, inst_tile, inst_gauss, ranges);
-    const size_t inst_state_bytes = ia.off;
-    uint32_t *part, *order;
-    auto carve_tmp = [&](Arena &a) {
-        tmp_tile = a.take<uint32_t>((size_t)(M > 0 ? M : 1));
-        tmp_gauss = a.take<uint32_t>((size_t)(M > 0 ? M : 1));
-        sort_tmp = a.take_bytes(sort_scratch_bytes(M));
-        part = a.take<uint32_t>((size_t)emit_blocks((uint64_t)M) + 1);
+    auto carve_scratch = [&](Arena &a) {
+        bs.carve(a, (uint64_t)S, G.n_super);
         order = a.take<uint32_t>(ntiles);
     };
-    carve_tmp(ja);
-    const size_t inst_scratch_bytes = ja.off;
-    if ((rc = alloc_arena(alloc, inst_state_bytes, OMNIGS_MEM_STATE, ia, "instance lists")) != OMNIGS_OK) return rc;
-    carve_inst(ia, inst_tile, inst_gauss, ranges);
-    if ((rc = alloc_arena(alloc, inst_scratch_bytes, OMNIGS_MEM_SCRATCH, ja, "instance sort scratch")) != OMNIGS_OK)
-        return rc;
-    carve_tmp(ja);
+    carve_state(ia);
+    carve_scratch(ja);
+    if ((rc = alloc_arena(alloc, ia.off, OMNIGS_MEM_STATE, ia, "instance lists")) != OMNIGS_OK) return rc;
+    carve_state(ia);
+    if ((rc = alloc_arena(alloc, ja.off, OMNIGS_MEM_SCRATCH, ja, "binning scratch")) != OMNIGS_OK) return rc;
+    carve_scratch(ja);
 
-    {
-        StageTimer t(st, kStEmit);
-        // emit where the ping-pong of the tile sort starts, so that the
-        // last pass lands in the state buffers
-        uint32_t *et = (passes % 2) ? tmp_tile : inst_tile;
-        uint32_t *eg = (passes % 2) ? tmp_gauss : inst_gauss;
-        EmitFrames ef{};
-        ef.n_per = n > 0 ? n : 1;
-        ef.count = 1;
-        ef.tiles_x[0] = pa.tiles_x;
-        ef.tile_base[0] = 0u;
-        HIP_TRY(launch_emit(gst.order, gst.n_tiles, gst.rect, gs.offs, n, part, gs.offs + n, ef, (uint64_t)M, et, eg,
-                            nullptr, st));
-    }
-    {
-        StageTimer t(st, kStTileSort);
-        // odd pass counts start from the scratch pair, even ones from the
-        // state pair; the ping-pong never reads and writes one buffer
-        const bool odd = passes % 2;
-        HIP_TRY(radix_sort_pairs(odd ? tmp_tile : inst_tile, odd ? tmp_gauss : inst_gauss, tmp_tile, tmp_gauss,
-                                 inst_tile, inst_gauss, M, bits, sort_tmp, st));
-    }
-    {
-        StageTimer t(st, kStRanges);
-        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), 0u, 2 * (int64_t)ntiles, st));
-        HIP_TRY(launch_tile_ranges(inst_tile, gs.offs + n, (uint64_t)M, ranges, ntiles, st));
-    }
+    if ((rc = run_binning(n, gst, gs, G, (uint64_t)S, (uint64_t)M, false, bs, ranges, inst_gauss, nullptr, st)) !=
+        OMNIGS_OK)
+        return rc;
     {
         StageTimer t(st, kStTileOrder);
         HIP_TRY(launch_tile_order(ranges, nullptr, ntiles, order, st));
@@ -384,6 +428,7 @@ omnigs_status omnigs_forward(const omnigs_gaussians *g, const omnigs_camera *cam
     }
     state->n = n;
     state->n_instances = M;
+    state->n_entries = S;
     state->width = cam->width;
     state->height = cam->height;
     state->tiles_x = pa.tiles_x;
@@ -391,7 +436,6 @@ omnigs_status omnigs_forward(const omnigs_gaussians *g, const omnigs_camera *cam
     state->records = gst.rec;
     state->n_tiles = gst.n_tiles;
     state->depth_order = gst.order;
-    state->inst_tile = inst_tile;
     state->inst_gauss = inst_gauss;
     state->tile_range = reinterpret_cast<const uint32_t *>(ranges);
     state->tile_work = tile_work;
@@ -487,9 +531,11 @@ omnigs_status omnigs_forward_batch(const omnigs_gaussians *g, const omnigs_camer
     FrameGeom frames[kMaxBatch];
     CamTable ct{};
     ct.count = batch;
-    EmitFrames ef{};
-    ef.n_per = n > 0 ? n : 1;
-    ef.count = batch;
+    Grids G;
+    G.ef.n_per = n > 0 ? n : 1;
+    G.ef.count = batch;
+    G.ef.super = 1;
+    G.sup.count = batch;
     for (int b = 0; b < batch; ++b) {
         if ((rc = check_camera(&cams[b])) != OMNIGS_OK) return rc;
         if (!outs[b].image || !outs[b].final_T || !outs[b].n_contrib)
@@ -506,12 +552,10 @@ omnigs_status omnigs_forward_batch(const omnigs_gaussians *g, const omnigs_camer
         cg.tiles_x = pb.tiles_x;
         cg.tiles_y = pb.tiles_y;
         frames[b] = FrameGeom{pb.width, pb.height, pb.tiles_x, pb.tiles_y, (uint32_t)total_tiles};
-        ef.tiles_x[b] = pb.tiles_x;
-        ef.tile_base[b] = (uint32_t)total_tiles;
         total_tiles += (uint64_t)pb.tiles_x * pb.tiles_y;
+        if (total_tiles >= (uint64_t(1) << 31)) return fail(OMNIGS_ERR_INVALID, "too many tiles in the batch");
+        G.add(b, pb.tiles_x, pb.tiles_y);
     }
-    // the last id is kept free so that bits_for always has room
-    if (total_tiles >= (uint64_t(1) << 31)) return fail(OMNIGS_ERR_INVALID, "too many tiles in the batch");
     const ProjectArgs pa = make_project_args(g, &cams[0], s);
     hipStream_t st = static_cast<hipStream_t>(stream);
     const uint32_t ntiles = (uint32_t)total_tiles;
@@ -530,67 +574,42 @@ omnigs_status omnigs_forward_batch(const omnigs_gaussians *g, const omnigs_camer
     if (overflow) HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(overflow), 0u, 1, st));
     {
         StageTimer t(st, kStProject);
-        HIP_TRY(launch_project_batch(pa, ct, gst.rec, gs.depth_key, gst.n_tiles, gst.rect, st));
+        HIP_TRY(launch_project_batch(pa, ct, gst.rec, gs.depth_key, gst.n_tiles, gst.rect, gs.n_super, st));
     }
-    {
-        StageTimer t(st, kStDepthSort);
-        HIP_TRY(launch_iota(gs.iota, nrec, st));
-        HIP_TRY(radix_sort_pairs(gs.depth_key, gs.iota, gs.keys_tmp, gs.vals_tmp, gs.keys_sorted, gst.order, nrec,
-                                 32, gs.sort_tmp, st));
-    }
-    uint32_t *m_dev = gs.offs + nrec;
-    {
-        StageTimer t(st, kStEmitCount);
-        HIP_TRY(scan_exclusive(gst.n_tiles, gs.offs, nrec, m_dev, gs.scan_tmp, st, gst.order));
-    }
-    int64_t cap = instance_capacity;
-    if (cap == 0) {
-        uint32_t m32 = 0;
-        HIP_TRY(hipMemcpyAsync(&m32, m_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    if ((rc = sort_and_count(nrec, gst, gs, st)) != OMNIGS_OK) return rc;
+    // capacities: read back (exact), or the caller's instance capacity for
+    // both levels, counted on the device: every block entry holds at least
+    // one covered tile (a rectangle that wraps across the seam reaches the
+    // last tile column and misses fewer than 8 columns), so S <= M
+    uint64_t super_cap, inst_cap;
+    const bool counted = instance_capacity > 0;
+    if (!counted) {
+        uint32_t tot[2] = {0, 0};
+        HIP_TRY(hipMemcpyAsync(tot, gs.totals, sizeof(tot), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
-        cap = m32;
-        if (n_instances) *n_instances = m32;
+        super_cap = tot[0];
+        inst_cap = tot[1];
+        if (n_instances) *n_instances = tot[1];
+    } else {
+        inst_cap = (uint64_t)instance_capacity;
+        super_cap = inst_cap;
     }
-    const int bits = bits_for(total_tiles);
-    const int passes = (bits + 7) / 8;
-    const size_t mc = (size_t)(cap > 0 ? cap : 1);
     Arena ia;
-    uint32_t *inst_tile, *inst_gauss, *tmp_tile, *tmp_gauss, *part, *order;
+    uint32_t *inst_gauss, *order;
     uint2 *ranges;
-    void *sort_tmp;
+    BinScratch bs;
     auto carve_inst = [&](Arena &a) {
-        inst_tile = a.take<uint32_t>(mc);
-        inst_gauss = a.take<uint32_t>(mc);
-        tmp_tile = a.take<uint32_t>(mc);
-        tmp_gauss = a.take<uint32_t>(mc);
-        sort_tmp = a.take_bytes(sort_scratch_bytes((int64_t)mc));
-        part = a.take<uint32_t>((size_t)emit_blocks((uint64_t)cap) + 1);
+        inst_gauss = a.take<uint32_t>((size_t)(inst_cap > 0 ? inst_cap : 1));
         ranges = a.take<uint2>(ntiles);
         order = a.take<uint32_t>(ntiles);
+        bs.carve(a, super_cap, G.n_super);
     };
     carve_inst(ia);
     if ((rc = alloc_arena(alloc, ia.off, OMNIGS_MEM_SCRATCH, ia, "instance lists")) != OMNIGS_OK) return rc;
     carve_inst(ia);
-    // with a capacity, the counts the kernels use are min(M, capacity),
-    // read on the device
-    const uint32_t *count_dev = instance_capacity > 0 ? m_dev : nullptr;
-    {
-        StageTimer t(st, kStEmit);
-        const bool odd = passes % 2;
-        HIP_TRY(launch_emit(gst.order, gst.n_tiles, gst.rect, gs.offs, nrec, part, m_dev, ef, (uint64_t)cap,
-                            odd ? tmp_tile : inst_tile, odd ? tmp_gauss : inst_gauss, overflow, st));
-    }
-    {
-        StageTimer t(st, kStTileSort);
-        const bool odd = passes % 2;
-        HIP_TRY(radix_sort_pairs(odd ? tmp_tile : inst_tile, odd ? tmp_gauss : inst_gauss, tmp_tile, tmp_gauss,
-                                 inst_tile, inst_gauss, cap, bits, sort_tmp, st, count_dev));
-    }
-    {
-        StageTimer t(st, kStRanges);
-        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), 0u, 2 * (int64_t)ntiles, st));
-        HIP_TRY(launch_tile_ranges(inst_tile, m_dev, (uint64_t)cap, ranges, ntiles, st));
-    }
+    if ((rc = run_binning(nrec, gst, gs, G, super_cap, inst_cap, counted, bs, ranges, inst_gauss, overflow, st)) !=
+        OMNIGS_OK)
+        return rc;
     {
         StageTimer t(st, kStTileOrder);
         HIP_TRY(launch_tile_order(ranges, nullptr, ntiles, order, st));

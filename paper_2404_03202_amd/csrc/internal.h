@@ -59,22 +59,75 @@ struct CamTable {
     CamGeom c[kMaxBatch];
 };
 
-// Tile geometry of the cameras behind record index g = b * n_per + i.
+// Two-level binning: super-tiles of 8x8 tiles.  A record first gets one
+// entry per super-tile its tile rectangle touches; each super-tile's list is
+// then expanded into the lists of its 64 tiles.
+constexpr int kSuper = 8;
+
+// Super-tile rectangle (packed like the tile rectangle: x0 | n_x << 16,
+// y0 | n_y << 16; columns wrap modulo ceil(tiles_x / 8)) of the super-tiles
+// that the tile rectangle r touches.  When the two pieces of a rectangle
+// that wraps across the seam meet in one super-tile column, every column is
+// taken; each is still touched (such a rectangle misses fewer than 8 tile
+// columns, never the last one), so every super-tile of the rectangle holds
+// at least one covered tile.
+__host__ __device__ inline uint2 super_rect(uint2 r, int tiles_x) {
+    const uint32_t ntx = r.x >> 16, tx0 = r.x & 0xffffu, nty = r.y >> 16, ty0 = r.y & 0xffffu;
+    if (ntx == 0 || nty == 0) return make_uint2(0u, 0u);
+    const uint32_t tx = (uint32_t)tiles_x, sxn = (tx + kSuper - 1) / kSuper;
+    const uint32_t sy0 = ty0 / kSuper, sy1 = (ty0 + nty - 1) / kSuper;
+    uint32_t sx0, nsx;
+    if (ntx >= tx) {
+        sx0 = 0;
+        nsx = sxn;
+    } else if (tx0 + ntx <= tx) {
+        sx0 = tx0 / kSuper;
+        nsx = (tx0 + ntx - 1) / kSuper - sx0 + 1;
+    } else {
+        const uint32_t a0 = tx0 / kSuper, b1 = (tx0 + ntx - 1 - tx) / kSuper;
+        if (b1 >= a0) {
+            sx0 = 0;
+            nsx = sxn;
+        } else {
+            sx0 = a0;
+            nsx = (sxn - a0) + b1 + 1;
+        }
+    }
+    return make_uint2(sx0 | (nsx << 16), sy0 | ((sy1 - sy0 + 1) << 16));
+}
+
+// Grid geometry of the cameras behind record index g = b * n_per + i, for
+// emission into tiles (super == 0: cols = tiles_x, base = first tile id) or
+// super-tiles (super == 1: cols = ceil(tiles_x / 8), base = first super id).
 struct EmitFrames {
     int64_t n_per;  // records per camera
     int count;
+    int super;
     int tiles_x[kMaxBatch];
-    uint32_t tile_base[kMaxBatch];
+    int cols[kMaxBatch];
+    uint32_t base[kMaxBatch];
+};
+
+// Tile and super-tile grids of the images of a (possibly batched) launch.
+struct SuperFrame {
+    uint32_t super_base, tile_base;
+    int super_x, super_y, tiles_x, tiles_y;
+};
+struct SuperTable {
+    int count;
+    SuperFrame f[kMaxBatch];
 };
 
 // Host-side launchers (each .hip file owns its kernels).
+// Per record: blend record, depth key, tiles covered, tile rectangle and
+// super-tiles touched.
 hipError_t launch_project(const ProjectArgs &a, BlendRecord *rec, uint32_t *depth_key, uint32_t *n_tiles,
-                          uint2 *rect, hipStream_t st);
+                          uint2 *rect, uint32_t *n_super, hipStream_t st);
 // All cameras of `cams` in one launch: the outputs of camera b for Gaussian i
 // land at index b * a.n + i, bit-identical to launch_project of that camera
 // (a's camera fields are ignored).
 hipError_t launch_project_batch(const ProjectArgs &a, const CamTable &cams, BlendRecord *rec, uint32_t *depth_key,
-                                uint32_t *n_tiles, uint2 *rect, hipStream_t st);
+                                uint32_t *n_tiles, uint2 *rect, uint32_t *n_super, hipStream_t st);
 hipError_t launch_project_backward(const ProjectArgs &a, const uint32_t *n_tiles, const float *acc,
                                    const omnigs_grads &gr, hipStream_t st);
 
@@ -94,11 +147,12 @@ size_t scan_scratch_bytes(int64_t n);
 hipError_t scan_exclusive(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *total, void *scratch,
                           hipStream_t st, const uint32_t *gather);
 
-// Instance emission in depth order: offs[r] = exclusive scan of the tile
-// counts in depth order (offs[n] = M at *m_dev).  Writes min(M, capacity)
-// instances, with global tile ids (frames.tile_base of the record's camera
-// plus the tile inside its image); sets *overflow when M > capacity.  `part`
-// holds emit_blocks(capacity) entries of scratch.
+// Emission in depth order: offs[r] = exclusive scan of the per-record counts
+// (tiles or super-tiles, as frames.super says) in depth order (offs[n] = M at
+// *m_dev).  Writes min(M, capacity) (grid id, record) pairs, with global grid
+// ids (frames.base of the record's camera plus the id inside its grid); sets
+// *overflow when M > capacity.  `part` holds emit_blocks(capacity) entries of
+// scratch.
 uint64_t emit_blocks(uint64_t capacity);
 hipError_t launch_emit(const uint32_t *order, const uint32_t *n_tiles, const uint2 *rect, const uint32_t *offs,
                        int64_t n, uint32_t *part, const uint32_t *m_dev, const EmitFrames &frames,
@@ -108,6 +162,19 @@ hipError_t launch_tile_ranges(const uint32_t *inst_tile, const uint32_t *m_dev, 
                               uint2 *ranges, uint32_t n_tiles_total, hipStream_t st);
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);
+
+// Second level of the binning: expands the super-tile lists (sorted by
+// super-tile, each in depth order; sranges [start, end) per super-tile)
+// into per-tile lists of record ids in depth order, written once each to
+// inst_gauss, and fills the [start, end) range of every tile.  Tiles are laid
+// out super-tile by super-tile.  super_count (device) is the number of valid
+// super entries (at most super_cap).  Instances past inst_cap are dropped and
+// set *overflow (may be null); ranges are clamped to inst_cap.  Scratch from
+// binning_scratch_bytes.
+size_t binning_scratch_bytes(uint64_t super_cap, uint32_t n_super_total);
+hipError_t launch_binning(const SuperTable &T, uint32_t n_super_total, const uint2 *rect, const uint32_t *sinst_gauss,
+                          const uint2 *sranges, uint64_t super_cap, uint64_t inst_cap, void *scratch, uint2 *ranges,
+                          uint32_t *inst_gauss, int32_t *overflow, hipStream_t st);
 
 // Blend kernels.
 struct BlendSettings {

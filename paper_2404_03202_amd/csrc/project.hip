@@ -193,7 +193,7 @@ __device__ inline void load_sh(const ProjectArgs &A, int64_t i, double (*sh)[3])
 // `slot` of the output arrays.
 template <int D>
 __device__ inline void project_one(const ProjectArgs &A, int64_t i, int64_t slot, BlendRecord *rec,
-                                   uint32_t *depth_key, uint32_t *n_tiles, uint2 *rect) {
+                                   uint32_t *depth_key, uint32_t *n_tiles, uint2 *rect, uint32_t *n_super) {
     const double o = A.opacities[i];
     Proj P;
     bool vis = project_core(A, i, o, P);
@@ -232,6 +232,7 @@ __device__ inline void project_one(const ProjectArgs &A, int64_t i, int64_t slot
         depth_key[slot] = kCulledKey;
         n_tiles[slot] = 0;
         rect[slot] = make_uint2(0, 0);
+        n_super[slot] = 0;
         return;
     }
     constexpr int K = (D + 1) * (D + 1);
@@ -267,22 +268,26 @@ __device__ inline void project_one(const ProjectArgs &A, int64_t i, int64_t slot
     dst[2] = make_float4(r.r, r.g, r.b, r.reach);
     depth_key[slot] = __float_as_uint((float)P.tr);
     n_tiles[slot] = ntx * nty;
-    rect[slot] = make_uint2(tx0 | (ntx << 16), ty0 | (nty << 16));
+    const uint2 tr = make_uint2(tx0 | (ntx << 16), ty0 | (nty << 16));
+    rect[slot] = tr;
+    const uint2 sr = super_rect(tr, A.tiles_x);
+    n_super[slot] = (sr.x >> 16) * (sr.y >> 16);
 }
 
 template <int D>
 __global__ __launch_bounds__(256) void k_project(ProjectArgs A, BlendRecord *rec, uint32_t *depth_key,
-                                                 uint32_t *n_tiles, uint2 *rect) {
+                                                 uint32_t *n_tiles, uint2 *rect, uint32_t *n_super) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= A.n) return;
-    project_one<D>(A, i, i, rec, depth_key, n_tiles, rect);
+    project_one<D>(A, i, i, rec, depth_key, n_tiles, rect, n_super);
 }
 
 // Every camera of a batch for Gaussian i in turn: the Gaussian's parameters
 // are fetched from HBM once and re-read from cache for the later cameras.
 template <int D>
 __global__ __launch_bounds__(256) void k_project_batch(ProjectArgs A, CamTable T, BlendRecord *rec,
-                                                       uint32_t *depth_key, uint32_t *n_tiles, uint2 *rect) {
+                                                       uint32_t *depth_key, uint32_t *n_tiles, uint2 *rect,
+                                                       uint32_t *n_super) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= A.n) return;
     for (int b = 0; b < T.count; ++b) {
@@ -297,7 +302,7 @@ __global__ __launch_bounds__(256) void k_project_batch(ProjectArgs A, CamTable T
         C.height = g.height;
         C.tiles_x = g.tiles_x;
         C.tiles_y = g.tiles_y;
-        project_one<D>(C, i, (int64_t)b * A.n + i, rec, depth_key, n_tiles, rect);
+        project_one<D>(C, i, (int64_t)b * A.n + i, rec, depth_key, n_tiles, rect, n_super);
     }
 }
 
@@ -451,27 +456,27 @@ __global__ __launch_bounds__(256) void k_project_backward(ProjectArgs A, const u
 }  // namespace
 
 hipError_t launch_project(const ProjectArgs &a, BlendRecord *rec, uint32_t *depth_key, uint32_t *n_tiles,
-                          uint2 *rect, hipStream_t st) {
+                          uint2 *rect, uint32_t *n_super, hipStream_t st) {
     if (a.n == 0) return hipSuccess;
     const dim3 grid((unsigned)((a.n + 255) / 256));
     switch (a.sh_degree) {
-        case 0: hipLaunchKernelGGL(k_project<0>, grid, dim3(256), 0, st, a, rec, depth_key, n_tiles, rect); break;
-        case 1: hipLaunchKernelGGL(k_project<1>, grid, dim3(256), 0, st, a, rec, depth_key, n_tiles, rect); break;
-        case 2: hipLaunchKernelGGL(k_project<2>, grid, dim3(256), 0, st, a, rec, depth_key, n_tiles, rect); break;
-        default: hipLaunchKernelGGL(k_project<3>, grid, dim3(256), 0, st, a, rec, depth_key, n_tiles, rect); break;
+        case 0: hipLaunchKernelGGL(k_project<0>, grid, dim3(256), 0, st, a, rec, depth_key, n_tiles, rect, n_super); break;
+        case 1: hipLaunchKernelGGL(k_project<1>, grid, dim3(256), 0, st, a, rec, depth_key, n_tiles, rect, n_super); break;
+        case 2: hipLaunchKernelGGL(k_project<2>, grid, dim3(256), 0, st, a, rec, depth_key, n_tiles, rect, n_super); break;
+        default: hipLaunchKernelGGL(k_project<3>, grid, dim3(256), 0, st, a, rec, depth_key, n_tiles, rect, n_super); break;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_project_batch(const ProjectArgs &a, const CamTable &cams, BlendRecord *rec, uint32_t *depth_key,
-                                uint32_t *n_tiles, uint2 *rect, hipStream_t st) {
+                                uint32_t *n_tiles, uint2 *rect, uint32_t *n_super, hipStream_t st) {
     if (a.n == 0 || cams.count == 0) return hipSuccess;
     const dim3 grid((unsigned)((a.n + 255) / 256));
     switch (a.sh_degree) {
-        case 0: hipLaunchKernelGGL(k_project_batch<0>, grid, dim3(256), 0, st, a, cams, rec, depth_key, n_tiles, rect); break;
-        case 1: hipLaunchKernelGGL(k_project_batch<1>, grid, dim3(256), 0, st, a, cams, rec, depth_key, n_tiles, rect); break;
-        case 2: hipLaunchKernelGGL(k_project_batch<2>, grid, dim3(256), 0, st, a, cams, rec, depth_key, n_tiles, rect); break;
-        default: hipLaunchKernelGGL(k_project_batch<3>, grid, dim3(256), 0, st, a, cams, rec, depth_key, n_tiles, rect); break;
+        case 0: hipLaunchKernelGGL(k_project_batch<0>, grid, dim3(256), 0, st, a, cams, rec, depth_key, n_tiles, rect, n_super); break;
+        case 1: hipLaunchKernelGGL(k_project_batch<1>, grid, dim3(256), 0, st, a, cams, rec, depth_key, n_tiles, rect, n_super); break;
+        case 2: hipLaunchKernelGGL(k_project_batch<2>, grid, dim3(256), 0, st, a, cams, rec, depth_key, n_tiles, rect, n_super); break;
+        default: hipLaunchKernelGGL(k_project_batch<3>, grid, dim3(256), 0, st, a, cams, rec, depth_key, n_tiles, rect, n_super); break;
     }
     return hipGetLastError();
 }

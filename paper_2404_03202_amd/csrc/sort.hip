@@ -248,8 +248,9 @@ __global__ __launch_bounds__(kThreads) void k_scan_tile(const uint32_t *in, cons
 }
 
 // ---------------------------------------------------------------- emission
-// Instances are emitted in depth order: rank r of the depth order owns the
-// output range [offs[r], offs[r] + n_tiles(r)).  Every emit block writes a
+// Entries are emitted in depth order: rank r of the depth order owns the
+// output range [offs[r], offs[r] + count(r)), count = tiles or super-tiles of
+// its rectangle (the scan behind offs used the same count).  Every emit block writes a
 // fixed span of kEmitSpan consecutive outputs, whatever the tile counts of the
 // Gaussians behind them (the nearest Gaussians, which come first, cover up to
 // thousands of tiles each).  part[b] = the rank owning output b * kEmitSpan.
@@ -293,11 +294,14 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *order, const 
     for (int i = threadIdx.x; i < cnt; i += kThreads) {
         const uint32_t r = r0 + i;
         const uint32_t g = order[r];
+        // camera of record g = b * n_per + i
+        const int cam = F.count > 1 && g < (uint64_t)n ? (int)min((int64_t)g / F.n_per, (int64_t)F.count - 1) : 0;
+        uint2 rc = (g < (uint64_t)n && n_tiles[g]) ? rect[g] : make_uint2(0, 0);
+        if (F.super) rc = super_rect(rc, F.tiles_x[cam]);
         s_off[i] = offs[r];
         s_gid[i] = g;
-        s_rect[i] = (g < (uint64_t)n && n_tiles[g]) ? rect[g] : make_uint2(0, 0);
-        // camera of record g = b * n_per + i
-        s_cam[i] = (uint8_t)(F.count > 1 && g < (uint64_t)n ? min((int64_t)g / F.n_per, (int64_t)F.count - 1) : 0);
+        s_rect[i] = rc;
+        s_cam[i] = (uint8_t)cam;
     }
     __syncthreads();
     uint64_t jend = j0 + kEmitSpan;
@@ -315,11 +319,11 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *order, const 
         const uint32_t ntx = rc.x >> 16, tx0 = rc.x & 0xffffu, ty0 = rc.y & 0xffffu;
         if (ntx == 0) continue;
         const int cam = s_cam[lo];
-        const uint32_t tiles_x = (uint32_t)F.tiles_x[cam];
+        const uint32_t cols = (uint32_t)F.cols[cam];
         const uint32_t ty = ty0 + k / ntx;
         uint32_t tx = tx0 + k % ntx;
-        if (tx >= tiles_x) tx -= tiles_x;
-        inst_tile[j] = F.tile_base[cam] + ty * tiles_x + tx;
+        if (tx >= cols) tx -= cols;
+        inst_tile[j] = F.base[cam] + ty * cols + tx;
         inst_gauss[j] = s_gid[lo];
     }
 }

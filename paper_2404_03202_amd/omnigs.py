@@ -63,11 +63,11 @@ class c_image_out(ctypes.Structure):
 
 
 class c_state(ctypes.Structure):
-    _fields_ = [("n", ctypes.c_int64), ("n_instances", ctypes.c_int64), ("width", ctypes.c_int32),
+    _fields_ = [("n", ctypes.c_int64), ("n_instances", ctypes.c_int64), ("n_entries", ctypes.c_int64),
+                ("width", ctypes.c_int32),
                 ("height", ctypes.c_int32), ("tiles_x", ctypes.c_int32), ("tiles_y", ctypes.c_int32),
                 ("records", ctypes.c_void_p), ("n_tiles", ctypes.c_void_p), ("depth_order", ctypes.c_void_p),
-                ("inst_tile", ctypes.c_void_p), ("inst_gauss", ctypes.c_void_p), ("tile_range", ctypes.c_void_p),
-                ("tile_work", ctypes.c_void_p)]
+                ("inst_gauss", ctypes.c_void_p), ("tile_range", ctypes.c_void_p), ("tile_work", ctypes.c_void_p)]
 
 
 class c_grads(ctypes.Structure):
@@ -228,6 +228,10 @@ class ForwardResult:
     def n_instances(self):
         return int(self.state.n_instances)
 
+    @property
+    def n_entries(self):
+        return int(self.state.n_entries)
+
     def _view(self, ptr, count, dtype):
         """View a state buffer as a tensor (for tests / debugging)."""
         for t in self._keep:
@@ -239,11 +243,19 @@ class ForwardResult:
         raise KeyError("pointer not in state buffers")
 
     def instance_lists(self):
-        """(tile id [M] int32, Gaussian id [M] int32, tile ranges [tiles, 2] int32) as device tensors."""
+        """Per-tile lists concatenated in tile-id order: (tile id [M] int32,
+        Gaussian id [M] int32, ranges [tiles, 2] int32 of the library's own
+        layout), device tensors (the tile ids are re-derived from the ranges)."""
         M = self.n_instances
         tiles = self.state.tiles_x * self.state.tiles_y
-        return (self._view(self.state.inst_tile, M, torch.int32), self._view(self.state.inst_gauss, M, torch.int32),
-                self._view(self.state.tile_range, 2 * tiles, torch.int32).view(tiles, 2))
+        gauss = self._view(self.state.inst_gauss, M, torch.int32)
+        rng = self._view(self.state.tile_range, 2 * tiles, torch.int32).view(tiles, 2)
+        lens = (rng[:, 1] - rng[:, 0]).long()
+        tile = torch.repeat_interleave(torch.arange(tiles, device=gauss.device, dtype=torch.int32), lens)
+        starts = torch.repeat_interleave(rng[:, 0].long(), lens)
+        first = torch.repeat_interleave(torch.cumsum(lens, 0) - lens, lens)
+        idx = starts + torch.arange(int(lens.sum()), device=gauss.device) - first
+        return tile, gauss[idx], rng
 
     def depth_order(self):
         return self._view(self.state.depth_order, int(self.state.n), torch.int32)

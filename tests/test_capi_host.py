@@ -119,7 +119,7 @@ def test_l1_and_backward_argument_checks(lib):
 def test_profile_stage_names(lib):
     n = lib.omnigs_profile_num_stages()
     names = [lib.omnigs_profile_stage_name(k).decode() for k in range(n)]
-    assert names[:8] == ["project", "depth_sort", "emit_count", "emit", "tile_sort", "tile_ranges", "tile_order",
+    assert names[:8] == ["project", "depth_sort", "emit_count", "super_emit", "super_sort", "tile_bin", "tile_order",
                          "blend_fwd"]
     assert "blend_bwd" in names and "project_bwd" in names
     assert lib.omnigs_profile_stage_name(n).decode() == ""

@@ -114,11 +114,13 @@ def check_fullsize(g, cam, seed, n_random=32):
     sel = osub["n_flags"] == 0
     assert (sub(fwd.n_blended.cpu().numpy())[sel] == osub["n_blended"][sel]).all()
     ot, og, otr = O.tile_lists(sc, tile_mask=mask)
+    # it / ig hold the tile lists concatenated in tile-id order
+    cat = np.cumsum(lens.reshape(-1)) - lens.reshape(-1)
     gpu_t, gpu_g = [], []
     for t in np.nonzero(mask)[0]:
-        a, b = rng_t[t]
-        gpu_t.append(it[a:b])
-        gpu_g.append(ig[a:b])
+        a = cat[t]
+        gpu_t.append(it[a:a + lens.reshape(-1)[t]])
+        gpu_g.append(ig[a:a + lens.reshape(-1)[t]])
     rep.update(parity.check_tile_lists(np.concatenate(gpu_t), np.concatenate(gpu_g), ot, og, otr, flagged))
 
     # backward: seeded cotangent on the sampled tiles, zero elsewhere and at
