@@ -188,10 +188,10 @@ def stress_bench(steps, log):
     passes = -(-max(1, int(np.ceil(np.log2(supers)))) // 8)
     # algorithmic bytes per stage (u32 keys and values; each radix pass reads
     # the keys for its histogram, then reads and writes key + value):
-    # depth sort over N; scans of the block and tile counts; block entries
+    # depth sort over N; the scan of the block counts in depth order; block entries
     # (S) emitted, sorted by block and ranged; the expansion reads every entry
     # and its rectangle twice (count, write) and writes each instance once
-    algo = dict(depth_sort=4 * 20 * n + 4 * n, emit_count=20 * n, super_emit=8 * S + 20 * n,
+    algo = dict(depth_sort=4 * 20 * n + 4 * n, emit_count=12 * n, super_emit=8 * S + 20 * n,
                 super_sort=passes * 20 * S + 4 * S, tile_bin=24 * S + 4 * M)
     rates = {k: algo[k] / (ms[k] * 1e-3) / 1e9 for k in algo if k in ms}
     out = dict(workload="3M Gaussians, room layout, scales log-uniform [0.002, 0.5], SH degree 3, 3840x1920 ERP, "
@@ -205,6 +205,46 @@ def stress_bench(steps, log):
     return out
 
 
+def train_bench(g, poses, targets, steps, log):
+    """The full iteration of Alg. 1 on the benchmark workload: forward, L1,
+    backward, densification statistics and the Adam step (train.Trainer),
+    plus one densification event on the 1M-Gaussian set."""
+    import torch
+    from paper_2404_03202_amd import omnigs as B
+    from paper_2404_03202_amd.train import Trainer, TrainSettings
+
+    tr = Trainer(g, TrainSettings(extent=10.0, densify_from=10 ** 9))  # no densification inside the timing
+    for k in range(3):
+        tr.step(poses[k % len(poses)], targets[k % len(poses)])
+    torch.cuda.synchronize()
+    B.omnigs_profile_read()
+    B.omnigs_profile_enable(True)
+    t0 = time.perf_counter()
+    for k in range(steps):
+        tr.step(poses[k % len(poses)], targets[k % len(poses)])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    B.omnigs_profile_enable(False)
+    prof = B.omnigs_profile_read()
+    n0 = tr.n
+    torch.cuda.synchronize()
+    B.omnigs_profile_enable(True)
+    t1 = time.perf_counter()
+    tr.densify(screen=False)  # as before the first opacity reset
+    torch.cuda.synchronize()
+    dens = time.perf_counter() - t1
+    B.omnigs_profile_enable(False)
+    dprof = B.omnigs_profile_read()
+    out = dict(workload="forward + L1 + backward + densification statistics + Adam per pose, 1M Gaussians, "
+                        "2048x1024, the benchmark poses",
+               steps=steps, iters_per_s=steps / dt, ms_per_step=dt * 1e3 / steps,
+               stage_ms={k: v[0] / steps for k, v in prof.items() if v[1]},
+               densify=dict(gaussians_before=n0, gaussians_after=tr.n, ms=dens * 1e3,
+                            kernel_ms=dprof["densify"][0]))
+    log(f"train: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -214,6 +254,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--stress", action="store_true", help="also measure the 3M-Gaussian 3840x1920 workload")
+    ap.add_argument("--no-train", action="store_true", help="skip the full training-iteration measurement")
     ap.add_argument("--stress-steps", type=int, default=8)
     ap.add_argument("--serve-requests", type=int, default=800)
     ap.add_argument("--serve-slots", type=int, default=4)
@@ -297,6 +338,8 @@ def main():
                            gaussians=int(g["means"].shape[0]), width=2048, height=1024, poses=len(poses)),
                stage_ms={k: v[0] / args.steps for k, v in prof.items() if v[1]},
                roofline=roofline)
+    if not args.no_train:
+        out["train"] = train_bench(g, poses, targets, min(args.steps, 100), log)
     if args.stress:
         out["stress"] = stress_bench(args.stress_steps, log)
     if not args.no_serve:

@@ -119,6 +119,9 @@ typedef struct {
                                     in inst_gauss                                   */
     const uint32_t *tile_work;   /* [tiles] largest n_contrib of the tile (the
                                     backward's walk length)                        */
+    const float *radii;          /* [n] screen radius in pixels (the larger half
+                                    extent of the alpha = alpha_min box), 0 when
+                                    culled                                          */
 } omnigs_state;
 
 /* Parameter gradients (device, caller-allocated, overwritten). */
@@ -207,6 +210,98 @@ omnigs_status omnigs_l1_loss(const float *image, const float *target, int64_t co
 omnigs_status omnigs_forward_batch(const omnigs_gaussians *g, const omnigs_camera *cams, int32_t batch,
                                    const omnigs_settings *s, omnigs_allocator alloc, omnigs_image_out *outs,
                                    int64_t instance_capacity, int32_t *overflow, int64_t *n_instances,
+                                   void *stream);
+
+/* ------------------------------------------------------------------------
+ * Optimisation around the rasterizer (Sec. 4, Alg. 1).  The paper leaves
+ * the optimizer and the densification rules to 3DGS (and to its absent
+ * supplement), except that densification is driven by dL/ds, the gradient
+ * w.r.t. the uniform ERP screen coordinate s of Eq. 4.  This library takes
+ * 3DGS's published method: Adam on raw parameters, the mean of ||dL/ds||
+ * over the views where a Gaussian is visible, clone / split / prune, and a
+ * periodic opacity reset.
+ * ------------------------------------------------------------------------ */
+
+/* Raw (optimised) parameters, device float32, densely packed: the
+ * rasterizer sees S = exp(log_scales) and o = sigmoid(logits).  The same
+ * struct describes the two Adam moment sets (same shapes). */
+typedef struct {
+    float *means;      /* [n][3]                                     */
+    float *log_scales; /* [n][3]                                     */
+    float *quats;      /* [n][4]  raw, normalised by the rasterizer  */
+    float *logits;     /* [n]                                        */
+    float *sh;         /* [n][sh_coeffs][3]                          */
+    int64_t n;
+    int32_t sh_degree;
+    int32_t sh_coeffs;
+} omnigs_params;
+
+/* Adam settings (host).  Learning rates per group: means, SH degree 0, SH
+ * degrees >= 1, opacity logits, log-scales, quaternions.  step counts from
+ * 1 (bias correction 1 - beta^step). */
+typedef struct {
+    double lr_means, lr_sh_dc, lr_sh_rest, lr_logits, lr_log_scales, lr_quats;
+    double beta1, beta2, eps;
+    int32_t step;
+} omnigs_adam_settings;
+
+/* Densification statistics (device float32, [n] each). */
+typedef struct {
+    float *accum;      /* sum of ||dL/ds||_2 over the views where visible */
+    float *denom;      /* number of those views                           */
+    float *max_radius; /* largest screen radius in pixels seen            */
+} omnigs_densify_stats;
+
+/* Densification settings (host).  max_screen <= 0 disables pruning by
+ * screen radius and by world size. */
+typedef struct {
+    double grad_threshold; /* tau: densify where accum / denom >= tau                */
+    double percent_dense;  /* clone where max scale <= percent_dense * extent, else split */
+    double extent;         /* scene extent (world units)                              */
+    double min_opacity;    /* prune where o < min_opacity                             */
+    double max_screen;     /* prune where max_radius > max_screen (pixels)            */
+    double big_fraction;   /* prune where max scale > big_fraction * extent           */
+    double split_shrink;   /* children's scales are the parent's / split_shrink (1.6) */
+} omnigs_densify_settings;
+
+/* One Adam step over every parameter (elementwise, float32): the gradients
+ * `g` (w.r.t. the activated scales and opacities, as omnigs_backward writes
+ * them) are chained through exp and sigmoid; m <- b1 m + (1 - b1) g,
+ * v <- b2 v + (1 - b2) g^2, p <- p - lr / (1 - b1^t) m / (sqrt(v) /
+ * sqrt(1 - b2^t) + eps).  p, m1, m2 are updated in place.  act (may be NULL)
+ * receives the rasterizer's inputs for the new parameters: act->scales =
+ * exp(log_scales), act->opacities = sigmoid(logits) (its other pointers are
+ * not written).  Errors: OMNIGS_ERR_INVALID for null pointers or mismatched
+ * sizes. */
+omnigs_status omnigs_adam_step(omnigs_params *p, const omnigs_grads *g, omnigs_params *m1, omnigs_params *m2,
+                               const omnigs_adam_settings *s, omnigs_gaussians *act, void *stream);
+
+/* Densification statistics of one view: for every Gaussian the forward
+ * `state` saw covering a tile, accum += ||dscreen||_2, denom += 1 and
+ * max_radius = max(max_radius, its screen radius in pixels (the larger half
+ * extent of the alpha = alpha_min box)).  g->dscreen from omnigs_backward
+ * of that view. */
+omnigs_status omnigs_accumulate_stats(const omnigs_state *state, const omnigs_grads *g,
+                                      omnigs_densify_stats *stats, void *stream);
+
+/* Densify and prune (see the section comment; decisions in float32: the
+ * averaged gradient by float32 division, scales and opacities compared in
+ * log / logit space against thresholds rounded once to float32).  Output
+ * order: surviving originals, surviving clones, surviving first children,
+ * surviving second children, each in input order.  noise: device [n][2][3]
+ * standard normals (children at m + R(q) (S * z)).  The new arrays (p_out,
+ * m1_out, m2_out, stats_out; their pointer fields are set by the call) are
+ * OMNIGS_MEM_STATE allocations of the caller's allocator; new Gaussians get
+ * zero moments, and all statistics start at zero.  *n_out receives the new
+ * count (read back: one host synchronisation). */
+omnigs_status omnigs_densify(const omnigs_params *p, const omnigs_params *m1, const omnigs_params *m2,
+                             const omnigs_densify_stats *stats, const float *noise, const omnigs_densify_settings *s,
+                             omnigs_allocator alloc, omnigs_params *p_out, omnigs_params *m1_out,
+                             omnigs_params *m2_out, omnigs_densify_stats *stats_out, int64_t *n_out, void *stream);
+
+/* Opacity reset: logits <- min(logits, logit(value)); the logits' Adam
+ * moments are zeroed. */
+omnigs_status omnigs_reset_opacity(omnigs_params *p, omnigs_params *m1, omnigs_params *m2, double value,
                                    void *stream);
 
 /* Thread-local message describing the last non-OK status of this thread. */

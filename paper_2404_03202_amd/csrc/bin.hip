@@ -3,12 +3,14 @@
 //
 // The first level (sort.hip) leaves, for every super-tile of 8x8 tiles, the
 // list of records whose tile rectangle touches it, in depth order.  Here each
-// list is cut into chunks of kChunk entries.  For an entry, the 64 tiles of
-// its super-tile that the record covers form a 64-bit mask (its rectangle,
-// columns wrapping across the seam, clipped to the super-tile).  Per chunk,
-// 64 wave ballots (one per tile) give each tile's instance count and, in the
-// expansion, each entry's rank among the chunk's entries that cover the
-// tile, in list order.  Counts are laid out per super-tile as [tile][chunk],
+// list is cut into chunks of kChunk entries.  The tiles of its super-tile
+// that an entry's record covers are a product of covered rows and covered
+// columns (its rectangle, columns wrapping across the seam, clipped to the
+// super-tile), so per wave 8 row ballots and 8 column ballots give, for each
+// of the 64 tiles, the lanes that cover it (the AND of its row's and its
+// column's ballots): the tile's instance count and, in the expansion, each
+// entry's rank among the chunk's entries that cover the tile, in list
+// order.  Counts are laid out per super-tile as [tile][chunk],
 // super-tiles one after another, so that one exclusive scan yields at once
 // the start of every tile's list (tiles are stored super-tile by super-tile,
 // each tile's list contiguous) and the offset of every chunk inside it.
@@ -33,12 +35,16 @@ __device__ inline int find_super_frame(const SuperTable &T, uint32_t s) {
     return f;
 }
 
-// Tiles of super-tile (sx, sy) covered by the tile rectangle r: bit
-// 8 * (row in super-tile) + (column in super-tile).
-__device__ inline uint64_t cover_mask(uint2 r, int tiles_x, int sx, int sy) {
+// Rows and columns of super-tile (sx, sy) covered by the tile rectangle r
+// (columns wrapping across the seam): the covered tiles are their product,
+// tile (row k, column c) being tile 8k + c of the super-tile.
+struct Cover {
+    uint32_t rows, cols;
+};
+__device__ inline Cover cover_of(uint2 r, int tiles_x, int sx, int sy) {
     const int ntx = (int)(r.x >> 16), tx0 = (int)(r.x & 0xffffu), nty = (int)(r.y >> 16), ty0 = (int)(r.y & 0xffffu);
     const int y_lo = max(ty0, sy * kSuper) - sy * kSuper, y_hi = min(ty0 + nty, sy * kSuper + kSuper) - sy * kSuper;
-    if (ntx == 0 || y_hi <= y_lo) return 0ull;
+    if (ntx == 0 || y_hi <= y_lo) return Cover{0u, 0u};
     uint32_t cols = 0;
 #pragma unroll
     for (int c = 0; c < kSuper; ++c) {
@@ -47,11 +53,23 @@ __device__ inline uint64_t cover_mask(uint2 r, int tiles_x, int sx, int sy) {
         d += d < 0 ? tiles_x : 0;  // offset from the rectangle's first column, modulo tiles_x
         cols |= (tx < tiles_x && d < ntx) ? (1u << c) : 0u;
     }
-    uint64_t m = 0;
+    return Cover{((1u << y_hi) - 1u) & ~((1u << y_lo) - 1u), cols};
+}
+
+// The wave's ballots of covered rows and columns: lane q < 8 receives the
+// ballot of row q, lane 8 + q that of column q.  The lanes covering tile
+// (k, c) are then rowball(k) & colball(c): a product of rectangles is the
+// product of their row and column sets.
+__device__ inline uint64_t row_col_ballots(Cover cv, int lane) {
+    uint64_t mine = 0ull;
 #pragma unroll
-    for (int k = 0; k < kSuper; ++k)
-        if (k >= y_lo && k < y_hi) m |= (uint64_t)cols << (kSuper * k);
-    return m;
+    for (int q = 0; q < kSuper; ++q) {
+        const uint64_t br = __ballot((cv.rows >> q) & 1u);
+        const uint64_t bc = __ballot((cv.cols >> q) & 1u);
+        mine = lane == q ? br : mine;
+        mine = lane == kSuper + q ? bc : mine;
+    }
+    return mine;
 }
 
 // Position of (super-tile s, tile j, chunk c) in the count layout.
@@ -80,7 +98,7 @@ __global__ __launch_bounds__(kThreads) void k_bin_count(SuperTable T, const uint
                                                         const uint2 *sranges, const uint32_t *choff,
                                                         const uint32_t *nch, const uint32_t *desc, uint32_t n_super,
                                                         uint32_t *counts) {
-    __shared__ uint32_t wcnt[kWaves][kTilesPer];
+    __shared__ uint64_t rc[kWaves][2 * kSuper];
     const uint32_t k = blockIdx.x;
     const uint32_t K = choff[n_super];  // chunks in all (device)
     const int w = threadIdx.x / kWave, lane = __lane_id();
@@ -95,20 +113,17 @@ __global__ __launch_bounds__(kThreads) void k_bin_count(SuperTable T, const uint
     const uint32_t ls = s - F.super_base;
     const int sx = (int)(ls % (uint32_t)F.super_x), sy = (int)(ls / (uint32_t)F.super_x);
     const uint32_t e = sranges[s].x + c * kChunk + threadIdx.x;
-    uint64_t mask = 0ull;
-    if (e < sranges[s].y) mask = cover_mask(rect[sinst_gauss[e]], F.tiles_x, sx, sy);
-    uint32_t mine = 0;
-    for (int j = 0; j < kTilesPer; ++j) {
-        const uint32_t cnt = (uint32_t)__popcll(__ballot((mask >> j) & 1ull));
-        mine = (lane == j) ? cnt : mine;
-    }
-    wcnt[w][lane] = mine;
+    Cover cv{0u, 0u};
+    if (e < sranges[s].y) cv = cover_of(rect[sinst_gauss[e]], F.tiles_x, sx, sy);
+    const uint64_t b = row_col_ballots(cv, lane);
+    if (lane < 2 * kSuper) rc[w][lane] = b;
     __syncthreads();
     if (threadIdx.x < kTilesPer) {
+        const int j = threadIdx.x;
         uint32_t t = 0;
 #pragma unroll
-        for (int q = 0; q < kWaves; ++q) t += wcnt[q][threadIdx.x];
-        counts[layout(o, n, threadIdx.x, c)] = t;
+        for (int q = 0; q < kWaves; ++q) t += (uint32_t)__popcll(rc[q][j / kSuper] & rc[q][kSuper + j % kSuper]);
+        counts[layout(o, n, j, c)] = t;
     }
 }
 
@@ -138,7 +153,7 @@ __global__ __launch_bounds__(kThreads) void k_bin_expand(SuperTable T, const uin
                                                          const uint32_t *nch, const uint32_t *desc, uint32_t n_super,
                                                          const uint32_t *scanned, uint64_t inst_cap,
                                                          uint32_t *inst_gauss, int32_t *overflow) {
-    __shared__ uint64_t wball[kWaves][kTilesPer];
+    __shared__ uint64_t rc[kWaves][2 * kSuper];
     __shared__ uint32_t wpre[kWaves][kTilesPer];
     const uint32_t k = blockIdx.x;
     if (k >= choff[n_super]) return;
@@ -148,18 +163,14 @@ __global__ __launch_bounds__(kThreads) void k_bin_expand(SuperTable T, const uin
     const uint32_t ls = s - F.super_base;
     const int sx = (int)(ls % (uint32_t)F.super_x), sy = (int)(ls / (uint32_t)F.super_x);
     const uint32_t e = sranges[s].x + c * kChunk + threadIdx.x;
-    uint64_t mask = 0ull;
+    Cover cv{0u, 0u};
     uint32_t g = 0;
     if (e < sranges[s].y) {
         g = sinst_gauss[e];
-        mask = cover_mask(rect[g], F.tiles_x, sx, sy);
+        cv = cover_of(rect[g], F.tiles_x, sx, sy);
     }
-    uint64_t mine = 0;
-    for (int j = 0; j < kTilesPer; ++j) {
-        const uint64_t b = __ballot((mask >> j) & 1ull);
-        mine = (lane == j) ? b : mine;
-    }
-    wball[w][lane] = mine;
+    const uint64_t b = row_col_ballots(cv, lane);
+    if (lane < 2 * kSuper) rc[w][lane] = b;
     __syncthreads();
     if (threadIdx.x < kTilesPer) {
         // start of this chunk's instances in tile j, plus the entries of the
@@ -169,19 +180,25 @@ __global__ __launch_bounds__(kThreads) void k_bin_expand(SuperTable T, const uin
 #pragma unroll
         for (int q = 0; q < kWaves; ++q) {
             wpre[q][j] = run;
-            run += (uint32_t)__popcll(wball[q][j]);
+            run += (uint32_t)__popcll(rc[q][j / kSuper] & rc[q][kSuper + j % kSuper]);
         }
     }
     __syncthreads();
+    // tile by tile (uniform loops over the wave's covered rows and columns);
+    // the lanes of one tile write consecutive positions
     const uint64_t below = (1ull << lane) - 1ull;
     bool dropped = false;
-    for (int j = 0; j < kTilesPer; ++j) {
-        const uint64_t b = wball[w][j];
-        if (b == 0ull) continue;  // uniform
-        if ((mask >> j) & 1ull) {
-            const uint64_t pos = (uint64_t)wpre[w][j] + (uint64_t)__popcll(b & below);
-            if (pos < inst_cap) inst_gauss[pos] = g;
-            else dropped = true;
+    for (int r = 0; r < kSuper; ++r) {
+        const uint64_t br = rc[w][r];
+        if (br == 0ull) continue;  // uniform
+        for (int q = 0; q < kSuper; ++q) {
+            const uint64_t bt = br & rc[w][kSuper + q];
+            if (bt == 0ull) continue;  // uniform
+            if ((bt >> lane) & 1ull) {
+                const uint64_t pos = (uint64_t)wpre[w][r * kSuper + q] + (uint64_t)__popcll(bt & below);
+                if (pos < inst_cap) inst_gauss[pos] = g;
+                else dropped = true;
+            }
         }
     }
     if (dropped && overflow) *overflow = 1;

@@ -50,11 +50,14 @@ enum Stage {
     kStBwdClear,
     kStBlendBwd,
     kStProjectBwd,
+    kStStats,
+    kStAdam,
+    kStDensify,
     kStCount
 };
 const char *kStageNames[kStCount] = {"project",    "depth_sort", "emit_count", "super_emit", "super_sort",
                                      "tile_bin",   "tile_order", "blend_fwd",  "l1_loss",    "bwd_clear",
-                                     "blend_bwd",  "project_bwd"};
+                                     "blend_bwd",  "project_bwd", "stats",      "adam",       "densify"};
 
 struct Profiler {
     std::mutex mu;
@@ -215,12 +218,14 @@ struct GeomState {
     BlendRecord *rec;
     uint32_t *n_tiles, *order;
     uint2 *rect;
+    float *radii;
     void carve(Arena &a, int64_t n) {
         const size_t m = (size_t)(n > 0 ? n : 1);
         rec = a.take<BlendRecord>(m);
         n_tiles = a.take<uint32_t>(m);
         order = a.take<uint32_t>(m);
         rect = a.take<uint2>(m);
+        radii = a.take<float>(m);
     }
 };
 struct GeomScratch {
@@ -243,8 +248,8 @@ struct GeomScratch {
 };
 
 // Depth sort and per-rank super-entry offsets of n records (projected
-// already): gs.offs, S at gs.totals[0], M = total tile instances at
-// gs.totals[1].
+// already, which left M = total tile instances at gs.totals[1]): gs.offs
+// and S at gs.totals[0].
 omnigs_status sort_and_count(int64_t n, GeomState &gst, GeomScratch &gs, hipStream_t st) {
     {
         StageTimer t(st, kStDepthSort);
@@ -255,9 +260,6 @@ omnigs_status sort_and_count(int64_t n, GeomState &gst, GeomScratch &gs, hipStre
     {
         StageTimer t(st, kStEmitCount);
         HIP_TRY(scan_exclusive(gs.n_super, gs.offs, n, gs.totals, gs.scan_tmp, st, gst.order));
-        // the sort's key scratch is free again: it takes the (unused) scan of
-        // the tile counts whose total is M
-        HIP_TRY(scan_exclusive(gst.n_tiles, gs.keys_tmp, n, gs.totals + 1, gs.scan_tmp, st, nullptr));
     }
     return OMNIGS_OK;
 }
@@ -376,7 +378,8 @@ omnigs_status omnigs_forward(const omnigs_gaussians *g, const omnigs_camera *cam
 
     {
         StageTimer t(st, kStProject);
-        HIP_TRY(launch_project(pa, gst.rec, gs.depth_key, gst.n_tiles, gst.rect, gs.n_super, st));
+        HIP_TRY(launch_project(pa, gst.rec, gs.depth_key, gst.n_tiles, gst.rect, gs.n_super, gst.radii, gs.totals + 1,
+                               st));
     }
     if ((rc = sort_and_count(n, gst, gs, st)) != OMNIGS_OK) return rc;
 
@@ -439,6 +442,7 @@ omnigs_status omnigs_forward(const omnigs_gaussians *g, const omnigs_camera *cam
     state->inst_gauss = inst_gauss;
     state->tile_range = reinterpret_cast<const uint32_t *>(ranges);
     state->tile_work = tile_work;
+    state->radii = gst.radii;
     return OMNIGS_OK;
 }
 
@@ -574,7 +578,8 @@ omnigs_status omnigs_forward_batch(const omnigs_gaussians *g, const omnigs_camer
     if (overflow) HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(overflow), 0u, 1, st));
     {
         StageTimer t(st, kStProject);
-        HIP_TRY(launch_project_batch(pa, ct, gst.rec, gs.depth_key, gst.n_tiles, gst.rect, gs.n_super, st));
+        HIP_TRY(launch_project_batch(pa, ct, gst.rec, gs.depth_key, gst.n_tiles, gst.rect, gs.n_super, gs.totals + 1,
+                                     st));
     }
     if ((rc = sort_and_count(nrec, gst, gs, st)) != OMNIGS_OK) return rc;
     // capacities: read back (exact), or the caller's instance capacity for
@@ -619,6 +624,179 @@ omnigs_status omnigs_forward_batch(const omnigs_gaussians *g, const omnigs_camer
         HIP_TRY(launch_blend_forward_frames(frames, outs, batch, gst.rec, inst_gauss, ranges, make_blend_settings(s),
                                             order, ntiles, st));
     }
+    return OMNIGS_OK;
+}
+
+// ---------------------------------------------------------- optimisation
+}  // extern "C"
+
+namespace {
+
+omnigs_status check_params(const omnigs_params *p, const char *what) {
+    if (!p) return fail(OMNIGS_ERR_INVALID, "%s is NULL", what);
+    if (p->n < 0 || p->n >= (int64_t(1) << 31)) return fail(OMNIGS_ERR_INVALID, "%s: n out of range", what);
+    if (p->sh_coeffs < 1 || p->sh_coeffs > 16) return fail(OMNIGS_ERR_INVALID, "%s: sh_coeffs out of range", what);
+    if (p->n > 0 && (!p->means || !p->log_scales || !p->quats || !p->logits || !p->sh))
+        return fail(OMNIGS_ERR_INVALID, "%s: a parameter pointer is NULL", what);
+    return OMNIGS_OK;
+}
+
+OptimArrays arrays_of(const omnigs_params *p) {
+    return OptimArrays{{p->means, p->log_scales, p->quats, p->logits, p->sh}};
+}
+
+omnigs_status same_shape(const omnigs_params *a, const omnigs_params *b, const char *what) {
+    if (a->n != b->n || a->sh_coeffs != b->sh_coeffs) return fail(OMNIGS_ERR_INVALID, "%s: shape mismatch", what);
+    return OMNIGS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+omnigs_status omnigs_adam_step(omnigs_params *p, const omnigs_grads *g, omnigs_params *m1, omnigs_params *m2,
+                               const omnigs_adam_settings *s, omnigs_gaussians *act, void *stream) {
+    omnigs_status rc;
+    if ((rc = check_params(p, "params")) != OMNIGS_OK || (rc = check_params(m1, "m1")) != OMNIGS_OK ||
+        (rc = check_params(m2, "m2")) != OMNIGS_OK)
+        return rc;
+    if ((rc = same_shape(p, m1, "m1")) != OMNIGS_OK || (rc = same_shape(p, m2, "m2")) != OMNIGS_OK) return rc;
+    if (!g || !s) return fail(OMNIGS_ERR_INVALID, "gradients or settings is NULL");
+    if (p->n > 0 && (!g->dmeans || !g->dscales || !g->dquats || !g->dopacities || !g->dsh))
+        return fail(OMNIGS_ERR_INVALID, "a gradient pointer is NULL");
+    if (s->step < 1) return fail(OMNIGS_ERR_INVALID, "step must be >= 1");
+    if (!(s->beta1 >= 0.0 && s->beta1 < 1.0 && s->beta2 >= 0.0 && s->beta2 < 1.0 && s->eps >= 0.0))
+        return fail(OMNIGS_ERR_INVALID, "bad Adam coefficients");
+    const int64_t n = p->n;
+    const int64_t shf = (int64_t)p->sh_coeffs * 3;
+    AdamArgs a{};
+    const int64_t len[kSegments] = {3 * n, 3 * n, 4 * n, n, shf * n};
+    int64_t off = 0;
+    for (int k = 0; k < kSegments; ++k) {
+        a.begin[k] = off;
+        off += len[k];
+    }
+    a.total = off;
+    a.lr[kSegMeans] = (float)s->lr_means;
+    a.lr[kSegLogScales] = (float)s->lr_log_scales;
+    a.lr[kSegQuats] = (float)s->lr_quats;
+    a.lr[kSegLogits] = (float)s->lr_logits;
+    a.lr[kSegSh] = (float)s->lr_sh_dc;
+    a.lr_sh_rest = (float)s->lr_sh_rest;
+    a.sh_stride = shf;
+    a.beta1 = (float)s->beta1;
+    a.beta2 = (float)s->beta2;
+    a.eps = (float)s->eps;
+    a.inv_bc1 = (float)(1.0 / (1.0 - std::pow(s->beta1, s->step)));
+    a.inv_sqrt_bc2 = (float)(1.0 / std::sqrt(1.0 - std::pow(s->beta2, s->step)));
+    const OptimArrays G{{g->dmeans, g->dscales, g->dquats, g->dopacities, g->dsh}};
+    StageTimer t(static_cast<hipStream_t>(stream), kStAdam);
+    HIP_TRY(launch_adam(arrays_of(p), G, arrays_of(m1), arrays_of(m2), a,
+                        act ? const_cast<float *>(act->scales) : nullptr,
+                        act ? const_cast<float *>(act->opacities) : nullptr, static_cast<hipStream_t>(stream)));
+    return OMNIGS_OK;
+}
+
+omnigs_status omnigs_accumulate_stats(const omnigs_state *state, const omnigs_grads *g,
+                                      omnigs_densify_stats *stats, void *stream) {
+    if (!state || !g || !stats) return fail(OMNIGS_ERR_INVALID, "state, gradients or statistics is NULL");
+    if (state->n > 0 && (!state->n_tiles || !state->radii || !g->dscreen || !stats->accum || !stats->denom ||
+                         !stats->max_radius))
+        return fail(OMNIGS_ERR_INVALID, "a state, gradient or statistics pointer is NULL");
+    StageTimer t(static_cast<hipStream_t>(stream), kStStats);
+    HIP_TRY(launch_stats(state->n_tiles, state->radii, g->dscreen, state->n, stats->accum, stats->denom,
+                         stats->max_radius, static_cast<hipStream_t>(stream)));
+    return OMNIGS_OK;
+}
+
+omnigs_status omnigs_densify(const omnigs_params *p, const omnigs_params *m1, const omnigs_params *m2,
+                             const omnigs_densify_stats *stats, const float *noise, const omnigs_densify_settings *s,
+                             omnigs_allocator alloc, omnigs_params *p_out, omnigs_params *m1_out,
+                             omnigs_params *m2_out, omnigs_densify_stats *stats_out, int64_t *n_out, void *stream) {
+    omnigs_status rc;
+    if ((rc = check_params(p, "params")) != OMNIGS_OK || (rc = check_params(m1, "m1")) != OMNIGS_OK ||
+        (rc = check_params(m2, "m2")) != OMNIGS_OK)
+        return rc;
+    if ((rc = same_shape(p, m1, "m1")) != OMNIGS_OK || (rc = same_shape(p, m2, "m2")) != OMNIGS_OK) return rc;
+    if (!stats || !s || !p_out || !m1_out || !m2_out || !stats_out || !n_out || !alloc.alloc)
+        return fail(OMNIGS_ERR_INVALID, "a statistics, settings, output or allocator argument is NULL");
+    const int64_t n = p->n;
+    if (n > 0 && (!noise || !stats->accum || !stats->denom || !stats->max_radius))
+        return fail(OMNIGS_ERR_INVALID, "noise or a statistics array is NULL");
+    if (!(s->grad_threshold >= 0.0 && s->percent_dense > 0.0 && s->extent > 0.0 && s->min_opacity > 0.0 &&
+          s->min_opacity < 1.0 && s->big_fraction > 0.0 && s->split_shrink > 0.0))
+        return fail(OMNIGS_ERR_INVALID, "bad densification settings");
+    if ((int64_t)4 * n >= (int64_t(1) << 32)) return fail(OMNIGS_ERR_INVALID, "too many Gaussians");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    StageTimer timer(st, kStDensify);
+    const int shf = p->sh_coeffs * 3;
+    // thresholds rounded once to float32: the decisions compare float32
+    // values (log-scales, logits, radii, the averaged gradient)
+    DensifyArgs d{};
+    d.tau = (float)s->grad_threshold;
+    d.log_clone = (float)std::log(s->percent_dense * s->extent);
+    d.logit_min = (float)std::log(s->min_opacity / (1.0 - s->min_opacity));
+    d.screen_on = s->max_screen > 0.0;
+    d.max_screen = (float)s->max_screen;
+    d.log_big = (float)std::log(s->big_fraction * s->extent);
+    d.log_shrink = (float)std::log(s->split_shrink);
+    Arena a;
+    a.take<uint32_t>((size_t)(4 * n + 1));
+    a.take<uint32_t>((size_t)(4 * n + 1));
+    a.take_bytes(scan_scratch_bytes(4 * n + 1));
+    if ((rc = alloc_arena(alloc, a.off, OMNIGS_MEM_SCRATCH, a, "densification scratch")) != OMNIGS_OK) return rc;
+    uint32_t *flags = a.take<uint32_t>((size_t)(4 * n + 1));
+    uint32_t *pos = a.take<uint32_t>((size_t)(4 * n + 1));
+    void *scan_tmp = a.take_bytes(scan_scratch_bytes(4 * n + 1));
+    const OptimArrays P = arrays_of(p);
+    HIP_TRY(launch_dens_flags(P, stats->accum, stats->denom, stats->max_radius, n, d, flags, st));
+    HIP_TRY(scan_exclusive(flags, pos, 4 * n, pos + 4 * n, scan_tmp, st, nullptr));
+    uint32_t total = 0;
+    HIP_TRY(hipMemcpyAsync(&total, pos + 4 * n, sizeof(total), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const int64_t no = total;
+    // outputs: parameters, two moment sets, statistics
+    Arena o;
+    auto carve = [&](Arena &ar, omnigs_params *q) {
+        q->means = ar.take<float>((size_t)(3 * (no > 0 ? no : 1)));
+        q->log_scales = ar.take<float>((size_t)(3 * (no > 0 ? no : 1)));
+        q->quats = ar.take<float>((size_t)(4 * (no > 0 ? no : 1)));
+        q->logits = ar.take<float>((size_t)(no > 0 ? no : 1));
+        q->sh = ar.take<float>((size_t)shf * (no > 0 ? no : 1));
+        q->n = no;
+        q->sh_degree = p->sh_degree;
+        q->sh_coeffs = p->sh_coeffs;
+    };
+    auto carve_all = [&](Arena &ar) {
+        carve(ar, p_out);
+        carve(ar, m1_out);
+        carve(ar, m2_out);
+        stats_out->accum = ar.take<float>((size_t)(no > 0 ? no : 1));
+        stats_out->denom = ar.take<float>((size_t)(no > 0 ? no : 1));
+        stats_out->max_radius = ar.take<float>((size_t)(no > 0 ? no : 1));
+    };
+    carve_all(o);
+    if ((rc = alloc_arena(alloc, o.off, OMNIGS_MEM_STATE, o, "densified parameters")) != OMNIGS_OK) return rc;
+    carve_all(o);
+    HIP_TRY(launch_dens_scatter(P, arrays_of(m1), arrays_of(m2), flags, pos, noise, n, shf, d.log_shrink,
+                                arrays_of(p_out), arrays_of(m1_out), arrays_of(m2_out), st));
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(stats_out->accum), 0u, no, st));
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(stats_out->denom), 0u, no, st));
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(stats_out->max_radius), 0u, no, st));
+    *n_out = no;
+    return OMNIGS_OK;
+}
+
+omnigs_status omnigs_reset_opacity(omnigs_params *p, omnigs_params *m1, omnigs_params *m2, double value,
+                                   void *stream) {
+    omnigs_status rc;
+    if ((rc = check_params(p, "params")) != OMNIGS_OK || (rc = check_params(m1, "m1")) != OMNIGS_OK ||
+        (rc = check_params(m2, "m2")) != OMNIGS_OK)
+        return rc;
+    if ((rc = same_shape(p, m1, "m1")) != OMNIGS_OK || (rc = same_shape(p, m2, "m2")) != OMNIGS_OK) return rc;
+    if (!(value > 0.0 && value < 1.0)) return fail(OMNIGS_ERR_INVALID, "reset value must be in (0, 1)");
+    HIP_TRY(launch_reset_opacity(p->logits, m1->logits, m2->logits, p->n, (float)std::log(value / (1.0 - value)),
+                                 static_cast<hipStream_t>(stream)));
     return OMNIGS_OK;
 }
 

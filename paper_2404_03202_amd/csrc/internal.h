@@ -119,15 +119,17 @@ struct SuperTable {
 };
 
 // Host-side launchers (each .hip file owns its kernels).
-// Per record: blend record, depth key, tiles covered, tile rectangle and
-// super-tiles touched.
+// Per record: blend record, depth key, tiles covered, tile rectangle,
+// super-tiles touched and screen radius (radii may be null); *tiles_total
+// (device) receives the sum of the tiles covered (M).
 hipError_t launch_project(const ProjectArgs &a, BlendRecord *rec, uint32_t *depth_key, uint32_t *n_tiles,
-                          uint2 *rect, uint32_t *n_super, hipStream_t st);
+                          uint2 *rect, uint32_t *n_super, float *radii, uint32_t *tiles_total, hipStream_t st);
 // All cameras of `cams` in one launch: the outputs of camera b for Gaussian i
 // land at index b * a.n + i, bit-identical to launch_project of that camera
 // (a's camera fields are ignored).
 hipError_t launch_project_batch(const ProjectArgs &a, const CamTable &cams, BlendRecord *rec, uint32_t *depth_key,
-                                uint32_t *n_tiles, uint2 *rect, uint32_t *n_super, hipStream_t st);
+                                uint32_t *n_tiles, uint2 *rect, uint32_t *n_super, uint32_t *tiles_total,
+                                hipStream_t st);
 hipError_t launch_project_backward(const ProjectArgs &a, const uint32_t *n_tiles, const float *acc,
                                    const omnigs_grads &gr, hipStream_t st);
 
@@ -202,6 +204,36 @@ hipError_t launch_blend_backward(const FrameGeom &f, const BlendRecord *rec, con
 // per-tile work array.  One workgroup; ntiles unbounded.
 hipError_t launch_tile_order(const uint2 *ranges, const uint32_t *work, uint32_t ntiles, uint32_t *order,
                              hipStream_t st);
+
+// Optimisation (optim.hip).  Parameter arrays as five segments.
+constexpr int kSegments = 5;
+enum { kSegMeans = 0, kSegLogScales = 1, kSegQuats = 2, kSegLogits = 3, kSegSh = 4 };
+struct OptimArrays {
+    float *ptr[kSegments];
+};
+struct AdamArgs {
+    int64_t total;               // elements in all segments
+    int64_t begin[kSegments];    // first element of each segment
+    float lr[kSegments];         // per segment (the SH segment's: degree 0)
+    float lr_sh_rest;            // SH degrees >= 1
+    int64_t sh_stride;           // floats of SH per Gaussian
+    float beta1, beta2, eps, inv_bc1, inv_sqrt_bc2;
+};
+struct DensifyArgs {
+    float tau, log_clone, logit_min, max_screen, log_big, log_shrink;
+    int screen_on;
+};
+hipError_t launch_adam(const OptimArrays &P, const OptimArrays &G, const OptimArrays &M1, const OptimArrays &M2,
+                       const AdamArgs &a, float *act_scales, float *act_opacities, hipStream_t st);
+hipError_t launch_stats(const uint32_t *n_tiles, const float *radii, const float *dscreen, int64_t n, float *accum,
+                        float *denom, float *max_radius, hipStream_t st);
+hipError_t launch_dens_flags(const OptimArrays &P, const float *accum, const float *denom, const float *max_radius,
+                             int64_t n, const DensifyArgs &d, uint32_t *flags, hipStream_t st);
+hipError_t launch_dens_scatter(const OptimArrays &P, const OptimArrays &M1, const OptimArrays &M2,
+                               const uint32_t *flags, const uint32_t *pos, const float *noise, int64_t n,
+                               int sh_floats, float log_shrink, const OptimArrays &PO, const OptimArrays &M1O,
+                               const OptimArrays &M2O, hipStream_t st);
+hipError_t launch_reset_opacity(float *logits, float *m1, float *m2, int64_t n, float lo, hipStream_t st);
 
 // L1 loss.
 size_t l1_scratch_bytes();

@@ -192,15 +192,18 @@ __device__ inline void load_sh(const ProjectArgs &A, int64_t i, double (*sh)[3])
 // Projection of Gaussian i for the camera of A; the outputs go to index
 // `slot` of the output arrays.
 template <int D>
-__device__ inline void project_one(const ProjectArgs &A, int64_t i, int64_t slot, BlendRecord *rec,
-                                   uint32_t *depth_key, uint32_t *n_tiles, uint2 *rect, uint32_t *n_super) {
+__device__ inline uint32_t project_one(const ProjectArgs &A, int64_t i, int64_t slot, BlendRecord *rec,
+                                       uint32_t *depth_key, uint32_t *n_tiles, uint2 *rect, uint32_t *n_super,
+                                       float *radii) {
     const double o = A.opacities[i];
     Proj P;
     bool vis = project_core(A, i, o, P);
     uint32_t ntx = 0, nty = 0, tx0 = 0, ty0 = 0;
+    double radius = 0.0;
     if (vis) {
         const double kcut = 2.0 * log(o / A.alpha_min);
         const double ex = sqrt(kcut * P.a), ey = sqrt(kcut * P.c);
+        radius = fmax(ex, ey);
         const double xs = ceil(P.px - ex - 0.5), xe = floor(P.px + ex - 0.5);
         double ys = ceil(P.py - ey - 0.5), ye = floor(P.py + ey - 0.5);
         ys = fmax(ys, 0.0);
@@ -233,7 +236,8 @@ __device__ inline void project_one(const ProjectArgs &A, int64_t i, int64_t slot
         n_tiles[slot] = 0;
         rect[slot] = make_uint2(0, 0);
         n_super[slot] = 0;
-        return;
+        if (radii) radii[slot] = 0.0f;
+        return 0u;
     }
     constexpr int K = (D + 1) * (D + 1);
     double Y[16];
@@ -272,14 +276,29 @@ __device__ inline void project_one(const ProjectArgs &A, int64_t i, int64_t slot
     rect[slot] = tr;
     const uint2 sr = super_rect(tr, A.tiles_x);
     n_super[slot] = (sr.x >> 16) * (sr.y >> 16);
+    if (radii) radii[slot] = (float)radius;
+    return ntx * nty;
+}
+
+// Adds the sum of v over the 256-thread block to *total (one atomic per
+// block; integer, so the result does not depend on the order).
+__device__ inline void add_block_total(uint32_t v, uint32_t *total) {
+    __shared__ uint32_t part[4];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    if (__lane_id() == 0) part[threadIdx.x / kWave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(total, part[0] + part[1] + part[2] + part[3]);
 }
 
 template <int D>
 __global__ __launch_bounds__(256) void k_project(ProjectArgs A, BlendRecord *rec, uint32_t *depth_key,
-                                                 uint32_t *n_tiles, uint2 *rect, uint32_t *n_super) {
+                                                 uint32_t *n_tiles, uint2 *rect, uint32_t *n_super, float *radii,
+                                                 uint32_t *tiles_total) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= A.n) return;
-    project_one<D>(A, i, i, rec, depth_key, n_tiles, rect, n_super);
+    uint32_t covered = 0;
+    if (i < A.n) covered = project_one<D>(A, i, i, rec, depth_key, n_tiles, rect, n_super, radii);
+    add_block_total(covered, tiles_total);
 }
 
 // Every camera of a batch for Gaussian i in turn: the Gaussian's parameters
@@ -287,10 +306,10 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs A, BlendRecord *rec
 template <int D>
 __global__ __launch_bounds__(256) void k_project_batch(ProjectArgs A, CamTable T, BlendRecord *rec,
                                                        uint32_t *depth_key, uint32_t *n_tiles, uint2 *rect,
-                                                       uint32_t *n_super) {
+                                                       uint32_t *n_super, uint32_t *tiles_total) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= A.n) return;
-    for (int b = 0; b < T.count; ++b) {
+    uint32_t covered = 0;
+    for (int b = 0; b < T.count && i < A.n; ++b) {
         ProjectArgs C = A;
         const CamGeom &g = T.c[b];
         for (int k = 0; k < 9; ++k) C.R[k] = g.R[k];
@@ -302,8 +321,9 @@ __global__ __launch_bounds__(256) void k_project_batch(ProjectArgs A, CamTable T
         C.height = g.height;
         C.tiles_x = g.tiles_x;
         C.tiles_y = g.tiles_y;
-        project_one<D>(C, i, (int64_t)b * A.n + i, rec, depth_key, n_tiles, rect, n_super);
+        covered += project_one<D>(C, i, (int64_t)b * A.n + i, rec, depth_key, n_tiles, rect, n_super, nullptr);
     }
+    add_block_total(covered, tiles_total);
 }
 
 // dJ/dt for the spherical Jacobian: dJ[e][n] = d J_e / d t_n, e = 3a + j.
@@ -456,27 +476,30 @@ __global__ __launch_bounds__(256) void k_project_backward(ProjectArgs A, const u
 }  // namespace
 
 hipError_t launch_project(const ProjectArgs &a, BlendRecord *rec, uint32_t *depth_key, uint32_t *n_tiles,
-                          uint2 *rect, uint32_t *n_super, hipStream_t st) {
-    if (a.n == 0) return hipSuccess;
+                          uint2 *rect, uint32_t *n_super, float *radii, uint32_t *tiles_total, hipStream_t st) {
+    hipError_t e = launch_fill_u32(tiles_total, 0u, 1, st);
+    if (e != hipSuccess || a.n == 0) return e;
     const dim3 grid((unsigned)((a.n + 255) / 256));
     switch (a.sh_degree) {
-        case 0: hipLaunchKernelGGL(k_project<0>, grid, dim3(256), 0, st, a, rec, depth_key, n_tiles, rect, n_super); break;
-        case 1: hipLaunchKernelGGL(k_project<1>, grid, dim3(256), 0, st, a, rec, depth_key, n_tiles, rect, n_super); break;
-        case 2: hipLaunchKernelGGL(k_project<2>, grid, dim3(256), 0, st, a, rec, depth_key, n_tiles, rect, n_super); break;
-        default: hipLaunchKernelGGL(k_project<3>, grid, dim3(256), 0, st, a, rec, depth_key, n_tiles, rect, n_super); break;
+        case 0: hipLaunchKernelGGL(k_project<0>, grid, dim3(256), 0, st, a, rec, depth_key, n_tiles, rect, n_super, radii, tiles_total); break;
+        case 1: hipLaunchKernelGGL(k_project<1>, grid, dim3(256), 0, st, a, rec, depth_key, n_tiles, rect, n_super, radii, tiles_total); break;
+        case 2: hipLaunchKernelGGL(k_project<2>, grid, dim3(256), 0, st, a, rec, depth_key, n_tiles, rect, n_super, radii, tiles_total); break;
+        default: hipLaunchKernelGGL(k_project<3>, grid, dim3(256), 0, st, a, rec, depth_key, n_tiles, rect, n_super, radii, tiles_total); break;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_project_batch(const ProjectArgs &a, const CamTable &cams, BlendRecord *rec, uint32_t *depth_key,
-                                uint32_t *n_tiles, uint2 *rect, uint32_t *n_super, hipStream_t st) {
-    if (a.n == 0 || cams.count == 0) return hipSuccess;
+                                uint32_t *n_tiles, uint2 *rect, uint32_t *n_super, uint32_t *tiles_total,
+                                hipStream_t st) {
+    hipError_t e = launch_fill_u32(tiles_total, 0u, 1, st);
+    if (e != hipSuccess || a.n == 0 || cams.count == 0) return e;
     const dim3 grid((unsigned)((a.n + 255) / 256));
     switch (a.sh_degree) {
-        case 0: hipLaunchKernelGGL(k_project_batch<0>, grid, dim3(256), 0, st, a, cams, rec, depth_key, n_tiles, rect, n_super); break;
-        case 1: hipLaunchKernelGGL(k_project_batch<1>, grid, dim3(256), 0, st, a, cams, rec, depth_key, n_tiles, rect, n_super); break;
-        case 2: hipLaunchKernelGGL(k_project_batch<2>, grid, dim3(256), 0, st, a, cams, rec, depth_key, n_tiles, rect, n_super); break;
-        default: hipLaunchKernelGGL(k_project_batch<3>, grid, dim3(256), 0, st, a, cams, rec, depth_key, n_tiles, rect, n_super); break;
+        case 0: hipLaunchKernelGGL(k_project_batch<0>, grid, dim3(256), 0, st, a, cams, rec, depth_key, n_tiles, rect, n_super, tiles_total); break;
+        case 1: hipLaunchKernelGGL(k_project_batch<1>, grid, dim3(256), 0, st, a, cams, rec, depth_key, n_tiles, rect, n_super, tiles_total); break;
+        case 2: hipLaunchKernelGGL(k_project_batch<2>, grid, dim3(256), 0, st, a, cams, rec, depth_key, n_tiles, rect, n_super, tiles_total); break;
+        default: hipLaunchKernelGGL(k_project_batch<3>, grid, dim3(256), 0, st, a, cams, rec, depth_key, n_tiles, rect, n_super, tiles_total); break;
     }
     return hipGetLastError();
 }

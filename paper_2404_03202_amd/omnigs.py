@@ -67,7 +67,8 @@ class c_state(ctypes.Structure):
                 ("width", ctypes.c_int32),
                 ("height", ctypes.c_int32), ("tiles_x", ctypes.c_int32), ("tiles_y", ctypes.c_int32),
                 ("records", ctypes.c_void_p), ("n_tiles", ctypes.c_void_p), ("depth_order", ctypes.c_void_p),
-                ("inst_gauss", ctypes.c_void_p), ("tile_range", ctypes.c_void_p), ("tile_work", ctypes.c_void_p)]
+                ("inst_gauss", ctypes.c_void_p), ("tile_range", ctypes.c_void_p), ("tile_work", ctypes.c_void_p),
+                ("radii", ctypes.c_void_p)]
 
 
 class c_grads(ctypes.Structure):
@@ -75,7 +76,28 @@ class c_grads(ctypes.Structure):
                 ("dopacities", ctypes.c_void_p), ("dsh", ctypes.c_void_p), ("dscreen", ctypes.c_void_p)]
 
 
+class c_params(ctypes.Structure):
+    _fields_ = [("means", ctypes.c_void_p), ("log_scales", ctypes.c_void_p), ("quats", ctypes.c_void_p),
+                ("logits", ctypes.c_void_p), ("sh", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("sh_degree", ctypes.c_int32), ("sh_coeffs", ctypes.c_int32)]
+
+
+class c_adam_settings(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in ("lr_means", "lr_sh_dc", "lr_sh_rest", "lr_logits", "lr_log_scales",
+                                                 "lr_quats", "beta1", "beta2", "eps")] + [("step", ctypes.c_int32)]
+
+
+class c_dens_stats(ctypes.Structure):
+    _fields_ = [("accum", ctypes.c_void_p), ("denom", ctypes.c_void_p), ("max_radius", ctypes.c_void_p)]
+
+
+class c_dens_settings(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in ("grad_threshold", "percent_dense", "extent", "min_opacity",
+                                                 "max_screen", "big_fraction", "split_shrink")]
+
+
 EXPORTS = ("omnigs_default_settings", "omnigs_forward", "omnigs_backward", "omnigs_l1_loss", "omnigs_forward_batch",
+           "omnigs_adam_step", "omnigs_accumulate_stats", "omnigs_densify", "omnigs_reset_opacity",
            "omnigs_last_error", "omnigs_profile_enable", "omnigs_profile_num_stages", "omnigs_profile_stage_name",
            "omnigs_profile_read")
 
@@ -108,6 +130,17 @@ def load_library(path: str = LIB_PATH):
         lib.omnigs_forward_batch.argtypes = [P(c_gaussians), P(c_camera), ctypes.c_int32, P(c_settings), c_allocator,
                                              P(c_image_out), ctypes.c_int64, vp, P(ctypes.c_int64), vp]
         lib.omnigs_forward_batch.restype = ctypes.c_int
+        lib.omnigs_adam_step.argtypes = [P(c_params), P(c_grads), P(c_params), P(c_params), P(c_adam_settings),
+                                         P(c_gaussians), vp]
+        lib.omnigs_adam_step.restype = ctypes.c_int
+        lib.omnigs_accumulate_stats.argtypes = [P(c_state), P(c_grads), P(c_dens_stats), vp]
+        lib.omnigs_accumulate_stats.restype = ctypes.c_int
+        lib.omnigs_densify.argtypes = [P(c_params), P(c_params), P(c_params), P(c_dens_stats), vp, P(c_dens_settings),
+                                       c_allocator, P(c_params), P(c_params), P(c_params), P(c_dens_stats),
+                                       P(ctypes.c_int64), vp]
+        lib.omnigs_densify.restype = ctypes.c_int
+        lib.omnigs_reset_opacity.argtypes = [P(c_params), P(c_params), P(c_params), ctypes.c_double, vp]
+        lib.omnigs_reset_opacity.restype = ctypes.c_int
         lib.omnigs_last_error.argtypes = []
         lib.omnigs_last_error.restype = ctypes.c_char_p
         lib.omnigs_profile_enable.argtypes = [ctypes.c_int32]
@@ -380,6 +413,97 @@ def omnigs_forward_batch(g: dict, cameras: list, settings: dict | None = None, i
     # ordered after the enqueued kernels on this stream
     del keep
     return BatchResult(outs, overflow, int(m.value), [])
+
+
+# ------------------------------------------------------------- optimisation
+PARAM_KEYS = ("means", "log_scales", "quats", "logits", "sh")
+
+
+def make_params(p: dict) -> c_params:
+    """p: means [N,3], log_scales [N,3], quats [N,4], logits [N], sh [N,K,3]
+    (contiguous float32 CUDA tensors), sh_degree."""
+    for k in PARAM_KEYS:
+        t = p[k]
+        if t.dtype != torch.float32 or not t.is_contiguous() or t.device.type != "cuda":
+            raise ValueError(f"{k} must be a contiguous float32 CUDA tensor")
+    n = int(p["means"].shape[0])
+    return c_params(_ptr(p["means"]), _ptr(p["log_scales"]), _ptr(p["quats"]), _ptr(p["logits"]), _ptr(p["sh"]), n,
+                    int(p["sh_degree"]), int(p["sh"].shape[1]))
+
+
+def _grads(grads: dict) -> c_grads:
+    return c_grads(_ptr(grads["means"]), _ptr(grads["scales"]), _ptr(grads["quats"]), _ptr(grads["opacities"]),
+                   _ptr(grads["sh"]), _ptr(grads.get("screen")))
+
+
+def omnigs_adam_step(p: dict, grads: dict, m1: dict, m2: dict, lrs: dict, step: int, act: dict | None = None,
+                     beta1=0.9, beta2=0.999, eps=1e-15):
+    """In-place Adam step of p, m1, m2 (dicts of raw parameters); act (may be
+    None): a Gaussian dict whose scales / opacities receive exp / sigmoid of
+    the new log-scales / logits."""
+    lib = load_library()
+    s = c_adam_settings(lrs["means"], lrs["sh_dc"], lrs["sh_rest"], lrs["logits"], lrs["log_scales"], lrs["quats"],
+                        beta1, beta2, eps, int(step))
+    cp, c1, c2 = make_params(p), make_params(m1), make_params(m2)
+    ca = None
+    if act is not None:
+        ca = c_gaussians()
+        ca.scales, ca.opacities = _ptr(act["scales"]), _ptr(act["opacities"])
+    _check(lib.omnigs_adam_step(ctypes.byref(cp), ctypes.byref(_grads(grads)), ctypes.byref(c1), ctypes.byref(c2),
+                                ctypes.byref(s), ctypes.byref(ca) if ca is not None else None,
+                                ctypes.c_void_p(_stream_ptr(p["means"].device))))
+
+
+def omnigs_accumulate_stats(fwd: "ForwardResult", grads: dict, stats: dict):
+    """stats: accum, denom, max_radius ([N] float32 tensors), updated in place."""
+    lib = load_library()
+    cs = c_dens_stats(_ptr(stats["accum"]), _ptr(stats["denom"]), _ptr(stats["max_radius"]))
+    _check(lib.omnigs_accumulate_stats(ctypes.byref(fwd.state), ctypes.byref(_grads(grads)), ctypes.byref(cs),
+                                       ctypes.c_void_p(_stream_ptr(stats["accum"].device))))
+
+
+def omnigs_densify(p: dict, m1: dict, m2: dict, stats: dict, noise: torch.Tensor, settings: dict,
+                   allocator: Allocator | None = None):
+    """Densify and prune.  Returns (p, m1, m2, stats) as new tensor dicts."""
+    lib = load_library()
+    dev = p["means"].device
+    cs = c_dens_settings(*(float(settings[k]) for k in ("grad_threshold", "percent_dense", "extent", "min_opacity",
+                                                        "max_screen", "big_fraction", "split_shrink")))
+    st_in = c_dens_stats(_ptr(stats["accum"]), _ptr(stats["denom"]), _ptr(stats["max_radius"]))
+    outs = [c_params() for _ in range(3)]
+    st_out = c_dens_stats()
+    n_out = ctypes.c_int64(0)
+    al = allocator or Allocator(dev)
+    _check(lib.omnigs_densify(ctypes.byref(make_params(p)), ctypes.byref(make_params(m1)), ctypes.byref(make_params(m2)),
+                              ctypes.byref(st_in), ctypes.c_void_p(_ptr(noise)), ctypes.byref(cs), al.c,
+                              *[ctypes.byref(o) for o in outs], ctypes.byref(st_out), ctypes.byref(n_out),
+                              ctypes.c_void_p(_stream_ptr(dev))))
+    buf = al.state[-1] if al.state else None
+    al.scratch.clear()
+    al.state.clear()
+    n = int(n_out.value)
+    K = int(p["sh"].shape[1])
+
+    def view(ptr, shape):
+        if buf is None or n == 0:
+            return torch.zeros(shape, dtype=torch.float32, device=dev)
+        off = ptr - buf.data_ptr()
+        cnt = int(np.prod(shape))
+        return buf[off:off + 4 * cnt].view(torch.float32).view(shape)
+
+    def as_dict(o):
+        return dict(means=view(o.means, (n, 3)), log_scales=view(o.log_scales, (n, 3)), quats=view(o.quats, (n, 4)),
+                    logits=view(o.logits, (n,)), sh=view(o.sh, (n, K, 3)), sh_degree=p["sh_degree"])
+    stats_out = dict(accum=view(st_out.accum, (n,)), denom=view(st_out.denom, (n,)),
+                     max_radius=view(st_out.max_radius, (n,)))
+    return as_dict(outs[0]), as_dict(outs[1]), as_dict(outs[2]), stats_out
+
+
+def omnigs_reset_opacity(p: dict, m1: dict, m2: dict, value: float = 0.01):
+    lib = load_library()
+    _check(lib.omnigs_reset_opacity(ctypes.byref(make_params(p)), ctypes.byref(make_params(m1)),
+                                    ctypes.byref(make_params(m2)), float(value),
+                                    ctypes.c_void_p(_stream_ptr(p["means"].device))))
 
 
 # ---------------------------------------------------------------- profiling
