@@ -235,8 +235,8 @@ def train_bench(g, poses, targets, steps, log):
     dens = time.perf_counter() - t1
     B.omnigs_profile_enable(False)
     dprof = B.omnigs_profile_read()
-    out = dict(workload="forward + L1 + backward + densification statistics + Adam per pose, 1M Gaussians, "
-                        "2048x1024, the benchmark poses",
+    out = dict(workload="forward + photometric loss (L1 + 0.2 SSIM term) + backward + densification statistics + "
+                        "Adam per pose, 1M Gaussians, 2048x1024, the benchmark poses",
                steps=steps, iters_per_s=steps / dt, ms_per_step=dt * 1e3 / steps,
                stage_ms={k: v[0] / steps for k, v in prof.items() if v[1]},
                densify=dict(gaussians_before=n0, gaussians_after=tr.n, ms=dens * 1e3,

@@ -185,6 +185,18 @@ omnigs_status omnigs_backward(const omnigs_gaussians *g, const omnigs_camera *ca
 omnigs_status omnigs_l1_loss(const float *image, const float *target, int64_t count, float *dL_dimage, float *loss,
                              omnigs_allocator alloc, void *stream);
 
+/* Photometric loss of Eq. 17, L = (1 - lambda) L1 + lambda (1 - SSIM), for
+ * [channels][height][width] float32 images (device): L1 is the mean |image -
+ * target|; SSIM is the mean over channels and pixels of the structural
+ * similarity on 11x11 Gaussian windows (sigma 1.5; C1 = 0.01^2, C2 = 0.03^2)
+ * over zero-padded images (the paper gives the weight lambda in its absent
+ * supplement: a parameter here).  *loss (device) receives L and dL_dimage
+ * (device, may be NULL) its gradient.  Scratch comes from `alloc`.
+ * OMNIGS_ERR_INVALID for null pointers, sizes < 1 or lambda outside [0, 1]. */
+omnigs_status omnigs_photometric_loss(const float *image, const float *target, int32_t channels, int32_t height,
+                                      int32_t width, double lambda, float *dL_dimage, float *loss,
+                                      omnigs_allocator alloc, void *stream);
+
 /* Batched forward render of `batch` cameras (1 <= batch <= OMNIGS_MAX_BATCH,
  * mixed resolutions) over one resident Gaussian set: the path of
  * omnigs_forward (Sec. 3.2-3.3) run once for all of them.  One projection

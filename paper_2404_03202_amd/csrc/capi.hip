@@ -515,6 +515,25 @@ omnigs_status omnigs_l1_loss(const float *image, const float *target, int64_t co
     return OMNIGS_OK;
 }
 
+omnigs_status omnigs_photometric_loss(const float *image, const float *target, int32_t channels, int32_t height,
+                                      int32_t width, double lambda, float *dL_dimage, float *loss,
+                                      omnigs_allocator alloc, void *stream) {
+    if (!image || !target || !loss) return fail(OMNIGS_ERR_INVALID, "image, target or loss is NULL");
+    if (channels < 1 || height < 1 || width < 1 || channels > 64 || height > 65520 || width > 65520)
+        return fail(OMNIGS_ERR_INVALID, "image size out of range");
+    if (!(lambda >= 0.0 && lambda <= 1.0)) return fail(OMNIGS_ERR_INVALID, "lambda must be in [0, 1]");
+    if (!alloc.alloc) return fail(OMNIGS_ERR_INVALID, "allocator callback is NULL");
+    Arena a;
+    omnigs_status rc;
+    if ((rc = alloc_arena(alloc, ssim_scratch_bytes(channels, height, width), OMNIGS_MEM_SCRATCH, a,
+                          "loss partial sums")) != OMNIGS_OK)
+        return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    StageTimer t(st, kStL1);
+    HIP_TRY(launch_photometric(image, target, channels, height, width, (float)lambda, dL_dimage, loss, a.base, st));
+    return OMNIGS_OK;
+}
+
 omnigs_status omnigs_forward_batch(const omnigs_gaussians *g, const omnigs_camera *cams, int32_t batch,
                                    const omnigs_settings *s, omnigs_allocator alloc, omnigs_image_out *outs,
                                    int64_t instance_capacity, int32_t *overflow, int64_t *n_instances,

@@ -235,6 +235,13 @@ hipError_t launch_dens_scatter(const OptimArrays &P, const OptimArrays &M1, cons
                                const OptimArrays &M2O, hipStream_t st);
 hipError_t launch_reset_opacity(float *logits, float *m1, float *m2, int64_t n, float lo, hipStream_t st);
 
+// Photometric loss (1 - lambda) L1 + lambda (1 - SSIM) of [channels][H][W]
+// images and its gradient (grad may be null); scratch from
+// ssim_scratch_bytes.
+size_t ssim_scratch_bytes(int channels, int height, int width);
+hipError_t launch_photometric(const float *image, const float *target, int channels, int height, int width,
+                              float lambda, float *grad, float *loss, void *scratch, hipStream_t st);
+
 // L1 loss.
 size_t l1_scratch_bytes();
 hipError_t launch_l1(const float *image, const float *target, int64_t count, float *grad, float *loss,

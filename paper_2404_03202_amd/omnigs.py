@@ -96,7 +96,8 @@ class c_dens_settings(ctypes.Structure):
                                                  "max_screen", "big_fraction", "split_shrink")]
 
 
-EXPORTS = ("omnigs_default_settings", "omnigs_forward", "omnigs_backward", "omnigs_l1_loss", "omnigs_forward_batch",
+EXPORTS = ("omnigs_default_settings", "omnigs_forward", "omnigs_backward", "omnigs_l1_loss", "omnigs_photometric_loss",
+           "omnigs_forward_batch",
            "omnigs_adam_step", "omnigs_accumulate_stats", "omnigs_densify", "omnigs_reset_opacity",
            "omnigs_last_error", "omnigs_profile_enable", "omnigs_profile_num_stages", "omnigs_profile_stage_name",
            "omnigs_profile_read")
@@ -127,6 +128,9 @@ def load_library(path: str = LIB_PATH):
         lib.omnigs_backward.restype = ctypes.c_int
         lib.omnigs_l1_loss.argtypes = [vp, vp, ctypes.c_int64, vp, vp, c_allocator, vp]
         lib.omnigs_l1_loss.restype = ctypes.c_int
+        lib.omnigs_photometric_loss.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                                vp, vp, c_allocator, vp]
+        lib.omnigs_photometric_loss.restype = ctypes.c_int
         lib.omnigs_forward_batch.argtypes = [P(c_gaussians), P(c_camera), ctypes.c_int32, P(c_settings), c_allocator,
                                              P(c_image_out), ctypes.c_int64, vp, P(ctypes.c_int64), vp]
         lib.omnigs_forward_batch.restype = ctypes.c_int
@@ -373,6 +377,27 @@ class BatchResult:
         self.overflow = overflow
         self.n_instances = n_instances
         self._keep = keepalive
+
+
+def omnigs_photometric_loss(image: torch.Tensor, target: torch.Tensor, lam: float, grad: bool = True,
+                            allocator: Allocator | None = None):
+    """(loss [1] float32, dL/dimage or None) of (1 - lam) L1 + lam (1 - SSIM)
+    for [C, H, W] float32 images."""
+    lib = load_library()
+    if image.shape != target.shape or image.dim() != 3 or image.dtype != torch.float32 or \
+            target.dtype != torch.float32:
+        raise ValueError("image and target must be [C, H, W] float32 tensors of one shape")
+    image, target = image.contiguous(), target.contiguous()
+    C, H, W = image.shape
+    dev = image.device
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    g = torch.empty_like(image) if grad else None
+    al = allocator or Allocator(dev)
+    _check(lib.omnigs_photometric_loss(ctypes.c_void_p(image.data_ptr()), ctypes.c_void_p(target.data_ptr()), C, H, W,
+                                       float(lam), ctypes.c_void_p(_ptr(g)), ctypes.c_void_p(loss.data_ptr()), al.c,
+                                       ctypes.c_void_p(_stream_ptr(dev))))
+    al.scratch.clear()
+    return loss, g
 
 
 def omnigs_forward_batch(g: dict, cameras: list, settings: dict | None = None, instance_capacity: int = 0,

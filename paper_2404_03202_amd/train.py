@@ -1,4 +1,5 @@
-"""Training loop of Alg. 1 on the C ABI: render, L1 loss, backward,
+"""Training loop of Alg. 1 on the C ABI: render, photometric loss (Eq. 17:
+L1 and, with lambda_dssim > 0, the SSIM term), backward,
 densification statistics and the Adam step every iteration; densify and
 prune every `densify_interval` iterations up to `densify_until`, opacity
 reset every `reset_interval`.  Every step runs in the library's kernels;
@@ -40,6 +41,7 @@ class TrainSettings:
     big_fraction: float = 0.1
     split_shrink: float = 1.6
     reset_value: float = 0.01
+    lambda_dssim: float = 0.2  # weight of the SSIM term of Eq. 17 (0: L1 only)
 
 
 def logit(p):
@@ -92,7 +94,10 @@ class Trainer:
         """One iteration; returns the loss tensor (device)."""
         self.step_count += 1
         fwd = B.omnigs_forward(self.act, camera, self.render_settings)
-        loss, dl = B.omnigs_l1_loss(fwd.image, target)
+        if self.s.lambda_dssim > 0.0:
+            loss, dl = B.omnigs_photometric_loss(fwd.image, target, self.s.lambda_dssim)
+        else:
+            loss, dl = B.omnigs_l1_loss(fwd.image, target)
         grads = B.omnigs_backward(self.act, camera, self.render_settings, fwd, dl)
         B.omnigs_accumulate_stats(fwd, grads, self.stats)
         # the activated copies are rewritten in place by the Adam kernel
