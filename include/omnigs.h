@@ -191,7 +191,9 @@ omnigs_status omnigs_l1_loss(const float *image, const float *target, int64_t co
  * similarity on 11x11 Gaussian windows (sigma 1.5; C1 = 0.01^2, C2 = 0.03^2)
  * over zero-padded images (the paper gives the weight lambda in its absent
  * supplement: a parameter here).  *loss (device) receives L and dL_dimage
- * (device, may be NULL) its gradient.  Scratch comes from `alloc`.
+ * (device, may be NULL) its gradient.  Scratch comes from `alloc`: per-tile
+ * partial sums, plus with a gradient 12 bytes per image element (three
+ * window-filtered planes).
  * OMNIGS_ERR_INVALID for null pointers, sizes < 1 or lambda outside [0, 1]. */
 omnigs_status omnigs_photometric_loss(const float *image, const float *target, int32_t channels, int32_t height,
                                       int32_t width, double lambda, float *dL_dimage, float *loss,

@@ -525,8 +525,8 @@ omnigs_status omnigs_photometric_loss(const float *image, const float *target, i
     if (!alloc.alloc) return fail(OMNIGS_ERR_INVALID, "allocator callback is NULL");
     Arena a;
     omnigs_status rc;
-    if ((rc = alloc_arena(alloc, ssim_scratch_bytes(channels, height, width), OMNIGS_MEM_SCRATCH, a,
-                          "loss partial sums")) != OMNIGS_OK)
+    if ((rc = alloc_arena(alloc, ssim_scratch_bytes(channels, height, width, dL_dimage != nullptr), OMNIGS_MEM_SCRATCH,
+                          a, "loss planes and partial sums")) != OMNIGS_OK)
         return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
     StageTimer t(st, kStL1);

@@ -237,8 +237,8 @@ hipError_t launch_reset_opacity(float *logits, float *m1, float *m2, int64_t n, 
 
 // Photometric loss (1 - lambda) L1 + lambda (1 - SSIM) of [channels][H][W]
 // images and its gradient (grad may be null); scratch from
-// ssim_scratch_bytes.
-size_t ssim_scratch_bytes(int channels, int height, int width);
+// ssim_scratch_bytes (with_grad: room for the three filtered planes).
+size_t ssim_scratch_bytes(int channels, int height, int width, bool with_grad);
 hipError_t launch_photometric(const float *image, const float *target, int channels, int height, int width,
                               float lambda, float *grad, float *loss, void *scratch, hipStream_t st);
 

@@ -47,153 +47,266 @@ __global__ __launch_bounds__(kL1Threads) void k_l1_final(const double *partial, 
 }
 
 // ------------------------------------------------------------------ SSIM
-// One workgroup per 16x16 tile and channel, fused forward and backward.  The
-// gradient at pixel p gathers the windows centred at q with |q - p| <= 5
-// (the window is symmetric), so the workgroup needs the SSIM partials on the
-// 26x26 centres around its tile, hence the window statistics there, hence x
-// and y on a 36x36 halo: every step is a separable 11-tap pass in LDS.  Only
-// x, y are read and dL/dx written; per-tile partial sums of S and |x - y|
-// go to a partials array reduced in a fixed order.
-constexpr int kSsimT = 16;              // output tile edge
-constexpr int kSsimR = 5;               // window radius (11 taps)
-constexpr int kSsimC = kSsimT + 2 * kSsimR;  // 26: centres whose window reaches the tile
-constexpr int kSsimH = kSsimC + 2 * kSsimR;  // 36: pixels those windows read
+// Photometric loss with the SSIM term, two kernels over 116 x 16 tiles.  The
+// gradient at pixel p gathers the windows centred at q with |q - p| <= 5 (the
+// window is symmetric); with S's partials A = dS/dmu_x, B = dS/ds_xx and
+// C = dS/ds_xy at q it is
+//   sum_q w(p - q) [A + 2 B (x_p - mu_x) + C (y_p - mu_y)]
+//   = (G*D)(p) + 2 x_p (G*B)(p) + y_p (G*C)(p),   D = A - 2 B mu_x - C mu_y,
+// (G* a window sum), so the first kernel writes the planes D, B, C at every
+// pixel together with the per-tile sums of S and |x - y|, and the second
+// filters them.  Both run one separable 11-tap pattern: the tile's inputs
+// with a 5-pixel halo in LDS, a vertical pass (a thread per input column and
+// 8 output rows, accumulating in registers), then a horizontal pass (a thread
+// per row and 8 output columns) over the vertical sums, which reuse the LDS.
+constexpr int kSsimR = 5;                      // window radius
+constexpr int kTaps = 2 * kSsimR + 1;          // 11
+constexpr int kSsimTW = 116;                   // output columns per tile
+constexpr int kSsimTH = 16;                    // output rows per tile
+constexpr int kSsimIW = kSsimTW + 2 * kSsimR;  // 126 input columns
+constexpr int kSsimIH = kSsimTH + 2 * kSsimR;  // 26 input rows
+constexpr int kRun = 8;                        // outputs per thread in each pass
+constexpr int kGroups = (kSsimTW + kRun - 1) / kRun;      // 15 column groups
+constexpr int kVPitch = kRun * (kGroups - 1) + kRun + kTaps - 1 + 1;  // 131 > the last group's reads
 constexpr int kSsimThreads = 256;
+constexpr int kPass1Items = kSsimIW * (kSsimTH / kRun);  // 252
+constexpr int kPass2Items = kSsimTH * kGroups;            // 240
+static_assert(kPass1Items <= kSsimThreads && kPass2Items <= kSsimThreads, "one item per thread");
+static_assert(kSsimTH % kRun == 0, "whole runs of rows");
 constexpr float kC1 = 0.01f * 0.01f, kC2 = 0.03f * 0.03f;
 
 struct SsimArgs {
     const float *x, *y;
+    float *planes;    // [3][channels][H][W]: D, B, C (null: loss only)
     float *grad;      // may be null
-    double *partial;  // [tiles * channels][2]: sum S, sum |x - y| over the tile
-    int width, height, tiles_x;
-    float w1[2 * kSsimR + 1];  // normalised 1D Gaussian, sigma 1.5
+    double *partial;  // [tiles][2]: sum S, sum |x - y| over the tile
+    int64_t plane_stride;  // channels * H * W
+    int width, height, tiles_x, tiles_y, tiles, per_xcd;
+    float w1[kTaps];  // normalised 1D Gaussian, sigma 1.5
     float lambda, inv_n;
 };
 
-__global__ __launch_bounds__(kSsimThreads) void k_ssim(SsimArgs a) {
-    __shared__ float X[kSsimH][kSsimH], Y[kSsimH][kSsimH];
-    __shared__ float Hs[5][kSsimH][kSsimC];    // horizontal sums: x, y, xx, yy, xy
-    __shared__ float Mp[5][kSsimC][kSsimC];    // partials at the centres: A, B, B mu_x, C, C mu_y
-    __shared__ float H2[5][kSsimC][kSsimT];    // their horizontal sums
-    __shared__ double red[2][kSsimThreads];
-    const int c = blockIdx.z;
-    const int tx0 = blockIdx.x * kSsimT, ty0 = blockIdx.y * kSsimT;
-    const int64_t plane = (int64_t)a.width * a.height;
-    const float *xs = a.x + c * plane, *ys = a.y + c * plane;
-    const int tid = threadIdx.x;
-    // 1. halo, zero outside the image
-    for (int k = tid; k < kSsimH * kSsimH; k += kSsimThreads) {
-        const int r = k / kSsimH, q = k % kSsimH;
-        const int gy = ty0 - 2 * kSsimR + r, gx = tx0 - 2 * kSsimR + q;
-        const bool in = gy >= 0 && gy < a.height && gx >= 0 && gx < a.width;
-        X[r][q] = in ? xs[(int64_t)gy * a.width + gx] : 0.0f;
-        Y[r][q] = in ? ys[(int64_t)gy * a.width + gx] : 0.0f;
-    }
-    __syncthreads();
-    // 2. horizontal window sums for every halo row at the 26 centre columns
-    for (int k = tid; k < kSsimH * kSsimC; k += kSsimThreads) {
-        const int r = k / kSsimC, q = k % kSsimC;
-        float sx = 0.0f, sy = 0.0f, sxx = 0.0f, syy = 0.0f, sxy = 0.0f;
+// Tile of this workgroup.  Consecutive workgroups go to the 8 XCDs in turn,
+// so tile = (b mod 8) * per_xcd + b / 8 hands each XCD a contiguous run of
+// tiles, ordered down the columns of tiles: a tile and its lower neighbour,
+// whose input rows overlap, are read through the same L2.
+__device__ inline int ssim_tile(const SsimArgs &a, int &c, int &tx0, int &ty0) {
+    const int b = blockIdx.x;
+    const int t = (b & 7) * a.per_xcd + (b >> 3);
+    if (t >= a.tiles) return -1;
+    const int rest = t / a.tiles_y;
+    ty0 = (t - rest * a.tiles_y) * kSsimTH;
+    c = rest / a.tiles_x;
+    tx0 = (rest - c * a.tiles_x) * kSsimTW;
+    return t;
+}
+
+// Inputs of the tile with their halo, zero outside the image.  Every load
+// is issued before the first LDS store, so a workgroup waits for one round
+// trip to HBM rather than one per row of threads.
+constexpr int kHaloElems = kSsimIH * kSsimIW;
+constexpr int kHaloIters = (kHaloElems + kSsimThreads - 1) / kSsimThreads;  // 13
+template <int NIn>
+__device__ inline void load_halo(float *lds, const float *const (&src)[NIn], int64_t plane_off, int tx0, int ty0,
+                                 int width, int height) {
+    float v[kHaloIters][NIn];
 #pragma unroll
-        for (int t = 0; t <= 2 * kSsimR; ++t) {
-            const float w = a.w1[t], xv = X[r][q + t], yv = Y[r][q + t];
-            sx = __builtin_fmaf(w, xv, sx);
-            sy = __builtin_fmaf(w, yv, sy);
-            sxx = __builtin_fmaf(w, xv * xv, sxx);
-            syy = __builtin_fmaf(w, yv * yv, syy);
-            sxy = __builtin_fmaf(w, xv * yv, sxy);
-        }
-        Hs[0][r][q] = sx;
-        Hs[1][r][q] = sy;
-        Hs[2][r][q] = sxx;
-        Hs[3][r][q] = syy;
-        Hs[4][r][q] = sxy;
-    }
-    __syncthreads();
-    // 3. vertical sums: statistics, S and its partials at the 26x26 centres
-    double s_sum = 0.0, l1_sum = 0.0;
-    for (int k = tid; k < kSsimC * kSsimC; k += kSsimThreads) {
-        const int r = k / kSsimC, q = k % kSsimC;
+    for (int i = 0; i < kHaloIters; ++i) {
+        const int k = threadIdx.x + i * kSsimThreads;
+        const int r = k / kSsimIW, q = k - r * kSsimIW;
         const int gy = ty0 - kSsimR + r, gx = tx0 - kSsimR + q;
-        float m[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        const bool inside = k < kHaloElems && gy >= 0 && gy < height && gx >= 0 && gx < width;
+        const int64_t off = plane_off + (int64_t)gy * width + gx;
 #pragma unroll
-        for (int t = 0; t <= 2 * kSsimR; ++t) {
-            const float w = a.w1[t];
+        for (int p = 0; p < NIn; ++p) v[i][p] = inside ? src[p][off] : 0.0f;
+    }
 #pragma unroll
-            for (int f = 0; f < 5; ++f) m[f] = __builtin_fmaf(w, Hs[f][r + t][q], m[f]);
+    for (int i = 0; i < kHaloIters; ++i) {
+        const int k = threadIdx.x + i * kSsimThreads;
+        if (k < kHaloElems) {
+#pragma unroll
+            for (int p = 0; p < NIn; ++p) lds[p * kHaloElems + k] = v[i][p];
         }
-        float A = 0.0f, Bv = 0.0f, Cv = 0.0f, mx = 0.0f, my = 0.0f;
-        if (gy >= 0 && gy < a.height && gx >= 0 && gx < a.width) {
-            mx = m[0];
-            my = m[1];
-            const float vxx = m[2] - mx * mx, vyy = m[3] - my * my, vxy = m[4] - mx * my;
+    }
+}
+
+// Accumulate one input row (values v) into the kRun outputs it reaches: the
+// t-th row of a run feeds output j with tap t - j.
+template <int NV>
+__device__ __forceinline__ void add_row(float (&acc)[kRun][NV], const float (&v)[NV], int t, const float *w) {
+#pragma unroll
+    for (int j = 0; j < kRun; ++j) {
+        const int tap = t - j;
+        if (tap >= 0 && tap < kTaps) {
+#pragma unroll
+            for (int f = 0; f < NV; ++f) acc[j][f] = __builtin_fmaf(w[tap], v[f], acc[j][f]);
+        }
+    }
+}
+
+// Vertical sums -> LDS [NV][kSsimTH][kVPitch] (over the inputs, after a
+// barrier), then the horizontal pass of this thread's item into m.
+template <int NV>
+__device__ inline void store_vertical(float *lds, const float (&acc)[kRun][NV], int k) {
+    if (k >= kPass1Items) return;
+    const int h = k / kSsimIW, q = k - h * kSsimIW;
+#pragma unroll
+    for (int j = 0; j < kRun; ++j)
+#pragma unroll
+        for (int f = 0; f < NV; ++f) lds[(f * kSsimTH + h * kRun + j) * kVPitch + q] = acc[j][f];
+}
+
+template <int NV>
+__device__ inline void horizontal(const float *lds, int r, int g, const float *w, float (&m)[kRun][NV]) {
+#pragma unroll
+    for (int j = 0; j < kRun; ++j)
+#pragma unroll
+        for (int f = 0; f < NV; ++f) m[j][f] = 0.0f;
+#pragma unroll
+    for (int t = 0; t < kRun + kTaps - 1; ++t) {
+        float v[NV];
+#pragma unroll
+        for (int f = 0; f < NV; ++f) v[f] = lds[(f * kSsimTH + r) * kVPitch + g * kRun + t];
+        add_row<NV>(m, v, t, w);
+    }
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+constexpr int kLdsStats = 5 * kSsimTH * kVPitch > 2 * kSsimIH * kSsimIW ? 5 * kSsimTH * kVPitch : 2 * kSsimIH * kSsimIW;
+constexpr int kLdsGrad = 3 * kSsimTH * kVPitch > 3 * kSsimIH * kSsimIW ? 3 * kSsimTH * kVPitch : 3 * kSsimIH * kSsimIW;
+
+// Window statistics, S, the planes D, B, C and the tile's sums of S, |x - y|.
+__global__ __launch_bounds__(kSsimThreads) void k_ssim_stats(SsimArgs a) {
+    __shared__ float lds[kLdsStats];
+    __shared__ double red[2][kSsimThreads / 64];
+    int c, tx0, ty0;
+    const int tile = ssim_tile(a, c, tx0, ty0);
+    if (tile < 0) return;
+    const int64_t plane = (int64_t)a.width * a.height;
+    const float *const src[2] = {a.x, a.y};
+    load_halo<2>(lds, src, c * plane, tx0, ty0, a.width, a.height);
+    __syncthreads();
+    const int k = threadIdx.x;
+    // vertical pass over x, y, x^2, y^2, xy; |x - y| at the tile's own pixels
+    float acc[kRun][5] = {};
+    double l1_sum = 0.0;
+    if (k < kPass1Items) {
+        const int h = k / kSsimIW, q = k - h * kSsimIW;
+        const bool own_col = q >= kSsimR && q < kSsimR + kSsimTW;
+        float l1 = 0.0f;
+#pragma unroll
+        for (int t = 0; t < kRun + kTaps - 1; ++t) {
+            const int row = h * kRun + t;
+            const float xv = lds[row * kSsimIW + q], yv = lds[(kSsimIH + row) * kSsimIW + q];
+            const float v[5] = {xv, yv, xv * xv, yv * yv, xv * yv};
+            add_row<5>(acc, v, t, a.w1);
+            if (t >= kSsimR && t < kSsimR + kRun) l1 += fabsf(xv - yv);
+        }
+        if (own_col) l1_sum = (double)l1;
+    }
+    __syncthreads();
+    store_vertical<5>(lds, acc, k);
+    __syncthreads();
+    double s_sum = 0.0;
+    if (k < kPass2Items) {
+        const int r = k % kSsimTH, g = k / kSsimTH;
+        float m[kRun][5];
+        horizontal<5>(lds, r, g, a.w1, m);
+        const int gy = ty0 + r;
+#pragma unroll
+        for (int j = 0; j < kRun; ++j) {
+            const int col = g * kRun + j, gx = tx0 + col;
+            if (col >= kSsimTW || gx >= a.width || gy >= a.height) continue;
+            const float mx = m[j][0], my = m[j][1];
+            const float vxx = m[j][2] - mx * mx, vyy = m[j][3] - my * my, vxy = m[j][4] - mx * my;
             const float n1 = 2.0f * mx * my + kC1, n2 = 2.0f * vxy + kC2;
             const float d1 = mx * mx + my * my + kC1, d2 = vxx + vyy + kC2;
             const float inv = 1.0f / (d1 * d2);
             const float S = n1 * n2 * inv;
-            A = 2.0f * my * n2 * inv - S * 2.0f * mx / d1;  // dS/dmu_x
-            Bv = -S / d2;                                     // dS/ds_xx
-            Cv = 2.0f * n1 * inv;                             // dS/ds_xy
-            // the tile's own centres carry the loss
-            if (r >= kSsimR && r < kSsimR + kSsimT && q >= kSsimR && q < kSsimR + kSsimT) {
-                s_sum += (double)S;
-                l1_sum += (double)fabsf(X[r + kSsimR][q + kSsimR] - Y[r + kSsimR][q + kSsimR]);
+            s_sum += (double)S;
+            if (a.planes) {
+                const float A = 2.0f * my * n2 * inv - S * 2.0f * mx / d1;  // dS/dmu_x
+                const float B = -S / d2;                                    // dS/ds_xx
+                const float C = 2.0f * n1 * inv;                            // dS/ds_xy
+                const int64_t o = c * plane + (int64_t)gy * a.width + gx;
+                a.planes[o] = A - 2.0f * B * mx - C * my;
+                a.planes[a.plane_stride + o] = B;
+                a.planes[2 * a.plane_stride + o] = C;
             }
         }
-        Mp[0][r][q] = A;
-        Mp[1][r][q] = Bv;
-        Mp[2][r][q] = Bv * mx;
-        Mp[3][r][q] = Cv;
-        Mp[4][r][q] = Cv * my;
     }
-    red[0][tid] = s_sum;
-    red[1][tid] = l1_sum;
-    __syncthreads();
-    // 4. horizontal sums of the partials at the 16 output columns
-    for (int k = tid; k < kSsimC * kSsimT; k += kSsimThreads) {
-        const int r = k / kSsimT, q = k % kSsimT;
-        float m[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int t = 0; t <= 2 * kSsimR; ++t) {
-            const float w = a.w1[t];
-#pragma unroll
-            for (int f = 0; f < 5; ++f) m[f] = __builtin_fmaf(w, Mp[f][r][q + t], m[f]);
-        }
-#pragma unroll
-        for (int f = 0; f < 5; ++f) H2[f][r][q] = m[f];
-    }
-    for (int off = kSsimThreads / 2; off > 0; off >>= 1) {
-        __syncthreads();
-        if (tid < off) {
-            red[0][tid] += red[0][tid + off];
-            red[1][tid] += red[1][tid + off];
-        }
+    s_sum = wave_sum(s_sum);
+    l1_sum = wave_sum(l1_sum);
+    if ((k & 63) == 0) {
+        red[0][k >> 6] = s_sum;
+        red[1][k >> 6] = l1_sum;
     }
     __syncthreads();
-    const int64_t blk = ((int64_t)c * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    if (tid == 0) {
-        a.partial[2 * blk] = red[0][0];
-        a.partial[2 * blk + 1] = red[1][0];
-    }
-    if (!a.grad) return;
-    // 5. vertical sums and the gradient at the tile's pixels
-    {
-        const int r = tid / kSsimT, q = tid % kSsimT;
-        const int gy = ty0 + r, gx = tx0 + q;
-        if (gy >= a.height || gx >= a.width) return;
-        float m[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int t = 0; t <= 2 * kSsimR; ++t) {
-            const float w = a.w1[t];
-#pragma unroll
-            for (int f = 0; f < 5; ++f) m[f] = __builtin_fmaf(w, H2[f][r + t][q], m[f]);
+    if (k == 0) {
+        double s = 0.0, l = 0.0;
+        for (int w = 0; w < kSsimThreads / 64; ++w) {
+            s += red[0][w];
+            l += red[1][w];
         }
-        const float xv = X[r + 2 * kSsimR][q + 2 * kSsimR], yv = Y[r + 2 * kSsimR][q + 2 * kSsimR];
-        // d S_sum / d x_p = G*A + 2 x_p G*B - 2 G*(B mu_x) + y_p G*C - G*(C mu_y)
-        const float dS = m[0] + 2.0f * xv * m[1] - 2.0f * m[2] + yv * m[3] - m[4];
-        const float d = xv - yv;
+        a.partial[2 * tile] = s;
+        a.partial[2 * tile + 1] = l;
+    }
+}
+
+// dL/dx = [(1 - lambda) sign(x - y) - lambda (G*D + 2 x G*B + y G*C)] / N.
+__global__ __launch_bounds__(kSsimThreads) void k_ssim_grad(SsimArgs a) {
+    __shared__ float lds[kLdsGrad];
+    int c, tx0, ty0;
+    if (ssim_tile(a, c, tx0, ty0) < 0) return;
+    const int64_t plane = (int64_t)a.width * a.height;
+    const int k = threadIdx.x;
+    // x, y at this thread's outputs, fetched while the passes run
+    const int r = k % kSsimTH, g = k / kSsimTH;
+    const int gy = ty0 + r;
+    float xv[kRun], yv[kRun];
+#pragma unroll
+    for (int j = 0; j < kRun; ++j) {
+        const int col = g * kRun + j, gx = tx0 + col;
+        const bool own = k < kPass2Items && col < kSsimTW && gx < a.width && gy < a.height;
+        const int64_t o = c * plane + (int64_t)gy * a.width + gx;
+        xv[j] = own ? a.x[o] : 0.0f;
+        yv[j] = own ? a.y[o] : 0.0f;
+    }
+    const float *const src[3] = {a.planes, a.planes + a.plane_stride, a.planes + 2 * a.plane_stride};
+    load_halo<3>(lds, src, c * plane, tx0, ty0, a.width, a.height);
+    __syncthreads();
+    float acc[kRun][3] = {};
+    if (k < kPass1Items) {
+        const int h = k / kSsimIW, q = k - h * kSsimIW;
+#pragma unroll
+        for (int t = 0; t < kRun + kTaps - 1; ++t) {
+            const int row = h * kRun + t;
+            const float v[3] = {lds[row * kSsimIW + q], lds[(kSsimIH + row) * kSsimIW + q],
+                                lds[(2 * kSsimIH + row) * kSsimIW + q]};
+            add_row<3>(acc, v, t, a.w1);
+        }
+    }
+    __syncthreads();
+    store_vertical<3>(lds, acc, k);
+    __syncthreads();
+    if (k >= kPass2Items || gy >= a.height) return;
+    float m[kRun][3];
+    horizontal<3>(lds, r, g, a.w1, m);
+    const float l1w = 1.0f - a.lambda;
+#pragma unroll
+    for (int j = 0; j < kRun; ++j) {
+        const int col = g * kRun + j, gx = tx0 + col;
+        if (col >= kSsimTW || gx >= a.width) continue;
+        const int64_t o = c * plane + (int64_t)gy * a.width + gx;
+        const float dS = m[j][0] + 2.0f * xv[j] * m[j][1] + yv[j] * m[j][2];
+        const float d = xv[j] - yv[j];
         const float sgn = d > 0.0f ? 1.0f : (d < 0.0f ? -1.0f : 0.0f);
-        a.grad[c * plane + (int64_t)gy * a.width + gx] = a.inv_n * ((1.0f - a.lambda) * sgn - a.lambda * dS);
+        a.grad[o] = a.inv_n * (l1w * sgn - a.lambda * dS);
     }
 }
 
@@ -221,9 +334,13 @@ __global__ __launch_bounds__(256) void k_ssim_final(const double *partial, int64
 
 }  // namespace
 
-size_t ssim_scratch_bytes(int channels, int height, int width) {
-    const int64_t tiles = (int64_t)((width + kSsimT - 1) / kSsimT) * ((height + kSsimT - 1) / kSsimT) * channels;
-    return (size_t)tiles * 2 * sizeof(double);
+static int64_t ssim_tiles(int channels, int height, int width) {
+    return (int64_t)((width + kSsimTW - 1) / kSsimTW) * ((height + kSsimTH - 1) / kSsimTH) * channels;
+}
+
+size_t ssim_scratch_bytes(int channels, int height, int width, bool with_grad) {
+    const size_t partial = ((size_t)ssim_tiles(channels, height, width) * 2 * sizeof(double) + 255) & ~(size_t)255;
+    return partial + (with_grad ? (size_t)3 * channels * height * width * sizeof(float) : 0);
 }
 
 hipError_t launch_photometric(const float *image, const float *target, int channels, int height, int width,
@@ -235,21 +352,27 @@ hipError_t launch_photometric(const float *image, const float *target, int chann
     a.partial = static_cast<double *>(scratch);
     a.width = width;
     a.height = height;
-    a.tiles_x = (width + kSsimT - 1) / kSsimT;
-    double g[2 * kSsimR + 1], sum = 0.0;
-    for (int t = 0; t <= 2 * kSsimR; ++t) {
+    a.tiles_x = (width + kSsimTW - 1) / kSsimTW;
+    a.tiles_y = (height + kSsimTH - 1) / kSsimTH;
+    a.tiles = (int)ssim_tiles(channels, height, width);
+    a.per_xcd = (a.tiles + 7) / 8;
+    a.plane_stride = (int64_t)channels * height * width;
+    const size_t partial = ssim_scratch_bytes(channels, height, width, false);
+    a.planes = grad ? reinterpret_cast<float *>(static_cast<char *>(scratch) + partial) : nullptr;
+    double g[kTaps], sum = 0.0;
+    for (int t = 0; t < kTaps; ++t) {
         const double d = t - kSsimR;
         g[t] = std::exp(-d * d / (2.0 * 1.5 * 1.5));
         sum += g[t];
     }
-    for (int t = 0; t <= 2 * kSsimR; ++t) a.w1[t] = (float)(g[t] / sum);
+    for (int t = 0; t < kTaps; ++t) a.w1[t] = (float)(g[t] / sum);
     const double n = (double)channels * height * width;
     a.lambda = lambda;
     a.inv_n = (float)(1.0 / n);
-    const dim3 grid((unsigned)a.tiles_x, (unsigned)((height + kSsimT - 1) / kSsimT), (unsigned)channels);
-    hipLaunchKernelGGL(k_ssim, grid, dim3(kSsimThreads), 0, st, a);
-    const int64_t blocks = (int64_t)grid.x * grid.y * grid.z;
-    hipLaunchKernelGGL(k_ssim_final, dim3(1), dim3(256), 0, st, a.partial, blocks, n, (double)lambda, loss);
+    const dim3 grid((unsigned)(8 * a.per_xcd));
+    hipLaunchKernelGGL(k_ssim_stats, grid, dim3(kSsimThreads), 0, st, a);
+    if (grad) hipLaunchKernelGGL(k_ssim_grad, grid, dim3(kSsimThreads), 0, st, a);
+    hipLaunchKernelGGL(k_ssim_final, dim3(1), dim3(256), 0, st, a.partial, (int64_t)a.tiles, n, (double)lambda, loss);
     return hipGetLastError();
 }
 

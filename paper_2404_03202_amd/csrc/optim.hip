@@ -3,6 +3,7 @@
 // reset.  All HBM-bound elementwise or per-Gaussian passes.
 #include "internal.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace omnigs {
@@ -12,34 +13,86 @@ constexpr int kThreads = 256;
 
 __device__ inline float sigmoidf_(float x) { return 1.0f / (1.0f + expf(-x)); }
 
-// One Adam step over the concatenation of the parameter arrays (means,
-// log_scales, quats, logits, sh); segment boundaries in elements.
+// One Adam step of one element (x: parameter, g: gradient w.r.t. the
+// activated value for log-scales and logits).
+struct AdamOut {
+    float x, m, v, act;
+};
+template <int kSeg>
+__device__ __forceinline__ AdamOut adam_one(float x, float g, float m, float v, float lr, const AdamArgs &a) {
+    if (kSeg == kSegLogScales) g *= expf(x);  // dS/dlog S = S
+    if (kSeg == kSegLogits) {
+        const float o = sigmoidf_(x);
+        g *= o * (1.0f - o);  // do/dlogit
+    }
+    AdamOut r;
+    r.m = a.beta1 * m + (1.0f - a.beta1) * g;
+    r.v = a.beta2 * v + (1.0f - a.beta2) * (g * g);
+    r.x = x - lr * a.inv_bc1 * r.m / (sqrtf(r.v) * a.inv_sqrt_bc2 + a.eps);
+    r.act = kSeg == kSegLogScales ? expf(r.x) : (kSeg == kSegLogits ? sigmoidf_(r.x) : 0.0f);
+    return r;
+}
+
+// One Adam step over one parameter array (blockIdx.y selects it): each
+// thread takes four consecutive elements, as float4 when the arrays are
+// 16-byte aligned.
+template <int kSeg>
+__device__ inline void adam_segment(const OptimArrays &P, const OptimArrays &G, const OptimArrays &M1,
+                                    const OptimArrays &M2, const AdamArgs &a, float *act) {
+    const int64_t len = (kSeg + 1 < kSegments ? a.begin[kSeg + 1] : a.total) - a.begin[kSeg];
+    float *p = P.ptr[kSeg], *m = M1.ptr[kSeg], *v = M2.ptr[kSeg];
+    const float *g = G.ptr[kSeg];
+    const float lr = a.lr[kSeg];
+    const bool vec = ((reinterpret_cast<uintptr_t>(p) | reinterpret_cast<uintptr_t>(m) | reinterpret_cast<uintptr_t>(v) |
+                       reinterpret_cast<uintptr_t>(g) | (act ? reinterpret_cast<uintptr_t>(act) : 0)) & 15u) == 0;
+    const int64_t stride = (int64_t)gridDim.x * kThreads * 4;
+    for (int64_t i0 = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * 4; i0 < len; i0 += stride) {
+        if (vec && i0 + 4 <= len) {
+            const float4 x4 = *reinterpret_cast<const float4 *>(p + i0), g4 = *reinterpret_cast<const float4 *>(g + i0);
+            const float4 m4 = *reinterpret_cast<const float4 *>(m + i0), v4 = *reinterpret_cast<const float4 *>(v + i0);
+            const float xs[4] = {x4.x, x4.y, x4.z, x4.w}, gs[4] = {g4.x, g4.y, g4.z, g4.w};
+            const float ms[4] = {m4.x, m4.y, m4.z, m4.w}, vs[4] = {v4.x, v4.y, v4.z, v4.w};
+            // column of i0 within its Gaussian's SH block (sh_stride >= 3, so
+            // one wrap covers the next three)
+            const int64_t c0 = kSeg == kSegSh ? i0 % a.sh_stride : 0;
+            AdamOut r[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                float lk = lr;
+                if (kSeg == kSegSh) {
+                    int64_t c = c0 + k;
+                    if (c >= a.sh_stride) c -= a.sh_stride;
+                    if (c >= 3) lk = a.lr_sh_rest;  // SH degrees >= 1
+                }
+                r[k] = adam_one<kSeg>(xs[k], gs[k], ms[k], vs[k], lk, a);
+            }
+            *reinterpret_cast<float4 *>(p + i0) = make_float4(r[0].x, r[1].x, r[2].x, r[3].x);
+            *reinterpret_cast<float4 *>(m + i0) = make_float4(r[0].m, r[1].m, r[2].m, r[3].m);
+            *reinterpret_cast<float4 *>(v + i0) = make_float4(r[0].v, r[1].v, r[2].v, r[3].v);
+            if ((kSeg == kSegLogScales || kSeg == kSegLogits) && act)
+                *reinterpret_cast<float4 *>(act + i0) = make_float4(r[0].act, r[1].act, r[2].act, r[3].act);
+        } else {
+            for (int64_t i = i0; i < i0 + 4 && i < len; ++i) {
+                float lk = lr;
+                if (kSeg == kSegSh && (i % a.sh_stride) >= 3) lk = a.lr_sh_rest;
+                const AdamOut r = adam_one<kSeg>(p[i], g[i], m[i], v[i], lk, a);
+                p[i] = r.x;
+                m[i] = r.m;
+                v[i] = r.v;
+                if ((kSeg == kSegLogScales || kSeg == kSegLogits) && act) act[i] = r.act;
+            }
+        }
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void k_adam(OptimArrays P, OptimArrays G, OptimArrays M1, OptimArrays M2,
                                                    AdamArgs a, float *act_scales, float *act_opacities) {
-    const int64_t stride = (int64_t)gridDim.x * kThreads;
-    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < a.total; e += stride) {
-        int seg = 0;
-#pragma unroll
-        for (int k = 1; k < kSegments; ++k) seg += e >= a.begin[k] ? 1 : 0;
-        const int64_t i = e - a.begin[seg];
-        float *p = P.ptr[seg] + i, *m = M1.ptr[seg] + i, *v = M2.ptr[seg] + i;
-        float g = G.ptr[seg][i];
-        const float x = *p;
-        float lr = a.lr[seg];
-        if (seg == kSegLogScales) g *= expf(x);                    // dS/dlog S = S
-        if (seg == kSegLogits) {
-            const float o = sigmoidf_(x);
-            g *= o * (1.0f - o);                                    // do/dlogit
-        }
-        if (seg == kSegSh && (i % a.sh_stride) >= 3) lr = a.lr_sh_rest;  // SH degrees >= 1
-        const float mn = a.beta1 * *m + (1.0f - a.beta1) * g;
-        const float vn = a.beta2 * *v + (1.0f - a.beta2) * (g * g);
-        const float xn = x - lr * a.inv_bc1 * mn / (sqrtf(vn) * a.inv_sqrt_bc2 + a.eps);
-        *m = mn;
-        *v = vn;
-        *p = xn;
-        if (seg == kSegLogScales && act_scales) act_scales[i] = expf(xn);
-        if (seg == kSegLogits && act_opacities) act_opacities[i] = sigmoidf_(xn);
+    switch (blockIdx.y) {
+        case kSegMeans: adam_segment<kSegMeans>(P, G, M1, M2, a, nullptr); break;
+        case kSegLogScales: adam_segment<kSegLogScales>(P, G, M1, M2, a, act_scales); break;
+        case kSegQuats: adam_segment<kSegQuats>(P, G, M1, M2, a, nullptr); break;
+        case kSegLogits: adam_segment<kSegLogits>(P, G, M1, M2, a, act_opacities); break;
+        default: adam_segment<kSegSh>(P, G, M1, M2, a, nullptr); break;
     }
 }
 
@@ -151,8 +204,13 @@ unsigned blocks(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 hipError_t launch_adam(const OptimArrays &P, const OptimArrays &G, const OptimArrays &M1, const OptimArrays &M2,
                        const AdamArgs &a, float *act_scales, float *act_opacities, hipStream_t st) {
     if (a.total == 0) return hipSuccess;
-    const unsigned grid = (unsigned)std::min<int64_t>((a.total + kThreads - 1) / kThreads, 256 * 64);
-    hipLaunchKernelGGL(k_adam, dim3(grid), dim3(kThreads), 0, st, P, G, M1, M2, a, act_scales, act_opacities);
+    // blockIdx.y: the parameter array; x: enough blocks for the largest (SH)
+    int64_t longest = 0;
+    for (int k = 0; k < kSegments; ++k)
+        longest = std::max<int64_t>(longest, (k + 1 < kSegments ? a.begin[k + 1] : a.total) - a.begin[k]);
+    const unsigned grid = (unsigned)std::min<int64_t>((longest + 4 * kThreads - 1) / (4 * kThreads), 256 * 32);
+    hipLaunchKernelGGL(k_adam, dim3(grid, kSegments), dim3(kThreads), 0, st, P, G, M1, M2, a, act_scales,
+                       act_opacities);
     return hipGetLastError();
 }
 

@@ -1,6 +1,7 @@
 """Parity of omnigs_photometric_loss (L1 + SSIM term of Eq. 17) with the FP64
 oracle (oracle/ssim.py) on seeded images, including a rendered image and sizes
-that are not multiples of the 16-pixel tile."""
+that are not multiples of the 116 x 16 tile (several tiles with ragged tails
+in both directions)."""
 import numpy as np
 import pytest
 import torch
@@ -18,7 +19,9 @@ def check(x, y, lam):
     xd = torch.from_numpy(x.astype(np.float32)).to(DEV)
     yd = torch.from_numpy(y.astype(np.float32)).to(DEV)
     loss, g = B.omnigs_photometric_loss(xd, yd, lam)
+    loss_only, none = B.omnigs_photometric_loss(xd, yd, lam, grad=False)
     torch.cuda.synchronize()
+    assert none is None and float(loss_only.item()) == float(loss.item())
     x32, y32 = x.astype(np.float32).astype(np.float64), y.astype(np.float32).astype(np.float64)
     ol, og = Q.photometric(x32, y32, lam)
     # float32 window sums of 121 terms; the loss is a mean of O(1) terms
@@ -32,7 +35,7 @@ def check(x, y, lam):
     return ol
 
 
-@pytest.mark.parametrize("shape", [(3, 64, 128), (3, 40, 96), (1, 16, 16), (2, 7, 23)])
+@pytest.mark.parametrize("shape", [(3, 64, 128), (3, 40, 96), (1, 16, 16), (2, 7, 23), (2, 50, 250)])
 @pytest.mark.parametrize("lam", [0.0, 0.2, 1.0])
 def test_photometric_random_images(shape, lam):
     rng = np.random.default_rng([hash(shape) % 1000, scenes.STREAM_FD])
