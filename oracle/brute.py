@@ -4,9 +4,10 @@ TEST INFRASTRUCTURE ONLY.  A second, independent statement of the forward
 pass, used to pin the tiled C oracle:
 
 * no tiles and no radius of influence: every pixel visits every Gaussian in
-  (t_r, index) order (Eq. 6 and the depth criterion of Sec. 3.3);
+  (depth, index) order (Eq. 6 and the depth criterion of Sec. 3.3: t_r for
+  the ERP camera, t_z for the pinhole camera of Eq. 2);
 * the Jacobian of Eq. 10 is taken by central finite differences of the
-  projection Eqs. 3-5 instead of the closed forms of Eq. 11-16;
+  projection (Eqs. 3-5, or Eq. 2) instead of closed forms;
 * the rotation comes from scipy's quaternion conversion, the inverse 2D
   covariance from ``numpy.linalg.inv``;
 * the SH basis comes from scipy's complex spherical harmonics
@@ -44,14 +45,21 @@ def erp_project(t, W, H):
     return np.stack([(lon / np.pi + 1.0) * W / 2.0, (2.0 * lat / np.pi + 1.0) * H / 2.0], axis=-1)
 
 
-def fd_jacobian(t, W, H, rel=1e-6):
-    """Central-difference Jacobian d p / d t (2x3) of Eq. 3-5."""
+def pinhole_project(t, fx, fy, cx, cy):
+    """Eq. 2: camera-space point -> pinhole pixel coordinates (x, y)."""
+    return np.stack([fx * t[..., 0] / t[..., 2] + cx, fy * t[..., 1] / t[..., 2] + cy], axis=-1)
+
+
+def fd_jacobian(t, W, H, rel=1e-6, proj=None):
+    """Central-difference Jacobian d p / d t (2x3) of Eq. 3-5 (or of the
+    projection ``proj``)."""
+    proj = proj or (lambda u: erp_project(u, W, H))
     J = np.zeros((2, 3))
     h = rel * np.linalg.norm(t)
     for k in range(3):
         e = np.zeros(3)
         e[k] = h
-        J[:, k] = (erp_project(t + e, W, H) - erp_project(t - e, W, H)) / (2.0 * h)
+        J[:, k] = (proj(t + e) - proj(t - e)) / (2.0 * h)
     return J
 
 
@@ -74,22 +82,32 @@ def real_sh(degree, d):
 
 
 def project_independent(scene):
-    """Per-Gaussian (visible, t_r, px, py, Q00, Q01, Q11, rgb) computed without
-    the C oracle.  Returns a dict of arrays."""
+    """Per-Gaussian (visible, depth ("tr"), px, py, Q00, Q01, Q11, rgb)
+    computed without the C oracle.  Returns a dict of arrays."""
     st = scene.settings
     n, W, H = scene.n, scene.width, scene.height
     out = dict(visible=np.zeros(n, bool), tr=np.zeros(n), px=np.zeros(n), py=np.zeros(n), Q=np.zeros((n, 3)),
                rgb=np.zeros((n, 3)))
     cam_centre = -scene.R.T @ scene.t
+    pinhole = getattr(scene, "model", 0) == 1
     for i in range(n):
         t = scene.R @ scene.means[i] + scene.t
         tr = np.linalg.norm(t)
         rho = np.hypot(t[0], t[2])
         o = scene.opac[i]
-        if tr <= st["near_plane"] or o <= st["alpha_min"] or rho <= 1e-6 * tr:
-            continue
-        p = erp_project(t, W, H)
-        J = fd_jacobian(t, W, H)
+        if pinhole:
+            if t[2] <= st["near_plane"] or o <= st["alpha_min"]:
+                continue
+            proj = lambda u: pinhole_project(u, *scene.intrinsics)
+            p = proj(t)
+            J = fd_jacobian(t, W, H, proj=proj)
+            depth = t[2]
+        else:
+            if tr <= st["near_plane"] or o <= st["alpha_min"] or rho <= 1e-6 * tr:
+                continue
+            p = erp_project(t, W, H)
+            J = fd_jacobian(t, W, H)
+            depth = tr
         q = scene.quats[i]
         Rq = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()
         Sig = Rq @ np.diag(scene.scales[i] ** 2) @ Rq.T
@@ -104,7 +122,7 @@ def project_independent(scene):
         K = (scene.sh_degree + 1) ** 2
         rgb = np.maximum(Y @ scene.sh[i, :K, :] + 0.5, 0.0)
         out["visible"][i] = True
-        out["tr"][i] = tr
+        out["tr"][i] = depth
         out["px"][i], out["py"][i] = p
         out["Q"][i] = (Q[0, 0], Q[0, 1], Q[1, 1])
         out["rgb"][i] = rgb
@@ -135,10 +153,12 @@ def render(scene, records=None):
     C = np.zeros((3, H, W))
     active = np.ones((H, W), bool)
     nb = np.zeros((H, W), dtype=np.int64)
+    wrap = getattr(scene, "model", 0) != 1  # the ERP seam; the pinhole image does not wrap
     for i in order:
         dx = xc - proj["px"][i]
-        dx = np.where(dx >= 0.5 * W, dx - W, dx)
-        dx = np.where(dx < -0.5 * W, dx + W, dx)
+        if wrap:
+            dx = np.where(dx >= 0.5 * W, dx - W, dx)
+            dx = np.where(dx < -0.5 * W, dx + W, dx)
         dy = yc - proj["py"][i]
         q00, q01, q11 = proj["Q"][i]
         power = -0.5 * (q00 * dx * dx + 2.0 * q01 * dx * dy + q11 * dy * dy)

@@ -23,6 +23,10 @@
  *   Eq. 18-20    chain rule to m, q, S through the replaced
  *                omnidirectional terms dSigma2D/dSigma, dJ/dt,
  *                dp/ds, ds/dt                                    (Sec. 3.4)
+ *   Eq. 2        the perspective (pinhole) camera the paper starts from,
+ *                p = (f_x t_x / t_z + c_x, f_y t_y / t_z + c_y), with its
+ *                Jacobian in Eq. 9 and instances ordered by t_z (Sec. 3.2,
+ *                3.3); selected per camera
  *
  * Readings where the paper is silent (each is listed in the design notes):
  *   - atan2 takes (t_x, t_z); lon = +pi is mapped to -pi (Eq. 3 range).
@@ -43,6 +47,12 @@
  *     centre to m, plus 1/2, clamped below at 0.
  *   - gradient is taken w.r.t. activated scales and opacities, the raw
  *     quaternion (normalised inside), means and SH coefficients.
+ *   - pinhole camera: J is the exact derivative of Eq. 2 at the Gaussian's
+ *     centre (no clamping of t_x / t_z); Gaussians with t_z <= near_plane are
+ *     culled; the depth order is (t_z, index); pixel (x, y) samples at
+ *     (x + 1/2, y + 1/2); nothing wraps: columns clamp like rows, and the
+ *     width need not be a multiple of 16 (the last tile column is ragged);
+ *     the screen-space gradient is (W/2, H/2) * dL/dp as for the ERP image.
  */
 #include <math.h>
 #include <stdint.h>
@@ -54,6 +64,8 @@
 
 #define ORC_TILE 16
 #define ORC_MAXK 16
+#define ORC_ERP 0
+#define ORC_PINHOLE 1
 
 typedef struct {
     int64_t n;
@@ -72,7 +84,24 @@ typedef struct {
     /* near-tie flagging margins (relative for alpha, T, depth; absolute
      * pixels for the rect bounds) */
     double flag_rel_alpha, flag_rel_T, flag_rel_depth, flag_abs_rect;
+    int32_t model;        /* ORC_ERP or ORC_PINHOLE                         */
+    int32_t reserved;
+    double fx, fy, cx, cy; /* pinhole intrinsics of Eq. 2 (pixels)         */
 } orc_scene;
+
+/* tile columns: W / 16 for the ERP image (W a multiple of 16, the columns
+ * wrap), ceil(W / 16) for the pinhole image */
+static int orc_tiles_x(const orc_scene *s) {
+    return s->model == ORC_PINHOLE ? (s->width + ORC_TILE - 1) / ORC_TILE : s->width / ORC_TILE;
+}
+
+static int orc_valid(const orc_scene *s) {
+    if (s->height < 1 || s->width < 1) return 0;
+    if (s->model == ORC_ERP) return s->width % ORC_TILE == 0;
+    if (s->model == ORC_PINHOLE) return isfinite(s->fx) && isfinite(s->fy) && s->fx > 0.0 && s->fy > 0.0 &&
+                                        isfinite(s->cx) && isfinite(s->cy);
+    return 0;
+}
 
 /* ------------------------------------------------------------------------ */
 /* Real spherical harmonics, evaluated from their definition.                */
@@ -181,6 +210,7 @@ void orc_sh_eval(int degree, const double *dir, double *Y, double *dY) {
 typedef struct {
     int visible;
     double tc[3], tr, rho;
+    double depth;      /* sort key: t_r (ERP) or t_z (pinhole) */
     double lon, lat, px, py;
     double J[6];       /* 2x3, row-major (third row of Eq. 10 is zero) */
     double M[6];       /* J W, 2x3 */
@@ -216,28 +246,46 @@ static void project_one(const orc_scene *s, int64_t i, orc_proj *P) {
     const double tx = P->tc[0], ty = P->tc[1], tz = P->tc[2];
     P->tr = sqrt(tx * tx + ty * ty + tz * tz);
     P->rho = sqrt(tx * tx + tz * tz);
-    /* culling: behind the near sphere, too transparent to ever pass alpha_min,
-     * or on the polar axis where Eq. 11-16 diverge */
-    if (fabs(P->tr - s->near_plane) < 1e-9 * s->near_plane) P->flag = 1;
     if (fabs(o - s->alpha_min) < 1e-9 * s->alpha_min) P->flag = 1;
-    if (P->tr <= s->near_plane || o <= s->alpha_min || P->rho <= 1e-6 * P->tr) return;
-    /* Eq. 3 */
-    P->lon = atan2(tx, tz);
-    if (P->lon >= M_PI) P->lon = -M_PI;
-    P->lat = asin(ty / P->tr);
-    /* Eq. 4, 5 */
-    const double sx = P->lon / M_PI, sy = 2.0 * P->lat / M_PI;
-    P->px = (sx + 1.0) * W / 2.0;
-    P->py = (sy + 1.0) * H / 2.0;
-    /* Eq. 11-16 */
-    const double rho2 = P->rho * P->rho, r2 = P->tr * P->tr;
-    const double kx = W / (2.0 * M_PI), ky = H / M_PI;
-    P->J[0] = kx * tz / rho2;
-    P->J[1] = 0.0;
-    P->J[2] = -kx * tx / rho2;
-    P->J[3] = -ky * tx * ty / (r2 * P->rho);
-    P->J[4] = ky * P->rho / r2;
-    P->J[5] = -ky * tz * ty / (r2 * P->rho);
+    if (s->model == ORC_PINHOLE) {
+        /* culling: behind the near plane or too transparent */
+        if (fabs(tz - s->near_plane) < 1e-9 * s->near_plane) P->flag = 1;
+        if (tz <= s->near_plane || o <= s->alpha_min) return;
+        P->depth = tz;
+        /* Eq. 2 */
+        P->px = s->fx * tx / tz + s->cx;
+        P->py = s->fy * ty / tz + s->cy;
+        /* its Jacobian d p / d t */
+        P->J[0] = s->fx / tz;
+        P->J[1] = 0.0;
+        P->J[2] = -s->fx * tx / (tz * tz);
+        P->J[3] = 0.0;
+        P->J[4] = s->fy / tz;
+        P->J[5] = -s->fy * ty / (tz * tz);
+    } else {
+        /* culling: behind the near sphere, too transparent to ever pass
+         * alpha_min, or on the polar axis where Eq. 11-16 diverge */
+        if (fabs(P->tr - s->near_plane) < 1e-9 * s->near_plane) P->flag = 1;
+        if (P->tr <= s->near_plane || o <= s->alpha_min || P->rho <= 1e-6 * P->tr) return;
+        P->depth = P->tr;
+        /* Eq. 3 */
+        P->lon = atan2(tx, tz);
+        if (P->lon >= M_PI) P->lon = -M_PI;
+        P->lat = asin(ty / P->tr);
+        /* Eq. 4, 5 */
+        const double sx = P->lon / M_PI, sy = 2.0 * P->lat / M_PI;
+        P->px = (sx + 1.0) * W / 2.0;
+        P->py = (sy + 1.0) * H / 2.0;
+        /* Eq. 11-16 */
+        const double rho2 = P->rho * P->rho, r2 = P->tr * P->tr;
+        const double kx = W / (2.0 * M_PI), ky = H / M_PI;
+        P->J[0] = kx * tz / rho2;
+        P->J[1] = 0.0;
+        P->J[2] = -kx * tx / rho2;
+        P->J[3] = -ky * tx * ty / (r2 * P->rho);
+        P->J[4] = ky * P->rho / r2;
+        P->J[5] = -ky * tz * ty / (r2 * P->rho);
+    }
     /* M = J W */
     for (int a = 0; a < 2; ++a)
         for (int k = 0; k < 3; ++k) {
@@ -288,8 +336,15 @@ static void project_one(const orc_scene *s, int64_t i, orc_proj *P) {
     if (near_int(bx0, tol + 1e-12 * P->ex) || near_int(bx1, tol + 1e-12 * P->ex) ||
         near_int(by0, tol + 1e-12 * P->ey) || near_int(by1, tol + 1e-12 * P->ey))
         P->flag = 1;
-    const double cxs = ceil(bx0), cxe = floor(bx1);
-    if (cxe - cxs + 1.0 >= W) {
+    double cxs = ceil(bx0), cxe = floor(bx1);
+    if (s->model == ORC_PINHOLE) {
+        /* no seam: columns clamp to the image */
+        if (cxs < 0.0) cxs = 0.0;
+        if (cxe > W - 1.0) cxe = W - 1.0;
+        if (cxe < cxs) return;
+        P->xs = (int64_t)cxs;
+        P->xe = (int64_t)cxe;
+    } else if (cxe - cxs + 1.0 >= W) {
         P->full_x = 1;
         P->xs = 0;
         P->xe = s->width - 1;
@@ -304,8 +359,11 @@ static void project_one(const orc_scene *s, int64_t i, orc_proj *P) {
     if (cye < cys) return;
     P->ys = (int64_t)cys;
     P->ye = (int64_t)cye;
-    const int tiles_x = s->width / ORC_TILE;
-    if (P->full_x) {
+    const int tiles_x = orc_tiles_x(s);
+    if (s->model == ORC_PINHOLE) {
+        P->tx0 = (int)(P->xs / ORC_TILE);
+        P->ntx = (int)(P->xe / ORC_TILE) - P->tx0 + 1;
+    } else if (P->full_x) {
         P->tx0 = 0;
         P->ntx = tiles_x;
     } else {
@@ -346,7 +404,7 @@ static void project_one(const orc_scene *s, int64_t i, orc_proj *P) {
 
 /* ------------------------------------------------------------------------ */
 /* Instance lists: one instance per (Gaussian, covered tile), sorted by       */
-/* (tile, t_r, Gaussian index).                                               */
+/* (tile, depth, Gaussian index); depth = t_r (ERP) or t_z (pinhole).         */
 /* ------------------------------------------------------------------------ */
 typedef struct {
     int32_t tile;
@@ -381,7 +439,7 @@ static void lists_free(orc_lists *L) {
 /* tile_mask may be NULL (all tiles) */
 static int build_lists(const orc_scene *s, const uint8_t *tile_mask, orc_lists *L) {
     memset(L, 0, sizeof(*L));
-    L->tiles_x = s->width / ORC_TILE;
+    L->tiles_x = orc_tiles_x(s);
     L->tiles_y = (s->height + ORC_TILE - 1) / ORC_TILE;
     const int64_t n = s->n, ntiles = (int64_t)L->tiles_x * L->tiles_y;
     L->P = (orc_proj *)malloc(sizeof(orc_proj) * (size_t)(n > 0 ? n : 1));
@@ -417,7 +475,7 @@ static int build_lists(const orc_scene *s, const uint8_t *tile_mask, orc_lists *
                 if (tile_mask && !tile_mask[tid]) continue;
                 L->inst[w].tile = tid;
                 L->inst[w].gid = (int32_t)i;
-                L->inst[w].tr = P->tr;
+                L->inst[w].tr = P->depth;
                 ++w;
             }
     }
@@ -474,7 +532,7 @@ static void render_pixel(const orc_scene *s, const orc_lists *L, int64_t start, 
     for (int64_t k = start; k < end; ++k) {
         const orc_inst *I = &L->inst[k];
         const orc_proj *P = &L->P[I->gid];
-        const double dx = wrap_dx((x + 0.5) - P->px, W);
+        const double dx = s->model == ORC_PINHOLE ? (x + 0.5) - P->px : wrap_dx((x + 0.5) - P->px, W);
         const double dy = (y + 0.5) - P->py;
         const double power = -0.5 * (P->Q[0] * dx * dx + 2.0 * P->Q[1] * dx * dy + P->Q[2] * dy * dy);
         const double G = exp(power);
@@ -539,13 +597,13 @@ static int64_t tile_of_pixel(const orc_lists *L, int x, int y) {
 /* ------------------------------------------------------------------------ */
 
 /* Per-Gaussian projection records for the pins.  Layout of each record (48
- * doubles): 0 visible, 1-3 t, 4 t_r, 5 lon, 6 lat, 7 px, 8 py, 9-14 J,
+ * doubles): 0 visible, 1-3 t, 4 depth (t_r or t_z), 5 lon, 6 lat, 7 px, 8 py, 9-14 J,
  * 15-17 Sigma2D (a, b, c), 18-20 Q (00, 01, 11), 21 e_x, 22 e_y, 23 xs, 24 xe,
  * 25 ys, 26 ye, 27 full_x, 28 tx0, 29 ntx, 30 ty0, 31 nty, 32 ntiles,
- * 33-35 rgb, 36-38 clamp, 39 flag, 40-42 dir, 43 det, 44-47 unused. */
+ * 33-35 rgb, 36-38 clamp, 39 flag, 40-42 dir, 43 det, 44 t_r, 45-47 unused. */
 #define ORC_REC 48
 int orc_project(const orc_scene *s, double *rec) {
-    if (s->width % ORC_TILE != 0 || s->height < 1) return -1;
+    if (!orc_valid(s)) return -1;
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < s->n; ++i) {
         orc_proj P;
@@ -554,7 +612,8 @@ int orc_project(const orc_scene *s, double *rec) {
         memset(r, 0, sizeof(double) * ORC_REC);
         r[0] = P.visible;
         for (int k = 0; k < 3; ++k) r[1 + k] = P.tc[k];
-        r[4] = P.tr;
+        r[4] = P.depth;
+        r[44] = P.tr;
         r[5] = P.lon;
         r[6] = P.lat;
         r[7] = P.px;
@@ -589,7 +648,7 @@ int orc_project(const orc_scene *s, double *rec) {
  * Returns M, or -1 on error; writes at most cap entries. */
 int64_t orc_tile_lists(const orc_scene *s, const uint8_t *tile_mask, int64_t cap, int32_t *tile_out, int32_t *gid_out,
                        double *tr_out) {
-    if (s->width % ORC_TILE != 0 || s->height < 1) return -1;
+    if (!orc_valid(s)) return -1;
     orc_lists L;
     if (build_lists(s, tile_mask, &L) != 0) {
         lists_free(&L);
@@ -614,7 +673,7 @@ int64_t orc_tile_lists(const orc_scene *s, const uint8_t *tile_mask, int64_t cap
  * instances blended into each pixel. */
 int orc_render(const orc_scene *s, const uint8_t *tile_mask, double *image, double *final_T, int32_t *n_contrib,
                int32_t *n_flags, double *alt, int32_t *n_grad_flags, int32_t *n_blended) {
-    if (s->width % ORC_TILE != 0 || s->height < 1) return -1;
+    if (!orc_valid(s)) return -1;
     orc_lists L;
     if (build_lists(s, tile_mask, &L) != 0) {
         lists_free(&L);
@@ -655,7 +714,7 @@ int orc_render(const orc_scene *s, const uint8_t *tile_mask, double *image, doub
  * validity checks). */
 int orc_l1_tiles(const orc_scene *s, const double *target, const double *weight, const uint8_t *tile_mask,
                  double *loss, uint64_t *signature) {
-    if (s->width % ORC_TILE != 0 || s->height < 1) return -1;
+    if (!orc_valid(s)) return -1;
     orc_lists L;
     if (build_lists(s, tile_mask, &L) != 0) {
         lists_free(&L);
@@ -669,7 +728,7 @@ int orc_l1_tiles(const orc_scene *s, const double *target, const double *weight,
         if (!tile_mask[t]) continue;
         const int tx = (int)(t % L.tiles_x), ty = (int)(t / L.tiles_x);
         for (int y = ty * ORC_TILE; y < ty * ORC_TILE + ORC_TILE && y < Hd; ++y)
-            for (int x = tx * ORC_TILE; x < tx * ORC_TILE + ORC_TILE; ++x) {
+            for (int x = tx * ORC_TILE; x < tx * ORC_TILE + ORC_TILE && x < Wd; ++x) {
                 orc_pixel px;
                 render_pixel(s, &L, L.tstart[t], L.tend[t], x, y, -1, &px, NULL);
                 const int64_t p = (int64_t)y * Wd + x;
@@ -693,6 +752,21 @@ int orc_l1_tiles(const orc_scene *s, const double *target, const double *weight,
 /* per-Gaussian accumulator layout: dL/dp (2), dL/dQ (00, 01, 11), dL/do,
  * dL/drgb (3) */
 #define ORC_NACC 9
+
+/* dJ_{a,j}/dt_n for the pinhole Jacobian (derivatives of the Jacobian of
+ * Eq. 2: J00 = fx / tz, J02 = -fx tx / tz^2, J11 = fy / tz,
+ * J12 = -fy ty / tz^2) */
+static void jacobian_dt_pinhole(const double t[3], double fx, double fy, double dJ[6][3]) {
+    const double tx = t[0], ty = t[1], tz = t[2];
+    const double tz2 = tz * tz, tz3 = tz2 * tz;
+    for (int e = 0; e < 6; ++e) dJ[e][0] = dJ[e][1] = dJ[e][2] = 0.0;
+    dJ[0][2] = -fx / tz2;
+    dJ[2][0] = -fx / tz2;
+    dJ[2][2] = 2.0 * fx * tx / tz3;
+    dJ[4][2] = -fy / tz2;
+    dJ[5][1] = -fy / tz2;
+    dJ[5][2] = 2.0 * fy * ty / tz3;
+}
 
 /* dJ_{a,j}/dt_n for the spherical Jacobian (derivatives of Eq. 11-16) */
 static void jacobian_dt(const double t[3], double W, double H, double dJ[6][3]) {
@@ -776,7 +850,10 @@ static void chain_one(const orc_scene *s, int64_t i, const orc_proj *P, const do
         }
     /* dL/dt: through p (J = dp/dt) and through J(t) */
     double dJdt[6][3];
-    jacobian_dt(P->tc, W, H, dJdt);
+    if (s->model == ORC_PINHOLE)
+        jacobian_dt_pinhole(P->tc, s->fx, s->fy, dJdt);
+    else
+        jacobian_dt(P->tc, W, H, dJdt);
     double gt[3];
     for (int nn = 0; nn < 3; ++nn) {
         double v = gp[0] * P->J[nn] + gp[1] * P->J[3 + nn];
@@ -850,7 +927,7 @@ static void chain_one(const orc_scene *s, int64_t i, const orc_proj *P, const do
 int orc_backward(const orc_scene *s, const uint8_t *tile_mask, const double *dLdC, double *dmeans, double *dscales,
                  double *dquats, double *dopac, double *dsh, double *dscreen, double *acc_out, double *abs_means,
                  double *abs_scales, double *abs_quats, double *abs_opac, double *abs_sh, double *abs_screen) {
-    if (s->width % ORC_TILE != 0 || s->height < 1) return -1;
+    if (!orc_valid(s)) return -1;
     orc_lists L;
     if (build_lists(s, tile_mask, &L) != 0) {
         lists_free(&L);
@@ -886,7 +963,7 @@ int orc_backward(const orc_scene *s, const uint8_t *tile_mask, const double *dLd
             if (tile_mask && !tile_mask[t]) continue;
             const int tx = (int)(t % L.tiles_x), ty = (int)(t / L.tiles_x);
             for (int y = ty * ORC_TILE; y < ty * ORC_TILE + ORC_TILE && y < Hd; ++y)
-                for (int x = tx * ORC_TILE; x < tx * ORC_TILE + ORC_TILE; ++x) {
+                for (int x = tx * ORC_TILE; x < tx * ORC_TILE + ORC_TILE && x < Wd; ++x) {
                     const int64_t p = (int64_t)y * Wd + x;
                     orc_pixel px;
                     render_pixel(s, &L, L.tstart[t], L.tend[t], x, y, -1, &px, con);

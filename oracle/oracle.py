@@ -29,9 +29,23 @@ DEFAULT_SETTINGS = dict(alpha_min=1.0 / 255.0, alpha_max=0.99, T_min=1e-4, dilat
                         bg=(0.0, 0.0, 0.0))
 
 REC = 48  # doubles per projection record
-REC_FIELDS = dict(visible=0, t=slice(1, 4), t_r=4, lon=5, lat=6, px=7, py=8, J=slice(9, 15), cov2d=slice(15, 18),
+# depth: the sort key, t_r for the ERP camera and t_z for the pinhole camera;
+# t_r: the distance to the camera centre in both
+REC_FIELDS = dict(visible=0, t=slice(1, 4), depth=4, lon=5, lat=6, px=7, py=8, J=slice(9, 15), cov2d=slice(15, 18),
                   conic=slice(18, 21), ex=21, ey=22, xs=23, xe=24, ys=25, ye=26, full_x=27, tx0=28, ntx=29, ty0=30,
-                  nty=31, ntiles=32, rgb=slice(33, 36), clamp=slice(36, 39), flag=39, dir=slice(40, 43), det=43)
+                  nty=31, ntiles=32, rgb=slice(33, 36), clamp=slice(36, 39), flag=39, dir=slice(40, 43), det=43,
+                  t_r=44)
+
+ERP, PINHOLE = 0, 1
+
+
+def camera_model(camera) -> int:
+    """0 (ERP, Eq. 3-5) or 1 (pinhole, Eq. 2) from a camera dict's "model"
+    ("erp" / "pinhole" or the number; absent: ERP)."""
+    m = camera.get("model", ERP)
+    if isinstance(m, str):
+        m = {"erp": ERP, "pinhole": PINHOLE}[m.lower()]
+    return int(m)
 
 
 def build(force: bool = False) -> str:
@@ -69,6 +83,12 @@ class _Scene(ctypes.Structure):
         ("flag_rel_T", ctypes.c_double),
         ("flag_rel_depth", ctypes.c_double),
         ("flag_abs_rect", ctypes.c_double),
+        ("model", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("fx", ctypes.c_double),
+        ("fy", ctypes.c_double),
+        ("cx", ctypes.c_double),
+        ("cy", ctypes.c_double),
     ]
 
 
@@ -113,7 +133,8 @@ class Scene:
     ``gaussians``: dict with means [N,3], scales [N,3] (activated), quats
     [N,4] (w,x,y,z), opacities [N] (activated), sh [N,K,3], sh_degree.
     ``camera``: dict with R [3,3] (world -> camera rotation), t [3], width,
-    height.
+    height; for the pinhole camera of Eq. 2 also model="pinhole", fx, fy, cx,
+    cy (pixels).
     """
 
     def __init__(self, gaussians, camera, settings=None, flags=None):
@@ -134,12 +155,22 @@ class Scene:
         self.height = int(camera["height"])
         self.R = _f64(camera["R"]).reshape(3, 3)
         self.t = _f64(camera["t"]).reshape(3)
+        self.model = camera_model(camera)
+        self.intrinsics = tuple(float(camera[k]) for k in ("fx", "fy", "cx", "cy")) if self.model == PINHOLE \
+            else (0.0, 0.0, 0.0, 0.0)
         self.settings = st
         self.flags = fl
 
     @property
     def tiles_x(self):
-        return self.width // 16
+        return (self.width + 15) // 16 if self.model == PINHOLE else self.width // 16
+
+    def camera(self, R=None, t=None):
+        cam = dict(R=self.R if R is None else R, t=self.t if t is None else t, width=self.width,
+                   height=self.height, model=self.model)
+        if self.model == PINHOLE:
+            cam.update(zip(("fx", "fy", "cx", "cy"), self.intrinsics))
+        return cam
 
     @property
     def tiles_y(self):
@@ -171,6 +202,8 @@ class Scene:
             s.bg[k] = float(st["bg"][k])
         for k, v in self.flags.items():
             setattr(s, k, float(v))
+        s.model = self.model
+        s.fx, s.fy, s.cx, s.cy = self.intrinsics
         return s
 
     def with_params(self, **kw):
@@ -178,15 +211,12 @@ class Scene:
         g = dict(means=self.means, scales=self.scales, quats=self.quats, opacities=self.opac, sh=self.sh,
                  sh_degree=self.sh_degree)
         g.update(kw)
-        cam = dict(R=self.R, t=self.t, width=self.width, height=self.height)
-        return Scene(g, cam, self.settings, self.flags)
+        return Scene(g, self.camera(), self.settings, self.flags)
 
     def with_camera(self, R=None, t=None):
         g = dict(means=self.means, scales=self.scales, quats=self.quats, opacities=self.opac, sh=self.sh,
                  sh_degree=self.sh_degree)
-        cam = dict(R=self.R if R is None else R, t=self.t if t is None else t, width=self.width,
-                   height=self.height)
-        return Scene(g, cam, self.settings, self.flags)
+        return Scene(g, self.camera(R, t), self.settings, self.flags)
 
 
 def project(scene: Scene) -> np.ndarray:
@@ -200,7 +230,7 @@ def project(scene: Scene) -> np.ndarray:
 
 
 def tile_lists(scene: Scene, tile_mask=None):
-    """Sorted instances: (tile_id int32 [M], gaussian_id int32 [M], t_r float64 [M]),
+    """Sorted instances: (tile_id int32 [M], gaussian_id int32 [M], depth float64 [M]),
     of the tiles set in ``tile_mask`` ([tiles] bool; None: all)."""
     lib = _load()
     s = scene._struct()

@@ -11,7 +11,8 @@ Parameter conventions (the library's input layout):
   quats [N,4] f32       rotation quaternion (w, x, y, z), not necessarily unit
   opacities [N] f32     activated opacity in (0, 1)
   sh [N,16,3] f32       real SH coefficients, degree <= 3, RGB innermost
-Camera: R [3,3] f64 world->camera rotation, t [3] f64, width, height (ERP).
+Camera: R [3,3] f64 world->camera rotation, t [3] f64, width, height (ERP);
+a pinhole camera (Eq. 2) adds model="pinhole", fx, fy, cx, cy (pixels).
 
 Generators use ``np.random.default_rng([config, stream])`` with streams
 0 = scene, 1 = target perturbation, 2 = poses, 3 = request stream,
@@ -122,11 +123,42 @@ def rot_y(angle: float) -> np.ndarray:
     return np.array([[c, 0.0, s], [0.0, 1.0, 0.0], [-s, 0.0, c]])
 
 
+def rot_x(angle: float) -> np.ndarray:
+    c, s = np.cos(angle), np.sin(angle)
+    return np.array([[1.0, 0.0, 0.0], [0.0, c, -s], [0.0, s, c]])
+
+
 def camera(width: int, height: int, R=None, centre=None) -> dict:
     """Camera dict from a world->camera rotation and a camera centre."""
     R = np.eye(3) if R is None else np.asarray(R, dtype=np.float64)
     c = np.zeros(3) if centre is None else np.asarray(centre, dtype=np.float64)
     return dict(R=R, t=-R @ c, width=int(width), height=int(height))
+
+
+def pinhole_camera(width: int, height: int, fov_x_deg=90.0, R=None, centre=None, fy=None, cx=None, cy=None) -> dict:
+    """Pinhole camera dict: f_x from the horizontal field of view, f_y = f_x
+    (square pixels) and the principal point at the image centre unless
+    given."""
+    cam = camera(width, height, R, centre)
+    fx = 0.5 * width / np.tan(np.radians(fov_x_deg) / 2.0)
+    cam.update(model="pinhole", fx=float(fx), fy=float(fx if fy is None else fy),
+               cx=float(0.5 * width if cx is None else cx), cy=float(0.5 * height if cy is None else cy))
+    return cam
+
+
+def crop_poses(config: int, count: int, width: int, height: int, fov_x_deg=90.0, radius=1.0):
+    """Seeded perspective crops: centre uniform in the ball of ``radius``,
+    yaw ~ U[-pi, pi), pitch ~ U[-pi/6, pi/6], world->camera rotation
+    (R_y(yaw) R_x(pitch))^T."""
+    rng = rng_for(config, STREAM_POSES, 1)
+    out = []
+    for _ in range(count):
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        c = d * radius * rng.uniform() ** (1.0 / 3.0)
+        yaw, pitch = rng.uniform(-np.pi, np.pi), rng.uniform(-np.pi / 6, np.pi / 6)
+        out.append(pinhole_camera(width, height, fov_x_deg, (rot_y(yaw) @ rot_x(pitch)).T, c))
+    return out
 
 
 def poses(config: int, count: int, width: int, height: int, radius=1.0, yaw_zero=False):

@@ -1,0 +1,283 @@
+"""Pins of the FP64 oracle's pinhole camera (Eq. 2, the perspective model the
+paper starts from; instances ordered by t_z, Sec. 3.3).
+
+Each test checks the oracle against something other than itself: the inverse
+of the projection (a point on a pixel's ray), projective invariance, finite
+differences of the oracle's own projection, closed forms of the isotropic
+footprint, the ERP model at the image centre (where the two Jacobians
+coincide), compositions of single-Gaussian renders, the independent
+brute-force renderer (including a width that is not a multiple of 16), rigid
+invariance and finite differences of the backward.  CPU only.
+"""
+import numpy as np
+import pytest
+
+from oracle import brute
+from oracle import oracle as O
+from paper_2404_03202_amd import scenes
+
+
+def _single(means, scales=0.05, opac=0.9, dc=(0.3, 0.4, 0.5), quat=(1, 0, 0, 0), sh_degree=0):
+    means = np.atleast_2d(np.asarray(means, dtype=np.float64))
+    n = means.shape[0]
+    sc = np.broadcast_to(np.asarray(scales, dtype=np.float64), (n, 3)) if np.ndim(scales) < 2 else scales
+    op = np.broadcast_to(np.asarray(opac, dtype=np.float64), (n,))
+    sh = np.zeros((n, 16, 3))
+    sh[:, 0, :] = np.broadcast_to(np.asarray(dc, dtype=np.float64), (n, 3))
+    q = np.broadcast_to(np.asarray(quat, dtype=np.float64), (n, 4))
+    return dict(means=means, scales=np.array(sc), quats=np.array(q), opacities=np.array(op), sh=sh,
+                sh_degree=sh_degree)
+
+
+def _cam(W=80, H=48, fov=70.0, **kw):
+    return scenes.pinhole_camera(W, H, fov, **kw)
+
+
+def _on_ray(x, y, cam, depth):
+    """Camera-space point at depth t_z on the ray through pixel (x, y)'s
+    centre (the inverse of the pinhole map)."""
+    return depth * np.array([(x + 0.5 - cam["cx"]) / cam["fx"], (y + 0.5 - cam["cy"]) / cam["fy"], 1.0])
+
+
+# ---------------------------------------------------------------- projection
+def test_pixel_ray_lands_on_pixel_and_peaks_there():
+    """A small Gaussian on the ray of pixel (x, y) projects to its centre at
+    any depth (projective invariance) and its rendered peak is that pixel,
+    corners and a ragged last tile column (W = 80 + 7) included."""
+    W, H = 87, 48
+    cam = _cam(W, H, fov=80.0, cx=40.3, cy=22.9, fy=55.0)
+    for x in [0, 1, 40, 63, 64, 85, 86]:
+        for y in [0, 5, 24, 47]:
+            for depth in (0.7, 3.0):
+                m = _on_ray(x, y, cam, depth)
+                sc = O.Scene(_single(m, scales=0.002 * depth), cam)
+                rec = O.project(sc)[0]
+                assert rec[0] == 1.0
+                assert rec[7] == pytest.approx(x + 0.5, abs=1e-9)
+                assert rec[8] == pytest.approx(y + 0.5, abs=1e-9)
+                assert rec[4] == pytest.approx(depth, rel=1e-15)  # sort depth = t_z
+                assert rec[44] == pytest.approx(np.linalg.norm(m), rel=1e-15)  # t_r kept
+            img = O.render(sc, alt=False)["image"][0]
+            assert np.unravel_index(np.argmax(img), img.shape) == (y, x)
+
+
+def test_near_plane_cull_uses_t_z():
+    """The pinhole camera culls t_z <= near_plane: a point far off-axis with
+    t_r > near but t_z < near is culled, one just beyond the plane is not."""
+    cam = _cam()
+    near = O.DEFAULT_SETTINGS["near_plane"]
+    rec = O.project(O.Scene(_single([[5.0, 0.0, 0.9 * near], [0.01, 0.0, 1.1 * near], [0.0, 0.0, -2.0]]), cam))
+    assert list(rec[:, 0]) == [0.0, 1.0, 0.0]
+
+
+def test_jacobian_matches_finite_differences_of_projection():
+    """The Jacobian of Eq. 2 against central differences of the oracle's own
+    projected centre (identity pose, so t = m), and of Eq. 2 retyped in the
+    brute-force module."""
+    rng = np.random.default_rng(21)
+    cam = _cam(W=640, H=480, fov=75.0, cx=301.2, cy=250.7, fy=420.0)
+    m = rng.normal(size=(24, 3)) * np.array([2.0, 1.5, 1.0]) + np.array([0, 0, 4.0])
+    rec = O.project(O.Scene(_single(m), cam))
+    h = 1e-5
+    for i in range(m.shape[0]):
+        J = rec[i, 9:15].reshape(2, 3)
+        Jfd = np.zeros((2, 3))
+        for k in range(3):
+            e = np.zeros(3)
+            e[k] = h
+            rp = O.project(O.Scene(_single(m[i] + e), cam))[0]
+            rm = O.project(O.Scene(_single(m[i] - e), cam))[0]
+            Jfd[:, k] = (rp[7:9] - rm[7:9]) / (2 * h)
+        np.testing.assert_allclose(J, Jfd, rtol=1e-7, atol=1e-7 * np.abs(J).max())
+        proj = lambda u: brute.pinhole_project(u, cam["fx"], cam["fy"], cam["cx"], cam["cy"])
+        np.testing.assert_allclose(J, brute.fd_jacobian(m[i], 0, 0, rel=1e-6, proj=proj), rtol=1e-7,
+                                   atol=1e-7 * np.abs(J).max())
+    # dp_x/dt_y = dp_y/dt_x = 0
+    assert np.all(rec[:, 10] == 0.0) and np.all(rec[:, 12] == 0.0)
+
+
+def test_isotropic_cov2d_closed_form():
+    """For Sigma = s^2 I the footprint is s^2 J J^T with J's rows
+    (f_x / t_z)(1, 0, -a) and (f_y / t_z)(0, 1, -b), a = t_x / t_z,
+    b = t_y / t_z: diag entries (f s / t_z)^2 (1 + a^2), (1 + b^2), off-diagonal
+    f_x f_y s^2 a b / t_z^2; on the axis it is diag((f_x s / t_z)^2,
+    (f_y s / t_z)^2)."""
+    rng = np.random.default_rng(22)
+    cam = _cam(W=320, H=240, fov=60.0, fy=250.0)
+    fx, fy = cam["fx"], cam["fy"]
+    for dil in (0.0, 0.3):
+        for k in range(20):
+            tz = rng.uniform(0.5, 8.0)
+            a, b = (0.0, 0.0) if k == 0 else rng.uniform(-0.6, 0.6, size=2)
+            s = rng.uniform(0.01, 0.3)
+            sc = O.Scene(_single([a * tz, b * tz, tz], scales=s, quat=rng.normal(size=4)), cam,
+                         settings=dict(dilation=dil))
+            rec = O.project(sc)[0]
+            expect = [(fx * s / tz) ** 2 * (1 + a * a) + dil, fx * fy * s * s * a * b / tz ** 2,
+                      (fy * s / tz) ** 2 * (1 + b * b) + dil]
+            np.testing.assert_allclose(rec[15:18], expect, rtol=1e-12, atol=1e-12 * expect[0])
+
+
+def test_agrees_with_erp_at_the_image_centre():
+    """With f_x = W / 2pi, f_y = H / pi and the principal point at the image
+    centre, the pinhole and ERP maps agree to first order at lon = lat = 0
+    (both Jacobians are diag(f_x, f_y) / t_z there): a Gaussian on the optical
+    axis gets the same centre, footprint, conic and tile rect in both."""
+    W, H = 256, 128
+    rng = np.random.default_rng(23)
+    erp = scenes.camera(W, H)
+    pin = scenes.pinhole_camera(W, H, fy=H / np.pi)
+    pin["fx"] = W / (2 * np.pi)
+    for _ in range(10):
+        g = _single([0.0, 0.0, rng.uniform(0.5, 6.0)], scales=rng.uniform(0.01, 0.4, size=(1, 3)),
+                    quat=rng.normal(size=4))
+        re = O.project(O.Scene(g, erp))[0]
+        rp = O.project(O.Scene(g, pin))[0]
+        for f in ("px", "py", "cov2d", "conic", "ex", "ey", "xs", "xe", "ys", "ye", "tx0", "ntx", "ty0", "nty",
+                  "depth"):
+            np.testing.assert_allclose(rp[O.REC_FIELDS[f]], re[O.REC_FIELDS[f]], rtol=1e-12, atol=1e-12, err_msg=f)
+
+
+# ------------------------------------------------------------------ blending
+def test_depth_order_is_t_z():
+    """Two overlapping Gaussians whose t_z order is the reverse of their t_r
+    order blend in t_z order (Sec. 3.3): at a pixel both reach, the pair's
+    colour is c_a alpha_a + c_b alpha_b (1 - alpha_a) with a the smaller t_z,
+    where each c alpha is that Gaussian's colour rendered alone (bg 0)."""
+    W, H = 64, 48
+    cam = _cam(W, H, fov=90.0)
+    # A: far off-axis, small t_z, large t_r; B: on axis, larger t_z, smaller t_r
+    A = np.array([2.6, 0.0, 1.6])
+    B = np.array([0.0, 0.0, 2.2])
+    assert A[2] < B[2] and np.linalg.norm(A) > np.linalg.norm(B)
+    gA = _single(A, scales=0.9, opac=0.7, dc=(1.0, 0.0, 0.0))
+    gB = _single(B, scales=0.9, opac=0.8, dc=(0.0, 1.0, 0.0))
+    both = {k: (np.concatenate([gB[k], gA[k]]) if k != "sh_degree" else 0) for k in gA}
+    ia = O.render(O.Scene(gA, cam), alt=False)
+    ib = O.render(O.Scene(gB, cam), alt=False)
+    ip = O.render(O.Scene(both, cam), alt=False)
+    sel = (ia["n_blended"] == 1) & (ib["n_blended"] == 1)
+    assert sel.sum() > 100
+    cA, cB = ia["image"], ib["image"]          # c alpha of each alone
+    aA = 1.0 - ia["final_T"]                   # alpha of each alone
+    aB = 1.0 - ib["final_T"]
+    tz_order = cA + cB * (1.0 - aA)[None]
+    tr_order = cB + cA * (1.0 - aB)[None]
+    np.testing.assert_allclose(ip["image"][:, sel], tz_order[:, sel], rtol=1e-12, atol=1e-14)
+    assert np.abs(ip["image"][:, sel] - tr_order[:, sel]).max() > 1e-2
+    # the instance lists carry t_z as depth, ordered by it
+    tile, gid, depth = O.tile_lists(O.Scene(both, cam))
+    assert set(np.unique(depth)) == {A[2], B[2]}
+    for t in np.unique(tile):
+        d = depth[tile == t]
+        assert np.all(np.diff(d) >= 0)
+
+
+@pytest.mark.parametrize("W,H", [(64, 48), (87, 41)])
+def test_tiling_equals_brute_force_exactly(W, H):
+    """With the oracle's own projection records, the brute-force blend over
+    all Gaussians (no tiles, no radius) equals the tiled oracle (to the last
+    bit of exp; the same instances blended in every pixel), also
+    with a ragged last tile column and row, Gaussians behind the camera and
+    Gaussians whose centre is off-screen."""
+    g = scenes.shell_scene(24, 300, r0=0.5, r1=6.0, scale_lo=0.02, scale_hi=0.5)
+    cam = _cam(W, H, fov=100.0, R=scenes.rot_y(0.7).T, centre=[0.1, -0.2, 0.3])
+    sc = O.Scene(g, cam)
+    rec = O.project(sc)
+    vis = rec[:, 0] > 0
+    offscreen = vis & ((rec[:, 7] < 0) | (rec[:, 7] > W) | (rec[:, 8] < 0) | (rec[:, 8] > H))
+    assert vis.sum() > 50 and offscreen.sum() > 5 and (~vis).sum() > 50
+    r = O.render(sc, alt=False)
+    img, T, nb = brute.render(sc, records=rec)
+    # numpy's exp and libm's may differ in the last bit
+    np.testing.assert_allclose(r["image"], img, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(r["final_T"], T, rtol=0, atol=1e-12)
+    np.testing.assert_array_equal(r["n_blended"], nb)
+
+
+def test_independent_projection_brute_force():
+    """The brute-force renderer with its own projection (FD Jacobian of
+    Eq. 2, scipy rotation, numpy inverse, scipy SH) agrees with the oracle."""
+    g = scenes.shell_scene(25, 150, r0=1.0, r1=5.0, scale_lo=0.02, scale_hi=0.3)
+    cam = _cam(72, 40, fov=90.0, R=scenes.rot_y(-0.4).T)
+    sc = O.Scene(g, cam)
+    r = O.render(sc, alt=False)
+    img, T, _ = brute.render(sc)
+    np.testing.assert_allclose(r["image"], img, atol=1e-6)
+    np.testing.assert_allclose(r["final_T"], T, atol=1e-6)
+
+
+def test_rigid_motion_invariance():
+    """A scene moved rigidly together with its camera renders identically
+    (degree 0; translation at any degree)."""
+    g = scenes.shell_scene(26, 200, r0=1.5, r1=6.0, scale_lo=0.05, scale_hi=0.4)
+    c0 = np.array([0.1, 0.2, -0.3])
+    R0 = scenes.rot_y(0.4).T
+    base = O.render(O.Scene(g, _cam(R=R0, centre=c0)), alt=False)["image"]
+    shift = np.array([3.0, -1.0, 2.0])
+    g2 = dict(g, means=g["means"].astype(np.float64) + shift)
+    img = O.render(O.Scene(g2, _cam(R=R0, centre=c0 + shift)), alt=False)["image"]
+    np.testing.assert_allclose(img, base, atol=1e-9)
+    g0 = dict(g, sh_degree=0)
+    base0 = O.render(O.Scene(g0, _cam(R=R0, centre=c0)), alt=False)["image"]
+    rng = np.random.default_rng(5)
+    A = np.linalg.qr(rng.normal(size=(3, 3)))[0]
+    if np.linalg.det(A) < 0:
+        A[:, 0] *= -1
+    from scipy.spatial.transform import Rotation
+    qa = Rotation.from_matrix(A)
+    q = g["quats"].astype(np.float64)
+    qr = (qa * Rotation.from_quat(q[:, [1, 2, 3, 0]])).as_quat()[:, [3, 0, 1, 2]]
+    g3 = dict(g0, means=g["means"].astype(np.float64) @ A.T, quats=qr)
+    img = O.render(O.Scene(g3, _cam(R=R0 @ A.T, centre=A @ c0)), alt=False)["image"]
+    np.testing.assert_allclose(img, base0, atol=1e-9)
+
+
+# ----------------------------------------------------------------- gradients
+def _fd_scene(seed=27):
+    g = scenes.shell_scene(seed, 60, r0=1.0, r1=3.5, scale_lo=0.05, scale_hi=0.4)
+    cam = _cam(56, 40, fov=100.0, R=scenes.rot_y(0.3).T, centre=[0.1, -0.2, 0.05])
+    return O.Scene(g, cam, settings=dict(bg=(0.05, 0.1, 0.15)))
+
+
+_ATTR = dict(means="means", scales="scales", quats="quats", opacities="opac", sh="sh")
+
+
+def _richardson(f, h):
+    d1 = (f(h) - f(-h)) / (2 * h)
+    d2 = (f(h / 2) - f(-h / 2)) / h
+    return (4 * d2 - d1) / 3
+
+
+@pytest.mark.parametrize("name,width", [("means", 3), ("scales", 3), ("quats", 4), ("opacities", 1), ("sh", 48)])
+def test_gradient_matches_finite_differences(name, width):
+    """The chain of Eq. 18-20 with the pinhole dJ/dt against central
+    differences of <G, render> for a random image-space cotangent G."""
+    sc = _fd_scene()
+    n = sc.n
+    rng = np.random.default_rng(200 + width)
+    G = rng.normal(size=(3, sc.height, sc.width))
+    b = O.backward(sc, G, with_abs=False)
+    base = getattr(sc, _ATTR[name])
+    zero = np.zeros((3, sc.height, sc.width))
+    mask = np.ones(sc.tiles_x * sc.tiles_y, np.uint8)
+    visible = np.nonzero(O.project(sc)[:, 0] > 0)[0]
+    checked = 0
+    for _ in range(60):
+        i, k = visible[rng.integers(len(visible))], rng.integers(width)
+
+        def perturbed_scene(d):
+            a = base.copy()
+            a.reshape(n, -1)[i, k] += d
+            return sc.with_params(**{name: a})
+
+        h = 1e-4
+        if len({O.l1_tiles(perturbed_scene(d), zero, mask)[1] for d in (h, -h, h / 2, -h / 2)}) != 1:
+            continue
+        fd = _richardson(lambda d: float((O.render(perturbed_scene(d), alt=False)["image"] * G).sum()), h)
+        an = b[name].reshape(n, -1)[i, k]
+        assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-3), (name, i, k, an, fd)
+        checked += 1
+        if checked == 6:
+            break
+    assert checked == 6
