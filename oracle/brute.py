@@ -7,7 +7,8 @@ pass, used to pin the tiled C oracle:
   (depth, index) order (Eq. 6 and the depth criterion of Sec. 3.3: t_r for
   the ERP camera, t_z for the pinhole camera of Eq. 2);
 * the Jacobian of Eq. 10 is taken by central finite differences of the
-  projection (Eqs. 3-5, or Eq. 2) instead of closed forms;
+  projection (Eqs. 3-5, or Eq. 2 at the guarded direction) instead of closed
+  forms;
 * the rotation comes from scipy's quaternion conversion, the inverse 2D
   covariance from ``numpy.linalg.inv``;
 * the SH basis comes from scipy's complex spherical harmonics
@@ -48,6 +49,19 @@ def erp_project(t, W, H):
 def pinhole_project(t, fx, fy, cx, cy):
     """Eq. 2: camera-space point -> pinhole pixel coordinates (x, y)."""
     return np.stack([fx * t[..., 0] / t[..., 2] + cx, fy * t[..., 1] / t[..., 2] + cy], axis=-1)
+
+
+def pinhole_guard(t, W, H, fx, fy, cx, cy):
+    """The point at which the pinhole Jacobian is taken: t with its direction
+    t_x / t_z, t_y / t_z clamped to 1.3 times the image's angular half-extent
+    around the image's middle (3DGS's guard), at the same t_z."""
+    lo_x, hi_x = (0.0 - cx) / fx, (W - cx) / fx
+    lo_y, hi_y = (0.0 - cy) / fy, (H - cy) / fy
+    mx, hx = 0.5 * (lo_x + hi_x), 0.65 * (hi_x - lo_x)
+    my, hy = 0.5 * (lo_y + hi_y), 0.65 * (hi_y - lo_y)
+    a = np.clip(t[0] / t[2], mx - hx, mx + hx)
+    b = np.clip(t[1] / t[2], my - hy, my + hy)
+    return np.array([a * t[2], b * t[2], t[2]])
 
 
 def fd_jacobian(t, W, H, rel=1e-6, proj=None):
@@ -100,7 +114,7 @@ def project_independent(scene):
                 continue
             proj = lambda u: pinhole_project(u, *scene.intrinsics)
             p = proj(t)
-            J = fd_jacobian(t, W, H, proj=proj)
+            J = fd_jacobian(pinhole_guard(t, W, H, *scene.intrinsics), W, H, proj=proj)
             depth = t[2]
         else:
             if tr <= st["near_plane"] or o <= st["alpha_min"] or rho <= 1e-6 * tr:

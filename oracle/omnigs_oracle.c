@@ -47,8 +47,12 @@
  *     centre to m, plus 1/2, clamped below at 0.
  *   - gradient is taken w.r.t. activated scales and opacities, the raw
  *     quaternion (normalised inside), means and SH coefficients.
- *   - pinhole camera: J is the exact derivative of Eq. 2 at the Gaussian's
- *     centre (no clamping of t_x / t_z); Gaussians with t_z <= near_plane are
+ *   - pinhole camera: J is the derivative of Eq. 2 evaluated at the
+ *     Gaussian's direction with t_x / t_z and t_y / t_z clamped to 1.3 times
+ *     the image's angular half-extent around its middle (3DGS's guard against
+ *     the affine approximation's blow-up near the image plane; p itself is not
+ *     clamped, and J's derivative is that of the clamped function);
+ *     Gaussians with t_z <= near_plane are
  *     culled; the depth order is (t_z, index); pixel (x, y) samples at
  *     (x + 1/2, y + 1/2); nothing wraps: columns clamp like rows, and the
  *     width need not be a multiple of 16 (the last tile column is ragged);
@@ -211,8 +215,11 @@ typedef struct {
     int visible;
     double tc[3], tr, rho;
     double depth;      /* sort key: t_r (ERP) or t_z (pinhole) */
+    double dir_c[2];   /* pinhole: t_x / t_z, t_y / t_z after clamping */
+    int clamped[2];    /* pinhole: whether each was clamped */
     double lon, lat, px, py;
     double J[6];       /* 2x3, row-major (third row of Eq. 10 is zero) */
+    double Jp[6];      /* dp/dt: J itself, except for a guarded pinhole direction */
     double M[6];       /* J W, 2x3 */
     double qn[4], qnorm, Rq[9];
     double Sig[9];     /* 3D covariance */
@@ -255,13 +262,25 @@ static void project_one(const orc_scene *s, int64_t i, orc_proj *P) {
         /* Eq. 2 */
         P->px = s->fx * tx / tz + s->cx;
         P->py = s->fy * ty / tz + s->cy;
-        /* its Jacobian d p / d t */
+        /* its Jacobian d p / d t, at the direction clamped to 1.3 x the
+         * image's angular half-extent around its middle */
+        const double ax = tx / tz, ay = ty / tz;
+        const double mx = (0.5 * W - s->cx) / s->fx, hx = 1.3 * 0.5 * W / s->fx;
+        const double my = (0.5 * H - s->cy) / s->fy, hy = 1.3 * 0.5 * H / s->fy;
+        P->dir_c[0] = ax < mx - hx ? mx - hx : (ax > mx + hx ? mx + hx : ax);
+        P->dir_c[1] = ay < my - hy ? my - hy : (ay > my + hy ? my + hy : ay);
+        P->clamped[0] = P->dir_c[0] != ax;
+        P->clamped[1] = P->dir_c[1] != ay;
         P->J[0] = s->fx / tz;
         P->J[1] = 0.0;
-        P->J[2] = -s->fx * tx / (tz * tz);
+        P->J[2] = -s->fx * P->dir_c[0] / tz;
         P->J[3] = 0.0;
         P->J[4] = s->fy / tz;
-        P->J[5] = -s->fy * ty / (tz * tz);
+        P->J[5] = -s->fy * P->dir_c[1] / tz;
+        /* the centre itself moves with the unclamped derivative of Eq. 2 */
+        for (int k = 0; k < 6; ++k) P->Jp[k] = P->J[k];
+        P->Jp[2] = -s->fx * ax / tz;
+        P->Jp[5] = -s->fy * ay / tz;
     } else {
         /* culling: behind the near sphere, too transparent to ever pass
          * alpha_min, or on the polar axis where Eq. 11-16 diverge */
@@ -285,6 +304,7 @@ static void project_one(const orc_scene *s, int64_t i, orc_proj *P) {
         P->J[3] = -ky * tx * ty / (r2 * P->rho);
         P->J[4] = ky * P->rho / r2;
         P->J[5] = -ky * tz * ty / (r2 * P->rho);
+        for (int k = 0; k < 6; ++k) P->Jp[k] = P->J[k];
     }
     /* M = J W */
     for (int a = 0; a < 2; ++a)
@@ -753,19 +773,28 @@ int orc_l1_tiles(const orc_scene *s, const double *target, const double *weight,
  * dL/drgb (3) */
 #define ORC_NACC 9
 
-/* dJ_{a,j}/dt_n for the pinhole Jacobian (derivatives of the Jacobian of
- * Eq. 2: J00 = fx / tz, J02 = -fx tx / tz^2, J11 = fy / tz,
- * J12 = -fy ty / tz^2) */
-static void jacobian_dt_pinhole(const double t[3], double fx, double fy, double dJ[6][3]) {
-    const double tx = t[0], ty = t[1], tz = t[2];
-    const double tz2 = tz * tz, tz3 = tz2 * tz;
+/* dJ_{a,j}/dt_n for the pinhole Jacobian J00 = fx / tz, J02 = -fx a / tz,
+ * J11 = fy / tz, J12 = -fy b / tz with a = t_x / t_z, b = t_y / t_z, each
+ * clamped: a clamped direction is constant in t */
+static void jacobian_dt_pinhole(const orc_proj *P, double fx, double fy, double dJ[6][3]) {
+    const double tz = P->tc[2], tz2 = tz * tz;
     for (int e = 0; e < 6; ++e) dJ[e][0] = dJ[e][1] = dJ[e][2] = 0.0;
     dJ[0][2] = -fx / tz2;
-    dJ[2][0] = -fx / tz2;
-    dJ[2][2] = 2.0 * fx * tx / tz3;
     dJ[4][2] = -fy / tz2;
-    dJ[5][1] = -fy / tz2;
-    dJ[5][2] = 2.0 * fy * ty / tz3;
+    /* J02: d/dt_x (-fx t_x / t_z^2) = -fx / t_z^2, d/dt_z = 2 fx t_x / t_z^3;
+     * clamped: d/dt_z (-fx a / t_z) = fx a / t_z^2 */
+    if (P->clamped[0]) {
+        dJ[2][2] = fx * P->dir_c[0] / tz2;
+    } else {
+        dJ[2][0] = -fx / tz2;
+        dJ[2][2] = 2.0 * fx * P->tc[0] / (tz2 * tz);
+    }
+    if (P->clamped[1]) {
+        dJ[5][2] = fy * P->dir_c[1] / tz2;
+    } else {
+        dJ[5][1] = -fy / tz2;
+        dJ[5][2] = 2.0 * fy * P->tc[1] / (tz2 * tz);
+    }
 }
 
 /* dJ_{a,j}/dt_n for the spherical Jacobian (derivatives of Eq. 11-16) */
@@ -848,15 +877,15 @@ static void chain_one(const orc_scene *s, int64_t i, const orc_proj *P, const do
             for (int k = 0; k < 3; ++k) v += gM[3 * a + k] * s->R[3 * ii + k];
             gJ[3 * a + ii] = v;
         }
-    /* dL/dt: through p (J = dp/dt) and through J(t) */
+    /* dL/dt: through p (dp/dt) and through J(t) */
     double dJdt[6][3];
     if (s->model == ORC_PINHOLE)
-        jacobian_dt_pinhole(P->tc, s->fx, s->fy, dJdt);
+        jacobian_dt_pinhole(P, s->fx, s->fy, dJdt);
     else
         jacobian_dt(P->tc, W, H, dJdt);
     double gt[3];
     for (int nn = 0; nn < 3; ++nn) {
-        double v = gp[0] * P->J[nn] + gp[1] * P->J[3 + nn];
+        double v = gp[0] * P->Jp[nn] + gp[1] * P->Jp[3 + nn];
         for (int e = 0; e < 6; ++e) v += gJ[e] * dJdt[e][nn];
         gt[nn] = v;
     }

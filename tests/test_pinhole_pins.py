@@ -72,26 +72,51 @@ def test_near_plane_cull_uses_t_z():
 
 def test_jacobian_matches_finite_differences_of_projection():
     """The Jacobian of Eq. 2 against central differences of the oracle's own
-    projected centre (identity pose, so t = m), and of Eq. 2 retyped in the
-    brute-force module."""
+    projected centre (identity pose, so t = m) inside the field-of-view
+    guard; outside it, the Jacobian is the one at the guarded direction (the
+    same t_z), and is constant along t_x or t_y where that component is
+    clamped."""
     rng = np.random.default_rng(21)
-    cam = _cam(W=640, H=480, fov=75.0, cx=301.2, cy=250.7, fy=420.0)
-    m = rng.normal(size=(24, 3)) * np.array([2.0, 1.5, 1.0]) + np.array([0, 0, 4.0])
+    W, H = 640, 480
+    cam = _cam(W=W, H=H, fov=75.0, cx=301.2, cy=250.7, fy=420.0)
+    intr = (cam["fx"], cam["fy"], cam["cx"], cam["cy"])
+    m = rng.normal(size=(40, 3)) * np.array([3.0, 2.5, 1.0]) + np.array([0, 0, 4.0])
     rec = O.project(O.Scene(_single(m), cam))
     h = 1e-5
-    for i in range(m.shape[0]):
-        J = rec[i, 9:15].reshape(2, 3)
+
+    def J_of(p):
+        return O.project(O.Scene(_single(p), cam))[0, 9:15].reshape(2, 3)
+
+    def fd(p):
         Jfd = np.zeros((2, 3))
         for k in range(3):
             e = np.zeros(3)
             e[k] = h
-            rp = O.project(O.Scene(_single(m[i] + e), cam))[0]
-            rm = O.project(O.Scene(_single(m[i] - e), cam))[0]
-            Jfd[:, k] = (rp[7:9] - rm[7:9]) / (2 * h)
-        np.testing.assert_allclose(J, Jfd, rtol=1e-7, atol=1e-7 * np.abs(J).max())
-        proj = lambda u: brute.pinhole_project(u, cam["fx"], cam["fy"], cam["cx"], cam["cy"])
-        np.testing.assert_allclose(J, brute.fd_jacobian(m[i], 0, 0, rel=1e-6, proj=proj), rtol=1e-7,
-                                   atol=1e-7 * np.abs(J).max())
+            Jfd[:, k] = (O.project(O.Scene(_single(p + e), cam))[0, 7:9] -
+                         O.project(O.Scene(_single(p - e), cam))[0, 7:9]) / (2 * h)
+        return Jfd
+
+    inside = outside = 0
+    for i in range(m.shape[0]):
+        J = rec[i, 9:15].reshape(2, 3)
+        g = brute.pinhole_guard(m[i], W, H, *intr)
+        clamped = np.abs(g - m[i]) > 1e-12 * np.abs(m[i])
+        if not clamped.any():
+            inside += 1
+            np.testing.assert_allclose(J, fd(m[i]), rtol=1e-7, atol=1e-7 * np.abs(J).max())
+            proj = lambda u: brute.pinhole_project(u, *intr)
+            np.testing.assert_allclose(J, brute.fd_jacobian(m[i], 0, 0, rel=1e-6, proj=proj), rtol=1e-7,
+                                       atol=1e-7 * np.abs(J).max())
+        else:
+            outside += 1
+            np.testing.assert_allclose(J, fd(g), rtol=1e-7, atol=1e-7 * np.abs(J).max())
+            np.testing.assert_allclose(J, J_of(g), rtol=1e-13, atol=1e-13 * np.abs(J).max())
+            for k in range(2):
+                if clamped[k]:  # clamped component: J does not move with it
+                    e = np.zeros(3)
+                    e[k] = 0.1 * abs(m[i][k])
+                    np.testing.assert_allclose(J_of(m[i] + e * np.sign(m[i][k])), J, rtol=1e-13)
+    assert inside >= 10 and outside >= 10, (inside, outside)
     # dp_x/dt_y = dp_y/dt_x = 0
     assert np.all(rec[:, 10] == 0.0) and np.all(rec[:, 12] == 0.0)
 
@@ -180,7 +205,7 @@ def test_tiling_equals_brute_force_exactly(W, H):
     bit of exp; the same instances blended in every pixel), also
     with a ragged last tile column and row, Gaussians behind the camera and
     Gaussians whose centre is off-screen."""
-    g = scenes.shell_scene(24, 300, r0=0.5, r1=6.0, scale_lo=0.02, scale_hi=0.5)
+    g = scenes.shell_scene(24, 800, r0=0.5, r1=6.0, scale_lo=0.02, scale_hi=0.5)
     cam = _cam(W, H, fov=100.0, R=scenes.rot_y(0.7).T, centre=[0.1, -0.2, 0.3])
     sc = O.Scene(g, cam)
     rec = O.project(sc)
@@ -281,3 +306,39 @@ def test_gradient_matches_finite_differences(name, width):
         if checked == 6:
             break
     assert checked == 6
+
+
+def test_mean_gradient_of_guarded_gaussians():
+    """For Gaussians whose direction is clamped by the field-of-view guard
+    (their Jacobian is taken at the guarded direction), the mean gradient
+    still matches central differences of <G, render>."""
+    g = scenes.shell_scene(28, 400, r0=0.4, r1=2.5, scale_lo=0.1, scale_hi=0.5)
+    cam = _cam(48, 40, fov=70.0, R=scenes.rot_y(0.9).T)
+    sc = O.Scene(g, cam)
+    rec = O.project(sc)
+    intr = (cam["fx"], cam["fy"], cam["cx"], cam["cy"])
+    t = rec[:, 1:4]
+    guarded = [i for i in np.nonzero(rec[:, 0] > 0)[0]
+               if np.any(np.abs(brute.pinhole_guard(t[i], 48, 40, *intr) - t[i]) > 1e-9 * np.abs(t[i]))]
+    assert len(guarded) >= 6
+    rng = np.random.default_rng(29)
+    G = rng.normal(size=(3, sc.height, sc.width))
+    b = O.backward(sc, G, with_abs=False)
+    zero = np.zeros((3, sc.height, sc.width))
+    mask = np.ones(sc.tiles_x * sc.tiles_y, np.uint8)
+    checked = 0
+    for i in guarded:
+        for k in range(3):
+            def scene_at(d):
+                a = sc.means.copy()
+                a[i, k] += d
+                return sc.with_params(means=a)
+
+            h = 1e-4
+            if len({O.l1_tiles(scene_at(d), zero, mask)[1] for d in (h, -h, h / 2, -h / 2)}) != 1:
+                continue
+            fd = _richardson(lambda d: float((O.render(scene_at(d), alt=False)["image"] * G).sum()), h)
+            an = b["means"][i, k]
+            assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-3), (i, k, an, fd)
+            checked += 1
+    assert checked >= 12
