@@ -69,13 +69,28 @@ typedef struct {
     int32_t sh_coeffs;      /* stored coefficients per Gaussian: (D+1)^2 <= it <= 16 */
 } omnigs_gaussians;
 
+/* Camera models. */
+#define OMNIGS_CAMERA_ERP 0     /* equirectangular image of Eq. 3-5 (the paper's) */
+#define OMNIGS_CAMERA_PINHOLE 1 /* perspective image of Eq. 2 (perspective crops) */
+
 /* Camera pose T_cw of Eq. 1 (host, float64): t = R_cw m + t_cw, camera axes
- * +X right, +Y down, +Z forward (Fig. 2); the X-Z plane is the equator. */
+ * +X right, +Y down, +Z forward (Fig. 2); for the ERP camera the X-Z plane is
+ * the equator.  A zero-initialised model selects the ERP camera.
+ *   ERP:     width a multiple of 16 (the seam wraps whole tile columns);
+ *            Gaussians ordered by t_r; the fx..cy fields are ignored.
+ *   PINHOLE: p = (fx t_x / t_z + cx, fy t_y / t_z + cy) (Eq. 2), pixel (x, y)
+ *            sampled at (x + 1/2, y + 1/2); any width (the last tile column
+ *            may be partial); Gaussians ordered by t_z; t_z <= near_plane
+ *            culled; fx, fy > 0 and cx, cy finite (pixels).
+ * OMNIGS_ERR_INVALID for an unknown model, reserved != 0 or bad intrinsics. */
 typedef struct {
     double R_cw[9]; /* row-major rotation W of Eq. 1 */
     double t_cw[3];
-    int32_t width;  /* ERP image W, multiple of 16 */
-    int32_t height; /* ERP image H */
+    int32_t width;  /* image W, <= 65520 */
+    int32_t height; /* image H, <= 65520 */
+    int32_t model;  /* OMNIGS_CAMERA_ERP or OMNIGS_CAMERA_PINHOLE */
+    int32_t reserved; /* 0 */
+    double fx, fy, cx, cy; /* pinhole intrinsics of Eq. 2 */
 } omnigs_camera;
 
 /* Rasterisation settings (host).  The paper fixes the stop threshold (Sec.

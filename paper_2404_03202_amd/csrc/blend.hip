@@ -12,7 +12,9 @@
 // LDS (each lane gathers one 48-byte record); positions are made
 // tile-relative from the record's hi/lo split, so pixel offsets keep full
 // precision at any width.  The x offset is the shortest signed offset on the
-// circle of circumference W (the longitude seam).
+// circle of circumference W (the longitude seam of the ERP image; a pinhole
+// image sets the period to infinity, so nothing wraps).  Pixels past the
+// image's right or bottom edge (partial last tiles) never blend.
 //
 // The lane that stages an instance also tests which quadrants its
 // alpha >= alpha_min ellipse can reach (the exact minimum of the quadratic
@@ -48,13 +50,13 @@
 namespace omnigs {
 namespace {
 
-constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kLn2 = 0.69314718055994531f;
 constexpr int kQuads = 4;  // 8x8 quadrants per tile
 
 struct BlendFrame {
     int width, height, tiles_x, tiles_y;
     uint32_t tile_base;
+    float period;  // x wrap period: the width (ERP) or +infinity (pinhole)
     float *image;
     float *final_T;
     int32_t *n_contrib;
@@ -75,9 +77,9 @@ __device__ inline int find_frame(const FrameTable &T, uint32_t tile) {
 }
 
 // Staged instances (LDS):
-//   a = (x, y, c00, c01), b = (c11, o, r, g), c = b, quad = quadrant mask
-// with (x, y) the centre relative to the tile origin and the conic
-// pre-scaled for a base-2 exponent: c00 dx^2 + c01 dx dy + c11 dy^2 =
+//   a = (x, y, l00, l10), b = (l11, o, r, g), c = b, quad = quadrant mask
+// with (x, y) the centre relative to the tile origin and L the record's
+// scaled Cholesky factor of the conic: -(l00 dx + l10 dy)^2 - (l11 dy)^2 =
 // log2(e) * (-1/2 d^T Q d).  list[w] holds, for wave w, the staged slots
 // that reach one of its quadrants, in order, as slot | (wave mask << 8).
 template <int kW>
@@ -90,25 +92,29 @@ struct Stage {
     uint16_t list[kW][kBatch];
 };
 
-// Minimum of q(u, v) = qa u^2 + 2 qb u v + qc v^2 (positive definite) over
-// the rectangle [u0, u1] x [v0, v1]: zero if it holds the origin, else the
-// least of the four edges' clamped one-dimensional minima (ra = 1/qa,
-// rc = 1/qc).
-__device__ inline float rect_min_quadratic(float qa, float qb, float qc, float ra, float rc, float u0, float u1,
-                                           float v0, float v1) {
+// Minimum of q(u, v) = (l00 u + l10 v)^2 + (l11 v)^2 (positive definite)
+// over the rectangle [u0, u1] x [v0, v1]: zero if it holds the origin, else
+// the least of the four edges' clamped one-dimensional minima.  The clamp
+// points use the expanded coefficients qa = l00^2, qb = l00 l10,
+// qc = l10^2 + l11^2 (ra = 1/qa, rc = 1/qc); q itself is evaluated as two
+// squares, which stays accurate when the expanded terms would cancel.
+__device__ inline float rect_min_quadratic(float l00, float l10, float l11, float qb, float ra, float rc, float u0,
+                                           float u1, float v0, float v1) {
     if (u0 <= 0.0f && u1 >= 0.0f && v0 <= 0.0f && v1 >= 0.0f) return 0.0f;
+    auto q = [&](float u, float v) {
+        const float s = __builtin_fmaf(l10, v, l00 * u), t = l11 * v;
+        return __builtin_fmaf(s, s, t * t);
+    };
     float best = __builtin_huge_valf();
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
         const float u = e ? u1 : u0;
-        const float v = fminf(fmaxf(-qb * u * rc, v0), v1);
-        best = fminf(best, qa * u * u + 2.0f * qb * u * v + qc * v * v);
+        best = fminf(best, q(u, fminf(fmaxf(-qb * u * rc, v0), v1)));
     }
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
         const float v = e ? v1 : v0;
-        const float u = fminf(fmaxf(-qb * v * ra, u0), u1);
-        best = fminf(best, qa * u * u + 2.0f * qb * u * v + qc * v * v);
+        best = fminf(best, q(fminf(fmaxf(-qb * v * ra, u0), u1), v));
     }
     return best;
 }
@@ -125,14 +131,14 @@ __device__ inline void stage(const BlendRecord *rec, uint32_t gid, float X0, flo
     const float half = 0.5f * W;
     if (x - 8.0f >= half) x -= W;
     if (x - 8.0f < -half) x += W;
-    const float c00 = -0.5f * kLog2e * rb4.x, c01 = -kLog2e * rb4.y, c11 = -0.5f * kLog2e * rb4.z;
+    const float l00 = rb4.x, l10 = rb4.y, l11 = rb4.z;
     // quadrants the alpha >= alpha_min region can reach:
-    // -(c00 u^2 + c01 u v + c11 v^2) <= log2(o / alpha_min), with a margin;
-    // the clamped edge minima only need to be near-exact: a slightly wrong
-    // clamp point still bounds the minimum over an edge from above, and the
-    // margin absorbs the rounding
+    // |L^T (u, v)|^2 <= log2(o / alpha_min), with a margin; the clamped edge
+    // minima only need to be near-exact: a slightly wrong clamp point still
+    // bounds the minimum over an edge from above, and the margin absorbs the
+    // rounding
     const float reach = rc4.w + 1e-3f * (1.0f + fabsf(rc4.w));
-    const float qa = -c00, qb = -0.5f * c01, qc = -c11;
+    const float qa = l00 * l00, qb = l00 * l10, qc = __builtin_fmaf(l10, l10, l11 * l11);
     const float ra = __builtin_amdgcn_rcpf(qa), rc = __builtin_amdgcn_rcpf(qc);
     uint32_t quad = 0;
 #pragma unroll
@@ -142,10 +148,10 @@ __device__ inline void stage(const BlendRecord *rec, uint32_t gid, float X0, flo
         const float v0 = qy + 0.5f - y, v1 = qy + 7.5f - y;
         // offsets that the seam wrap may shift: keep the quadrant
         const bool wraps = u0 < -half || u1 >= half;
-        if (wraps || rect_min_quadratic(qa, qb, qc, ra, rc, u0, u1, v0, v1) <= reach) quad |= 1u << k;
+        if (wraps || rect_min_quadratic(l00, l10, l11, qb, ra, rc, u0, u1, v0, v1) <= reach) quad |= 1u << k;
     }
-    S.a[slot] = make_float4(x, y, c00, c01);
-    S.b[slot] = make_float4(c11, rb4.w, rc4.x, rc4.y);
+    S.a[slot] = make_float4(x, y, l00, l10);
+    S.b[slot] = make_float4(l11, rb4.w, rc4.x, rc4.y);
     S.c[slot] = rc4.z;
     S.quad[slot] = quad;
     S.gid[slot] = gid;
@@ -170,16 +176,15 @@ __device__ inline int compact(Stage<kW> &S, int w, int lo, int nb) {
 
 // alpha at one pixel: returns the unclamped alpha, writes the clamped one,
 // G = exp(-1/2 d^T Q d) and the pixel offset (x wrapped across the seam).
-__device__ __forceinline__ float pixel_alpha(float fx, float fy, float4 a, float c11, float o, float W, float half,
+__device__ __forceinline__ float pixel_alpha(float fx, float fy, float4 a, float l11, float o, float W, float half,
                                              float alpha_max, float &alpha, float &G, float &dx, float &dy) {
     float d = fx - a.x;
     d = (d >= half) ? d - W : d;
     d = (d < -half) ? d + W : d;
     dx = d;
     dy = fy - a.y;
-    const float t = __builtin_fmaf(a.w, dy, a.z * dx);
-    const float p2 = __builtin_fmaf(c11 * dy, dy, dx * t);
-    G = __builtin_amdgcn_exp2f(p2);
+    const float u = __builtin_fmaf(a.w, dy, a.z * dx), v = l11 * dy;  // L^T d
+    G = __builtin_amdgcn_exp2f(-__builtin_fmaf(u, u, v * v));
     const float araw = o * G;
     alpha = araw < alpha_max ? araw : alpha_max;
     return araw;
@@ -207,7 +212,7 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_forward(FrameTable FT, con
     const int tx = lt % F.tiles_x, ty = lt / F.tiles_x;
     const int w = threadIdx.x / kWave, lane = __lane_id();
     const int lx = lane & 7, ly = lane >> 3;
-    const float W = (float)F.width, half = 0.5f * W;
+    const float W = F.period, half = 0.5f * W;
     const float X0 = (float)(tx * kTile), Y0 = (float)(ty * kTile);
     const uint2 range = ranges[tile];
     const int count = (int)(range.y - range.x);
@@ -219,7 +224,8 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_forward(FrameTable FT, con
         T[k] = 1.0f;
         C0[k] = C1[k] = C2[k] = 0.0f;
         last[k] = blended[k] = 0;
-        if (ty * kTile + slot_py<kW>(w, k, ly) >= F.height) done |= 1u << k;
+        if (ty * kTile + slot_py<kW>(w, k, ly) >= F.height || tx * kTile + slot_px<kW>(w, k, lx) >= F.width)
+            done |= 1u << k;
     }
     for (int base = 0; base < count; base += kBatch) {
         if (__syncthreads_count(done == kAll) == kNT) break;
@@ -273,9 +279,9 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_forward(FrameTable FT, con
     const int64_t HW = (int64_t)F.width * F.height;
 #pragma unroll
     for (int k = 0; k < kPPL; ++k) {
-        const int y = ty * kTile + slot_py<kW>(w, k, ly);
-        if (y >= F.height) continue;
-        const int64_t p = (int64_t)y * F.width + tx * kTile + slot_px<kW>(w, k, lx);
+        const int y = ty * kTile + slot_py<kW>(w, k, ly), x = tx * kTile + slot_px<kW>(w, k, lx);
+        if (y >= F.height || x >= F.width) continue;
+        const int64_t p = (int64_t)y * F.width + x;
         F.image[p] = __builtin_fmaf(T[k], s.bg[0], C0[k]);
         F.image[HW + p] = __builtin_fmaf(T[k], s.bg[1], C1[k]);
         F.image[2 * HW + p] = __builtin_fmaf(T[k], s.bg[2], C2[k]);
@@ -333,7 +339,7 @@ template <int kW, bool kBatched>
 __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, const BlendRecord *rec,
                                                                 const uint32_t *inst_gauss, const uint2 *ranges,
                                                                 BlendSettings s, float *acc, const uint32_t *order) {
-    constexpr int kNT = kWave * kW, kPPL = kQuads / kW, kBatch = Stage<kW>::kBatch;
+    constexpr int kPPL = kQuads / kW, kBatch = Stage<kW>::kBatch;
     __shared__ Stage<kW> S;
     __shared__ float part[kBatch][kAcc];
     __shared__ int s_max[kW];
@@ -344,7 +350,7 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, co
     const int tx = lt % F.tiles_x, ty = lt / F.tiles_x;
     const int w = threadIdx.x / kWave, lane = __lane_id();
     const int lx = lane & 7, ly = lane >> 3;
-    const float W = (float)F.width, half = 0.5f * W;
+    const float W = F.period, half = 0.5f * W;
     const float X0 = (float)(tx * kTile), Y0 = (float)(ty * kTile);
     const uint2 range = ranges[tile];
     const int64_t HW = (int64_t)F.width * F.height;
@@ -353,12 +359,12 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, co
     int wmax = 0;
 #pragma unroll
     for (int k = 0; k < kPPL; ++k) {
-        const int y = ty * kTile + slot_py<kW>(w, k, ly);
+        const int y = ty * kTile + slot_py<kW>(w, k, ly), x = tx * kTile + slot_px<kW>(w, k, lx);
         T[k] = 1.0f;
         dL0[k] = dL1[k] = dL2[k] = 0.0f;
         last[k] = 0;
-        if (y < F.height) {
-            const int64_t p = (int64_t)y * F.width + tx * kTile + slot_px<kW>(w, k, lx);
+        if (y < F.height && x < F.width) {
+            const int64_t p = (int64_t)y * F.width + x;
             T[k] = F.final_T[p];
             last[k] = F.n_contrib[p];
             dL0[k] = F.dL[p];
@@ -454,9 +460,11 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, co
             float mo[kAcc];
 #pragma unroll
             for (int f = 0; f < kAcc; ++f) mo[f] = part[j][f];
-            // conic back to Q: q00 = -2 ln2 c00, q01 = -ln2 c01, q11 = -2 ln2 c11
+            // Q = 2 ln2 L L^T (L scaled by sqrt(log2(e) / 2))
             const float4 a = S.a[j], b = S.b[j];
-            const float q00 = -2.0f * kLn2 * a.z, q01 = -kLn2 * a.w, q11 = -2.0f * kLn2 * b.x;
+            const float l00 = a.z, l10 = a.w, l11 = b.x;
+            const float q00 = 2.0f * kLn2 * l00 * l00, q01 = 2.0f * kLn2 * l00 * l10,
+                        q11 = 2.0f * kLn2 * __builtin_fmaf(l10, l10, l11 * l11);
             float out[kAcc];
             out[0] = q00 * mo[0] + q01 * mo[1];  // dL/dp_x
             out[1] = q01 * mo[0] + q11 * mo[1];  // dL/dp_y
@@ -523,6 +531,8 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(const uint2 *range
     for (uint32_t t = threadIdx.x; t < ntiles; t += kOrderThreads) order[atomicAdd(&cnt[bucket(t)], 1u)] = t;
 }
 
+float period_of(const FrameGeom &f) { return f.wrap ? (float)f.width : __builtin_huge_valf(); }
+
 }  // namespace
 
 hipError_t launch_tile_order(const uint2 *ranges, const uint32_t *work, uint32_t ntiles, uint32_t *order,
@@ -538,7 +548,8 @@ hipError_t launch_blend_forward(const FrameGeom &f, const BlendRecord *rec, cons
                                 hipStream_t st) {
     FrameTable T{};
     T.n = 1;
-    T.f[0] = BlendFrame{f.width, f.height, f.tiles_x, f.tiles_y, 0u, image, final_T, n_contrib, n_blended, nullptr};
+    T.f[0] = BlendFrame{f.width, f.height, f.tiles_x, f.tiles_y, 0u, period_of(f), image, final_T, n_contrib,
+                        n_blended, nullptr};
     const unsigned tiles = (unsigned)(f.tiles_x * f.tiles_y);
     if (tiles == 0) return hipSuccess;
     constexpr int kW = OMNIGS_FWD_WAVES;
@@ -557,8 +568,8 @@ hipError_t launch_blend_forward_frames(const FrameGeom *frames, const omnigs_ima
     T.n = count;
     for (int k = 0; k < count; ++k) {
         const FrameGeom &f = frames[k];
-        T.f[k] = BlendFrame{f.width, f.height, f.tiles_x, f.tiles_y, f.tile_base, outs[k].image, outs[k].final_T,
-                            outs[k].n_contrib, outs[k].n_blended, nullptr};
+        T.f[k] = BlendFrame{f.width, f.height, f.tiles_x, f.tiles_y, f.tile_base, period_of(f), outs[k].image,
+                            outs[k].final_T, outs[k].n_contrib, outs[k].n_blended, nullptr};
     }
     constexpr int kW = OMNIGS_FWD_WAVES;
     hipLaunchKernelGGL((k_blend_forward<kW, true>), dim3(total_tiles), dim3(kWave * kW), 0, st, T, rec, inst_gauss,
@@ -572,8 +583,8 @@ hipError_t launch_blend_backward(const FrameGeom &f, const BlendRecord *rec, con
                                  hipStream_t st) {
     FrameTable T{};
     T.n = 1;
-    T.f[0] = BlendFrame{f.width, f.height, f.tiles_x, f.tiles_y, 0u, nullptr, const_cast<float *>(final_T),
-                        const_cast<int32_t *>(n_contrib), nullptr, dL_dimage};
+    T.f[0] = BlendFrame{f.width, f.height, f.tiles_x, f.tiles_y, 0u, period_of(f), nullptr,
+                        const_cast<float *>(final_T), const_cast<int32_t *>(n_contrib), nullptr, dL_dimage};
     const unsigned tiles = (unsigned)(f.tiles_x * f.tiles_y);
     if (tiles == 0) return hipSuccess;
     constexpr int kW = OMNIGS_BWD_WAVES;

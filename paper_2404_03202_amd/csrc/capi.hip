@@ -151,8 +151,17 @@ omnigs_status check_gaussians(const omnigs_gaussians *g) {
 
 omnigs_status check_camera(const omnigs_camera *c) {
     if (!c) return fail(OMNIGS_ERR_INVALID, "camera is NULL");
-    if (c->width <= 0 || c->width % kTile != 0 || c->width > 65520)
-        return fail(OMNIGS_ERR_INVALID, "width %d must be a positive multiple of 16, <= 65520", c->width);
+    if (c->model != OMNIGS_CAMERA_ERP && c->model != OMNIGS_CAMERA_PINHOLE)
+        return fail(OMNIGS_ERR_INVALID, "unknown camera model %d", c->model);
+    if (c->reserved != 0) return fail(OMNIGS_ERR_INVALID, "camera field 'reserved' must be 0");
+    if (c->model == OMNIGS_CAMERA_ERP && (c->width <= 0 || c->width % kTile != 0 || c->width > 65520))
+        return fail(OMNIGS_ERR_INVALID, "ERP width %d must be a positive multiple of 16, <= 65520", c->width);
+    if (c->model == OMNIGS_CAMERA_PINHOLE) {
+        if (c->width < 1 || c->width > 65520) return fail(OMNIGS_ERR_INVALID, "width %d not in [1, 65520]", c->width);
+        if (!(c->fx > 0.0) || !(c->fy > 0.0) || !std::isfinite(c->fx) || !std::isfinite(c->fy) ||
+            !std::isfinite(c->cx) || !std::isfinite(c->cy))
+            return fail(OMNIGS_ERR_INVALID, "pinhole intrinsics need finite fx, fy > 0 and finite cx, cy");
+    }
     if (c->height < 1 || c->height > 65520) return fail(OMNIGS_ERR_INVALID, "height %d not in [1, 65520]", c->height);
     for (int k = 0; k < 9; ++k)
         if (!std::isfinite(c->R_cw[k])) return fail(OMNIGS_ERR_INVALID, "non-finite camera rotation");
@@ -190,7 +199,14 @@ ProjectArgs make_project_args(const omnigs_gaussians *g, const omnigs_camera *c,
     for (int k = 0; k < 3; ++k) a.campos[k] = -(c->R_cw[k] * c->t_cw[0] + c->R_cw[3 + k] * c->t_cw[1] + c->R_cw[6 + k] * c->t_cw[2]);
     a.width = c->width;
     a.height = c->height;
-    a.tiles_x = c->width / kTile;
+    a.model = c->model;
+    a.fx = c->fx;
+    a.fy = c->fy;
+    a.cx = c->cx;
+    a.cy = c->cy;
+    // the ERP width is a multiple of the tile; a pinhole image may end in a
+    // partial tile column
+    a.tiles_x = (c->width + kTile - 1) / kTile;
     a.tiles_y = (c->height + kTile - 1) / kTile;
     a.alpha_min = s->alpha_min;
     a.dilation = s->dilation;
@@ -425,7 +441,7 @@ omnigs_status omnigs_forward(const omnigs_gaussians *g, const omnigs_camera *cam
     }
     {
         StageTimer t(st, kStBlendFwd);
-        FrameGeom f{cam->width, cam->height, pa.tiles_x, pa.tiles_y, 0u};
+        FrameGeom f{cam->width, cam->height, pa.tiles_x, pa.tiles_y, 0u, pa.model == OMNIGS_CAMERA_ERP};
         HIP_TRY(launch_blend_forward(f, gst.rec, inst_gauss, ranges, make_blend_settings(s), out->image, out->final_T,
                                      out->n_contrib, out->n_blended, order, tile_work, st));
     }
@@ -483,7 +499,7 @@ omnigs_status omnigs_backward(const omnigs_gaussians *g, const omnigs_camera *ca
         StageTimer t(st, kStBwdClear);
         HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(acc), 0u, n * kAcc, st));
     }
-    const FrameGeom f{cam->width, cam->height, pa.tiles_x, pa.tiles_y, 0u};
+    const FrameGeom f{cam->width, cam->height, pa.tiles_x, pa.tiles_y, 0u, pa.model == OMNIGS_CAMERA_ERP};
     {
         StageTimer t(st, kStTileOrder);
         HIP_TRY(launch_tile_order(ranges, state->tile_work, ntiles, order, st));
@@ -574,7 +590,13 @@ omnigs_status omnigs_forward_batch(const omnigs_gaussians *g, const omnigs_camer
         cg.height = pb.height;
         cg.tiles_x = pb.tiles_x;
         cg.tiles_y = pb.tiles_y;
-        frames[b] = FrameGeom{pb.width, pb.height, pb.tiles_x, pb.tiles_y, (uint32_t)total_tiles};
+        cg.model = pb.model;
+        cg.fx = pb.fx;
+        cg.fy = pb.fy;
+        cg.cx = pb.cx;
+        cg.cy = pb.cy;
+        frames[b] = FrameGeom{pb.width, pb.height, pb.tiles_x, pb.tiles_y, (uint32_t)total_tiles,
+                              pb.model == OMNIGS_CAMERA_ERP};
         total_tiles += (uint64_t)pb.tiles_x * pb.tiles_y;
         if (total_tiles >= (uint64_t(1) << 31)) return fail(OMNIGS_ERR_INVALID, "too many tiles in the batch");
         G.add(b, pb.tiles_x, pb.tiles_y);

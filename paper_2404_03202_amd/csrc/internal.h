@@ -20,11 +20,12 @@ constexpr int kMaxBatch = OMNIGS_MAX_BATCH;  // cameras per batched launch
 // float lo remainder (p = hi + lo to ~1e-12 px) so that pixel offsets formed
 // next to a tile keep full precision at 4K widths.
 struct alignas(16) BlendRecord {
-    float px_hi, px_lo, py_hi, py_lo;  // ERP pixel position of the centre (Eq. 5)
-    float q00, q01, q11, opacity;      // inverse 2D covariance (Eq. 8), opacity
+    float px_hi, px_lo, py_hi, py_lo;  // pixel position of the centre (Eq. 5 or Eq. 2)
+    float l00, l10, l11, opacity;      // Cholesky factor L of Q = Sigma2D^-1 (Eq. 8), scaled by
+                                       // sqrt(log2(e) / 2), and the opacity
     float r, g, b;                     // SH colour, clamped at 0
     float reach;                       // log2(opacity / alpha_min): alpha >= alpha_min
-                                       // iff -log2(e)/2 d^T Q d >= -reach
+                                       // iff |L^T d|^2 <= reach (L scaled as above)
 };
 static_assert(sizeof(BlendRecord) == 48, "record layout");
 
@@ -32,7 +33,7 @@ static_assert(sizeof(BlendRecord) == 48, "record layout");
 // blend: dL/dp (2), dL/dQ (q00, q01, q11), dL/do, dL/drgb (3).
 constexpr int kAcc = 9;
 
-// Depth-sort key of a culled Gaussian: sorts after every finite t_r.
+// Depth-sort key of a culled Gaussian: sorts after every finite depth.
 constexpr uint32_t kCulledKey = 0xffffffffu;
 
 struct ProjectArgs {
@@ -41,18 +42,23 @@ struct ProjectArgs {
     int sh_degree, sh_coeffs;
     double R[9], t[3], campos[3];
     int width, height, tiles_x, tiles_y;
+    int model;                 // OMNIGS_CAMERA_ERP or OMNIGS_CAMERA_PINHOLE
+    double fx, fy, cx, cy;     // pinhole intrinsics (Eq. 2)
     double alpha_min, dilation, near_plane;
 };
 
 struct FrameGeom {  // one camera's image inside a (possibly batched) launch
     int width, height, tiles_x, tiles_y;
     uint32_t tile_base;  // first global tile id of this image
+    int wrap;            // x offsets wrap modulo the width (the ERP seam)
 };
 
 // Camera-dependent part of ProjectArgs, one entry per camera of a batch.
 struct CamGeom {
     double R[9], t[3], campos[3];
     int width, height, tiles_x, tiles_y;
+    int model;
+    double fx, fy, cx, cy;
 };
 struct CamTable {
     int count;

@@ -17,6 +17,14 @@
 // point.  The radius of influence is the axis-aligned box of the
 // alpha = alpha_min iso-ellipse; its pixel columns wrap across the seam.
 //
+// A pinhole camera (Eq. 2) replaces Eq. 3-5 and 10-16 by
+// p = (f_x t_x / t_z + c_x, f_y t_y / t_z + c_y) and its Jacobian, taken at
+// the direction t_x / t_z, t_y / t_z clamped to 1.3 times the image's angular
+// half-extent around its middle (3DGS's guard against the affine
+// approximation's blow-up near the image plane; the centre is not clamped),
+// orders by t_z, culls t_z <= near_plane and clamps the box's columns to the
+// image.
+//
 // Backward (Sec. 3.4, Eq. 18-20): from the per-Gaussian accumulators
 // dL/dp, dL/dQ (Q = Sigma2D^-1), dL/do, dL/drgb to dL/dm, dL/dS, dL/dq,
 // dL/do, dL/dSH and dL/ds, through the replaced omnidirectional terms
@@ -115,8 +123,12 @@ __device__ inline void sh_basis_grad(double x, double y, double z, double (*dY)[
 // Everything the forward computes for one Gaussian, in double precision.
 struct Proj {
     double t[3], tr, rho;
+    double depth;  // sort key: t_r (ERP) or t_z (pinhole)
     double px, py;
-    double J[6];   // dp/dt, 2x3 row-major
+    double J[6];   // Jacobian of the projection used for Sigma2D, 2x3 row-major
+    double Jp[6];  // dp/dt: J, except for a guarded pinhole direction
+    double dirc[2];    // pinhole: t_x / t_z, t_y / t_z after the guard
+    bool clamped[2];   // pinhole: whether the guard clamped each
     double M[6];   // J W
     double qn[4], qnorm, Rq[9];
     double S[3];
@@ -125,9 +137,10 @@ struct Proj {
     double dir[3], vnorm; // unit direction camera centre -> m (world frame)
 };
 
-// Eq. 1, 3-5, 9-16.  Returns false when the Gaussian is culled (t_r below the
-// near plane, opacity that can never pass alpha_min, on the polar axis, or a
-// degenerate 2D covariance).
+// Eq. 1, 3-5, 9-16 (or Eq. 2 for a pinhole camera).  Returns false when the
+// Gaussian is culled (inside the near sphere / in front of the near plane,
+// opacity that can never pass alpha_min, on the polar axis of the ERP
+// camera, or a degenerate 2D covariance).
 __device__ inline bool project_core(const ProjectArgs &A, int64_t i, double o, Proj &P) {
     const double m0 = A.means[3 * i], m1 = A.means[3 * i + 1], m2 = A.means[3 * i + 2];
     for (int r = 0; r < 3; ++r) P.t[r] = A.R[3 * r] * m0 + A.R[3 * r + 1] * m1 + A.R[3 * r + 2] * m2 + A.t[r];
@@ -135,20 +148,45 @@ __device__ inline bool project_core(const ProjectArgs &A, int64_t i, double o, P
     const double rho2 = tx * tx + tz * tz;
     P.rho = sqrt(rho2);
     P.tr = sqrt(rho2 + ty * ty);
-    if (!(P.tr > A.near_plane) || !(o > A.alpha_min) || !(P.rho > 1e-6 * P.tr)) return false;
-    double lon = atan2(tx, tz);
-    if (lon >= kPi) lon = -kPi;
-    const double lat = asin(ty / P.tr);
-    P.px = (lon / kPi + 1.0) * (0.5 * A.width);
-    P.py = (2.0 * lat / kPi + 1.0) * (0.5 * A.height);
-    const double kx = A.width / (2.0 * kPi), ky = A.height / kPi;
-    const double r2 = P.tr * P.tr;
-    P.J[0] = kx * tz / rho2;
-    P.J[1] = 0.0;
-    P.J[2] = -kx * tx / rho2;
-    P.J[3] = -ky * tx * ty / (r2 * P.rho);
-    P.J[4] = ky * P.rho / r2;
-    P.J[5] = -ky * tz * ty / (r2 * P.rho);
+    if (A.model == OMNIGS_CAMERA_PINHOLE) {
+        if (!(tz > A.near_plane) || !(o > A.alpha_min)) return false;
+        P.depth = tz;
+        P.px = A.fx * tx / tz + A.cx;
+        P.py = A.fy * ty / tz + A.cy;
+        const double ax = tx / tz, ay = ty / tz;
+        const double mx = (0.5 * A.width - A.cx) / A.fx, hx = 1.3 * 0.5 * A.width / A.fx;
+        const double my = (0.5 * A.height - A.cy) / A.fy, hy = 1.3 * 0.5 * A.height / A.fy;
+        P.dirc[0] = ax < mx - hx ? mx - hx : (ax > mx + hx ? mx + hx : ax);
+        P.dirc[1] = ay < my - hy ? my - hy : (ay > my + hy ? my + hy : ay);
+        P.clamped[0] = P.dirc[0] != ax;
+        P.clamped[1] = P.dirc[1] != ay;
+        P.J[0] = A.fx / tz;
+        P.J[1] = 0.0;
+        P.J[2] = -A.fx * P.dirc[0] / tz;
+        P.J[3] = 0.0;
+        P.J[4] = A.fy / tz;
+        P.J[5] = -A.fy * P.dirc[1] / tz;
+        for (int k = 0; k < 6; ++k) P.Jp[k] = P.J[k];
+        P.Jp[2] = -A.fx * ax / tz;
+        P.Jp[5] = -A.fy * ay / tz;
+    } else {
+        if (!(P.tr > A.near_plane) || !(o > A.alpha_min) || !(P.rho > 1e-6 * P.tr)) return false;
+        P.depth = P.tr;
+        double lon = atan2(tx, tz);
+        if (lon >= kPi) lon = -kPi;
+        const double lat = asin(ty / P.tr);
+        P.px = (lon / kPi + 1.0) * (0.5 * A.width);
+        P.py = (2.0 * lat / kPi + 1.0) * (0.5 * A.height);
+        const double kx = A.width / (2.0 * kPi), ky = A.height / kPi;
+        const double r2 = P.tr * P.tr;
+        P.J[0] = kx * tz / rho2;
+        P.J[1] = 0.0;
+        P.J[2] = -kx * tx / rho2;
+        P.J[3] = -ky * tx * ty / (r2 * P.rho);
+        P.J[4] = ky * P.rho / r2;
+        P.J[5] = -ky * tz * ty / (r2 * P.rho);
+        for (int k = 0; k < 6; ++k) P.Jp[k] = P.J[k];
+    }
     for (int a = 0; a < 2; ++a)
         for (int k = 0; k < 3; ++k)
             P.M[3 * a + k] = P.J[3 * a] * A.R[k] + P.J[3 * a + 1] * A.R[3 + k] + P.J[3 * a + 2] * A.R[6 + k];
@@ -204,15 +242,23 @@ __device__ inline uint32_t project_one(const ProjectArgs &A, int64_t i, int64_t 
         const double kcut = 2.0 * log(o / A.alpha_min);
         const double ex = sqrt(kcut * P.a), ey = sqrt(kcut * P.c);
         radius = fmax(ex, ey);
-        const double xs = ceil(P.px - ex - 0.5), xe = floor(P.px + ex - 0.5);
+        double xs = ceil(P.px - ex - 0.5), xe = floor(P.px + ex - 0.5);
         double ys = ceil(P.py - ey - 0.5), ye = floor(P.py + ey - 0.5);
         ys = fmax(ys, 0.0);
         ye = fmin(ye, (double)(A.height - 1));
-        const bool full = (xe - xs + 1.0) >= (double)A.width;
+        const bool pinhole = A.model == OMNIGS_CAMERA_PINHOLE;
+        if (pinhole) {  // no seam: columns clamp like rows
+            xs = fmax(xs, 0.0);
+            xe = fmin(xe, (double)(A.width - 1));
+        }
+        const bool full = !pinhole && (xe - xs + 1.0) >= (double)A.width;
         if ((!full && xe < xs) || ye < ys) {
             vis = false;
         } else {
-            if (full) {
+            if (pinhole) {
+                tx0 = (uint32_t)((int)xs / kTile);
+                ntx = (uint32_t)((int)xe / kTile) - tx0 + 1;
+            } else if (full) {
                 tx0 = 0;
                 ntx = A.tiles_x;
             } else {
@@ -257,10 +303,16 @@ __device__ inline uint32_t project_one(const ProjectArgs &A, int64_t i, int64_t 
     r.px_lo = (float)(P.px - (double)r.px_hi);
     r.py_hi = (float)P.py;
     r.py_lo = (float)(P.py - (double)r.py_hi);
-    const double inv_det = 1.0 / P.det;
-    r.q00 = (float)(P.c * inv_det);
-    r.q01 = (float)(-P.b * inv_det);
-    r.q11 = (float)(P.a * inv_det);
+    // Q = Sigma2D^-1 = L L^T with L = [[l00, 0], [l10, l11]]:
+    // l00 = sqrt(c / det), l10 = -b / sqrt(c det), l11 = 1 / sqrt(c); the
+    // blend evaluates d^T Q d as |L^T d|^2, a sum of two squares, which keeps
+    // its precision for elongated footprints seen from far away (centres
+    // thousands of pixels off a pinhole image), where the three terms of the
+    // expanded form cancel.  Scaled by sqrt(log2(e) / 2): log2 G = -|L^T d|^2.
+    const double ls = sqrt(0.5 * 1.4426950408889634074), sc = sqrt(P.c);
+    r.l00 = (float)(ls * sqrt(P.c / P.det));
+    r.l10 = (float)(ls * (-P.b / (sc * sqrt(P.det))));
+    r.l11 = (float)(ls / sc);
     r.opacity = (float)o;
     r.r = rgb[0];
     r.g = rgb[1];
@@ -268,9 +320,9 @@ __device__ inline uint32_t project_one(const ProjectArgs &A, int64_t i, int64_t 
     r.reach = (float)(log2(o / A.alpha_min));
     float4 *dst = reinterpret_cast<float4 *>(rec + slot);
     dst[0] = make_float4(r.px_hi, r.px_lo, r.py_hi, r.py_lo);
-    dst[1] = make_float4(r.q00, r.q01, r.q11, r.opacity);
+    dst[1] = make_float4(r.l00, r.l10, r.l11, r.opacity);
     dst[2] = make_float4(r.r, r.g, r.b, r.reach);
-    depth_key[slot] = __float_as_uint((float)P.tr);
+    depth_key[slot] = __float_as_uint((float)P.depth);
     n_tiles[slot] = ntx * nty;
     const uint2 tr = make_uint2(tx0 | (ntx << 16), ty0 | (nty << 16));
     rect[slot] = tr;
@@ -321,9 +373,36 @@ __global__ __launch_bounds__(256) void k_project_batch(ProjectArgs A, CamTable T
         C.height = g.height;
         C.tiles_x = g.tiles_x;
         C.tiles_y = g.tiles_y;
+        C.model = g.model;
+        C.fx = g.fx;
+        C.fy = g.fy;
+        C.cx = g.cx;
+        C.cy = g.cy;
         covered += project_one<D>(C, i, (int64_t)b * A.n + i, rec, depth_key, n_tiles, rect, n_super, nullptr);
     }
     add_block_total(covered, tiles_total);
+}
+
+// dJ/dt for the pinhole Jacobian J00 = fx / tz, J02 = -fx a / tz,
+// J11 = fy / tz, J12 = -fy b / tz (a = t_x / t_z, b = t_y / t_z, each
+// constant in t where the guard clamped it): dJ[e][n] = d J_e / d t_n.
+__device__ inline void jacobian_grad_pinhole(const Proj &P, double fx, double fy, double (*dJ)[3]) {
+    const double tz = P.t[2], iz2 = 1.0 / (tz * tz), iz3 = iz2 / tz;
+    for (int e = 0; e < 6; ++e) dJ[e][0] = dJ[e][1] = dJ[e][2] = 0.0;
+    dJ[0][2] = -fx * iz2;
+    dJ[4][2] = -fy * iz2;
+    if (P.clamped[0]) {
+        dJ[2][2] = fx * P.dirc[0] * iz2;
+    } else {
+        dJ[2][0] = -fx * iz2;
+        dJ[2][2] = 2.0 * fx * P.t[0] * iz3;
+    }
+    if (P.clamped[1]) {
+        dJ[5][2] = fy * P.dirc[1] * iz2;
+    } else {
+        dJ[5][1] = -fy * iz2;
+        dJ[5][2] = 2.0 * fy * P.t[1] * iz3;
+    }
 }
 
 // dJ/dt for the spherical Jacobian: dJ[e][n] = d J_e / d t_n, e = 3a + j.
@@ -429,12 +508,14 @@ __global__ __launch_bounds__(256) void k_project_backward(ProjectArgs A, const u
     for (int a = 0; a < 2; ++a)
         for (int j = 0; j < 3; ++j)
             dJ[3 * a + j] = dM[3 * a] * A.R[3 * j] + dM[3 * a + 1] * A.R[3 * j + 1] + dM[3 * a + 2] * A.R[3 * j + 2];
-    const double kx = A.width / (2.0 * kPi), ky = A.height / kPi;
     double dJdt[6][3];
-    jacobian_grad(P, kx, ky, dJdt);
+    if (A.model == OMNIGS_CAMERA_PINHOLE)
+        jacobian_grad_pinhole(P, A.fx, A.fy, dJdt);
+    else
+        jacobian_grad(P, A.width / (2.0 * kPi), A.height / kPi, dJdt);
     double dt[3];
     for (int nn = 0; nn < 3; ++nn) {
-        double v = P.J[nn] * g[0] + P.J[3 + nn] * g[1];
+        double v = P.Jp[nn] * g[0] + P.Jp[3 + nn] * g[1];
         for (int e = 0; e < 6; ++e) v += dJ[e] * dJdt[e][nn];
         dt[nn] = v;
     }

@@ -47,9 +47,13 @@ class c_gaussians(ctypes.Structure):
                 ("sh_degree", ctypes.c_int32), ("sh_coeffs", ctypes.c_int32)]
 
 
+CAMERA_ERP, CAMERA_PINHOLE = 0, 1
+
+
 class c_camera(ctypes.Structure):
     _fields_ = [("R_cw", ctypes.c_double * 9), ("t_cw", ctypes.c_double * 3), ("width", ctypes.c_int32),
-                ("height", ctypes.c_int32)]
+                ("height", ctypes.c_int32), ("model", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("fx", ctypes.c_double), ("fy", ctypes.c_double), ("cx", ctypes.c_double), ("cy", ctypes.c_double)]
 
 
 class c_settings(ctypes.Structure):
@@ -186,9 +190,22 @@ def make_settings(settings: dict | None) -> c_settings:
     return s
 
 
+def camera_model(camera: dict) -> int:
+    """CAMERA_ERP or CAMERA_PINHOLE from a camera dict's "model" ("erp",
+    "pinhole" or the number; absent: ERP)."""
+    m = camera.get("model", CAMERA_ERP)
+    if isinstance(m, str):
+        m = {"erp": CAMERA_ERP, "pinhole": CAMERA_PINHOLE}[m.lower()]
+    return int(m)
+
+
 def make_camera(camera: dict) -> c_camera:
-    """camera: R [3,3] world->camera rotation, t [3], width, height."""
+    """camera: R [3,3] world->camera rotation, t [3], width, height; a pinhole
+    camera (Eq. 2) also model="pinhole", fx, fy, cx, cy (pixels)."""
     c = c_camera()
+    c.model = camera_model(camera)
+    if c.model == CAMERA_PINHOLE:
+        c.fx, c.fy, c.cx, c.cy = (float(camera[k]) for k in ("fx", "fy", "cx", "cy"))
     R = np.asarray(camera["R"], dtype=np.float64).reshape(9)
     t = np.asarray(camera["t"], dtype=np.float64).reshape(3)
     for k in range(9):
@@ -547,5 +564,5 @@ def omnigs_profile_read() -> dict:
 
 
 def tile_sort_bits(width: int, height: int) -> int:
-    tiles = (width // 16) * ((height + 15) // 16)
+    tiles = ((width + 15) // 16) * ((height + 15) // 16)
     return max(1, math.ceil(math.log2(max(tiles, 2))))

@@ -61,11 +61,11 @@ class Request:
 
 
 def _tiles(camera) -> int:
-    return (int(camera["width"]) // 16) * ((int(camera["height"]) + 15) // 16)
+    return ((int(camera["width"]) + 15) // 16) * ((int(camera["height"]) + 15) // 16)
 
 
 def footprint(n_gaussians: int, width: int, height: int, instances: int) -> int:
-    tiles = (width // 16) * ((height + 15) // 16)
+    tiles = ((width + 15) // 16) * ((height + 15) // 16)
     return (n_gaussians * BYTES_PER_RECORD + instances * BYTES_PER_INSTANCE + width * height * BYTES_PER_PIXEL
             + tiles * BYTES_PER_TILE)
 

@@ -53,6 +53,11 @@ def _fake_args(n=10, width=64, height=32, degree=3, coeffs=16):
     return g, c, s, out
 
 
+def _pinhole(c, fx=50.0, fy=50.0, cx=32.0, cy=16.0):
+    c.model = B.CAMERA_PINHOLE
+    c.fx, c.fy, c.cx, c.cy = fx, fy, cx, cy
+
+
 def _alloc(fail):
     calls = []
 
@@ -82,6 +87,12 @@ def _forward(lib, g, c, s, out, alloc):
     (lambda g, c, s, o: setattr(s, "alpha_min", 0.0), "alpha_min"),
     (lambda g, c, s, o: setattr(s, "T_min", 1.5), "T_min"),
     (lambda g, c, s, o: setattr(o, "image", None), "NULL"),
+    (lambda g, c, s, o: setattr(c, "model", 7), "unknown camera model"),
+    (lambda g, c, s, o: setattr(c, "reserved", 1), "reserved"),
+    (lambda g, c, s, o: _pinhole(c, fx=0.0), "intrinsics"),
+    (lambda g, c, s, o: _pinhole(c, fy=float("nan")), "intrinsics"),
+    (lambda g, c, s, o: _pinhole(c, cx=float("inf")), "intrinsics"),
+    (lambda g, c, s, o: (_pinhole(c), setattr(c, "width", 0)), "width"),
 ])
 def test_invalid_arguments(lib, mutate, needle):
     g, c, s, out = _fake_args()
@@ -91,6 +102,16 @@ def test_invalid_arguments(lib, mutate, needle):
     assert rc == B.OMNIGS_ERR_INVALID
     assert needle in B.omnigs_last_error()
     assert calls == []  # rejected before allocating
+
+
+def test_pinhole_accepts_any_width(lib):
+    """A pinhole image need not be a multiple of 16 wide: validation passes
+    and the call proceeds to allocation."""
+    g, c, s, out = _fake_args(n=1000, width=100)
+    _pinhole(c)
+    alloc, calls, keep = _alloc(fail=True)
+    assert _forward(lib, g, c, s, out, alloc) == B.OMNIGS_ERR_ALLOC
+    assert calls
 
 
 def test_allocator_failure_reports_err_alloc(lib):
