@@ -245,6 +245,61 @@ def train_bench(g, poses, targets, steps, log):
     return out
 
 
+def pinhole_bench(gd, crops, crop_targets, poses, steps, log):
+    """The pinhole camera of Eq. 2 on the benchmark scene: (1) forward + L1 +
+    backward of 1024x1024 perspective crops (90 degree field of view, seeded
+    poses inside the room); (2) the six 512x512 faces of a cube map around
+    each benchmark pose rendered as one batch, against the 2048x1024 ERP
+    forward of the same pose (the same pixel count on the sphere)."""
+    import torch
+    from paper_2404_03202_amd import omnigs as B
+    from paper_2404_03202_amd import scenes
+
+    def crop_step(k):
+        c = crops[k % len(crops)]
+        fwd = B.omnigs_forward(gd, c)
+        loss, dl = B.omnigs_l1_loss(fwd.image, crop_targets[k % len(crops)])
+        B.omnigs_backward(gd, c, None, fwd, dl)
+
+    for k in range(5):
+        crop_step(k)
+    torch.cuda.synchronize()
+    B.omnigs_profile_read()
+    B.omnigs_profile_enable(True)
+    t0 = time.perf_counter()
+    for k in range(steps):
+        crop_step(k)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    B.omnigs_profile_enable(False)
+    prof = B.omnigs_profile_read()
+    crop = dict(workload="1M Gaussians, 1024x1024 pinhole crops (90 deg), forward + L1 + backward per crop",
+                steps=steps, iters_per_s=steps / dt, ms_per_step=dt * 1e3 / steps,
+                stage_ms={k: v[0] / steps for k, v in prof.items() if v[1]})
+    n = min(steps, len(poses))
+    faces = [scenes.cube_faces(p, 512) for p in poses[:n]]
+    for k in range(3):
+        B.omnigs_forward_batch(gd, faces[k])
+        B.omnigs_forward(gd, poses[k])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(n):
+        B.omnigs_forward_batch(gd, faces[k])
+    torch.cuda.synchronize()
+    t_cube = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for k in range(n):
+        B.omnigs_forward(gd, poses[k])
+    torch.cuda.synchronize()
+    t_erp = time.perf_counter() - t0
+    cube = dict(workload="six 512x512 cube-map faces per benchmark pose, one batched forward",
+                poses=n, poses_per_s=n / t_cube, ms_per_pose=t_cube * 1e3 / n,
+                erp_forward_poses_per_s=n / t_erp, erp_ms_per_pose=t_erp * 1e3 / n)
+    out = dict(crop=crop, cube_map=cube)
+    log(f"pinhole: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -255,6 +310,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--stress", action="store_true", help="also measure the 3M-Gaussian 3840x1920 workload")
     ap.add_argument("--no-train", action="store_true", help="skip the full training-iteration measurement")
+    ap.add_argument("--no-pinhole", action="store_true", help="skip the pinhole-camera measurement")
     ap.add_argument("--stress-steps", type=int, default=8)
     ap.add_argument("--serve-requests", type=int, default=800)
     ap.add_argument("--serve-slots", type=int, default=4)
@@ -289,6 +345,8 @@ def main():
     targets = []
     for p in poses:
         targets.append(B.omnigs_forward(gtd, p).image.clone())
+    crops = scenes.crop_poses(2, 100, 1024, 1024, 90.0)
+    crop_targets = [] if args.no_pinhole else [B.omnigs_forward(gtd, c).image.clone() for c in crops]
     del gtd
     torch.cuda.synchronize()
     log("targets rendered")
@@ -340,6 +398,8 @@ def main():
                roofline=roofline)
     if not args.no_train:
         out["train"] = train_bench(g, poses, targets, min(args.steps, 100), log)
+    if not args.no_pinhole:
+        out["pinhole"] = pinhole_bench(gd, crops, crop_targets, poses, min(args.steps, 100), log)
     if args.stress:
         out["stress"] = stress_bench(args.stress_steps, log)
     if not args.no_serve:

@@ -161,6 +161,22 @@ def crop_poses(config: int, count: int, width: int, height: int, fov_x_deg=90.0,
     return out
 
 
+def cube_faces(cam: dict, size: int) -> list:
+    """The six 90-degree pinhole faces (size x size) of a cube map around an
+    ERP camera's centre: front, right, back, left (about the camera's Y
+    axis), up and down.  Face k's world->camera rotation is F_k^T R with F_k
+    the face's axes in the ERP camera frame."""
+    R = np.asarray(cam["R"], dtype=np.float64)
+    t = np.asarray(cam["t"], dtype=np.float64)
+    faces = [rot_y(0.0), rot_y(np.pi / 2), rot_y(np.pi), rot_y(-np.pi / 2), rot_x(np.pi / 2), rot_x(-np.pi / 2)]
+    out = []
+    for F in faces:
+        c = pinhole_camera(size, size, 90.0)
+        c.update(R=F.T @ R, t=F.T @ t)
+        out.append(c)
+    return out
+
+
 def poses(config: int, count: int, width: int, height: int, radius=1.0, yaw_zero=False):
     """Seeded poses: centre uniform in the ball of ``radius``, yaw ~ U[-pi, pi),
     world->camera rotation R_y(yaw)^T."""

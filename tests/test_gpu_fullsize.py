@@ -2,7 +2,8 @@
 times (omnigs_forward / omnigs_backward, default settings):
 
 * 1M Gaussians in the room layout at 2048x1024 (a benchmark pose and a yaw-0
-  pose where the seam wedge straddles the +-pi seam);
+  pose where the seam wedge straddles the +-pi seam), and a 1024x1024
+  pinhole crop of the same scene;
 * 3M Gaussians with scales log-uniform [0.002, 0.5] at 3840x1920.
 
 The GPU renders and back-propagates the whole image; the FP64 oracle computes
@@ -156,6 +157,12 @@ def test_fullsize_1m_2048x1024_seam_pose(room1m):
     # yaw 0: the wedge at world longitude pi straddles the seam
     cam = scenes.camera(2048, 1024, np.eye(3), [0.2, -0.1, 0.15])
     check_fullsize(room1m, cam, seed=201)
+
+
+def test_fullsize_1m_pinhole_crop_1024(room1m):
+    # the perspective crop that bench.py times (pinhole, 90 degrees)
+    cam = scenes.crop_poses(2, 100, 1024, 1024, 90.0)[0]
+    check_fullsize(room1m, cam, seed=202)
 
 
 def test_fullsize_3m_3840x1920():
