@@ -143,15 +143,16 @@ def project_independent(scene):
     return out
 
 
-def render(scene, records=None):
+def render(scene, records=None, with_depth=False):
     """Per-pixel front-to-back blend over all Gaussians (no tiles).
 
     ``records``: the C oracle's projection records (exact tiling check) or
     None (independent projection).  Returns (image [3,H,W], final_T [H,W],
-    n_blended [H,W]).
+    n_blended [H,W]) and, with ``with_depth``, the depth image
+    sum_i depth_i alpha_i T_i [H,W]; H is the rendered rows.
     """
     st = scene.settings
-    W, H = scene.width, scene.height
+    W, H = scene.width, getattr(scene, "out_height", scene.height)
     if records is not None:
         vis = records[:, 0] > 0.5
         proj = dict(visible=vis, tr=records[:, 4], px=records[:, 7], py=records[:, 8], Q=records[:, 18:21],
@@ -167,6 +168,7 @@ def render(scene, records=None):
     C = np.zeros((3, H, W))
     active = np.ones((H, W), bool)
     nb = np.zeros((H, W), dtype=np.int64)
+    D = np.zeros((H, W))
     wrap = getattr(scene, "model", 0) != 1  # the ERP seam; the pinhole image does not wrap
     for i in order:
         dx = xc - proj["px"][i]
@@ -184,7 +186,10 @@ def render(scene, records=None):
         take &= ~stop
         for ch in range(3):
             C[ch] = np.where(take, C[ch] + proj["rgb"][i, ch] * a * T, C[ch])
+        D = np.where(take, D + proj["tr"][i] * a * T, D)
         T = np.where(take, Tn, T)
         nb += take
     bg = np.asarray(st["bg"], dtype=np.float64)
+    if with_depth:
+        return C + T[None] * bg[:, None, None], T, nb, D
     return C + T[None] * bg[:, None, None], T, nb

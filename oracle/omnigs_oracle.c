@@ -57,6 +57,15 @@
  *     (x + 1/2, y + 1/2); nothing wraps: columns clamp like rows, and the
  *     width need not be a multiple of 16 (the last tile column is ragged);
  *     the screen-space gradient is (W/2, H/2) * dL/dp as for the ERP image.
+ *   - loss masks (Sec. 4, the 360Roam evaluation skips the images' bottom
+ *     rows): a camera may render only its top `rows` rows (the mapping still
+ *     uses the full height H); the image then has `rows` rows.
+ *   - auxiliary outputs of the same blend: the depth image
+ *     D = sum_i d_i alpha_i T_i (d = the sort depth, t_r or t_z) and the
+ *     alpha image A = 1 - T_final = sum_i alpha_i T_i; both back-propagate
+ *     like colour channels with colour d_i (respectively 1) and a zero
+ *     background, and dL/dd_i reaches the mean through d(t_r)/dt = t / t_r or
+ *     d(t_z)/dt = (0, 0, 1).
  */
 #include <math.h>
 #include <stdint.h>
@@ -91,7 +100,12 @@ typedef struct {
     int32_t model;        /* ORC_ERP or ORC_PINHOLE                         */
     int32_t reserved;
     double fx, fy, cx, cy; /* pinhole intrinsics of Eq. 2 (pixels)         */
+    int32_t rows;         /* rendered rows: the top `rows` rows (0: all)   */
+    int32_t reserved2;
 } orc_scene;
+
+/* rows of the rendered image */
+static int orc_rows(const orc_scene *s) { return s->rows > 0 ? s->rows : s->height; }
 
 /* tile columns: W / 16 for the ERP image (W a multiple of 16, the columns
  * wrap), ceil(W / 16) for the pinhole image */
@@ -100,7 +114,7 @@ static int orc_tiles_x(const orc_scene *s) {
 }
 
 static int orc_valid(const orc_scene *s) {
-    if (s->height < 1 || s->width < 1) return 0;
+    if (s->height < 1 || s->width < 1 || s->rows < 0 || s->rows > s->height) return 0;
     if (s->model == ORC_ERP) return s->width % ORC_TILE == 0;
     if (s->model == ORC_PINHOLE) return isfinite(s->fx) && isfinite(s->fy) && s->fx > 0.0 && s->fy > 0.0 &&
                                         isfinite(s->cx) && isfinite(s->cy);
@@ -375,7 +389,7 @@ static void project_one(const orc_scene *s, int64_t i, orc_proj *P) {
     }
     double cys = ceil(by0), cye = floor(by1);
     if (cys < 0.0) cys = 0.0;
-    if (cye > H - 1.0) cye = H - 1.0;
+    if (cye > orc_rows(s) - 1.0) cye = orc_rows(s) - 1.0;
     if (cye < cys) return;
     P->ys = (int64_t)cys;
     P->ye = (int64_t)cye;
@@ -460,7 +474,7 @@ static void lists_free(orc_lists *L) {
 static int build_lists(const orc_scene *s, const uint8_t *tile_mask, orc_lists *L) {
     memset(L, 0, sizeof(*L));
     L->tiles_x = orc_tiles_x(s);
-    L->tiles_y = (s->height + ORC_TILE - 1) / ORC_TILE;
+    L->tiles_y = (orc_rows(s) + ORC_TILE - 1) / ORC_TILE;
     const int64_t n = s->n, ntiles = (int64_t)L->tiles_x * L->tiles_y;
     L->P = (orc_proj *)malloc(sizeof(orc_proj) * (size_t)(n > 0 ? n : 1));
     L->tstart = (int64_t *)calloc((size_t)ntiles, sizeof(int64_t));
@@ -519,6 +533,7 @@ typedef struct {
 
 typedef struct {
     double C[3], T;
+    double D;             /* depth image: sum of d_i alpha_i T_i */
     int32_t n_contrib;    /* 1 + list position of the last blended instance */
     int32_t n_flags;      /* near-threshold decisions met */
     int32_t n_grad_flags; /* also counts alpha_max-clamp kinks */
@@ -545,7 +560,7 @@ static double wrap_dx(double d, double W) {
  * contrib (may be NULL) receives the blended instances in order. */
 static void render_pixel(const orc_scene *s, const orc_lists *L, int64_t start, int64_t end, int x, int y,
                          int flip, orc_pixel *out, orc_contrib *contrib) {
-    double T = 1.0, C[3] = {0, 0, 0};
+    double T = 1.0, C[3] = {0, 0, 0}, D = 0.0;
     int32_t last = 0, nflag = 0, ngflag = 0, ncon = 0;
     uint64_t sig = 1469598103934665603ull;
     const double W = (double)s->width;
@@ -596,10 +611,12 @@ static void render_pixel(const orc_scene *s, const orc_lists *L, int64_t start, 
         ++ncon;
         sig = fnv(sig, ((uint64_t)(uint32_t)I->gid << 1) | (uint64_t)(araw >= s->alpha_max));
         for (int ch = 0; ch < 3; ++ch) C[ch] += P->rgb[ch] * alpha * T;
+        D += P->depth * alpha * T;
         T = Tn;
         last = (int32_t)(k - start + 1);
     }
     for (int ch = 0; ch < 3; ++ch) out->C[ch] = C[ch] + T * s->bg[ch];
+    out->D = D;
     out->T = T;
     out->n_contrib = last;
     out->n_flags = nflag;
@@ -690,16 +707,17 @@ int64_t orc_tile_lists(const orc_scene *s, const uint8_t *tile_mask, int64_t cap
  * flagged decision, the value with that decision inverted (else the value);
  * n_grad_flags (may be NULL) also counts alpha_max-clamp near-ties, where
  * the gradient (not the value) changes; n_blended (may be NULL) counts the
- * instances blended into each pixel. */
+ * instances blended into each pixel; depth (may be NULL) receives the depth
+ * image. */
 int orc_render(const orc_scene *s, const uint8_t *tile_mask, double *image, double *final_T, int32_t *n_contrib,
-               int32_t *n_flags, double *alt, int32_t *n_grad_flags, int32_t *n_blended) {
+               int32_t *n_flags, double *alt, int32_t *n_grad_flags, int32_t *n_blended, double *depth) {
     if (!orc_valid(s)) return -1;
     orc_lists L;
     if (build_lists(s, tile_mask, &L) != 0) {
         lists_free(&L);
         return -1;
     }
-    const int Wd = s->width, Hd = s->height;
+    const int Wd = s->width, Hd = orc_rows(s);
     const int64_t HW = (int64_t)Wd * Hd;
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t p = 0; p < HW; ++p) {
@@ -714,6 +732,7 @@ int orc_render(const orc_scene *s, const uint8_t *tile_mask, double *image, doub
         n_flags[p] = px.n_flags;
         if (n_grad_flags) n_grad_flags[p] = px.n_grad_flags;
         if (n_blended) n_blended[p] = px.n_blended;
+        if (depth) depth[p] = px.D;
         if (alt) {
             if (px.n_flags == 1) {
                 orc_pixel q;
@@ -740,7 +759,7 @@ int orc_l1_tiles(const orc_scene *s, const double *target, const double *weight,
         lists_free(&L);
         return -1;
     }
-    const int Wd = s->width, Hd = s->height;
+    const int Wd = s->width, Hd = orc_rows(s);
     const int64_t HW = (int64_t)Wd * Hd;
     double total = 0.0;
     uint64_t sig = 1469598103934665603ull;
@@ -770,8 +789,8 @@ int orc_l1_tiles(const orc_scene *s, const double *target, const double *weight,
 /* Backward (Eq. 18-20)                                                       */
 /* ------------------------------------------------------------------------ */
 /* per-Gaussian accumulator layout: dL/dp (2), dL/dQ (00, 01, 11), dL/do,
- * dL/drgb (3) */
-#define ORC_NACC 9
+ * dL/drgb (3), dL/dd (the depth value of the depth image) */
+#define ORC_NACC 10
 
 /* dJ_{a,j}/dt_n for the pinhole Jacobian J00 = fx / tz, J02 = -fx a / tz,
  * J11 = fy / tz, J12 = -fy b / tz with a = t_x / t_z, b = t_y / t_z, each
@@ -877,7 +896,8 @@ static void chain_one(const orc_scene *s, int64_t i, const orc_proj *P, const do
             for (int k = 0; k < 3; ++k) v += gM[3 * a + k] * s->R[3 * ii + k];
             gJ[3 * a + ii] = v;
         }
-    /* dL/dt: through p (dp/dt) and through J(t) */
+    /* dL/dt: through p (dp/dt), through J(t) and through the depth d of the
+     * depth image (d = t_r: dd/dt = t / t_r; d = t_z: dd/dt = (0, 0, 1)) */
     double dJdt[6][3];
     if (s->model == ORC_PINHOLE)
         jacobian_dt_pinhole(P, s->fx, s->fy, dJdt);
@@ -887,6 +907,10 @@ static void chain_one(const orc_scene *s, int64_t i, const orc_proj *P, const do
     for (int nn = 0; nn < 3; ++nn) {
         double v = gp[0] * P->Jp[nn] + gp[1] * P->Jp[3 + nn];
         for (int e = 0; e < 6; ++e) v += gJ[e] * dJdt[e][nn];
+        if (s->model == ORC_PINHOLE)
+            v += nn == 2 ? acc[9] : 0.0;
+        else
+            v += acc[9] * P->tc[nn] / P->tr;
         gt[nn] = v;
     }
     /* t = W m + t_cw */
@@ -944,16 +968,18 @@ static void chain_one(const orc_scene *s, int64_t i, const orc_proj *P, const do
     dscreen[1] = gp[1] * H / 2.0;
 }
 
-/* Backward of image = render(params) for a given dL/dimage [3][H][W],
+/* Backward of image = render(params) for a given dL/dimage [3][H][W] and,
+ * each may be NULL, dL/ddepth [H][W] and dL/dalpha [H][W] (alpha = 1 - T_final),
  * restricted to the tiles set in tile_mask (NULL: all); exact when dL/dimage
  * vanishes outside them.
  * Gradient outputs are overwritten: dmeans [n][3], dscales [n][3],
  * dquats [n][4], dopac [n], dsh [n][sh_coeffs][3], dscreen [n][2].
- * acc_out (may be NULL): [n][9] screen-space accumulators.
+ * acc_out (may be NULL): [n][10] screen-space accumulators.
  * abs_* (may all be NULL): sums of |per-pixel contributions|, each weighted
  * by 1 + the pixel's optical depth ln(1 / T_final), propagated through
  * |chain|: the scale against which float32 sums are judged. */
-int orc_backward(const orc_scene *s, const uint8_t *tile_mask, const double *dLdC, double *dmeans, double *dscales,
+int orc_backward(const orc_scene *s, const uint8_t *tile_mask, const double *dLdC, const double *dLdD,
+                 const double *dLdA, double *dmeans, double *dscales,
                  double *dquats, double *dopac, double *dsh, double *dscreen, double *acc_out, double *abs_means,
                  double *abs_scales, double *abs_quats, double *abs_opac, double *abs_sh, double *abs_screen) {
     if (!orc_valid(s)) return -1;
@@ -963,7 +989,7 @@ int orc_backward(const orc_scene *s, const uint8_t *tile_mask, const double *dLd
         return -1;
     }
     const int64_t n = s->n;
-    const int Wd = s->width, Hd = s->height;
+    const int Wd = s->width, Hd = orc_rows(s);
     const int64_t HW = (int64_t)Wd * Hd;
     const int64_t ntiles = (int64_t)L.tiles_x * L.tiles_y;
     int nthreads = 1;
@@ -984,7 +1010,7 @@ int orc_backward(const orc_scene *s, const uint8_t *tile_mask, const double *dLd
 #ifdef _OPENMP
         tid = omp_get_thread_num();
 #endif
-        double *A = acc + (int64_t)tid * n * ORC_NACC * 2; /* [n][9] signed then [n][9] abs */
+        double *A = acc + (int64_t)tid * n * ORC_NACC * 2; /* [n][10] signed then [n][10] abs */
         double *Aabs = A + n * ORC_NACC;
         orc_contrib *con = (orc_contrib *)malloc(sizeof(orc_contrib) * (size_t)maxlen);
 #pragma omp for schedule(dynamic, 4)
@@ -998,6 +1024,7 @@ int orc_backward(const orc_scene *s, const uint8_t *tile_mask, const double *dLd
                     render_pixel(s, &L, L.tstart[t], L.tend[t], x, y, -1, &px, con);
                     const int ncon = px.n_blended;
                     const double g[3] = {dLdC[p], dLdC[HW + p], dLdC[2 * HW + p]};
+                    const double gD = dLdD ? dLdD[p] : 0.0, gA = dLdA ? dLdA[p] : 0.0;
                     /* weight of this pixel's |contributions| in the abs
                      * sums: 1 + its optical depth ln(1 / T_final).  A float32
                      * alpha carries a relative error of ~1e-6 and the
@@ -1008,7 +1035,7 @@ int orc_backward(const orc_scene *s, const uint8_t *tile_mask, const double *dLd
                     const double wd = 1.0 + log(1.0 / px.T);
                     /* S = colour blended behind the current instance, plus
                      * the background seen through the final transmittance */
-                    double Sb[3];
+                    double Sb[3], SD = 0.0, SA = 0.0; /* depth and alpha: zero background */
                     for (int ch = 0; ch < 3; ++ch) Sb[ch] = px.T * s->bg[ch];
                     for (int j = ncon - 1; j >= 0; --j) {
                         const orc_contrib *c = &con[j];
@@ -1023,6 +1050,14 @@ int orc_backward(const orc_scene *s, const uint8_t *tile_mask, const double *dLd
                             dalpha += g[ch] * (P->rgb[ch] * c->T - Sb[ch] / (1.0 - c->alpha));
                         }
                         for (int ch = 0; ch < 3; ++ch) Sb[ch] += P->rgb[ch] * c->alpha * c->T;
+                        /* depth and alpha channels: colour d_i and 1 */
+                        const double tD = gD * c->alpha * c->T;
+                        a[9] += tD;
+                        aa[9] += fabs(tD) * wd;
+                        dalpha += gD * (P->depth * c->T - SD / (1.0 - c->alpha));
+                        dalpha += gA * (c->T - SA / (1.0 - c->alpha));
+                        SD += P->depth * c->alpha * c->T;
+                        SA += c->alpha * c->T;
                         if (c->alpha_raw >= s->alpha_max) continue; /* clamped: no gradient */
                         const double o = s->opac[c->gid];
                         const double gO = c->G * dalpha;

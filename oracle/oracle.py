@@ -89,6 +89,8 @@ class _Scene(ctypes.Structure):
         ("fy", ctypes.c_double),
         ("cx", ctypes.c_double),
         ("cy", ctypes.c_double),
+        ("rows", ctypes.c_int32),
+        ("reserved2", ctypes.c_int32),
     ]
 
 
@@ -105,11 +107,11 @@ def _load():
         _lib.orc_tile_lists.argtypes = [P(_Scene), ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p]
         _lib.orc_tile_lists.restype = ctypes.c_int64
-        _lib.orc_render.argtypes = [P(_Scene)] + [ctypes.c_void_p] * 8
+        _lib.orc_render.argtypes = [P(_Scene)] + [ctypes.c_void_p] * 9
         _lib.orc_render.restype = ctypes.c_int
         _lib.orc_l1_tiles.argtypes = [P(_Scene)] + [ctypes.c_void_p] * 5
         _lib.orc_l1_tiles.restype = ctypes.c_int
-        _lib.orc_backward.argtypes = [P(_Scene)] + [ctypes.c_void_p] * 15
+        _lib.orc_backward.argtypes = [P(_Scene)] + [ctypes.c_void_p] * 17
         _lib.orc_backward.restype = ctypes.c_int
         _lib.orc_l1.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         _lib.orc_l1.restype = ctypes.c_double
@@ -134,7 +136,8 @@ class Scene:
     [N,4] (w,x,y,z), opacities [N] (activated), sh [N,K,3], sh_degree.
     ``camera``: dict with R [3,3] (world -> camera rotation), t [3], width,
     height; for the pinhole camera of Eq. 2 also model="pinhole", fx, fy, cx,
-    cy (pixels).
+    cy (pixels); optionally rows: render only the top ``rows`` rows (0 or
+    absent: all), the image then has ``rows`` rows (``out_height``).
     """
 
     def __init__(self, gaussians, camera, settings=None, flags=None):
@@ -156,6 +159,7 @@ class Scene:
         self.R = _f64(camera["R"]).reshape(3, 3)
         self.t = _f64(camera["t"]).reshape(3)
         self.model = camera_model(camera)
+        self.rows = int(camera.get("rows", 0))
         self.intrinsics = tuple(float(camera[k]) for k in ("fx", "fy", "cx", "cy")) if self.model == PINHOLE \
             else (0.0, 0.0, 0.0, 0.0)
         self.settings = st
@@ -167,14 +171,19 @@ class Scene:
 
     def camera(self, R=None, t=None):
         cam = dict(R=self.R if R is None else R, t=self.t if t is None else t, width=self.width,
-                   height=self.height, model=self.model)
+                   height=self.height, model=self.model, rows=self.rows)
         if self.model == PINHOLE:
             cam.update(zip(("fx", "fy", "cx", "cy"), self.intrinsics))
         return cam
 
     @property
+    def out_height(self):
+        """Rows of the rendered image."""
+        return self.rows if self.rows > 0 else self.height
+
+    @property
     def tiles_y(self):
-        return (self.height + 15) // 16
+        return (self.out_height + 15) // 16
 
     def _struct(self):
         s = _Scene()
@@ -204,6 +213,7 @@ class Scene:
             setattr(s, k, float(v))
         s.model = self.model
         s.fx, s.fy, s.cx, s.cy = self.intrinsics
+        s.rows = self.rows
         return s
 
     def with_params(self, **kw):
@@ -257,11 +267,12 @@ def _mask(scene, tile_mask):
 
 def render(scene: Scene, alt: bool = True, tile_mask=None):
     """Forward render: dict(image [3,H,W], final_T [H,W], n_contrib [H,W],
-    n_flags [H,W], alt [3,H,W] or None, n_grad_flags [H,W], n_blended [H,W]).  With
-    ``tile_mask`` ([tiles] bool) only those tiles are rendered (the other
-    pixels stay zero)."""
+    n_flags [H,W], alt [3,H,W] or None, n_grad_flags [H,W], n_blended [H,W],
+    depth [H,W], alpha [H,W]) with H the rendered rows.  With ``tile_mask``
+    ([tiles] bool) only those tiles are rendered (the other pixels stay
+    zero)."""
     lib = _load()
-    H, W = scene.height, scene.width
+    H, W = scene.out_height, scene.width
     image = np.zeros((3, H, W))
     T = np.zeros((H, W))
     nc = np.zeros((H, W), dtype=np.int32)
@@ -269,14 +280,16 @@ def render(scene: Scene, alt: bool = True, tile_mask=None):
     altimg = np.zeros((3, H, W)) if alt else None
     ngf = np.zeros((H, W), dtype=np.int32)
     nbl = np.zeros((H, W), dtype=np.int32)
+    depth = np.zeros((H, W))
     s = scene._struct()
     m = _mask(scene, tile_mask)
     rc = lib.orc_render(ctypes.byref(s), m.ctypes.data if m is not None else None, image.ctypes.data, T.ctypes.data,
                         nc.ctypes.data, nf.ctypes.data, altimg.ctypes.data if alt else None, ngf.ctypes.data,
-                        nbl.ctypes.data)
+                        nbl.ctypes.data, depth.ctypes.data)
     if rc != 0:
         raise ValueError("oracle: invalid scene")
-    return dict(image=image, final_T=T, n_contrib=nc, n_flags=nf, alt=altimg, n_grad_flags=ngf, n_blended=nbl)
+    return dict(image=image, final_T=T, n_contrib=nc, n_flags=nf, alt=altimg, n_grad_flags=ngf, n_blended=nbl,
+                depth=depth, alpha=1.0 - T)
 
 
 def l1(image, target):
@@ -294,7 +307,7 @@ def l1_tiles(scene: Scene, target, tile_mask, weight=None):
     hash); ``weight`` [H,W] or None (all ones)."""
     lib = _load()
     tg = _f64(target)
-    w = None if weight is None else _f64(weight).reshape(scene.height, scene.width)
+    w = None if weight is None else _f64(weight).reshape(scene.out_height, scene.width)
     mask = np.ascontiguousarray(np.asarray(tile_mask, dtype=np.uint8).reshape(-1))
     assert mask.size == scene.tiles_x * scene.tiles_y
     loss = ctypes.c_double(0.0)
@@ -306,8 +319,9 @@ def l1_tiles(scene: Scene, target, tile_mask, weight=None):
     return loss.value, sig.value
 
 
-def backward(scene: Scene, dL_dimage, with_abs: bool = True, tile_mask=None):
-    """Analytic gradient of <dL_dimage, render(scene)> w.r.t. the parameters.
+def backward(scene: Scene, dL_dimage, with_abs: bool = True, tile_mask=None, dL_ddepth=None, dL_dalpha=None):
+    """Analytic gradient of <dL_dimage, image> + <dL_ddepth, depth> +
+    <dL_dalpha, 1 - final_T> (the last two optional) w.r.t. the parameters.
 
     Returns dict(means, scales, quats, opacities, sh, screen, acc) and, with
     ``with_abs``, the same keys prefixed ``abs_``: sums of |per-pixel
@@ -319,9 +333,11 @@ def backward(scene: Scene, dL_dimage, with_abs: bool = True, tile_mask=None):
     """
     lib = _load()
     n, K = scene.n, scene.sh_coeffs
-    g = _f64(dL_dimage).reshape(3, scene.height, scene.width)
+    g = _f64(dL_dimage).reshape(3, scene.out_height, scene.width)
+    gD = None if dL_ddepth is None else _f64(dL_ddepth).reshape(scene.out_height, scene.width)
+    gA = None if dL_dalpha is None else _f64(dL_dalpha).reshape(scene.out_height, scene.width)
     out = dict(means=np.zeros((n, 3)), scales=np.zeros((n, 3)), quats=np.zeros((n, 4)), opacities=np.zeros(n),
-               sh=np.zeros((n, K, 3)), screen=np.zeros((n, 2)), acc=np.zeros((n, 9)))
+               sh=np.zeros((n, K, 3)), screen=np.zeros((n, 2)), acc=np.zeros((n, 10)))
     names = ["means", "scales", "quats", "opacities", "sh", "screen"]
     if with_abs:
         for k in names:
@@ -330,7 +346,9 @@ def backward(scene: Scene, dL_dimage, with_abs: bool = True, tile_mask=None):
     args = [out[k].ctypes.data for k in names] + [out["acc"].ctypes.data]
     args += [out["abs_" + k].ctypes.data for k in names] if with_abs else [None] * 6
     m = _mask(scene, tile_mask)
-    if lib.orc_backward(ctypes.byref(s), m.ctypes.data if m is not None else None, g.ctypes.data, *args) != 0:
+    if lib.orc_backward(ctypes.byref(s), m.ctypes.data if m is not None else None, g.ctypes.data,
+                        gD.ctypes.data if gD is not None else None, gA.ctypes.data if gA is not None else None,
+                        *args) != 0:
         raise ValueError("oracle: invalid scene")
     return out
 

@@ -14,6 +14,11 @@ supplement); the readings (3DGS's form of the term):
   s_xy = sum w x y - mu_x mu_y, with C1 = 0.01^2, C2 = 0.03^2:
   S = (2 mu_x mu_y + C1)(2 s_xy + C2) / ((mu_x^2 + mu_y^2 + C1)(s_xx + s_yy + C2));
 * SSIM = mean of S over channels and pixels; the term is 1 - SSIM.
+
+A loss mask m [H, W] (Sec. 4: the 360Roam evaluation leaves the images'
+bottom rows out of the loss) weights both terms per pixel: L1 =
+sum m |x - y| / (C sum m), SSIM = sum m S / (C sum m), with the windows still
+taken over the whole (zero-padded) images.
 """
 from __future__ import annotations
 
@@ -65,19 +70,21 @@ def ssim(x, y, w=None) -> float:
     return float(ssim_terms(x, y, w)["S"].mean())
 
 
-def dssim_grad(x, y, w=None):
+def dssim_grad(x, y, w=None, mask=None):
     """(1 - SSIM, d(1 - SSIM)/dx).  For a window centred at q, S(q) depends
     on x through mu_x(q), s_xx(q), s_xy(q); x_p enters them with weight
     w(p - q): d mu_x(q)/dx_p = w, d s_xx(q)/dx_p = 2 w (x_p - mu_x(q)),
     d s_xy(q)/dx_p = w (y_p - mu_y(q)).  The gradient sums these over the
-    windows that contain p."""
+    windows that contain p.  With a mask, S(q) enters with weight m(q) and
+    the mean is over C sum m."""
     w = window() if w is None else w
     t = ssim_terms(x, y, w)
-    N = t["S"].size
-    # partials of S(q)
-    dS_dmx = (2 * t["my"] * t["num2"]) / (t["den1"] * t["den2"]) - t["S"] * 2 * t["mx"] / t["den1"]
-    dS_dsxx = -t["S"] / t["den2"]
-    dS_dsxy = 2 * t["num1"] / (t["den1"] * t["den2"])
+    m = np.ones(t["S"].shape[1:]) if mask is None else np.asarray(mask, np.float64)
+    N = t["S"].shape[0] * m.sum()
+    # partials of S(q), weighted by the mask at q
+    dS_dmx = ((2 * t["my"] * t["num2"]) / (t["den1"] * t["den2"]) - t["S"] * 2 * t["mx"] / t["den1"]) * m
+    dS_dsxx = -t["S"] / t["den2"] * m
+    dS_dsxy = 2 * t["num1"] / (t["den1"] * t["den2"]) * m
     x = np.asarray(x, np.float64)
     y = np.asarray(y, np.float64)
     C, H, W = x.shape
@@ -97,14 +104,17 @@ def dssim_grad(x, y, w=None):
             xp, yp = x[sl_p], y[sl_p]
             grad[sl_p] += wq * (dS_dmx[sl_q] + dS_dsxx[sl_q] * 2 * (xp - t["mx"][sl_q])
                                 + dS_dsxy[sl_q] * (yp - t["my"][sl_q]))
-    return 1.0 - float(t["S"].mean()), -grad / N
+    return 1.0 - float((t["S"] * m).sum() / N), -grad / N
 
 
-def photometric(x, y, lam: float, w=None):
-    """(L, dL/dx) for L = (1 - lam) mean|x - y| + lam (1 - SSIM)."""
+def photometric(x, y, lam: float, w=None, mask=None):
+    """(L, dL/dx) for L = (1 - lam) L1 + lam (1 - SSIM), each the mean over
+    channels and pixels, weighted by ``mask`` [H, W] when given."""
     x = np.asarray(x, np.float64)
     y = np.asarray(y, np.float64)
-    l1 = float(np.abs(x - y).mean())
-    g1 = np.sign(x - y) / x.size
-    d, gd = dssim_grad(x, y, w)
+    m = np.ones(x.shape[1:]) if mask is None else np.asarray(mask, np.float64)
+    n = x.shape[0] * m.sum()
+    l1 = float((np.abs(x - y) * m).sum() / n)
+    g1 = np.sign(x - y) * m / n
+    d, gd = dssim_grad(x, y, w, mask)
     return (1 - lam) * l1 + lam * d, (1 - lam) * g1 + lam * gd
