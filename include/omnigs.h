@@ -82,14 +82,19 @@ typedef struct {
  *            sampled at (x + 1/2, y + 1/2); any width (the last tile column
  *            may be partial); Gaussians ordered by t_z; t_z <= near_plane
  *            culled; fx, fy > 0 and cx, cy finite (pixels).
- * OMNIGS_ERR_INVALID for an unknown model, reserved != 0 or bad intrinsics. */
+ * rows: the number of image rows rendered, from the top (0 = all H).  The
+ * mapping still uses H; the outputs then have `rows` rows and the rows below
+ * cost nothing, forward or backward (the paper's 360Roam evaluation leaves
+ * the bottom rows out of the loss, Sec. 4).
+ * OMNIGS_ERR_INVALID for an unknown model, rows outside [0, H] or bad
+ * intrinsics. */
 typedef struct {
     double R_cw[9]; /* row-major rotation W of Eq. 1 */
     double t_cw[3];
     int32_t width;  /* image W, <= 65520 */
     int32_t height; /* image H, <= 65520 */
     int32_t model;  /* OMNIGS_CAMERA_ERP or OMNIGS_CAMERA_PINHOLE */
-    int32_t reserved; /* 0 */
+    int32_t rows;   /* rendered rows from the top, 0 = all */
     double fx, fy, cx, cy; /* pinhole intrinsics of Eq. 2 */
 } omnigs_camera;
 
@@ -107,13 +112,17 @@ typedef struct {
     double bg[3];      /* background colour seen through the final transmittance       */
 } omnigs_settings;
 
-/* Per-pixel outputs of the forward pass (device, caller-allocated). */
+/* Per-pixel outputs of the forward pass (device, caller-allocated; H is the
+ * rendered rows).  The alpha image is 1 - final_T. */
 typedef struct {
     float *image;       /* [3][H][W]  C + T_final * bg  (Eq. 6)                   */
     float *final_T;     /* [H][W]     transmittance after the last blended one   */
     int32_t *n_contrib; /* [H][W]     1 + tile-list position of the last blended */
     int32_t *n_blended; /* [H][W]     instances blended (alpha >= alpha_min);
                            optional: NULL skips it                              */
+    float *depth;       /* [H][W]     depth image sum_i d_i alpha_i T_i, d the
+                           sort depth (t_r, or t_z for a pinhole camera), not
+                           normalised by the alpha; optional: NULL skips it    */
 } omnigs_image_out;
 
 /* Saved forward state (filled by omnigs_forward, read by omnigs_backward).
@@ -123,7 +132,7 @@ typedef struct {
     int64_t n;           /* Gaussians                                    */
     int64_t n_instances; /* M: (Gaussian, covered tile) instances         */
     int64_t n_entries;   /* S: (Gaussian, touched 8x8-tile block) entries  */
-    int32_t width, height, tiles_x, tiles_y;
+    int32_t width, height, tiles_x, tiles_y; /* height: the rendered rows */
     const void *records;         /* [n] 48-byte blend records (opaque)              */
     const uint32_t *n_tiles;     /* [n] tiles covered per Gaussian, 0 when culled    */
     const uint32_t *depth_order; /* [n] Gaussian ids sorted by (t_r, id), culled last */
@@ -137,6 +146,7 @@ typedef struct {
     const float *radii;          /* [n] screen radius in pixels (the larger half
                                     extent of the alpha = alpha_min box), 0 when
                                     culled                                          */
+    const float *depth;          /* [n] sort depth d (t_r or t_z) of each Gaussian */
 } omnigs_state;
 
 /* Parameter gradients (device, caller-allocated, overwritten). */
@@ -178,7 +188,11 @@ omnigs_status omnigs_forward(const omnigs_gaussians *g, const omnigs_camera *cam
                              omnigs_allocator alloc, omnigs_image_out *out, omnigs_state *state, void *stream);
 
 /* Backward pass of the render (Sec. 3.4, Eq. 18-20) for an image-space
- * cotangent dL_dimage [3][H][W] (device).  Re-walks each pixel's tile list
+ * cotangent dL_dimage [3][H][W] (device) and, each optional (NULL), the
+ * cotangents dL_ddepth [H][W] of the depth image and dL_dalpha [H][W] of the
+ * alpha image 1 - final_T: both flow back as colour channels with colour d_i
+ * (respectively 1) over a black background, and dL/dd_i reaches the mean
+ * through d t_r / dt = t / t_r (t_z: (0, 0, 1)).  Re-walks each pixel's tile list
  * back to front from the saved final T and n_contrib (recomputing alpha and
  * T rather than reading stored per-pixel lists), accumulates per-Gaussian
  * dL/dp, dL/dSigma2D^-1, dL/do, dL/dcolour with one atomic per field per
@@ -190,7 +204,8 @@ omnigs_status omnigs_forward(const omnigs_gaussians *g, const omnigs_camera *cam
  * Scratch (the accumulators) comes from `alloc`.  Errors as omnigs_forward. */
 omnigs_status omnigs_backward(const omnigs_gaussians *g, const omnigs_camera *cam, const omnigs_settings *s,
                               const omnigs_state *state, const omnigs_image_out *fwd, const float *dL_dimage,
-                              omnigs_grads *grads, omnigs_allocator alloc, void *stream);
+                              const float *dL_ddepth, const float *dL_dalpha, omnigs_grads *grads,
+                              omnigs_allocator alloc, void *stream);
 
 /* L1 photometric term of Eq. 17 (lambda = 0): *loss = mean |image - target|
  * over `count` float32 entries, and dL_dimage = sign(image - target) / count
@@ -205,13 +220,18 @@ omnigs_status omnigs_l1_loss(const float *image, const float *target, int64_t co
  * target|; SSIM is the mean over channels and pixels of the structural
  * similarity on 11x11 Gaussian windows (sigma 1.5; C1 = 0.01^2, C2 = 0.03^2)
  * over zero-padded images (the paper gives the weight lambda in its absent
- * supplement: a parameter here).  *loss (device) receives L and dL_dimage
- * (device, may be NULL) its gradient.  Scratch comes from `alloc`: per-tile
- * partial sums, plus with a gradient 12 bytes per image element (three
- * window-filtered planes).
+ * supplement: a parameter here).  mask (device, [height][width], may be
+ * NULL): per-pixel loss weights m >= 0 with a positive sum, shared by the
+ * channels: both means become m-weighted, L1 = sum m |x - y| / (C sum m) and
+ * SSIM = sum m S / (C sum m), the windows still over the whole images (the
+ * paper leaves the 360Roam images' bottom rows out of the loss, Sec. 4; a
+ * camera's `rows` skips such rows outright).  *loss (device) receives L and
+ * dL_dimage (device, may be NULL) its gradient.  Scratch comes from `alloc`:
+ * per-tile partial sums, plus with a gradient 12 bytes per image element
+ * (three window-filtered planes).
  * OMNIGS_ERR_INVALID for null pointers, sizes < 1 or lambda outside [0, 1]. */
 omnigs_status omnigs_photometric_loss(const float *image, const float *target, int32_t channels, int32_t height,
-                                      int32_t width, double lambda, float *dL_dimage, float *loss,
+                                      int32_t width, double lambda, const float *mask, float *dL_dimage, float *loss,
                                       omnigs_allocator alloc, void *stream);
 
 /* Batched forward render of `batch` cameras (1 <= batch <= OMNIGS_MAX_BATCH,

@@ -62,6 +62,9 @@ struct BlendFrame {
     int32_t *n_contrib;
     int32_t *n_blended;  // forward only, may be null
     const float *dL;     // backward only
+    float *depth;        // forward only: the depth image (with kAux)
+    const float *dLD;    // backward only: dL/ddepth, may be null
+    const float *dLA;    // backward only: dL/dalpha, may be null
 };
 
 struct FrameTable {
@@ -82,11 +85,13 @@ __device__ inline int find_frame(const FrameTable &T, uint32_t tile) {
 // scaled Cholesky factor of the conic: -(l00 dx + l10 dy)^2 - (l11 dy)^2 =
 // log2(e) * (-1/2 d^T Q d).  list[w] holds, for wave w, the staged slots
 // that reach one of its quadrants, in order, as slot | (wave mask << 8).
-template <int kW>
+// With kAux, d holds each staged instance's depth value.
+template <int kW, bool kAux>
 struct Stage {
     static constexpr int kBatch = kWave * kW;
     float4 a[kBatch], b[kBatch];
     float c[kBatch];
+    float d[kAux ? kBatch : 1];
     uint32_t quad[kBatch];
     uint32_t gid[kBatch];
     uint16_t list[kW][kBatch];
@@ -120,9 +125,9 @@ __device__ inline float rect_min_quadratic(float l00, float l10, float l11, floa
 }
 
 // Stage the record of Gaussian gid in slot `slot`.
-template <int kW>
-__device__ inline void stage(const BlendRecord *rec, uint32_t gid, float X0, float Y0, float W, Stage<kW> &S,
-                             int slot) {
+template <int kW, bool kAux>
+__device__ inline void stage(const BlendRecord *rec, const float *rdepth, uint32_t gid, float X0, float Y0, float W,
+                             Stage<kW, kAux> &S, int slot) {
     const float4 *p = reinterpret_cast<const float4 *>(rec + gid);
     const float4 ra4 = p[0], rb4 = p[1], rc4 = p[2];
     float x = (ra4.x - X0) + ra4.y;  // px_hi - X0 is exact near the tile
@@ -153,18 +158,19 @@ __device__ inline void stage(const BlendRecord *rec, uint32_t gid, float X0, flo
     S.a[slot] = make_float4(x, y, l00, l10);
     S.b[slot] = make_float4(l11, rb4.w, rc4.x, rc4.y);
     S.c[slot] = rc4.z;
+    if (kAux) S.d[slot] = rdepth[gid];
     S.quad[slot] = quad;
     S.gid[slot] = gid;
 }
 
 // Wave w lists, in order, the staged slots in [lo, nb) that reach one of its
 // quadrants; returns the count (uniform).
-template <int kW>
-__device__ inline int compact(Stage<kW> &S, int w, int lo, int nb) {
+template <int kW, bool kAux>
+__device__ inline int compact(Stage<kW, kAux> &S, int w, int lo, int nb) {
     constexpr int kPPL = kQuads / kW;
     const int lane = __lane_id();
     int n = 0;
-    for (int c = 0; c < Stage<kW>::kBatch; c += kWave) {
+    for (int c = 0; c < Stage<kW, kAux>::kBatch; c += kWave) {
         const int slot = c + lane;
         const uint32_t m = (slot >= lo && slot < nb) ? (S.quad[slot] >> (w * kPPL)) & ((1u << kPPL) - 1u) : 0u;
         const uint64_t hits = __ballot(m != 0u);
@@ -196,14 +202,15 @@ __device__ __forceinline__ int slot_px(int w, int s, int lx) { return (((w * (kQ
 template <int kW>
 __device__ __forceinline__ int slot_py(int w, int s, int ly) { return (((w * (kQuads / kW)) + s) >> 1) * 8 + ly; }
 
-template <int kW, bool kBatched>
+// kDepth: also the depth image sum_i d_i alpha_i T_i.
+template <int kW, bool kBatched, bool kDepth>
 __global__ __launch_bounds__(kWave * kW) void k_blend_forward(FrameTable FT, const BlendRecord *rec,
-                                                               const uint32_t *inst_gauss, const uint2 *ranges,
-                                                               BlendSettings s, const uint32_t *order,
-                                                               uint32_t *tile_work) {
-    constexpr int kNT = kWave * kW, kPPL = kQuads / kW, kBatch = Stage<kW>::kBatch;
+                                                               const float *rdepth, const uint32_t *inst_gauss,
+                                                               const uint2 *ranges, BlendSettings s,
+                                                               const uint32_t *order, uint32_t *tile_work) {
+    constexpr int kNT = kWave * kW, kPPL = kQuads / kW, kBatch = Stage<kW, kDepth>::kBatch;
     constexpr uint32_t kAll = (1u << kPPL) - 1u;
-    __shared__ Stage<kW> S;
+    __shared__ Stage<kW, kDepth> S;
     __shared__ int s_wmax[kW];
     const uint32_t tile = order ? order[blockIdx.x] : blockIdx.x;
     const int fi = kBatched ? find_frame(FT, tile) : 0;
@@ -216,13 +223,13 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_forward(FrameTable FT, con
     const float X0 = (float)(tx * kTile), Y0 = (float)(ty * kTile);
     const uint2 range = ranges[tile];
     const int count = (int)(range.y - range.x);
-    float T[kPPL], C0[kPPL], C1[kPPL], C2[kPPL];
+    float T[kPPL], C0[kPPL], C1[kPPL], C2[kPPL], Dp[kPPL];
     int last[kPPL], blended[kPPL];
     uint32_t done = 0;
 #pragma unroll
     for (int k = 0; k < kPPL; ++k) {
         T[k] = 1.0f;
-        C0[k] = C1[k] = C2[k] = 0.0f;
+        C0[k] = C1[k] = C2[k] = Dp[k] = 0.0f;
         last[k] = blended[k] = 0;
         if (ty * kTile + slot_py<kW>(w, k, ly) >= F.height || tx * kTile + slot_px<kW>(w, k, lx) >= F.width)
             done |= 1u << k;
@@ -230,7 +237,8 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_forward(FrameTable FT, con
     for (int base = 0; base < count; base += kBatch) {
         if (__syncthreads_count(done == kAll) == kNT) break;
         const int nb = min(kBatch, count - base);
-        if ((int)threadIdx.x < nb) stage(rec, inst_gauss[range.x + base + threadIdx.x], X0, Y0, W, S, threadIdx.x);
+        if ((int)threadIdx.x < nb)
+            stage(rec, rdepth, inst_gauss[range.x + base + threadIdx.x], X0, Y0, W, S, threadIdx.x);
         __syncthreads();
         if (__ballot(done != kAll) == 0ull) continue;  // this wave is finished: keep staging with the others
         const int n = compact(S, w, 0, nb);
@@ -240,6 +248,7 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_forward(FrameTable FT, con
             const uint32_t m = e >> 8;
             const float4 a = S.a[j], b = S.b[j];
             const float cb = S.c[j];
+            const float dj = kDepth ? S.d[j] : 0.0f;
 #pragma unroll
             for (int k = 0; k < kPPL; ++k) {
                 if (!(m & (1u << k))) continue;  // uniform
@@ -255,6 +264,7 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_forward(FrameTable FT, con
                 C0[k] = __builtin_fmaf(b.z, wgt, C0[k]);
                 C1[k] = __builtin_fmaf(b.w, wgt, C1[k]);
                 C2[k] = __builtin_fmaf(cb, wgt, C2[k]);
+                if (kDepth) Dp[k] = __builtin_fmaf(dj, wgt, Dp[k]);
                 T[k] = take ? Tn : T[k];
                 last[k] = take ? base + j + 1 : last[k];
                 blended[k] += take ? 1 : 0;
@@ -288,6 +298,7 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_forward(FrameTable FT, con
         F.final_T[p] = T[k];
         F.n_contrib[p] = last[k];
         if (F.n_blended) F.n_blended[p] = blended[k];
+        if (kDepth) F.depth[p] = Dp[k];
     }
 }
 
@@ -318,9 +329,9 @@ __device__ __forceinline__ float row_sum(float v) {
 // (p, q) leaves rows (2p, 2q, 2p+1, 2q+1)
 __device__ __forceinline__ int field_of(int k, int row) { return 4 * k + ((row & 1) << 1) + (row >> 1); }
 
-__device__ __forceinline__ void wave_reduce_scatter(const float (&v)[kAcc], float (&o)[3]) {
+__device__ __forceinline__ void wave_reduce_scatter(const float (&v)[kAccAux], float (&o)[3]) {
     float a0 = v[0], a1 = v[2], a2 = v[4], a3 = v[6], a4 = v[8];
-    float b0 = v[1], b1 = v[3], b2 = v[5], b3 = v[7], b4 = 0.0f;
+    float b0 = v[1], b1 = v[3], b2 = v[5], b3 = v[7], b4 = v[9];
     swap_add(a0, b0, true);
     swap_add(a1, b1, true);
     swap_add(a2, b2, true);
@@ -335,13 +346,17 @@ __device__ __forceinline__ void wave_reduce_scatter(const float (&v)[kAcc], floa
     o[2] = row_sum(a4);
 }
 
-template <int kW, bool kBatched>
+// kAux: the depth and alpha cotangents too (colour channels with colour
+// d_i and 1 over a black background), and a tenth accumulator dL/dd.
+template <int kW, bool kBatched, bool kAux>
 __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, const BlendRecord *rec,
-                                                                const uint32_t *inst_gauss, const uint2 *ranges,
-                                                                BlendSettings s, float *acc, const uint32_t *order) {
-    constexpr int kPPL = kQuads / kW, kBatch = Stage<kW>::kBatch;
-    __shared__ Stage<kW> S;
-    __shared__ float part[kBatch][kAcc];
+                                                                const float *rdepth, const uint32_t *inst_gauss,
+                                                                const uint2 *ranges, BlendSettings s, float *acc,
+                                                                const uint32_t *order) {
+    constexpr int kPPL = kQuads / kW, kBatch = Stage<kW, kAux>::kBatch;
+    constexpr int kNF = kAux ? kAccAux : kAcc;  // accumulator fields per Gaussian
+    __shared__ Stage<kW, kAux> S;
+    __shared__ float part[kBatch][kNF];
     __shared__ int s_max[kW];
     const uint32_t tile = order ? order[blockIdx.x] : blockIdx.x;
     const int fi = kBatched ? find_frame(FT, tile) : 0;
@@ -354,14 +369,14 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, co
     const float X0 = (float)(tx * kTile), Y0 = (float)(ty * kTile);
     const uint2 range = ranges[tile];
     const int64_t HW = (int64_t)F.width * F.height;
-    float T[kPPL], dLS[kPPL], dL0[kPPL], dL1[kPPL], dL2[kPPL];
+    float T[kPPL], dLS[kPPL], dL0[kPPL], dL1[kPPL], dL2[kPPL], dLD[kPPL], dLA[kPPL];
     int last[kPPL];
     int wmax = 0;
 #pragma unroll
     for (int k = 0; k < kPPL; ++k) {
         const int y = ty * kTile + slot_py<kW>(w, k, ly), x = tx * kTile + slot_px<kW>(w, k, lx);
         T[k] = 1.0f;
-        dL0[k] = dL1[k] = dL2[k] = 0.0f;
+        dL0[k] = dL1[k] = dL2[k] = dLD[k] = dLA[k] = 0.0f;
         last[k] = 0;
         if (y < F.height && x < F.width) {
             const int64_t p = (int64_t)y * F.width + x;
@@ -370,6 +385,10 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, co
             dL0[k] = F.dL[p];
             dL1[k] = F.dL[HW + p];
             dL2[k] = F.dL[2 * HW + p];
+            if (kAux) {
+                dLD[k] = F.dLD ? F.dLD[p] : 0.0f;
+                dLA[k] = F.dLA ? F.dLA[p] : 0.0f;
+            }
         }
         // dL . (colour blended behind the current instance + T_final bg)
         dLS[k] = T[k] * (dL0[k] * s.bg[0] + dL1[k] * s.bg[1] + dL2[k] * s.bg[2]);
@@ -388,9 +407,9 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, co
         __syncthreads();
         if ((int)threadIdx.x < nb) {
             // slot i holds list position hi-1-i
-            stage(rec, inst_gauss[range.x + hi - 1 - threadIdx.x], X0, Y0, W, S, threadIdx.x);
+            stage(rec, rdepth, inst_gauss[range.x + hi - 1 - threadIdx.x], X0, Y0, W, S, threadIdx.x);
 #pragma unroll
-            for (int f = 0; f < kAcc; ++f) part[threadIdx.x][f] = 0.0f;
+            for (int f = 0; f < kNF; ++f) part[threadIdx.x][f] = 0.0f;
         }
         __syncthreads();
         // positions at or past this wave's largest contributor count (slots
@@ -403,9 +422,10 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, co
             const int pos = hi - 1 - j;
             const float4 a = S.a[j], b = S.b[j];
             const float cb = S.c[j];
-            float v[kAcc];
+            const float dj = kAux ? S.d[j] : 0.0f;
+            float v[kAccAux];
 #pragma unroll
-            for (int f = 0; f < kAcc; ++f) v[f] = 0.0f;
+            for (int f = 0; f < kAccAux; ++f) v[f] = 0.0f;
             bool any = false;
 #pragma unroll
             for (int k = 0; k < kPPL; ++k) {
@@ -420,12 +440,14 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, co
                 const float Tf = T[k] * inv;  // transmittance in front of this instance
                 T[k] = valid ? Tf : T[k];
                 const float wgt = valid ? alpha * Tf : 0.0f;
-                const float dLc = dL0[k] * b.z + dL1[k] * b.w + dL2[k] * cb;
+                float dLc = dL0[k] * b.z + dL1[k] * b.w + dL2[k] * cb;
+                if (kAux) dLc += __builtin_fmaf(dLD[k], dj, dLA[k]);  // depth and alpha channels
                 const float dalpha = dLc * Tf - dLS[k] * inv;
                 dLS[k] = __builtin_fmaf(dLc, wgt, dLS[k]);
                 v[6] = __builtin_fmaf(dL0[k], wgt, v[6]);
                 v[7] = __builtin_fmaf(dL1[k], wgt, v[7]);
                 v[8] = __builtin_fmaf(dL2[k], wgt, v[8]);
+                if (kAux) v[9] = __builtin_fmaf(dLD[k], wgt, v[9]);
                 // dL/dalpha through an unclamped alpha only
                 const float da = (valid && araw < s.alpha_max) ? dalpha : 0.0f;
                 // moments of gp = dL/d(-1/2 d^T Q d) = alpha * dL/dalpha
@@ -446,7 +468,7 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, co
 #pragma unroll
                     for (int k = 0; k < 3; ++k) {
                         const int f = field_of(k, row);
-                        if (f >= kAcc) continue;
+                        if (f >= kNF) continue;
                         if (kW == 1) part[j][f] = o[k];
                         else atomicAdd(&part[j][f], o[k]);  // the waves of this instance meet here
                     }
@@ -457,15 +479,15 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, co
         // moments -> screen-space gradients: the staging lane of each slot
         if ((int)threadIdx.x < nb && S.quad[threadIdx.x]) {
             const int j = threadIdx.x;
-            float mo[kAcc];
+            float mo[kNF];
 #pragma unroll
-            for (int f = 0; f < kAcc; ++f) mo[f] = part[j][f];
+            for (int f = 0; f < kNF; ++f) mo[f] = part[j][f];
             // Q = 2 ln2 L L^T (L scaled by sqrt(log2(e) / 2))
             const float4 a = S.a[j], b = S.b[j];
             const float l00 = a.z, l10 = a.w, l11 = b.x;
             const float q00 = 2.0f * kLn2 * l00 * l00, q01 = 2.0f * kLn2 * l00 * l10,
                         q11 = 2.0f * kLn2 * __builtin_fmaf(l10, l10, l11 * l11);
-            float out[kAcc];
+            float out[kNF];
             out[0] = q00 * mo[0] + q01 * mo[1];  // dL/dp_x
             out[1] = q01 * mo[0] + q11 * mo[1];  // dL/dp_y
             out[2] = -0.5f * mo[2];              // dL/dq00
@@ -475,9 +497,10 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, co
             out[6] = mo[6];
             out[7] = mo[7];
             out[8] = mo[8];
-            float *dst = acc + (int64_t)S.gid[j] * kAcc;
+            if (kAux) out[kNF - 1] = mo[kNF - 1];  // dL/dd
+            float *dst = acc + (int64_t)S.gid[j] * kNF;
 #pragma unroll
-            for (int f = 0; f < kAcc; ++f)
+            for (int f = 0; f < kNF; ++f)
                 if (out[f] != 0.0f) atomicAdd(dst + f, out[f]);
         }
     }
@@ -542,54 +565,75 @@ hipError_t launch_tile_order(const uint2 *ranges, const uint32_t *work, uint32_t
     return hipGetLastError();
 }
 
-hipError_t launch_blend_forward(const FrameGeom &f, const BlendRecord *rec, const uint32_t *inst_gauss,
-                                const uint2 *ranges, const BlendSettings &s, float *image, float *final_T,
-                                int32_t *n_contrib, int32_t *n_blended, const uint32_t *order, uint32_t *tile_work,
-                                hipStream_t st) {
+hipError_t launch_blend_forward(const FrameGeom &f, const BlendRecord *rec, const float *rdepth,
+                                const uint32_t *inst_gauss, const uint2 *ranges, const BlendSettings &s, float *image,
+                                float *final_T, int32_t *n_contrib, int32_t *n_blended, float *depth_out,
+                                const uint32_t *order, uint32_t *tile_work, hipStream_t st) {
     FrameTable T{};
     T.n = 1;
     T.f[0] = BlendFrame{f.width, f.height, f.tiles_x, f.tiles_y, 0u, period_of(f), image, final_T, n_contrib,
-                        n_blended, nullptr};
+                        n_blended, nullptr, depth_out, nullptr, nullptr};
     const unsigned tiles = (unsigned)(f.tiles_x * f.tiles_y);
     if (tiles == 0) return hipSuccess;
     constexpr int kW = OMNIGS_FWD_WAVES;
-    hipLaunchKernelGGL((k_blend_forward<kW, false>), dim3(tiles), dim3(kWave * kW), 0, st, T, rec, inst_gauss,
-                       ranges + f.tile_base, s, order, tile_work);
+    if (depth_out)
+        hipLaunchKernelGGL((k_blend_forward<kW, false, true>), dim3(tiles), dim3(kWave * kW), 0, st, T, rec, rdepth,
+                           inst_gauss, ranges + f.tile_base, s, order, tile_work);
+    else
+        hipLaunchKernelGGL((k_blend_forward<kW, false, false>), dim3(tiles), dim3(kWave * kW), 0, st, T, rec,
+                           (const float *)nullptr, inst_gauss, ranges + f.tile_base, s, order, tile_work);
     return hipGetLastError();
 }
 
 hipError_t launch_blend_forward_frames(const FrameGeom *frames, const omnigs_image_out *outs, int count,
-                                       const BlendRecord *rec, const uint32_t *inst_gauss, const uint2 *ranges,
-                                       const BlendSettings &s, const uint32_t *order, uint32_t total_tiles,
-                                       hipStream_t st) {
+                                       const BlendRecord *rec, const float *rdepth, const uint32_t *inst_gauss,
+                                       const uint2 *ranges, const BlendSettings &s, const uint32_t *order,
+                                       uint32_t total_tiles, hipStream_t st) {
     if (count < 1 || count > kMaxBatch) return hipErrorInvalidValue;
     if (total_tiles == 0) return hipSuccess;
     FrameTable T{};
     T.n = count;
+    bool any_depth = false;
     for (int k = 0; k < count; ++k) {
         const FrameGeom &f = frames[k];
         T.f[k] = BlendFrame{f.width, f.height, f.tiles_x, f.tiles_y, f.tile_base, period_of(f), outs[k].image,
-                            outs[k].final_T, outs[k].n_contrib, outs[k].n_blended, nullptr};
+                            outs[k].final_T, outs[k].n_contrib, outs[k].n_blended, nullptr, outs[k].depth,
+                            nullptr, nullptr};
+        any_depth |= outs[k].depth != nullptr;
     }
     constexpr int kW = OMNIGS_FWD_WAVES;
-    hipLaunchKernelGGL((k_blend_forward<kW, true>), dim3(total_tiles), dim3(kWave * kW), 0, st, T, rec, inst_gauss,
-                       ranges, s, order, (uint32_t *)nullptr);
+    if (any_depth) {
+        // every frame then needs a depth buffer
+        for (int k = 0; k < count; ++k)
+            if (!T.f[k].depth) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_blend_forward<kW, true, true>), dim3(total_tiles), dim3(kWave * kW), 0, st, T, rec,
+                           rdepth, inst_gauss, ranges, s, order, (uint32_t *)nullptr);
+    } else {
+        hipLaunchKernelGGL((k_blend_forward<kW, true, false>), dim3(total_tiles), dim3(kWave * kW), 0, st, T, rec,
+                           (const float *)nullptr, inst_gauss, ranges, s, order, (uint32_t *)nullptr);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_blend_backward(const FrameGeom &f, const BlendRecord *rec, const uint32_t *inst_gauss,
-                                 const uint2 *ranges, const BlendSettings &s, const float *final_T,
-                                 const int32_t *n_contrib, const float *dL_dimage, float *acc, const uint32_t *order,
+hipError_t launch_blend_backward(const FrameGeom &f, const BlendRecord *rec, const float *rdepth,
+                                 const uint32_t *inst_gauss, const uint2 *ranges, const BlendSettings &s,
+                                 const float *final_T, const int32_t *n_contrib, const float *dL_dimage,
+                                 const float *dL_ddepth, const float *dL_dalpha, float *acc, const uint32_t *order,
                                  hipStream_t st) {
     FrameTable T{};
     T.n = 1;
     T.f[0] = BlendFrame{f.width, f.height, f.tiles_x, f.tiles_y, 0u, period_of(f), nullptr,
-                        const_cast<float *>(final_T), const_cast<int32_t *>(n_contrib), nullptr, dL_dimage};
+                        const_cast<float *>(final_T), const_cast<int32_t *>(n_contrib), nullptr, dL_dimage, nullptr,
+                        dL_ddepth, dL_dalpha};
     const unsigned tiles = (unsigned)(f.tiles_x * f.tiles_y);
     if (tiles == 0) return hipSuccess;
     constexpr int kW = OMNIGS_BWD_WAVES;
-    hipLaunchKernelGGL((k_blend_backward<kW, false>), dim3(tiles), dim3(kWave * kW), 0, st, T, rec, inst_gauss,
-                       ranges + f.tile_base, s, acc, order);
+    if (dL_ddepth || dL_dalpha)
+        hipLaunchKernelGGL((k_blend_backward<kW, false, true>), dim3(tiles), dim3(kWave * kW), 0, st, T, rec, rdepth,
+                           inst_gauss, ranges + f.tile_base, s, acc, order);
+    else
+        hipLaunchKernelGGL((k_blend_backward<kW, false, false>), dim3(tiles), dim3(kWave * kW), 0, st, T, rec,
+                           (const float *)nullptr, inst_gauss, ranges + f.tile_base, s, acc, order);
     return hipGetLastError();
 }
 

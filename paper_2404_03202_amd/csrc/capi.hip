@@ -153,7 +153,8 @@ omnigs_status check_camera(const omnigs_camera *c) {
     if (!c) return fail(OMNIGS_ERR_INVALID, "camera is NULL");
     if (c->model != OMNIGS_CAMERA_ERP && c->model != OMNIGS_CAMERA_PINHOLE)
         return fail(OMNIGS_ERR_INVALID, "unknown camera model %d", c->model);
-    if (c->reserved != 0) return fail(OMNIGS_ERR_INVALID, "camera field 'reserved' must be 0");
+    if (c->rows < 0 || c->rows > c->height)
+        return fail(OMNIGS_ERR_INVALID, "rows %d not in [0, height %d]", c->rows, c->height);
     if (c->model == OMNIGS_CAMERA_ERP && (c->width <= 0 || c->width % kTile != 0 || c->width > 65520))
         return fail(OMNIGS_ERR_INVALID, "ERP width %d must be a positive multiple of 16, <= 65520", c->width);
     if (c->model == OMNIGS_CAMERA_PINHOLE) {
@@ -207,7 +208,8 @@ ProjectArgs make_project_args(const omnigs_gaussians *g, const omnigs_camera *c,
     // the ERP width is a multiple of the tile; a pinhole image may end in a
     // partial tile column
     a.tiles_x = (c->width + kTile - 1) / kTile;
-    a.tiles_y = (c->height + kTile - 1) / kTile;
+    a.rows = c->rows > 0 ? c->rows : c->height;  // the image holds the top `rows` rows
+    a.tiles_y = (a.rows + kTile - 1) / kTile;
     a.alpha_min = s->alpha_min;
     a.dilation = s->dilation;
     a.near_plane = s->near_plane;
@@ -234,7 +236,7 @@ struct GeomState {
     BlendRecord *rec;
     uint32_t *n_tiles, *order;
     uint2 *rect;
-    float *radii;
+    float *radii, *depth;
     void carve(Arena &a, int64_t n) {
         const size_t m = (size_t)(n > 0 ? n : 1);
         rec = a.take<BlendRecord>(m);
@@ -242,6 +244,7 @@ struct GeomState {
         order = a.take<uint32_t>(m);
         rect = a.take<uint2>(m);
         radii = a.take<float>(m);
+        depth = a.take<float>(m);
     }
 };
 struct GeomScratch {
@@ -394,8 +397,8 @@ omnigs_status omnigs_forward(const omnigs_gaussians *g, const omnigs_camera *cam
 
     {
         StageTimer t(st, kStProject);
-        HIP_TRY(launch_project(pa, gst.rec, gs.depth_key, gst.n_tiles, gst.rect, gs.n_super, gst.radii, gs.totals + 1,
-                               st));
+        HIP_TRY(launch_project(pa, gst.rec, gs.depth_key, gst.depth, gst.n_tiles, gst.rect, gs.n_super, gst.radii,
+                               gs.totals + 1, st));
     }
     if ((rc = sort_and_count(n, gst, gs, st)) != OMNIGS_OK) return rc;
 
@@ -441,15 +444,15 @@ omnigs_status omnigs_forward(const omnigs_gaussians *g, const omnigs_camera *cam
     }
     {
         StageTimer t(st, kStBlendFwd);
-        FrameGeom f{cam->width, cam->height, pa.tiles_x, pa.tiles_y, 0u, pa.model == OMNIGS_CAMERA_ERP};
-        HIP_TRY(launch_blend_forward(f, gst.rec, inst_gauss, ranges, make_blend_settings(s), out->image, out->final_T,
-                                     out->n_contrib, out->n_blended, order, tile_work, st));
+        FrameGeom f{cam->width, pa.rows, pa.tiles_x, pa.tiles_y, 0u, pa.model == OMNIGS_CAMERA_ERP};
+        HIP_TRY(launch_blend_forward(f, gst.rec, gst.depth, inst_gauss, ranges, make_blend_settings(s), out->image,
+                                     out->final_T, out->n_contrib, out->n_blended, out->depth, order, tile_work, st));
     }
     state->n = n;
     state->n_instances = M;
     state->n_entries = S;
     state->width = cam->width;
-    state->height = cam->height;
+    state->height = pa.rows;
     state->tiles_x = pa.tiles_x;
     state->tiles_y = pa.tiles_y;
     state->records = gst.rec;
@@ -459,12 +462,14 @@ omnigs_status omnigs_forward(const omnigs_gaussians *g, const omnigs_camera *cam
     state->tile_range = reinterpret_cast<const uint32_t *>(ranges);
     state->tile_work = tile_work;
     state->radii = gst.radii;
+    state->depth = gst.depth;
     return OMNIGS_OK;
 }
 
 omnigs_status omnigs_backward(const omnigs_gaussians *g, const omnigs_camera *cam, const omnigs_settings *s,
                               const omnigs_state *state, const omnigs_image_out *fwd, const float *dL_dimage,
-                              omnigs_grads *grads, omnigs_allocator alloc, void *stream) {
+                              const float *dL_ddepth, const float *dL_dalpha, omnigs_grads *grads,
+                              omnigs_allocator alloc, void *stream) {
     omnigs_status rc;
     if ((rc = check_gaussians(g)) != OMNIGS_OK) return rc;
     if ((rc = check_camera(cam)) != OMNIGS_OK) return rc;
@@ -477,8 +482,11 @@ omnigs_status omnigs_backward(const omnigs_gaussians *g, const omnigs_camera *ca
         return fail(OMNIGS_ERR_INVALID, "a gradient output pointer is NULL");
     if (g->n > 0 && reinterpret_cast<uintptr_t>(grads->dquats) % 16 != 0)
         return fail(OMNIGS_ERR_INVALID, "dquats must be 16-byte aligned");
-    if (state->n != g->n || state->width != cam->width || state->height != cam->height)
+    const bool aux = dL_ddepth || dL_dalpha;
+    if (state->n != g->n || state->width != cam->width ||
+        state->height != (cam->rows > 0 ? cam->rows : cam->height))
         return fail(OMNIGS_ERR_INVALID, "state does not match the Gaussians / camera");
+    if (aux && g->n > 0 && !state->depth) return fail(OMNIGS_ERR_INVALID, "state depth buffer is NULL");
     if (g->n > 0 && (!state->records || !state->n_tiles || !state->inst_gauss || !state->tile_range ||
                      !state->tile_work))
         return fail(OMNIGS_ERR_INVALID, "state buffers are NULL");
@@ -487,31 +495,32 @@ omnigs_status omnigs_backward(const omnigs_gaussians *g, const omnigs_camera *ca
     if (n == 0) return OMNIGS_OK;
     const ProjectArgs pa = make_project_args(g, cam, s);
     const uint32_t ntiles = (uint32_t)(pa.tiles_x * pa.tiles_y);
+    const int nacc = aux ? kAccAux : kAcc;  // accumulator fields per Gaussian
     Arena a;
-    a.take<float>((size_t)n * kAcc);
+    a.take<float>((size_t)n * nacc);
     a.take<uint32_t>(ntiles);
     if ((rc = alloc_arena(alloc, a.off, OMNIGS_MEM_SCRATCH, a, "gradient accumulators")) != OMNIGS_OK) return rc;
-    float *acc = a.take<float>((size_t)n * kAcc);
+    float *acc = a.take<float>((size_t)n * nacc);
     uint32_t *order = a.take<uint32_t>(ntiles);
     const auto *rec = static_cast<const BlendRecord *>(state->records);
     const auto *ranges = reinterpret_cast<const uint2 *>(state->tile_range);
     {
         StageTimer t(st, kStBwdClear);
-        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(acc), 0u, n * kAcc, st));
+        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(acc), 0u, n * nacc, st));
     }
-    const FrameGeom f{cam->width, cam->height, pa.tiles_x, pa.tiles_y, 0u, pa.model == OMNIGS_CAMERA_ERP};
+    const FrameGeom f{cam->width, pa.rows, pa.tiles_x, pa.tiles_y, 0u, pa.model == OMNIGS_CAMERA_ERP};
     {
         StageTimer t(st, kStTileOrder);
         HIP_TRY(launch_tile_order(ranges, state->tile_work, ntiles, order, st));
     }
     {
         StageTimer t(st, kStBlendBwd);
-        HIP_TRY(launch_blend_backward(f, rec, state->inst_gauss, ranges, make_blend_settings(s), fwd->final_T,
-                                      fwd->n_contrib, dL_dimage, acc, order, st));
+        HIP_TRY(launch_blend_backward(f, rec, state->depth, state->inst_gauss, ranges, make_blend_settings(s),
+                                      fwd->final_T, fwd->n_contrib, dL_dimage, dL_ddepth, dL_dalpha, acc, order, st));
     }
     {
         StageTimer t(st, kStProjectBwd);
-        HIP_TRY(launch_project_backward(pa, state->n_tiles, acc, *grads, st));
+        HIP_TRY(launch_project_backward(pa, state->n_tiles, acc, nacc, *grads, st));
     }
     return OMNIGS_OK;
 }
@@ -532,7 +541,7 @@ omnigs_status omnigs_l1_loss(const float *image, const float *target, int64_t co
 }
 
 omnigs_status omnigs_photometric_loss(const float *image, const float *target, int32_t channels, int32_t height,
-                                      int32_t width, double lambda, float *dL_dimage, float *loss,
+                                      int32_t width, double lambda, const float *mask, float *dL_dimage, float *loss,
                                       omnigs_allocator alloc, void *stream) {
     if (!image || !target || !loss) return fail(OMNIGS_ERR_INVALID, "image, target or loss is NULL");
     if (channels < 1 || height < 1 || width < 1 || channels > 64 || height > 65520 || width > 65520)
@@ -546,7 +555,8 @@ omnigs_status omnigs_photometric_loss(const float *image, const float *target, i
         return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
     StageTimer t(st, kStL1);
-    HIP_TRY(launch_photometric(image, target, channels, height, width, (float)lambda, dL_dimage, loss, a.base, st));
+    HIP_TRY(launch_photometric(image, target, mask, channels, height, width, (float)lambda, dL_dimage, loss, a.base,
+                               st));
     return OMNIGS_OK;
 }
 
@@ -579,6 +589,8 @@ omnigs_status omnigs_forward_batch(const omnigs_gaussians *g, const omnigs_camer
         if ((rc = check_camera(&cams[b])) != OMNIGS_OK) return rc;
         if (!outs[b].image || !outs[b].final_T || !outs[b].n_contrib)
             return fail(OMNIGS_ERR_INVALID, "output pointer of camera %d is NULL", b);
+        if ((outs[b].depth != nullptr) != (outs[0].depth != nullptr))
+            return fail(OMNIGS_ERR_INVALID, "depth images must be requested for every camera of a batch or for none");
         const ProjectArgs pb = make_project_args(g, &cams[b], s);
         CamGeom &cg = ct.c[b];
         for (int k = 0; k < 9; ++k) cg.R[k] = pb.R[k];
@@ -588,6 +600,7 @@ omnigs_status omnigs_forward_batch(const omnigs_gaussians *g, const omnigs_camer
         }
         cg.width = pb.width;
         cg.height = pb.height;
+        cg.rows = pb.rows;
         cg.tiles_x = pb.tiles_x;
         cg.tiles_y = pb.tiles_y;
         cg.model = pb.model;
@@ -595,7 +608,7 @@ omnigs_status omnigs_forward_batch(const omnigs_gaussians *g, const omnigs_camer
         cg.fy = pb.fy;
         cg.cx = pb.cx;
         cg.cy = pb.cy;
-        frames[b] = FrameGeom{pb.width, pb.height, pb.tiles_x, pb.tiles_y, (uint32_t)total_tiles,
+        frames[b] = FrameGeom{pb.width, pb.rows, pb.tiles_x, pb.tiles_y, (uint32_t)total_tiles,
                               pb.model == OMNIGS_CAMERA_ERP};
         total_tiles += (uint64_t)pb.tiles_x * pb.tiles_y;
         if (total_tiles >= (uint64_t(1) << 31)) return fail(OMNIGS_ERR_INVALID, "too many tiles in the batch");
@@ -619,7 +632,8 @@ omnigs_status omnigs_forward_batch(const omnigs_gaussians *g, const omnigs_camer
     if (overflow) HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(overflow), 0u, 1, st));
     {
         StageTimer t(st, kStProject);
-        HIP_TRY(launch_project_batch(pa, ct, gst.rec, gs.depth_key, gst.n_tiles, gst.rect, gs.n_super, gs.totals + 1,
+        HIP_TRY(launch_project_batch(pa, ct, gst.rec, gs.depth_key, gst.depth, gst.n_tiles, gst.rect, gs.n_super,
+                                     gs.totals + 1,
                                      st));
     }
     if ((rc = sort_and_count(nrec, gst, gs, st)) != OMNIGS_OK) return rc;
@@ -662,7 +676,8 @@ omnigs_status omnigs_forward_batch(const omnigs_gaussians *g, const omnigs_camer
     }
     {
         StageTimer t(st, kStBlendFwd);
-        HIP_TRY(launch_blend_forward_frames(frames, outs, batch, gst.rec, inst_gauss, ranges, make_blend_settings(s),
+        HIP_TRY(launch_blend_forward_frames(frames, outs, batch, gst.rec, gst.depth, inst_gauss, ranges,
+                                            make_blend_settings(s),
                                             order, ntiles, st));
     }
     return OMNIGS_OK;

@@ -30,8 +30,10 @@ struct alignas(16) BlendRecord {
 static_assert(sizeof(BlendRecord) == 48, "record layout");
 
 // Per-Gaussian screen-space gradient accumulators written by the backward
-// blend: dL/dp (2), dL/dQ (q00, q01, q11), dL/do, dL/drgb (3).
+// blend: dL/dp (2), dL/dQ (q00, q01, q11), dL/do, dL/drgb (3); with the
+// depth / alpha cotangents a tenth, dL/dd (the Gaussian's depth value).
 constexpr int kAcc = 9;
+constexpr int kAccAux = 10;
 
 // Depth-sort key of a culled Gaussian: sorts after every finite depth.
 constexpr uint32_t kCulledKey = 0xffffffffu;
@@ -42,6 +44,7 @@ struct ProjectArgs {
     int sh_degree, sh_coeffs;
     double R[9], t[3], campos[3];
     int width, height, tiles_x, tiles_y;
+    int rows;                  // rendered rows (<= height; tiles_y covers them)
     int model;                 // OMNIGS_CAMERA_ERP or OMNIGS_CAMERA_PINHOLE
     double fx, fy, cx, cy;     // pinhole intrinsics (Eq. 2)
     double alpha_min, dilation, near_plane;
@@ -56,7 +59,7 @@ struct FrameGeom {  // one camera's image inside a (possibly batched) launch
 // Camera-dependent part of ProjectArgs, one entry per camera of a batch.
 struct CamGeom {
     double R[9], t[3], campos[3];
-    int width, height, tiles_x, tiles_y;
+    int width, height, tiles_x, tiles_y, rows;
     int model;
     double fx, fy, cx, cy;
 };
@@ -125,18 +128,20 @@ struct SuperTable {
 };
 
 // Host-side launchers (each .hip file owns its kernels).
-// Per record: blend record, depth key, tiles covered, tile rectangle,
-// super-tiles touched and screen radius (radii may be null); *tiles_total
-// (device) receives the sum of the tiles covered (M).
-hipError_t launch_project(const ProjectArgs &a, BlendRecord *rec, uint32_t *depth_key, uint32_t *n_tiles,
+// Per record: blend record, depth key, depth value (t_r or t_z; depth may
+// be null), tiles covered, tile rectangle, super-tiles touched and screen
+// radius (radii may be null); *tiles_total (device) receives the sum of the
+// tiles covered (M).
+hipError_t launch_project(const ProjectArgs &a, BlendRecord *rec, uint32_t *depth_key, float *depth, uint32_t *n_tiles,
                           uint2 *rect, uint32_t *n_super, float *radii, uint32_t *tiles_total, hipStream_t st);
 // All cameras of `cams` in one launch: the outputs of camera b for Gaussian i
 // land at index b * a.n + i, bit-identical to launch_project of that camera
 // (a's camera fields are ignored).
 hipError_t launch_project_batch(const ProjectArgs &a, const CamTable &cams, BlendRecord *rec, uint32_t *depth_key,
-                                uint32_t *n_tiles, uint2 *rect, uint32_t *n_super, uint32_t *tiles_total,
-                                hipStream_t st);
-hipError_t launch_project_backward(const ProjectArgs &a, const uint32_t *n_tiles, const float *acc,
+                                float *depth, uint32_t *n_tiles, uint2 *rect, uint32_t *n_super,
+                                uint32_t *tiles_total, hipStream_t st);
+// acc: [n][acc_stride] accumulators, acc_stride kAcc or kAccAux.
+hipError_t launch_project_backward(const ProjectArgs &a, const uint32_t *n_tiles, const float *acc, int acc_stride,
                                    const omnigs_grads &gr, hipStream_t st);
 
 // radix sort of (u32 key, u32 value) pairs on the low `bits` bits of the key;
@@ -191,20 +196,24 @@ struct BlendSettings {
 };
 // `order` (device, may be null): launch order of the tiles (a permutation).
 // The forward writes each tile's largest contributor count (the backward's
-// walk length) to tile_work (may be null).
-hipError_t launch_blend_forward(const FrameGeom &f, const BlendRecord *rec, const uint32_t *inst_gauss,
-                                const uint2 *ranges, const BlendSettings &s, float *image, float *final_T,
-                                int32_t *n_contrib, int32_t *n_blended, const uint32_t *order, uint32_t *tile_work,
-                                hipStream_t st);
+// walk length) to tile_work (may be null).  With depth_out, the depth image
+// from the per-record depth values rdepth.
+hipError_t launch_blend_forward(const FrameGeom &f, const BlendRecord *rec, const float *rdepth,
+                                const uint32_t *inst_gauss, const uint2 *ranges, const BlendSettings &s, float *image,
+                                float *final_T, int32_t *n_contrib, int32_t *n_blended, float *depth_out,
+                                const uint32_t *order, uint32_t *tile_work, hipStream_t st);
 // Forward blend of several images in one launch over their concatenated
 // tile space (frames[k].tile_base ascending, total_tiles in all).
 hipError_t launch_blend_forward_frames(const FrameGeom *frames, const omnigs_image_out *outs, int count,
-                                       const BlendRecord *rec, const uint32_t *inst_gauss, const uint2 *ranges,
-                                       const BlendSettings &s, const uint32_t *order, uint32_t total_tiles,
-                                       hipStream_t st);
-hipError_t launch_blend_backward(const FrameGeom &f, const BlendRecord *rec, const uint32_t *inst_gauss,
-                                 const uint2 *ranges, const BlendSettings &s, const float *final_T,
-                                 const int32_t *n_contrib, const float *dL_dimage, float *acc, const uint32_t *order,
+                                       const BlendRecord *rec, const float *rdepth, const uint32_t *inst_gauss,
+                                       const uint2 *ranges, const BlendSettings &s, const uint32_t *order,
+                                       uint32_t total_tiles, hipStream_t st);
+// With dL_ddepth or dL_dalpha (either may be null) the accumulators have
+// kAccAux fields per Gaussian, else kAcc; rdepth is read only then.
+hipError_t launch_blend_backward(const FrameGeom &f, const BlendRecord *rec, const float *rdepth,
+                                 const uint32_t *inst_gauss, const uint2 *ranges, const BlendSettings &s,
+                                 const float *final_T, const int32_t *n_contrib, const float *dL_dimage,
+                                 const float *dL_ddepth, const float *dL_dalpha, float *acc, const uint32_t *order,
                                  hipStream_t st);
 // Longest-first tile order from the list lengths (work == null) or from a
 // per-tile work array.  One workgroup; ntiles unbounded.
@@ -242,11 +251,12 @@ hipError_t launch_dens_scatter(const OptimArrays &P, const OptimArrays &M1, cons
 hipError_t launch_reset_opacity(float *logits, float *m1, float *m2, int64_t n, float lo, hipStream_t st);
 
 // Photometric loss (1 - lambda) L1 + lambda (1 - SSIM) of [channels][H][W]
-// images and its gradient (grad may be null); scratch from
-// ssim_scratch_bytes (with_grad: room for the three filtered planes).
+// images, weighted by the [H][W] mask (may be null), and its gradient (grad
+// may be null); scratch from ssim_scratch_bytes (with_grad: room for the
+// three filtered planes).
 size_t ssim_scratch_bytes(int channels, int height, int width, bool with_grad);
-hipError_t launch_photometric(const float *image, const float *target, int channels, int height, int width,
-                              float lambda, float *grad, float *loss, void *scratch, hipStream_t st);
+hipError_t launch_photometric(const float *image, const float *target, const float *mask, int channels, int height,
+                              int width, float lambda, float *grad, float *loss, void *scratch, hipStream_t st);
 
 // L1 loss.
 size_t l1_scratch_bytes();

@@ -77,13 +77,15 @@ constexpr float kC1 = 0.01f * 0.01f, kC2 = 0.03f * 0.03f;
 
 struct SsimArgs {
     const float *x, *y;
-    float *planes;    // [3][channels][H][W]: D, B, C (null: loss only)
+    const float *mask;  // [H][W] loss weights (null: all 1)
+    float *planes;    // [3][channels][H][W]: D, B, C, weighted by the mask (null: loss only)
     float *grad;      // may be null
-    double *partial;  // [tiles][2]: sum S, sum |x - y| over the tile
+    double *partial;  // [tiles][3]: sums of m S, m |x - y| and m over the tile
+    float *scale;     // 1 / (C sum m), written by the final reduction for the gradient
     int64_t plane_stride;  // channels * H * W
     int width, height, tiles_x, tiles_y, tiles, per_xcd;
     float w1[kTaps];  // normalised 1D Gaussian, sigma 1.5
-    float lambda, inv_n;
+    float lambda;
 };
 
 // Tile of this workgroup.  Consecutive workgroups go to the 8 XCDs in turn,
@@ -180,10 +182,11 @@ __device__ inline double wave_sum(double v) {
 constexpr int kLdsStats = 5 * kSsimTH * kVPitch > 2 * kSsimIH * kSsimIW ? 5 * kSsimTH * kVPitch : 2 * kSsimIH * kSsimIW;
 constexpr int kLdsGrad = 3 * kSsimTH * kVPitch > 3 * kSsimIH * kSsimIW ? 3 * kSsimTH * kVPitch : 3 * kSsimIH * kSsimIW;
 
-// Window statistics, S, the planes D, B, C and the tile's sums of S, |x - y|.
+// Window statistics, S, the planes D, B, C (weighted by the loss mask m at
+// the window centre) and the tile's sums of m S, m |x - y| and m.
 __global__ __launch_bounds__(kSsimThreads) void k_ssim_stats(SsimArgs a) {
     __shared__ float lds[kLdsStats];
-    __shared__ double red[2][kSsimThreads / 64];
+    __shared__ double red[3][kSsimThreads / 64];
     int c, tx0, ty0;
     const int tile = ssim_tile(a, c, tx0, ty0);
     if (tile < 0) return;
@@ -197,7 +200,15 @@ __global__ __launch_bounds__(kSsimThreads) void k_ssim_stats(SsimArgs a) {
     double l1_sum = 0.0;
     if (k < kPass1Items) {
         const int h = k / kSsimIW, q = k - h * kSsimIW;
-        const bool own_col = q >= kSsimR && q < kSsimR + kSsimTW;
+        const int gx = tx0 - kSsimR + q;
+        const bool own_col = q >= kSsimR && q < kSsimR + kSsimTW && gx < a.width;
+        // loss weights of this column's own pixels (zero outside the image)
+        float mw[kRun];
+#pragma unroll
+        for (int j = 0; j < kRun; ++j) {
+            const int gy = ty0 + h * kRun + j;
+            mw[j] = !a.mask ? 1.0f : (own_col && gy < a.height ? a.mask[(int64_t)gy * a.width + gx] : 0.0f);
+        }
         float l1 = 0.0f;
 #pragma unroll
         for (int t = 0; t < kRun + kTaps - 1; ++t) {
@@ -205,14 +216,14 @@ __global__ __launch_bounds__(kSsimThreads) void k_ssim_stats(SsimArgs a) {
             const float xv = lds[row * kSsimIW + q], yv = lds[(kSsimIH + row) * kSsimIW + q];
             const float v[5] = {xv, yv, xv * xv, yv * yv, xv * yv};
             add_row<5>(acc, v, t, a.w1);
-            if (t >= kSsimR && t < kSsimR + kRun) l1 += fabsf(xv - yv);
+            if (t >= kSsimR && t < kSsimR + kRun) l1 = __builtin_fmaf(mw[t - kSsimR], fabsf(xv - yv), l1);
         }
         if (own_col) l1_sum = (double)l1;
     }
     __syncthreads();
     store_vertical<5>(lds, acc, k);
     __syncthreads();
-    double s_sum = 0.0;
+    double s_sum = 0.0, m_sum = 0.0;
     if (k < kPass2Items) {
         const int r = k % kSsimTH, g = k / kSsimTH;
         float m[kRun][5];
@@ -222,43 +233,50 @@ __global__ __launch_bounds__(kSsimThreads) void k_ssim_stats(SsimArgs a) {
         for (int j = 0; j < kRun; ++j) {
             const int col = g * kRun + j, gx = tx0 + col;
             if (col >= kSsimTW || gx >= a.width || gy >= a.height) continue;
+            const float wq = a.mask ? a.mask[(int64_t)gy * a.width + gx] : 1.0f;
+            m_sum += (double)wq;
             const float mx = m[j][0], my = m[j][1];
             const float vxx = m[j][2] - mx * mx, vyy = m[j][3] - my * my, vxy = m[j][4] - mx * my;
             const float n1 = 2.0f * mx * my + kC1, n2 = 2.0f * vxy + kC2;
             const float d1 = mx * mx + my * my + kC1, d2 = vxx + vyy + kC2;
             const float inv = 1.0f / (d1 * d2);
             const float S = n1 * n2 * inv;
-            s_sum += (double)S;
+            s_sum += (double)(wq * S);
             if (a.planes) {
                 const float A = 2.0f * my * n2 * inv - S * 2.0f * mx / d1;  // dS/dmu_x
                 const float B = -S / d2;                                    // dS/ds_xx
                 const float C = 2.0f * n1 * inv;                            // dS/ds_xy
                 const int64_t o = c * plane + (int64_t)gy * a.width + gx;
-                a.planes[o] = A - 2.0f * B * mx - C * my;
-                a.planes[a.plane_stride + o] = B;
-                a.planes[2 * a.plane_stride + o] = C;
+                a.planes[o] = wq * (A - 2.0f * B * mx - C * my);
+                a.planes[a.plane_stride + o] = wq * B;
+                a.planes[2 * a.plane_stride + o] = wq * C;
             }
         }
     }
     s_sum = wave_sum(s_sum);
     l1_sum = wave_sum(l1_sum);
+    m_sum = wave_sum(m_sum);
     if ((k & 63) == 0) {
         red[0][k >> 6] = s_sum;
         red[1][k >> 6] = l1_sum;
+        red[2][k >> 6] = m_sum;
     }
     __syncthreads();
     if (k == 0) {
-        double s = 0.0, l = 0.0;
+        double s = 0.0, l = 0.0, mm = 0.0;
         for (int w = 0; w < kSsimThreads / 64; ++w) {
             s += red[0][w];
             l += red[1][w];
+            mm += red[2][w];
         }
-        a.partial[2 * tile] = s;
-        a.partial[2 * tile + 1] = l;
+        a.partial[3 * tile] = s;
+        a.partial[3 * tile + 1] = l;
+        a.partial[3 * tile + 2] = mm;
     }
 }
 
-// dL/dx = [(1 - lambda) sign(x - y) - lambda (G*D + 2 x G*B + y G*C)] / N.
+// dL/dx = [(1 - lambda) m sign(x - y) - lambda (G*D + 2 x G*B + y G*C)] / N
+// with N = C sum m from the final reduction (the planes carry m already).
 __global__ __launch_bounds__(kSsimThreads) void k_ssim_grad(SsimArgs a) {
     __shared__ float lds[kLdsGrad];
     int c, tx0, ty0;
@@ -268,7 +286,7 @@ __global__ __launch_bounds__(kSsimThreads) void k_ssim_grad(SsimArgs a) {
     // x, y at this thread's outputs, fetched while the passes run
     const int r = k % kSsimTH, g = k / kSsimTH;
     const int gy = ty0 + r;
-    float xv[kRun], yv[kRun];
+    float xv[kRun], yv[kRun], mv[kRun];
 #pragma unroll
     for (int j = 0; j < kRun; ++j) {
         const int col = g * kRun + j, gx = tx0 + col;
@@ -276,6 +294,7 @@ __global__ __launch_bounds__(kSsimThreads) void k_ssim_grad(SsimArgs a) {
         const int64_t o = c * plane + (int64_t)gy * a.width + gx;
         xv[j] = own ? a.x[o] : 0.0f;
         yv[j] = own ? a.y[o] : 0.0f;
+        mv[j] = !a.mask ? 1.0f : (own ? a.mask[(int64_t)gy * a.width + gx] : 0.0f);
     }
     const float *const src[3] = {a.planes, a.planes + a.plane_stride, a.planes + 2 * a.plane_stride};
     load_halo<3>(lds, src, c * plane, tx0, ty0, a.width, a.height);
@@ -297,7 +316,7 @@ __global__ __launch_bounds__(kSsimThreads) void k_ssim_grad(SsimArgs a) {
     if (k >= kPass2Items || gy >= a.height) return;
     float m[kRun][3];
     horizontal<3>(lds, r, g, a.w1, m);
-    const float l1w = 1.0f - a.lambda;
+    const float l1w = 1.0f - a.lambda, inv_n = *a.scale;
 #pragma unroll
     for (int j = 0; j < kRun; ++j) {
         const int col = g * kRun + j, gx = tx0 + col;
@@ -306,30 +325,39 @@ __global__ __launch_bounds__(kSsimThreads) void k_ssim_grad(SsimArgs a) {
         const float dS = m[j][0] + 2.0f * xv[j] * m[j][1] + yv[j] * m[j][2];
         const float d = xv[j] - yv[j];
         const float sgn = d > 0.0f ? 1.0f : (d < 0.0f ? -1.0f : 0.0f);
-        a.grad[o] = a.inv_n * (l1w * sgn - a.lambda * dS);
+        a.grad[o] = inv_n * (l1w * mv[j] * sgn - a.lambda * dS);
     }
 }
 
-// loss = (1 - lambda) sum|x - y| / N + lambda (1 - sum S / N), in a fixed order
-__global__ __launch_bounds__(256) void k_ssim_final(const double *partial, int64_t blocks, double n, double lambda,
-                                                    float *loss) {
-    __shared__ double red[2][256];
-    double s = 0.0, l = 0.0;
+// loss = (1 - lambda) sum m|x - y| / N + lambda (1 - sum m S / N),
+// N = sum over the tiles of sum m (C sum m over the pixels), in a fixed
+// order; 1 / N goes to *scale for the gradient.
+__global__ __launch_bounds__(256) void k_ssim_final(const double *partial, int64_t blocks, double lambda,
+                                                    float *loss, float *scale) {
+    __shared__ double red[3][256];
+    double s = 0.0, l = 0.0, mm = 0.0;
     for (int64_t k = threadIdx.x; k < blocks; k += 256) {
-        s += partial[2 * k];
-        l += partial[2 * k + 1];
+        s += partial[3 * k];
+        l += partial[3 * k + 1];
+        mm += partial[3 * k + 2];
     }
     red[0][threadIdx.x] = s;
     red[1][threadIdx.x] = l;
+    red[2][threadIdx.x] = mm;
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
         if (threadIdx.x < off) {
             red[0][threadIdx.x] += red[0][threadIdx.x + off];
             red[1][threadIdx.x] += red[1][threadIdx.x + off];
+            red[2][threadIdx.x] += red[2][threadIdx.x + off];
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) *loss = (float)((1.0 - lambda) * red[1][0] / n + lambda * (1.0 - red[0][0] / n));
+    if (threadIdx.x == 0) {
+        const double n = red[2][0];
+        *loss = (float)((1.0 - lambda) * red[1][0] / n + lambda * (1.0 - red[0][0] / n));
+        *scale = (float)(1.0 / n);
+    }
 }
 
 }  // namespace
@@ -338,18 +366,29 @@ static int64_t ssim_tiles(int channels, int height, int width) {
     return (int64_t)((width + kSsimTW - 1) / kSsimTW) * ((height + kSsimTH - 1) / kSsimTH) * channels;
 }
 
-size_t ssim_scratch_bytes(int channels, int height, int width, bool with_grad) {
-    const size_t partial = ((size_t)ssim_tiles(channels, height, width) * 2 * sizeof(double) + 255) & ~(size_t)255;
-    return partial + (with_grad ? (size_t)3 * channels * height * width * sizeof(float) : 0);
+// Scratch: per-tile partial sums (3 doubles per tile and channel), the
+// gradient scale (one float in its own 256 bytes), then with a gradient the
+// three filtered planes.
+static size_t ssim_partial_bytes(int channels, int height, int width) {
+    return ((size_t)ssim_tiles(channels, height, width) * 3 * sizeof(double) + 255) & ~(size_t)255;
 }
 
-hipError_t launch_photometric(const float *image, const float *target, int channels, int height, int width,
-                              float lambda, float *grad, float *loss, void *scratch, hipStream_t st) {
+size_t ssim_scratch_bytes(int channels, int height, int width, bool with_grad) {
+    return ssim_partial_bytes(channels, height, width) + 256 +
+           (with_grad ? (size_t)3 * channels * height * width * sizeof(float) : 0);
+}
+
+hipError_t launch_photometric(const float *image, const float *target, const float *mask, int channels, int height,
+                              int width, float lambda, float *grad, float *loss, void *scratch, hipStream_t st) {
     SsimArgs a{};
     a.x = image;
     a.y = target;
+    a.mask = mask;
     a.grad = grad;
     a.partial = static_cast<double *>(scratch);
+    const size_t partial = ssim_partial_bytes(channels, height, width);
+    a.scale = reinterpret_cast<float *>(static_cast<char *>(scratch) + partial);
+    a.planes = grad ? reinterpret_cast<float *>(static_cast<char *>(scratch) + partial + 256) : nullptr;
     a.width = width;
     a.height = height;
     a.tiles_x = (width + kSsimTW - 1) / kSsimTW;
@@ -357,8 +396,6 @@ hipError_t launch_photometric(const float *image, const float *target, int chann
     a.tiles = (int)ssim_tiles(channels, height, width);
     a.per_xcd = (a.tiles + 7) / 8;
     a.plane_stride = (int64_t)channels * height * width;
-    const size_t partial = ssim_scratch_bytes(channels, height, width, false);
-    a.planes = grad ? reinterpret_cast<float *>(static_cast<char *>(scratch) + partial) : nullptr;
     double g[kTaps], sum = 0.0;
     for (int t = 0; t < kTaps; ++t) {
         const double d = t - kSsimR;
@@ -366,13 +403,12 @@ hipError_t launch_photometric(const float *image, const float *target, int chann
         sum += g[t];
     }
     for (int t = 0; t < kTaps; ++t) a.w1[t] = (float)(g[t] / sum);
-    const double n = (double)channels * height * width;
     a.lambda = lambda;
-    a.inv_n = (float)(1.0 / n);
     const dim3 grid((unsigned)(8 * a.per_xcd));
     hipLaunchKernelGGL(k_ssim_stats, grid, dim3(kSsimThreads), 0, st, a);
+    hipLaunchKernelGGL(k_ssim_final, dim3(1), dim3(256), 0, st, a.partial, (int64_t)a.tiles, (double)lambda, loss,
+                       a.scale);
     if (grad) hipLaunchKernelGGL(k_ssim_grad, grid, dim3(kSsimThreads), 0, st, a);
-    hipLaunchKernelGGL(k_ssim_final, dim3(1), dim3(256), 0, st, a.partial, (int64_t)a.tiles, n, (double)lambda, loss);
     return hipGetLastError();
 }
 

@@ -231,8 +231,8 @@ __device__ inline void load_sh(const ProjectArgs &A, int64_t i, double (*sh)[3])
 // `slot` of the output arrays.
 template <int D>
 __device__ inline uint32_t project_one(const ProjectArgs &A, int64_t i, int64_t slot, BlendRecord *rec,
-                                       uint32_t *depth_key, uint32_t *n_tiles, uint2 *rect, uint32_t *n_super,
-                                       float *radii) {
+                                       uint32_t *depth_key, float *depth, uint32_t *n_tiles, uint2 *rect,
+                                       uint32_t *n_super, float *radii) {
     const double o = A.opacities[i];
     Proj P;
     bool vis = project_core(A, i, o, P);
@@ -245,7 +245,7 @@ __device__ inline uint32_t project_one(const ProjectArgs &A, int64_t i, int64_t 
         double xs = ceil(P.px - ex - 0.5), xe = floor(P.px + ex - 0.5);
         double ys = ceil(P.py - ey - 0.5), ye = floor(P.py + ey - 0.5);
         ys = fmax(ys, 0.0);
-        ye = fmin(ye, (double)(A.height - 1));
+        ye = fmin(ye, (double)(A.rows - 1));  // the rendered rows
         const bool pinhole = A.model == OMNIGS_CAMERA_PINHOLE;
         if (pinhole) {  // no seam: columns clamp like rows
             xs = fmax(xs, 0.0);
@@ -279,6 +279,7 @@ __device__ inline uint32_t project_one(const ProjectArgs &A, int64_t i, int64_t 
     }
     if (!vis) {
         depth_key[slot] = kCulledKey;
+        if (depth) depth[slot] = 0.0f;
         n_tiles[slot] = 0;
         rect[slot] = make_uint2(0, 0);
         n_super[slot] = 0;
@@ -323,6 +324,7 @@ __device__ inline uint32_t project_one(const ProjectArgs &A, int64_t i, int64_t 
     dst[1] = make_float4(r.l00, r.l10, r.l11, r.opacity);
     dst[2] = make_float4(r.r, r.g, r.b, r.reach);
     depth_key[slot] = __float_as_uint((float)P.depth);
+    if (depth) depth[slot] = (float)P.depth;
     n_tiles[slot] = ntx * nty;
     const uint2 tr = make_uint2(tx0 | (ntx << 16), ty0 | (nty << 16));
     rect[slot] = tr;
@@ -344,12 +346,12 @@ __device__ inline void add_block_total(uint32_t v, uint32_t *total) {
 }
 
 template <int D>
-__global__ __launch_bounds__(256) void k_project(ProjectArgs A, BlendRecord *rec, uint32_t *depth_key,
+__global__ __launch_bounds__(256) void k_project(ProjectArgs A, BlendRecord *rec, uint32_t *depth_key, float *depth,
                                                  uint32_t *n_tiles, uint2 *rect, uint32_t *n_super, float *radii,
                                                  uint32_t *tiles_total) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t covered = 0;
-    if (i < A.n) covered = project_one<D>(A, i, i, rec, depth_key, n_tiles, rect, n_super, radii);
+    if (i < A.n) covered = project_one<D>(A, i, i, rec, depth_key, depth, n_tiles, rect, n_super, radii);
     add_block_total(covered, tiles_total);
 }
 
@@ -357,8 +359,8 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs A, BlendRecord *rec
 // are fetched from HBM once and re-read from cache for the later cameras.
 template <int D>
 __global__ __launch_bounds__(256) void k_project_batch(ProjectArgs A, CamTable T, BlendRecord *rec,
-                                                       uint32_t *depth_key, uint32_t *n_tiles, uint2 *rect,
-                                                       uint32_t *n_super, uint32_t *tiles_total) {
+                                                       uint32_t *depth_key, float *depth, uint32_t *n_tiles,
+                                                       uint2 *rect, uint32_t *n_super, uint32_t *tiles_total) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t covered = 0;
     for (int b = 0; b < T.count && i < A.n; ++b) {
@@ -373,12 +375,14 @@ __global__ __launch_bounds__(256) void k_project_batch(ProjectArgs A, CamTable T
         C.height = g.height;
         C.tiles_x = g.tiles_x;
         C.tiles_y = g.tiles_y;
+        C.rows = g.rows;
         C.model = g.model;
         C.fx = g.fx;
         C.fy = g.fy;
         C.cx = g.cx;
         C.cy = g.cy;
-        covered += project_one<D>(C, i, (int64_t)b * A.n + i, rec, depth_key, n_tiles, rect, n_super, nullptr);
+        covered += project_one<D>(C, i, (int64_t)b * A.n + i, rec, depth_key, depth, n_tiles, rect, n_super,
+                                  nullptr);
     }
     add_block_total(covered, tiles_total);
 }
@@ -434,7 +438,7 @@ __device__ inline void jacobian_grad(const Proj &P, double kx, double ky, double
 
 template <int D>
 __global__ __launch_bounds__(256) void k_project_backward(ProjectArgs A, const uint32_t *n_tiles, const float *acc,
-                                                          omnigs_grads G) {
+                                                          int acc_stride, omnigs_grads G) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= A.n) return;
     const int K = A.sh_coeffs;
@@ -451,9 +455,10 @@ __global__ __launch_bounds__(256) void k_project_backward(ProjectArgs A, const u
         G.dscreen[2 * i] = G.dscreen[2 * i + 1] = 0.0f;
         return;
     }
-    double g[kAcc];
+    double g[kAccAux];
 #pragma unroll
-    for (int k = 0; k < kAcc; ++k) g[k] = acc[i * kAcc + k];
+    for (int k = 0; k < kAcc; ++k) g[k] = acc[i * acc_stride + k];
+    g[kAcc] = acc_stride > kAcc ? acc[i * acc_stride + kAcc] : 0.0;  // dL/dd of the depth image
     // Q = Sigma2D^-1; the blend's dL/dQ treats q01 as one variable used in
     // both off-diagonal entries: the symmetric gradient is [[g00, g01/2], ...].
     const double id = 1.0 / P.det;
@@ -517,6 +522,8 @@ __global__ __launch_bounds__(256) void k_project_backward(ProjectArgs A, const u
     for (int nn = 0; nn < 3; ++nn) {
         double v = P.Jp[nn] * g[0] + P.Jp[3 + nn] * g[1];
         for (int e = 0; e < 6; ++e) v += dJ[e] * dJdt[e][nn];
+        // the depth value d: t_r (d t_r / dt = t / t_r) or t_z
+        v += A.model == OMNIGS_CAMERA_PINHOLE ? (nn == 2 ? g[kAcc] : 0.0) : g[kAcc] * P.t[nn] / P.tr;
         dt[nn] = v;
     }
     double dm[3];
@@ -556,44 +563,44 @@ __global__ __launch_bounds__(256) void k_project_backward(ProjectArgs A, const u
 
 }  // namespace
 
-hipError_t launch_project(const ProjectArgs &a, BlendRecord *rec, uint32_t *depth_key, uint32_t *n_tiles,
+hipError_t launch_project(const ProjectArgs &a, BlendRecord *rec, uint32_t *depth_key, float *depth, uint32_t *n_tiles,
                           uint2 *rect, uint32_t *n_super, float *radii, uint32_t *tiles_total, hipStream_t st) {
     hipError_t e = launch_fill_u32(tiles_total, 0u, 1, st);
     if (e != hipSuccess || a.n == 0) return e;
     const dim3 grid((unsigned)((a.n + 255) / 256));
     switch (a.sh_degree) {
-        case 0: hipLaunchKernelGGL(k_project<0>, grid, dim3(256), 0, st, a, rec, depth_key, n_tiles, rect, n_super, radii, tiles_total); break;
-        case 1: hipLaunchKernelGGL(k_project<1>, grid, dim3(256), 0, st, a, rec, depth_key, n_tiles, rect, n_super, radii, tiles_total); break;
-        case 2: hipLaunchKernelGGL(k_project<2>, grid, dim3(256), 0, st, a, rec, depth_key, n_tiles, rect, n_super, radii, tiles_total); break;
-        default: hipLaunchKernelGGL(k_project<3>, grid, dim3(256), 0, st, a, rec, depth_key, n_tiles, rect, n_super, radii, tiles_total); break;
+        case 0: hipLaunchKernelGGL(k_project<0>, grid, dim3(256), 0, st, a, rec, depth_key, depth, n_tiles, rect, n_super, radii, tiles_total); break;
+        case 1: hipLaunchKernelGGL(k_project<1>, grid, dim3(256), 0, st, a, rec, depth_key, depth, n_tiles, rect, n_super, radii, tiles_total); break;
+        case 2: hipLaunchKernelGGL(k_project<2>, grid, dim3(256), 0, st, a, rec, depth_key, depth, n_tiles, rect, n_super, radii, tiles_total); break;
+        default: hipLaunchKernelGGL(k_project<3>, grid, dim3(256), 0, st, a, rec, depth_key, depth, n_tiles, rect, n_super, radii, tiles_total); break;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_project_batch(const ProjectArgs &a, const CamTable &cams, BlendRecord *rec, uint32_t *depth_key,
-                                uint32_t *n_tiles, uint2 *rect, uint32_t *n_super, uint32_t *tiles_total,
-                                hipStream_t st) {
+                                float *depth, uint32_t *n_tiles, uint2 *rect, uint32_t *n_super,
+                                uint32_t *tiles_total, hipStream_t st) {
     hipError_t e = launch_fill_u32(tiles_total, 0u, 1, st);
     if (e != hipSuccess || a.n == 0 || cams.count == 0) return e;
     const dim3 grid((unsigned)((a.n + 255) / 256));
     switch (a.sh_degree) {
-        case 0: hipLaunchKernelGGL(k_project_batch<0>, grid, dim3(256), 0, st, a, cams, rec, depth_key, n_tiles, rect, n_super, tiles_total); break;
-        case 1: hipLaunchKernelGGL(k_project_batch<1>, grid, dim3(256), 0, st, a, cams, rec, depth_key, n_tiles, rect, n_super, tiles_total); break;
-        case 2: hipLaunchKernelGGL(k_project_batch<2>, grid, dim3(256), 0, st, a, cams, rec, depth_key, n_tiles, rect, n_super, tiles_total); break;
-        default: hipLaunchKernelGGL(k_project_batch<3>, grid, dim3(256), 0, st, a, cams, rec, depth_key, n_tiles, rect, n_super, tiles_total); break;
+        case 0: hipLaunchKernelGGL(k_project_batch<0>, grid, dim3(256), 0, st, a, cams, rec, depth_key, depth, n_tiles, rect, n_super, tiles_total); break;
+        case 1: hipLaunchKernelGGL(k_project_batch<1>, grid, dim3(256), 0, st, a, cams, rec, depth_key, depth, n_tiles, rect, n_super, tiles_total); break;
+        case 2: hipLaunchKernelGGL(k_project_batch<2>, grid, dim3(256), 0, st, a, cams, rec, depth_key, depth, n_tiles, rect, n_super, tiles_total); break;
+        default: hipLaunchKernelGGL(k_project_batch<3>, grid, dim3(256), 0, st, a, cams, rec, depth_key, depth, n_tiles, rect, n_super, tiles_total); break;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_project_backward(const ProjectArgs &a, const uint32_t *n_tiles, const float *acc,
+hipError_t launch_project_backward(const ProjectArgs &a, const uint32_t *n_tiles, const float *acc, int acc_stride,
                                    const omnigs_grads &gr, hipStream_t st) {
     if (a.n == 0) return hipSuccess;
     const dim3 grid((unsigned)((a.n + 255) / 256));
     switch (a.sh_degree) {
-        case 0: hipLaunchKernelGGL(k_project_backward<0>, grid, dim3(256), 0, st, a, n_tiles, acc, gr); break;
-        case 1: hipLaunchKernelGGL(k_project_backward<1>, grid, dim3(256), 0, st, a, n_tiles, acc, gr); break;
-        case 2: hipLaunchKernelGGL(k_project_backward<2>, grid, dim3(256), 0, st, a, n_tiles, acc, gr); break;
-        default: hipLaunchKernelGGL(k_project_backward<3>, grid, dim3(256), 0, st, a, n_tiles, acc, gr); break;
+        case 0: hipLaunchKernelGGL(k_project_backward<0>, grid, dim3(256), 0, st, a, n_tiles, acc, acc_stride, gr); break;
+        case 1: hipLaunchKernelGGL(k_project_backward<1>, grid, dim3(256), 0, st, a, n_tiles, acc, acc_stride, gr); break;
+        case 2: hipLaunchKernelGGL(k_project_backward<2>, grid, dim3(256), 0, st, a, n_tiles, acc, acc_stride, gr); break;
+        default: hipLaunchKernelGGL(k_project_backward<3>, grid, dim3(256), 0, st, a, n_tiles, acc, acc_stride, gr); break;
     }
     return hipGetLastError();
 }

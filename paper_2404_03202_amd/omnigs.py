@@ -52,7 +52,7 @@ CAMERA_ERP, CAMERA_PINHOLE = 0, 1
 
 class c_camera(ctypes.Structure):
     _fields_ = [("R_cw", ctypes.c_double * 9), ("t_cw", ctypes.c_double * 3), ("width", ctypes.c_int32),
-                ("height", ctypes.c_int32), ("model", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("height", ctypes.c_int32), ("model", ctypes.c_int32), ("rows", ctypes.c_int32),
                 ("fx", ctypes.c_double), ("fy", ctypes.c_double), ("cx", ctypes.c_double), ("cy", ctypes.c_double)]
 
 
@@ -63,7 +63,7 @@ class c_settings(ctypes.Structure):
 
 class c_image_out(ctypes.Structure):
     _fields_ = [("image", ctypes.c_void_p), ("final_T", ctypes.c_void_p), ("n_contrib", ctypes.c_void_p),
-                ("n_blended", ctypes.c_void_p)]
+                ("n_blended", ctypes.c_void_p), ("depth", ctypes.c_void_p)]
 
 
 class c_state(ctypes.Structure):
@@ -72,7 +72,7 @@ class c_state(ctypes.Structure):
                 ("height", ctypes.c_int32), ("tiles_x", ctypes.c_int32), ("tiles_y", ctypes.c_int32),
                 ("records", ctypes.c_void_p), ("n_tiles", ctypes.c_void_p), ("depth_order", ctypes.c_void_p),
                 ("inst_gauss", ctypes.c_void_p), ("tile_range", ctypes.c_void_p), ("tile_work", ctypes.c_void_p),
-                ("radii", ctypes.c_void_p)]
+                ("radii", ctypes.c_void_p), ("depth", ctypes.c_void_p)]
 
 
 class c_grads(ctypes.Structure):
@@ -128,12 +128,12 @@ def load_library(path: str = LIB_PATH):
                                        P(c_state), vp]
         lib.omnigs_forward.restype = ctypes.c_int
         lib.omnigs_backward.argtypes = [P(c_gaussians), P(c_camera), P(c_settings), P(c_state), P(c_image_out), vp,
-                                        P(c_grads), c_allocator, vp]
+                                        vp, vp, P(c_grads), c_allocator, vp]
         lib.omnigs_backward.restype = ctypes.c_int
         lib.omnigs_l1_loss.argtypes = [vp, vp, ctypes.c_int64, vp, vp, c_allocator, vp]
         lib.omnigs_l1_loss.restype = ctypes.c_int
         lib.omnigs_photometric_loss.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
-                                                vp, vp, c_allocator, vp]
+                                                vp, vp, vp, c_allocator, vp]
         lib.omnigs_photometric_loss.restype = ctypes.c_int
         lib.omnigs_forward_batch.argtypes = [P(c_gaussians), P(c_camera), ctypes.c_int32, P(c_settings), c_allocator,
                                              P(c_image_out), ctypes.c_int64, vp, P(ctypes.c_int64), vp]
@@ -214,7 +214,15 @@ def make_camera(camera: dict) -> c_camera:
         c.t_cw[k] = float(t[k])
     c.width = int(camera["width"])
     c.height = int(camera["height"])
+    c.rows = int(camera.get("rows", 0))
     return c
+
+
+def image_rows(camera: dict) -> int:
+    """Rows of the rendered image: the camera's "rows" (top rows only) or
+    its height."""
+    r = int(camera.get("rows", 0))
+    return r if r > 0 else int(camera["height"])
 
 
 def _ptr(t):
@@ -270,11 +278,12 @@ def _stream_ptr(device):
 class ForwardResult:
     """Outputs of omnigs_forward plus the saved state for omnigs_backward."""
 
-    def __init__(self, image, final_T, n_contrib, state: c_state, keepalive, n_blended=None):
+    def __init__(self, image, final_T, n_contrib, state: c_state, keepalive, n_blended=None, depth=None):
         self.image = image
         self.final_T = final_T
         self.n_contrib = n_contrib
         self.n_blended = n_blended
+        self.depth = depth
         self.state = state
         self._keep = keepalive
 
@@ -319,18 +328,24 @@ class ForwardResult:
 
 
 def omnigs_forward(g: dict, camera: dict, settings: dict | None = None, allocator: Allocator | None = None,
-                   out: dict | None = None, with_blended: bool = False) -> ForwardResult:
+                   out: dict | None = None, with_blended: bool = False, with_depth: bool = False) -> ForwardResult:
+    """Render one camera: image [3,H,W], final_T, n_contrib (and n_blended,
+    depth [H,W] on request), H the rendered rows; the alpha image is
+    1 - final_T."""
     lib = load_library()
     dev = g["means"].device
     cg, cc, cs = make_gaussians(g), make_camera(camera), make_settings(settings)
-    H, W = cc.height, cc.width
+    H, W = image_rows(camera), cc.width
     if out is None:
         out = dict(image=torch.empty((3, H, W), dtype=torch.float32, device=dev),
                    final_T=torch.empty((H, W), dtype=torch.float32, device=dev),
                    n_contrib=torch.empty((H, W), dtype=torch.int32, device=dev))
         if with_blended:
             out["n_blended"] = torch.empty((H, W), dtype=torch.int32, device=dev)
-    co = c_image_out(_ptr(out["image"]), _ptr(out["final_T"]), _ptr(out["n_contrib"]), _ptr(out.get("n_blended")))
+        if with_depth:
+            out["depth"] = torch.empty((H, W), dtype=torch.float32, device=dev)
+    co = c_image_out(_ptr(out["image"]), _ptr(out["final_T"]), _ptr(out["n_contrib"]), _ptr(out.get("n_blended")),
+                     _ptr(out.get("depth")))
     st = c_state()
     al = allocator or Allocator(dev)
     _check(lib.omnigs_forward(ctypes.byref(cg), ctypes.byref(cc), ctypes.byref(cs), al.c, ctypes.byref(co),
@@ -338,28 +353,34 @@ def omnigs_forward(g: dict, camera: dict, settings: dict | None = None, allocato
     keep = list(al.state)
     al.scratch.clear()
     al.state.clear()
-    return ForwardResult(out["image"], out["final_T"], out["n_contrib"], st, keep, out.get("n_blended"))
+    return ForwardResult(out["image"], out["final_T"], out["n_contrib"], st, keep, out.get("n_blended"),
+                         out.get("depth"))
 
 
 def omnigs_backward(g: dict, camera: dict, settings: dict | None, fwd: ForwardResult, dL_dimage: torch.Tensor,
-                    allocator: Allocator | None = None, grads: dict | None = None) -> dict:
+                    allocator: Allocator | None = None, grads: dict | None = None,
+                    dL_ddepth: torch.Tensor | None = None, dL_dalpha: torch.Tensor | None = None) -> dict:
+    """Gradients of <dL_dimage, image> (+ <dL_ddepth, depth> + <dL_dalpha,
+    1 - final_T>, each optional) w.r.t. the parameters."""
     lib = load_library()
     dev = g["means"].device
     n = int(g["means"].shape[0])
     cg, cc, cs = make_gaussians(g), make_camera(camera), make_settings(settings)
-    if dL_dimage.dtype != torch.float32 or not dL_dimage.is_contiguous():
-        raise ValueError("dL_dimage must be a contiguous float32 tensor")
+    for t in (dL_dimage, dL_ddepth, dL_dalpha):
+        if t is not None and (t.dtype != torch.float32 or not t.is_contiguous()):
+            raise ValueError("cotangents must be contiguous float32 tensors")
     if grads is None:
         z = lambda *shape: torch.empty(shape, dtype=torch.float32, device=dev)
         grads = dict(means=z(n, 3), scales=z(n, 3), quats=z(n, 4), opacities=z(n), sh=torch.empty_like(g["sh"]),
                      screen=z(n, 2))
     cgr = c_grads(_ptr(grads["means"]), _ptr(grads["scales"]), _ptr(grads["quats"]), _ptr(grads["opacities"]),
                   _ptr(grads["sh"]), _ptr(grads["screen"]))
-    co = c_image_out(_ptr(fwd.image), _ptr(fwd.final_T), _ptr(fwd.n_contrib), None)
+    co = c_image_out(_ptr(fwd.image), _ptr(fwd.final_T), _ptr(fwd.n_contrib), None, None)
     al = allocator or Allocator(dev)
     _check(lib.omnigs_backward(ctypes.byref(cg), ctypes.byref(cc), ctypes.byref(cs), ctypes.byref(fwd.state),
-                               ctypes.byref(co), ctypes.c_void_p(dL_dimage.data_ptr()), ctypes.byref(cgr), al.c,
-                               ctypes.c_void_p(_stream_ptr(dev))))
+                               ctypes.byref(co), ctypes.c_void_p(dL_dimage.data_ptr()),
+                               ctypes.c_void_p(_ptr(dL_ddepth)), ctypes.c_void_p(_ptr(dL_dalpha)),
+                               ctypes.byref(cgr), al.c, ctypes.c_void_p(_stream_ptr(dev))))
     al.scratch.clear()
     return grads
 
@@ -397,29 +418,34 @@ class BatchResult:
 
 
 def omnigs_photometric_loss(image: torch.Tensor, target: torch.Tensor, lam: float, grad: bool = True,
-                            allocator: Allocator | None = None):
+                            allocator: Allocator | None = None, mask: torch.Tensor | None = None):
     """(loss [1] float32, dL/dimage or None) of (1 - lam) L1 + lam (1 - SSIM)
-    for [C, H, W] float32 images."""
+    for [C, H, W] float32 images, both means weighted by the [H, W] mask when
+    one is given."""
     lib = load_library()
     if image.shape != target.shape or image.dim() != 3 or image.dtype != torch.float32 or \
             target.dtype != torch.float32:
         raise ValueError("image and target must be [C, H, W] float32 tensors of one shape")
     image, target = image.contiguous(), target.contiguous()
     C, H, W = image.shape
+    if mask is not None:
+        if mask.shape != (H, W) or mask.dtype != torch.float32:
+            raise ValueError("mask must be a [H, W] float32 tensor")
+        mask = mask.contiguous()
     dev = image.device
     loss = torch.empty(1, dtype=torch.float32, device=dev)
     g = torch.empty_like(image) if grad else None
     al = allocator or Allocator(dev)
     _check(lib.omnigs_photometric_loss(ctypes.c_void_p(image.data_ptr()), ctypes.c_void_p(target.data_ptr()), C, H, W,
-                                       float(lam), ctypes.c_void_p(_ptr(g)), ctypes.c_void_p(loss.data_ptr()), al.c,
-                                       ctypes.c_void_p(_stream_ptr(dev))))
+                                       float(lam), ctypes.c_void_p(_ptr(mask)), ctypes.c_void_p(_ptr(g)),
+                                       ctypes.c_void_p(loss.data_ptr()), al.c, ctypes.c_void_p(_stream_ptr(dev))))
     al.scratch.clear()
     return loss, g
 
 
 def omnigs_forward_batch(g: dict, cameras: list, settings: dict | None = None, instance_capacity: int = 0,
                          allocator: Allocator | None = None, outs: list | None = None,
-                         with_blended: bool = False) -> BatchResult:
+                         with_blended: bool = False, with_depth: bool = False) -> BatchResult:
     """Render up to OMNIGS_MAX_BATCH cameras (mixed resolutions) in one
     batched launch sequence on the current stream.  instance_capacity 0 reads
     the instance count back (one host sync); > 0 enqueues only and flags
@@ -432,15 +458,17 @@ def omnigs_forward_batch(g: dict, cameras: list, settings: dict | None = None, i
     if outs is None:
         outs = []
         for c in cameras:
-            H, W = int(c["height"]), int(c["width"])
+            H, W = image_rows(c), int(c["width"])
             o = dict(image=torch.empty((3, H, W), dtype=torch.float32, device=dev),
                      final_T=torch.empty((H, W), dtype=torch.float32, device=dev),
                      n_contrib=torch.empty((H, W), dtype=torch.int32, device=dev))
             if with_blended:
                 o["n_blended"] = torch.empty((H, W), dtype=torch.int32, device=dev)
+            if with_depth:
+                o["depth"] = torch.empty((H, W), dtype=torch.float32, device=dev)
             outs.append(o)
     couts = (c_image_out * max(B, 1))(*[c_image_out(_ptr(o["image"]), _ptr(o["final_T"]), _ptr(o["n_contrib"]),
-                                                    _ptr(o.get("n_blended"))) for o in outs])
+                                                    _ptr(o.get("n_blended")), _ptr(o.get("depth"))) for o in outs])
     overflow = torch.empty(1, dtype=torch.int32, device=dev)
     m = ctypes.c_int64(-1)
     al = allocator or Allocator(dev)

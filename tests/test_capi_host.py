@@ -88,7 +88,8 @@ def _forward(lib, g, c, s, out, alloc):
     (lambda g, c, s, o: setattr(s, "T_min", 1.5), "T_min"),
     (lambda g, c, s, o: setattr(o, "image", None), "NULL"),
     (lambda g, c, s, o: setattr(c, "model", 7), "unknown camera model"),
-    (lambda g, c, s, o: setattr(c, "reserved", 1), "reserved"),
+    (lambda g, c, s, o: setattr(c, "rows", 33), "rows"),
+    (lambda g, c, s, o: setattr(c, "rows", -1), "rows"),
     (lambda g, c, s, o: _pinhole(c, fx=0.0), "intrinsics"),
     (lambda g, c, s, o: _pinhole(c, fy=float("nan")), "intrinsics"),
     (lambda g, c, s, o: _pinhole(c, cx=float("inf")), "intrinsics"),
@@ -133,7 +134,18 @@ def test_l1_and_backward_argument_checks(lib):
     st.n, st.width, st.height = 5, 64, 32  # does not match n = 10
     gr = B.c_grads(0x1000, 0x2000, 0x3000, 0x4000, 0x5000, 0x6000)
     rc = lib.omnigs_backward(ctypes.byref(g), ctypes.byref(c), ctypes.byref(s), ctypes.byref(st), ctypes.byref(out),
-                             0x9000, ctypes.byref(gr), alloc, None)
+                             0x9000, None, None, ctypes.byref(gr), alloc, None)
+    assert rc == B.OMNIGS_ERR_INVALID and "state does not match" in B.omnigs_last_error()
+    # depth / alpha cotangents need the state's depth values
+    st.n = 10
+    st.records = st.n_tiles = st.inst_gauss = st.tile_range = st.tile_work = 0xa000
+    rc = lib.omnigs_backward(ctypes.byref(g), ctypes.byref(c), ctypes.byref(s), ctypes.byref(st), ctypes.byref(out),
+                             0x9000, 0xb000, None, ctypes.byref(gr), alloc, None)
+    assert rc == B.OMNIGS_ERR_INVALID and "depth" in B.omnigs_last_error()
+    # a crop's state has the rendered rows
+    c.rows = 20
+    rc = lib.omnigs_backward(ctypes.byref(g), ctypes.byref(c), ctypes.byref(s), ctypes.byref(st), ctypes.byref(out),
+                             0x9000, None, None, ctypes.byref(gr), alloc, None)
     assert rc == B.OMNIGS_ERR_INVALID and "state does not match" in B.omnigs_last_error()
 
 
