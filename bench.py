@@ -300,6 +300,67 @@ def pinhole_bench(gd, crops, crop_targets, poses, steps, log):
     return out
 
 
+def aux_bench(g, gd, masked, steps, log):
+    """Loss masks and auxiliary outputs: (1) training at 1520x760 with the
+    bottom 48 rows left out of the loss (the 360Roam setting: 712 rows used),
+    once with the camera's row crop (the rows are never rendered) and once
+    rendering all 760 rows with a loss mask of zeros there; (2) forward +
+    backward at 2048x1024 with the depth image and depth / alpha cotangents
+    against the plain colour pass."""
+    import torch
+    from paper_2404_03202_amd import omnigs as B
+    from paper_2404_03202_amd.train import Trainer, TrainSettings
+
+    cams, targets_full = masked
+    out = {}
+    H, rows = 760, 712
+    mask = torch.zeros(H, 1520, device="cuda:0")
+    mask[:rows] = 1.0
+    for name, use_rows in (("rows_712_of_760", True), ("mask_712_of_760", False)):
+        tr = Trainer(g, TrainSettings(extent=10.0, densify_from=10 ** 9))
+
+        def it(k):
+            c = cams[k % len(cams)]
+            t = targets_full[k % len(cams)]
+            if use_rows:
+                return tr.step(dict(c, rows=rows), t[:, :rows].contiguous())
+            return tr.step(c, t, mask=mask)
+
+        for k in range(3):
+            it(k)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            it(k)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[name] = dict(iters_per_s=steps / dt, ms_per_step=dt * 1e3 / steps)
+        del tr
+    from paper_2404_03202_amd import scenes
+    poses = scenes.poses(2, 50, 2048, 1024)
+    rng = torch.Generator(device="cuda:0").manual_seed(7)
+    GD = torch.randn(1024, 2048, device="cuda:0", generator=rng) * 1e-6
+    GA = torch.randn(1024, 2048, device="cuda:0", generator=rng) * 1e-6
+    G = torch.randn(3, 1024, 2048, device="cuda:0", generator=rng) * 1e-6
+    for name, aux in (("colour", False), ("colour_depth_alpha", True)):
+        def it(k):
+            p = poses[k % len(poses)]
+            fwd = B.omnigs_forward(gd, p, with_depth=aux)
+            B.omnigs_backward(gd, p, None, fwd, G, dL_ddepth=GD if aux else None, dL_dalpha=GA if aux else None)
+
+        for k in range(3):
+            it(k)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            it(k)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out["fwd_bwd_2048x1024_" + name] = dict(iters_per_s=steps / dt, ms_per_step=dt * 1e3 / steps)
+    log(f"aux: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -311,6 +372,7 @@ def main():
     ap.add_argument("--stress", action="store_true", help="also measure the 3M-Gaussian 3840x1920 workload")
     ap.add_argument("--no-train", action="store_true", help="skip the full training-iteration measurement")
     ap.add_argument("--no-pinhole", action="store_true", help="skip the pinhole-camera measurement")
+    ap.add_argument("--no-aux", action="store_true", help="skip the loss-mask / depth-output measurement")
     ap.add_argument("--stress-steps", type=int, default=8)
     ap.add_argument("--serve-requests", type=int, default=800)
     ap.add_argument("--serve-slots", type=int, default=4)
@@ -347,6 +409,8 @@ def main():
         targets.append(B.omnigs_forward(gtd, p).image.clone())
     crops = scenes.crop_poses(2, 100, 1024, 1024, 90.0)
     crop_targets = [] if args.no_pinhole else [B.omnigs_forward(gtd, c).image.clone() for c in crops]
+    masked_cams = scenes.poses(2, 50, 1520, 760)
+    masked = (masked_cams, [] if args.no_aux else [B.omnigs_forward(gtd, c).image.clone() for c in masked_cams])
     del gtd
     torch.cuda.synchronize()
     log("targets rendered")
@@ -400,6 +464,8 @@ def main():
         out["train"] = train_bench(g, poses, targets, min(args.steps, 100), log)
     if not args.no_pinhole:
         out["pinhole"] = pinhole_bench(gd, crops, crop_targets, poses, min(args.steps, 100), log)
+    if not args.no_aux:
+        out["aux"] = aux_bench(g, gd, masked, min(args.steps, 50), log)
     if args.stress:
         out["stress"] = stress_bench(args.stress_steps, log)
     if not args.no_serve:

@@ -90,12 +90,14 @@ class Trainer:
         return dict(means=lr_m, sh_dc=self.s.lr_sh_dc, sh_rest=self.s.lr_sh_rest, logits=self.s.lr_logits,
                     log_scales=self.s.lr_log_scales, quats=self.s.lr_quats)
 
-    def step(self, camera: dict, target: torch.Tensor):
-        """One iteration; returns the loss tensor (device)."""
+    def step(self, camera: dict, target: torch.Tensor, mask: torch.Tensor | None = None):
+        """One iteration; returns the loss tensor (device).  ``mask`` [H, W]:
+        per-pixel loss weights (a camera's "rows" skips bottom rows
+        outright)."""
         self.step_count += 1
         fwd = B.omnigs_forward(self.act, camera, self.render_settings)
-        if self.s.lambda_dssim > 0.0:
-            loss, dl = B.omnigs_photometric_loss(fwd.image, target, self.s.lambda_dssim)
+        if self.s.lambda_dssim > 0.0 or mask is not None:
+            loss, dl = B.omnigs_photometric_loss(fwd.image, target, self.s.lambda_dssim, mask=mask)
         else:
             loss, dl = B.omnigs_l1_loss(fwd.image, target)
         grads = B.omnigs_backward(self.act, camera, self.render_settings, fwd, dl)
