@@ -80,18 +80,24 @@ __device__ inline int find_frame(const FrameTable &T, uint32_t tile) {
 }
 
 // Staged instances (LDS):
-//   a = (x, y, l00, l10), b = (l11, o, r, g), c = b, quad = quadrant mask
-// with (x, y) the centre relative to the tile origin and L the record's
-// scaled Cholesky factor of the conic: -(l00 dx + l10 dy)^2 - (l11 dy)^2 =
-// log2(e) * (-1/2 d^T Q d).  list[w] holds, for wave w, the staged slots
-// that reach one of its quadrants, in order, as slot | (wave mask << 8).
-// With kAux, d holds each staged instance's depth value.
-template <int kW, bool kAux>
+//   a = (u0a, v0, l00, l10), b = (l11, o, r, g), c = (b, u0b, thr, depth),
+//   e = (xa, y) (backward only), quad = quadrant mask
+// with L the record's scaled Cholesky factor of the conic:
+// -(l00 dx + l10 dy)^2 - (l11 dy)^2 = log2(e) * (-1/2 d^T Q d).  The pixel at
+// integer tile coordinates (i, j) has d = (i + 1/2 - x, j + 1/2 - y) with the
+// centre x relative to the tile origin taken as xa for i < thr and as xb for
+// i >= thr: thr lies past the tile (xb unused) except where the offsets of
+// the tile's columns cross the seam (a centre near the antipode of the
+// tile); there xb = xa + W and thr splits the columns.  So L^T d = (l00 i + l10 j + u0, l11 j +
+// v0) with u0 = u0a or u0b, formed once per (tile, instance) in double
+// precision: a pixel pays a compare, a select and three FMAs for L^T d.
+// list[w] holds, for wave w, the staged slots that reach one of its
+// quadrants, in order, as slot | (wave mask << 8).
+template <int kW, bool kBwd>
 struct Stage {
     static constexpr int kBatch = kWave * kW;
-    float4 a[kBatch], b[kBatch];
-    float c[kBatch];
-    float d[kAux ? kBatch : 1];
+    float4 a[kBatch], b[kBatch], c[kBatch];
+    float2 e[kBwd ? kBatch : 1];
     uint32_t quad[kBatch];
     uint32_t gid[kBatch];
     uint16_t list[kW][kBatch];
@@ -124,18 +130,28 @@ __device__ inline float rect_min_quadratic(float l00, float l10, float l11, floa
     return best;
 }
 
-// Stage the record of Gaussian gid in slot `slot`.
-template <int kW, bool kAux>
+// Stage the record of Gaussian gid in slot `slot` (rdepth: per-record depth
+// values, read when kAux).
+template <bool kAux, int kW, bool kBwd>
 __device__ inline void stage(const BlendRecord *rec, const float *rdepth, uint32_t gid, float X0, float Y0, float W,
-                             Stage<kW, kAux> &S, int slot) {
+                             Stage<kW, kBwd> &S, int slot) {
     const float4 *p = reinterpret_cast<const float4 *>(rec + gid);
     const float4 ra4 = p[0], rb4 = p[1], rc4 = p[2];
     float x = (ra4.x - X0) + ra4.y;  // px_hi - X0 is exact near the tile
     const float y = (ra4.z - Y0) + ra4.w;
+    // the same centre in double precision: exactly hi - X0 + lo
+    double xd = ((double)ra4.x - (double)X0) + (double)ra4.y;
+    const double yd = ((double)ra4.z - (double)Y0) + (double)ra4.w;
     // bring the centre within half a turn of the tile's middle column
     const float half = 0.5f * W;
-    if (x - 8.0f >= half) x -= W;
-    if (x - 8.0f < -half) x += W;
+    if (x - 8.0f >= half) {
+        x -= W;
+        xd -= (double)W;
+    }
+    if (x - 8.0f < -half) {
+        x += W;
+        xd += (double)W;
+    }
     const float l00 = rb4.x, l10 = rb4.y, l11 = rb4.z;
     // quadrants the alpha >= alpha_min region can reach:
     // |L^T (u, v)|^2 <= log2(o / alpha_min), with a margin; the clamped edge
@@ -155,22 +171,38 @@ __device__ inline void stage(const BlendRecord *rec, const float *rdepth, uint32
         const bool wraps = u0 < -half || u1 >= half;
         if (wraps || rect_min_quadratic(l00, l10, l11, qb, ra, rc, u0, u1, v0, v1) <= reach) quad |= 1u << k;
     }
-    S.a[slot] = make_float4(x, y, l00, l10);
+    // columns whose offset i + 1/2 - x leaves [-W/2, W/2) take the centre a
+    // turn away: the right ones (offset >= W/2) or the left ones (< -W/2)
+    float xa = x, thr = 1e30f;
+    double xad = xd, xbd = xd;
+    if (15.5f - x >= half) {
+        xbd = xd + (double)W;
+        thr = x + half - 0.5f;
+    } else if (0.5f - x < -half) {
+        xa = x - W;
+        xad = xd - (double)W;
+        thr = x - half - 0.5f;
+    }
+    const double dy0 = 0.5 - yd;
+    const float u0a = (float)((double)l00 * (0.5 - xad) + (double)l10 * dy0);
+    const float u0b = (float)((double)l00 * (0.5 - xbd) + (double)l10 * dy0);
+    const float v0 = (float)((double)l11 * dy0);
+    S.a[slot] = make_float4(u0a, v0, l00, l10);
     S.b[slot] = make_float4(l11, rb4.w, rc4.x, rc4.y);
-    S.c[slot] = rc4.z;
-    if (kAux) S.d[slot] = rdepth[gid];
+    S.c[slot] = make_float4(rc4.z, u0b, thr, kAux ? rdepth[gid] : 0.0f);
+    if (kBwd) S.e[slot] = make_float2(xa, y);
     S.quad[slot] = quad;
     S.gid[slot] = gid;
 }
 
 // Wave w lists, in order, the staged slots in [lo, nb) that reach one of its
 // quadrants; returns the count (uniform).
-template <int kW, bool kAux>
-__device__ inline int compact(Stage<kW, kAux> &S, int w, int lo, int nb) {
+template <int kW, bool kBwd>
+__device__ inline int compact(Stage<kW, kBwd> &S, int w, int lo, int nb) {
     constexpr int kPPL = kQuads / kW;
     const int lane = __lane_id();
     int n = 0;
-    for (int c = 0; c < Stage<kW, kAux>::kBatch; c += kWave) {
+    for (int c = 0; c < Stage<kW, kBwd>::kBatch; c += kWave) {
         const int slot = c + lane;
         const uint32_t m = (slot >= lo && slot < nb) ? (S.quad[slot] >> (w * kPPL)) & ((1u << kPPL) - 1u) : 0u;
         const uint64_t hits = __ballot(m != 0u);
@@ -180,16 +212,14 @@ __device__ inline int compact(Stage<kW, kAux> &S, int w, int lo, int nb) {
     return n;
 }
 
-// alpha at one pixel: returns the unclamped alpha, writes the clamped one,
-// G = exp(-1/2 d^T Q d) and the pixel offset (x wrapped across the seam).
-__device__ __forceinline__ float pixel_alpha(float fx, float fy, float4 a, float l11, float o, float W, float half,
-                                             float alpha_max, float &alpha, float &G, float &dx, float &dy) {
-    float d = fx - a.x;
-    d = (d >= half) ? d - W : d;
-    d = (d < -half) ? d + W : d;
-    dx = d;
-    dy = fy - a.y;
-    const float u = __builtin_fmaf(a.w, dy, a.z * dx), v = l11 * dy;  // L^T d
+// alpha at the pixel (i, j) of the tile (integer coordinates as floats):
+// returns the unclamped alpha, writes the clamped one and
+// G = exp(-1/2 d^T Q d).
+__device__ __forceinline__ float pixel_alpha(float i, float j, float4 a, float4 c, float l11, float o,
+                                             float alpha_max, float &alpha, float &G) {
+    const float u0 = i >= c.z ? c.y : a.x;
+    const float u = __builtin_fmaf(a.z, i, __builtin_fmaf(a.w, j, u0));  // L^T d
+    const float v = __builtin_fmaf(l11, j, a.y);
     G = __builtin_amdgcn_exp2f(-__builtin_fmaf(u, u, v * v));
     const float araw = o * G;
     alpha = araw < alpha_max ? araw : alpha_max;
@@ -208,9 +238,9 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_forward(FrameTable FT, con
                                                                const float *rdepth, const uint32_t *inst_gauss,
                                                                const uint2 *ranges, BlendSettings s,
                                                                const uint32_t *order, uint32_t *tile_work) {
-    constexpr int kNT = kWave * kW, kPPL = kQuads / kW, kBatch = Stage<kW, kDepth>::kBatch;
+    constexpr int kNT = kWave * kW, kPPL = kQuads / kW, kBatch = Stage<kW, false>::kBatch;
     constexpr uint32_t kAll = (1u << kPPL) - 1u;
-    __shared__ Stage<kW, kDepth> S;
+    __shared__ Stage<kW, false> S;
     __shared__ int s_wmax[kW];
     const uint32_t tile = order ? order[blockIdx.x] : blockIdx.x;
     const int fi = kBatched ? find_frame(FT, tile) : 0;
@@ -219,7 +249,7 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_forward(FrameTable FT, con
     const int tx = lt % F.tiles_x, ty = lt / F.tiles_x;
     const int w = threadIdx.x / kWave, lane = __lane_id();
     const int lx = lane & 7, ly = lane >> 3;
-    const float W = F.period, half = 0.5f * W;
+    const float W = F.period;
     const float X0 = (float)(tx * kTile), Y0 = (float)(ty * kTile);
     const uint2 range = ranges[tile];
     const int count = (int)(range.y - range.x);
@@ -238,7 +268,7 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_forward(FrameTable FT, con
         if (__syncthreads_count(done == kAll) == kNT) break;
         const int nb = min(kBatch, count - base);
         if ((int)threadIdx.x < nb)
-            stage(rec, rdepth, inst_gauss[range.x + base + threadIdx.x], X0, Y0, W, S, threadIdx.x);
+            stage<kDepth>(rec, rdepth, inst_gauss[range.x + base + threadIdx.x], X0, Y0, W, S, threadIdx.x);
         __syncthreads();
         if (__ballot(done != kAll) == 0ull) continue;  // this wave is finished: keep staging with the others
         const int n = compact(S, w, 0, nb);
@@ -246,15 +276,15 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_forward(FrameTable FT, con
             const uint32_t e = __builtin_amdgcn_readfirstlane(S.list[w][t]);
             const int j = e & 0xff;
             const uint32_t m = e >> 8;
-            const float4 a = S.a[j], b = S.b[j];
-            const float cb = S.c[j];
-            const float dj = kDepth ? S.d[j] : 0.0f;
+            const float4 a = S.a[j], b = S.b[j], c = S.c[j];
+            const float cb = c.x;
+            const float dj = c.w;
 #pragma unroll
             for (int k = 0; k < kPPL; ++k) {
                 if (!(m & (1u << k))) continue;  // uniform
-                float alpha, G, dx, dy;
-                pixel_alpha(slot_px<kW>(w, k, lx) + 0.5f, slot_py<kW>(w, k, ly) + 0.5f, a, b.x, b.y, W, half,
-                            s.alpha_max, alpha, G, dx, dy);
+                float alpha, G;
+                pixel_alpha((float)slot_px<kW>(w, k, lx), (float)slot_py<kW>(w, k, ly), a, c, b.x, b.y, s.alpha_max,
+                            alpha, G);
                 const float Tn = T[k] * (1.0f - alpha);
                 const bool live = !(done & (1u << k)) && alpha >= s.alpha_min;
                 const bool stop = live && Tn < s.T_min;
@@ -353,9 +383,9 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, co
                                                                 const float *rdepth, const uint32_t *inst_gauss,
                                                                 const uint2 *ranges, BlendSettings s, float *acc,
                                                                 const uint32_t *order) {
-    constexpr int kPPL = kQuads / kW, kBatch = Stage<kW, kAux>::kBatch;
+    constexpr int kPPL = kQuads / kW, kBatch = Stage<kW, true>::kBatch;
     constexpr int kNF = kAux ? kAccAux : kAcc;  // accumulator fields per Gaussian
-    __shared__ Stage<kW, kAux> S;
+    __shared__ Stage<kW, true> S;
     __shared__ float part[kBatch][kNF];
     __shared__ int s_max[kW];
     const uint32_t tile = order ? order[blockIdx.x] : blockIdx.x;
@@ -365,7 +395,7 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, co
     const int tx = lt % F.tiles_x, ty = lt / F.tiles_x;
     const int w = threadIdx.x / kWave, lane = __lane_id();
     const int lx = lane & 7, ly = lane >> 3;
-    const float W = F.period, half = 0.5f * W;
+    const float W = F.period;
     const float X0 = (float)(tx * kTile), Y0 = (float)(ty * kTile);
     const uint2 range = ranges[tile];
     const int64_t HW = (int64_t)F.width * F.height;
@@ -407,7 +437,7 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, co
         __syncthreads();
         if ((int)threadIdx.x < nb) {
             // slot i holds list position hi-1-i
-            stage(rec, rdepth, inst_gauss[range.x + hi - 1 - threadIdx.x], X0, Y0, W, S, threadIdx.x);
+            stage<kAux>(rec, rdepth, inst_gauss[range.x + hi - 1 - threadIdx.x], X0, Y0, W, S, threadIdx.x);
 #pragma unroll
             for (int f = 0; f < kNF; ++f) part[threadIdx.x][f] = 0.0f;
         }
@@ -420,9 +450,10 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, co
             const int j = e & 0xff;
             const uint32_t m = e >> 8;
             const int pos = hi - 1 - j;
-            const float4 a = S.a[j], b = S.b[j];
-            const float cb = S.c[j];
-            const float dj = kAux ? S.d[j] : 0.0f;
+            const float4 a = S.a[j], b = S.b[j], c = S.c[j];
+            const float2 ex = S.e[j];
+            const float cb = c.x;
+            const float dj = c.w;
             float v[kAccAux];
 #pragma unroll
             for (int f = 0; f < kAccAux; ++f) v[f] = 0.0f;
@@ -430,11 +461,13 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, co
 #pragma unroll
             for (int k = 0; k < kPPL; ++k) {
                 if (!(m & (1u << k))) continue;  // uniform
-                float alpha, G, dx, dy;
-                const float araw = pixel_alpha(slot_px<kW>(w, k, lx) + 0.5f, slot_py<kW>(w, k, ly) + 0.5f, a, b.x,
-                                               b.y, W, half, s.alpha_max, alpha, G, dx, dy);
+                const float fi = (float)slot_px<kW>(w, k, lx), fj = (float)slot_py<kW>(w, k, ly);
+                float alpha, G;
+                const float araw = pixel_alpha(fi, fj, a, c, b.x, b.y, s.alpha_max, alpha, G);
                 const bool valid = pos < last[k] && alpha >= s.alpha_min;
                 if (__ballot(valid) == 0ull) continue;  // uniform: nothing blended in this quadrant
+                // the pixel offset d (the centre a turn further for the columns past thr)
+                const float dx = ((fi + 0.5f) - ex.x) - (fi >= c.z ? W : 0.0f), dy = (fj + 0.5f) - ex.y;
                 any |= valid;
                 const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
                 const float Tf = T[k] * inv;  // transmittance in front of this instance
