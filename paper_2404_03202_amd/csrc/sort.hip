@@ -27,7 +27,10 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / kWave;
-constexpr int kItems = 16;                  // keys per thread per pass
+#ifndef OMNIGS_SORT_ITEMS
+#define OMNIGS_SORT_ITEMS 8
+#endif
+constexpr int kItems = OMNIGS_SORT_ITEMS;   // keys per thread per pass
 constexpr int kTileKeys = kThreads * kItems;  // keys per block
 constexpr int kRadixBits = 8;
 constexpr int kBins = 1 << kRadixBits;
