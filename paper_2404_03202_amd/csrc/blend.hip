@@ -36,8 +36,10 @@
 // between rows pair two fields per exchange, DPP finishes inside the rows: no
 // LDS traffic), and one lane per row adds up to three of the sums into the
 // instance's LDS slot; after the batch, the lane that staged the instance
-// converts the sums and issues the float atomics to global memory (one per
-// nonzero field per (tile, instance)).
+// converts the sums to screen-space gradients in place, and the workgroup
+// adds them to global memory with float atomics (one per nonzero field per
+// (tile, instance)), issued field-contiguous: consecutive lanes take
+// consecutive fields of the same few Gaussians.
 #include "internal.h"
 
 #ifndef OMNIGS_FWD_WAVES
@@ -531,10 +533,19 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, co
             out[7] = mo[7];
             out[8] = mo[8];
             if (kAux) out[kNF - 1] = mo[kNF - 1];  // dL/dd
-            float *dst = acc + (int64_t)S.gid[j] * kNF;
 #pragma unroll
-            for (int f = 0; f < kNF; ++f)
-                if (out[f] != 0.0f) atomicAdd(dst + f, out[f]);
+            for (int f = 0; f < kNF; ++f) part[j][f] = out[f];
+        }
+        __syncthreads();
+        // the workgroup's threads walk the slots' fields in order, so the
+        // lanes of one atomic instruction cover whole records of a few
+        // Gaussians (a handful of cache lines) rather than one field of 64
+        // scattered Gaussians (64 lines): L2 takes far fewer atomic requests
+        const float *flat = &part[0][0];
+        for (int q = threadIdx.x; q < nb * kNF; q += kWave * kW) {
+            const int j = q / kNF, f = q - j * kNF;
+            const float val = flat[q];
+            if (val != 0.0f) atomicAdd(acc + (int64_t)S.gid[j] * kNF + f, val);
         }
     }
 }
