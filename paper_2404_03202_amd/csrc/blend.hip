@@ -83,7 +83,7 @@ __device__ inline int find_frame(const FrameTable &T, uint32_t tile) {
 
 // Staged instances (LDS):
 //   a = (u0a, v0, l00, l10), b = (l11, o, r, g), c = (b, u0b, thr, depth),
-//   e = (xa, y) (backward only), quad = quadrant mask
+//   e = (xa, xb, y) (backward only), quad = quadrant mask
 // with L the record's scaled Cholesky factor of the conic:
 // -(l00 dx + l10 dy)^2 - (l11 dy)^2 = log2(e) * (-1/2 d^T Q d).  The pixel at
 // integer tile coordinates (i, j) has d = (i + 1/2 - x, j + 1/2 - y) with the
@@ -99,7 +99,7 @@ template <int kW, bool kBwd>
 struct Stage {
     static constexpr int kBatch = kWave * kW;
     float4 a[kBatch], b[kBatch], c[kBatch];
-    float2 e[kBwd ? kBatch : 1];
+    float4 e[kBwd ? kBatch : 1];
     uint32_t quad[kBatch];
     uint32_t gid[kBatch];
     uint16_t list[kW][kBatch];
@@ -192,7 +192,7 @@ __device__ inline void stage(const BlendRecord *rec, const float *rdepth, uint32
     S.a[slot] = make_float4(u0a, v0, l00, l10);
     S.b[slot] = make_float4(l11, rb4.w, rc4.x, rc4.y);
     S.c[slot] = make_float4(rc4.z, u0b, thr, kAux ? rdepth[gid] : 0.0f);
-    if (kBwd) S.e[slot] = make_float2(xa, y);
+    if (kBwd) S.e[slot] = make_float4(xa, (float)xbd, y, 0.0f);
     S.quad[slot] = quad;
     S.gid[slot] = gid;
 }
@@ -224,7 +224,7 @@ __device__ __forceinline__ float pixel_alpha(float i, float j, float4 a, float4 
     const float v = __builtin_fmaf(l11, j, a.y);
     G = __builtin_amdgcn_exp2f(-__builtin_fmaf(u, u, v * v));
     const float araw = o * G;
-    alpha = araw < alpha_max ? araw : alpha_max;
+    alpha = fminf(araw, alpha_max);  // alpha_max also for a NaN araw
     return araw;
 }
 
@@ -287,12 +287,13 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_forward(FrameTable FT, con
                 float alpha, G;
                 pixel_alpha((float)slot_px<kW>(w, k, lx), (float)slot_py<kW>(w, k, ly), a, c, b.x, b.y, s.alpha_max,
                             alpha, G);
-                const float Tn = T[k] * (1.0f - alpha);
+                const float aT = alpha * T[k];
+                const float Tn = T[k] - aT;  // T (1 - alpha)
                 const bool live = !(done & (1u << k)) && alpha >= s.alpha_min;
-                const bool stop = live && Tn < s.T_min;
-                const bool take = live && !stop;
-                done |= stop ? (1u << k) : 0u;
-                const float wgt = take ? alpha * T[k] : 0.0f;
+                const bool keep = Tn >= s.T_min;  // T and alpha are finite
+                const bool take = live && keep;
+                done |= (live && !keep) ? (1u << k) : 0u;
+                const float wgt = take ? aT : 0.0f;
                 C0[k] = __builtin_fmaf(b.z, wgt, C0[k]);
                 C1[k] = __builtin_fmaf(b.w, wgt, C1[k]);
                 C2[k] = __builtin_fmaf(cb, wgt, C2[k]);
@@ -453,7 +454,7 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, co
             const uint32_t m = e >> 8;
             const int pos = hi - 1 - j;
             const float4 a = S.a[j], b = S.b[j], c = S.c[j];
-            const float2 ex = S.e[j];
+            const float4 ex = S.e[j];
             const float cb = c.x;
             const float dj = c.w;
             float v[kAccAux];
@@ -469,15 +470,15 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, co
                 const bool valid = pos < last[k] && alpha >= s.alpha_min;
                 if (__ballot(valid) == 0ull) continue;  // uniform: nothing blended in this quadrant
                 // the pixel offset d (the centre a turn further for the columns past thr)
-                const float dx = ((fi + 0.5f) - ex.x) - (fi >= c.z ? W : 0.0f), dy = (fj + 0.5f) - ex.y;
+                const float dx = (fi + 0.5f) - (fi >= c.z ? ex.y : ex.x), dy = (fj + 0.5f) - ex.z;
                 any |= valid;
                 const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
                 const float Tf = T[k] * inv;  // transmittance in front of this instance
                 T[k] = valid ? Tf : T[k];
                 const float wgt = valid ? alpha * Tf : 0.0f;
-                float dLc = dL0[k] * b.z + dL1[k] * b.w + dL2[k] * cb;
+                float dLc = __builtin_fmaf(dL0[k], b.z, __builtin_fmaf(dL1[k], b.w, dL2[k] * cb));
                 if (kAux) dLc += __builtin_fmaf(dLD[k], dj, dLA[k]);  // depth and alpha channels
-                const float dalpha = dLc * Tf - dLS[k] * inv;
+                const float dalpha = __builtin_fmaf(dLc, Tf, -(dLS[k] * inv));
                 dLS[k] = __builtin_fmaf(dLc, wgt, dLS[k]);
                 v[6] = __builtin_fmaf(dL0[k], wgt, v[6]);
                 v[7] = __builtin_fmaf(dL1[k], wgt, v[7]);
