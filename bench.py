@@ -11,8 +11,10 @@ omnigs_backward (reverse blend, projection chain).  Inputs are resident in
 HBM when timing starts.
 
 Prints one JSON line (stdout) with the throughput, the roofline of the
-dominant kernel (from HIP-event timings of every stage taken during the timed
-region), the serving measurement (continuous batching vs one request at a
+dominant kernel (its stage bracketed with HIP events during the timed region;
+no other stage is, since each event costs the stream a few microseconds; the
+per-stage breakdown comes from a second pass over the same steps with every
+stage timed), the serving measurement (continuous batching vs one request at a
 time on the same resident scene: renders/s and p50/p99 latency at Poisson
 arrival rates of 0.5, 1 and 2 times the one-at-a-time capacity) and the FP64
 CPU oracle timed on one pose of the training workload.
@@ -67,6 +69,24 @@ def measured_traffic():
         return float(kv["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def timed(step, ks, stages):
+    """Seconds taken by step(k) for k in ks between two synchronisations,
+    with the library's stage events on for `stages` only (None: every stage,
+    (): none); returns (seconds, {stage: (ms, launches)})."""
+    import torch
+    from paper_2404_03202_amd import omnigs as B
+    B.omnigs_profile_read()
+    B.omnigs_profile_enable(stages is None or len(stages) > 0, stages=None if stages is None else list(stages))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in ks:
+        step(k)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    B.omnigs_profile_enable(False)
+    return dt, B.omnigs_profile_read()
 
 
 def cpu_baseline(g, poses, gt_images):
@@ -168,15 +188,8 @@ def stress_bench(steps, log):
     torch.cuda.synchronize()
     inst.clear()
     entries.clear()
-    B.omnigs_profile_read()
-    B.omnigs_profile_enable(True)
-    t0 = time.perf_counter()
-    for k in range(steps):
-        step(k)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    B.omnigs_profile_enable(False)
-    prof = B.omnigs_profile_read()
+    dt, _ = timed(step, range(steps), ())
+    _, prof = timed(step, range(steps), None)  # stage breakdown
     ms = {k: v[0] / steps for k, v in prof.items() if v[1]}
     M = float(np.mean(inst))
     S = float(np.mean(entries))
@@ -189,13 +202,15 @@ def stress_bench(steps, log):
     blended /= steps
     supers = ((W // 16 + 7) // 8) * ((H // 16 + 7) // 8)
     passes = -(-max(1, int(np.ceil(np.log2(supers)))) // 8)
-    # algorithmic bytes per stage (u32 keys and values; each radix pass reads
-    # the keys for its histogram, then reads and writes key + value):
-    # depth sort over N; the scan of the block counts in depth order; block entries
-    # (S) emitted, sorted by block and ranged; the expansion reads every entry
-    # and its rectangle twice (count, write) and writes each instance once
-    algo = dict(depth_sort=4 * 20 * n + 4 * n, emit_count=12 * n, super_emit=8 * S + 20 * n,
-                super_sort=passes * 20 * S + 4 * S, tile_bin=24 * S + 4 * M)
+    # algorithmic bytes per stage (u32 keys and values; a sort reads the keys
+    # once for the digit histograms of all its passes, then each pass reads
+    # and writes key + value, the depth sort's first pass generating its
+    # values): depth sort over N; the scan of the block counts in depth order;
+    # block entries (S) emitted, sorted by block and ranged; the expansion
+    # reads every entry and its rectangle twice (count, write) and writes each
+    # instance once
+    algo = dict(depth_sort=(4 + 4 * 16 - 4) * n, emit_count=12 * n, super_emit=8 * S + 20 * n,
+                super_sort=(4 + passes * 16) * S + 4 * S, tile_bin=24 * S + 4 * M)
     rates = {k: algo[k] / (ms[k] * 1e-3) / 1e9 for k in algo if k in ms}
     out = dict(workload="3M Gaussians, room layout, scales log-uniform [0.002, 0.5], SH degree 3, 3840x1920 ERP, "
                         f"{len(poses)} poses, forward + L1 + backward per pose",
@@ -220,15 +235,12 @@ def train_bench(g, poses, targets, steps, log):
     for k in range(3):
         tr.step(poses[k % len(poses)], targets[k % len(poses)])
     torch.cuda.synchronize()
-    B.omnigs_profile_read()
-    B.omnigs_profile_enable(True)
-    t0 = time.perf_counter()
-    for k in range(steps):
+
+    def it(k):
         tr.step(poses[k % len(poses)], targets[k % len(poses)])
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    B.omnigs_profile_enable(False)
-    prof = B.omnigs_profile_read()
+
+    dt, _ = timed(it, range(steps), ())
+    _, prof = timed(it, range(steps), None)  # stage breakdown
     n0 = tr.n
     torch.cuda.synchronize()
     B.omnigs_profile_enable(True)
@@ -267,15 +279,8 @@ def pinhole_bench(gd, crops, crop_targets, poses, steps, log):
     for k in range(5):
         crop_step(k)
     torch.cuda.synchronize()
-    B.omnigs_profile_read()
-    B.omnigs_profile_enable(True)
-    t0 = time.perf_counter()
-    for k in range(steps):
-        crop_step(k)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    B.omnigs_profile_enable(False)
-    prof = B.omnigs_profile_read()
+    dt, _ = timed(crop_step, range(steps), ())
+    _, prof = timed(crop_step, range(steps), None)  # stage breakdown
     crop = dict(workload="1M Gaussians, 1024x1024 pinhole crops (90 deg), forward + L1 + backward per crop",
                 steps=steps, iters_per_s=steps / dt, ms_per_step=dt * 1e3 / steps,
                 stage_ms={k: v[0] / steps for k, v in prof.items() if v[1]})
@@ -428,16 +433,12 @@ def main():
     for k in range(args.warmup):
         step(k)
     torch.cuda.synchronize()
-    B.omnigs_profile_read()
-    B.omnigs_profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.warmup, args.warmup + args.steps):
-        step(k)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    B.omnigs_profile_enable(False)
-    prof = B.omnigs_profile_read()
+    ks = range(args.warmup, args.warmup + args.steps)
+    # the timed region: only the dominant kernel's stage carries events
+    dt, prof_bwd = timed(step, ks, ("blend_bwd",))
+    # stage breakdown: the same steps again, every stage bracketed
+    dt_prof, prof = timed(step, ks, None)
+    log(f"{args.steps / dt:.1f} iters/s ({args.steps / dt_prof:.1f} with every stage timed)")
     log("stages (ms per step): " + ", ".join(f"{k} {v[0] / args.steps:.3f}" for k, v in prof.items() if v[1]))
 
     # pairs walked / blended by the timed steps (deterministic re-render)
@@ -446,7 +447,7 @@ def main():
         f = B.omnigs_forward(gd, poses[k % len(poses)], with_blended=True)
         walked += int(f.n_contrib.sum(dtype=torch.int64))
         blended += int(f.n_blended.sum(dtype=torch.int64))
-    bwd_ms, bwd_n = prof["blend_bwd"]
+    bwd_ms, bwd_n = prof_bwd["blend_bwd"]
     flops = FLOP_ALPHA * walked + FLOP_GRAD * blended
     achieved = flops / (bwd_ms * 1e-3)
     dominant = max(((k, v[0]) for k, v in prof.items()), key=lambda kv: kv[1])[0]
@@ -462,6 +463,7 @@ def main():
                                     "2048x1024 ERP, 200 poses, forward + L1 + backward per pose",
                            gaussians=int(g["means"].shape[0]), width=2048, height=1024, poses=len(poses)),
                stage_ms={k: v[0] / args.steps for k, v in prof.items() if v[1]},
+               ms_per_step_all_stages_timed=dt_prof * 1e3 / args.steps,
                roofline=roofline)
     if not args.no_train:
         out["train"] = train_bench(g, poses, targets, min(args.steps, 100), log)

@@ -356,11 +356,15 @@ omnigs_status omnigs_reset_opacity(omnigs_params *p, omnigs_params *m1, omnigs_p
 /* Thread-local message describing the last non-OK status of this thread. */
 const char *omnigs_last_error(void);
 
-/* Stage timing.  When enabled, each stage is bracketed with HIP events on
- * the call's stream and its GPU time is accumulated per stage until
+/* Stage timing.  Bit k of `stages` enables stage k (0 disables all,
+ * OMNIGS_PROFILE_ALL every stage): each enabled stage is bracketed with HIP
+ * events on the call's stream and its GPU time is accumulated per stage until
  * omnigs_profile_read (which synchronises the recorded events, then resets
- * the accumulators).  Stages: see omnigs_profile_stage_name. */
-omnigs_status omnigs_profile_enable(int32_t on);
+ * the accumulators).  Recording an event costs the stream a few microseconds,
+ * so a throughput measurement enables only the stages it reports.  Stages:
+ * see omnigs_profile_stage_name. */
+#define OMNIGS_PROFILE_ALL 0xffffffffu
+omnigs_status omnigs_profile_enable(uint32_t stages);
 int32_t omnigs_profile_num_stages(void);
 const char *omnigs_profile_stage_name(int32_t stage);
 /* ms[k] = total ms of stage k since the last read, launches[k] = number of

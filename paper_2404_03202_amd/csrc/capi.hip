@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <atomic>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -61,7 +62,7 @@ const char *kStageNames[kStCount] = {"project",    "depth_sort", "emit_count", "
 
 struct Profiler {
     std::mutex mu;
-    bool on = false;
+    std::atomic<uint32_t> stages{0};  // bit k: stage k is timed (read without the lock)
     struct Rec {
         int stage;
         hipEvent_t a, b;
@@ -90,7 +91,7 @@ struct StageTimer {
     int stage;
     hipEvent_t a = nullptr, b = nullptr;
     StageTimer(hipStream_t s, int stg) : st(s), stage(stg) {
-        if (!g_prof.on) return;
+        if (!((g_prof.stages.load(std::memory_order_relaxed) >> stg) & 1u)) return;
         std::lock_guard<std::mutex> lk(g_prof.mu);
         a = g_prof.get();
         b = g_prof.get();
@@ -248,13 +249,12 @@ struct GeomState {
     }
 };
 struct GeomScratch {
-    uint32_t *depth_key, *iota, *keys_tmp, *vals_tmp, *keys_sorted, *offs, *n_super;
+    uint32_t *depth_key, *keys_tmp, *vals_tmp, *keys_sorted, *offs, *n_super;
     uint32_t *totals;  // [0] super entries S, [1] tile instances M (adjacent: one readback)
     void *sort_tmp, *scan_tmp;
     void carve(Arena &a, int64_t n) {
         const size_t m = (size_t)(n > 0 ? n : 1);
         depth_key = a.take<uint32_t>(m);
-        iota = a.take<uint32_t>(m);
         keys_tmp = a.take<uint32_t>(m);
         vals_tmp = a.take<uint32_t>(m);
         keys_sorted = a.take<uint32_t>(m);
@@ -272,8 +272,7 @@ struct GeomScratch {
 omnigs_status sort_and_count(int64_t n, GeomState &gst, GeomScratch &gs, hipStream_t st) {
     {
         StageTimer t(st, kStDepthSort);
-        HIP_TRY(launch_iota(gs.iota, n, st));
-        HIP_TRY(radix_sort_pairs(gs.depth_key, gs.iota, gs.keys_tmp, gs.vals_tmp, gs.keys_sorted, gst.order, n, 32,
+        HIP_TRY(radix_sort_pairs(gs.depth_key, nullptr, gs.keys_tmp, gs.vals_tmp, gs.keys_sorted, gst.order, n, 32,
                                  gs.sort_tmp, st));
     }
     {
@@ -856,9 +855,9 @@ omnigs_status omnigs_reset_opacity(omnigs_params *p, omnigs_params *m1, omnigs_p
     return OMNIGS_OK;
 }
 
-omnigs_status omnigs_profile_enable(int32_t on) {
+omnigs_status omnigs_profile_enable(uint32_t stages) {
     std::lock_guard<std::mutex> lk(g_prof.mu);
-    g_prof.on = on != 0;
+    g_prof.stages.store(stages, std::memory_order_relaxed);
     return OMNIGS_OK;
 }
 

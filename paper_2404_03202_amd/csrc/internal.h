@@ -145,14 +145,15 @@ hipError_t launch_project_backward(const ProjectArgs &a, const uint32_t *n_tiles
                                    const omnigs_grads &gr, hipStream_t st);
 
 // radix sort of (u32 key, u32 value) pairs on the low `bits` bits of the key;
-// stable.  Result lands in keys_out/vals_out.  `scratch` from sort_scratch_bytes.
+// stable.  Result lands in keys_out/vals_out.  vals_in == nullptr sorts the
+// input positions 0..n-1 as values.  `scratch` from sort_scratch_bytes.
 // n_dev (device, may be null): the element count is min(n, *n_dev), read on
-// the device (n then only bounds the buffers and the grid).
+// the device (n then only bounds the buffers and the grid).  n < 2^31 - 1,
+// else hipErrorInvalidValue.
 size_t sort_scratch_bytes(int64_t n);
 hipError_t radix_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_tmp,
                             uint32_t *vals_tmp, uint32_t *keys_out, uint32_t *vals_out, int64_t n, int bits,
                             void *scratch, hipStream_t st, const uint32_t *n_dev = nullptr);
-hipError_t launch_iota(uint32_t *v, int64_t n, hipStream_t st);
 
 // Exclusive scan of u32 (optionally of in[gather[i]]); *total (device, may be
 // null) receives the sum.  `scratch` from scan_scratch_bytes.

@@ -1,7 +1,7 @@
-// sort.hip -- binning of Gaussian instances into 16x16 tiles (Sec. 3.3: "each
-// tile counts the 2D Gaussians whose radius of influence covers this tile,
-// generating one instance per influence"), ordered by distance t_r inside
-// each tile (Sec. 3.3: ERP sorts by t_r, not t_z).
+// sort.hip -- binning of Gaussian instances into 16x16 tiles (Sec. 3.3: one
+// instance per Gaussian and tile its footprint covers), ordered by the
+// distance t_r inside each tile (Sec. 3.3: the ERP model orders by t_r, not
+// t_z).
 //
 // Instead of one wide (tile | depth) key sort over all M instances, the
 // order is built in two narrow stable sorts:
@@ -15,12 +15,18 @@
 // sort on (tile, t_r, id), with ~4x less traffic than a 6-pass 64-bit key
 // sort over M.
 //
-// The LSD passes use 8-bit digits.  A pass is: per-block digit histogram,
-// exclusive scan of the [digit][block] count matrix, and a scatter in which
-// each wave ranks its keys with ballot-based match (8 ballots per key, wave64),
-// the block places keys in LDS in digit order, and writes them out as
-// contiguous per-digit runs.
+// The LSD radix sort uses 8-bit digits and one kernel per pass after a
+// single histogram kernel (the one-sweep scheme of Adinets and Merrill,
+// 2022): the histogram kernel counts every pass's digits over the whole
+// input at once; in a pass, each block ranks its keys with ballot-based
+// matches (8 ballots per key, wave64), publishes its per-digit counts, takes
+// the counts of all earlier blocks from their published words (decoupled
+// lookback), places its keys in LDS in digit order and writes them out as
+// contiguous per-digit runs.  A sort is a clear, the histogram and the
+// passes: no scan kernels between passes.
 #include "internal.h"
+
+#include <algorithm>
 
 namespace omnigs {
 namespace {
@@ -28,7 +34,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / kWave;
 #ifndef OMNIGS_SORT_ITEMS
-#define OMNIGS_SORT_ITEMS 8
+#define OMNIGS_SORT_ITEMS 16
 #endif
 constexpr int kItems = OMNIGS_SORT_ITEMS;   // keys per thread per pass
 constexpr int kTileKeys = kThreads * kItems;  // keys per block
@@ -84,51 +90,95 @@ __device__ inline int64_t sort_count(int64_t n, const uint32_t *n_dev) {
     return m < n ? m : n;
 }
 
-__global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t *keys, int64_t n_max, const uint32_t *n_dev,
-                                                          int shift, int bits, uint32_t *counts, int nblocks) {
-    __shared__ uint32_t hist[kWaves][kBins];
-    const int64_t n = sort_count(n_max, n_dev);
-    const int w = threadIdx.x / kWave, lane = __lane_id();
-    for (int k = threadIdx.x; k < kWaves * kBins; k += kThreads) (&hist[0][0])[k] = 0;
+// Lookback words: 0 until published, then count + 1 of one digit, the top
+// bit set when the count is inclusive (this block and all earlier ones)
+// rather than this block's own.  Counts stay below 2^31 - 1 (checked on the
+// host).
+constexpr uint32_t kInc = 1u << 31, kCountMask = kInc - 1u;
+constexpr int kMaxPasses = 4;
+constexpr int kHeadWords = kMaxPasses * kBins + 64;  // digit totals, then one ticket per pass
+// Bound on the polls of one lookback word: an earlier block always publishes
+// (blocks take their position from a ticket, so every earlier position is
+// held by a block that is already running), the bound only guarantees that
+// the kernel ends whatever happens.
+constexpr uint32_t kMaxPolls = 1u << 20;
+#ifndef OMNIGS_SORT_LOOK
+#define OMNIGS_SORT_LOOK 4
+#endif
+constexpr int kLook = OMNIGS_SORT_LOOK;  // lookback words loaded at once
+
+// Digit totals of every pass over the whole input (one read of the keys);
+// ghist is zero on entry.  Each block takes chunks of kHistChunk keys (all
+// loads of a chunk issued before its counts), counts them in per-wave LDS
+// histograms and adds its nonzero totals to ghist once.
+constexpr int kHistItems = 16;
+constexpr int kHistChunk = kThreads * kHistItems;
+constexpr int kHistMaxBlocks = 256;  // bounds the global atomics per digit
+__global__ __launch_bounds__(kThreads) void k_sort_hist(const uint32_t *keys, int64_t n_max, const uint32_t *n_dev,
+                                                         int passes, int bits, uint32_t *ghist) {
+    __shared__ uint32_t h[kWaves][kMaxPasses * kBins];
+    for (int k = threadIdx.x; k < kWaves * kMaxPasses * kBins; k += kThreads) (&h[0][0])[k] = 0;
     __syncthreads();
-    const uint32_t mask = (1u << bits) - 1u;
-    const int64_t base = (int64_t)blockIdx.x * kTileKeys + (int64_t)w * (kItems * kWave);
-#pragma unroll 4
-    for (int it = 0; it < kItems; ++it) {
-        const int64_t idx = base + it * kWave + lane;
-        const bool valid = idx < n;
-        const uint32_t d = valid ? (keys[idx] >> shift) & mask : 0u;
-        const uint64_t peers = match_digit(d, bits, valid);
-        if (valid && (peers & lanemask_lt()) == 0) hist[w][d] += (uint32_t)__popcll(peers);
+    const int64_t n = sort_count(n_max, n_dev);
+    const int w = threadIdx.x / kWave;
+    for (int64_t c0 = (int64_t)blockIdx.x * kHistChunk; c0 < n; c0 += (int64_t)gridDim.x * kHistChunk) {
+        uint32_t key[kHistItems];
+#pragma unroll
+        for (int it = 0; it < kHistItems; ++it) {
+            const int64_t idx = c0 + it * kThreads + threadIdx.x;
+            key[it] = idx < n ? keys[idx] : 0u;
+        }
+#pragma unroll
+        for (int it = 0; it < kHistItems; ++it) {
+            if (c0 + it * kThreads + threadIdx.x >= n) continue;
+            for (int p = 0; p < passes; ++p) {
+                const int pb = min(kRadixBits, bits - p * kRadixBits);
+                atomicAdd(&h[w][p * kBins + ((key[it] >> (p * kRadixBits)) & ((1u << pb) - 1u))], 1u);
+            }
+        }
     }
     __syncthreads();
-    for (int d = threadIdx.x; d < kBins; d += kThreads) {
-        if (d <= (int)mask) {
-            uint32_t s = 0;
-            for (int k = 0; k < kWaves; ++k) s += hist[k][d];
-            counts[(int64_t)d * nblocks + blockIdx.x] = s;
-        }
+    for (int k = threadIdx.x; k < passes * kBins; k += kThreads) {
+        uint32_t t = 0;
+#pragma unroll
+        for (int q = 0; q < kWaves; ++q) t += h[q][k];
+        if (t) atomicAdd(&ghist[k], t);
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t *keys_in, const uint32_t *vals_in,
-                                                             uint32_t *keys_out, uint32_t *vals_out, int64_t n_max,
-                                                             const uint32_t *n_dev, int shift, int bits,
-                                                             const uint32_t *offsets, int nblocks) {
+// One pass: the block at ticket position b ranks its kTileKeys keys by digit
+// (ballot matches per wave), publishes its digit counts, looks back over the
+// earlier blocks' words for the count of each digit before it (decoupled
+// lookback), and writes its keys as contiguous per-digit runs at
+// (keys of smaller digits) + (earlier blocks' keys of the same digit) +
+// (rank in the block).  vals_in == nullptr: the values are the input
+// positions.
+__global__ __launch_bounds__(kThreads) void k_radix_pass(const uint32_t *keys_in, const uint32_t *vals_in,
+                                                          uint32_t *keys_out, uint32_t *vals_out, int64_t n_max,
+                                                          const uint32_t *n_dev, int shift, int bits,
+                                                          const uint32_t *ghist, uint32_t *status,
+                                                          uint32_t *ticket) {
     __shared__ uint32_t s_keys[kTileKeys];
     __shared__ uint32_t s_vals[kTileKeys];
     __shared__ uint32_t cnt[kWaves][kBins];
-    __shared__ uint32_t digit_start[kBins];
     __shared__ uint32_t gbase[kBins];
     __shared__ uint32_t wave_tot[kWaves];
     __shared__ uint32_t total;
+    __shared__ uint32_t s_pos;
     const int64_t n = sort_count(n_max, n_dev);
-    const int w = threadIdx.x / kWave, lane = __lane_id();
-    const uint32_t mask = (1u << bits) - 1u;
-    const int64_t block0 = (int64_t)blockIdx.x * kTileKeys;
-    const int64_t base = block0 + (int64_t)w * (kItems * kWave);
+    // the first ceil(n / kTileKeys) workgroups take the tickets 0, 1, ... in
+    // the order they start; the others (a grid sized for a capacity) have no
+    // keys and leave at once
+    if ((int64_t)blockIdx.x * kTileKeys >= n) return;
+    if (threadIdx.x == 0) s_pos = atomicAdd(ticket, 1u);
+    const uint32_t gcount = ghist[threadIdx.x];  // keys of digit threadIdx.x (0 past the pass's digits)
     for (int k = threadIdx.x; k < kWaves * kBins; k += kThreads) (&cnt[0][0])[k] = 0;
     __syncthreads();
+    const uint32_t b = s_pos;
+    const int64_t block0 = (int64_t)b * kTileKeys;
+    const int w = threadIdx.x / kWave, lane = __lane_id();
+    const uint32_t mask = (1u << bits) - 1u;
+    const int64_t base = block0 + (int64_t)w * (kItems * kWave);
     uint32_t key[kItems], val[kItems], rank[kItems];
     // keys past n get the largest digit: they sort last in the block and are
     // never written out
@@ -137,7 +187,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t *keys
         const int64_t idx = base + it * kWave + lane;
         const bool valid = idx < n;
         key[it] = valid ? keys_in[idx] : 0xffffffffu;
-        val[it] = valid ? vals_in[idx] : 0u;
+        val[it] = valid ? (vals_in ? vals_in[idx] : (uint32_t)idx) : 0u;
     }
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
@@ -149,7 +199,6 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t *keys
         if ((peers & lanemask_lt()) == 0) cnt[w][d] = before + (uint32_t)__popcll(peers);
     }
     __syncthreads();
-    // digit-major block layout: digit_start[d] + sum of earlier waves' counts
     const int d = threadIdx.x;  // kThreads == kBins
     uint32_t per[kWaves], tot = 0;
 #pragma unroll
@@ -157,8 +206,53 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t *keys
         per[k] = cnt[k][d];
         tot += per[k];
     }
+    // padding keys (digit `mask`) are not counted
+    const int64_t nvalid64 = n - block0 < kTileKeys ? n - block0 : kTileKeys;
+    const uint32_t pad = (uint32_t)(kTileKeys - nvalid64);
+    const uint32_t mine = d == (int)mask ? tot - pad : tot;
+    uint32_t before = 0;  // keys of digit d in the earlier blocks
+    if (d <= (int)mask) {
+        uint32_t *word = status + (int64_t)b * kBins + d;
+        __hip_atomic_store(word, (b == 0 ? kInc : 0u) | (mine + 1u), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (b > 0) {
+            // windows of kLook earlier blocks, loaded together: sum their own
+            // counts back to the first inclusive word; an unpublished word is
+            // polled again from its position
+            int64_t p = (int64_t)b - 1;
+            uint32_t polls = 0;
+            for (;;) {
+                uint32_t v[kLook];
+#pragma unroll
+                for (int i = 0; i < kLook; ++i)
+                    v[i] = p - i >= 0 ? __hip_atomic_load(status + (p - i) * kBins + d, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT)
+                                      : kInc | 1u;  // before block 0: nothing
+                int used = 0;
+                bool inc = false, wait = false;
+#pragma unroll
+                for (int i = 0; i < kLook; ++i) {
+                    if (inc || wait) continue;
+                    if (v[i] == 0u) {
+                        wait = true;
+                        continue;
+                    }
+                    before += (v[i] & kCountMask) - 1u;
+                    inc = (v[i] & kInc) != 0u;
+                    ++used;
+                }
+                if (inc) break;
+                p -= used;
+                if (wait) {
+                    if (++polls >= kMaxPolls) break;
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+            __hip_atomic_store(word, kInc | (before + mine + 1u), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    // block layout: digit runs in order, each wave's keys after the earlier
+    // waves' keys of the same digit
     const uint32_t start = block_exclusive_scan(tot, wave_tot, &total);
-    digit_start[d] = start;
     {
         uint32_t run = start;
 #pragma unroll
@@ -167,7 +261,9 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t *keys
             run += per[k];
         }
     }
-    if (d <= (int)mask) gbase[d] = offsets[(int64_t)d * nblocks + blockIdx.x] - start;
+    // first output position of digit d: the keys of all smaller digits
+    const uint32_t gstart = block_exclusive_scan(gcount, wave_tot, &total);
+    if (d <= (int)mask) gbase[d] = gstart + before - start;
     __syncthreads();
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
@@ -178,15 +274,14 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t *keys
         s_vals[pos] = val[it];
     }
     __syncthreads();
-    int64_t nvalid = n - block0 < kTileKeys ? n - block0 : kTileKeys;
-    if (nvalid < 0) nvalid = 0;
-    for (int p = threadIdx.x; p < nvalid; p += kThreads) {
-        const uint32_t k = s_keys[p];
+    const int nvalid = (int)nvalid64;
+    for (int q = threadIdx.x; q < nvalid; q += kThreads) {
+        const uint32_t k = s_keys[q];
         const uint32_t dg = (k >> shift) & mask;
-        const uint32_t dst = gbase[dg] + (uint32_t)p;
+        const uint32_t dst = gbase[dg] + (uint32_t)q;
         if (dst < (uint64_t)n) {
             keys_out[dst] = k;
-            vals_out[dst] = s_vals[p];
+            vals_out[dst] = s_vals[q];
         }
     }
 }
@@ -345,11 +440,6 @@ __global__ __launch_bounds__(kThreads) void k_tile_ranges(const uint32_t *inst_t
     if (i + 1 == m || inst_tile[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
 }
 
-__global__ void k_iota(uint32_t *v, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) v[i] = (uint32_t)i;
-}
-
 __global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -393,48 +483,41 @@ hipError_t scan_exclusive(const uint32_t *in, uint32_t *out, int64_t n, uint32_t
 
 size_t sort_scratch_bytes(int64_t n) {
     const int64_t nb = blocks_for(n > 0 ? n : 1, kTileKeys);
-    const int64_t cells = nb * kBins;
-    return (((size_t)cells * 4 + 255) & ~(size_t)255) * 2 + scan_scratch_bytes(cells);
+    return ((size_t)kHeadWords + (size_t)kMaxPasses * nb * kBins) * 4 + 256;
 }
 
 hipError_t radix_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_tmp,
                             uint32_t *vals_tmp, uint32_t *keys_out, uint32_t *vals_out, int64_t n, int bits,
                             void *scratch, hipStream_t st, const uint32_t *n_dev) {
     if (n <= 0) return hipSuccess;
-    const int64_t nb = blocks_for(n, kTileKeys);
-    const int64_t cells = nb * kBins;
-    uint32_t *counts = static_cast<uint32_t *>(scratch);
-    uint32_t *offsets = reinterpret_cast<uint32_t *>(static_cast<char *>(scratch) +
-                                                      (((size_t)cells * 4 + 255) & ~(size_t)255));
-    void *scan_tmp = reinterpret_cast<char *>(offsets) + (((size_t)cells * 4 + 255) & ~(size_t)255);
+    if (n >= (int64_t)kCountMask) return hipErrorInvalidValue;  // lookback words hold count + 1 in 31 bits
     if (bits < 1) bits = 1;
+    if (bits > 32) bits = 32;
     const int passes = (bits + kRadixBits - 1) / kRadixBits;
+    const int64_t nb = blocks_for(n, kTileKeys);
+    // [digit totals per pass | tickets | lookback words per pass], cleared at once
+    uint32_t *head = static_cast<uint32_t *>(scratch);
+    uint32_t *ghist = head, *tickets = head + kMaxPasses * kBins;
+    uint32_t *status = head + kHeadWords;
+    const int64_t words = kHeadWords + (int64_t)passes * nb * kBins;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks_for(words, 256)), dim3(256), 0, st, head, 0u, words);
+    const int64_t hist_blocks = std::min<int64_t>(blocks_for(n, kHistChunk), kHistMaxBlocks);
+    hipLaunchKernelGGL(k_sort_hist, dim3((unsigned)hist_blocks), dim3(kThreads), 0, st, keys_in, n, n_dev, passes,
+                       bits, ghist);
     // ping-pong so that the last pass lands in keys_out / vals_out
     const uint32_t *src_k = keys_in, *src_v = vals_in;
     for (int p = 0; p < passes; ++p) {
         const int shift = p * kRadixBits;
-        const int pbits = (bits - shift) < kRadixBits ? (bits - shift) : kRadixBits;
-        const bool last = (p == passes - 1);
+        const int pbits = std::min(kRadixBits, bits - shift);
         const bool to_out = ((passes - 1 - p) % 2) == 0;
         uint32_t *dk = to_out ? keys_out : keys_tmp;
         uint32_t *dv = to_out ? vals_out : vals_tmp;
-        (void)last;
-        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kThreads), 0, st, src_k, n, n_dev, shift, pbits,
-                           counts, (int)nb);
-        // only (1 << pbits) digit rows are used: scan that prefix of the matrix
-        hipError_t e = scan_exclusive(counts, offsets, (int64_t)(1 << pbits) * nb, nullptr, scan_tmp, st, nullptr);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kThreads), 0, st, src_k, src_v, dk, dv, n,
-                           n_dev, shift, pbits, offsets, (int)nb);
+        hipLaunchKernelGGL(k_radix_pass, dim3((unsigned)nb), dim3(kThreads), 0, st, src_k, src_v, dk, dv, n, n_dev,
+                           shift, pbits, (const uint32_t *)(ghist + p * kBins), status + (int64_t)p * nb * kBins,
+                           tickets + p);
         src_k = dk;
         src_v = dv;
     }
-    return hipGetLastError();
-}
-
-hipError_t launch_iota(uint32_t *v, int64_t n, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_iota, dim3((unsigned)blocks_for(n, 256)), dim3(256), 0, st, v, n);
     return hipGetLastError();
 }
 

@@ -151,7 +151,7 @@ def load_library(path: str = LIB_PATH):
         lib.omnigs_reset_opacity.restype = ctypes.c_int
         lib.omnigs_last_error.argtypes = []
         lib.omnigs_last_error.restype = ctypes.c_char_p
-        lib.omnigs_profile_enable.argtypes = [ctypes.c_int32]
+        lib.omnigs_profile_enable.argtypes = [ctypes.c_uint32]
         lib.omnigs_profile_enable.restype = ctypes.c_int
         lib.omnigs_profile_num_stages.argtypes = []
         lib.omnigs_profile_num_stages.restype = ctypes.c_int32
@@ -577,8 +577,19 @@ def omnigs_reset_opacity(p: dict, m1: dict, m2: dict, value: float = 0.01):
 
 
 # ---------------------------------------------------------------- profiling
-def omnigs_profile_enable(on: bool = True):
-    _check(load_library().omnigs_profile_enable(1 if on else 0))
+def omnigs_profile_enable(on: bool = True, stages=None):
+    """Stage timing on or off; `stages` (names) limits it to those stages."""
+    lib = load_library()
+    if not on:
+        mask = 0
+    elif stages is None:
+        mask = 0xFFFFFFFF
+    else:
+        names = [lib.omnigs_profile_stage_name(k).decode() for k in range(lib.omnigs_profile_num_stages())]
+        mask = 0
+        for st in stages:
+            mask |= 1 << names.index(st)
+    _check(lib.omnigs_profile_enable(mask))
 
 
 def omnigs_profile_read() -> dict:
