@@ -85,13 +85,18 @@ __global__ __launch_bounds__(256) void k_bin_chunks(const uint2 *sranges, uint32
     nch[s] = (len + kChunk - 1) / kChunk;
 }
 
-// desc[k] = super-tile of chunk k.
-__global__ __launch_bounds__(256) void k_bin_desc(const uint32_t *choff, const uint32_t *nch, uint32_t n_super,
-                                                  uint64_t max_chunks, uint32_t *desc) {
-    const uint32_t s = blockIdx.x * 256u + threadIdx.x;
-    if (s >= n_super) return;
-    const uint32_t o = choff[s], n = nch[s];
-    for (uint32_t c = 0; c < n && (uint64_t)o + c < max_chunks; ++c) desc[o + c] = s;
+// desc[k] = super-tile of chunk k: the last s with choff[s] <= k (super-tiles
+// without chunks share their offset with the next one), one thread per chunk.
+__global__ __launch_bounds__(256) void k_bin_desc(const uint32_t *choff, uint32_t n_super, uint64_t max_chunks,
+                                                  uint32_t *desc) {
+    const uint64_t k = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+    if (k >= max_chunks || k >= choff[n_super]) return;
+    uint32_t lo = 0, hi = n_super;  // choff[lo] <= k < choff[hi]
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (choff[mid] <= k) lo = mid; else hi = mid;
+    }
+    desc[k] = lo;
 }
 
 __global__ __launch_bounds__(kThreads) void k_bin_count(SuperTable T, const uint2 *rect, const uint32_t *sinst_gauss,
@@ -243,7 +248,8 @@ hipError_t launch_binning(const SuperTable &T, uint32_t n_super_total, const uin
     hipLaunchKernelGGL(k_bin_chunks, dim3(sb), dim3(256), 0, st, sranges, n_super_total, nch);
     hipError_t e = scan_exclusive(nch, choff, n_super_total, choff + n_super_total, scan_tmp, st, nullptr);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_bin_desc, dim3(sb), dim3(256), 0, st, choff, nch, n_super_total, K, desc);
+    hipLaunchKernelGGL(k_bin_desc, dim3((unsigned)blocks_for((int64_t)K, 256)), dim3(256), 0, st, choff, n_super_total,
+                       K, desc);
     hipLaunchKernelGGL(k_bin_count, dim3((unsigned)K), dim3(kThreads), 0, st, T, rect, sinst_gauss, sranges, choff, nch,
                        desc, n_super_total, counts);
     e = scan_exclusive(counts, scanned, (int64_t)cells, scanned + cells, scan_tmp, st, nullptr);

@@ -78,45 +78,39 @@ __device__ inline void sh_basis(double x, double y, double z, double *Y) {
     }
 }
 
-// Gradient of each basis polynomial w.r.t. (x, y, z): dY[k][0..2].
-template <int D>
-__device__ inline void sh_basis_grad(double x, double y, double z, double (*dY)[3]) {
-    dY[0][0] = dY[0][1] = dY[0][2] = 0.0;
-    if (D >= 1) {
-        dY[1][0] = 0.0;   dY[1][1] = -kSH1; dY[1][2] = 0.0;
-        dY[2][0] = 0.0;   dY[2][1] = 0.0;   dY[2][2] = kSH1;
-        dY[3][0] = -kSH1; dY[3][1] = 0.0;   dY[3][2] = 0.0;
-    }
-    if (D >= 2) {
-        dY[4][0] = kSH2a * y;          dY[4][1] = kSH2a * x;          dY[4][2] = 0.0;
-        dY[5][0] = 0.0;                dY[5][1] = -kSH2a * z;         dY[5][2] = -kSH2a * y;
-        dY[6][0] = -2.0 * kSH2b * x;   dY[6][1] = -2.0 * kSH2b * y;   dY[6][2] = 4.0 * kSH2b * z;
-        dY[7][0] = -kSH2a * z;         dY[7][1] = 0.0;                dY[7][2] = -kSH2a * x;
-        dY[8][0] = 2.0 * kSH2c * x;    dY[8][1] = -2.0 * kSH2c * y;   dY[8][2] = 0.0;
-        if (D >= 3) {
-            const double xx = x * x, yy = y * y, zz = z * z;
-            dY[9][0] = -kSH3a * 6.0 * x * y;
-            dY[9][1] = -kSH3a * 3.0 * (xx - yy);
-            dY[9][2] = 0.0;
-            dY[10][0] = kSH3b * y * z;
-            dY[10][1] = kSH3b * x * z;
-            dY[10][2] = kSH3b * x * y;
-            dY[11][0] = kSH3c * 2.0 * x * y;
-            dY[11][1] = -kSH3c * (4.0 * zz - xx - 3.0 * yy);
-            dY[11][2] = -kSH3c * 8.0 * y * z;
-            dY[12][0] = -kSH3d * 6.0 * x * z;
-            dY[12][1] = -kSH3d * 6.0 * y * z;
-            dY[12][2] = kSH3d * (6.0 * zz - 3.0 * xx - 3.0 * yy);
-            dY[13][0] = -kSH3c * (4.0 * zz - 3.0 * xx - yy);
-            dY[13][1] = kSH3c * 2.0 * x * y;
-            dY[13][2] = -kSH3c * 8.0 * x * z;
-            dY[14][0] = kSH3e * 2.0 * x * z;
-            dY[14][1] = -kSH3e * 2.0 * y * z;
-            dY[14][2] = kSH3e * (xx - yy);
-            dY[15][0] = -kSH3a * 3.0 * (xx - yy);
-            dY[15][1] = kSH3a * 6.0 * x * y;
-            dY[15][2] = 0.0;
-        }
+// Gradient of basis polynomial k w.r.t. (x, y, z) (k constant after
+// unrolling, so the switch folds).
+__device__ inline void sh_basis_grad_k(int k, double x, double y, double z, double d[3]) {
+    const double xx = x * x, yy = y * y, zz = z * z;
+    switch (k) {
+        case 1: d[0] = 0.0; d[1] = -kSH1; d[2] = 0.0; break;
+        case 2: d[0] = 0.0; d[1] = 0.0; d[2] = kSH1; break;
+        case 3: d[0] = -kSH1; d[1] = 0.0; d[2] = 0.0; break;
+        case 4: d[0] = kSH2a * y; d[1] = kSH2a * x; d[2] = 0.0; break;
+        case 5: d[0] = 0.0; d[1] = -kSH2a * z; d[2] = -kSH2a * y; break;
+        case 6: d[0] = -2.0 * kSH2b * x; d[1] = -2.0 * kSH2b * y; d[2] = 4.0 * kSH2b * z; break;
+        case 7: d[0] = -kSH2a * z; d[1] = 0.0; d[2] = -kSH2a * x; break;
+        case 8: d[0] = 2.0 * kSH2c * x; d[1] = -2.0 * kSH2c * y; d[2] = 0.0; break;
+        case 9: d[0] = -kSH3a * 6.0 * x * y; d[1] = -kSH3a * 3.0 * (xx - yy); d[2] = 0.0; break;
+        case 10: d[0] = kSH3b * y * z; d[1] = kSH3b * x * z; d[2] = kSH3b * x * y; break;
+        case 11:
+            d[0] = kSH3c * 2.0 * x * y;
+            d[1] = -kSH3c * (4.0 * zz - xx - 3.0 * yy);
+            d[2] = -kSH3c * 8.0 * y * z;
+            break;
+        case 12:
+            d[0] = -kSH3d * 6.0 * x * z;
+            d[1] = -kSH3d * 6.0 * y * z;
+            d[2] = kSH3d * (6.0 * zz - 3.0 * xx - 3.0 * yy);
+            break;
+        case 13:
+            d[0] = -kSH3c * (4.0 * zz - 3.0 * xx - yy);
+            d[1] = kSH3c * 2.0 * x * y;
+            d[2] = -kSH3c * 8.0 * x * z;
+            break;
+        case 14: d[0] = kSH3e * 2.0 * x * z; d[1] = -kSH3e * 2.0 * y * z; d[2] = kSH3e * (xx - yy); break;
+        case 15: d[0] = -kSH3a * 3.0 * (xx - yy); d[1] = kSH3a * 6.0 * x * y; d[2] = 0.0; break;
+        default: d[0] = d[1] = d[2] = 0.0; break;  // k = 0: constant
     }
 }
 
@@ -528,23 +522,37 @@ __global__ __launch_bounds__(256) void k_project_backward(ProjectArgs A, const u
     }
     double dm[3];
     for (int k = 0; k < 3; ++k) dm[k] = A.R[k] * dt[0] + A.R[3 + k] * dt[1] + A.R[6 + k] * dt[2];
-    // SH colour
-    double Y[16], dY[16][3], sh[KD][3];
+    // SH colour: the coefficients loaded once as floats (all loads ahead of
+    // the dsh stores, which may alias them), the basis gradient accumulated
+    // term by term
+    double Y[16];
     sh_basis<D>(P.dir[0], P.dir[1], P.dir[2], Y);
-    sh_basis_grad<D>(P.dir[0], P.dir[1], P.dir[2], dY);
-    load_sh<D>(A, i, sh);
+    float shp[KD * 3];
+    {
+        const float *src = A.sh + i * (int64_t)K * 3;
+#pragma unroll
+        for (int k = 0; k < KD * 3; ++k) shp[k] = src[k];
+    }
     double grgb[3];
-    for (int ch = 0; ch < 3; ++ch) {
-        double v = 0.5;
-        for (int k = 0; k < KD; ++k) v += Y[k] * sh[k][ch];
-        grgb[ch] = v < 0.0 ? 0.0 : g[6 + ch];
+    {
+        double v[3] = {0.5, 0.5, 0.5};
+#pragma unroll
+        for (int k = 0; k < KD; ++k)
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) v[ch] += Y[k] * (double)shp[3 * k + ch];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) grgb[ch] = v[ch] < 0.0 ? 0.0 : g[6 + ch];
     }
     double gdir[3] = {0.0, 0.0, 0.0};
+#pragma unroll
     for (int k = 0; k < KD; ++k) {
-        const double s = sh[k][0] * grgb[0] + sh[k][1] * grgb[1] + sh[k][2] * grgb[2];
-        gdir[0] += s * dY[k][0];
-        gdir[1] += s * dY[k][1];
-        gdir[2] += s * dY[k][2];
+        const double s = (double)shp[3 * k] * grgb[0] + (double)shp[3 * k + 1] * grgb[1] +
+                         (double)shp[3 * k + 2] * grgb[2];
+        double d[3];
+        sh_basis_grad_k(k, P.dir[0], P.dir[1], P.dir[2], d);
+        gdir[0] += s * d[0];
+        gdir[1] += s * d[1];
+        gdir[2] += s * d[2];
         dsh[3 * k] = (float)(Y[k] * grgb[0]);
         dsh[3 * k + 1] = (float)(Y[k] * grgb[1]);
         dsh[3 * k + 2] = (float)(Y[k] * grgb[2]);

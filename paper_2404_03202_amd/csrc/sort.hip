@@ -295,53 +295,129 @@ __device__ inline uint32_t scan_input(const uint32_t *in, const uint32_t *gather
     return g < (uint64_t)n ? in[g] : 0u;
 }
 
-__global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t *in, const uint32_t *gather, int64_t n,
-                                                           uint32_t *block_sums) {
-    __shared__ uint32_t wave_tot[kWaves];
-    __shared__ uint32_t total;
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x;
-    uint32_t s = 0;
-#pragma unroll
-    for (int it = 0; it < kScanItems; ++it) {
-        const int64_t idx = base + (int64_t)it * kThreads;
-        if (idx < n) s += scan_input(in, gather, idx, n);
-    }
-    block_exclusive_scan(s, wave_tot, &total);
-    if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
-}
-
-// exclusive scan of a tile with a per-block offset; blocked arrangement:
-// thread t owns items [t*kScanItems, (t+1)*kScanItems)
-__global__ __launch_bounds__(kThreads) void k_scan_tile(const uint32_t *in, const uint32_t *gather, uint32_t *out,
-                                                         int64_t n, const uint32_t *block_offsets,
-                                                         uint32_t *grand_total) {
+// Single-pass exclusive scan of kScanTile-element tiles: the workgroup at
+// ticket position b loads its tile (all loads issued before use), publishes
+// the tile sum, and its first wave takes the sum of all earlier tiles by
+// decoupled lookback over 64 earlier status words per round (the nearest
+// inclusive word ends it); the tile is then scanned with that offset.
+// status: one 64-bit word per tile, zero until published, then value + 1
+// with the top bit set when the value is inclusive.
+constexpr uint64_t kInc64 = 1ull << 63;
+__global__ __launch_bounds__(kThreads) void k_scan_lookback(const uint32_t *in, const uint32_t *gather, uint32_t *out,
+                                                             int64_t n, uint64_t *status, uint32_t *ticket,
+                                                             uint32_t *grand_total) {
     __shared__ uint32_t wave_tot[kWaves];
     __shared__ uint32_t total;
     __shared__ uint32_t s_data[kScanTile];
-    const int64_t block0 = (int64_t)blockIdx.x * kScanTile;
-    for (int k = threadIdx.x; k < kScanTile; k += kThreads) {
-        const int64_t idx = block0 + k;
-        s_data[k] = idx < n ? scan_input(in, gather, idx, n) : 0u;
-    }
+    __shared__ uint32_t s_pos;
+    __shared__ uint64_t s_before;
+    if (threadIdx.x == 0) s_pos = atomicAdd(ticket, 1u);
     __syncthreads();
-    uint32_t v[kScanItems], s = 0;
+    const uint32_t b = s_pos;
+    const int64_t block0 = (int64_t)b * kScanTile;
+    uint32_t v[kScanItems];
+#pragma unroll
+    for (int it = 0; it < kScanItems; ++it) {
+        const int64_t idx = block0 + it * kThreads + threadIdx.x;
+        v[it] = idx < n ? scan_input(in, gather, idx, n) : 0u;
+    }
+#pragma unroll
+    for (int it = 0; it < kScanItems; ++it) s_data[it * kThreads + threadIdx.x] = v[it];
+    __syncthreads();
+    // blocked arrangement: thread t owns items [t*kScanItems, (t+1)*kScanItems)
+    uint32_t s = 0;
 #pragma unroll
     for (int it = 0; it < kScanItems; ++it) {
         v[it] = s_data[threadIdx.x * kScanItems + it];
         s += v[it];
     }
     uint32_t run = block_exclusive_scan(s, wave_tot, &total);
-    if (block_offsets) run += block_offsets[blockIdx.x];
+    if (threadIdx.x < kWave) {
+        const int lane = __lane_id();
+        const uint64_t agg = total;
+        if (lane == 0)
+            __hip_atomic_store(status + b, (b == 0 ? kInc64 : 0ull) | (agg + 1ull), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        uint64_t before = 0;
+        int64_t p = (int64_t)b - 1;  // nearest earlier tile not yet summed
+        uint32_t polls = 0;
+        while (p >= 0) {
+            const int64_t q = p - lane;
+            const uint64_t w = q >= 0 ? __hip_atomic_load(status + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                      : kInc64 | 1ull;  // before tile 0: nothing
+            const uint64_t incs = __ballot((w & kInc64) != 0ull);
+            const int first_inc = incs ? __builtin_ctzll(incs) : kWave;
+            const uint64_t need = first_inc < kWave ? (2ull << first_inc) - 1ull : ~0ull;  // lanes 0..first_inc
+            const uint64_t zeros = __ballot(w == 0ull) & need;
+            const int upto = zeros ? __builtin_ctzll(zeros) : (first_inc < kWave ? first_inc + 1 : kWave);
+            uint64_t c = lane < upto ? (w & ~kInc64) - 1ull : 0ull;
+#pragma unroll
+            for (int off = 1; off < kWave; off <<= 1) c += __shfl_xor(c, off, kWave);
+            before += c;
+            if (!zeros && first_inc < kWave) break;
+            p -= upto;
+            if (zeros) {
+                if (++polls >= kMaxPolls) break;
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        if (lane == 0) {
+            if (b > 0)
+                __hip_atomic_store(status + b, kInc64 | (before + agg + 1ull), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            s_before = before;
+        }
+    }
+    __syncthreads();
+    run += (uint32_t)s_before;
 #pragma unroll
     for (int it = 0; it < kScanItems; ++it) {
         s_data[threadIdx.x * kScanItems + it] = run;
         run += v[it];
     }
-    if (grand_total && blockIdx.x == gridDim.x - 1 && threadIdx.x == kThreads - 1) *grand_total = run;
+    if (grand_total && block0 + kScanTile >= n && threadIdx.x == kThreads - 1) *grand_total = run;
     __syncthreads();
-    for (int k = threadIdx.x; k < kScanTile; k += kThreads) {
-        const int64_t idx = block0 + k;
-        if (idx < n) out[idx] = s_data[k];
+#pragma unroll
+    for (int it = 0; it < kScanItems; ++it) {
+        const int64_t idx = block0 + it * kThreads + threadIdx.x;
+        if (idx < n) out[idx] = s_data[it * kThreads + threadIdx.x];
+    }
+}
+
+// Exclusive scan of at most kScanTile elements in one workgroup (blocked
+// arrangement: thread t owns items [t*kScanItems, (t+1)*kScanItems)).
+__global__ __launch_bounds__(kThreads) void k_scan_tile(const uint32_t *in, const uint32_t *gather, uint32_t *out,
+                                                         int64_t n, uint32_t *grand_total) {
+    __shared__ uint32_t wave_tot[kWaves];
+    __shared__ uint32_t total;
+    __shared__ uint32_t s_data[kScanTile];
+    uint32_t v[kScanItems];
+#pragma unroll
+    for (int it = 0; it < kScanItems; ++it) {
+        const int64_t idx = it * kThreads + threadIdx.x;
+        v[it] = idx < n ? scan_input(in, gather, idx, n) : 0u;
+    }
+#pragma unroll
+    for (int it = 0; it < kScanItems; ++it) s_data[it * kThreads + threadIdx.x] = v[it];
+    __syncthreads();
+    uint32_t s = 0;
+#pragma unroll
+    for (int it = 0; it < kScanItems; ++it) {
+        v[it] = s_data[threadIdx.x * kScanItems + it];
+        s += v[it];
+    }
+    uint32_t run = block_exclusive_scan(s, wave_tot, &total);
+#pragma unroll
+    for (int it = 0; it < kScanItems; ++it) {
+        s_data[threadIdx.x * kScanItems + it] = run;
+        run += v[it];
+    }
+    if (grand_total && threadIdx.x == kThreads - 1) *grand_total = run;
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kScanItems; ++it) {
+        const int64_t idx = it * kThreads + threadIdx.x;
+        if (idx < n) out[idx] = s_data[it * kThreads + threadIdx.x];
     }
 }
 
@@ -450,14 +526,8 @@ int64_t blocks_for(int64_t n, int64_t per) { return (n + per - 1) / per; }
 }  // namespace
 
 size_t scan_scratch_bytes(int64_t n) {
-    // block sums of every level, 256-byte aligned
-    size_t bytes = 0;
-    int64_t m = n;
-    while (m > kScanTile) {
-        m = blocks_for(m, kScanTile);
-        bytes += ((size_t)m * 4 + 255) & ~(size_t)255;
-    }
-    return bytes + 256;
+    // one status word per tile, then the ticket
+    return ((size_t)blocks_for(n > 0 ? n : 1, kScanTile) * 8 + 64 + 255) / 256 * 256 + 256;
 }
 
 hipError_t scan_exclusive(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *total, void *scratch,
@@ -468,16 +538,16 @@ hipError_t scan_exclusive(const uint32_t *in, uint32_t *out, int64_t n, uint32_t
     }
     const int64_t nb = blocks_for(n, kScanTile);
     if (nb == 1) {
-        hipLaunchKernelGGL(k_scan_tile, dim3(1), dim3(kThreads), 0, st, in, gather, out, n,
-                           (const uint32_t *)nullptr, total);
+        hipLaunchKernelGGL(k_scan_tile, dim3(1), dim3(kThreads), 0, st, in, gather, out, n, total);
         return hipGetLastError();
     }
-    uint32_t *sums = static_cast<uint32_t *>(scratch);
-    void *next = static_cast<char *>(scratch) + (((size_t)nb * 4 + 255) & ~(size_t)255);
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kThreads), 0, st, in, gather, n, sums);
-    hipError_t e = scan_exclusive(sums, sums, nb, nullptr, next, st, nullptr);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_scan_tile, dim3((unsigned)nb), dim3(kThreads), 0, st, in, gather, out, n, sums, total);
+    uint64_t *status = static_cast<uint64_t *>(scratch);
+    uint32_t *ticket = reinterpret_cast<uint32_t *>(status + nb);
+    const int64_t words = nb * 2 + 1;  // the status words and the ticket, as u32
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks_for(words, 256)), dim3(256), 0, st,
+                       reinterpret_cast<uint32_t *>(status), 0u, words);
+    hipLaunchKernelGGL(k_scan_lookback, dim3((unsigned)nb), dim3(kThreads), 0, st, in, gather, out, n, status, ticket,
+                       total);
     return hipGetLastError();
 }
 
