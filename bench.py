@@ -5,7 +5,8 @@ Workload: 1M Gaussians in the indoor room layout (70% on the faces of an
 axis-aligned box, 30% in a shell, 20% moved across the +-pi seam), SH degree
 3, 2048x1024 ERP images, 200 seeded poses (centre in the unit ball, random
 yaw).  One step = one pose: omnigs_forward (project, depth sort, emit, tile
-sort, ranges, blend), omnigs_l1_loss against a per-pose target image (the
+sort, ranges, blend; with instance and block-entry capacities sized from the
+poses' counts, so no step reads anything back), omnigs_l1_loss against a per-pose target image (the
 render of a perturbed copy of the scene, prepared before timing), and
 omnigs_backward (reverse blend, projection chain).  Inputs are resident in
 HBM when timing starts.
@@ -423,9 +424,21 @@ def main():
     torch.cuda.synchronize()
     log("targets rendered")
 
+    # instance and block-entry capacities from one counted forward of every
+    # pose (5% headroom): the timed forwards then read nothing back, and every
+    # step's overflow flag is checked after the timed region
+    m_max = s_max = 0
+    for p in poses:
+        f = B.omnigs_forward(gd, p)
+        m_max, s_max = max(m_max, f.n_instances), max(s_max, f.n_entries)
+    del f
+    cap = (int(1.05 * m_max) + 1, int(1.05 * s_max) + 1)
+    overflow = []
+
     def step(k):
         p = poses[k % len(poses)]
-        fwd = B.omnigs_forward(gd, p)
+        fwd = B.omnigs_forward(gd, p, capacity=cap)
+        overflow.append(fwd.overflow)
         loss, dl = B.omnigs_l1_loss(fwd.image, targets[k % len(poses)])
         B.omnigs_backward(gd, p, None, fwd, dl)
         return fwd
@@ -438,7 +451,10 @@ def main():
     dt, prof_bwd = timed(step, ks, ("blend_bwd",))
     # stage breakdown: the same steps again, every stage bracketed
     dt_prof, prof = timed(step, ks, None)
-    log(f"{args.steps / dt:.1f} iters/s ({args.steps / dt_prof:.1f} with every stage timed)")
+    n_over = int(torch.cat(overflow).sum())
+    if n_over:
+        raise SystemExit(f"bench.py: {n_over} steps overflowed the capacities {cap}")
+    log(f"{args.steps / dt:.1f} iters/s ({args.steps / dt_prof:.1f} with every stage timed), capacities {cap}")
     log("stages (ms per step): " + ", ".join(f"{k} {v[0] / args.steps:.3f}" for k, v in prof.items() if v[1]))
 
     # pairs walked / blended by the timed steps (deterministic re-render)
@@ -461,7 +477,9 @@ def main():
                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
                config=dict(workload="1M Gaussians, room layout with 20% across the seam, SH degree 3, "
                                     "2048x1024 ERP, 200 poses, forward + L1 + backward per pose",
-                           gaussians=int(g["means"].shape[0]), width=2048, height=1024, poses=len(poses)),
+                           gaussians=int(g["means"].shape[0]), width=2048, height=1024, poses=len(poses),
+                           forward="caller capacities, no host read-back (overflow checked: none)",
+                           instance_capacity=cap[0], entry_capacity=cap[1]),
                stage_ms={k: v[0] / args.steps for k, v in prof.items() if v[1]},
                ms_per_step_all_stages_timed=dt_prof * 1e3 / args.steps,
                roofline=roofline)

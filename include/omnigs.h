@@ -147,7 +147,25 @@ typedef struct {
                                     extent of the alpha = alpha_min box), 0 when
                                     culled                                          */
     const float *depth;          /* [n] sort depth d (t_r or t_z) of each Gaussian */
+    const uint32_t *counts;      /* [2] S and M as counted on the device (device
+                                    words; n_entries and n_instances are -1 when
+                                    the call read nothing back)                     */
 } omnigs_state;
+
+/* Capacities of a forward call that reads nothing back (host struct).  With
+ * instances > 0 the instance buffers hold that many (Gaussian, tile)
+ * instances and the block-entry buffers `entries` (Gaussian, 8x8-tile
+ * block) entries (entries == 0: as many as instances; S <= M always), the
+ * counts stay on the device and the call only enqueues work.  If M or S
+ * exceeds its capacity the call still stays within its buffers, but its
+ * outputs (and a backward from its state) are invalid and *overflow is 1.
+ * overflow (device int32, may be NULL) is set to 0 or 1 on the call's stream.
+ * Both capacities must stay below 2^31 - 1. */
+typedef struct {
+    int64_t instances;
+    int64_t entries;
+    int32_t *overflow;
+} omnigs_capacity;
 
 /* Parameter gradients (device, caller-allocated, overwritten). */
 typedef struct {
@@ -176,8 +194,10 @@ omnigs_settings omnigs_default_settings(void);
  *      is in (t_r, id) order; per-tile [start, end) ranges;
  *   3. front-to-back alpha blending of Eq. 6-8, one 16x16 tile per
  *      workgroup, stopping per pixel before T would drop below T_min.
- * The instance counts are read back to size the instance buffers: this is
- * the only host synchronisation of the call.
+ * cap == NULL or cap->instances == 0: the instance counts are read back to
+ * size the instance buffers, the only host synchronisation of the call;
+ * otherwise the buffers take the capacities of *cap and nothing is read
+ * back (see omnigs_capacity).
  * Inputs: g (device arrays), cam and s (host).  Outputs: out (device,
  * caller-allocated) and *state (host struct; device buffers from `alloc`).
  * Returns OMNIGS_ERR_INVALID for null pointers, n < 0, sh_degree outside
@@ -185,7 +205,8 @@ omnigs_settings omnigs_default_settings(void);
  * camera; OMNIGS_ERR_ALLOC if `alloc` fails; OMNIGS_ERR_HIP on a runtime
  * failure. */
 omnigs_status omnigs_forward(const omnigs_gaussians *g, const omnigs_camera *cam, const omnigs_settings *s,
-                             omnigs_allocator alloc, omnigs_image_out *out, omnigs_state *state, void *stream);
+                             omnigs_allocator alloc, omnigs_image_out *out, omnigs_state *state,
+                             const omnigs_capacity *cap, void *stream);
 
 /* Backward pass of the render (Sec. 3.4, Eq. 18-20) for an image-space
  * cotangent dL_dimage [3][H][W] (device) and, each optional (NULL), the

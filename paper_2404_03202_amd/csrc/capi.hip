@@ -238,6 +238,7 @@ struct GeomState {
     uint32_t *n_tiles, *order;
     uint2 *rect;
     float *radii, *depth;
+    uint32_t *totals;  // [0] super entries S, [1] tile instances M (adjacent: one readback)
     void carve(Arena &a, int64_t n) {
         const size_t m = (size_t)(n > 0 ? n : 1);
         rec = a.take<BlendRecord>(m);
@@ -246,11 +247,11 @@ struct GeomState {
         rect = a.take<uint2>(m);
         radii = a.take<float>(m);
         depth = a.take<float>(m);
+        totals = a.take<uint32_t>(2);
     }
 };
 struct GeomScratch {
     uint32_t *depth_key, *keys_tmp, *vals_tmp, *keys_sorted, *offs, *n_super;
-    uint32_t *totals;  // [0] super entries S, [1] tile instances M (adjacent: one readback)
     void *sort_tmp, *scan_tmp;
     void carve(Arena &a, int64_t n) {
         const size_t m = (size_t)(n > 0 ? n : 1);
@@ -260,15 +261,14 @@ struct GeomScratch {
         keys_sorted = a.take<uint32_t>(m);
         offs = a.take<uint32_t>(m + 1);
         n_super = a.take<uint32_t>(m);
-        totals = a.take<uint32_t>(2);
         sort_tmp = a.take_bytes(sort_scratch_bytes((int64_t)m));
         scan_tmp = a.take_bytes(scan_scratch_bytes((int64_t)m));
     }
 };
 
 // Depth sort and per-rank super-entry offsets of n records (projected
-// already, which left M = total tile instances at gs.totals[1]): gs.offs
-// and S at gs.totals[0].
+// already, which left M = total tile instances at gst.totals[1]): gs.offs
+// and S at gst.totals[0].
 omnigs_status sort_and_count(int64_t n, GeomState &gst, GeomScratch &gs, hipStream_t st) {
     {
         StageTimer t(st, kStDepthSort);
@@ -277,7 +277,7 @@ omnigs_status sort_and_count(int64_t n, GeomState &gst, GeomScratch &gs, hipStre
     }
     {
         StageTimer t(st, kStEmitCount);
-        HIP_TRY(scan_exclusive(gs.n_super, gs.offs, n, gs.totals, gs.scan_tmp, st, gst.order));
+        HIP_TRY(scan_exclusive(gs.n_super, gs.offs, n, gst.totals, gs.scan_tmp, st, gst.order));
     }
     return OMNIGS_OK;
 }
@@ -330,15 +330,15 @@ omnigs_status run_binning(int64_t nrec, const GeomState &gst, const GeomScratch 
         StageTimer t(st, kStSuperEmit);
         // emit where the sort's ping-pong starts, so that the last pass lands
         // in stile / sgauss
-        HIP_TRY(launch_emit(gst.order, gs.n_super, gst.rect, gs.offs, nrec, bs.part, gs.totals, G.ef, super_cap, et,
+        HIP_TRY(launch_emit(gst.order, gs.n_super, gst.rect, gs.offs, nrec, bs.part, gst.totals, G.ef, super_cap, et,
                             eg, overflow, st));
     }
     {
         StageTimer t(st, kStSuperSort);
         HIP_TRY(radix_sort_pairs(et, eg, bs.stile_tmp, bs.sgauss_tmp, bs.stile, bs.sgauss, (int64_t)super_cap, bits,
-                                 bs.sort_tmp, st, counted ? gs.totals : nullptr));
+                                 bs.sort_tmp, st, counted ? gst.totals : nullptr));
         HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(bs.sranges), 0u, 2 * (int64_t)G.n_super, st));
-        HIP_TRY(launch_tile_ranges(bs.stile, gs.totals, super_cap, bs.sranges, G.n_super, st));
+        HIP_TRY(launch_tile_ranges(bs.stile, gst.totals, super_cap, bs.sranges, G.n_super, st));
     }
     {
         StageTimer t(st, kStTileBin);
@@ -367,7 +367,8 @@ omnigs_settings omnigs_default_settings(void) {
 const char *omnigs_last_error(void) { return g_error.c_str(); }
 
 omnigs_status omnigs_forward(const omnigs_gaussians *g, const omnigs_camera *cam, const omnigs_settings *s,
-                             omnigs_allocator alloc, omnigs_image_out *out, omnigs_state *state, void *stream) {
+                             omnigs_allocator alloc, omnigs_image_out *out, omnigs_state *state,
+                             const omnigs_capacity *cap, void *stream) {
     omnigs_status rc;
     if ((rc = check_gaussians(g)) != OMNIGS_OK) return rc;
     if ((rc = check_camera(cam)) != OMNIGS_OK) return rc;
@@ -375,37 +376,17 @@ omnigs_status omnigs_forward(const omnigs_gaussians *g, const omnigs_camera *cam
     if (!alloc.alloc) return fail(OMNIGS_ERR_INVALID, "allocator callback is NULL");
     if (!out || !out->image || !out->final_T || !out->n_contrib) return fail(OMNIGS_ERR_INVALID, "output pointer is NULL");
     if (!state) return fail(OMNIGS_ERR_INVALID, "state is NULL");
+    const bool counted = cap && cap->instances > 0;
+    if (cap) {
+        const int64_t lim = (int64_t(1) << 31) - 1;
+        if (cap->instances < 0 || cap->instances >= lim || cap->entries < 0 || cap->entries >= lim)
+            return fail(OMNIGS_ERR_INVALID, "capacities (%lld instances, %lld entries) out of range",
+                        (long long)cap->instances, (long long)cap->entries);
+    }
     hipStream_t st = static_cast<hipStream_t>(stream);
     const ProjectArgs pa = make_project_args(g, cam, s);
     const int64_t n = g->n;
     const uint32_t ntiles = (uint32_t)(pa.tiles_x * pa.tiles_y);
-
-    // N-sized buffers
-    Arena sa, ta;
-    GeomState gst;
-    GeomScratch gs;
-    gst.carve(sa, n);
-    const size_t geom_state_bytes = sa.off;
-    gs.carve(ta, n);
-    const size_t geom_scratch_bytes = ta.off;
-    if ((rc = alloc_arena(alloc, geom_state_bytes, OMNIGS_MEM_STATE, sa, "per-Gaussian state")) != OMNIGS_OK) return rc;
-    gst.carve(sa, n);
-    if ((rc = alloc_arena(alloc, geom_scratch_bytes, OMNIGS_MEM_SCRATCH, ta, "per-Gaussian scratch")) != OMNIGS_OK)
-        return rc;
-    gs.carve(ta, n);
-
-    {
-        StageTimer t(st, kStProject);
-        HIP_TRY(launch_project(pa, gst.rec, gs.depth_key, gst.depth, gst.n_tiles, gst.rect, gs.n_super, gst.radii,
-                               gs.totals + 1, st));
-    }
-    if ((rc = sort_and_count(n, gst, gs, st)) != OMNIGS_OK) return rc;
-
-    // super entries S and tile instances M: the one host synchronisation
-    uint32_t tot[2] = {0, 0};
-    HIP_TRY(hipMemcpyAsync(tot, gs.totals, sizeof(tot), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    const int64_t S = tot[0], M = tot[1];
 
     Grids G;
     G.ef.n_per = n > 0 ? n : 1;
@@ -413,29 +394,75 @@ omnigs_status omnigs_forward(const omnigs_gaussians *g, const omnigs_camera *cam
     G.ef.super = 1;
     G.sup.count = 1;
     G.add(0, pa.tiles_x, pa.tiles_y);
-    // M-sized state and S-sized scratch
-    Arena ia, ja;
-    uint32_t *inst_gauss, *tile_work, *order;
-    uint2 *ranges;
+    // N-sized state and scratch; M-sized state and S-sized scratch, with the
+    // caller's capacities (allocated with the N-sized buffers) or the counts
+    // read back after the depth sort
+    GeomState gst;
+    GeomScratch gs;
+    uint64_t super_cap = 0, inst_cap = 0;
+    uint32_t *inst_gauss = nullptr, *tile_work = nullptr, *order = nullptr;
+    uint2 *ranges = nullptr;
     BinScratch bs;
-    auto carve_state = [&](Arena &a) {
-        inst_gauss = a.take<uint32_t>((size_t)(M > 0 ? M : 1));
+    auto carve_inst_state = [&](Arena &a) {
+        inst_gauss = a.take<uint32_t>((size_t)(inst_cap > 0 ? inst_cap : 1));
         ranges = a.take<uint2>(ntiles);
         tile_work = a.take<uint32_t>(ntiles);
     };
-    auto carve_scratch = [&](Arena &a) {
-        bs.carve(a, (uint64_t)S, G.n_super);
+    auto carve_inst_scratch = [&](Arena &a) {
+        bs.carve(a, super_cap, G.n_super);
         order = a.take<uint32_t>(ntiles);
     };
-    carve_state(ia);
-    carve_scratch(ja);
-    if ((rc = alloc_arena(alloc, ia.off, OMNIGS_MEM_STATE, ia, "instance lists")) != OMNIGS_OK) return rc;
-    carve_state(ia);
-    if ((rc = alloc_arena(alloc, ja.off, OMNIGS_MEM_SCRATCH, ja, "binning scratch")) != OMNIGS_OK) return rc;
-    carve_scratch(ja);
+    if (counted) {
+        inst_cap = (uint64_t)cap->instances;
+        super_cap = cap->entries > 0 ? (uint64_t)cap->entries : inst_cap;
+    }
+    {
+        Arena sa, ta;
+        auto carve_state = [&](Arena &a) {
+            gst.carve(a, n);
+            if (counted) carve_inst_state(a);
+        };
+        auto carve_scratch = [&](Arena &a) {
+            gs.carve(a, n);
+            if (counted) carve_inst_scratch(a);
+        };
+        carve_state(sa);
+        carve_scratch(ta);
+        if ((rc = alloc_arena(alloc, sa.off, OMNIGS_MEM_STATE, sa, "forward state")) != OMNIGS_OK) return rc;
+        carve_state(sa);
+        if ((rc = alloc_arena(alloc, ta.off, OMNIGS_MEM_SCRATCH, ta, "forward scratch")) != OMNIGS_OK) return rc;
+        carve_scratch(ta);
+    }
+    if (counted && cap->overflow) HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(cap->overflow), 0u, 1, st));
 
-    if ((rc = run_binning(n, gst, gs, G, (uint64_t)S, (uint64_t)M, false, bs, ranges, inst_gauss, nullptr, st)) !=
-        OMNIGS_OK)
+    {
+        StageTimer t(st, kStProject);
+        HIP_TRY(launch_project(pa, gst.rec, gs.depth_key, gst.depth, gst.n_tiles, gst.rect, gs.n_super, gst.radii,
+                               gst.totals + 1, st));
+    }
+    if ((rc = sort_and_count(n, gst, gs, st)) != OMNIGS_OK) return rc;
+
+    int64_t S = -1, M = -1;
+    if (!counted) {
+        // super entries S and tile instances M: the one host synchronisation
+        uint32_t tot[2] = {0, 0};
+        HIP_TRY(hipMemcpyAsync(tot, gst.totals, sizeof(tot), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        S = tot[0];
+        M = tot[1];
+        super_cap = (uint64_t)S;
+        inst_cap = (uint64_t)M;
+        Arena ia, ja;
+        carve_inst_state(ia);
+        carve_inst_scratch(ja);
+        if ((rc = alloc_arena(alloc, ia.off, OMNIGS_MEM_STATE, ia, "instance lists")) != OMNIGS_OK) return rc;
+        carve_inst_state(ia);
+        if ((rc = alloc_arena(alloc, ja.off, OMNIGS_MEM_SCRATCH, ja, "binning scratch")) != OMNIGS_OK) return rc;
+        carve_inst_scratch(ja);
+    }
+
+    if ((rc = run_binning(n, gst, gs, G, super_cap, inst_cap, counted, bs, ranges, inst_gauss,
+                          counted ? cap->overflow : nullptr, st)) != OMNIGS_OK)
         return rc;
     {
         StageTimer t(st, kStTileOrder);
@@ -462,6 +489,7 @@ omnigs_status omnigs_forward(const omnigs_gaussians *g, const omnigs_camera *cam
     state->tile_work = tile_work;
     state->radii = gst.radii;
     state->depth = gst.depth;
+    state->counts = gst.totals;
     return OMNIGS_OK;
 }
 
@@ -632,7 +660,7 @@ omnigs_status omnigs_forward_batch(const omnigs_gaussians *g, const omnigs_camer
     {
         StageTimer t(st, kStProject);
         HIP_TRY(launch_project_batch(pa, ct, gst.rec, gs.depth_key, gst.depth, gst.n_tiles, gst.rect, gs.n_super,
-                                     gs.totals + 1,
+                                     gst.totals + 1,
                                      st));
     }
     if ((rc = sort_and_count(nrec, gst, gs, st)) != OMNIGS_OK) return rc;
@@ -644,7 +672,7 @@ omnigs_status omnigs_forward_batch(const omnigs_gaussians *g, const omnigs_camer
     const bool counted = instance_capacity > 0;
     if (!counted) {
         uint32_t tot[2] = {0, 0};
-        HIP_TRY(hipMemcpyAsync(tot, gs.totals, sizeof(tot), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(tot, gst.totals, sizeof(tot), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         super_cap = tot[0];
         inst_cap = tot[1];

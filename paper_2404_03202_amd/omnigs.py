@@ -72,7 +72,11 @@ class c_state(ctypes.Structure):
                 ("height", ctypes.c_int32), ("tiles_x", ctypes.c_int32), ("tiles_y", ctypes.c_int32),
                 ("records", ctypes.c_void_p), ("n_tiles", ctypes.c_void_p), ("depth_order", ctypes.c_void_p),
                 ("inst_gauss", ctypes.c_void_p), ("tile_range", ctypes.c_void_p), ("tile_work", ctypes.c_void_p),
-                ("radii", ctypes.c_void_p), ("depth", ctypes.c_void_p)]
+                ("radii", ctypes.c_void_p), ("depth", ctypes.c_void_p), ("counts", ctypes.c_void_p)]
+
+
+class c_capacity(ctypes.Structure):
+    _fields_ = [("instances", ctypes.c_int64), ("entries", ctypes.c_int64), ("overflow", ctypes.c_void_p)]
 
 
 class c_grads(ctypes.Structure):
@@ -125,7 +129,7 @@ def load_library(path: str = LIB_PATH):
         lib.omnigs_default_settings.argtypes = []
         lib.omnigs_default_settings.restype = c_settings
         lib.omnigs_forward.argtypes = [P(c_gaussians), P(c_camera), P(c_settings), c_allocator, P(c_image_out),
-                                       P(c_state), vp]
+                                       P(c_state), P(c_capacity), vp]
         lib.omnigs_forward.restype = ctypes.c_int
         lib.omnigs_backward.argtypes = [P(c_gaussians), P(c_camera), P(c_settings), P(c_state), P(c_image_out), vp,
                                         vp, vp, P(c_grads), c_allocator, vp]
@@ -278,22 +282,30 @@ def _stream_ptr(device):
 class ForwardResult:
     """Outputs of omnigs_forward plus the saved state for omnigs_backward."""
 
-    def __init__(self, image, final_T, n_contrib, state: c_state, keepalive, n_blended=None, depth=None):
+    def __init__(self, image, final_T, n_contrib, state: c_state, keepalive, n_blended=None, depth=None,
+                 overflow=None):
         self.image = image
         self.final_T = final_T
         self.n_contrib = n_contrib
         self.n_blended = n_blended
         self.depth = depth
         self.state = state
+        self.overflow = overflow  # device int32 [1] with capacities, else None
         self._keep = keepalive
 
     @property
     def n_instances(self):
+        """M, or -1 when the call read nothing back (see counts())."""
         return int(self.state.n_instances)
 
     @property
     def n_entries(self):
         return int(self.state.n_entries)
+
+    def counts(self):
+        """(S, M) as counted on the device (synchronises)."""
+        c = self._view(self.state.counts, 2, torch.int32)
+        return int(c[0]), int(c[1])
 
     def _view(self, ptr, count, dtype):
         """View a state buffer as a tensor (for tests / debugging)."""
@@ -309,10 +321,10 @@ class ForwardResult:
         """Per-tile lists concatenated in tile-id order: (tile id [M] int32,
         Gaussian id [M] int32, ranges [tiles, 2] int32 of the library's own
         layout), device tensors (the tile ids are re-derived from the ranges)."""
-        M = self.n_instances
         tiles = self.state.tiles_x * self.state.tiles_y
-        gauss = self._view(self.state.inst_gauss, M, torch.int32)
         rng = self._view(self.state.tile_range, 2 * tiles, torch.int32).view(tiles, 2)
+        M = self.n_instances if self.n_instances >= 0 else int(rng[:, 1].max()) if tiles else 0
+        gauss = self._view(self.state.inst_gauss, M, torch.int32)
         lens = (rng[:, 1] - rng[:, 0]).long()
         tile = torch.repeat_interleave(torch.arange(tiles, device=gauss.device, dtype=torch.int32), lens)
         starts = torch.repeat_interleave(rng[:, 0].long(), lens)
@@ -328,10 +340,13 @@ class ForwardResult:
 
 
 def omnigs_forward(g: dict, camera: dict, settings: dict | None = None, allocator: Allocator | None = None,
-                   out: dict | None = None, with_blended: bool = False, with_depth: bool = False) -> ForwardResult:
+                   out: dict | None = None, with_blended: bool = False, with_depth: bool = False,
+                   capacity=None) -> ForwardResult:
     """Render one camera: image [3,H,W], final_T, n_contrib (and n_blended,
     depth [H,W] on request), H the rendered rows; the alpha image is
-    1 - final_T."""
+    1 - final_T.  capacity None reads the instance counts back (one host
+    sync); (instances, entries) sizes the instance and block-entry buffers
+    instead, reads nothing back and flags overflow in result.overflow."""
     lib = load_library()
     dev = g["means"].device
     cg, cc, cs = make_gaussians(g), make_camera(camera), make_settings(settings)
@@ -348,13 +363,19 @@ def omnigs_forward(g: dict, camera: dict, settings: dict | None = None, allocato
                      _ptr(out.get("depth")))
     st = c_state()
     al = allocator or Allocator(dev)
+    cap, overflow = None, None
+    if capacity is not None:
+        instances, entries = capacity
+        overflow = torch.empty(1, dtype=torch.int32, device=dev)
+        cap = c_capacity(int(instances), int(entries), _ptr(overflow))
     _check(lib.omnigs_forward(ctypes.byref(cg), ctypes.byref(cc), ctypes.byref(cs), al.c, ctypes.byref(co),
-                              ctypes.byref(st), ctypes.c_void_p(_stream_ptr(dev))))
+                              ctypes.byref(st), ctypes.byref(cap) if cap is not None else None,
+                              ctypes.c_void_p(_stream_ptr(dev))))
     keep = list(al.state)
     al.scratch.clear()
     al.state.clear()
     return ForwardResult(out["image"], out["final_T"], out["n_contrib"], st, keep, out.get("n_blended"),
-                         out.get("depth"))
+                         out.get("depth"), overflow)
 
 
 def omnigs_backward(g: dict, camera: dict, settings: dict | None, fwd: ForwardResult, dL_dimage: torch.Tensor,

@@ -69,10 +69,10 @@ def _alloc(fail):
     return B.c_allocator(f, None), calls, f
 
 
-def _forward(lib, g, c, s, out, alloc):
+def _forward(lib, g, c, s, out, alloc, cap=None):
     st = B.c_state()
     return lib.omnigs_forward(ctypes.byref(g), ctypes.byref(c), ctypes.byref(s), alloc, ctypes.byref(out),
-                              ctypes.byref(st), None)
+                              ctypes.byref(st), ctypes.byref(cap) if cap is not None else None, None)
 
 
 @pytest.mark.parametrize("mutate,needle", [
@@ -103,6 +103,27 @@ def test_invalid_arguments(lib, mutate, needle):
     assert rc == B.OMNIGS_ERR_INVALID
     assert needle in B.omnigs_last_error()
     assert calls == []  # rejected before allocating
+
+
+@pytest.mark.parametrize("instances,entries", [(-1, 0), (0, -5), (1 << 31, 0), (100, (1 << 31) - 1)])
+def test_invalid_capacities(lib, instances, entries):
+    g, c, s, out = _fake_args()
+    alloc, calls, keep = _alloc(fail=True)
+    rc = _forward(lib, g, c, s, out, alloc, B.c_capacity(instances, entries, None))
+    assert rc == B.OMNIGS_ERR_INVALID
+    assert "capacities" in B.omnigs_last_error()
+    assert calls == []
+
+
+def test_capacity_mode_allocates_up_front(lib):
+    """With capacities the instance and block-entry buffers come with the
+    per-Gaussian ones: one state and one scratch request, before any work
+    (the failing allocator stops the call at the first)."""
+    g, c, s, out = _fake_args(n=1000)
+    alloc, calls, keep = _alloc(fail=True)
+    rc = _forward(lib, g, c, s, out, alloc, B.c_capacity(5_000_000, 0, None))
+    assert rc == B.OMNIGS_ERR_ALLOC
+    assert len(calls) == 1 and calls[0][1] == B.OMNIGS_MEM_STATE and calls[0][0] >= 5_000_000 * 4
 
 
 def test_pinhole_accepts_any_width(lib):
