@@ -335,10 +335,16 @@ omnigs_status run_binning(int64_t nrec, const GeomState &gst, const GeomScratch 
     }
     {
         StageTimer t(st, kStSuperSort);
+        // one pass (up to 256 blocks): the sort writes each block's range
+        // from its digit totals; else the ranges from adjacent sorted keys
+        const bool one_pass = bits <= 8;
         HIP_TRY(radix_sort_pairs(et, eg, bs.stile_tmp, bs.sgauss_tmp, bs.stile, bs.sgauss, (int64_t)super_cap, bits,
-                                 bs.sort_tmp, st, counted ? gst.totals : nullptr));
-        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(bs.sranges), 0u, 2 * (int64_t)G.n_super, st));
-        HIP_TRY(launch_tile_ranges(bs.stile, gst.totals, super_cap, bs.sranges, G.n_super, st));
+                                 bs.sort_tmp, st, counted ? gst.totals : nullptr, one_pass ? bs.sranges : nullptr,
+                                 one_pass ? (int)G.n_super : 0));
+        if (!one_pass) {
+            HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(bs.sranges), 0u, 2 * (int64_t)G.n_super, st));
+            HIP_TRY(launch_tile_ranges(bs.stile, gst.totals, super_cap, bs.sranges, G.n_super, st));
+        }
     }
     {
         StageTimer t(st, kStTileBin);

@@ -149,11 +149,14 @@ hipError_t launch_project_backward(const ProjectArgs &a, const uint32_t *n_tiles
 // input positions 0..n-1 as values.  `scratch` from sort_scratch_bytes.
 // n_dev (device, may be null): the element count is min(n, *n_dev), read on
 // the device (n then only bounds the buffers and the grid).  n < 2^31 - 1,
-// else hipErrorInvalidValue.
+// else hipErrorInvalidValue.  key_ranges (device, may be null; only with
+// bits <= 8 and n_ranges <= 256): receives [start, end) of each key value
+// 0 .. n_ranges-1 in the sorted output.
 size_t sort_scratch_bytes(int64_t n);
 hipError_t radix_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_tmp,
                             uint32_t *vals_tmp, uint32_t *keys_out, uint32_t *vals_out, int64_t n, int bits,
-                            void *scratch, hipStream_t st, const uint32_t *n_dev = nullptr);
+                            void *scratch, hipStream_t st, const uint32_t *n_dev = nullptr,
+                            uint2 *key_ranges = nullptr, int n_ranges = 0);
 
 // Exclusive scan of u32 (optionally of in[gather[i]]); *total (device, may be
 // null) receives the sum.  `scratch` from scan_scratch_bytes.

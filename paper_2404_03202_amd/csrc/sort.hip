@@ -152,12 +152,13 @@ __global__ __launch_bounds__(kThreads) void k_sort_hist(const uint32_t *keys, in
 // lookback), and writes its keys as contiguous per-digit runs at
 // (keys of smaller digits) + (earlier blocks' keys of the same digit) +
 // (rank in the block).  vals_in == nullptr: the values are the input
-// positions.
+// positions.  key_ranges (one-pass sorts, may be null): workgroup 0 writes
+// [start, end) of every key value below n_ranges from the digit totals.
 __global__ __launch_bounds__(kThreads) void k_radix_pass(const uint32_t *keys_in, const uint32_t *vals_in,
                                                           uint32_t *keys_out, uint32_t *vals_out, int64_t n_max,
                                                           const uint32_t *n_dev, int shift, int bits,
                                                           const uint32_t *ghist, uint32_t *status,
-                                                          uint32_t *ticket) {
+                                                          uint32_t *ticket, uint2 *key_ranges, int n_ranges) {
     __shared__ uint32_t s_keys[kTileKeys];
     __shared__ uint32_t s_vals[kTileKeys];
     __shared__ uint32_t cnt[kWaves][kBins];
@@ -166,6 +167,11 @@ __global__ __launch_bounds__(kThreads) void k_radix_pass(const uint32_t *keys_in
     __shared__ uint32_t total;
     __shared__ uint32_t s_pos;
     const int64_t n = sort_count(n_max, n_dev);
+    if (key_ranges && blockIdx.x == 0) {
+        const uint32_t c = ghist[threadIdx.x];
+        const uint32_t start = block_exclusive_scan(c, wave_tot, &total);
+        if ((int)threadIdx.x < n_ranges) key_ranges[threadIdx.x] = make_uint2(start, start + c);
+    }
     // the first ceil(n / kTileKeys) workgroups take the tickets 0, 1, ... in
     // the order they start; the others (a grid sized for a capacity) have no
     // keys and leave at once
@@ -558,8 +564,15 @@ size_t sort_scratch_bytes(int64_t n) {
 
 hipError_t radix_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_tmp,
                             uint32_t *vals_tmp, uint32_t *keys_out, uint32_t *vals_out, int64_t n, int bits,
-                            void *scratch, hipStream_t st, const uint32_t *n_dev) {
-    if (n <= 0) return hipSuccess;
+                            void *scratch, hipStream_t st, const uint32_t *n_dev, uint2 *key_ranges,
+                            int n_ranges) {
+    if (key_ranges && (bits > kRadixBits || n_ranges > kBins)) return hipErrorInvalidValue;
+    if (n <= 0) {
+        if (key_ranges && n_ranges > 0)
+            hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks_for(2 * n_ranges, 256)), dim3(256), 0, st,
+                               reinterpret_cast<uint32_t *>(key_ranges), 0u, (int64_t)2 * n_ranges);
+        return hipGetLastError();
+    }
     if (n >= (int64_t)kCountMask) return hipErrorInvalidValue;  // lookback words hold count + 1 in 31 bits
     if (bits < 1) bits = 1;
     if (bits > 32) bits = 32;
@@ -584,7 +597,7 @@ hipError_t radix_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in, ui
         uint32_t *dv = to_out ? vals_out : vals_tmp;
         hipLaunchKernelGGL(k_radix_pass, dim3((unsigned)nb), dim3(kThreads), 0, st, src_k, src_v, dk, dv, n, n_dev,
                            shift, pbits, (const uint32_t *)(ghist + p * kBins), status + (int64_t)p * nb * kBins,
-                           tickets + p);
+                           tickets + p, key_ranges, n_ranges);
         src_k = dk;
         src_v = dv;
     }
