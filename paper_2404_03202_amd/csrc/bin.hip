@@ -217,47 +217,65 @@ uint64_t max_chunks(uint64_t super_cap, uint32_t n_super_total) {
 
 }  // namespace
 
+// Scratch layout: nch | choff | desc | counts | scanned | scan scratch of the
+// chunk offsets | scan scratch of the counts (each 256-byte aligned).
+struct BinLayout {
+    uint32_t *nch, *choff, *desc, *counts, *scanned;
+    void *scan_chunks, *scan_counts;
+    size_t bytes;
+    BinLayout(void *scratch, uint64_t super_cap, uint32_t n_super_total) {
+        const uint64_t K = max_chunks(super_cap, n_super_total);
+        const uint64_t cells = (uint64_t)kTilesPer * K;
+        auto al = [](uint64_t b) { return (size_t)((b + 255) & ~(uint64_t)255); };
+        char *base = static_cast<char *>(scratch), *p = base;
+        auto take = [&](size_t b) {
+            char *q = p;
+            p += al(b);
+            return q;
+        };
+        nch = reinterpret_cast<uint32_t *>(take(4ull * n_super_total));
+        choff = reinterpret_cast<uint32_t *>(take(4ull * (n_super_total + 1)));
+        desc = reinterpret_cast<uint32_t *>(take(4ull * K));
+        counts = reinterpret_cast<uint32_t *>(take(4ull * cells));
+        scanned = reinterpret_cast<uint32_t *>(take(4ull * (cells + 1)));
+        scan_chunks = take(scan_scratch_bytes((int64_t)n_super_total));
+        scan_counts = take(scan_scratch_bytes((int64_t)cells));
+        bytes = (size_t)(p - base) + 256;
+    }
+};
+
 size_t binning_scratch_bytes(uint64_t super_cap, uint32_t n_super_total) {
-    const uint64_t K = max_chunks(super_cap, n_super_total);
-    const uint64_t cells = (uint64_t)kTilesPer * K;
-    auto al = [](uint64_t b) { return (size_t)((b + 255) & ~(uint64_t)255); };
-    return al(4ull * n_super_total) + al(4ull * (n_super_total + 1)) + al(4ull * K) + al(4ull * cells) +
-           al(4ull * (cells + 1)) + scan_scratch_bytes((int64_t)std::max<uint64_t>(cells, n_super_total)) + 256;
+    return BinLayout(nullptr, super_cap, n_super_total).bytes;
+}
+
+void binning_clear(void *scratch, uint64_t super_cap, uint32_t n_super_total, ClearList &L) {
+    if (n_super_total == 0) return;
+    const BinLayout B(scratch, super_cap, n_super_total);
+    const uint64_t cells = (uint64_t)kTilesPer * max_chunks(super_cap, n_super_total);
+    L.add(B.scan_counts, scan_clear_words((int64_t)cells));
 }
 
 hipError_t launch_binning(const SuperTable &T, uint32_t n_super_total, const uint2 *rect, const uint32_t *sinst_gauss,
                           const uint2 *sranges, uint64_t super_cap, uint64_t inst_cap, void *scratch, uint2 *ranges,
-                          uint32_t *inst_gauss, int32_t *overflow, hipStream_t st) {
+                          uint32_t *inst_gauss, int32_t *overflow, hipStream_t st, bool cleared) {
     if (n_super_total == 0) return hipSuccess;
     const uint64_t K = max_chunks(super_cap, n_super_total);
     const uint64_t cells = (uint64_t)kTilesPer * K;
-    auto al = [](uint64_t b) { return (size_t)((b + 255) & ~(uint64_t)255); };
-    char *p = static_cast<char *>(scratch);
-    uint32_t *nch = reinterpret_cast<uint32_t *>(p);
-    p += al(4ull * n_super_total);
-    uint32_t *choff = reinterpret_cast<uint32_t *>(p);
-    p += al(4ull * (n_super_total + 1));
-    uint32_t *desc = reinterpret_cast<uint32_t *>(p);
-    p += al(4ull * K);
-    uint32_t *counts = reinterpret_cast<uint32_t *>(p);
-    p += al(4ull * cells);
-    uint32_t *scanned = reinterpret_cast<uint32_t *>(p);
-    p += al(4ull * (cells + 1));
-    void *scan_tmp = p;
+    const BinLayout B(scratch, super_cap, n_super_total);
     const unsigned sb = (unsigned)blocks_for(n_super_total, 256);
-    hipLaunchKernelGGL(k_bin_chunks, dim3(sb), dim3(256), 0, st, sranges, n_super_total, nch);
-    hipError_t e = scan_exclusive(nch, choff, n_super_total, choff + n_super_total, scan_tmp, st, nullptr);
+    hipLaunchKernelGGL(k_bin_chunks, dim3(sb), dim3(256), 0, st, sranges, n_super_total, B.nch);
+    hipError_t e = scan_exclusive(B.nch, B.choff, n_super_total, B.choff + n_super_total, B.scan_chunks, st, nullptr);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_bin_desc, dim3((unsigned)blocks_for((int64_t)K, 256)), dim3(256), 0, st, choff, n_super_total,
-                       K, desc);
-    hipLaunchKernelGGL(k_bin_count, dim3((unsigned)K), dim3(kThreads), 0, st, T, rect, sinst_gauss, sranges, choff, nch,
-                       desc, n_super_total, counts);
-    e = scan_exclusive(counts, scanned, (int64_t)cells, scanned + cells, scan_tmp, st, nullptr);
+    hipLaunchKernelGGL(k_bin_desc, dim3((unsigned)blocks_for((int64_t)K, 256)), dim3(256), 0, st, B.choff,
+                       n_super_total, K, B.desc);
+    hipLaunchKernelGGL(k_bin_count, dim3((unsigned)K), dim3(kThreads), 0, st, T, rect, sinst_gauss, sranges, B.choff,
+                       B.nch, B.desc, n_super_total, B.counts);
+    e = scan_exclusive(B.counts, B.scanned, (int64_t)cells, B.scanned + cells, B.scan_counts, st, nullptr, cleared);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_bin_ranges, dim3((unsigned)blocks_for((int64_t)n_super_total * kTilesPer, 256)), dim3(256), 0,
-                       st, T, n_super_total, choff, nch, scanned, inst_cap, ranges);
-    hipLaunchKernelGGL(k_bin_expand, dim3((unsigned)K), dim3(kThreads), 0, st, T, rect, sinst_gauss, sranges, choff,
-                       nch, desc, n_super_total, scanned, inst_cap, inst_gauss, overflow);
+                       st, T, n_super_total, B.choff, B.nch, B.scanned, inst_cap, ranges);
+    hipLaunchKernelGGL(k_bin_expand, dim3((unsigned)K), dim3(kThreads), 0, st, T, rect, sinst_gauss, sranges, B.choff,
+                       B.nch, B.desc, n_super_total, B.scanned, inst_cap, inst_gauss, overflow);
     return hipGetLastError();
 }
 

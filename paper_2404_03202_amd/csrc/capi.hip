@@ -269,17 +269,28 @@ struct GeomScratch {
 // Depth sort and per-rank super-entry offsets of n records (projected
 // already, which left M = total tile instances at gst.totals[1]): gs.offs
 // and S at gst.totals[0].
-omnigs_status sort_and_count(int64_t n, GeomState &gst, GeomScratch &gs, hipStream_t st) {
+// cleared: the sort's and the scan's lookback words are already zero
+// (geom_clear).
+omnigs_status sort_and_count(int64_t n, GeomState &gst, GeomScratch &gs, hipStream_t st, bool cleared = false) {
     {
         StageTimer t(st, kStDepthSort);
         HIP_TRY(radix_sort_pairs(gs.depth_key, nullptr, gs.keys_tmp, gs.vals_tmp, gs.keys_sorted, gst.order, n, 32,
-                                 gs.sort_tmp, st));
+                                 gs.sort_tmp, st, nullptr, nullptr, 0, cleared));
     }
     {
         StageTimer t(st, kStEmitCount);
-        HIP_TRY(scan_exclusive(gs.n_super, gs.offs, n, gst.totals, gs.scan_tmp, st, gst.order));
+        HIP_TRY(scan_exclusive(gs.n_super, gs.offs, n, gst.totals, gs.scan_tmp, st, gst.order, cleared));
     }
     return OMNIGS_OK;
+}
+
+// The words that sort_and_count with cleared == true expects zero, and the
+// counters of the state.
+void geom_clear(int64_t n, GeomState &gst, GeomScratch &gs, ClearList &L) {
+    const int64_t m = n > 0 ? n : 1;
+    L.add(gs.sort_tmp, sort_clear_words(m, 32));
+    L.add(gs.scan_tmp, scan_clear_words(m));
+    L.add(gst.totals, 2);
 }
 
 // Grids of the images of a launch.
@@ -322,7 +333,7 @@ struct BinScratch {
 // true the entry count is read on the device (min(S, super_cap)).
 omnigs_status run_binning(int64_t nrec, const GeomState &gst, const GeomScratch &gs, const Grids &G,
                           uint64_t super_cap, uint64_t inst_cap, bool counted, BinScratch &bs, uint2 *ranges,
-                          uint32_t *inst_gauss, int32_t *overflow, hipStream_t st) {
+                          uint32_t *inst_gauss, int32_t *overflow, hipStream_t st, bool cleared = false) {
     const int bits = bits_for(G.n_super);
     const bool odd = ((bits + 7) / 8) % 2;
     uint32_t *et = odd ? bs.stile_tmp : bs.stile, *eg = odd ? bs.sgauss_tmp : bs.sgauss;
@@ -340,7 +351,7 @@ omnigs_status run_binning(int64_t nrec, const GeomState &gst, const GeomScratch 
         const bool one_pass = bits <= 8;
         HIP_TRY(radix_sort_pairs(et, eg, bs.stile_tmp, bs.sgauss_tmp, bs.stile, bs.sgauss, (int64_t)super_cap, bits,
                                  bs.sort_tmp, st, counted ? gst.totals : nullptr, one_pass ? bs.sranges : nullptr,
-                                 one_pass ? (int)G.n_super : 0));
+                                 one_pass ? (int)G.n_super : 0, cleared));
         if (!one_pass) {
             HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(bs.sranges), 0u, 2 * (int64_t)G.n_super, st));
             HIP_TRY(launch_tile_ranges(bs.stile, gst.totals, super_cap, bs.sranges, G.n_super, st));
@@ -349,12 +360,18 @@ omnigs_status run_binning(int64_t nrec, const GeomState &gst, const GeomScratch 
     {
         StageTimer t(st, kStTileBin);
         HIP_TRY(launch_binning(G.sup, G.n_super, gst.rect, bs.sgauss, bs.sranges, super_cap, inst_cap, bs.bin_tmp,
-                               ranges, inst_gauss, overflow, st));
+                               ranges, inst_gauss, overflow, st, cleared));
     }
     return OMNIGS_OK;
 }
 
 }  // namespace
+
+// The words that run_binning with cleared == true expects zero.
+void bin_clear(uint64_t super_cap, const Grids &G, BinScratch &bs, ClearList &L) {
+    L.add(bs.sort_tmp, sort_clear_words((int64_t)(super_cap > 0 ? super_cap : 1), bits_for(G.n_super)));
+    binning_clear(bs.bin_tmp, super_cap, G.n_super, L);
+}
 
 // ============================================================== public API
 extern "C" {
@@ -439,14 +456,22 @@ omnigs_status omnigs_forward(const omnigs_gaussians *g, const omnigs_camera *cam
         if ((rc = alloc_arena(alloc, ta.off, OMNIGS_MEM_SCRATCH, ta, "forward scratch")) != OMNIGS_OK) return rc;
         carve_scratch(ta);
     }
-    if (counted && cap->overflow) HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(cap->overflow), 0u, 1, st));
-
+    {
+        // every counter and lookback word the call starts from, in one launch
+        ClearList L{};
+        geom_clear(n, gst, gs, L);
+        if (counted) {
+            bin_clear(super_cap, G, bs, L);
+            L.add(cap->overflow, 1);
+        }
+        HIP_TRY(launch_clear(L, st));
+    }
     {
         StageTimer t(st, kStProject);
         HIP_TRY(launch_project(pa, gst.rec, gs.depth_key, gst.depth, gst.n_tiles, gst.rect, gs.n_super, gst.radii,
-                               gst.totals + 1, st));
+                               gst.totals + 1, st, true));
     }
-    if ((rc = sort_and_count(n, gst, gs, st)) != OMNIGS_OK) return rc;
+    if ((rc = sort_and_count(n, gst, gs, st, true)) != OMNIGS_OK) return rc;
 
     int64_t S = -1, M = -1;
     if (!counted) {
@@ -465,10 +490,13 @@ omnigs_status omnigs_forward(const omnigs_gaussians *g, const omnigs_camera *cam
         carve_inst_state(ia);
         if ((rc = alloc_arena(alloc, ja.off, OMNIGS_MEM_SCRATCH, ja, "binning scratch")) != OMNIGS_OK) return rc;
         carve_inst_scratch(ja);
+        ClearList L{};
+        bin_clear(super_cap, G, bs, L);
+        HIP_TRY(launch_clear(L, st));
     }
 
     if ((rc = run_binning(n, gst, gs, G, super_cap, inst_cap, counted, bs, ranges, inst_gauss,
-                          counted ? cap->overflow : nullptr, st)) != OMNIGS_OK)
+                          counted ? cap->overflow : nullptr, st, true)) != OMNIGS_OK)
         return rc;
     {
         StageTimer t(st, kStTileOrder);

@@ -133,7 +133,8 @@ struct SuperTable {
 // radius (radii may be null); *tiles_total (device) receives the sum of the
 // tiles covered (M).
 hipError_t launch_project(const ProjectArgs &a, BlendRecord *rec, uint32_t *depth_key, float *depth, uint32_t *n_tiles,
-                          uint2 *rect, uint32_t *n_super, float *radii, uint32_t *tiles_total, hipStream_t st);
+                          uint2 *rect, uint32_t *n_super, float *radii, uint32_t *tiles_total, hipStream_t st,
+                          bool cleared = false);
 // All cameras of `cams` in one launch: the outputs of camera b for Gaussian i
 // land at index b * a.n + i, bit-identical to launch_project of that camera
 // (a's camera fields are ignored).
@@ -152,17 +153,38 @@ hipError_t launch_project_backward(const ProjectArgs &a, const uint32_t *n_tiles
 // else hipErrorInvalidValue.  key_ranges (device, may be null; only with
 // bits <= 8 and n_ranges <= 256): receives [start, end) of each key value
 // 0 .. n_ranges-1 in the sorted output.
+// cleared: the first sort_clear_words(n, bits) words of `scratch` are
+// already zero (the sort then launches no clear of its own).
 size_t sort_scratch_bytes(int64_t n);
+int64_t sort_clear_words(int64_t n, int bits);
 hipError_t radix_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_tmp,
                             uint32_t *vals_tmp, uint32_t *keys_out, uint32_t *vals_out, int64_t n, int bits,
                             void *scratch, hipStream_t st, const uint32_t *n_dev = nullptr,
-                            uint2 *key_ranges = nullptr, int n_ranges = 0);
+                            uint2 *key_ranges = nullptr, int n_ranges = 0, bool cleared = false);
 
 // Exclusive scan of u32 (optionally of in[gather[i]]); *total (device, may be
-// null) receives the sum.  `scratch` from scan_scratch_bytes.
+// null) receives the sum.  `scratch` from scan_scratch_bytes; cleared: its
+// first scan_clear_words(n) words are already zero.
 size_t scan_scratch_bytes(int64_t n);
+int64_t scan_clear_words(int64_t n);
 hipError_t scan_exclusive(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *total, void *scratch,
-                          hipStream_t st, const uint32_t *gather);
+                          hipStream_t st, const uint32_t *gather, bool cleared = false);
+
+// Zeroes up to kMaxClear regions of u32 words in one launch (the lookback
+// words and counters of the sorts and scans of a call).
+constexpr int kMaxClear = 8;
+struct ClearList {
+    uint32_t *p[kMaxClear];
+    int64_t n[kMaxClear];
+    int count;
+    void add(void *ptr, int64_t words) {
+        if (ptr && words > 0 && count < kMaxClear) {
+            p[count] = static_cast<uint32_t *>(ptr);
+            n[count++] = words;
+        }
+    }
+};
+hipError_t launch_clear(const ClearList &L, hipStream_t st);
 
 // Emission in depth order: offs[r] = exclusive scan of the per-record counts
 // (tiles or super-tiles, as frames.super says) in depth order (offs[n] = M at
@@ -188,10 +210,13 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);
 // super entries (at most super_cap).  Instances past inst_cap are dropped and
 // set *overflow (may be null); ranges are clamped to inst_cap.  Scratch from
 // binning_scratch_bytes.
+// binning_clear adds to L the scratch words that a launch with
+// cleared == true expects zero.
 size_t binning_scratch_bytes(uint64_t super_cap, uint32_t n_super_total);
+void binning_clear(void *scratch, uint64_t super_cap, uint32_t n_super_total, ClearList &L);
 hipError_t launch_binning(const SuperTable &T, uint32_t n_super_total, const uint2 *rect, const uint32_t *sinst_gauss,
                           const uint2 *sranges, uint64_t super_cap, uint64_t inst_cap, void *scratch, uint2 *ranges,
-                          uint32_t *inst_gauss, int32_t *overflow, hipStream_t st);
+                          uint32_t *inst_gauss, int32_t *overflow, hipStream_t st, bool cleared = false);
 
 // Blend kernels.
 struct BlendSettings {

@@ -572,8 +572,9 @@ __global__ __launch_bounds__(256) void k_project_backward(ProjectArgs A, const u
 }  // namespace
 
 hipError_t launch_project(const ProjectArgs &a, BlendRecord *rec, uint32_t *depth_key, float *depth, uint32_t *n_tiles,
-                          uint2 *rect, uint32_t *n_super, float *radii, uint32_t *tiles_total, hipStream_t st) {
-    hipError_t e = launch_fill_u32(tiles_total, 0u, 1, st);
+                          uint2 *rect, uint32_t *n_super, float *radii, uint32_t *tiles_total, hipStream_t st,
+                          bool cleared) {
+    hipError_t e = cleared ? hipSuccess : launch_fill_u32(tiles_total, 0u, 1, st);
     if (e != hipSuccess || a.n == 0) return e;
     const dim3 grid((unsigned)((a.n + 255) / 256));
     switch (a.sh_degree) {

@@ -522,6 +522,14 @@ __global__ __launch_bounds__(kThreads) void k_tile_ranges(const uint32_t *inst_t
     if (i + 1 == m || inst_tile[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
 }
 
+// Region blockIdx.y of the list, grid-strided in x.
+__global__ __launch_bounds__(256) void k_clear_list(ClearList L) {
+    const int r = blockIdx.y;
+    uint32_t *p = L.p[r];
+    const int64_t n = L.n[r];
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = 0u;
+}
+
 __global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -536,8 +544,13 @@ size_t scan_scratch_bytes(int64_t n) {
     return ((size_t)blocks_for(n > 0 ? n : 1, kScanTile) * 8 + 64 + 255) / 256 * 256 + 256;
 }
 
+int64_t scan_clear_words(int64_t n) {
+    const int64_t nb = blocks_for(n > 0 ? n : 1, kScanTile);
+    return nb == 1 ? 0 : nb * 2 + 1;  // the status words and the ticket, as u32
+}
+
 hipError_t scan_exclusive(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *total, void *scratch,
-                          hipStream_t st, const uint32_t *gather) {
+                          hipStream_t st, const uint32_t *gather, bool cleared) {
     if (n <= 0) {
         if (total) hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, total, 0u, (int64_t)1);
         return hipGetLastError();
@@ -549,9 +562,10 @@ hipError_t scan_exclusive(const uint32_t *in, uint32_t *out, int64_t n, uint32_t
     }
     uint64_t *status = static_cast<uint64_t *>(scratch);
     uint32_t *ticket = reinterpret_cast<uint32_t *>(status + nb);
-    const int64_t words = nb * 2 + 1;  // the status words and the ticket, as u32
-    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks_for(words, 256)), dim3(256), 0, st,
-                       reinterpret_cast<uint32_t *>(status), 0u, words);
+    const int64_t words = scan_clear_words(n);
+    if (!cleared)
+        hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks_for(words, 256)), dim3(256), 0, st,
+                           reinterpret_cast<uint32_t *>(status), 0u, words);
     hipLaunchKernelGGL(k_scan_lookback, dim3((unsigned)nb), dim3(kThreads), 0, st, in, gather, out, n, status, ticket,
                        total);
     return hipGetLastError();
@@ -562,10 +576,17 @@ size_t sort_scratch_bytes(int64_t n) {
     return ((size_t)kHeadWords + (size_t)kMaxPasses * nb * kBins) * 4 + 256;
 }
 
+int64_t sort_clear_words(int64_t n, int bits) {
+    if (n <= 0) return 0;
+    bits = std::min(std::max(bits, 1), 32);
+    const int passes = (bits + kRadixBits - 1) / kRadixBits;
+    return kHeadWords + (int64_t)passes * blocks_for(n, kTileKeys) * kBins;
+}
+
 hipError_t radix_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_tmp,
                             uint32_t *vals_tmp, uint32_t *keys_out, uint32_t *vals_out, int64_t n, int bits,
                             void *scratch, hipStream_t st, const uint32_t *n_dev, uint2 *key_ranges,
-                            int n_ranges) {
+                            int n_ranges, bool cleared) {
     if (key_ranges && (bits > kRadixBits || n_ranges > kBins)) return hipErrorInvalidValue;
     if (n <= 0) {
         if (key_ranges && n_ranges > 0)
@@ -582,8 +603,9 @@ hipError_t radix_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in, ui
     uint32_t *head = static_cast<uint32_t *>(scratch);
     uint32_t *ghist = head, *tickets = head + kMaxPasses * kBins;
     uint32_t *status = head + kHeadWords;
-    const int64_t words = kHeadWords + (int64_t)passes * nb * kBins;
-    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks_for(words, 256)), dim3(256), 0, st, head, 0u, words);
+    const int64_t words = sort_clear_words(n, bits);
+    if (!cleared)
+        hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks_for(words, 256)), dim3(256), 0, st, head, 0u, words);
     const int64_t hist_blocks = std::min<int64_t>(blocks_for(n, kHistChunk), kHistMaxBlocks);
     hipLaunchKernelGGL(k_sort_hist, dim3((unsigned)hist_blocks), dim3(kThreads), 0, st, keys_in, n, n_dev, passes,
                        bits, ghist);
@@ -601,6 +623,15 @@ hipError_t radix_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in, ui
         src_k = dk;
         src_v = dv;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_clear(const ClearList &L, hipStream_t st) {
+    if (L.count == 0) return hipSuccess;
+    int64_t most = 0;
+    for (int k = 0; k < L.count; ++k) most = std::max(most, L.n[k]);
+    const unsigned bx = (unsigned)std::min<int64_t>(blocks_for(most, 256), 2048);
+    hipLaunchKernelGGL(k_clear_list, dim3(bx, (unsigned)L.count), dim3(256), 0, st, L);
     return hipGetLastError();
 }
 
