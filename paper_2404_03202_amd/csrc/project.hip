@@ -211,16 +211,6 @@ __device__ inline bool project_core(const ProjectArgs &A, int64_t i, double o, P
     return true;
 }
 
-template <int D>
-__device__ inline void load_sh(const ProjectArgs &A, int64_t i, double (*sh)[3]) {
-    constexpr int K = (D + 1) * (D + 1);
-    const float *p = A.sh + i * (int64_t)A.sh_coeffs * 3;
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) sh[k][ch] = p[3 * k + ch];
-}
-
 // Projection of Gaussian i for the camera of A; the outputs go to index
 // `slot` of the output arrays.
 template <int D>
@@ -283,16 +273,23 @@ __device__ inline uint32_t project_one(const ProjectArgs &A, int64_t i, int64_t 
     constexpr int K = (D + 1) * (D + 1);
     double Y[16];
     sh_basis<D>(P.dir[0], P.dir[1], P.dir[2], Y);
-    double sh[K][3];
-    load_sh<D>(A, i, sh);
+    // all coefficient loads issued together (kept ahead of their use by a
+    // scheduling barrier), held as floats (not doubles)
+    float shp[K * 3];
+    {
+        const float *src = A.sh + i * (int64_t)A.sh_coeffs * 3;
+#pragma unroll
+        for (int k = 0; k < K * 3; ++k) shp[k] = src[k];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    double v[3] = {0.5, 0.5, 0.5};
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) v[ch] += Y[k] * (double)shp[3 * k + ch];
     float rgb[3];
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-        double v = 0.5;
-#pragma unroll
-        for (int k = 0; k < K; ++k) v += Y[k] * sh[k][ch];
-        rgb[ch] = v < 0.0 ? 0.0f : (float)v;
-    }
+    for (int ch = 0; ch < 3; ++ch) rgb[ch] = v[ch] < 0.0 ? 0.0f : (float)v[ch];
     BlendRecord r;
     r.px_hi = (float)P.px;
     r.px_lo = (float)(P.px - (double)r.px_hi);
