@@ -341,18 +341,22 @@ typedef struct {
  * sqrt(1 - b2^t) + eps).  p, m1, m2 are updated in place.  act (may be NULL)
  * receives the rasterizer's inputs for the new parameters: act->scales =
  * exp(log_scales), act->opacities = sigmoid(logits) (its other pointers are
- * not written).  Errors: OMNIGS_ERR_INVALID for null pointers or mismatched
- * sizes. */
+ * not written).  skip (device int32, may be NULL): when *skip is nonzero on
+ * the stream the step writes nothing (pass a forward's overflow flag so that
+ * an iteration whose forward overflowed its capacities leaves the
+ * parameters, moments and activations as they were).  Errors:
+ * OMNIGS_ERR_INVALID for null pointers or mismatched sizes. */
 omnigs_status omnigs_adam_step(omnigs_params *p, const omnigs_grads *g, omnigs_params *m1, omnigs_params *m2,
-                               const omnigs_adam_settings *s, omnigs_gaussians *act, void *stream);
+                               const omnigs_adam_settings *s, omnigs_gaussians *act, const int32_t *skip,
+                               void *stream);
 
 /* Densification statistics of one view: for every Gaussian the forward
  * `state` saw covering a tile, accum += ||dscreen||_2, denom += 1 and
  * max_radius = max(max_radius, its screen radius in pixels (the larger half
  * extent of the alpha = alpha_min box)).  g->dscreen from omnigs_backward
- * of that view. */
+ * of that view.  skip (device int32, may be NULL): as for omnigs_adam_step. */
 omnigs_status omnigs_accumulate_stats(const omnigs_state *state, const omnigs_grads *g,
-                                      omnigs_densify_stats *stats, void *stream);
+                                      omnigs_densify_stats *stats, const int32_t *skip, void *stream);
 
 /* Densify and prune (see the section comment; decisions in float32: the
  * averaged gradient by float32 division, scales and opacities compared in

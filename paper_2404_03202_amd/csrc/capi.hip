@@ -772,7 +772,8 @@ omnigs_status same_shape(const omnigs_params *a, const omnigs_params *b, const c
 extern "C" {
 
 omnigs_status omnigs_adam_step(omnigs_params *p, const omnigs_grads *g, omnigs_params *m1, omnigs_params *m2,
-                               const omnigs_adam_settings *s, omnigs_gaussians *act, void *stream) {
+                               const omnigs_adam_settings *s, omnigs_gaussians *act, const int32_t *skip,
+                               void *stream) {
     omnigs_status rc;
     if ((rc = check_params(p, "params")) != OMNIGS_OK || (rc = check_params(m1, "m1")) != OMNIGS_OK ||
         (rc = check_params(m2, "m2")) != OMNIGS_OK)
@@ -810,19 +811,19 @@ omnigs_status omnigs_adam_step(omnigs_params *p, const omnigs_grads *g, omnigs_p
     StageTimer t(static_cast<hipStream_t>(stream), kStAdam);
     HIP_TRY(launch_adam(arrays_of(p), G, arrays_of(m1), arrays_of(m2), a,
                         act ? const_cast<float *>(act->scales) : nullptr,
-                        act ? const_cast<float *>(act->opacities) : nullptr, static_cast<hipStream_t>(stream)));
+                        act ? const_cast<float *>(act->opacities) : nullptr, skip, static_cast<hipStream_t>(stream)));
     return OMNIGS_OK;
 }
 
 omnigs_status omnigs_accumulate_stats(const omnigs_state *state, const omnigs_grads *g,
-                                      omnigs_densify_stats *stats, void *stream) {
+                                      omnigs_densify_stats *stats, const int32_t *skip, void *stream) {
     if (!state || !g || !stats) return fail(OMNIGS_ERR_INVALID, "state, gradients or statistics is NULL");
     if (state->n > 0 && (!state->n_tiles || !state->radii || !g->dscreen || !stats->accum || !stats->denom ||
                          !stats->max_radius))
         return fail(OMNIGS_ERR_INVALID, "a state, gradient or statistics pointer is NULL");
     StageTimer t(static_cast<hipStream_t>(stream), kStStats);
     HIP_TRY(launch_stats(state->n_tiles, state->radii, g->dscreen, state->n, stats->accum, stats->denom,
-                         stats->max_radius, static_cast<hipStream_t>(stream)));
+                         stats->max_radius, skip, static_cast<hipStream_t>(stream)));
     return OMNIGS_OK;
 }
 

@@ -267,10 +267,12 @@ struct DensifyArgs {
     float tau, log_clone, logit_min, max_screen, log_big, log_shrink;
     int screen_on;
 };
+// skip (device, may be null): nothing is written when *skip != 0.
 hipError_t launch_adam(const OptimArrays &P, const OptimArrays &G, const OptimArrays &M1, const OptimArrays &M2,
-                       const AdamArgs &a, float *act_scales, float *act_opacities, hipStream_t st);
+                       const AdamArgs &a, float *act_scales, float *act_opacities, const int32_t *skip,
+                       hipStream_t st);
 hipError_t launch_stats(const uint32_t *n_tiles, const float *radii, const float *dscreen, int64_t n, float *accum,
-                        float *denom, float *max_radius, hipStream_t st);
+                        float *denom, float *max_radius, const int32_t *skip, hipStream_t st);
 hipError_t launch_dens_flags(const OptimArrays &P, const float *accum, const float *denom, const float *max_radius,
                              int64_t n, const DensifyArgs &d, uint32_t *flags, hipStream_t st);
 hipError_t launch_dens_scatter(const OptimArrays &P, const OptimArrays &M1, const OptimArrays &M2,

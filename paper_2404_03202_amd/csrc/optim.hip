@@ -86,7 +86,9 @@ __device__ inline void adam_segment(const OptimArrays &P, const OptimArrays &G, 
 }
 
 __global__ __launch_bounds__(kThreads) void k_adam(OptimArrays P, OptimArrays G, OptimArrays M1, OptimArrays M2,
-                                                   AdamArgs a, float *act_scales, float *act_opacities) {
+                                                   AdamArgs a, float *act_scales, float *act_opacities,
+                                                   const int32_t *skip) {
+    if (skip && *skip) return;
     switch (blockIdx.y) {
         case kSegMeans: adam_segment<kSegMeans>(P, G, M1, M2, a, nullptr); break;
         case kSegLogScales: adam_segment<kSegLogScales>(P, G, M1, M2, a, act_scales); break;
@@ -97,9 +99,10 @@ __global__ __launch_bounds__(kThreads) void k_adam(OptimArrays P, OptimArrays G,
 }
 
 __global__ __launch_bounds__(kThreads) void k_stats(const uint32_t *n_tiles, const float *radii, const float *dscreen,
-                                                    int64_t n, float *accum, float *denom, float *max_radius) {
+                                                    int64_t n, float *accum, float *denom, float *max_radius,
+                                                    const int32_t *skip) {
     const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (i >= n || n_tiles[i] == 0) return;
+    if (i >= n || (skip && *skip) || n_tiles[i] == 0) return;
     const float gx = dscreen[2 * i], gy = dscreen[2 * i + 1];
     accum[i] += sqrtf(gx * gx + gy * gy);
     denom[i] += 1.0f;
@@ -202,7 +205,8 @@ unsigned blocks(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 }  // namespace
 
 hipError_t launch_adam(const OptimArrays &P, const OptimArrays &G, const OptimArrays &M1, const OptimArrays &M2,
-                       const AdamArgs &a, float *act_scales, float *act_opacities, hipStream_t st) {
+                       const AdamArgs &a, float *act_scales, float *act_opacities, const int32_t *skip,
+                       hipStream_t st) {
     if (a.total == 0) return hipSuccess;
     // blockIdx.y: the parameter array; x: enough blocks for the largest (SH)
     int64_t longest = 0;
@@ -210,15 +214,15 @@ hipError_t launch_adam(const OptimArrays &P, const OptimArrays &G, const OptimAr
         longest = std::max<int64_t>(longest, (k + 1 < kSegments ? a.begin[k + 1] : a.total) - a.begin[k]);
     const unsigned grid = (unsigned)std::min<int64_t>((longest + 4 * kThreads - 1) / (4 * kThreads), 256 * 32);
     hipLaunchKernelGGL(k_adam, dim3(grid, kSegments), dim3(kThreads), 0, st, P, G, M1, M2, a, act_scales,
-                       act_opacities);
+                       act_opacities, skip);
     return hipGetLastError();
 }
 
 hipError_t launch_stats(const uint32_t *n_tiles, const float *radii, const float *dscreen, int64_t n, float *accum,
-                        float *denom, float *max_radius, hipStream_t st) {
+                        float *denom, float *max_radius, const int32_t *skip, hipStream_t st) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_stats, dim3(blocks(n)), dim3(kThreads), 0, st, n_tiles, radii, dscreen, n, accum, denom,
-                       max_radius);
+                       max_radius, skip);
     return hipGetLastError();
 }
 

@@ -143,9 +143,9 @@ def load_library(path: str = LIB_PATH):
                                              P(c_image_out), ctypes.c_int64, vp, P(ctypes.c_int64), vp]
         lib.omnigs_forward_batch.restype = ctypes.c_int
         lib.omnigs_adam_step.argtypes = [P(c_params), P(c_grads), P(c_params), P(c_params), P(c_adam_settings),
-                                         P(c_gaussians), vp]
+                                         P(c_gaussians), vp, vp]
         lib.omnigs_adam_step.restype = ctypes.c_int
-        lib.omnigs_accumulate_stats.argtypes = [P(c_state), P(c_grads), P(c_dens_stats), vp]
+        lib.omnigs_accumulate_stats.argtypes = [P(c_state), P(c_grads), P(c_dens_stats), vp, vp]
         lib.omnigs_accumulate_stats.restype = ctypes.c_int
         lib.omnigs_densify.argtypes = [P(c_params), P(c_params), P(c_params), P(c_dens_stats), vp, P(c_dens_settings),
                                        c_allocator, P(c_params), P(c_params), P(c_params), P(c_dens_stats),
@@ -528,10 +528,11 @@ def _grads(grads: dict) -> c_grads:
 
 
 def omnigs_adam_step(p: dict, grads: dict, m1: dict, m2: dict, lrs: dict, step: int, act: dict | None = None,
-                     beta1=0.9, beta2=0.999, eps=1e-15):
+                     beta1=0.9, beta2=0.999, eps=1e-15, skip: torch.Tensor | None = None):
     """In-place Adam step of p, m1, m2 (dicts of raw parameters); act (may be
     None): a Gaussian dict whose scales / opacities receive exp / sigmoid of
-    the new log-scales / logits."""
+    the new log-scales / logits.  skip (device int32 [1], may be None): the
+    step writes nothing when it is nonzero."""
     lib = load_library()
     s = c_adam_settings(lrs["means"], lrs["sh_dc"], lrs["sh_rest"], lrs["logits"], lrs["log_scales"], lrs["quats"],
                         beta1, beta2, eps, int(step))
@@ -542,15 +543,16 @@ def omnigs_adam_step(p: dict, grads: dict, m1: dict, m2: dict, lrs: dict, step: 
         ca.scales, ca.opacities = _ptr(act["scales"]), _ptr(act["opacities"])
     _check(lib.omnigs_adam_step(ctypes.byref(cp), ctypes.byref(_grads(grads)), ctypes.byref(c1), ctypes.byref(c2),
                                 ctypes.byref(s), ctypes.byref(ca) if ca is not None else None,
-                                ctypes.c_void_p(_stream_ptr(p["means"].device))))
+                                ctypes.c_void_p(_ptr(skip)), ctypes.c_void_p(_stream_ptr(p["means"].device))))
 
 
-def omnigs_accumulate_stats(fwd: "ForwardResult", grads: dict, stats: dict):
-    """stats: accum, denom, max_radius ([N] float32 tensors), updated in place."""
+def omnigs_accumulate_stats(fwd: "ForwardResult", grads: dict, stats: dict, skip: torch.Tensor | None = None):
+    """stats: accum, denom, max_radius ([N] float32 tensors), updated in place
+    (nothing written when skip, a device int32 [1], is nonzero)."""
     lib = load_library()
     cs = c_dens_stats(_ptr(stats["accum"]), _ptr(stats["denom"]), _ptr(stats["max_radius"]))
     _check(lib.omnigs_accumulate_stats(ctypes.byref(fwd.state), ctypes.byref(_grads(grads)), ctypes.byref(cs),
-                                       ctypes.c_void_p(_stream_ptr(stats["accum"].device))))
+                                       ctypes.c_void_p(_ptr(skip)), ctypes.c_void_p(_stream_ptr(stats["accum"].device))))
 
 
 def omnigs_densify(p: dict, m1: dict, m2: dict, stats: dict, noise: torch.Tensor, settings: dict,

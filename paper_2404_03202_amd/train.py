@@ -51,13 +51,27 @@ def logit(p):
 
 class Trainer:
     """Holds the raw parameters, the Adam moments, the statistics and the
-    activated copies the rasterizer reads."""
+    activated copies the rasterizer reads.
+
+    capacity_slack (None: every forward reads its instance counts back): the
+    forwards take instance and block-entry capacities of capacity_slack times
+    the largest counts read so far and read nothing back.  An iteration whose
+    forward overflowed leaves the parameters, moments and statistics as they
+    were (its overflow flag gates the Adam and statistics kernels on the
+    device); the flags are read `lag` iterations later, and such an iteration
+    is then run again with its counts read back, which regrows the
+    capacities."""
 
     def __init__(self, gaussians: dict, settings: TrainSettings | None = None, device="cuda:0", seed=0,
-                 render_settings: dict | None = None):
+                 render_settings: dict | None = None, capacity_slack: float | None = None, lag: int = 2):
         self.s = settings or TrainSettings()
         self.device = device
         self.render_settings = render_settings
+        self.slack = capacity_slack
+        self.lag = lag
+        self.cap = None      # (instances, block entries) once counted
+        self._pending = []   # (overflow flag, camera, target, mask) of recent capacity-mode iterations
+        self.redone = 0
         g = gaussians
         f = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device)
         self.p = dict(means=f(g["means"]), log_scales=f(np.log(g["scales"])), quats=f(g["quats"]),
@@ -95,15 +109,8 @@ class Trainer:
         per-pixel loss weights (a camera's "rows" skips bottom rows
         outright)."""
         self.step_count += 1
-        fwd = B.omnigs_forward(self.act, camera, self.render_settings)
-        if self.s.lambda_dssim > 0.0 or mask is not None:
-            loss, dl = B.omnigs_photometric_loss(fwd.image, target, self.s.lambda_dssim, mask=mask)
-        else:
-            loss, dl = B.omnigs_l1_loss(fwd.image, target)
-        grads = B.omnigs_backward(self.act, camera, self.render_settings, fwd, dl)
-        B.omnigs_accumulate_stats(fwd, grads, self.stats)
-        # the activated copies are rewritten in place by the Adam kernel
-        B.omnigs_adam_step(self.p, grads, self.m1, self.m2, self.lrs(), self.step_count, self.act)
+        loss = self._iterate(camera, target, mask, self.cap if self.slack else None)
+        self._settle(self.lag)
         j, s = self.step_count, self.s
         if j <= s.densify_until:
             if j >= s.densify_from and j % s.densify_interval == 0:
@@ -113,7 +120,40 @@ class Trainer:
                 self.act["opacities"] = torch.sigmoid(self.p["logits"]).contiguous()
         return loss
 
+    def _iterate(self, camera, target, mask, cap):
+        fwd = B.omnigs_forward(self.act, camera, self.render_settings, capacity=cap)
+        if self.s.lambda_dssim > 0.0 or mask is not None:
+            loss, dl = B.omnigs_photometric_loss(fwd.image, target, self.s.lambda_dssim, mask=mask)
+        else:
+            loss, dl = B.omnigs_l1_loss(fwd.image, target)
+        grads = B.omnigs_backward(self.act, camera, self.render_settings, fwd, dl)
+        B.omnigs_accumulate_stats(fwd, grads, self.stats, skip=fwd.overflow)
+        # the activated copies are rewritten in place by the Adam kernel
+        B.omnigs_adam_step(self.p, grads, self.m1, self.m2, self.lrs(), self.step_count, self.act,
+                           skip=fwd.overflow)
+        if cap is not None:
+            self._pending.append((fwd.overflow, camera, target, mask))
+        elif self.slack:
+            want = (int(self.slack * fwd.n_instances) + 1, int(self.slack * fwd.n_entries) + 1)
+            self.cap = want if self.cap is None else (max(self.cap[0], want[0]), max(self.cap[1], want[1]))
+        return loss
+
+    def _settle(self, keep: int):
+        """Read the overflow flags of all but the last `keep` capacity-mode
+        iterations; run the overflowed ones again with their counts read back."""
+        while len(self._pending) > keep:
+            overflow, camera, target, mask = self._pending.pop(0)
+            if int(overflow.item()):
+                self.redone += 1
+                self._iterate(camera, target, mask, None)
+
+    def flush(self):
+        """Settle every pending capacity-mode iteration."""
+        self._settle(0)
+
     def densify(self, screen: bool = True):
+        self.flush()
+        n_before = self.n
         s = self.s
         noise = torch.from_numpy(self.rng.standard_normal((self.n, 2, 3)).astype(np.float32)).to(self.device)
         settings = dict(grad_threshold=s.grad_threshold, percent_dense=s.percent_dense, extent=s.extent,
@@ -121,3 +161,6 @@ class Trainer:
                         big_fraction=s.big_fraction, split_shrink=s.split_shrink)
         self.p, self.m1, self.m2, self.stats = B.omnigs_densify(self.p, self.m1, self.m2, self.stats, noise, settings)
         self._activate()
+        if self.cap is not None and self.n > n_before:  # more Gaussians: scale the capacities with them
+            f = self.n / max(n_before, 1)
+            self.cap = (int(self.cap[0] * f) + 1, int(self.cap[1] * f) + 1)
