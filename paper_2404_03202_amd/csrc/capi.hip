@@ -341,8 +341,8 @@ omnigs_status run_binning(int64_t nrec, const GeomState &gst, const GeomScratch 
         StageTimer t(st, kStSuperEmit);
         // emit where the sort's ping-pong starts, so that the last pass lands
         // in stile / sgauss
-        HIP_TRY(launch_emit(gst.order, gs.n_super, gst.rect, gs.offs, nrec, bs.part, gst.totals, G.ef, super_cap, et,
-                            eg, overflow, st));
+        HIP_TRY(launch_emit(gst.order, gst.rect, gs.offs, nrec, bs.part, gst.totals, G.ef, super_cap, et, eg, overflow,
+                            st));
     }
     {
         StageTimer t(st, kStSuperSort);

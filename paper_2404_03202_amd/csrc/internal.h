@@ -187,16 +187,16 @@ struct ClearList {
 hipError_t launch_clear(const ClearList &L, hipStream_t st);
 
 // Emission in depth order: offs[r] = exclusive scan of the per-record counts
-// (tiles or super-tiles, as frames.super says) in depth order (offs[n] = M at
-// *m_dev).  Writes min(M, capacity) (grid id, record) pairs, with global grid
+// (tiles or super-tiles, as frames.super says) in depth order, their total M
+// at *m_dev (a record's count is the difference of adjacent offsets; a culled
+// record's rectangle is empty).  Writes min(M, capacity) (grid id, record) pairs, with global grid
 // ids (frames.base of the record's camera plus the id inside its grid); sets
 // *overflow when M > capacity.  `part` holds emit_blocks(capacity) entries of
 // scratch.
 uint64_t emit_blocks(uint64_t capacity);
-hipError_t launch_emit(const uint32_t *order, const uint32_t *n_tiles, const uint2 *rect, const uint32_t *offs,
-                       int64_t n, uint32_t *part, const uint32_t *m_dev, const EmitFrames &frames,
-                       uint64_t capacity, uint32_t *inst_tile, uint32_t *inst_gauss, int32_t *overflow,
-                       hipStream_t st);
+hipError_t launch_emit(const uint32_t *order, const uint2 *rect, const uint32_t *offs, int64_t n, uint32_t *part,
+                       const uint32_t *m_dev, const EmitFrames &frames, uint64_t capacity, uint32_t *inst_tile,
+                       uint32_t *inst_gauss, int32_t *overflow, hipStream_t st);
 hipError_t launch_tile_ranges(const uint32_t *inst_tile, const uint32_t *m_dev, uint64_t capacity,
                               uint2 *ranges, uint32_t n_tiles_total, hipStream_t st);
 

@@ -44,6 +44,7 @@ constexpr int kScanItems = 16;
 constexpr int kScanTile = kThreads * kScanItems;
 constexpr int kEmitItems = 8;
 constexpr int kEmitSpan = kThreads * kEmitItems;  // outputs per emit block
+static_assert(kEmitItems == 8, "k_emit stores a thread's outputs as two uint4");
 
 __device__ inline uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
 
@@ -434,20 +435,19 @@ __global__ __launch_bounds__(kThreads) void k_scan_tile(const uint32_t *in, cons
 // fixed span of kEmitSpan consecutive outputs, whatever the tile counts of the
 // Gaussians behind them (the nearest Gaussians, which come first, cover up to
 // thousands of tiles each).  part[b] = the rank owning output b * kEmitSpan.
-__global__ __launch_bounds__(kThreads) void k_emit_partition(const uint32_t *order, const uint32_t *n_tiles,
-                                                              const uint32_t *offs, int64_t n,
+__global__ __launch_bounds__(kThreads) void k_emit_partition(const uint32_t *offs, const uint32_t *m_dev, int64_t n,
                                                               uint64_t part_blocks, uint32_t *part) {
     const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (r >= n) return;
-    const uint32_t g = order[r];
-    const uint32_t c = g < (uint64_t)n ? n_tiles[g] : 0u;
-    if (c == 0) return;
+    // rank r's count from the adjacent offsets (the last rank ends at M)
     const uint64_t o = offs[r];
-    const uint64_t b1 = (o + c - 1) / kEmitSpan;
+    const uint64_t e = r + 1 < n ? (uint64_t)offs[r + 1] : (uint64_t)*m_dev;
+    if (e <= o) return;
+    const uint64_t b1 = (e - 1) / kEmitSpan;
     for (uint64_t b = (o + kEmitSpan - 1) / kEmitSpan; b <= b1 && b < part_blocks; ++b) part[b] = (uint32_t)r;
 }
 
-__global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *order, const uint32_t *n_tiles, const uint2 *rect,
+__global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *order, const uint2 *rect,
                                                     const uint32_t *offs, int64_t n, const uint32_t *part,
                                                     const uint32_t *m_dev, EmitFrames F, uint64_t capacity,
                                                     uint32_t *inst_tile, uint32_t *inst_gauss, int32_t *overflow) {
@@ -471,14 +471,30 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *order, const 
     if (r1 > (uint64_t)r0 + kEmitSpan) r1 = (uint64_t)r0 + kEmitSpan;
     if (r1 < r0) r1 = r0;
     const int cnt = (int)(r1 - r0) + 1;
-    for (int i = threadIdx.x; i < cnt; i += kThreads) {
-        const uint32_t r = r0 + i;
-        const uint32_t g = order[r];
+    // the ranks' records, in two rounds of loads (ids and offsets, then the
+    // gathered rectangles) each issued whole before use; a culled record's
+    // rectangle is empty, so no count is gathered
+    constexpr int kRankIters = (kEmitSpan + kThreads) / kThreads;  // covers kEmitSpan + 1 ranks
+    uint32_t gv[kRankIters], ov[kRankIters];
+    uint2 rv[kRankIters];
+#pragma unroll
+    for (int it = 0; it < kRankIters; ++it) {
+        const int i = threadIdx.x + it * kThreads;
+        gv[it] = i < cnt ? order[r0 + i] : 0xffffffffu;
+        ov[it] = i < cnt ? offs[r0 + i] : 0u;
+    }
+#pragma unroll
+    for (int it = 0; it < kRankIters; ++it) rv[it] = gv[it] < (uint64_t)n ? rect[gv[it]] : make_uint2(0, 0);
+#pragma unroll
+    for (int it = 0; it < kRankIters; ++it) {
+        const int i = threadIdx.x + it * kThreads;
+        if (i >= cnt) continue;
+        const uint32_t g = gv[it];
         // camera of record g = b * n_per + i
         const int cam = F.count > 1 && g < (uint64_t)n ? (int)min((int64_t)g / F.n_per, (int64_t)F.count - 1) : 0;
-        uint2 rc = (g < (uint64_t)n && n_tiles[g]) ? rect[g] : make_uint2(0, 0);
+        uint2 rc = rv[it];
         if (F.super) rc = super_rect(rc, F.tiles_x[cam]);
-        s_off[i] = offs[r];
+        s_off[i] = ov[it];
         s_gid[i] = g;
         s_rect[i] = rc;
         s_cam[i] = (uint8_t)cam;
@@ -487,13 +503,26 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *order, const 
     uint64_t jend = j0 + kEmitSpan;
     if (jend > M) jend = M;
     if (jend > capacity) jend = capacity;
-    for (uint64_t j = j0 + threadIdx.x; j < jend; j += kThreads) {
-        // last rank i with s_off[i] <= j
-        int lo = 0, hi = cnt;
+    // thread t writes the kEmitItems consecutive outputs from j0 + t kEmitItems:
+    // one search for the rank owning the first (the last rank i with
+    // s_off[i] <= j), then the owner only moves forward
+    const uint64_t jt = j0 + (uint64_t)threadIdx.x * kEmitItems;
+    if (jt >= jend) return;
+    int lo = 0;
+    {
+        int hi = cnt;
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
-            if (s_off[mid] <= j) lo = mid; else hi = mid;
+            if (s_off[mid] <= jt) lo = mid; else hi = mid;
         }
+    }
+    uint32_t tile[kEmitItems], gid[kEmitItems];
+#pragma unroll
+    for (int i = 0; i < kEmitItems; ++i) {
+        const uint64_t j = jt + i;
+        tile[i] = gid[i] = 0u;
+        if (j >= jend) continue;
+        while (lo + 1 < cnt && s_off[lo + 1] <= j) ++lo;
         const uint32_t k = (uint32_t)(j - s_off[lo]);
         const uint2 rc = s_rect[lo];
         const uint32_t ntx = rc.x >> 16, tx0 = rc.x & 0xffffu, ty0 = rc.y & 0xffffu;
@@ -503,8 +532,23 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *order, const 
         const uint32_t ty = ty0 + k / ntx;
         uint32_t tx = tx0 + k % ntx;
         if (tx >= cols) tx -= cols;
-        inst_tile[j] = F.base[cam] + ty * cols + tx;
-        inst_gauss[j] = s_gid[lo];
+        tile[i] = F.base[cam] + ty * cols + tx;
+        gid[i] = s_gid[lo];
+    }
+    if (jt + kEmitItems <= jend) {
+        // whole run: two 16-byte stores per array (jt is a multiple of 8)
+        uint4 *dt = reinterpret_cast<uint4 *>(inst_tile + jt), *dg = reinterpret_cast<uint4 *>(inst_gauss + jt);
+        dt[0] = make_uint4(tile[0], tile[1], tile[2], tile[3]);
+        dt[1] = make_uint4(tile[4], tile[5], tile[6], tile[7]);
+        dg[0] = make_uint4(gid[0], gid[1], gid[2], gid[3]);
+        dg[1] = make_uint4(gid[4], gid[5], gid[6], gid[7]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < kEmitItems; ++i)
+            if (jt + i < jend) {
+                inst_tile[jt + i] = tile[i];
+                inst_gauss[jt + i] = gid[i];
+            }
     }
 }
 
@@ -643,15 +687,14 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st) {
 
 uint64_t emit_blocks(uint64_t capacity) { return (capacity + kEmitSpan - 1) / kEmitSpan; }
 
-hipError_t launch_emit(const uint32_t *order, const uint32_t *n_tiles, const uint2 *rect, const uint32_t *offs,
-                       int64_t n, uint32_t *part, const uint32_t *m_dev, const EmitFrames &frames,
-                       uint64_t capacity, uint32_t *inst_tile, uint32_t *inst_gauss, int32_t *overflow,
-                       hipStream_t st) {
+hipError_t launch_emit(const uint32_t *order, const uint2 *rect, const uint32_t *offs, int64_t n, uint32_t *part,
+                       const uint32_t *m_dev, const EmitFrames &frames, uint64_t capacity, uint32_t *inst_tile,
+                       uint32_t *inst_gauss, int32_t *overflow, hipStream_t st) {
     if (n <= 0 || capacity == 0) return hipSuccess;
     const uint64_t nb = emit_blocks(capacity);
-    hipLaunchKernelGGL(k_emit_partition, dim3((unsigned)blocks_for(n, kThreads)), dim3(kThreads), 0, st, order,
-                       n_tiles, offs, n, nb, part);
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)nb), dim3(kThreads), 0, st, order, n_tiles, rect, offs, n,
+    hipLaunchKernelGGL(k_emit_partition, dim3((unsigned)blocks_for(n, kThreads)), dim3(kThreads), 0, st, offs, m_dev,
+                       n, nb, part);
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)nb), dim3(kThreads), 0, st, order, rect, offs, n,
                        (const uint32_t *)part, m_dev, frames, capacity, inst_tile, inst_gauss, overflow);
     return hipGetLastError();
 }
