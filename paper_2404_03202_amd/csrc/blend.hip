@@ -610,23 +610,45 @@ hipError_t launch_tile_order(const uint2 *ranges, const uint32_t *work, uint32_t
     return hipGetLastError();
 }
 
+template <int kW>
+void launch_forward_waves(const FrameTable &T, unsigned tiles, const BlendRecord *rec, const float *rdepth,
+                          const uint32_t *inst_gauss, const uint2 *ranges, const BlendSettings &s, bool depth,
+                          const uint32_t *order, uint32_t *tile_work, hipStream_t st) {
+    if (depth)
+        hipLaunchKernelGGL((k_blend_forward<kW, false, true>), dim3(tiles), dim3(kWave * kW), 0, st, T, rec, rdepth,
+                           inst_gauss, ranges, s, order, tile_work);
+    else
+        hipLaunchKernelGGL((k_blend_forward<kW, false, false>), dim3(tiles), dim3(kWave * kW), 0, st, T, rec,
+                           (const float *)nullptr, inst_gauss, ranges, s, order, tile_work);
+}
+
+// Mean instances per tile above which two waves per tile (two pixels per
+// lane: each staged instance's LDS reads and scalar work shared by two
+// pixels) beat four (shorter walks per wave); measured 0.51 -> 0.46 ms at
+// 5.8k per tile, 0.27 -> 0.31 ms the other way at 1.4k.  Every pixel's
+// arithmetic is the same either way.  With such lists the longest-first
+// launch order no longer shortens the forward (0.453 vs 0.448 ms at 5.8k;
+// 0.26 vs 0.31 ms at 1.4k), so the forward then runs in tile order.
+constexpr uint64_t kLongLists = 3000;
+
+bool forward_uses_order(uint64_t instances, uint32_t tiles) { return instances <= kLongLists * (uint64_t)tiles; }
+
 hipError_t launch_blend_forward(const FrameGeom &f, const BlendRecord *rec, const float *rdepth,
                                 const uint32_t *inst_gauss, const uint2 *ranges, const BlendSettings &s, float *image,
                                 float *final_T, int32_t *n_contrib, int32_t *n_blended, float *depth_out,
-                                const uint32_t *order, uint32_t *tile_work, hipStream_t st) {
+                                const uint32_t *order, uint32_t *tile_work, uint64_t instances, hipStream_t st) {
     FrameTable T{};
     T.n = 1;
     T.f[0] = BlendFrame{f.width, f.height, f.tiles_x, f.tiles_y, 0u, period_of(f), image, final_T, n_contrib,
                         n_blended, nullptr, depth_out, nullptr, nullptr};
     const unsigned tiles = (unsigned)(f.tiles_x * f.tiles_y);
     if (tiles == 0) return hipSuccess;
-    constexpr int kW = OMNIGS_FWD_WAVES;
-    if (depth_out)
-        hipLaunchKernelGGL((k_blend_forward<kW, false, true>), dim3(tiles), dim3(kWave * kW), 0, st, T, rec, rdepth,
-                           inst_gauss, ranges + f.tile_base, s, order, tile_work);
+    if (instances > kLongLists * tiles)
+        launch_forward_waves<2>(T, tiles, rec, rdepth, inst_gauss, ranges + f.tile_base, s, depth_out != nullptr,
+                                order, tile_work, st);
     else
-        hipLaunchKernelGGL((k_blend_forward<kW, false, false>), dim3(tiles), dim3(kWave * kW), 0, st, T, rec,
-                           (const float *)nullptr, inst_gauss, ranges + f.tile_base, s, order, tile_work);
+        launch_forward_waves<OMNIGS_FWD_WAVES>(T, tiles, rec, rdepth, inst_gauss, ranges + f.tile_base, s,
+                                               depth_out != nullptr, order, tile_work, st);
     return hipGetLastError();
 }
 

@@ -498,15 +498,18 @@ omnigs_status omnigs_forward(const omnigs_gaussians *g, const omnigs_camera *cam
     if ((rc = run_binning(n, gst, gs, G, super_cap, inst_cap, counted, bs, ranges, inst_gauss,
                           counted ? cap->overflow : nullptr, st, true)) != OMNIGS_OK)
         return rc;
-    {
+    if (forward_uses_order(inst_cap, ntiles)) {
         StageTimer t(st, kStTileOrder);
         HIP_TRY(launch_tile_order(ranges, nullptr, ntiles, order, st));
+    } else {
+        order = nullptr;
     }
     {
         StageTimer t(st, kStBlendFwd);
         FrameGeom f{cam->width, pa.rows, pa.tiles_x, pa.tiles_y, 0u, pa.model == OMNIGS_CAMERA_ERP};
         HIP_TRY(launch_blend_forward(f, gst.rec, gst.depth, inst_gauss, ranges, make_blend_settings(s), out->image,
-                                     out->final_T, out->n_contrib, out->n_blended, out->depth, order, tile_work, st));
+                                     out->final_T, out->n_contrib, out->n_blended, out->depth, order, tile_work,
+                                     inst_cap, st));
     }
     state->n = n;
     state->n_instances = M;

@@ -227,10 +227,13 @@ struct BlendSettings {
 // The forward writes each tile's largest contributor count (the backward's
 // walk length) to tile_work (may be null).  With depth_out, the depth image
 // from the per-record depth values rdepth.
+// Whether launch_blend_forward with `instances` instances over `tiles`
+// tiles wants the longest-first launch order (else order may be null).
+bool forward_uses_order(uint64_t instances, uint32_t tiles);
 hipError_t launch_blend_forward(const FrameGeom &f, const BlendRecord *rec, const float *rdepth,
                                 const uint32_t *inst_gauss, const uint2 *ranges, const BlendSettings &s, float *image,
                                 float *final_T, int32_t *n_contrib, int32_t *n_blended, float *depth_out,
-                                const uint32_t *order, uint32_t *tile_work, hipStream_t st);
+                                const uint32_t *order, uint32_t *tile_work, uint64_t instances, hipStream_t st);
 // Forward blend of several images in one launch over their concatenated
 // tile space (frames[k].tile_base ascending, total_tiles in all).
 hipError_t launch_blend_forward_frames(const FrameGeom *frames, const omnigs_image_out *outs, int count,

@@ -4,16 +4,17 @@
 // t_z).
 //
 // Instead of one wide (tile | depth) key sort over all M instances, the
-// order is built in two narrow stable sorts:
+// order is built from two narrow stable sorts:
 //   1. the N Gaussians are sorted by the float bits of t_r (4 passes over N);
-//   2. instances are emitted in that depth order (a scan of tiles-per-
-//      Gaussian in depth order gives each Gaussian its output range; every
-//      block writes a fixed span of consecutive outputs, coalesced), then
-//      stably radix-sorted on the tile id alone (ceil(log2 tiles / 8)
-//      passes over M).
+//   2. one entry per (Gaussian, touched block of 8x8 tiles) is emitted in
+//      that depth order (a scan of the block counts in depth order gives
+//      each Gaussian its output range; every emit workgroup writes a fixed
+//      span of consecutive outputs), then the S entries are stably
+//      radix-sorted on the block id alone (ceil(log2 blocks / 8) passes);
+//      bin.hip expands each block's list into the lists of its tiles.
 // The result is each tile's list in (t_r, Gaussian id) order, identical to a
-// sort on (tile, t_r, id), with ~4x less traffic than a 6-pass 64-bit key
-// sort over M.
+// sort on (tile, t_r, id), at a fraction of the traffic of a 64-bit key sort
+// over M.
 //
 // The LSD radix sort uses 8-bit digits and one kernel per pass after a
 // single histogram kernel (the one-sweep scheme of Adinets and Merrill,
@@ -22,8 +23,9 @@
 // matches (8 ballots per key, wave64), publishes its per-digit counts, takes
 // the counts of all earlier blocks from their published words (decoupled
 // lookback), places its keys in LDS in digit order and writes them out as
-// contiguous per-digit runs.  A sort is a clear, the histogram and the
-// passes: no scan kernels between passes.
+// contiguous per-digit runs.  A sort is a clear of its counters (or the
+// caller's shared clear), the histogram and the passes: no scan kernels
+// between passes.  The exclusive scan below uses the same lookback.
 #include "internal.h"
 
 #include <algorithm>
