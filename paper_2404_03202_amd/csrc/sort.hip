@@ -569,16 +569,27 @@ __global__ __launch_bounds__(kThreads) void k_tile_ranges(const uint32_t *inst_t
 }
 
 // Region blockIdx.y of the list, grid-strided in x.
+// Sets words [i, i + 4) of p[0, n) to v: one 16-byte store when they lie
+// inside and p + i is 16-byte aligned, else word by word.
+__device__ inline void fill4(uint32_t *p, int64_t n, int64_t i, uint32_t v) {
+    if (i + 4 <= n && ((reinterpret_cast<uintptr_t>(p + i) & 15u) == 0)) {
+        *reinterpret_cast<uint4 *>(p + i) = make_uint4(v, v, v, v);
+    } else {
+        for (int64_t k = i; k < i + 4 && k < n; ++k) p[k] = v;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_clear_list(ClearList L) {
     const int r = blockIdx.y;
     uint32_t *p = L.p[r];
     const int64_t n = L.n[r];
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = 0u;
+    for (int64_t i = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4; i < n; i += (int64_t)gridDim.x * 1024)
+        fill4(p, n, i, 0u);
 }
 
 __global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
+    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (i < n) fill4(p, n, i, v);
 }
 
 int64_t blocks_for(int64_t n, int64_t per) { return (n + per - 1) / per; }
@@ -598,7 +609,7 @@ int64_t scan_clear_words(int64_t n) {
 hipError_t scan_exclusive(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *total, void *scratch,
                           hipStream_t st, const uint32_t *gather, bool cleared) {
     if (n <= 0) {
-        if (total) hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, total, 0u, (int64_t)1);
+        if (total) launch_fill_u32(total, 0u, 1, st);
         return hipGetLastError();
     }
     const int64_t nb = blocks_for(n, kScanTile);
@@ -610,8 +621,7 @@ hipError_t scan_exclusive(const uint32_t *in, uint32_t *out, int64_t n, uint32_t
     uint32_t *ticket = reinterpret_cast<uint32_t *>(status + nb);
     const int64_t words = scan_clear_words(n);
     if (!cleared)
-        hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks_for(words, 256)), dim3(256), 0, st,
-                           reinterpret_cast<uint32_t *>(status), 0u, words);
+        launch_fill_u32(reinterpret_cast<uint32_t *>(status), 0u, words, st);
     hipLaunchKernelGGL(k_scan_lookback, dim3((unsigned)nb), dim3(kThreads), 0, st, in, gather, out, n, status, ticket,
                        total);
     return hipGetLastError();
@@ -636,8 +646,7 @@ hipError_t radix_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in, ui
     if (key_ranges && (bits > kRadixBits || n_ranges > kBins)) return hipErrorInvalidValue;
     if (n <= 0) {
         if (key_ranges && n_ranges > 0)
-            hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks_for(2 * n_ranges, 256)), dim3(256), 0, st,
-                               reinterpret_cast<uint32_t *>(key_ranges), 0u, (int64_t)2 * n_ranges);
+            launch_fill_u32(reinterpret_cast<uint32_t *>(key_ranges), 0u, (int64_t)2 * n_ranges, st);
         return hipGetLastError();
     }
     if (n >= (int64_t)kCountMask) return hipErrorInvalidValue;  // lookback words hold count + 1 in 31 bits
@@ -651,7 +660,7 @@ hipError_t radix_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in, ui
     uint32_t *status = head + kHeadWords;
     const int64_t words = sort_clear_words(n, bits);
     if (!cleared)
-        hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks_for(words, 256)), dim3(256), 0, st, head, 0u, words);
+        launch_fill_u32(head, 0u, words, st);
     const int64_t hist_blocks = std::min<int64_t>(blocks_for(n, kHistChunk), kHistMaxBlocks);
     hipLaunchKernelGGL(k_sort_hist, dim3((unsigned)hist_blocks), dim3(kThreads), 0, st, keys_in, n, n_dev, passes,
                        bits, ghist);
@@ -676,14 +685,14 @@ hipError_t launch_clear(const ClearList &L, hipStream_t st) {
     if (L.count == 0) return hipSuccess;
     int64_t most = 0;
     for (int k = 0; k < L.count; ++k) most = std::max(most, L.n[k]);
-    const unsigned bx = (unsigned)std::min<int64_t>(blocks_for(most, 256), 2048);
+    const unsigned bx = (unsigned)std::min<int64_t>(blocks_for(most, 1024), 2048);
     hipLaunchKernelGGL(k_clear_list, dim3(bx, (unsigned)L.count), dim3(256), 0, st, L);
     return hipGetLastError();
 }
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks_for(n, 256)), dim3(256), 0, st, p, v, n);
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks_for(n, 1024)), dim3(256), 0, st, p, v, n);
     return hipGetLastError();
 }
 
