@@ -13,16 +13,32 @@ constexpr int kL1Threads = 256;
 
 // Grid-stride pass with a fixed grid: every element lands in the same
 // thread's partial on every run, so the reduction order is fixed.
+// kVec: image, target and grad are 16-byte aligned and the grid strides over
+// float4 groups (the last count % 4 elements by the first threads).
+template <bool kVec>
 __global__ __launch_bounds__(kL1Threads) void k_l1_partial(const float *image, const float *target, int64_t count,
                                                             float *grad, double *partial) {
     __shared__ double red[kL1Threads];
     const float inv = (float)(1.0 / (double)count);
+    auto sgn = [inv](float r) { return r > 0.0f ? inv : (r < 0.0f ? -inv : 0.0f); };
     double s = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * kL1Threads + threadIdx.x; i < count;
-         i += (int64_t)kL1Blocks * kL1Threads) {
+    const int64_t tid = (int64_t)blockIdx.x * kL1Threads + threadIdx.x, stride = (int64_t)kL1Blocks * kL1Threads;
+    int64_t i = tid;
+    if (kVec) {
+        const int64_t n4 = count / 4;
+        for (int64_t q = tid; q < n4; q += stride) {
+            const float4 x = reinterpret_cast<const float4 *>(image)[q];
+            const float4 y = reinterpret_cast<const float4 *>(target)[q];
+            const float r0 = x.x - y.x, r1 = x.y - y.y, r2 = x.z - y.z, r3 = x.w - y.w;
+            s += (double)fabsf(r0) + (double)fabsf(r1) + (double)fabsf(r2) + (double)fabsf(r3);
+            if (grad) reinterpret_cast<float4 *>(grad)[q] = make_float4(sgn(r0), sgn(r1), sgn(r2), sgn(r3));
+        }
+        i = 4 * n4 + tid;
+    }
+    for (; i < count; i += stride) {
         const float r = image[i] - target[i];
         s += (double)fabsf(r);
-        if (grad) grad[i] = r > 0.0f ? inv : (r < 0.0f ? -inv : 0.0f);
+        if (grad) grad[i] = sgn(r);
     }
     red[threadIdx.x] = s;
     __syncthreads();
@@ -417,7 +433,13 @@ size_t l1_scratch_bytes() { return kL1Blocks * sizeof(double); }
 hipError_t launch_l1(const float *image, const float *target, int64_t count, float *grad, float *loss, void *scratch,
                      hipStream_t st) {
     double *partial = static_cast<double *>(scratch);
-    hipLaunchKernelGGL(k_l1_partial, dim3(kL1Blocks), dim3(kL1Threads), 0, st, image, target, count, grad, partial);
+    auto aligned = [](const void *q) { return (reinterpret_cast<uintptr_t>(q) & 15u) == 0; };
+    if (aligned(image) && aligned(target) && (!grad || aligned(grad)))
+        hipLaunchKernelGGL(k_l1_partial<true>, dim3(kL1Blocks), dim3(kL1Threads), 0, st, image, target, count, grad,
+                           partial);
+    else
+        hipLaunchKernelGGL(k_l1_partial<false>, dim3(kL1Blocks), dim3(kL1Threads), 0, st, image, target, count, grad,
+                           partial);
     hipLaunchKernelGGL(k_l1_final, dim3(1), dim3(kL1Threads), 0, st, partial, count, loss);
     return hipGetLastError();
 }

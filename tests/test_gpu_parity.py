@@ -142,13 +142,20 @@ def test_seam_roll_symmetry_gpu():
         assert np.abs(img - np.roll(base, k, axis=2)).max() <= 1e-4
 
 
-def test_l1_loss_kernel():
+@pytest.mark.parametrize("shape,offset", [((3, 100, 64), 0), ((3, 37, 41), 0), ((3, 37, 41), 1)])
+def test_l1_loss_kernel(shape, offset):
+    """16-byte groups with a ragged tail (count not a multiple of 4), and
+    inputs at an odd float offset (the word-by-word path)."""
     rng = np.random.default_rng(3)
-    a = rng.normal(size=(3, 100, 64)).astype(np.float32)
-    b = rng.normal(size=(3, 100, 64)).astype(np.float32)
-    b[0, 0, :7] = a[0, 0, :7]
-    loss, grad = B.omnigs_l1_loss(torch.from_numpy(a).to(DEV), torch.from_numpy(b).to(DEV))
-    ref, gref = O.l1(a, b)
+    n = int(np.prod(shape))
+    af = rng.normal(size=n + offset).astype(np.float32)
+    bf = rng.normal(size=n + offset).astype(np.float32)
+    bf[offset:offset + 7] = af[offset:offset + 7]  # exact zeros of the residual
+    a, b = af[offset:].reshape(shape), bf[offset:].reshape(shape)
+    ta = torch.from_numpy(af).to(DEV)[offset:].view(shape)
+    tb = torch.from_numpy(bf).to(DEV)[offset:].view(shape)
+    loss, grad = B.omnigs_l1_loss(ta, tb)
+    ref, gref = O.l1(a.astype(np.float64), b.astype(np.float64))
     assert float(loss) == pytest.approx(ref, rel=1e-6)
     np.testing.assert_array_equal(np_(grad), gref.astype(np.float32))
 
