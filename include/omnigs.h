@@ -259,9 +259,9 @@ omnigs_status omnigs_photometric_loss(const float *image, const float *target, i
  * mixed resolutions) over one resident Gaussian set: the path of
  * omnigs_forward (Sec. 3.2-3.3) run once for all of them.  One projection
  * launch covers every (camera, Gaussian) pair; one depth sort orders all of
- * them; instances are emitted into the concatenation of the cameras' tile
- * spaces (camera b's tiles follow those of cameras 0..b-1), so one tile sort
- * and one blend launch serve the whole batch.  A tile's list holds the same
+ * them; block entries and instances are emitted into the concatenation of
+ * the cameras' block and tile spaces (camera b's follow those of cameras
+ * 0..b-1), so one binning pass and one blend launch serve the whole batch.  A tile's list holds the same
  * records in the same order as when its camera is rendered alone, so every
  * output equals that of omnigs_forward for the camera, bit for bit.
  * cams[b] (host) and outs[b] (device, caller-allocated) per camera.

@@ -4,7 +4,8 @@ Requests (an ERP camera pose and resolution) arrive over time.  The server
 keeps `slots` batches in flight, each on its own HIP stream (default
 priority).  Whenever a slot is free, it forms a batch from the requests that
 have arrived (FIFO, at most `max_batch`, at most `max_tiles` 16x16 tiles in
-all -- 2^16 keeps the batch's tile ids to two 8-bit radix passes -- and only
+all -- larger batches of big images were measured slower than rendering
+them one by one -- and only
 while the estimated HBM footprint of everything in flight stays within
 `hbm_budget`), and enqueues it
 with one omnigs_forward_batch call in capacity mode: the instance buffers are
