@@ -88,6 +88,10 @@ EDGE = {
     "long_lists": lambda: (scenes.shell_scene(53, 6000, r0=2, r1=4, scale_lo=0.1, scale_hi=0.6), scenes.camera(64, 32)),
     "single_tile_image": lambda: (scenes.shell_scene(54, 300), scenes.camera(16, 16)),
     "odd_n": lambda: (scenes.shell_scene(55, 4097), scenes.camera(128, 64, scenes.rot_y(2.0).T, [0.3, -0.4, 0.2])),
+    # ~4900 instances per tile: above 3000 the forward runs two waves per
+    # tile and launches the tiles in index order
+    "very_long_lists": lambda: (scenes.shell_scene(56, 16000, r0=2, r1=4, scale_lo=0.2, scale_hi=0.8),
+                                scenes.camera(64, 32)),
 }
 
 
@@ -194,6 +198,41 @@ def test_backward_small(degree):
     cam = scenes.camera(128, 64, scenes.rot_y(0.8).T, [0.2, -0.1, 0.3])
     rep = compare_backward(g, cam, scenes.perturbed(90 + degree, g), settings=dict(bg=(0.1, 0.2, 0.3)))
     print("backward small", degree, rep)
+
+
+@pytest.mark.parametrize("case", sorted(EDGE))
+def test_backward_edge_cases(case):
+    g, cam = EDGE[case]()
+    if case == "very_long_lists":
+        fwd = B.omnigs_forward(to_dev(g), cam)
+        torch.cuda.synchronize()
+        tiles = -(-cam["width"] // 16) * -(-cam["height"] // 16)
+        assert fwd.n_instances > 3000 * tiles, fwd.n_instances
+    rep = compare_backward(g, cam, scenes.perturbed(100, g), settings=dict(bg=(0.1, 0.3, 0.2)))
+    print("backward edge", case, rep)
+
+
+def test_backward_empty_and_culled():
+    """No Gaussians: nothing to return.  Gaussians that reach no tile: every
+    gradient is zero (the blend walks no list; the chain writes zeros)."""
+    cam = scenes.camera(64, 32)
+    empty = to_dev(dict(means=np.zeros((0, 3)), scales=np.zeros((0, 3)), quats=np.zeros((0, 4)),
+                        opacities=np.zeros(0), sh=np.zeros((0, 16, 3)), sh_degree=3))
+    dl = torch.full((3, 32, 64), 0.5, device=DEV)
+    fwd = B.omnigs_forward(empty, cam)
+    grads = B.omnigs_backward(empty, cam, None, fwd, dl)
+    torch.cuda.synchronize()
+    assert all(v.numel() == 0 for v in grads.values())
+    g = scenes.shell_scene(71, 500)
+    g["opacities"][:] = 1.0 / 300.0        # below alpha_min: never visible
+    g["means"][:250] *= 0.01               # inside the near sphere
+    gd = to_dev(g)
+    fwd = B.omnigs_forward(gd, cam)
+    grads = B.omnigs_backward(gd, cam, None, fwd, dl)
+    torch.cuda.synchronize()
+    assert fwd.n_instances == 0
+    for k, v in grads.items():
+        assert v.shape[0] == 500 and float(v.abs().max()) == 0.0, k
 
 
 def test_backward_config1():
