@@ -558,6 +558,30 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, co
 // (work, backward).
 constexpr int kOrderBuckets = 4096;
 constexpr int kOrderThreads = 1024;
+constexpr int kOrderChunk = 8;  // tiles whose work one thread loads at once
+
+// Buckets of the tiles t0 + c * kOrderThreads, c < kOrderChunk: the loads go
+// out together (indices clamped to the last tile, so none is predicated
+// away), then tiles past ntiles are marked with kOrderBuckets.
+__device__ __forceinline__ void order_buckets(const uint2 *ranges, const uint32_t *work, uint32_t ntiles,
+                                              uint32_t t0, uint32_t bk[kOrderChunk]) {
+    uint32_t wk[kOrderChunk];
+    if (work) {
+#pragma unroll
+        for (int c = 0; c < kOrderChunk; ++c) wk[c] = work[min(t0 + (uint32_t)(c * kOrderThreads), ntiles - 1u)];
+    } else {
+        uint2 r[kOrderChunk];
+#pragma unroll
+        for (int c = 0; c < kOrderChunk; ++c) r[c] = ranges[min(t0 + (uint32_t)(c * kOrderThreads), ntiles - 1u)];
+#pragma unroll
+        for (int c = 0; c < kOrderChunk; ++c) wk[c] = r[c].y - r[c].x;
+    }
+#pragma unroll
+    for (int c = 0; c < kOrderChunk; ++c)
+        bk[c] = t0 + (uint32_t)(c * kOrderThreads) < ntiles
+                    ? (uint32_t)(kOrderBuckets - 1) - min(wk[c], (uint32_t)(kOrderBuckets - 1))
+                    : (uint32_t)kOrderBuckets;
+}
 
 __global__ __launch_bounds__(kOrderThreads) void k_tile_order(const uint2 *ranges, const uint32_t *work,
                                                               uint32_t ntiles, uint32_t *order) {
@@ -565,11 +589,13 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(const uint2 *range
     __shared__ uint32_t wave_tot[kOrderThreads / kWave];
     for (int b = threadIdx.x; b < kOrderBuckets; b += kOrderThreads) cnt[b] = 0;
     __syncthreads();
-    auto bucket = [&](uint32_t t) {
-        const uint32_t wk = work ? work[t] : ranges[t].y - ranges[t].x;
-        return (uint32_t)(kOrderBuckets - 1) - min(wk, (uint32_t)(kOrderBuckets - 1));
-    };
-    for (uint32_t t = threadIdx.x; t < ntiles; t += kOrderThreads) atomicAdd(&cnt[bucket(t)], 1u);
+    for (uint32_t t0 = threadIdx.x; t0 < ntiles; t0 += kOrderThreads * kOrderChunk) {
+        uint32_t bk[kOrderChunk];
+        order_buckets(ranges, work, ntiles, t0, bk);
+#pragma unroll
+        for (int c = 0; c < kOrderChunk; ++c)
+            if (bk[c] < kOrderBuckets) atomicAdd(&cnt[bk[c]], 1u);
+    }
     __syncthreads();
     // exclusive scan of the bucket counts: 4 per thread, then across waves
     constexpr int kPer = kOrderBuckets / kOrderThreads;
@@ -596,7 +622,13 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(const uint2 *range
         run += v[k];
     }
     __syncthreads();
-    for (uint32_t t = threadIdx.x; t < ntiles; t += kOrderThreads) order[atomicAdd(&cnt[bucket(t)], 1u)] = t;
+    for (uint32_t t0 = threadIdx.x; t0 < ntiles; t0 += kOrderThreads * kOrderChunk) {
+        uint32_t bk[kOrderChunk];
+        order_buckets(ranges, work, ntiles, t0, bk);
+#pragma unroll
+        for (int c = 0; c < kOrderChunk; ++c)
+            if (bk[c] < kOrderBuckets) order[atomicAdd(&cnt[bk[c]], 1u)] = t0 + (uint32_t)(c * kOrderThreads);
+    }
 }
 
 float period_of(const FrameGeom &f) { return f.wrap ? (float)f.width : __builtin_huge_valf(); }
