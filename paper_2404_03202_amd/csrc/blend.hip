@@ -234,8 +234,9 @@ __device__ __forceinline__ int slot_px(int w, int s, int lx) { return (((w * (kQ
 template <int kW>
 __device__ __forceinline__ int slot_py(int w, int s, int ly) { return (((w * (kQuads / kW)) + s) >> 1) * 8 + ly; }
 
-// kDepth: also the depth image sum_i d_i alpha_i T_i.
-template <int kW, bool kBatched, bool kDepth>
+// kDepth: also the depth image sum_i d_i alpha_i T_i.  kCount: also the
+// number of instances blended per pixel (only when a frame asks for it).
+template <int kW, bool kBatched, bool kDepth, bool kCount>
 __global__ __launch_bounds__(kWave * kW) void k_blend_forward(FrameTable FT, const BlendRecord *rec,
                                                                const float *rdepth, const uint32_t *inst_gauss,
                                                                const uint2 *ranges, BlendSettings s,
@@ -300,7 +301,7 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_forward(FrameTable FT, con
                 if (kDepth) Dp[k] = __builtin_fmaf(dj, wgt, Dp[k]);
                 T[k] = take ? Tn : T[k];
                 last[k] = take ? base + j + 1 : last[k];
-                blended[k] += take ? 1 : 0;
+                if (kCount) blended[k] += take ? 1 : 0;
             }
             if ((t & 15) == 15 && __ballot(done != kAll) == 0ull) break;
         }
@@ -330,7 +331,7 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_forward(FrameTable FT, con
         F.image[2 * HW + p] = __builtin_fmaf(T[k], s.bg[2], C2[k]);
         F.final_T[p] = T[k];
         F.n_contrib[p] = last[k];
-        if (F.n_blended) F.n_blended[p] = blended[k];
+        if (kCount && F.n_blended) F.n_blended[p] = blended[k];
         if (kDepth) F.depth[p] = Dp[k];
     }
 }
@@ -646,12 +647,20 @@ template <int kW>
 void launch_forward_waves(const FrameTable &T, unsigned tiles, const BlendRecord *rec, const float *rdepth,
                           const uint32_t *inst_gauss, const uint2 *ranges, const BlendSettings &s, bool depth,
                           const uint32_t *order, uint32_t *tile_work, hipStream_t st) {
-    if (depth)
-        hipLaunchKernelGGL((k_blend_forward<kW, false, true>), dim3(tiles), dim3(kWave * kW), 0, st, T, rec, rdepth,
+    const float *rd = depth ? rdepth : nullptr;
+    const bool count = T.f[0].n_blended != nullptr;
+    if (depth && count)
+        hipLaunchKernelGGL((k_blend_forward<kW, false, true, true>), dim3(tiles), dim3(kWave * kW), 0, st, T, rec, rd,
                            inst_gauss, ranges, s, order, tile_work);
+    else if (depth)
+        hipLaunchKernelGGL((k_blend_forward<kW, false, true, false>), dim3(tiles), dim3(kWave * kW), 0, st, T, rec,
+                           rd, inst_gauss, ranges, s, order, tile_work);
+    else if (count)
+        hipLaunchKernelGGL((k_blend_forward<kW, false, false, true>), dim3(tiles), dim3(kWave * kW), 0, st, T, rec,
+                           rd, inst_gauss, ranges, s, order, tile_work);
     else
-        hipLaunchKernelGGL((k_blend_forward<kW, false, false>), dim3(tiles), dim3(kWave * kW), 0, st, T, rec,
-                           (const float *)nullptr, inst_gauss, ranges, s, order, tile_work);
+        hipLaunchKernelGGL((k_blend_forward<kW, false, false, false>), dim3(tiles), dim3(kWave * kW), 0, st, T, rec,
+                           rd, inst_gauss, ranges, s, order, tile_work);
 }
 
 // Mean instances per tile above which two waves per tile (two pixels per
@@ -692,24 +701,32 @@ hipError_t launch_blend_forward_frames(const FrameGeom *frames, const omnigs_ima
     if (total_tiles == 0) return hipSuccess;
     FrameTable T{};
     T.n = count;
-    bool any_depth = false;
+    bool any_depth = false, any_count = false;
     for (int k = 0; k < count; ++k) {
         const FrameGeom &f = frames[k];
         T.f[k] = BlendFrame{f.width, f.height, f.tiles_x, f.tiles_y, f.tile_base, period_of(f), outs[k].image,
                             outs[k].final_T, outs[k].n_contrib, outs[k].n_blended, nullptr, outs[k].depth,
                             nullptr, nullptr};
         any_depth |= outs[k].depth != nullptr;
+        any_count |= outs[k].n_blended != nullptr;
     }
     constexpr int kW = OMNIGS_FWD_WAVES;
     if (any_depth) {
         // every frame then needs a depth buffer
         for (int k = 0; k < count; ++k)
             if (!T.f[k].depth) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_blend_forward<kW, true, true>), dim3(total_tiles), dim3(kWave * kW), 0, st, T, rec,
-                           rdepth, inst_gauss, ranges, s, order, (uint32_t *)nullptr);
+        if (any_count)
+            hipLaunchKernelGGL((k_blend_forward<kW, true, true, true>), dim3(total_tiles), dim3(kWave * kW), 0, st, T,
+                               rec, rdepth, inst_gauss, ranges, s, order, (uint32_t *)nullptr);
+        else
+            hipLaunchKernelGGL((k_blend_forward<kW, true, true, false>), dim3(total_tiles), dim3(kWave * kW), 0, st,
+                               T, rec, rdepth, inst_gauss, ranges, s, order, (uint32_t *)nullptr);
+    } else if (any_count) {
+        hipLaunchKernelGGL((k_blend_forward<kW, true, false, true>), dim3(total_tiles), dim3(kWave * kW), 0, st, T,
+                           rec, (const float *)nullptr, inst_gauss, ranges, s, order, (uint32_t *)nullptr);
     } else {
-        hipLaunchKernelGGL((k_blend_forward<kW, true, false>), dim3(total_tiles), dim3(kWave * kW), 0, st, T, rec,
-                           (const float *)nullptr, inst_gauss, ranges, s, order, (uint32_t *)nullptr);
+        hipLaunchKernelGGL((k_blend_forward<kW, true, false, false>), dim3(total_tiles), dim3(kWave * kW), 0, st, T,
+                           rec, (const float *)nullptr, inst_gauss, ranges, s, order, (uint32_t *)nullptr);
     }
     return hipGetLastError();
 }
