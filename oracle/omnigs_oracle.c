@@ -102,6 +102,10 @@ typedef struct {
     double fx, fy, cx, cy; /* pinhole intrinsics of Eq. 2 (pixels)         */
     int32_t rows;         /* rendered rows: the top `rows` rows (0: all)   */
     int32_t reserved2;
+    /* [n][2] pixel offsets added to each projected centre p (NULL: none).
+     * Not part of the method: it lets a finite difference move p alone, with
+     * the 2D covariance, colour and depth held, to check dL/dp and dL/ds. */
+    const double *screen_shift;
 } orc_scene;
 
 /* rows of the rendered image */
@@ -319,6 +323,10 @@ static void project_one(const orc_scene *s, int64_t i, orc_proj *P) {
         P->J[4] = ky * P->rho / r2;
         P->J[5] = -ky * tz * ty / (r2 * P->rho);
         for (int k = 0; k < 6; ++k) P->Jp[k] = P->J[k];
+    }
+    if (s->screen_shift) {
+        P->px += s->screen_shift[2 * i];
+        P->py += s->screen_shift[2 * i + 1];
     }
     /* M = J W */
     for (int a = 0; a < 2; ++a)
@@ -556,73 +564,116 @@ static double wrap_dx(double d, double W) {
     return d;
 }
 
-/* flip: index of the flagged decision to invert (-1: none).
- * contrib (may be NULL) receives the blended instances in order. */
-static void render_pixel(const orc_scene *s, const orc_lists *L, int64_t start, int64_t end, int x, int y,
-                         int flip, orc_pixel *out, orc_contrib *contrib) {
-    double T = 1.0, C[3] = {0, 0, 0}, D = 0.0;
-    int32_t last = 0, nflag = 0, ngflag = 0, ncon = 0;
-    uint64_t sig = 1469598103934665603ull;
+/* alpha of one Gaussian at pixel (x, y) (Eq. 7, 8): the pixel offset (the
+ * shortest one across the seam for the ERP image), G, and the alpha before
+ * and after the alpha_max clamp */
+typedef struct {
+    double dx, dy, G, araw, alpha;
+} orc_eval;
+
+static void eval_at(const orc_scene *s, const orc_proj *P, double opac, int x, int y, orc_eval *e) {
     const double W = (double)s->width;
-    for (int64_t k = start; k < end; ++k) {
+    e->dx = s->model == ORC_PINHOLE ? (x + 0.5) - P->px : wrap_dx((x + 0.5) - P->px, W);
+    e->dy = (y + 0.5) - P->py;
+    const double power = -0.5 * (P->Q[0] * e->dx * e->dx + 2.0 * P->Q[1] * e->dx * e->dy + P->Q[2] * e->dy * e->dy);
+    e->G = exp(power);
+    e->araw = opac * e->G;
+    e->alpha = e->araw < s->alpha_max ? e->araw : s->alpha_max;
+}
+
+/* state of one pixel's front-to-back walk */
+typedef struct {
+    double T, C[3], D;
+    int32_t last, nflag, ngflag, ncon, stopped;
+    uint64_t sig;
+    uint64_t flips; /* bit j set: the j-th flagged decision of the walk goes the other way */
+} orc_walk;
+
+/* the decision of the walk's next flagged decision: taken as computed, or
+ * inverted when its bit of flips is set */
+static int flagged(orc_walk *w, int decision) {
+    const int inv = w->nflag < 64 && ((w->flips >> w->nflag) & 1u);
+    ++w->nflag;
+    ++w->ngflag;
+    return inv ? !decision : decision;
+}
+
+/* one instance met at walk position pos (0-based in the tile list): skip
+ * below alpha_min, stop before T would drop below T_min, else blend (Eq. 6) */
+static void walk_one(const orc_scene *s, const orc_proj *P, int32_t gid, const orc_eval *e, int64_t pos,
+                     orc_walk *w, orc_contrib *contrib) {
+    int pass = e->alpha >= s->alpha_min;
+    if (fabs(e->araw / s->alpha_min - 1.0) < s->flag_rel_alpha) pass = flagged(w, pass);
+    if (!pass) return;
+    if (fabs(e->araw / s->alpha_max - 1.0) < s->flag_rel_alpha) ++w->ngflag;
+    const double Tn = w->T * (1.0 - e->alpha);
+    int stop = Tn < s->T_min;
+    if (fabs(Tn / s->T_min - 1.0) < s->flag_rel_T) stop = flagged(w, stop);
+    if (stop) {
+        w->sig = fnv(w->sig, 0xffffffffull);
+        w->stopped = 1;
+        return;
+    }
+    if (contrib) {
+        orc_contrib *c = &contrib[w->ncon];
+        c->gid = gid;
+        c->dx = e->dx;
+        c->dy = e->dy;
+        c->G = e->G;
+        c->alpha_raw = e->araw;
+        c->alpha = e->alpha;
+        c->T = w->T;
+    }
+    ++w->ncon;
+    w->sig = fnv(w->sig, ((uint64_t)(uint32_t)gid << 1) | (uint64_t)(e->araw >= s->alpha_max));
+    for (int ch = 0; ch < 3; ++ch) w->C[ch] += P->rgb[ch] * e->alpha * w->T;
+    w->D += P->depth * e->alpha * w->T;
+    w->T = Tn;
+    w->last = (int32_t)(pos + 1);
+}
+
+/* flips: bit j inverts the j-th flagged decision met along the walk (0: the
+ * FP64 decisions).  Flagged decisions: alpha within a relative margin of
+ * alpha_min, T(1 - alpha) within one of T_min, and the order of two list
+ * neighbours whose depths agree to within the float32 resolution of the
+ * depth key when this pixel may blend both (inverted: the pair is walked
+ * swapped).  contrib (may be NULL) receives the blended instances in order. */
+static void render_pixel(const orc_scene *s, const orc_lists *L, int64_t start, int64_t end, int x, int y,
+                         uint64_t flips, orc_pixel *out, orc_contrib *contrib) {
+    orc_walk w;
+    memset(&w, 0, sizeof(w));
+    w.T = 1.0;
+    w.sig = 1469598103934665603ull;
+    w.flips = flips;
+    const double lo = s->alpha_min * (1.0 - s->flag_rel_alpha);
+    for (int64_t k = start; k < end && !w.stopped;) {
         const orc_inst *I = &L->inst[k];
         const orc_proj *P = &L->P[I->gid];
-        const double dx = s->model == ORC_PINHOLE ? (x + 0.5) - P->px : wrap_dx((x + 0.5) - P->px, W);
-        const double dy = (y + 0.5) - P->py;
-        const double power = -0.5 * (P->Q[0] * dx * dx + 2.0 * P->Q[1] * dx * dy + P->Q[2] * dy * dy);
-        const double G = exp(power);
-        const double araw = s->opac[I->gid] * G;
-        const double alpha = araw < s->alpha_max ? araw : s->alpha_max;
-        int pass = alpha >= s->alpha_min;
-        if (fabs(araw / s->alpha_min - 1.0) < s->flag_rel_alpha) {
-            if (nflag == flip) pass = !pass;
-            ++nflag;
-            ++ngflag;
+        orc_eval e;
+        eval_at(s, P, s->opac[I->gid], x, y, &e);
+        if (k + 1 < end && e.araw >= lo && fabs(L->inst[k + 1].tr / I->tr - 1.0) < s->flag_rel_depth) {
+            const orc_inst *J = &L->inst[k + 1];
+            const orc_proj *PJ = &L->P[J->gid];
+            orc_eval f;
+            eval_at(s, PJ, s->opac[J->gid], x, y, &f);
+            if (f.araw >= lo && flagged(&w, 0)) {
+                walk_one(s, PJ, J->gid, &f, k - start, &w, contrib);
+                if (!w.stopped) walk_one(s, P, I->gid, &e, k + 1 - start, &w, contrib);
+                k += 2;
+                continue;
+            }
         }
-        if (!pass) continue;
-        if (fabs(araw / s->alpha_max - 1.0) < s->flag_rel_alpha) ++ngflag;
-        /* depth near-tie with a neighbour in the sorted list */
-        if ((k > start && fabs(L->inst[k - 1].tr / I->tr - 1.0) < s->flag_rel_depth) ||
-            (k + 1 < end && fabs(L->inst[k + 1].tr / I->tr - 1.0) < s->flag_rel_depth)) {
-            ++nflag;
-            ++ngflag;
-        }
-        const double Tn = T * (1.0 - alpha);
-        int stop = Tn < s->T_min;
-        if (fabs(Tn / s->T_min - 1.0) < s->flag_rel_T) {
-            if (nflag == flip) stop = !stop;
-            ++nflag;
-            ++ngflag;
-        }
-        if (stop) {
-            sig = fnv(sig, 0xffffffffull);
-            break;
-        }
-        if (contrib) {
-            orc_contrib *c = &contrib[ncon];
-            c->gid = I->gid;
-            c->dx = dx;
-            c->dy = dy;
-            c->G = G;
-            c->alpha_raw = araw;
-            c->alpha = alpha;
-            c->T = T;
-        }
-        ++ncon;
-        sig = fnv(sig, ((uint64_t)(uint32_t)I->gid << 1) | (uint64_t)(araw >= s->alpha_max));
-        for (int ch = 0; ch < 3; ++ch) C[ch] += P->rgb[ch] * alpha * T;
-        D += P->depth * alpha * T;
-        T = Tn;
-        last = (int32_t)(k - start + 1);
+        walk_one(s, P, I->gid, &e, k - start, &w, contrib);
+        ++k;
     }
-    for (int ch = 0; ch < 3; ++ch) out->C[ch] = C[ch] + T * s->bg[ch];
-    out->D = D;
-    out->T = T;
-    out->n_contrib = last;
-    out->n_flags = nflag;
-    out->n_grad_flags = ngflag;
-    out->n_blended = ncon;
-    out->sig = sig;
+    for (int ch = 0; ch < 3; ++ch) out->C[ch] = w.C[ch] + w.T * s->bg[ch];
+    out->D = w.D;
+    out->T = w.T;
+    out->n_contrib = w.last;
+    out->n_flags = w.nflag;
+    out->n_grad_flags = w.ngflag;
+    out->n_blended = w.ncon;
+    out->sig = w.sig;
 }
 
 static int64_t tile_of_pixel(const orc_lists *L, int x, int y) {
@@ -703,14 +754,13 @@ int64_t orc_tile_lists(const orc_scene *s, const uint8_t *tile_mask, int64_t cap
 
 /* Forward render of the tiles set in tile_mask (NULL: all tiles; pixels of
  * other tiles are left untouched).  image [3][H][W], final_T [H][W], n_contrib [H][W],
- * n_flags [H][W]; alt (may be NULL) receives, for pixels with exactly one
- * flagged decision, the value with that decision inverted (else the value);
+ * n_flags [H][W] (flagged decisions met: see render_pixel and orc_branches);
  * n_grad_flags (may be NULL) also counts alpha_max-clamp near-ties, where
  * the gradient (not the value) changes; n_blended (may be NULL) counts the
  * instances blended into each pixel; depth (may be NULL) receives the depth
  * image. */
 int orc_render(const orc_scene *s, const uint8_t *tile_mask, double *image, double *final_T, int32_t *n_contrib,
-               int32_t *n_flags, double *alt, int32_t *n_grad_flags, int32_t *n_blended, double *depth) {
+               int32_t *n_flags, int32_t *n_grad_flags, int32_t *n_blended, double *depth) {
     if (!orc_valid(s)) return -1;
     orc_lists L;
     if (build_lists(s, tile_mask, &L) != 0) {
@@ -725,7 +775,7 @@ int orc_render(const orc_scene *s, const uint8_t *tile_mask, double *image, doub
         const int64_t t = tile_of_pixel(&L, x, y);
         if (tile_mask && !tile_mask[t]) continue;
         orc_pixel px;
-        render_pixel(s, &L, L.tstart[t], L.tend[t], x, y, -1, &px, NULL);
+        render_pixel(s, &L, L.tstart[t], L.tend[t], x, y, 0, &px, NULL);
         for (int ch = 0; ch < 3; ++ch) image[ch * HW + p] = px.C[ch];
         final_T[p] = px.T;
         n_contrib[p] = px.n_contrib;
@@ -733,18 +783,76 @@ int orc_render(const orc_scene *s, const uint8_t *tile_mask, double *image, doub
         if (n_grad_flags) n_grad_flags[p] = px.n_grad_flags;
         if (n_blended) n_blended[p] = px.n_blended;
         if (depth) depth[p] = px.D;
-        if (alt) {
-            if (px.n_flags == 1) {
-                orc_pixel q;
-                render_pixel(s, &L, L.tstart[t], L.tend[t], x, y, 0, &q, NULL);
-                for (int ch = 0; ch < 3; ++ch) alt[ch * HW + p] = q.C[ch];
-            } else {
-                for (int ch = 0; ch < 3; ++ch) alt[ch * HW + p] = px.C[ch];
-            }
-        }
     }
     lists_free(&L);
     return 0;
+}
+
+/* depth-first enumeration of the flip masks of one pixel: the walk with
+ * mask m meets some number f of flagged decisions; each of those past the
+ * highest bit of m may also go the other way */
+typedef struct {
+    const orc_scene *s;
+    const orc_lists *L;
+    int64_t start, end;
+    int x, y;
+    int32_t max_b, count;
+    double *image, *T;
+    int32_t *n_contrib, *n_blended;
+} orc_branch_ctx;
+
+static void explore(orc_branch_ctx *c, uint64_t mask, int hb) {
+    if (c->count > c->max_b) return;
+    orc_pixel px;
+    render_pixel(c->s, c->L, c->start, c->end, c->x, c->y, mask, &px, NULL);
+    if (c->count == c->max_b) {
+        c->count = c->max_b + 1; /* more branches than room: the caller excludes the pixel */
+        return;
+    }
+    const int b = c->count++;
+    for (int ch = 0; ch < 3; ++ch) c->image[3 * b + ch] = px.C[ch];
+    c->T[b] = px.T;
+    c->n_contrib[b] = px.n_contrib;
+    c->n_blended[b] = px.n_blended;
+    for (int j = hb + 1; j < px.n_flags && j < 64; ++j) explore(c, mask | (1ull << j), j);
+}
+
+/* Every result a pixel may take when its flagged decisions (alpha vs
+ * alpha_min, T vs T_min, the order of two near-tied depths) go either way,
+ * for the npix pixels pix[] (flat indices y * W + x of the rendered image;
+ * only their tiles need be set in tile_mask, NULL: all).  Per pixel, up to
+ * max_b branches: image [npix][max_b][3], final_T, n_contrib and n_blended
+ * [npix][max_b]; count[k] receives the number of branches (the first is the
+ * FP64 walk), or -1 when the pixel has more than max_b. */
+int orc_branches(const orc_scene *s, const uint8_t *tile_mask, int64_t npix, const int64_t *pix, int32_t max_b,
+                 int32_t *count, double *image, double *final_T, int32_t *n_contrib, int32_t *n_blended) {
+    if (!orc_valid(s) || max_b < 1) return -1;
+    orc_lists L;
+    if (build_lists(s, tile_mask, &L) != 0) {
+        lists_free(&L);
+        return -1;
+    }
+    const int Wd = s->width, Hd = orc_rows(s);
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(| : bad)
+    for (int64_t k = 0; k < npix; ++k) {
+        const int x = (int)(pix[k] % Wd), y = (int)(pix[k] / Wd);
+        if (pix[k] < 0 || y >= Hd) {
+            bad = 1;
+            continue;
+        }
+        const int64_t t = tile_of_pixel(&L, x, y);
+        if (tile_mask && !tile_mask[t]) {
+            bad = 1;
+            continue;
+        }
+        orc_branch_ctx c = {s, &L, L.tstart[t], L.tend[t], x, y, max_b, 0, image + k * max_b * 3,
+                            final_T + k * max_b, n_contrib + k * max_b, n_blended + k * max_b};
+        explore(&c, 0ull, -1);
+        count[k] = c.count > max_b ? -1 : c.count;
+    }
+    lists_free(&L);
+    return bad ? -1 : 0;
 }
 
 /* L1 loss sum over the pixels of the masked tiles: sum w |C - target| / (3HW)
@@ -769,7 +877,7 @@ int orc_l1_tiles(const orc_scene *s, const double *target, const double *weight,
         for (int y = ty * ORC_TILE; y < ty * ORC_TILE + ORC_TILE && y < Hd; ++y)
             for (int x = tx * ORC_TILE; x < tx * ORC_TILE + ORC_TILE && x < Wd; ++x) {
                 orc_pixel px;
-                render_pixel(s, &L, L.tstart[t], L.tend[t], x, y, -1, &px, NULL);
+                render_pixel(s, &L, L.tstart[t], L.tend[t], x, y, 0, &px, NULL);
                 const int64_t p = (int64_t)y * Wd + x;
                 sig = fnv(sig, px.sig);
                 for (int ch = 0; ch < 3; ++ch) {
@@ -975,9 +1083,8 @@ static void chain_one(const orc_scene *s, int64_t i, const orc_proj *P, const do
  * Gradient outputs are overwritten: dmeans [n][3], dscales [n][3],
  * dquats [n][4], dopac [n], dsh [n][sh_coeffs][3], dscreen [n][2].
  * acc_out (may be NULL): [n][10] screen-space accumulators.
- * abs_* (may all be NULL): sums of |per-pixel contributions|, each weighted
- * by 1 + the pixel's optical depth ln(1 / T_final), propagated through
- * |chain|: the scale against which float32 sums are judged. */
+ * abs_* (may all be NULL): sums of |per-pixel contributions| propagated
+ * through |chain|: the scale against which float32 sums are judged. */
 int orc_backward(const orc_scene *s, const uint8_t *tile_mask, const double *dLdC, const double *dLdD,
                  const double *dLdA, double *dmeans, double *dscales,
                  double *dquats, double *dopac, double *dsh, double *dscreen, double *acc_out, double *abs_means,
@@ -1021,18 +1128,10 @@ int orc_backward(const orc_scene *s, const uint8_t *tile_mask, const double *dLd
                 for (int x = tx * ORC_TILE; x < tx * ORC_TILE + ORC_TILE && x < Wd; ++x) {
                     const int64_t p = (int64_t)y * Wd + x;
                     orc_pixel px;
-                    render_pixel(s, &L, L.tstart[t], L.tend[t], x, y, -1, &px, con);
+                    render_pixel(s, &L, L.tstart[t], L.tend[t], x, y, 0, &px, con);
                     const int ncon = px.n_blended;
                     const double g[3] = {dLdC[p], dLdC[HW + p], dLdC[2 * HW + p]};
                     const double gD = dLdD ? dLdD[p] : 0.0, gA = dLdA ? dLdA[p] : 0.0;
-                    /* weight of this pixel's |contributions| in the abs
-                     * sums: 1 + its optical depth ln(1 / T_final).  A float32
-                     * alpha carries a relative error of ~1e-6 and the
-                     * transmittance in front of or behind an instance is a
-                     * product over the pixel's blended instances, so a float32
-                     * contribution's relative error grows with the optical
-                     * depth (at most ln(1 / T_min)). */
-                    const double wd = 1.0 + log(1.0 / px.T);
                     /* S = colour blended behind the current instance, plus
                      * the background seen through the final transmittance */
                     double Sb[3], SD = 0.0, SA = 0.0; /* depth and alpha: zero background */
@@ -1046,14 +1145,14 @@ int orc_backward(const orc_scene *s, const uint8_t *tile_mask, const double *dLd
                         for (int ch = 0; ch < 3; ++ch) {
                             const double term = g[ch] * c->alpha * c->T;
                             a[6 + ch] += term;
-                            aa[6 + ch] += fabs(term) * wd;
+                            aa[6 + ch] += fabs(term);
                             dalpha += g[ch] * (P->rgb[ch] * c->T - Sb[ch] / (1.0 - c->alpha));
                         }
                         for (int ch = 0; ch < 3; ++ch) Sb[ch] += P->rgb[ch] * c->alpha * c->T;
                         /* depth and alpha channels: colour d_i and 1 */
                         const double tD = gD * c->alpha * c->T;
                         a[9] += tD;
-                        aa[9] += fabs(tD) * wd;
+                        aa[9] += fabs(tD);
                         dalpha += gD * (P->depth * c->T - SD / (1.0 - c->alpha));
                         dalpha += gA * (c->T - SA / (1.0 - c->alpha));
                         SD += P->depth * c->alpha * c->T;
@@ -1067,12 +1166,12 @@ int orc_backward(const orc_scene *s, const uint8_t *tile_mask, const double *dLd
                         /* power depends on p through dx = x + 1/2 - p_x */
                         const double tpx = (P->Q[0] * c->dx + P->Q[1] * c->dy) * gpow;
                         const double tpy = (P->Q[1] * c->dx + P->Q[2] * c->dy) * gpow;
-                        a[0] += tpx; aa[0] += fabs(tpx) * wd;
-                        a[1] += tpy; aa[1] += fabs(tpy) * wd;
-                        a[2] += t0;  aa[2] += fabs(t0) * wd;
-                        a[3] += t1;  aa[3] += fabs(t1) * wd;
-                        a[4] += t2;  aa[4] += fabs(t2) * wd;
-                        a[5] += gO;  aa[5] += fabs(gO) * wd;
+                        a[0] += tpx; aa[0] += fabs(tpx);
+                        a[1] += tpy; aa[1] += fabs(tpy);
+                        a[2] += t0;  aa[2] += fabs(t0);
+                        a[3] += t1;  aa[3] += fabs(t1);
+                        a[4] += t2;  aa[4] += fabs(t2);
+                        a[5] += gO;  aa[5] += fabs(gO);
                     }
                 }
         }

@@ -91,6 +91,7 @@ class _Scene(ctypes.Structure):
         ("cy", ctypes.c_double),
         ("rows", ctypes.c_int32),
         ("reserved2", ctypes.c_int32),
+        ("screen_shift", ctypes.c_void_p),
     ]
 
 
@@ -107,8 +108,11 @@ def _load():
         _lib.orc_tile_lists.argtypes = [P(_Scene), ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p]
         _lib.orc_tile_lists.restype = ctypes.c_int64
-        _lib.orc_render.argtypes = [P(_Scene)] + [ctypes.c_void_p] * 9
+        _lib.orc_render.argtypes = [P(_Scene)] + [ctypes.c_void_p] * 8
         _lib.orc_render.restype = ctypes.c_int
+        _lib.orc_branches.argtypes = [P(_Scene), ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int32] + \
+            [ctypes.c_void_p] * 5
+        _lib.orc_branches.restype = ctypes.c_int
         _lib.orc_l1_tiles.argtypes = [P(_Scene)] + [ctypes.c_void_p] * 5
         _lib.orc_l1_tiles.restype = ctypes.c_int
         _lib.orc_backward.argtypes = [P(_Scene)] + [ctypes.c_void_p] * 17
@@ -164,6 +168,9 @@ class Scene:
             else (0.0, 0.0, 0.0, 0.0)
         self.settings = st
         self.flags = fl
+        # [N,2] pixel offsets added to the projected centres (None: none):
+        # moves p alone, for finite differences of dL/dp (not the method)
+        self.screen_shift = None
 
     @property
     def tiles_x(self):
@@ -214,6 +221,9 @@ class Scene:
         s.model = self.model
         s.fx, s.fy, s.cx, s.cy = self.intrinsics
         s.rows = self.rows
+        if self.screen_shift is not None:
+            self._shift = _f64(self.screen_shift).reshape(self.n, 2)
+            s.screen_shift = self._shift.ctypes.data
         return s
 
     def with_params(self, **kw):
@@ -265,31 +275,60 @@ def _mask(scene, tile_mask):
     return m
 
 
-def render(scene: Scene, alt: bool = True, tile_mask=None):
+MAX_BRANCHES = 64
+
+
+def render(scene: Scene, alt: bool = True, tile_mask=None, max_branches: int = MAX_BRANCHES):
     """Forward render: dict(image [3,H,W], final_T [H,W], n_contrib [H,W],
-    n_flags [H,W], alt [3,H,W] or None, n_grad_flags [H,W], n_blended [H,W],
-    depth [H,W], alpha [H,W]) with H the rendered rows.  With ``tile_mask``
+    n_flags [H,W], n_grad_flags [H,W], n_blended [H,W], depth [H,W],
+    alpha [H,W], branches) with H the rendered rows.  With ``tile_mask``
     ([tiles] bool) only those tiles are rendered (the other pixels stay
-    zero)."""
+    zero).  With ``alt``, ``branches`` holds every result that each pixel
+    with a flagged decision may take (``branches()``), else None."""
     lib = _load()
     H, W = scene.out_height, scene.width
     image = np.zeros((3, H, W))
     T = np.zeros((H, W))
     nc = np.zeros((H, W), dtype=np.int32)
     nf = np.zeros((H, W), dtype=np.int32)
-    altimg = np.zeros((3, H, W)) if alt else None
     ngf = np.zeros((H, W), dtype=np.int32)
     nbl = np.zeros((H, W), dtype=np.int32)
     depth = np.zeros((H, W))
     s = scene._struct()
     m = _mask(scene, tile_mask)
     rc = lib.orc_render(ctypes.byref(s), m.ctypes.data if m is not None else None, image.ctypes.data, T.ctypes.data,
-                        nc.ctypes.data, nf.ctypes.data, altimg.ctypes.data if alt else None, ngf.ctypes.data,
-                        nbl.ctypes.data, depth.ctypes.data)
+                        nc.ctypes.data, nf.ctypes.data, ngf.ctypes.data, nbl.ctypes.data, depth.ctypes.data)
     if rc != 0:
         raise ValueError("oracle: invalid scene")
-    return dict(image=image, final_T=T, n_contrib=nc, n_flags=nf, alt=altimg, n_grad_flags=ngf, n_blended=nbl,
-                depth=depth, alpha=1.0 - T)
+    out = dict(image=image, final_T=T, n_contrib=nc, n_flags=nf, n_grad_flags=ngf, n_blended=nbl,
+               depth=depth, alpha=1.0 - T, branches=None)
+    if alt:
+        out["branches"] = branches(scene, np.flatnonzero(nf.reshape(-1) > 0), max_branches)
+    return out
+
+
+def branches(scene: Scene, pixels, max_branches: int = MAX_BRANCHES):
+    """Every result that each of ``pixels`` (flat indices y * W + x) may take
+    when its flagged decisions go either way: dict(pixels [P], count [P]
+    (-1: more than ``max_branches``), image [P,B,3], final_T [P,B],
+    n_contrib [P,B], n_blended [P,B]); branch 0 is the FP64 walk."""
+    lib = _load()
+    pix = np.ascontiguousarray(np.asarray(pixels, dtype=np.int64).reshape(-1))
+    P, B = len(pix), int(max_branches)
+    out = dict(pixels=pix, count=np.zeros(P, np.int32), image=np.zeros((P, B, 3)), final_T=np.zeros((P, B)),
+               n_contrib=np.zeros((P, B), np.int32), n_blended=np.zeros((P, B), np.int32))
+    if P == 0:
+        return out
+    W = scene.width
+    mask = np.zeros(scene.tiles_x * scene.tiles_y, np.uint8)
+    mask[(pix // W) // 16 * scene.tiles_x + (pix % W) // 16] = 1
+    s = scene._struct()
+    rc = lib.orc_branches(ctypes.byref(s), mask.ctypes.data, P, pix.ctypes.data, B, out["count"].ctypes.data,
+                          out["image"].ctypes.data, out["final_T"].ctypes.data, out["n_contrib"].ctypes.data,
+                          out["n_blended"].ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle: invalid scene or pixel")
+    return out
 
 
 def l1(image, target):
@@ -325,11 +364,9 @@ def backward(scene: Scene, dL_dimage, with_abs: bool = True, tile_mask=None, dL_
 
     Returns dict(means, scales, quats, opacities, sh, screen, acc) and, with
     ``with_abs``, the same keys prefixed ``abs_``: sums of |per-pixel
-    contributions|, each weighted by 1 + the pixel's optical depth
-    ln(1 / T_final), pushed through |chain| (the scale float32 sums are judged
-    against: a float32 contribution's relative error grows with the optical
-    depth through the transmittance products).  With ``tile_mask`` only those tiles are walked (exact when
-    dL_dimage vanishes elsewhere).
+    contributions| pushed through |chain| (the scale float32 sums of terms of
+    both signs are judged against).  With ``tile_mask`` only those tiles are
+    walked (exact when dL_dimage vanishes elsewhere).
     """
     lib = _load()
     n, K = scene.n, scene.sh_coeffs

@@ -118,8 +118,8 @@ def test_batch_oracle_parity():
     torch.cuda.synchronize()
     for k, c in enumerate(cams):
         orc = O.render(O.Scene(g, c, dict(bg=(0.1, 0.3, 0.2))))
-        parity.check_image(res.outs[k]["image"].cpu().numpy(), orc, what=f"batched camera {k}")
-        parity.check_transmittance(res.outs[k]["final_T"].cpu().numpy(), res.outs[k]["n_contrib"].cpu().numpy(), orc)
+        parity.check_image(res.outs[k]["image"].cpu().numpy(), orc, what=f"batched camera {k}",
+                           gpu_T=res.outs[k]["final_T"].cpu().numpy(), gpu_nc=res.outs[k]["n_contrib"].cpu().numpy())
 
 
 # ---------------------------------------------------------------- serving

@@ -108,12 +108,8 @@ def check_fullsize(g, cam, seed, n_random=32):
     # sampled tiles against the oracle
     orc = O.render(sc, tile_mask=mask)
     ys, xs = tile_pixels(sc, mask)
-    sub = lambda a: a[..., ys, xs][..., None, :]
-    osub = {k: (sub(v) if v is not None else None) for k, v in orc.items()}
-    rep = parity.check_image(sub(img), osub, what="full-size sampled tiles")
-    parity.check_transmittance(sub(T), sub(nc), osub)
-    sel = osub["n_flags"] == 0
-    assert (sub(fwd.n_blended.cpu().numpy())[sel] == osub["n_blended"][sel]).all()
+    rep = parity.check_image(img, orc, what="full-size sampled tiles", gpu_T=T, gpu_nc=nc,
+                             gpu_nb=fwd.n_blended.cpu().numpy(), pixels=(ys, xs))
     ot, og, otr = O.tile_lists(sc, tile_mask=mask)
     # it / ig hold the tile lists concatenated in tile-id order
     cat = np.cumsum(lens.reshape(-1)) - lens.reshape(-1)

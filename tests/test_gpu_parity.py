@@ -40,14 +40,12 @@ def flagged_gaussians(sc):
     return np.nonzero(rec[:, O.REC_FIELDS["flag"]] > 0)[0]
 
 
-def compare_forward(g, cam, settings=None, lists=True, what="", max_excluded=1e-3):
+def compare_forward(g, cam, settings=None, lists=True, what=""):
     sc = O.Scene(g, cam, settings)
     orc = O.render(sc)
     r = gpu_forward(g, cam, settings)
-    rep = parity.check_image(np_(r.image), orc, what=what, max_excluded=max_excluded)
-    parity.check_transmittance(np_(r.final_T), np_(r.n_contrib), orc)
-    sel = orc["n_flags"] == 0
-    assert (np_(r.n_blended)[sel] == orc["n_blended"][sel]).all(), "n_blended differs at unflagged pixels"
+    rep = parity.check_image(np_(r.image), orc, what=what, gpu_T=np_(r.final_T), gpu_nc=np_(r.n_contrib),
+                             gpu_nb=np_(r.n_blended))
     if lists:
         t, gid, tr = O.tile_lists(sc)
         it, ig, rng = (np_(x) for x in r.instance_lists())
@@ -98,9 +96,8 @@ EDGE = {
 @pytest.mark.parametrize("case", sorted(EDGE))
 def test_forward_edge_cases(case):
     g, cam = EDGE[case]()
-    # near-ties grow with the number of decisions per pixel: ~800 in long_lists
-    compare_forward(g, cam, settings=dict(bg=(0.1, 0.3, 0.2)), what=case,
-                    max_excluded=2e-2 if case == "long_lists" else 1e-3)
+    _, _, rep = compare_forward(g, cam, settings=dict(bg=(0.1, 0.3, 0.2)), what=case)
+    print(case, rep)
 
 
 @pytest.mark.parametrize("degree,coeffs", [(0, 1), (1, 4), (2, 9), (2, 16), (3, 16)])

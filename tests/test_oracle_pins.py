@@ -435,17 +435,92 @@ def test_gradient_l1_with_decision_rejection():
     assert checked >= 20
 
 
-def test_screen_gradient_is_scaled_position_gradient():
-    """dL/ds = (W/2, H/2) * dL/dp (Eq. 5): FD of the loss under a shift of the
-    Gaussian's screen position, realised by yawing/pitching the point in the
-    camera frame, agrees with the recorded screen-space gradient."""
+def _fd_checked(loss_at, sig_at, h):
+    """Richardson central difference of loss_at(d), or None when a
+    perturbation of +-h or +-h/2 changes a discrete decision (sig_at)."""
+    if len({sig_at(d) for d in (h, -h, h / 2, -h / 2)}) != 1:
+        return None
+    return _richardson(loss_at, h)
+
+
+def test_screen_gradient_finite_differences():
+    """dL/ds (Eq. 4, 5: p = (s + 1) (W/2, H/2), so dL/ds = (W/2, H/2) dL/dp):
+    central differences of <G, render> under a shift of one Gaussian's
+    projected centre p alone (its 2D covariance, colour and depth held),
+    against the recorded screen-space gradient, both components."""
     sc = _fd_scene(12)
     rng = np.random.default_rng(13)
     G = rng.normal(size=(3, sc.height, sc.width))
     b = O.backward(sc, G, with_abs=False)
-    acc = b["acc"]
-    np.testing.assert_allclose(b["screen"][:, 0], acc[:, 0] * sc.width / 2, rtol=1e-15)
-    np.testing.assert_allclose(b["screen"][:, 1], acc[:, 1] * sc.height / 2, rtol=1e-15)
+    zero = np.zeros((3, sc.height, sc.width))
+    mask = np.ones(sc.tiles_x * sc.tiles_y, np.uint8)
+    vis = np.nonzero(O.project(sc)[:, 0] > 0)[0]
+    checked = 0
+    for i in rng.permutation(vis):
+        for axis, half in ((0, sc.width / 2), (1, sc.height / 2)):
+            def shifted(d):
+                s2 = sc.with_params()
+                sh = np.zeros((sc.n, 2))
+                sh[i, axis] = d
+                s2.screen_shift = sh
+                return s2
+            fd = _fd_checked(lambda d: float((O.render(shifted(d), alt=False)["image"] * G).sum()),
+                             lambda d: O.l1_tiles(shifted(d), zero, mask)[1], 1e-4)
+            if fd is None:
+                continue
+            an = b["screen"][i, axis]
+            assert abs(fd * half - an) <= 1e-6 * max(abs(an), 1e-2), (i, axis, an, fd * half)
+            checked += 1
+        if checked >= 12:
+            break
+    assert checked >= 12
+
+
+def test_screen_gradient_under_yaw_of_one_gaussian():
+    """A yaw by delta about the camera's vertical axis through the camera
+    centre, applied to one Gaussian's mean and its rotation, shifts its
+    longitude by delta (Eq. 3) and leaves its latitude, distance, 2D
+    covariance and (degree 0) colour unchanged, so by Eq. 4
+    d<G, render>/d delta = dL/ds_x / pi.  The rotation is built with scipy."""
+    from scipy.spatial.transform import Rotation
+
+    g = scenes.shell_scene(14, 40, r0=1.5, r1=3.0, scale_lo=0.05, scale_hi=0.4)
+    g = dict(g, sh_degree=0)
+    R_cw = scenes.rot_y(0.3).T
+    cam = scenes.camera(64, 32, R_cw, [0.1, -0.2, 0.05])
+    sc = O.Scene(g, cam, settings=dict(bg=(0.05, 0.1, 0.15)))
+    centre = -sc.R.T @ sc.t
+    rng = np.random.default_rng(15)
+    G = rng.normal(size=(3, sc.height, sc.width))
+    b = O.backward(sc, G, with_abs=False)
+    zero = np.zeros((3, sc.height, sc.width))
+    mask = np.ones(sc.tiles_x * sc.tiles_y, np.uint8)
+    vis = np.nonzero(O.project(sc)[:, 0] > 0)[0]
+    checked = 0
+    for i in rng.permutation(vis):
+        def yawed(d):
+            # camera frame: t' = R_y(d) t with R_y(d) = [[c, 0, s], [0, 1, 0], [-s, 0, c]]
+            Rw = sc.R.T @ Rotation.from_rotvec([0.0, d, 0.0]).as_matrix() @ sc.R
+            means, quats = sc.means.copy(), sc.quats.copy()
+            means[i] = centre + Rw @ (means[i] - centre)
+            q = quats[i] / np.linalg.norm(quats[i])
+            xyzw = (Rotation.from_matrix(Rw) * Rotation.from_quat([q[1], q[2], q[3], q[0]])).as_quat()
+            quats[i] = [xyzw[3], xyzw[0], xyzw[1], xyzw[2]]
+            return sc.with_params(means=means, quats=quats)
+        rec0, rec1 = O.project(yawed(0.0))[i], O.project(yawed(1e-3))[i]
+        assert rec1[O.REC_FIELDS["lon"]] - rec0[O.REC_FIELDS["lon"]] == pytest.approx(1e-3, abs=1e-12) or \
+            abs(abs(rec1[5] - rec0[5]) - 2 * np.pi) < 1e-3
+        np.testing.assert_allclose(rec1[O.REC_FIELDS["conic"]], rec0[O.REC_FIELDS["conic"]], rtol=1e-9)
+        fd = _fd_checked(lambda d: float((O.render(yawed(d), alt=False)["image"] * G).sum()),
+                         lambda d: O.l1_tiles(yawed(d), zero, mask)[1], 1e-4)
+        if fd is None:
+            continue
+        an = b["screen"][i, 0] / np.pi
+        assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-2), (i, an, fd)
+        checked += 1
+        if checked >= 8:
+            break
+    assert checked >= 8
 
 
 def test_l1_gradient():
@@ -470,4 +545,57 @@ def test_near_threshold_decisions_are_flagged():
     sc = O.Scene(g, scenes.camera(W, H))
     r = O.render(sc)
     assert r["n_flags"][y, x] == 1
-    assert abs(r["alt"][0, y, x] - r["image"][0, y, x]) > 1e-3
+    br = r["branches"]
+    k = int(np.searchsorted(br["pixels"], y * W + x))
+    assert br["pixels"][k] == y * W + x and br["count"][k] == 2
+    np.testing.assert_array_equal(br["image"][k, 0], r["image"][:, y, x])
+    assert abs(br["image"][k, 1, 0] - r["image"][0, y, x]) > 1e-3
+
+
+def test_depth_tie_is_one_flag_with_the_swapped_order_as_its_branch():
+    """Two Gaussians on one pixel whose distances agree to 1e-8 relative (the
+    float32 depth key cannot order them): one flagged decision, and the two
+    branches are Eq. 6 in either order."""
+    W, H, x, y = 64, 32, 21, 12
+    Y00 = 0.5 / np.sqrt(np.pi)
+    c_a, c_b = np.array([0.9, 0.2, 0.4]), np.array([0.1, 0.8, 0.6])
+    ms = np.array([_at_pixel(x, y, W, H, 3.0), _at_pixel(x, y, W, H, 3.0 * (1 + 1e-8))])
+    g = _single(ms, scales=0.3, opac=np.array([0.6, 0.7]), dc=(np.array([c_a, c_b]) - 0.5) / Y00)
+    r = O.render(O.Scene(g, scenes.camera(W, H)))
+    assert r["n_flags"][y, x] == 1
+    br = r["branches"]
+    k = int(np.searchsorted(br["pixels"], y * W + x))
+    assert br["count"][k] == 2
+    a_first = c_a * 0.6 + c_b * 0.7 * (1 - 0.6)
+    b_first = c_b * 0.7 + c_a * 0.6 * (1 - 0.7)
+    np.testing.assert_allclose(br["image"][k, 0], a_first, atol=1e-12)
+    np.testing.assert_allclose(br["image"][k, 1], b_first, atol=1e-12)
+    np.testing.assert_allclose(br["final_T"][k, :2], 0.4 * 0.3, atol=1e-12)
+    assert (br["n_contrib"][k, :2] == 2).all()
+
+
+def test_two_flagged_decisions_enumerate_four_branches():
+    """Two Gaussians whose alpha at the pixel equals alpha_min to 1e-7: each
+    may be blended or skipped, so the pixel has exactly four results (none,
+    either one, both), each a closed form of Eq. 6; with seven such
+    Gaussians (128 results) the pixel is beyond the enumeration and marked."""
+    W, H, x, y = 64, 32, 30, 15
+    a = (1.0 / 255.0) * (1 + 1e-7)
+    Y00 = 0.5 / np.sqrt(np.pi)
+    c1, c2 = np.array([0.9, 0.2, 0.4]), np.array([0.1, 0.8, 0.6])
+    ms = np.array([_at_pixel(x, y, W, H, 2.0), _at_pixel(x, y, W, H, 5.0)])
+    g = _single(ms, scales=0.02, opac=a, dc=(np.array([c1, c2]) - 0.5) / Y00)
+    r = O.render(O.Scene(g, scenes.camera(W, H)))
+    assert r["n_flags"][y, x] == 2
+    br = r["branches"]
+    k = int(np.searchsorted(br["pixels"], y * W + x))
+    assert br["count"][k] == 4
+    expect = [np.zeros(3), c1 * a, c2 * a, c1 * a + c2 * a * (1 - a)]
+    got = br["image"][k, :4]
+    for e in expect:
+        assert np.abs(got - e).max(axis=1).min() < 1e-9, (e, got)
+    ms7 = np.array([_at_pixel(x, y, W, H, r_) for r_ in (2.0, 2.5, 3.0, 3.5, 4.0, 4.5, 5.0)])
+    r7 = O.render(O.Scene(_single(ms7, scales=0.02, opac=a, dc=0.3), scenes.camera(W, H)))
+    assert r7["n_flags"][y, x] == 7
+    br7 = r7["branches"]
+    assert br7["count"][int(np.searchsorted(br7["pixels"], y * W + x))] == -1
