@@ -21,7 +21,8 @@ defaults):
 * statistics: for every Gaussian visible in the view (covering a tile),
   accum += ||dL/ds||_2 and denom += 1; max_radius = max(max_radius, screen
   radius in pixels);
-* densify (every interval, up to an iteration limit): g = accum / denom
+* densify (every interval, up to an iteration limit), decided in FP64 with
+  the comparisons near their thresholds flagged: g = accum / denom
   (0 where denom = 0); clone if g >= tau and max(S) <= percent_dense *
   extent: an identical copy; split if g >= tau and max(S) > percent_dense *
   extent: two children at m + R(q) (S * z_k) for standard normal z_k (given
@@ -126,49 +127,72 @@ def quat_to_rot(q):
         np.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], -1)], -2)
 
 
+# Relative margin around each densification threshold within which a
+# comparison is flagged: float32 inputs, a float32 mean of the statistic and
+# thresholds rounded to float32 (or compared in log / logit space) move a
+# comparison by a few 1e-7 relative at most.
+DECISION_MARGIN = 1e-5
+
+COMPARISONS = ("hot", "small", "low", "big_radius", "big_world", "child_big_world")
+
+
 def decisions(raw: dict, stats: dict, tau: float, percent_dense: float, extent: float, min_opacity: float,
-              max_screen: float | None, big_fraction: float = 0.1, shrink: float = 1.6):
-    """Clone / split / keep decisions.  They turn floating point into
-    integers, so they are taken in float32 on the float32 inputs, as the
-    kernel takes them: the averaged gradient by a (correctly rounded) float32
-    division, scales and opacities compared in log / logit space against
-    thresholds rounded once to float32 (no transcendental function inside a
-    decision)."""
-    f = np.float32
-    accum = np.asarray(stats["accum"], f)
-    denom = np.asarray(stats["denom"], f)
-    g = np.where(denom > 0, accum / np.where(denom > 0, denom, f(1)), f(0)).astype(f)
-    ls = np.asarray(raw["log_scales"], f)
-    lsmax = ls.max(axis=1) if len(ls) else np.zeros(0, f)
-    logit = np.asarray(raw["logits"], f)
-    radius = np.asarray(stats["max_radius"], f)
-    hot = g >= f(tau)
-    small = lsmax <= f(np.log(percent_dense * extent))
+              max_screen: float | None, big_fraction: float = 0.1, shrink: float = 1.6, invert=None):
+    """Clone / split / keep decisions, taken in FP64 on the given inputs:
+
+    * hot: g = accum / denom (0 where denom = 0) >= tau;
+    * small: max S <= percent_dense * extent (clone if hot, else split);
+    * low: o < min_opacity (pruned);
+    * big_radius: max_radius > max_screen; big_world: max S > big_fraction *
+      extent; child_big_world: the same for the children's S / shrink (only
+      when the screen rule is on; clones and children have radius 0).
+
+    Each comparison whose value lies within a relative DECISION_MARGIN of its
+    threshold is flagged (``flags[name]``, bool [n]): an implementation in
+    float32 may take it either way.  ``invert`` (dict name -> bool [n], may be
+    None) takes the listed comparisons the other way, so that a test can
+    enumerate the results those flags allow."""
+    n = raw["means"].shape[0]
+    accum = np.asarray(stats["accum"], np.float64)
+    denom = np.asarray(stats["denom"], np.float64)
+    g = np.where(denom > 0, accum / np.where(denom > 0, denom, 1.0), 0.0)
+    smax = np.exp(np.asarray(raw["log_scales"], np.float64)).max(axis=1) if n else np.zeros(0)
+    o = sigmoid(np.asarray(raw["logits"], np.float64))
+    radius = np.asarray(stats["max_radius"], np.float64)
+    screen_on = max_screen is not None
+    big_s = big_fraction * extent
+    cmp = dict(hot=(g, tau, g >= tau), small=(smax, percent_dense * extent, smax <= percent_dense * extent),
+               low=(o, min_opacity, o < min_opacity),
+               big_radius=(radius, max_screen if screen_on else 1.0,
+                           radius > max_screen if screen_on else np.zeros(n, bool)),
+               big_world=(smax, big_s, smax > big_s if screen_on else np.zeros(n, bool)),
+               child_big_world=(smax / shrink, big_s, smax / shrink > big_s if screen_on else np.zeros(n, bool)))
+    flags, take = {}, {}
+    for name, (v, thr, dec) in cmp.items():
+        active = screen_on or name not in ("big_radius", "big_world", "child_big_world")
+        flags[name] = (np.abs(v / thr - 1.0) < DECISION_MARGIN) & active if n else np.zeros(0, bool)
+        inv = np.zeros(n, bool) if invert is None or name not in invert else np.asarray(invert[name], bool)
+        take[name] = dec ^ inv
+    hot, small, low = take["hot"], take["small"], take["low"]
     clone = hot & small
     split = hot & ~small
-    log_shrink = f(np.log(shrink))
-    child_lsmax = (ls - log_shrink).max(axis=1) if len(ls) else np.zeros(0, f)
-    low = logit < f(np.log(min_opacity / (1.0 - min_opacity)))
-
-    def big(lsm, r):
-        if max_screen is None:
-            return np.zeros(len(lsm), bool)
-        return (r > f(max_screen)) | (lsm > f(np.log(big_fraction * extent)))
-
-    keep_orig = ~split & ~low & ~big(lsmax, radius)
-    keep_clone = clone & ~low & ~big(lsmax, np.zeros_like(radius))
-    keep_child = split & ~low & ~big(child_lsmax, np.zeros_like(radius))
+    keep_orig = ~split & ~low & ~(take["big_radius"] | take["big_world"])
+    keep_clone = clone & ~low & ~take["big_world"]
+    keep_child = split & ~low & ~take["child_big_world"]
     return dict(clone=clone, split=split, keep_orig=keep_orig, keep_clone=keep_clone, keep_child=keep_child,
-                log_shrink=float(log_shrink))
+                flags=flags, log_shrink=float(np.log(shrink)))
 
 
 def densify_and_prune(raw: dict, moments: dict, stats: dict, noise, tau: float, percent_dense: float, extent: float,
-                      min_opacity: float, max_screen: float | None, big_fraction: float = 0.1, shrink: float = 1.6):
+                      min_opacity: float, max_screen: float | None, big_fraction: float = 0.1, shrink: float = 1.6,
+                      invert=None):
     """Clone / split by the averaged dL/ds, then prune (see the module
     docstring for the order).  noise: [n, 2, 3] standard normals (only the
-    rows of split Gaussians are used).  Returns (raw, moments, stats, counts)."""
+    rows of split Gaussians are used).  invert: as for ``decisions``.
+    Returns (raw, moments, stats, counts); counts["flagged"] holds the
+    flagged comparisons (``decisions``)."""
     n = raw["means"].shape[0]
-    d = decisions(raw, stats, tau, percent_dense, extent, min_opacity, max_screen, big_fraction, shrink)
+    d = decisions(raw, stats, tau, percent_dense, extent, min_opacity, max_screen, big_fraction, shrink, invert)
     keep_orig, keep_clone, keep_child = d["keep_orig"], d["keep_clone"], d["keep_child"]
     clone, split = d["clone"], d["split"]
     scales = np.exp(np.asarray(raw["log_scales"], np.float64))
@@ -200,7 +224,7 @@ def densify_and_prune(raw: dict, moments: dict, stats: dict, noise, tau: float, 
     mom = {k: (np.concatenate([p[k][0] for p in parts_mom]), np.concatenate([p[k][1] for p in parts_mom]))
            for k in GROUPS}
     counts = dict(kept=int(keep_orig.sum()), clones=int(keep_clone.sum()), children=2 * int(keep_child.sum()),
-                  split=int(split.sum()), cloned=int(clone.sum()))
+                  split=int(split.sum()), cloned=int(clone.sum()), flagged=d["flags"])
     return out, mom, zero_stats(out["means"].shape[0]), counts
 
 
