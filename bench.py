@@ -2,25 +2,32 @@
 """ERP rasterizer benchmark: forward + L1 + backward iterations per second.
 
 Workload: 1M Gaussians in the indoor room layout (70% on the faces of an
-axis-aligned box, 30% in a shell, 20% moved across the +-pi seam), SH degree
-3, 2048x1024 ERP images, 200 seeded poses (centre in the unit ball, random
-yaw).  One step = one pose: omnigs_forward (project, depth sort, emit, tile
-sort, ranges, blend; with instance and block-entry capacities sized from the
-poses' counts, so no step reads anything back), omnigs_l1_loss against a per-pose target image (the
-render of a perturbed copy of the scene, prepared before timing), and
+axis-aligned box, 30% in a shell, 20% of all moved into a 2-degree wedge at
+world longitude pi), SH degree 3, 2048x1024 ERP images, 200 seeded poses
+(centre in the unit ball, random yaw).  One step = one pose: omnigs_forward
+(project, depth sort, emit, tile sort, ranges, blend; with instance and
+block-entry capacities sized from the poses' counts, so no step reads
+anything back), omnigs_l1_loss against a per-pose target image (the render
+of a perturbed copy of the scene, prepared before timing), and
 omnigs_backward (reverse blend, projection chain).  Inputs are resident in
 HBM when timing starts.
 
-Prints one JSON line (stdout) with the throughput, the roofline of the
+Prints one JSON line (stdout) with the throughput; the roofline of the
 dominant kernel (its stage bracketed with HIP events during the timed region;
 no other stage is, since each event costs the stream a few microseconds; the
 per-stage breakdown comes from a second pass over the same steps with every
-stage timed), the serving measurement (continuous batching vs one request at a
-time on the same resident scene: renders/s and p50/p99 latency at Poisson
-arrival rates of 0.5, 1 and 2 times the one-at-a-time capacity) and the FP64
-CPU oracle timed on one pose of the training workload.
+stage timed); both blends against the FP32 peak and the bandwidth-bound
+stages against the HBM peak, each also against the device's measured FMA
+and copy ceilings; the per-pose fraction of Gaussians crossing the seam; and
+the legs: the same workload with every pose at yaw 0 (the wedge across the
+seam), 3M Gaussians at 3840x1920, the training iteration, pinhole crops,
+masks and auxiliary outputs, the serving measurement (continuous batching
+vs one request at a time on the same resident scene: renders/s and p50/p99
+latency at Poisson arrival rates of 0.5, 1 and 2 times the one-at-a-time
+capacity) and the FP64 CPU oracle timed on the host (all cores, and one core
+against all on a sample).
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-serve]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-serve] [--no-stress] ...
 """
 from __future__ import annotations
 
@@ -41,11 +48,24 @@ COPY_BYTES = 256 << 20        # plain copy used to calibrate the HBM counters
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "blend_bwd_1M_2048x1024_traffic.txt")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2404_03202_amd", "csrc", "blend.hip")
 
-# Algorithmic FP32 work per (pixel, instance) pair of the blend (FMA = 2):
-# evaluating alpha (offsets, quadratic form, exp2, opacity, clamp) = 12;
-# the backward's gradient terms for a pair that was blended = 24.
+# Algorithmic work of the blends, per (pixel, list position) pair walked up to
+# the pixel's last contributor (sum of n_contrib): about 12 operations + one
+# exp forward and 50 + one exp backward (alpha, transmittance, the colour and
+# opacity terms and the moments of the conic gradient), each operation
+# counted as one FLOP against the FP32 vector peak.
+OPS_FWD_PAIR = 13
+OPS_BWD_PAIR = 51
+# Refined count: evaluating alpha (offsets, quadratic form, exp2, opacity,
+# clamp; FMA = 2) = 12 FLOP per walked pair; the backward's gradient terms
+# for a pair that was blended = 24 more.
 FLOP_ALPHA = 12
 FLOP_GRAD = 24
+# HBM-bound stages, algorithmic bytes: per Gaussian for the projection (the
+# 236 parameter bytes read, the 48-byte blend record and the sort key,
+# depth, tile count and rectangle written) and its backward (parameters and
+# the ten accumulators read, 59 gradients + dL/ds written).
+BYTES_PROJECT = 300
+BYTES_PROJECT_BWD = 600
 
 
 def log(*a):
@@ -92,8 +112,12 @@ def timed(step, ks, stages):
 
 def cpu_baseline(g, poses, gt_images):
     """FP64 oracle (forward + L1 + backward) on the host cores over a bounded
-    sample of the benchmark's poses."""
+    sample of the benchmark's poses, plus one core against all of them on a
+    quarter of one pose's tiles."""
     from oracle import oracle as O
+    nproc = os.cpu_count()
+    affinity = sorted(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else []
+    cores = O.num_threads()
     t0 = time.perf_counter()
     for pose, gt_image in zip(poses, gt_images):
         sc = O.Scene(g, pose)
@@ -102,9 +126,38 @@ def cpu_baseline(g, poses, gt_images):
         O.backward(sc, dl, with_abs=False)
     dt = time.perf_counter() - t0
     n = len(poses)
-    return dict(value=n / dt, unit="iters/s", cores=O.num_threads(), kind="oracle",
+
+    # one core vs all cores: forward + L1 + backward of pose 0 restricted to
+    # a seeded quarter of its tiles (the projection still covers every
+    # Gaussian)
+    sc = O.Scene(g, poses[0])
+    ntiles = sc.tiles_x * sc.tiles_y
+    mask = np.zeros(ntiles, bool)
+    mask[np.random.default_rng(11).choice(ntiles, ntiles // 4, replace=False)] = True
+
+    def sample():
+        t = time.perf_counter()
+        r = O.render(sc, alt=False, tile_mask=mask)
+        _, dl = O.l1(r["image"], gt_images[0])
+        O.backward(sc, dl, with_abs=False, tile_mask=mask)
+        return time.perf_counter() - t
+
+    t_all = sample()
+    O.set_num_threads(1)
+    try:
+        t_one = sample()
+    finally:
+        O.set_num_threads(cores)
+    return dict(value=n / dt, unit="iters/s", cores=cores, kind="oracle",
                 sample=f"{n} of 200 poses (poses 0-{n - 1}), full 1M Gaussians at 2048x1024: forward + L1 + backward, "
-                       f"{dt:.1f} s")
+                       f"{dt:.1f} s on {cores} threads",
+                nproc=nproc, affinity=f"{len(affinity)} cpus: {affinity[0]}-{affinity[-1]}" if affinity else None,
+                one_core=dict(sample="pose 0, forward + L1 + backward over a seeded quarter of its 8192 tiles "
+                                     "(projection of all 1M Gaussians)",
+                              seconds_1_thread=t_one, seconds_all_threads=t_all, threads=cores,
+                              speedup=t_one / t_all,
+                              implied_1core_iters_per_s=(n / dt) * t_all / t_one),
+                note="baseline only")
 
 
 def serving_bench(gd, n_requests, slots, max_batch, log):
@@ -158,11 +211,74 @@ def serving_bench(gd, n_requests, slots, max_batch, log):
                 slots=slots, max_batch=max_batch, mu1_renders_per_s=mu1, saturated=sat, poisson=rates)
 
 
-def stress_bench(steps, log):
+def hbm_stages(ms, n, S, M, W, H, ceilings=None):
+    """Algorithmic HBM bytes, GB/s and fraction of the 8 TB/s peak (and of
+    the measured copy rate) of the bandwidth-bound stages: u32 keys and
+    values; a sort reads its keys once for the digit histograms of all its
+    passes, then each pass reads and writes key + value (the depth sort's
+    first pass generates its values); the scan of the block counts in depth
+    order reads the count and rectangle of every Gaussian; block entries (S)
+    are emitted, sorted by block and ranged; the expansion reads every entry
+    and its rectangle twice (count, write) and writes each instance (M) once."""
+    supers = ((W // 16 + 7) // 8) * ((H // 16 + 7) // 8)
+    passes = -(-max(1, int(np.ceil(np.log2(supers)))) // 8)
+    algo = dict(project=BYTES_PROJECT * n, depth_sort=(4 + 4 * 16 - 4) * n, emit_count=12 * n,
+                super_emit=8 * S + 20 * n, super_sort=(4 + passes * 16) * S + 4 * S, tile_bin=24 * S + 4 * M,
+                project_bwd=BYTES_PROJECT_BWD * n)
+    out = {}
+    for k, b in algo.items():
+        if k not in ms or ms[k] <= 0:
+            continue
+        rate = b / (ms[k] * 1e-3)
+        row = dict(ms=ms[k], algo_bytes=b, GBps=rate / 1e9, frac=rate / PEAK_HBM)
+        if ceilings and ceilings.get("copy_gbps"):
+            row["frac_of_measured_copy"] = rate / (ceilings["copy_gbps"] * 1e9)
+        out[k] = row
+    return out, passes
+
+
+def blend_rates(walked, blended, ms_fwd, ms_bwd, ceilings=None):
+    """The two blends against the FP32 vector peak: work in the survey unit
+    (ops per walked pair) and in the refined FLOP count."""
+    out = {}
+    for name, ms, ops, flops in (("blend_fwd", ms_fwd, OPS_FWD_PAIR * walked, FLOP_ALPHA * walked),
+                                 ("blend_bwd", ms_bwd, OPS_BWD_PAIR * walked, FLOP_ALPHA * walked + FLOP_GRAD * blended)):
+        if not ms:
+            continue
+        a = ops / (ms * 1e-3)
+        r = flops / (ms * 1e-3)
+        row = dict(ms=ms, TFLOPs=a / 1e12, frac=a / PEAK_FP32_VECTOR, refined_TFLOPs=r / 1e12,
+                   refined_frac=r / PEAK_FP32_VECTOR)
+        if ceilings and ceilings.get("fma_tflops"):
+            row["frac_of_measured_fma"] = a / (ceilings["fma_tflops"] * 1e12)
+        out[name] = row
+    return out
+
+
+def pair_counts(gd, cams):
+    """Mean (walked, blended) pixel-instance pairs per forward over `cams`:
+    walked = sum of n_contrib, blended = sum of n_blended."""
+    import torch
+    from paper_2404_03202_amd import omnigs as B
+    walked = blended = 0
+    for c in cams:
+        f = B.omnigs_forward(gd, c, with_blended=True)
+        walked += int(f.n_contrib.sum(dtype=torch.int64))
+        blended += int(f.n_blended.sum(dtype=torch.int64))
+    return walked / len(cams), blended / len(cams)
+
+
+def seam_fractions(gd, cams):
+    from paper_2404_03202_amd import omnigs as B
+    fr = np.array([B.omnigs_forward(gd, c).seam_fraction() for c in cams])
+    return dict(mean=float(fr.mean()), min=float(fr.min()), p50=float(np.median(fr)), max=float(fr.max()))
+
+
+def stress_bench(steps, log, ceilings=None):
     """Large scene: 3M Gaussians (room layout, scales log-uniform [0.002,
     0.5]) at 3840x1920, forward + L1 + backward per pose.  Reports stage
-    times, the algorithmic HBM rate of the sort and binning stages and the
-    algorithmic FP32 rate of the two blends."""
+    times, the algorithmic HBM rate of the sort and binning stages, the
+    algorithmic FP32 rate of the two blends and the backward's atomics."""
     import torch
     from paper_2404_03202_amd import omnigs as B
     from paper_2404_03202_amd import scenes
@@ -194,33 +310,60 @@ def stress_bench(steps, log):
     ms = {k: v[0] / steps for k, v in prof.items() if v[1]}
     M = float(np.mean(inst))
     S = float(np.mean(entries))
-    walked = blended = 0
-    for k in range(steps):
-        f = B.omnigs_forward(gd, poses[k % len(poses)], with_blended=True)
-        walked += int(f.n_contrib.sum(dtype=torch.int64))
-        blended += int(f.n_blended.sum(dtype=torch.int64))
-    walked /= steps
-    blended /= steps
-    supers = ((W // 16 + 7) // 8) * ((H // 16 + 7) // 8)
-    passes = -(-max(1, int(np.ceil(np.log2(supers)))) // 8)
-    # algorithmic bytes per stage (u32 keys and values; a sort reads the keys
-    # once for the digit histograms of all its passes, then each pass reads
-    # and writes key + value, the depth sort's first pass generating its
-    # values): depth sort over N; the scan of the block counts in depth order;
-    # block entries (S) emitted, sorted by block and ranged; the expansion
-    # reads every entry and its rectangle twice (count, write) and writes each
-    # instance once
-    algo = dict(depth_sort=(4 + 4 * 16 - 4) * n, emit_count=12 * n, super_emit=8 * S + 20 * n,
-                super_sort=(4 + passes * 16) * S + 4 * S, tile_bin=24 * S + 4 * M)
-    rates = {k: algo[k] / (ms[k] * 1e-3) / 1e9 for k in algo if k in ms}
+    walked, blended = pair_counts(gd, [poses[k % len(poses)] for k in range(steps)])
+    stages, passes = hbm_stages(ms, n, S, M, W, H, ceilings)
     out = dict(workload="3M Gaussians, room layout, scales log-uniform [0.002, 0.5], SH degree 3, 3840x1920 ERP, "
-                        f"{len(poses)} poses, forward + L1 + backward per pose",
+                        f"{len(poses)} poses, forward + L1 + backward per pose (instance counts read back)",
                steps=steps, ms_per_step=dt * 1e3 / steps, iters_per_s=steps / dt, instances_per_step=M,
-               block_entries_per_step=S, block_sort_passes=passes, stage_ms=ms, sort_binning_GBps=rates,
+               block_entries_per_step=S, block_sort_passes=passes, stage_ms=ms, hbm_stages=stages,
                blend_pairs=dict(walked=walked, blended=blended),
-               blend_fwd_TFLOPs=FLOP_ALPHA * walked / (ms["blend_fwd"] * 1e-3) / 1e12,
-               blend_bwd_TFLOPs=(FLOP_ALPHA * walked + FLOP_GRAD * blended) / (ms["blend_bwd"] * 1e-3) / 1e12)
+               blends=blend_rates(walked, blended, ms.get("blend_fwd"), ms.get("blend_bwd"), ceilings),
+               seam_fraction=seam_fractions(gd, poses))
     log(f"stress: {out}")
+    return out
+
+
+def seam_stress_bench(gd, gt, steps, warmup, n_poses, log):
+    """The benchmark workload with every pose at yaw 0, where the wedge of
+    Gaussians placed at world longitude pi straddles the image seam: centres
+    uniform in the unit ball as in the benchmark, forward + L1 + backward
+    per pose with capacities (no read-back)."""
+    import torch
+    from paper_2404_03202_amd import omnigs as B
+    from paper_2404_03202_amd import scenes
+
+    poses = scenes.poses(2, n_poses, 2048, 1024, yaw_zero=True)
+    used = [poses[k % len(poses)] for k in range(warmup + steps)]
+    gtd = {k: (torch.from_numpy(v).to("cuda:0") if k != "sh_degree" else v) for k, v in gt.items()}
+    targets = {id(p): B.omnigs_forward(gtd, p).image.clone() for p in used}
+    del gtd
+    m_max = s_max = 0
+    for p in used:
+        f = B.omnigs_forward(gd, p)
+        m_max, s_max = max(m_max, f.n_instances), max(s_max, f.n_entries)
+    cap = (int(1.05 * m_max) + 1, int(1.05 * s_max) + 1)
+    overflow = []
+
+    def step(k):
+        p = poses[k % len(poses)]
+        fwd = B.omnigs_forward(gd, p, capacity=cap)
+        overflow.append(fwd.overflow)
+        _, dl = B.omnigs_l1_loss(fwd.image, targets[id(p)])
+        B.omnigs_backward(gd, p, None, fwd, dl)
+
+    for k in range(warmup):
+        step(k)
+    torch.cuda.synchronize()
+    dt, _ = timed(step, range(warmup, warmup + steps), ())
+    _, prof = timed(step, range(warmup, warmup + steps), None)
+    if int(torch.cat(overflow).sum()):
+        raise SystemExit("bench.py: the seam-stress leg overflowed its capacities")
+    out = dict(workload=f"1M Gaussians, room layout, 2048x1024 ERP, {n_poses} poses at yaw 0 (centre in the unit "
+                        "ball), forward + L1 + backward per pose",
+               steps=steps, iters_per_s=steps / dt, ms_per_step=dt * 1e3 / steps,
+               stage_ms={k: v[0] / steps for k, v in prof.items() if v[1]},
+               seam_fraction=seam_fractions(gd, poses))
+    log(f"seam stress: {out}")
     return out
 
 
@@ -382,7 +525,9 @@ def main():
     ap.add_argument("--poses", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
-    ap.add_argument("--stress", action="store_true", help="also measure the 3M-Gaussian 3840x1920 workload")
+    ap.add_argument("--no-stress", action="store_true", help="skip the 3M-Gaussian 3840x1920 workload")
+    ap.add_argument("--no-seam-stress", action="store_true", help="skip the yaw-0 seam-stress workload")
+    ap.add_argument("--no-ceilings", action="store_true", help="skip the measured FMA/exp/atomic/copy ceilings")
     ap.add_argument("--no-train", action="store_true", help="skip the full training-iteration measurement")
     ap.add_argument("--no-pinhole", action="store_true", help="skip the pinhole-camera measurement")
     ap.add_argument("--no-aux", action="store_true", help="skip the loss-mask / depth-output measurement")
@@ -412,6 +557,10 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps(dict(copy_bytes=COPY_BYTES, copies=5)))
         return
+    ceilings = None
+    if not args.no_ceilings:
+        ceilings = B.omnigs_measure_ceilings(atomic_words=10 << 20, copy_bytes=COPY_BYTES)
+        log(f"ceilings: {ceilings}")
     t0 = time.perf_counter()
     g, poses, gt = scenes.config2(n_poses=args.poses)
     log(f"scene: {g['means'].shape[0]} Gaussians, {len(poses)} poses ({time.perf_counter() - t0:.1f} s)")
@@ -432,8 +581,11 @@ def main():
     # pose (5% headroom): the timed forwards then read nothing back, and every
     # step's overflow flag is checked after the timed region
     m_max = s_max = 0
+    m_pose, s_pose = [], []
     for p in poses:
         f = B.omnigs_forward(gd, p)
+        m_pose.append(f.n_instances)
+        s_pose.append(f.n_entries)
         m_max, s_max = max(m_max, f.n_instances), max(s_max, f.n_entries)
     del f
     cap = (int(1.05 * m_max) + 1, int(1.05 * s_max) + 1)
@@ -462,39 +614,49 @@ def main():
     log("stages (ms per step): " + ", ".join(f"{k} {v[0] / args.steps:.3f}" for k, v in prof.items() if v[1]))
 
     # pairs walked / blended by the timed steps (deterministic re-render)
-    walked = blended = 0
-    for k in range(args.warmup, args.warmup + args.steps):
-        f = B.omnigs_forward(gd, poses[k % len(poses)], with_blended=True)
-        walked += int(f.n_contrib.sum(dtype=torch.int64))
-        blended += int(f.n_blended.sum(dtype=torch.int64))
+    timed_poses = [poses[k % len(poses)] for k in ks]
+    walked, blended = pair_counts(gd, timed_poses)
     bwd_ms, bwd_n = prof_bwd["blend_bwd"]
-    flops = FLOP_ALPHA * walked + FLOP_GRAD * blended
-    achieved = flops / (bwd_ms * 1e-3)
+    bwd_avg = bwd_ms / max(bwd_n, 1)
+    stage_ms = {k: v[0] / args.steps for k, v in prof.items() if v[1]}
+    blends = blend_rates(walked, blended, stage_ms.get("blend_fwd"), bwd_avg, ceilings)
     dominant = max(((k, v[0]) for k, v in prof.items()), key=lambda kv: kv[1])[0]
-    roofline = dict(kernel="blend_bwd", bound="alu", achieved=achieved / 1e12, peak=PEAK_FP32_VECTOR / 1e12,
-                    unit="TFLOP/s", frac=achieved / PEAK_FP32_VECTOR, traffic=measured_traffic(),
-                    avg_launch_ms=bwd_ms / max(bwd_n, 1), pairs_walked_per_launch=walked / max(bwd_n, 1),
-                    pairs_blended_per_launch=blended / max(bwd_n, 1), dominant_stage=dominant)
+    rb = blends["blend_bwd"]
+    roofline = dict(kernel="blend_bwd", bound="alu", achieved=rb["TFLOPs"], peak=PEAK_FP32_VECTOR / 1e12,
+                    unit="TFLOP/s", frac=rb["frac"], traffic=measured_traffic(),
+                    work=f"{OPS_BWD_PAIR} ops per walked pixel-instance pair (sum of n_contrib), one op = one FLOP",
+                    refined_achieved=rb["refined_TFLOPs"], refined_frac=rb["refined_frac"],
+                    frac_of_measured_fma=rb.get("frac_of_measured_fma"),
+                    avg_launch_ms=bwd_avg, pairs_walked_per_launch=walked, pairs_blended_per_launch=blended,
+                    dominant_stage=dominant)
+    M = float(np.mean([m_pose[k % len(poses)] for k in ks]))
+    S = float(np.mean([s_pose[k % len(poses)] for k in ks]))
+    stages, _ = hbm_stages(stage_ms, int(g["means"].shape[0]), S, M, 2048, 1024, ceilings)
+    seam = seam_fractions(gd, poses)
 
     out = dict(metric="ERP fwd+bwd iters/s @1M Gaussians 2048x1024", value=args.steps / dt, unit="iters/s",
                n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=dt * 1e3 / args.steps,
                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
-               config=dict(workload="1M Gaussians, room layout with 20% across the seam, SH degree 3, "
-                                    "2048x1024 ERP, 200 poses, forward + L1 + backward per pose",
+               config=dict(workload="1M Gaussians, room layout (20% of them in a 2-degree wedge at world longitude "
+                                    f"pi; at random yaw {100 * seam['mean']:.1f}% of the visible ones cross the "
+                                    "seam), SH degree 3, 2048x1024 ERP, 200 poses, forward + L1 + backward per pose",
                            gaussians=int(g["means"].shape[0]), width=2048, height=1024, poses=len(poses),
                            forward="caller capacities, no host read-back (overflow checked: none)",
                            instance_capacity=cap[0], entry_capacity=cap[1]),
-               stage_ms={k: v[0] / args.steps for k, v in prof.items() if v[1]},
+               stage_ms=stage_ms,
                ms_per_step_all_stages_timed=dt_prof * 1e3 / args.steps,
-               roofline=roofline)
+               roofline=roofline, blends=blends, hbm_stages=stages,
+               instances_per_step=M, block_entries_per_step=S, seam_fraction=seam, ceilings=ceilings)
     if not args.no_train:
         out["train"] = train_bench(g, poses, targets, min(args.steps, 100), log)
     if not args.no_pinhole:
         out["pinhole"] = pinhole_bench(gd, crops, crop_targets, poses, min(args.steps, 100), log)
     if not args.no_aux:
         out["aux"] = aux_bench(g, gd, masked, min(args.steps, 50), log)
-    if args.stress:
-        out["stress"] = stress_bench(args.stress_steps, log)
+    if not args.no_seam_stress:
+        out["seam_stress"] = seam_stress_bench(gd, gt, args.steps, args.warmup, args.poses, log)
+    if not args.no_stress:
+        out["stress"] = stress_bench(args.stress_steps, log, ceilings)
     if not args.no_serve:
         out["serving"] = serving_bench(gd, args.serve_requests, args.serve_slots, args.serve_max_batch, log)
     if not args.no_cpu_baseline:

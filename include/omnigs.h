@@ -147,9 +147,11 @@ typedef struct {
                                     extent of the alpha = alpha_min box), 0 when
                                     culled                                          */
     const float *depth;          /* [n] sort depth d (t_r or t_z) of each Gaussian */
-    const uint32_t *counts;      /* [2] S and M as counted on the device (device
-                                    words; n_entries and n_instances are -1 when
-                                    the call read nothing back)                     */
+    const uint32_t *counts;      /* [3] S and M as counted on the device, then
+                                    fault bits (bit 0: a lookback wait of the sort
+                                    or scan gave up; the lists are then invalid)
+                                    (device words; n_entries and n_instances are
+                                    -1 when the call read nothing back)             */
 } omnigs_state;
 
 /* Capacities of a forward call that reads nothing back (host struct).  With
@@ -159,7 +161,10 @@ typedef struct {
  * counts stay on the device and the call only enqueues work.  If M or S
  * exceeds its capacity the call still stays within its buffers, but its
  * outputs (and a backward from its state) are invalid and *overflow is 1.
- * overflow (device int32, may be NULL) is set to 0 or 1 on the call's stream.
+ * overflow (device int32, may be NULL) is set on the call's stream to 0, or
+ * to a nonzero value when the outputs are invalid: bit 0 a capacity was
+ * exceeded, bit 1 a lookback wait of the sort or scan gave up (see
+ * omnigs_selftest_lookback).
  * Both capacities must stay below 2^31 - 1. */
 typedef struct {
     int64_t instances;
@@ -271,7 +276,8 @@ omnigs_status omnigs_photometric_loss(const float *image, const float *target, i
  *   nothing is read back (no host synchronisation: the call only enqueues);
  *   if M exceeds it, the call still stays within its buffers, but the
  *   outputs are invalid and *overflow is 1.
- * overflow (device int32, may be NULL) is set to 0 or 1 on `stream`.
+ * overflow (device int32, may be NULL) is set on `stream` to 0, or nonzero
+ * with the bits of omnigs_capacity's overflow.
  * n_instances (host, may be NULL) receives M when it was read back, else -1.
  * M must stay below 2^32.  No backward state is kept; all memory beyond the
  * outputs is OMNIGS_MEM_SCRATCH.  Errors as omnigs_forward, plus
@@ -377,6 +383,53 @@ omnigs_status omnigs_densify(const omnigs_params *p, const omnigs_params *m1, co
  * moments are zeroed. */
 omnigs_status omnigs_reset_opacity(omnigs_params *p, omnigs_params *m1, omnigs_params *m2, double value,
                                    void *stream);
+
+/* Self-test of the failure signalling of the single-pass sort and scan
+ * (Sec. 3.3's depth sort and the tile-list binning run on them).  Their
+ * decoupled lookback polls the status word of an earlier workgroup until it
+ * is published; the poll count is bounded so that a kernel always ends, and
+ * a wait that reaches the bound sets a fault bit that the forward calls
+ * surface (omnigs_forward and omnigs_forward_batch fail with
+ * OMNIGS_ERR_HIP when they read counts back, else set bit 1 (value 2) of
+ * *overflow; omnigs_densify fails).  This call runs one primitive on n
+ * device-generated keys with the poll bound lowered to max_polls (0: the
+ * library's bound; 1: a wait gives up at its first unpublished word),
+ * then restores the bound: primitive 0 sorts n 32-bit keys (key, index
+ * pairs), 1 scans n values in [0, 15].  *fault (host) receives the fault
+ * bits, *correct (host) 1 when the result checked on the host is exact
+ * (a wait that gave up leaves a wrong prefix: then normally 0).  Buffers
+ * come from `alloc`; the call synchronises `stream`.  Not to be called
+ * while other threads launch library work (the bound is process-wide).
+ * OMNIGS_ERR_INVALID for primitive not 0 or 1, n outside [1, 2^26] or null
+ * outputs. */
+omnigs_status omnigs_selftest_lookback(int32_t primitive, int64_t n, uint32_t max_polls, omnigs_allocator alloc,
+                                       uint32_t *fault, int32_t *correct, void *stream);
+
+/* Measured ceilings of the device that `stream` runs on, against which the
+ * stages are quoted: the blends are bound by FP32 issue (Sec. 3.3-3.4 do a
+ * few dozen scalar operations and one exp per pixel-instance pair), the
+ * backward also by the float atomics that merge per-tile gradient sums, the
+ * projection, sorting and binning stages by HBM bandwidth.  Each figure is
+ * the mean over `repeats` launches (>= 1) of one kernel, after a warm-up
+ * launch, timed with HIP events on `stream` (the call synchronises):
+ *   fma_tflops   non-packed FP32 FMAs (2 FLOP each), 16 independent chains
+ *                per lane, 128 waves per CU;
+ *   exp_gops     exp2 results per second (1e9), same shape;
+ *   atomic_gops  float atomic adds to hashed addresses spread over
+ *                `atomic_words` words (1e9 per second; 0 skips it);
+ *   copy_gbps    a float4 copy of `copy_bytes` bytes, read + written bytes
+ *                per second (1e9; 0 skips it).
+ * Buffers (atomic_words * 4 and 2 * copy_bytes bytes) come from `alloc` as
+ * OMNIGS_MEM_SCRATCH.  OMNIGS_ERR_INVALID for repeats < 1, atomic_words
+ * >= 2^32 or copy_bytes not a multiple of 16. */
+typedef struct {
+    double fma_tflops;
+    double exp_gops;
+    double atomic_gops;
+    double copy_gbps;
+} omnigs_ceilings;
+omnigs_status omnigs_measure_ceilings(int64_t atomic_words, int64_t copy_bytes, int32_t repeats,
+                                      omnigs_allocator alloc, omnigs_ceilings *out, void *stream);
 
 /* Thread-local message describing the last non-OK status of this thread. */
 const char *omnigs_last_error(void);

@@ -1262,3 +1262,13 @@ int orc_num_threads(void) {
     return 1;
 #endif
 }
+
+/* Threads used by later calls (n >= 1); used to time the oracle on one
+ * core beside all of them. */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -403,3 +403,11 @@ def sh_eval(degree: int, direction):
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads for later oracle calls (n >= 1)."""
+    lib = _load()
+    lib.orc_set_num_threads.argtypes = [ctypes.c_int]
+    lib.orc_set_num_threads.restype = None
+    lib.orc_set_num_threads(int(n))

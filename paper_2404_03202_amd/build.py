@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libomnigs.so")
-SOURCES = ["capi.hip", "project.hip", "sort.hip", "bin.hip", "blend.hip", "loss.hip", "optim.hip"]
+SOURCES = ["capi.hip", "project.hip", "sort.hip", "bin.hip", "blend.hip", "loss.hip", "optim.hip", "ceilings.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

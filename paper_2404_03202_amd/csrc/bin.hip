@@ -257,25 +257,39 @@ void binning_clear(void *scratch, uint64_t super_cap, uint32_t n_super_total, Cl
 
 hipError_t launch_binning(const SuperTable &T, uint32_t n_super_total, const uint2 *rect, const uint32_t *sinst_gauss,
                           const uint2 *sranges, uint64_t super_cap, uint64_t inst_cap, void *scratch, uint2 *ranges,
-                          uint32_t *inst_gauss, int32_t *overflow, hipStream_t st, bool cleared) {
+                          uint32_t *inst_gauss, int32_t *overflow, hipStream_t st, bool cleared,
+                          uint32_t *fault) {
     if (n_super_total == 0) return hipSuccess;
     const uint64_t K = max_chunks(super_cap, n_super_total);
     const uint64_t cells = (uint64_t)kTilesPer * K;
     const BinLayout B(scratch, super_cap, n_super_total);
     const unsigned sb = (unsigned)blocks_for(n_super_total, 256);
     hipLaunchKernelGGL(k_bin_chunks, dim3(sb), dim3(256), 0, st, sranges, n_super_total, B.nch);
-    hipError_t e = scan_exclusive(B.nch, B.choff, n_super_total, B.choff + n_super_total, B.scan_chunks, st, nullptr);
+    hipError_t e = scan_exclusive(B.nch, B.choff, n_super_total, B.choff + n_super_total, B.scan_chunks, st, nullptr,
+                                  false, fault);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_bin_desc, dim3((unsigned)blocks_for((int64_t)K, 256)), dim3(256), 0, st, B.choff,
                        n_super_total, K, B.desc);
     hipLaunchKernelGGL(k_bin_count, dim3((unsigned)K), dim3(kThreads), 0, st, T, rect, sinst_gauss, sranges, B.choff,
                        B.nch, B.desc, n_super_total, B.counts);
-    e = scan_exclusive(B.counts, B.scanned, (int64_t)cells, B.scanned + cells, B.scan_counts, st, nullptr, cleared);
+    e = scan_exclusive(B.counts, B.scanned, (int64_t)cells, B.scanned + cells, B.scan_counts, st, nullptr, cleared,
+                       fault);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_bin_ranges, dim3((unsigned)blocks_for((int64_t)n_super_total * kTilesPer, 256)), dim3(256), 0,
                        st, T, n_super_total, B.choff, B.nch, B.scanned, inst_cap, ranges);
     hipLaunchKernelGGL(k_bin_expand, dim3((unsigned)K), dim3(kThreads), 0, st, T, rect, sinst_gauss, sranges, B.choff,
                        B.nch, B.desc, n_super_total, B.scanned, inst_cap, inst_gauss, overflow);
+    return hipGetLastError();
+}
+
+namespace {
+__global__ void k_merge_fault(const uint32_t *fault, int32_t *overflow) {
+    if (*fault) *overflow |= 2;
+}
+}  // namespace
+
+hipError_t launch_merge_fault(const uint32_t *fault, int32_t *overflow, hipStream_t st) {
+    hipLaunchKernelGGL(k_merge_fault, dim3(1), dim3(1), 0, st, fault, overflow);
     return hipGetLastError();
 }
 

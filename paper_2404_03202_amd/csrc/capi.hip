@@ -238,7 +238,8 @@ struct GeomState {
     uint32_t *n_tiles, *order;
     uint2 *rect;
     float *radii, *depth;
-    uint32_t *totals;  // [0] super entries S, [1] tile instances M (adjacent: one readback)
+    uint32_t *totals;  // [0] super entries S, [1] tile instances M (adjacent: one readback),
+                       // [2] fault bits (bit 0: a lookback wait gave up)
     void carve(Arena &a, int64_t n) {
         const size_t m = (size_t)(n > 0 ? n : 1);
         rec = a.take<BlendRecord>(m);
@@ -247,7 +248,7 @@ struct GeomState {
         rect = a.take<uint2>(m);
         radii = a.take<float>(m);
         depth = a.take<float>(m);
-        totals = a.take<uint32_t>(2);
+        totals = a.take<uint32_t>(3);
     }
 };
 struct GeomScratch {
@@ -275,11 +276,12 @@ omnigs_status sort_and_count(int64_t n, GeomState &gst, GeomScratch &gs, hipStre
     {
         StageTimer t(st, kStDepthSort);
         HIP_TRY(radix_sort_pairs(gs.depth_key, nullptr, gs.keys_tmp, gs.vals_tmp, gs.keys_sorted, gst.order, n, 32,
-                                 gs.sort_tmp, st, nullptr, nullptr, 0, cleared));
+                                 gs.sort_tmp, st, nullptr, nullptr, 0, cleared, gst.totals + 2));
     }
     {
         StageTimer t(st, kStEmitCount);
-        HIP_TRY(scan_exclusive(gs.n_super, gs.offs, n, gst.totals, gs.scan_tmp, st, gst.order, cleared));
+        HIP_TRY(scan_exclusive(gs.n_super, gs.offs, n, gst.totals, gs.scan_tmp, st, gst.order, cleared,
+                               gst.totals + 2));
     }
     return OMNIGS_OK;
 }
@@ -290,7 +292,7 @@ void geom_clear(int64_t n, GeomState &gst, GeomScratch &gs, ClearList &L) {
     const int64_t m = n > 0 ? n : 1;
     L.add(gs.sort_tmp, sort_clear_words(m, 32));
     L.add(gs.scan_tmp, scan_clear_words(m));
-    L.add(gst.totals, 2);
+    L.add(gst.totals, 3);
 }
 
 // Grids of the images of a launch.
@@ -351,7 +353,7 @@ omnigs_status run_binning(int64_t nrec, const GeomState &gst, const GeomScratch 
         const bool one_pass = bits <= 8;
         HIP_TRY(radix_sort_pairs(et, eg, bs.stile_tmp, bs.sgauss_tmp, bs.stile, bs.sgauss, (int64_t)super_cap, bits,
                                  bs.sort_tmp, st, counted ? gst.totals : nullptr, one_pass ? bs.sranges : nullptr,
-                                 one_pass ? (int)G.n_super : 0, cleared));
+                                 one_pass ? (int)G.n_super : 0, cleared, gst.totals + 2));
         if (!one_pass) {
             HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(bs.sranges), 0u, 2 * (int64_t)G.n_super, st));
             HIP_TRY(launch_tile_ranges(bs.stile, gst.totals, super_cap, bs.sranges, G.n_super, st));
@@ -360,7 +362,12 @@ omnigs_status run_binning(int64_t nrec, const GeomState &gst, const GeomScratch 
     {
         StageTimer t(st, kStTileBin);
         HIP_TRY(launch_binning(G.sup, G.n_super, gst.rect, bs.sgauss, bs.sranges, super_cap, inst_cap, bs.bin_tmp,
-                               ranges, inst_gauss, overflow, st, cleared));
+                               ranges, inst_gauss, overflow, st, cleared, gst.totals + 2));
+    }
+    if (overflow) {
+        // with capacities nothing is read back: a lookback wait that gave up
+        // also marks the call's overflow word
+        HIP_TRY(launch_merge_fault(gst.totals + 2, overflow, st));
     }
     return OMNIGS_OK;
 }
@@ -372,6 +379,68 @@ void bin_clear(uint64_t super_cap, const Grids &G, BinScratch &bs, ClearList &L)
     L.add(bs.sort_tmp, sort_clear_words((int64_t)(super_cap > 0 ? super_cap : 1), bits_for(G.n_super)));
     binning_clear(bs.bin_tmp, super_cap, G.n_super, L);
 }
+
+namespace {
+
+// The checks and stages of the backward on caller-provided scratch: `carve`
+// maps the accumulator and tile-order sizes to their buffers (or fails).
+template <class Carve>
+omnigs_status backward_impl(const omnigs_gaussians *g, const omnigs_camera *cam, const omnigs_settings *s,
+                            const omnigs_state *state, const omnigs_image_out *fwd, const float *dL_dimage,
+                            const float *dL_ddepth, const float *dL_dalpha, omnigs_grads *grads, void *stream,
+                            Carve carve) {
+    omnigs_status rc;
+    if ((rc = check_gaussians(g)) != OMNIGS_OK) return rc;
+    if ((rc = check_camera(cam)) != OMNIGS_OK) return rc;
+    if ((rc = check_settings(s)) != OMNIGS_OK) return rc;
+    if (!state || !fwd || !fwd->final_T || !fwd->n_contrib || !dL_dimage || !grads)
+        return fail(OMNIGS_ERR_INVALID, "a state, forward-output, cotangent or gradient pointer is NULL");
+    if (g->n > 0 && (!grads->dmeans || !grads->dscales || !grads->dquats || !grads->dopacities || !grads->dsh ||
+                     !grads->dscreen))
+        return fail(OMNIGS_ERR_INVALID, "a gradient output pointer is NULL");
+    if (g->n > 0 && reinterpret_cast<uintptr_t>(grads->dquats) % 16 != 0)
+        return fail(OMNIGS_ERR_INVALID, "dquats must be 16-byte aligned");
+    const bool aux = dL_ddepth || dL_dalpha;
+    if (state->n != g->n || state->width != cam->width ||
+        state->height != (cam->rows > 0 ? cam->rows : cam->height))
+        return fail(OMNIGS_ERR_INVALID, "state does not match the Gaussians / camera");
+    if (aux && g->n > 0 && !state->depth) return fail(OMNIGS_ERR_INVALID, "state depth buffer is NULL");
+    if (g->n > 0 && (!state->records || !state->n_tiles || !state->inst_gauss || !state->tile_range ||
+                     !state->tile_work))
+        return fail(OMNIGS_ERR_INVALID, "state buffers are NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t n = g->n;
+    if (n == 0) return OMNIGS_OK;
+    const ProjectArgs pa = make_project_args(g, cam, s);
+    const uint32_t ntiles = (uint32_t)(pa.tiles_x * pa.tiles_y);
+    const int nacc = aux ? kAccAux : kAcc;  // accumulator fields per Gaussian
+    float *acc = nullptr;
+    uint32_t *order = nullptr;
+    if ((rc = carve((size_t)n * nacc, (size_t)ntiles, acc, order)) != OMNIGS_OK) return rc;
+    const auto *rec = static_cast<const BlendRecord *>(state->records);
+    const auto *ranges = reinterpret_cast<const uint2 *>(state->tile_range);
+    {
+        StageTimer t(st, kStBwdClear);
+        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(acc), 0u, n * nacc, st));
+    }
+    const FrameGeom f{cam->width, pa.rows, pa.tiles_x, pa.tiles_y, 0u, pa.model == OMNIGS_CAMERA_ERP};
+    {
+        StageTimer t(st, kStTileOrder);
+        HIP_TRY(launch_tile_order(ranges, state->tile_work, ntiles, order, st));
+    }
+    {
+        StageTimer t(st, kStBlendBwd);
+        HIP_TRY(launch_blend_backward(f, rec, state->depth, state->inst_gauss, ranges, make_blend_settings(s),
+                                      fwd->final_T, fwd->n_contrib, dL_dimage, dL_ddepth, dL_dalpha, acc, order, st));
+    }
+    {
+        StageTimer t(st, kStProjectBwd);
+        HIP_TRY(launch_project_backward(pa, state->n_tiles, acc, nacc, *grads, st));
+    }
+    return OMNIGS_OK;
+}
+
+}  // namespace
 
 // ============================================================== public API
 extern "C" {
@@ -476,9 +545,10 @@ omnigs_status omnigs_forward(const omnigs_gaussians *g, const omnigs_camera *cam
     int64_t S = -1, M = -1;
     if (!counted) {
         // super entries S and tile instances M: the one host synchronisation
-        uint32_t tot[2] = {0, 0};
+        uint32_t tot[3] = {0, 0, 0};
         HIP_TRY(hipMemcpyAsync(tot, gst.totals, sizeof(tot), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
+        if (tot[2]) return fail(OMNIGS_ERR_HIP, "a lookback wait of the depth sort or scan gave up (fault bits %u)", tot[2]);
         S = tot[0];
         M = tot[1];
         super_cap = (uint64_t)S;
@@ -534,59 +604,18 @@ omnigs_status omnigs_backward(const omnigs_gaussians *g, const omnigs_camera *ca
                               const omnigs_state *state, const omnigs_image_out *fwd, const float *dL_dimage,
                               const float *dL_ddepth, const float *dL_dalpha, omnigs_grads *grads,
                               omnigs_allocator alloc, void *stream) {
-    omnigs_status rc;
-    if ((rc = check_gaussians(g)) != OMNIGS_OK) return rc;
-    if ((rc = check_camera(cam)) != OMNIGS_OK) return rc;
-    if ((rc = check_settings(s)) != OMNIGS_OK) return rc;
     if (!alloc.alloc) return fail(OMNIGS_ERR_INVALID, "allocator callback is NULL");
-    if (!state || !fwd || !fwd->final_T || !fwd->n_contrib || !dL_dimage || !grads)
-        return fail(OMNIGS_ERR_INVALID, "a state, forward-output, cotangent or gradient pointer is NULL");
-    if (g->n > 0 && (!grads->dmeans || !grads->dscales || !grads->dquats || !grads->dopacities || !grads->dsh ||
-                     !grads->dscreen))
-        return fail(OMNIGS_ERR_INVALID, "a gradient output pointer is NULL");
-    if (g->n > 0 && reinterpret_cast<uintptr_t>(grads->dquats) % 16 != 0)
-        return fail(OMNIGS_ERR_INVALID, "dquats must be 16-byte aligned");
-    const bool aux = dL_ddepth || dL_dalpha;
-    if (state->n != g->n || state->width != cam->width ||
-        state->height != (cam->rows > 0 ? cam->rows : cam->height))
-        return fail(OMNIGS_ERR_INVALID, "state does not match the Gaussians / camera");
-    if (aux && g->n > 0 && !state->depth) return fail(OMNIGS_ERR_INVALID, "state depth buffer is NULL");
-    if (g->n > 0 && (!state->records || !state->n_tiles || !state->inst_gauss || !state->tile_range ||
-                     !state->tile_work))
-        return fail(OMNIGS_ERR_INVALID, "state buffers are NULL");
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    const int64_t n = g->n;
-    if (n == 0) return OMNIGS_OK;
-    const ProjectArgs pa = make_project_args(g, cam, s);
-    const uint32_t ntiles = (uint32_t)(pa.tiles_x * pa.tiles_y);
-    const int nacc = aux ? kAccAux : kAcc;  // accumulator fields per Gaussian
-    Arena a;
-    a.take<float>((size_t)n * nacc);
-    a.take<uint32_t>(ntiles);
-    if ((rc = alloc_arena(alloc, a.off, OMNIGS_MEM_SCRATCH, a, "gradient accumulators")) != OMNIGS_OK) return rc;
-    float *acc = a.take<float>((size_t)n * nacc);
-    uint32_t *order = a.take<uint32_t>(ntiles);
-    const auto *rec = static_cast<const BlendRecord *>(state->records);
-    const auto *ranges = reinterpret_cast<const uint2 *>(state->tile_range);
-    {
-        StageTimer t(st, kStBwdClear);
-        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(acc), 0u, n * nacc, st));
-    }
-    const FrameGeom f{cam->width, pa.rows, pa.tiles_x, pa.tiles_y, 0u, pa.model == OMNIGS_CAMERA_ERP};
-    {
-        StageTimer t(st, kStTileOrder);
-        HIP_TRY(launch_tile_order(ranges, state->tile_work, ntiles, order, st));
-    }
-    {
-        StageTimer t(st, kStBlendBwd);
-        HIP_TRY(launch_blend_backward(f, rec, state->depth, state->inst_gauss, ranges, make_blend_settings(s),
-                                      fwd->final_T, fwd->n_contrib, dL_dimage, dL_ddepth, dL_dalpha, acc, order, st));
-    }
-    {
-        StageTimer t(st, kStProjectBwd);
-        HIP_TRY(launch_project_backward(pa, state->n_tiles, acc, nacc, *grads, st));
-    }
-    return OMNIGS_OK;
+    auto carve = [&](size_t acc_words, size_t ntiles, float *&acc, uint32_t *&order) -> omnigs_status {
+        Arena a;
+        a.take<float>(acc_words);
+        a.take<uint32_t>(ntiles);
+        omnigs_status rc;
+        if ((rc = alloc_arena(alloc, a.off, OMNIGS_MEM_SCRATCH, a, "gradient accumulators")) != OMNIGS_OK) return rc;
+        acc = a.take<float>(acc_words);
+        order = a.take<uint32_t>(ntiles);
+        return OMNIGS_OK;
+    };
+    return backward_impl(g, cam, s, state, fwd, dL_dimage, dL_ddepth, dL_dalpha, grads, stream, carve);
 }
 
 omnigs_status omnigs_l1_loss(const float *image, const float *target, int64_t count, float *dL_dimage, float *loss,
@@ -601,6 +630,105 @@ omnigs_status omnigs_l1_loss(const float *image, const float *target, int64_t co
     hipStream_t st = static_cast<hipStream_t>(stream);
     StageTimer t(st, kStL1);
     HIP_TRY(launch_l1(image, target, count, dL_dimage, loss, a.base, st));
+    return OMNIGS_OK;
+}
+
+omnigs_status omnigs_selftest_lookback(int32_t primitive, int64_t n, uint32_t max_polls, omnigs_allocator alloc,
+                                       uint32_t *fault, int32_t *correct, void *stream) {
+    if (primitive != 0 && primitive != 1) return fail(OMNIGS_ERR_INVALID, "primitive must be 0 (sort) or 1 (scan)");
+    if (n < 1 || n > (int64_t(1) << 26)) return fail(OMNIGS_ERR_INVALID, "n = %lld not in [1, 2^26]", (long long)n);
+    if (!fault || !correct) return fail(OMNIGS_ERR_INVALID, "fault or correct is NULL");
+    if (!alloc.alloc) return fail(OMNIGS_ERR_INVALID, "allocator callback is NULL");
+    static std::mutex selftest_mutex;
+    std::lock_guard<std::mutex> lock(selftest_mutex);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t m = (size_t)n;
+    Arena a;
+    uint32_t *keys, *vals, *kt, *vt, *ko, *vo, *word;
+    void *tmp;
+    auto carve = [&](Arena &ar) {
+        keys = ar.take<uint32_t>(m);
+        vals = ar.take<uint32_t>(m + 1);
+        kt = ar.take<uint32_t>(m);
+        vt = ar.take<uint32_t>(m);
+        ko = ar.take<uint32_t>(m);
+        vo = ar.take<uint32_t>(m);
+        word = ar.take<uint32_t>(1);
+        tmp = ar.take_bytes(std::max(sort_scratch_bytes(n), scan_scratch_bytes(n)));
+    };
+    carve(a);
+    omnigs_status rc;
+    if ((rc = alloc_arena(alloc, a.off, OMNIGS_MEM_SCRATCH, a, "self-test buffers")) != OMNIGS_OK) return rc;
+    carve(a);
+    const uint32_t mask = primitive == 0 ? 0xffffffffu : 15u;
+    HIP_TRY(launch_selftest_keys(keys, n, mask, st));
+    HIP_TRY(launch_fill_u32(word, 0u, 1, st));
+    set_lookback_poll_limit(max_polls);
+    hipError_t e = primitive == 0 ? radix_sort_pairs(keys, nullptr, kt, vt, ko, vo, n, 32, tmp, st, nullptr, nullptr, 0,
+                                                     false, word)
+                                  : scan_exclusive(keys, vals, n, vals + n, tmp, st, nullptr, false, word);
+    set_lookback_poll_limit(0);
+    HIP_TRY(e);
+    std::vector<uint32_t> hk(primitive == 0 ? m : 0), hv(primitive == 0 ? m : m + 1);
+    if (primitive == 0) {
+        HIP_TRY(hipMemcpyAsync(hk.data(), ko, m * 4, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(hv.data(), vo, m * 4, hipMemcpyDeviceToHost, st));
+    } else {
+        HIP_TRY(hipMemcpyAsync(hv.data(), vals, (m + 1) * 4, hipMemcpyDeviceToHost, st));
+    }
+    HIP_TRY(hipMemcpyAsync(fault, word, 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    bool ok = true;
+    if (primitive == 0) {
+        // ascending keys, a stable permutation of the input
+        std::vector<char> seen(m, 0);
+        for (size_t i = 0; i < m && ok; ++i) {
+            const uint32_t v = hv[i];
+            ok = v < m && !seen[v] && hk[i] == selftest_key(v);
+            if (ok) seen[v] = 1;
+            if (ok && i > 0) ok = hk[i - 1] < hk[i] || (hk[i - 1] == hk[i] && hv[i - 1] < v);
+        }
+    } else {
+        uint64_t run = 0;
+        for (size_t i = 0; i <= m && ok; ++i) {
+            ok = hv[i] == (uint32_t)run;
+            if (i < m) run += selftest_key((uint32_t)i) & mask;
+        }
+    }
+    *correct = ok ? 1 : 0;
+    return OMNIGS_OK;
+}
+
+omnigs_status omnigs_measure_ceilings(int64_t atomic_words, int64_t copy_bytes, int32_t repeats,
+                                      omnigs_allocator alloc, omnigs_ceilings *out, void *stream) {
+    if (!out) return fail(OMNIGS_ERR_INVALID, "out is NULL");
+    if (repeats < 1) return fail(OMNIGS_ERR_INVALID, "repeats must be >= 1");
+    if (atomic_words < 0 || atomic_words >= (int64_t(1) << 32))
+        return fail(OMNIGS_ERR_INVALID, "atomic_words %lld out of range", (long long)atomic_words);
+    if (copy_bytes < 0 || copy_bytes % 16 != 0)
+        return fail(OMNIGS_ERR_INVALID, "copy_bytes must be a non-negative multiple of 16");
+    if (!alloc.alloc) return fail(OMNIGS_ERR_INVALID, "allocator callback is NULL");
+    Arena a;
+    auto carve = [&](Arena &ar, float *&abuf, float *&src, float *&dst) {
+        abuf = atomic_words ? ar.take<float>((size_t)atomic_words) : nullptr;
+        src = copy_bytes ? ar.take<float>((size_t)copy_bytes / 4) : nullptr;
+        dst = copy_bytes ? ar.take<float>((size_t)copy_bytes / 4) : nullptr;
+    };
+    float *abuf, *src, *dst;
+    carve(a, abuf, src, dst);
+    omnigs_status rc;
+    if ((rc = alloc_arena(alloc, a.off, OMNIGS_MEM_SCRATCH, a, "ceiling buffers")) != OMNIGS_OK) return rc;
+    carve(a, abuf, src, dst);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (abuf) HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(abuf), 0u, atomic_words, st));
+    if (src) HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(src), 0u, copy_bytes / 4, st));
+    double ms[4], work[4];
+    HIP_TRY(measure_ceilings(abuf, (uint32_t)atomic_words, src, dst, copy_bytes, repeats, ms, work, st));
+    auto rate = [&](int k) { return ms[k] > 0.0 ? work[k] / (ms[k] * 1e-3) : 0.0; };
+    out->fma_tflops = rate(0) / 1e12;
+    out->exp_gops = rate(1) / 1e9;
+    out->atomic_gops = rate(2) / 1e9;
+    out->copy_gbps = rate(3) / 1e9;
     return OMNIGS_OK;
 }
 
@@ -694,6 +822,7 @@ omnigs_status omnigs_forward_batch(const omnigs_gaussians *g, const omnigs_camer
     if ((rc = alloc_arena(alloc, ra.off, OMNIGS_MEM_SCRATCH, ra, "per-record scratch")) != OMNIGS_OK) return rc;
     carve_geom(ra);
     if (overflow) HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(overflow), 0u, 1, st));
+    HIP_TRY(launch_fill_u32(gst.totals + 2, 0u, 1, st));  // fault bits
     {
         StageTimer t(st, kStProject);
         HIP_TRY(launch_project_batch(pa, ct, gst.rec, gs.depth_key, gst.depth, gst.n_tiles, gst.rect, gs.n_super,
@@ -708,9 +837,10 @@ omnigs_status omnigs_forward_batch(const omnigs_gaussians *g, const omnigs_camer
     uint64_t super_cap, inst_cap;
     const bool counted = instance_capacity > 0;
     if (!counted) {
-        uint32_t tot[2] = {0, 0};
+        uint32_t tot[3] = {0, 0, 0};
         HIP_TRY(hipMemcpyAsync(tot, gst.totals, sizeof(tot), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
+        if (tot[2]) return fail(OMNIGS_ERR_HIP, "a lookback wait of the depth sort or scan gave up (fault bits %u)", tot[2]);
         super_cap = tot[0];
         inst_cap = tot[1];
         if (n_instances) *n_instances = tot[1];
@@ -863,19 +993,21 @@ omnigs_status omnigs_densify(const omnigs_params *p, const omnigs_params *m1, co
     d.log_shrink = (float)std::log(s->split_shrink);
     Arena a;
     a.take<uint32_t>((size_t)(4 * n + 1));
-    a.take<uint32_t>((size_t)(4 * n + 1));
+    a.take<uint32_t>((size_t)(4 * n + 2));
     a.take_bytes(scan_scratch_bytes(4 * n + 1));
     if ((rc = alloc_arena(alloc, a.off, OMNIGS_MEM_SCRATCH, a, "densification scratch")) != OMNIGS_OK) return rc;
     uint32_t *flags = a.take<uint32_t>((size_t)(4 * n + 1));
-    uint32_t *pos = a.take<uint32_t>((size_t)(4 * n + 1));
+    uint32_t *pos = a.take<uint32_t>((size_t)(4 * n + 2));  // scan, total, fault bits
     void *scan_tmp = a.take_bytes(scan_scratch_bytes(4 * n + 1));
     const OptimArrays P = arrays_of(p);
     HIP_TRY(launch_dens_flags(P, stats->accum, stats->denom, stats->max_radius, n, d, flags, st));
-    HIP_TRY(scan_exclusive(flags, pos, 4 * n, pos + 4 * n, scan_tmp, st, nullptr));
-    uint32_t total = 0;
-    HIP_TRY(hipMemcpyAsync(&total, pos + 4 * n, sizeof(total), hipMemcpyDeviceToHost, st));
+    HIP_TRY(launch_fill_u32(pos + 4 * n + 1, 0u, 1, st));
+    HIP_TRY(scan_exclusive(flags, pos, 4 * n, pos + 4 * n, scan_tmp, st, nullptr, false, pos + 4 * n + 1));
+    uint32_t tot[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(tot, pos + 4 * n, sizeof(tot), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    const int64_t no = total;
+    if (tot[1]) return fail(OMNIGS_ERR_HIP, "a lookback wait of the densification scan gave up");
+    const int64_t no = tot[0];
     // outputs: parameters, two moment sets, statistics
     Arena o;
     auto carve = [&](Arena &ar, omnigs_params *q) {

@@ -160,7 +160,8 @@ int64_t sort_clear_words(int64_t n, int bits);
 hipError_t radix_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_tmp,
                             uint32_t *vals_tmp, uint32_t *keys_out, uint32_t *vals_out, int64_t n, int bits,
                             void *scratch, hipStream_t st, const uint32_t *n_dev = nullptr,
-                            uint2 *key_ranges = nullptr, int n_ranges = 0, bool cleared = false);
+                            uint2 *key_ranges = nullptr, int n_ranges = 0, bool cleared = false,
+                            uint32_t *fault = nullptr);
 
 // Exclusive scan of u32 (optionally of in[gather[i]]); *total (device, may be
 // null) receives the sum.  `scratch` from scan_scratch_bytes; cleared: its
@@ -168,7 +169,21 @@ hipError_t radix_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in, ui
 size_t scan_scratch_bytes(int64_t n);
 int64_t scan_clear_words(int64_t n);
 hipError_t scan_exclusive(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *total, void *scratch,
-                          hipStream_t st, const uint32_t *gather, bool cleared = false);
+                          hipStream_t st, const uint32_t *gather, bool cleared = false, uint32_t *fault = nullptr);
+
+// Lookback self-test: the poll bound of every later lookback wait (the
+// default is restored by passing 0).  Only the self-test entry point lowers
+// it, to make waits give up on purpose.
+void set_lookback_poll_limit(uint32_t polls);
+// Self-test input: keys[i] = selftest_key(i) & mask.
+__host__ __device__ inline uint32_t selftest_key(uint32_t i) {
+    uint32_t h = i * 2654435761u + 0x9e3779b9u;
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    return h;
+}
+hipError_t launch_selftest_keys(uint32_t *keys, int64_t n, uint32_t mask, hipStream_t st);
 
 // Zeroes up to kMaxClear regions of u32 words in one launch (the lookback
 // words and counters of the sorts and scans of a call).
@@ -216,7 +231,10 @@ size_t binning_scratch_bytes(uint64_t super_cap, uint32_t n_super_total);
 void binning_clear(void *scratch, uint64_t super_cap, uint32_t n_super_total, ClearList &L);
 hipError_t launch_binning(const SuperTable &T, uint32_t n_super_total, const uint2 *rect, const uint32_t *sinst_gauss,
                           const uint2 *sranges, uint64_t super_cap, uint64_t inst_cap, void *scratch, uint2 *ranges,
-                          uint32_t *inst_gauss, int32_t *overflow, hipStream_t st, bool cleared = false);
+                          uint32_t *inst_gauss, int32_t *overflow, hipStream_t st, bool cleared = false,
+                          uint32_t *fault = nullptr);
+// *overflow |= 2 when *fault is nonzero (one thread).
+hipError_t launch_merge_fault(const uint32_t *fault, int32_t *overflow, hipStream_t st);
 
 // Blend kernels.
 struct BlendSettings {
@@ -293,6 +311,13 @@ hipError_t launch_photometric(const float *image, const float *target, const flo
                               int width, float lambda, float *grad, float *loss, void *scratch, hipStream_t st);
 
 // L1 loss.
+// Ceilings: FMA, exp2, scattered-atomic and copy kernels, each timed with
+// HIP events over `repeats` launches after a warm-up; ms[k] per launch and
+// work[k] per launch (FLOP, exp2 results, atomics, bytes moved).  A null
+// atomic buffer or copy source skips that measurement (ms = work = 0).
+hipError_t measure_ceilings(float *atomic_buf, uint32_t atomic_words, const float *copy_src, float *copy_dst,
+                            int64_t copy_bytes, int repeats, double ms[4], double work[4], hipStream_t st);
+
 size_t l1_scratch_bytes();
 hipError_t launch_l1(const float *image, const float *target, int64_t count, float *grad, float *loss,
                      void *scratch, hipStream_t st);

@@ -103,8 +103,11 @@ constexpr int kHeadWords = kMaxPasses * kBins + 64;  // digit totals, then one t
 // Bound on the polls of one lookback word: an earlier block always publishes
 // (blocks take their position from a ticket, so every earlier position is
 // held by a block that is already running), the bound only guarantees that
-// the kernel ends whatever happens.
+// the kernel ends whatever happens.  A wait that reaches it sets bit 0 of
+// the call's fault word (when given): the prefix it continues with is then
+// wrong, and the caller is told so.
 constexpr uint32_t kMaxPolls = 1u << 20;
+uint32_t g_max_polls = kMaxPolls;  // lowered only by the lookback self-test
 #ifndef OMNIGS_SORT_LOOK
 #define OMNIGS_SORT_LOOK 4
 #endif
@@ -161,7 +164,8 @@ __global__ __launch_bounds__(kThreads) void k_radix_pass(const uint32_t *keys_in
                                                           uint32_t *keys_out, uint32_t *vals_out, int64_t n_max,
                                                           const uint32_t *n_dev, int shift, int bits,
                                                           const uint32_t *ghist, uint32_t *status,
-                                                          uint32_t *ticket, uint2 *key_ranges, int n_ranges) {
+                                                          uint32_t *ticket, uint2 *key_ranges, int n_ranges,
+                                                          uint32_t *fault, uint32_t max_polls) {
     __shared__ uint32_t s_keys[kTileKeys];
     __shared__ uint32_t s_vals[kTileKeys];
     __shared__ uint32_t cnt[kWaves][kBins];
@@ -252,7 +256,10 @@ __global__ __launch_bounds__(kThreads) void k_radix_pass(const uint32_t *keys_in
                 if (inc) break;
                 p -= used;
                 if (wait) {
-                    if (++polls >= kMaxPolls) break;
+                    if (++polls >= max_polls) {
+                        if (fault) atomicOr(fault, 1u);
+                        break;
+                    }
                     __builtin_amdgcn_s_sleep(1);
                 }
             }
@@ -314,7 +321,8 @@ __device__ inline uint32_t scan_input(const uint32_t *in, const uint32_t *gather
 constexpr uint64_t kInc64 = 1ull << 63;
 __global__ __launch_bounds__(kThreads) void k_scan_lookback(const uint32_t *in, const uint32_t *gather, uint32_t *out,
                                                              int64_t n, uint64_t *status, uint32_t *ticket,
-                                                             uint32_t *grand_total) {
+                                                             uint32_t *grand_total, uint32_t *fault,
+                                                             uint32_t max_polls) {
     __shared__ uint32_t wave_tot[kWaves];
     __shared__ uint32_t total;
     __shared__ uint32_t s_data[kScanTile];
@@ -366,7 +374,10 @@ __global__ __launch_bounds__(kThreads) void k_scan_lookback(const uint32_t *in, 
             if (!zeros && first_inc < kWave) break;
             p -= upto;
             if (zeros) {
-                if (++polls >= kMaxPolls) break;
+                if (++polls >= max_polls) {
+                    if (fault && lane == 0) atomicOr(fault, 1u);
+                    break;
+                }
                 __builtin_amdgcn_s_sleep(1);
             }
         }
@@ -607,11 +618,8 @@ int64_t scan_clear_words(int64_t n) {
 }
 
 hipError_t scan_exclusive(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *total, void *scratch,
-                          hipStream_t st, const uint32_t *gather, bool cleared) {
-    if (n <= 0) {
-        if (total) launch_fill_u32(total, 0u, 1, st);
-        return hipGetLastError();
-    }
+                          hipStream_t st, const uint32_t *gather, bool cleared, uint32_t *fault) {
+    if (n <= 0) return total ? launch_fill_u32(total, 0u, 1, st) : hipSuccess;
     const int64_t nb = blocks_for(n, kScanTile);
     if (nb == 1) {
         hipLaunchKernelGGL(k_scan_tile, dim3(1), dim3(kThreads), 0, st, in, gather, out, n, total);
@@ -620,10 +628,12 @@ hipError_t scan_exclusive(const uint32_t *in, uint32_t *out, int64_t n, uint32_t
     uint64_t *status = static_cast<uint64_t *>(scratch);
     uint32_t *ticket = reinterpret_cast<uint32_t *>(status + nb);
     const int64_t words = scan_clear_words(n);
-    if (!cleared)
-        launch_fill_u32(reinterpret_cast<uint32_t *>(status), 0u, words, st);
+    if (!cleared) {
+        const hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(status), 0u, words, st);
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_scan_lookback, dim3((unsigned)nb), dim3(kThreads), 0, st, in, gather, out, n, status, ticket,
-                       total);
+                       total, fault, g_max_polls);
     return hipGetLastError();
 }
 
@@ -642,13 +652,12 @@ int64_t sort_clear_words(int64_t n, int bits) {
 hipError_t radix_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_tmp,
                             uint32_t *vals_tmp, uint32_t *keys_out, uint32_t *vals_out, int64_t n, int bits,
                             void *scratch, hipStream_t st, const uint32_t *n_dev, uint2 *key_ranges,
-                            int n_ranges, bool cleared) {
+                            int n_ranges, bool cleared, uint32_t *fault) {
     if (key_ranges && (bits > kRadixBits || n_ranges > kBins)) return hipErrorInvalidValue;
-    if (n <= 0) {
-        if (key_ranges && n_ranges > 0)
-            launch_fill_u32(reinterpret_cast<uint32_t *>(key_ranges), 0u, (int64_t)2 * n_ranges, st);
-        return hipGetLastError();
-    }
+    if (n <= 0)
+        return key_ranges && n_ranges > 0
+                   ? launch_fill_u32(reinterpret_cast<uint32_t *>(key_ranges), 0u, (int64_t)2 * n_ranges, st)
+                   : hipSuccess;
     if (n >= (int64_t)kCountMask) return hipErrorInvalidValue;  // lookback words hold count + 1 in 31 bits
     if (bits < 1) bits = 1;
     if (bits > 32) bits = 32;
@@ -659,8 +668,10 @@ hipError_t radix_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in, ui
     uint32_t *ghist = head, *tickets = head + kMaxPasses * kBins;
     uint32_t *status = head + kHeadWords;
     const int64_t words = sort_clear_words(n, bits);
-    if (!cleared)
-        launch_fill_u32(head, 0u, words, st);
+    if (!cleared) {
+        const hipError_t e = launch_fill_u32(head, 0u, words, st);
+        if (e != hipSuccess) return e;
+    }
     const int64_t hist_blocks = std::min<int64_t>(blocks_for(n, kHistChunk), kHistMaxBlocks);
     hipLaunchKernelGGL(k_sort_hist, dim3((unsigned)hist_blocks), dim3(kThreads), 0, st, keys_in, n, n_dev, passes,
                        bits, ghist);
@@ -674,7 +685,7 @@ hipError_t radix_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in, ui
         uint32_t *dv = to_out ? vals_out : vals_tmp;
         hipLaunchKernelGGL(k_radix_pass, dim3((unsigned)nb), dim3(kThreads), 0, st, src_k, src_v, dk, dv, n, n_dev,
                            shift, pbits, (const uint32_t *)(ghist + p * kBins), status + (int64_t)p * nb * kBins,
-                           tickets + p, key_ranges, n_ranges);
+                           tickets + p, key_ranges, n_ranges, fault, g_max_polls);
         src_k = dk;
         src_v = dv;
     }
@@ -687,6 +698,21 @@ hipError_t launch_clear(const ClearList &L, hipStream_t st) {
     for (int k = 0; k < L.count; ++k) most = std::max(most, L.n[k]);
     const unsigned bx = (unsigned)std::min<int64_t>(blocks_for(most, 1024), 2048);
     hipLaunchKernelGGL(k_clear_list, dim3(bx, (unsigned)L.count), dim3(256), 0, st, L);
+    return hipGetLastError();
+}
+
+void set_lookback_poll_limit(uint32_t polls) { g_max_polls = polls ? polls : kMaxPolls; }
+
+namespace {
+__global__ void k_selftest_keys(uint32_t *keys, int64_t n, uint32_t mask) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) keys[i] = selftest_key((uint32_t)i) & mask;
+}
+}  // namespace
+
+hipError_t launch_selftest_keys(uint32_t *keys, int64_t n, uint32_t mask, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_selftest_keys, dim3((unsigned)blocks_for(n, 256)), dim3(256), 0, st, keys, n, mask);
     return hipGetLastError();
 }
 

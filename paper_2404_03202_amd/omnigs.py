@@ -108,7 +108,8 @@ EXPORTS = ("omnigs_default_settings", "omnigs_forward", "omnigs_backward", "omni
            "omnigs_forward_batch",
            "omnigs_adam_step", "omnigs_accumulate_stats", "omnigs_densify", "omnigs_reset_opacity",
            "omnigs_last_error", "omnigs_profile_enable", "omnigs_profile_num_stages", "omnigs_profile_stage_name",
-           "omnigs_profile_read")
+           "omnigs_profile_read", "omnigs_measure_ceilings",
+           "omnigs_selftest_lookback")
 
 _lib = None
 _lib_lock = threading.Lock()
@@ -153,6 +154,12 @@ def load_library(path: str = LIB_PATH):
         lib.omnigs_densify.restype = ctypes.c_int
         lib.omnigs_reset_opacity.argtypes = [P(c_params), P(c_params), P(c_params), ctypes.c_double, vp]
         lib.omnigs_reset_opacity.restype = ctypes.c_int
+        lib.omnigs_measure_ceilings.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, c_allocator,
+                                                P(c_ceilings), vp]
+        lib.omnigs_measure_ceilings.restype = ctypes.c_int
+        lib.omnigs_selftest_lookback.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, c_allocator,
+                                                 P(ctypes.c_uint32), P(ctypes.c_int32), vp]
+        lib.omnigs_selftest_lookback.restype = ctypes.c_int
         lib.omnigs_last_error.argtypes = []
         lib.omnigs_last_error.restype = ctypes.c_char_p
         lib.omnigs_profile_enable.argtypes = [ctypes.c_uint32]
@@ -335,6 +342,23 @@ class ForwardResult:
     def depth_order(self):
         return self._view(self.state.depth_order, int(self.state.n), torch.int32)
 
+    def seam_fraction(self):
+        """Fraction of the visible Gaussians (covering at least one tile)
+        whose alpha >= alpha_min box crosses the longitude seam of the ERP
+        image: centre column minus the screen radius below 0 or plus it past
+        the width (synchronises)."""
+        n = int(self.state.n)
+        if n == 0:
+            return 0.0
+        rec = self._view(self.state.records, 12 * n, torch.float32).view(n, 12)
+        px = rec[:, 0].double() + rec[:, 1].double()
+        r = self._view(self.state.radii, n, torch.float32).double()
+        vis = self.n_tiles() > 0
+        W = float(self.state.width)
+        cross = vis & ((px - r < 0.0) | (px + r > W))
+        return float(cross.sum()) / max(int(vis.sum()), 1)
+
+
     def n_tiles(self):
         return self._view(self.state.n_tiles, int(self.state.n), torch.int32)
 
@@ -378,12 +402,7 @@ def omnigs_forward(g: dict, camera: dict, settings: dict | None = None, allocato
                          out.get("depth"), overflow)
 
 
-def omnigs_backward(g: dict, camera: dict, settings: dict | None, fwd: ForwardResult, dL_dimage: torch.Tensor,
-                    allocator: Allocator | None = None, grads: dict | None = None,
-                    dL_ddepth: torch.Tensor | None = None, dL_dalpha: torch.Tensor | None = None) -> dict:
-    """Gradients of <dL_dimage, image> (+ <dL_ddepth, depth> + <dL_dalpha,
-    1 - final_T>, each optional) w.r.t. the parameters."""
-    lib = load_library()
+def _backward_call(g, camera, settings, fwd, dL_dimage, grads, dL_ddepth, dL_dalpha, call):
     dev = g["means"].device
     n = int(g["means"].shape[0])
     cg, cc, cs = make_gaussians(g), make_camera(camera), make_settings(settings)
@@ -397,11 +416,21 @@ def omnigs_backward(g: dict, camera: dict, settings: dict | None, fwd: ForwardRe
     cgr = c_grads(_ptr(grads["means"]), _ptr(grads["scales"]), _ptr(grads["quats"]), _ptr(grads["opacities"]),
                   _ptr(grads["sh"]), _ptr(grads["screen"]))
     co = c_image_out(_ptr(fwd.image), _ptr(fwd.final_T), _ptr(fwd.n_contrib), None, None)
-    al = allocator or Allocator(dev)
-    _check(lib.omnigs_backward(ctypes.byref(cg), ctypes.byref(cc), ctypes.byref(cs), ctypes.byref(fwd.state),
-                               ctypes.byref(co), ctypes.c_void_p(dL_dimage.data_ptr()),
-                               ctypes.c_void_p(_ptr(dL_ddepth)), ctypes.c_void_p(_ptr(dL_dalpha)),
-                               ctypes.byref(cgr), al.c, ctypes.c_void_p(_stream_ptr(dev))))
+    call(ctypes.byref(cg), ctypes.byref(cc), ctypes.byref(cs), ctypes.byref(fwd.state), ctypes.byref(co),
+         ctypes.c_void_p(dL_dimage.data_ptr()), ctypes.c_void_p(_ptr(dL_ddepth)), ctypes.c_void_p(_ptr(dL_dalpha)),
+         ctypes.byref(cgr), ctypes.c_void_p(_stream_ptr(dev)))
+    return grads
+
+
+def omnigs_backward(g: dict, camera: dict, settings: dict | None, fwd: ForwardResult, dL_dimage: torch.Tensor,
+                    allocator: Allocator | None = None, grads: dict | None = None,
+                    dL_ddepth: torch.Tensor | None = None, dL_dalpha: torch.Tensor | None = None) -> dict:
+    """Gradients of <dL_dimage, image> (+ <dL_ddepth, depth> + <dL_dalpha,
+    1 - final_T>, each optional) w.r.t. the parameters."""
+    lib = load_library()
+    al = allocator or Allocator(g["means"].device)
+    grads = _backward_call(g, camera, settings, fwd, dL_dimage, grads, dL_ddepth, dL_dalpha,
+                           lambda *a: _check(lib.omnigs_backward(*a[:9], al.c, a[9])))
     al.scratch.clear()
     return grads
 
@@ -623,6 +652,41 @@ def omnigs_profile_read() -> dict:
     cnt = (ctypes.c_int64 * n)()
     _check(lib.omnigs_profile_read(ms, cnt))
     return {lib.omnigs_profile_stage_name(k).decode(): (ms[k], int(cnt[k])) for k in range(n)}
+
+
+class c_ceilings(ctypes.Structure):
+    _fields_ = [("fma_tflops", ctypes.c_double), ("exp_gops", ctypes.c_double), ("atomic_gops", ctypes.c_double),
+                ("copy_gbps", ctypes.c_double)]
+
+
+def omnigs_measure_ceilings(atomic_words: int = 10 << 20, copy_bytes: int = 256 << 20, repeats: int = 5,
+                            device: str = "cuda:0", allocator: Allocator | None = None) -> dict:
+    """Measured FP32 FMA (TFLOP/s), exp2 (G/s), scattered float atomic (G/s)
+    and copy (GB/s, read + written) rates of the device."""
+    lib = load_library()
+    dev = torch.device(device)
+    A = allocator or Allocator(dev)
+    out = c_ceilings()
+    with torch.cuda.device(dev):
+        _check(lib.omnigs_measure_ceilings(int(atomic_words), int(copy_bytes), int(repeats), A.c, ctypes.byref(out),
+                                           ctypes.c_void_p(_stream_ptr(dev))))
+    A.scratch.clear()
+    return {k: getattr(out, k) for k, _ in c_ceilings._fields_}
+
+
+def omnigs_selftest_lookback(primitive: str, n: int, max_polls: int = 0, device: str = "cuda:0") -> tuple:
+    """(fault bits, exact) of the sort ("sort") or scan ("scan") primitive on
+    n device-generated keys with the lookback poll bound set to max_polls (0:
+    the library's)."""
+    lib = load_library()
+    dev = torch.device(device)
+    A = Allocator(dev)
+    fault, correct = ctypes.c_uint32(0), ctypes.c_int32(0)
+    with torch.cuda.device(dev):
+        _check(lib.omnigs_selftest_lookback({"sort": 0, "scan": 1}[primitive], int(n), int(max_polls), A.c,
+                                            ctypes.byref(fault), ctypes.byref(correct),
+                                            ctypes.c_void_p(_stream_ptr(dev))))
+    return int(fault.value), bool(correct.value)
 
 
 def tile_sort_bits(width: int, height: int) -> int:

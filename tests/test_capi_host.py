@@ -170,6 +170,16 @@ def test_l1_and_backward_argument_checks(lib):
     assert rc == B.OMNIGS_ERR_INVALID and "state does not match" in B.omnigs_last_error()
 
 
+def test_ceilings_argument_checks(lib):
+    alloc, calls, keep = _alloc(fail=True)
+    out = B.c_ceilings()
+    assert lib.omnigs_measure_ceilings(0, 0, 0, alloc, ctypes.byref(out), None) == B.OMNIGS_ERR_INVALID
+    assert lib.omnigs_measure_ceilings(1 << 32, 0, 1, alloc, ctypes.byref(out), None) == B.OMNIGS_ERR_INVALID
+    assert lib.omnigs_measure_ceilings(0, 17, 1, alloc, ctypes.byref(out), None) == B.OMNIGS_ERR_INVALID
+    assert lib.omnigs_measure_ceilings(1024, 1 << 20, 1, alloc, None, None) == B.OMNIGS_ERR_INVALID
+    assert lib.omnigs_measure_ceilings(1024, 1 << 20, 1, alloc, ctypes.byref(out), None) == B.OMNIGS_ERR_ALLOC
+
+
 def test_profile_stage_names(lib):
     n = lib.omnigs_profile_num_stages()
     names = [lib.omnigs_profile_stage_name(k).decode() for k in range(n)]
