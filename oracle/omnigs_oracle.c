@@ -636,8 +636,8 @@ static void walk_one(const orc_scene *s, const orc_proj *P, int32_t gid, const o
  * FP64 decisions).  Flagged decisions: alpha within a relative margin of
  * alpha_min, T(1 - alpha) within one of T_min, and the order of two list
  * neighbours whose depths agree to within the float32 resolution of the
- * depth key when this pixel may blend both (inverted: the pair is walked
- * swapped).  contrib (may be NULL) receives the blended instances in order. */
+ * depth key when this pixel may blend either of them (inverted: the pair is
+ * walked swapped; with one of them blended, only its position changes).  contrib (may be NULL) receives the blended instances in order. */
 static void render_pixel(const orc_scene *s, const orc_lists *L, int64_t start, int64_t end, int x, int y,
                          uint64_t flips, orc_pixel *out, orc_contrib *contrib) {
     orc_walk w;
@@ -651,12 +651,14 @@ static void render_pixel(const orc_scene *s, const orc_lists *L, int64_t start, 
         const orc_proj *P = &L->P[I->gid];
         orc_eval e;
         eval_at(s, P, s->opac[I->gid], x, y, &e);
-        if (k + 1 < end && e.araw >= lo && fabs(L->inst[k + 1].tr / I->tr - 1.0) < s->flag_rel_depth) {
+        if (k + 1 < end && fabs(L->inst[k + 1].tr / I->tr - 1.0) < s->flag_rel_depth) {
             const orc_inst *J = &L->inst[k + 1];
             const orc_proj *PJ = &L->P[J->gid];
             orc_eval f;
             eval_at(s, PJ, s->opac[J->gid], x, y, &f);
-            if (f.araw >= lo && flagged(&w, 0)) {
+            /* the order matters when either may blend: with both, the
+             * image; with one, its list position (the contributor count) */
+            if ((e.araw >= lo || f.araw >= lo) && flagged(&w, 0)) {
                 walk_one(s, PJ, J->gid, &f, k - start, &w, contrib);
                 if (!w.stopped) walk_one(s, P, I->gid, &e, k + 1 - start, &w, contrib);
                 k += 2;

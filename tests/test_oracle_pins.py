@@ -574,6 +574,28 @@ def test_depth_tie_is_one_flag_with_the_swapped_order_as_its_branch():
     assert (br["n_contrib"][k, :2] == 2).all()
 
 
+def test_depth_tie_with_one_blended_member_moves_its_position():
+    """A depth tie where the pixel blends only one of the pair (the other is
+    a tiny Gaussian elsewhere in the tile): the order still decides the list
+    position of the blended one, so the tie is flagged, and its two branches
+    have the same image and transmittance and contributor counts 2 and 1."""
+    W, H, x, y = 64, 32, 21, 12
+    ms = np.array([_at_pixel(28, 5, W, H, 3.0), _at_pixel(x, y, W, H, 3.0 * (1 + 1e-8))])
+    g = _single(ms, scales=np.array([[0.02] * 3, [0.3] * 3]), opac=np.array([0.8, 0.7]), dc=0.4)
+    sc = O.Scene(g, scenes.camera(W, H))
+    t, gid, tr = O.tile_lists(sc)
+    tile = (y // 16) * (W // 16) + x // 16
+    assert list(gid[t == tile]) == [0, 1]
+    r = O.render(sc)
+    assert r["n_flags"][y, x] == 1 and r["n_contrib"][y, x] == 2 and r["n_blended"][y, x] == 1
+    br = r["branches"]
+    k = int(np.searchsorted(br["pixels"], y * W + x))
+    assert br["count"][k] == 2
+    np.testing.assert_array_equal(br["image"][k, 0], br["image"][k, 1])
+    assert br["final_T"][k, 0] == br["final_T"][k, 1] == pytest.approx(0.3)
+    assert sorted(br["n_contrib"][k, :2]) == [1, 2]
+
+
 def test_two_flagged_decisions_enumerate_four_branches():
     """Two Gaussians whose alpha at the pixel equals alpha_min to 1e-7: each
     may be blended or skipped, so the pixel has exactly four results (none,
