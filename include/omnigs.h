@@ -288,6 +288,16 @@ omnigs_status omnigs_forward_batch(const omnigs_gaussians *g, const omnigs_camer
                                    int64_t instance_capacity, int32_t *overflow, int64_t *n_instances,
                                    void *stream);
 
+/* Device bytes that omnigs_forward_batch with these cameras (host, checked
+ * as there), n Gaussians and instance_capacity > 0 requests from its
+ * allocator (the sum of its requests, each rounded up to 256 bytes), so that
+ * a scheduler can admit a batch by HBM footprint before enqueuing it; the
+ * caller's outputs come on top.  Host arithmetic only: nothing is enqueued.
+ * OMNIGS_ERR_INVALID for n outside [0, 2^31), instance_capacity outside
+ * [1, 2^32), batch out of range, a bad camera or batch * n >= 2^32. */
+omnigs_status omnigs_forward_batch_bytes(int64_t n, const omnigs_camera *cams, int32_t batch,
+                                         int64_t instance_capacity, uint64_t *bytes);
+
 /* ------------------------------------------------------------------------
  * Optimisation around the rasterizer (Sec. 4, Alg. 1).  The paper leaves
  * the optimizer and the densification rules to 3DGS (and to its absent

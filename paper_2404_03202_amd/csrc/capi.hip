@@ -440,6 +440,53 @@ omnigs_status backward_impl(const omnigs_gaussians *g, const omnigs_camera *cam,
     return OMNIGS_OK;
 }
 
+// Buffers of omnigs_forward_batch.  Its allocations and the size query
+// omnigs_forward_batch_bytes run the same carving (a measuring pass on a
+// null arena gives the byte count that the allocator is asked for).
+struct BatchBuffers {
+    GeomState gst;
+    GeomScratch gs;
+    uint32_t *inst_gauss = nullptr, *order = nullptr;
+    uint2 *ranges = nullptr;
+    BinScratch bs;
+    void carve_records(Arena &a, int64_t nrec) {
+        gst.carve(a, nrec);
+        gs.carve(a, nrec);
+    }
+    void carve_instances(Arena &a, uint64_t inst_cap, uint64_t super_cap, uint32_t ntiles, const Grids &G) {
+        inst_gauss = a.take<uint32_t>((size_t)(inst_cap > 0 ? inst_cap : 1));
+        ranges = a.take<uint2>(ntiles);
+        order = a.take<uint32_t>(ntiles);
+        bs.carve(a, super_cap, G.n_super);
+    }
+};
+
+// The bytes alloc_arena requests for an arena of `off` measured bytes.
+size_t arena_request(size_t off) { return align_up(off == 0 ? kAlign : off); }
+
+// Camera checks and the grids of a batch: tiles per frame, stacked.
+omnigs_status batch_grids(const omnigs_camera *cams, int32_t batch, int64_t n, Grids &G, uint64_t &total_tiles) {
+    if (batch < 1 || batch > kMaxBatch) return fail(OMNIGS_ERR_INVALID, "batch %d not in [1, %d]", batch, kMaxBatch);
+    if (!cams) return fail(OMNIGS_ERR_INVALID, "cameras is NULL");
+    G = Grids{};
+    G.ef.n_per = n > 0 ? n : 1;
+    G.ef.count = batch;
+    G.ef.super = 1;
+    G.sup.count = batch;
+    total_tiles = 0;
+    omnigs_status rc;
+    for (int b = 0; b < batch; ++b) {
+        if ((rc = check_camera(&cams[b])) != OMNIGS_OK) return rc;
+        const int tiles_x = (cams[b].width + kTile - 1) / kTile;
+        const int rows = cams[b].rows > 0 ? cams[b].rows : cams[b].height;
+        const int tiles_y = (rows + kTile - 1) / kTile;
+        total_tiles += (uint64_t)tiles_x * tiles_y;
+        if (total_tiles >= (uint64_t(1) << 31)) return fail(OMNIGS_ERR_INVALID, "too many tiles in the batch");
+        G.add(b, tiles_x, tiles_y);
+    }
+    return OMNIGS_OK;
+}
+
 }  // namespace
 
 // ============================================================== public API
@@ -752,6 +799,27 @@ omnigs_status omnigs_photometric_loss(const float *image, const float *target, i
     return OMNIGS_OK;
 }
 
+omnigs_status omnigs_forward_batch_bytes(int64_t n, const omnigs_camera *cams, int32_t batch,
+                                         int64_t instance_capacity, uint64_t *bytes) {
+    if (!bytes) return fail(OMNIGS_ERR_INVALID, "bytes is NULL");
+    *bytes = 0;
+    if (n < 0 || n >= (int64_t(1) << 31)) return fail(OMNIGS_ERR_INVALID, "n = %lld out of range", (long long)n);
+    if (instance_capacity < 1 || instance_capacity >= (int64_t(1) << 32))
+        return fail(OMNIGS_ERR_INVALID, "instance_capacity %lld not in [1, 2^32)", (long long)instance_capacity);
+    Grids G;
+    uint64_t total_tiles = 0;
+    omnigs_status rc;
+    if ((rc = batch_grids(cams, batch, n, G, total_tiles)) != OMNIGS_OK) return rc;
+    const int64_t nrec = n * batch;
+    if (nrec >= (int64_t(1) << 32) - 1) return fail(OMNIGS_ERR_INVALID, "batch * n must stay below 2^32");
+    BatchBuffers bb;
+    Arena ra, ia;
+    bb.carve_records(ra, nrec);
+    bb.carve_instances(ia, (uint64_t)instance_capacity, (uint64_t)instance_capacity, (uint32_t)total_tiles, G);
+    *bytes = arena_request(ra.off) + arena_request(ia.off);
+    return OMNIGS_OK;
+}
+
 omnigs_status omnigs_forward_batch(const omnigs_gaussians *g, const omnigs_camera *cams, int32_t batch,
                                    const omnigs_settings *s, omnigs_allocator alloc, omnigs_image_out *outs,
                                    int64_t instance_capacity, int32_t *overflow, int64_t *n_instances,
@@ -760,25 +828,20 @@ omnigs_status omnigs_forward_batch(const omnigs_gaussians *g, const omnigs_camer
     if (n_instances) *n_instances = -1;
     if ((rc = check_gaussians(g)) != OMNIGS_OK) return rc;
     if ((rc = check_settings(s)) != OMNIGS_OK) return rc;
-    if (batch < 1 || batch > kMaxBatch) return fail(OMNIGS_ERR_INVALID, "batch %d not in [1, %d]", batch, kMaxBatch);
     if (!cams || !outs) return fail(OMNIGS_ERR_INVALID, "cameras or outputs is NULL");
     if (!alloc.alloc) return fail(OMNIGS_ERR_INVALID, "allocator callback is NULL");
     if (instance_capacity < 0 || instance_capacity >= (int64_t(1) << 32))
         return fail(OMNIGS_ERR_INVALID, "instance_capacity %lld out of range", (long long)instance_capacity);
     const int64_t n = g->n;
+    Grids G;
+    uint64_t total_tiles = 0;
+    if ((rc = batch_grids(cams, batch, n, G, total_tiles)) != OMNIGS_OK) return rc;
     const int64_t nrec = n * batch;  // record b * n + i: camera b, Gaussian i
     if (nrec >= (int64_t(1) << 32) - 1) return fail(OMNIGS_ERR_INVALID, "batch * n must stay below 2^32");
-    uint64_t total_tiles = 0;
     FrameGeom frames[kMaxBatch];
     CamTable ct{};
     ct.count = batch;
-    Grids G;
-    G.ef.n_per = n > 0 ? n : 1;
-    G.ef.count = batch;
-    G.ef.super = 1;
-    G.sup.count = batch;
     for (int b = 0; b < batch; ++b) {
-        if ((rc = check_camera(&cams[b])) != OMNIGS_OK) return rc;
         if (!outs[b].image || !outs[b].final_T || !outs[b].n_contrib)
             return fail(OMNIGS_ERR_INVALID, "output pointer of camera %d is NULL", b);
         if ((outs[b].depth != nullptr) != (outs[0].depth != nullptr))
@@ -800,27 +863,21 @@ omnigs_status omnigs_forward_batch(const omnigs_gaussians *g, const omnigs_camer
         cg.fy = pb.fy;
         cg.cx = pb.cx;
         cg.cy = pb.cy;
-        frames[b] = FrameGeom{pb.width, pb.rows, pb.tiles_x, pb.tiles_y, (uint32_t)total_tiles,
+        frames[b] = FrameGeom{pb.width, pb.rows, pb.tiles_x, pb.tiles_y, G.sup.f[b].tile_base,
                               pb.model == OMNIGS_CAMERA_ERP};
-        total_tiles += (uint64_t)pb.tiles_x * pb.tiles_y;
-        if (total_tiles >= (uint64_t(1) << 31)) return fail(OMNIGS_ERR_INVALID, "too many tiles in the batch");
-        G.add(b, pb.tiles_x, pb.tiles_y);
     }
     const ProjectArgs pa = make_project_args(g, &cams[0], s);
     hipStream_t st = static_cast<hipStream_t>(stream);
     const uint32_t ntiles = (uint32_t)total_tiles;
 
     // per-record buffers (all scratch: no backward state is kept)
+    BatchBuffers bb;
+    GeomState &gst = bb.gst;
+    GeomScratch &gs = bb.gs;
     Arena ra;
-    GeomState gst;
-    GeomScratch gs;
-    auto carve_geom = [&](Arena &a) {
-        gst.carve(a, nrec);
-        gs.carve(a, nrec);
-    };
-    carve_geom(ra);
+    bb.carve_records(ra, nrec);
     if ((rc = alloc_arena(alloc, ra.off, OMNIGS_MEM_SCRATCH, ra, "per-record scratch")) != OMNIGS_OK) return rc;
-    carve_geom(ra);
+    bb.carve_records(ra, nrec);
     if (overflow) HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(overflow), 0u, 1, st));
     HIP_TRY(launch_fill_u32(gst.totals + 2, 0u, 1, st));  // fault bits
     {
@@ -849,30 +906,20 @@ omnigs_status omnigs_forward_batch(const omnigs_gaussians *g, const omnigs_camer
         super_cap = inst_cap;
     }
     Arena ia;
-    uint32_t *inst_gauss, *order;
-    uint2 *ranges;
-    BinScratch bs;
-    auto carve_inst = [&](Arena &a) {
-        inst_gauss = a.take<uint32_t>((size_t)(inst_cap > 0 ? inst_cap : 1));
-        ranges = a.take<uint2>(ntiles);
-        order = a.take<uint32_t>(ntiles);
-        bs.carve(a, super_cap, G.n_super);
-    };
-    carve_inst(ia);
+    bb.carve_instances(ia, inst_cap, super_cap, ntiles, G);
     if ((rc = alloc_arena(alloc, ia.off, OMNIGS_MEM_SCRATCH, ia, "instance lists")) != OMNIGS_OK) return rc;
-    carve_inst(ia);
-    if ((rc = run_binning(nrec, gst, gs, G, super_cap, inst_cap, counted, bs, ranges, inst_gauss, overflow, st)) !=
-        OMNIGS_OK)
+    bb.carve_instances(ia, inst_cap, super_cap, ntiles, G);
+    if ((rc = run_binning(nrec, gst, gs, G, super_cap, inst_cap, counted, bb.bs, bb.ranges, bb.inst_gauss, overflow,
+                          st)) != OMNIGS_OK)
         return rc;
     {
         StageTimer t(st, kStTileOrder);
-        HIP_TRY(launch_tile_order(ranges, nullptr, ntiles, order, st));
+        HIP_TRY(launch_tile_order(bb.ranges, nullptr, ntiles, bb.order, st));
     }
     {
         StageTimer t(st, kStBlendFwd);
-        HIP_TRY(launch_blend_forward_frames(frames, outs, batch, gst.rec, gst.depth, inst_gauss, ranges,
-                                            make_blend_settings(s),
-                                            order, ntiles, st));
+        HIP_TRY(launch_blend_forward_frames(frames, outs, batch, gst.rec, gst.depth, bb.inst_gauss, bb.ranges,
+                                            make_blend_settings(s), bb.order, ntiles, st));
     }
     return OMNIGS_OK;
 }

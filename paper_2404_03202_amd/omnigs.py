@@ -109,7 +109,7 @@ EXPORTS = ("omnigs_default_settings", "omnigs_forward", "omnigs_backward", "omni
            "omnigs_adam_step", "omnigs_accumulate_stats", "omnigs_densify", "omnigs_reset_opacity",
            "omnigs_last_error", "omnigs_profile_enable", "omnigs_profile_num_stages", "omnigs_profile_stage_name",
            "omnigs_profile_read", "omnigs_measure_ceilings",
-           "omnigs_selftest_lookback")
+           "omnigs_selftest_lookback", "omnigs_forward_batch_bytes")
 
 _lib = None
 _lib_lock = threading.Lock()
@@ -143,6 +143,9 @@ def load_library(path: str = LIB_PATH):
         lib.omnigs_forward_batch.argtypes = [P(c_gaussians), P(c_camera), ctypes.c_int32, P(c_settings), c_allocator,
                                              P(c_image_out), ctypes.c_int64, vp, P(ctypes.c_int64), vp]
         lib.omnigs_forward_batch.restype = ctypes.c_int
+        lib.omnigs_forward_batch_bytes.argtypes = [ctypes.c_int64, P(c_camera), ctypes.c_int32, ctypes.c_int64,
+                                                   P(ctypes.c_uint64)]
+        lib.omnigs_forward_batch_bytes.restype = ctypes.c_int
         lib.omnigs_adam_step.argtypes = [P(c_params), P(c_grads), P(c_params), P(c_params), P(c_adam_settings),
                                          P(c_gaussians), vp, vp]
         lib.omnigs_adam_step.restype = ctypes.c_int
@@ -533,6 +536,23 @@ def omnigs_forward_batch(g: dict, cameras: list, settings: dict | None = None, i
     # ordered after the enqueued kernels on this stream
     del keep
     return BatchResult(outs, overflow, int(m.value), [])
+
+
+def omnigs_forward_batch_bytes(n: int, cameras: list, instance_capacity: int) -> int:
+    """Device bytes omnigs_forward_batch requests from its allocator for n
+    Gaussians, these cameras and an instance capacity (outputs excluded)."""
+    lib = load_library()
+    cams = (c_camera * max(len(cameras), 1))(*[make_camera(c) for c in cameras])
+    out = ctypes.c_uint64(0)
+    _check(lib.omnigs_forward_batch_bytes(int(n), cams, len(cameras), int(instance_capacity), ctypes.byref(out)))
+    return int(out.value)
+
+
+def output_bytes(camera: dict, with_blended: bool = False, with_depth: bool = False) -> int:
+    """Bytes of one camera's forward outputs: image [3,H,W], final_T and
+    n_contrib [H,W] (+ n_blended, depth)."""
+    px = image_rows(camera) * int(camera["width"])
+    return px * 4 * (5 + int(with_blended) + int(with_depth))
 
 
 # ------------------------------------------------------------- optimisation

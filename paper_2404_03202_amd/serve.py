@@ -32,15 +32,6 @@ import torch
 
 from . import omnigs as B
 
-# bytes per item of what a batch allocates (omnigs_forward_batch's scratch
-# and outputs): per (camera, Gaussian) record, per instance, per pixel and
-# per tile; used to admit requests by footprint
-BYTES_PER_RECORD = 90
-BYTES_PER_INSTANCE = 17
-BYTES_PER_PIXEL = 20
-BYTES_PER_TILE = 12
-
-
 @dataclasses.dataclass
 class Request:
     rid: int
@@ -65,10 +56,12 @@ def _tiles(camera) -> int:
     return ((int(camera["width"]) + 15) // 16) * ((int(camera["height"]) + 15) // 16)
 
 
-def footprint(n_gaussians: int, width: int, height: int, instances: int) -> int:
-    tiles = ((width + 15) // 16) * ((height + 15) // 16)
-    return (n_gaussians * BYTES_PER_RECORD + instances * BYTES_PER_INSTANCE + width * height * BYTES_PER_PIXEL
-            + tiles * BYTES_PER_TILE)
+def footprint(n_gaussians: int, cameras: list, instances: int) -> int:
+    """HBM bytes of one batch: what omnigs_forward_batch allocates for these
+    cameras and instance capacity (the library's own size query) plus the
+    outputs the server allocates."""
+    return (B.omnigs_forward_batch_bytes(n_gaussians, cameras, instances)
+            + sum(B.output_bytes(c) for c in cameras))
 
 
 class _Slot:
@@ -119,8 +112,10 @@ class Server:
                 self.est[key] = 16 * self.n
         return int(self.est[key] * self.margin) + 1024
 
-    def request_bytes(self, req: Request) -> int:
-        return footprint(self.n, int(req.camera["width"]), int(req.camera["height"]), self.instances_for(req))
+    def batch_bytes(self, batch: list) -> int:
+        """Footprint of a batch with the capacity it is launched with."""
+        cap = min(sum(self.instances_for(r) for r in batch), (1 << 32) - 1)
+        return footprint(self.n, [r.camera for r in batch], cap)
 
     def calibrate(self, cameras):
         """Render each distinct resolution once alone (instance count read
@@ -143,7 +138,7 @@ class Server:
             r.start = now
             r.batch_size = len(batch)
         slot.batch, slot.result = batch, res
-        slot.bytes = sum(self.request_bytes(r) for r in batch)
+        slot.bytes = self.batch_bytes(batch)
         self.batches += 1
 
     def _finish(self, slot: _Slot, now: float, queue: collections.deque, done: list):
@@ -188,14 +183,14 @@ class Server:
                 # whole budget still runs, alone, when nothing else is in flight
                 batch, need, tiles = [], 0, 0
                 while queue and len(batch) < self.max_batch:
-                    b = self.request_bytes(queue[0])
-                    if in_flight + need + b > self.budget and (batch or in_flight > 0):
+                    b = self.batch_bytes(batch + [queue[0]])
+                    if in_flight + b > self.budget and (batch or in_flight > 0):
                         break
                     t = _tiles(queue[0].camera)
                     if batch and tiles + t > self.max_tiles:
                         break
                     batch.append(queue.popleft())
-                    need += b
+                    need = b
                     tiles += t
                 if not batch:
                     break

@@ -242,3 +242,27 @@ def test_forward_batch_allocator_failure(lib):
     assert rc == B.OMNIGS_ERR_ALLOC
     # one scratch allocation holding the records of both cameras
     assert len(calls) == 1 and calls[0][1] == B.OMNIGS_MEM_SCRATCH and calls[0][0] >= 2 * 1000 * 48
+
+
+def test_forward_batch_bytes_host_query(lib):
+    """The size query runs on the host: it grows by exactly 4 bytes per
+    instance of capacity (the Gaussian id) plus the block-entry scratch
+    sized by the same capacity, by the per-record buffers per Gaussian and
+    camera, and rejects what omnigs_forward_batch rejects."""
+    from paper_2404_03202_amd import scenes
+    cams = [scenes.camera(w, h) for (w, h) in scenes.SERVE_RESOLUTIONS]
+    q = lambda n, cs, cap: B.omnigs_forward_batch_bytes(n, cs, cap)
+    base = q(100_000, cams[:1], 1 << 20)
+    assert base > 100_000 * 48  # at least the blend records
+    # linear in the capacity once the per-capacity buffers dominate
+    d1 = q(100_000, cams[:1], 2 << 20) - base
+    d2 = q(100_000, cams[:1], 3 << 20) - q(100_000, cams[:1], 2 << 20)
+    assert abs(d1 - d2) <= 4096 and d1 >= 4 * (1 << 20)
+    # more cameras: more records and tiles
+    assert q(100_000, cams, 1 << 20) > q(100_000, cams[:2], 1 << 20) > base
+    for bad in ((-1, cams[:1], 1), (10, cams[:1], 0), (10, [], 1), (10, cams * 5, 1)):
+        with pytest.raises(B.OmnigsError):
+            q(*bad)
+    odd = dict(scenes.camera(64, 32), width=60)
+    with pytest.raises(B.OmnigsError, match="multiple of 16"):
+        q(10, [odd], 1)

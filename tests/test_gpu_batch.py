@@ -146,7 +146,7 @@ def test_serving_admission_by_footprint(room):
     cams = scenes.serve_cameras(94, 12, SERVE_RES)
     srv = serve.Server(room, slots=2, max_batch=8)
     srv.calibrate([scenes.camera(w, h) for (w, h) in SERVE_RES])
-    smallest = min(srv.request_bytes(r) for r in serve.make_requests(cams))
+    smallest = min(srv.batch_bytes([r]) for r in serve.make_requests(cams))
     # a budget below any two requests' footprint: one request in flight at a time
     srv.budget = smallest + 1
     out = srv.run(serve.make_requests(cams))
@@ -155,6 +155,28 @@ def test_serving_admission_by_footprint(room):
     srv.calibrate([scenes.camera(w, h) for (w, h) in SERVE_RES])
     out = srv.run(serve.make_requests(cams))
     assert out["mean_batch"] > 1.0
+
+
+def test_footprint_matches_allocations(room):
+    """The footprint the server admits by (the library's size query plus the
+    outputs) equals what one batch takes from the caching allocator, up to
+    the allocator's 512-byte rounding of each block."""
+    cams = [scenes.camera(w, h, scenes.rot_y(0.3 * k).T, [0.1 * k, 0.0, 0.0]) for k, (w, h) in enumerate(SERVE_RES)]
+    counts = [alone(room, c)[1] for c in cams]
+    cap = int(1.1 * sum(counts)) + 1
+    n = int(room["means"].shape[0])
+    expect = serve.footprint(n, cams, cap)
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    torch.cuda.reset_peak_memory_stats()
+    res = B.omnigs_forward_batch(room, cams, instance_capacity=cap)
+    torch.cuda.synchronize()
+    peak = torch.cuda.max_memory_allocated() - base
+    assert int(res.overflow) == 0
+    blocks = 2 + 3 * len(cams) + 1  # two scratch arenas, three outputs per camera, the overflow word
+    assert expect <= peak <= expect + 512 * blocks, (expect, peak)
+    with pytest.raises(B.OmnigsError):
+        B.omnigs_forward_batch_bytes(n, cams, 0)
 
 
 def test_serving_sampled_oracle():
