@@ -20,6 +20,8 @@
  *       them as soon as the call returns);
  *     OMNIGS_MEM_STATE allocations back an omnigs_state and must stay alive
  *       until the last omnigs_backward that uses that state has run.
+ *   omnigs_backward_noalloc is the exception: it allocates nothing and takes
+ *   its scratch from a fixed device array of the library.
  * - Errors: every entry point returns an omnigs_status.  On a non-OK status
  *   nothing valid was produced, and omnigs_last_error() returns a
  *   thread-local message.  No exception crosses the ABI.
@@ -232,6 +234,22 @@ omnigs_status omnigs_backward(const omnigs_gaussians *g, const omnigs_camera *ca
                               const omnigs_state *state, const omnigs_image_out *fwd, const float *dL_dimage,
                               const float *dL_ddepth, const float *dL_dalpha, omnigs_grads *grads,
                               omnigs_allocator alloc, void *stream);
+
+/* omnigs_backward for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving or training loops, harnesses that forbid
+ * hipMalloc): the same checks, kernels and results, with the gradient
+ * accumulators and the tile launch order in a fixed 64 MiB device array of
+ * the library instead of `alloc` scratch; no device memory is allocated.
+ * It holds (10 n + tiles) 32-bit words, about 1.6M Gaussians at 2048x1024;
+ * a larger call returns OMNIGS_ERR_INVALID before enqueuing anything.  Each
+ * device has its own array, shared by every call on that device and cleared
+ * by each call before use: calls that overlap on one device (other streams,
+ * other host threads) race and must be serialised by the caller.  Arguments,
+ * outputs and other errors as omnigs_backward. */
+omnigs_status omnigs_backward_noalloc(const omnigs_gaussians *g, const omnigs_camera *cam, const omnigs_settings *s,
+                                      const omnigs_state *state, const omnigs_image_out *fwd, const float *dL_dimage,
+                                      const float *dL_ddepth, const float *dL_dalpha, omnigs_grads *grads,
+                                      void *stream);
 
 /* L1 photometric term of Eq. 17 (lambda = 0): *loss = mean |image - target|
  * over `count` float32 entries, and dL_dimage = sign(image - target) / count

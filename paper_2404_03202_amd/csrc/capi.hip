@@ -380,7 +380,36 @@ void bin_clear(uint64_t super_cap, const Grids &G, BinScratch &bs, ClearList &L)
     binning_clear(bs.bin_tmp, super_cap, G.n_super, L);
 }
 
+// Device scratch of omnigs_backward_noalloc (gradient accumulators and the
+// tile launch order of one backward), for callers that cannot allocate.
+// Every device the library runs on holds its own copy until the process
+// ends; host code reaches it only through the address that
+// hipGetSymbolAddress returns on that device (the array's name in host code
+// is a host-side stand-in, not a device address).
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+char *g_noalloc_ptr[kMaxDevices] = {};
+
+// The current device's copy of `scratch`, looked up once per device.
+omnigs_status noalloc_scratch(char *&base) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(OMNIGS_ERR_INVALID, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(OMNIGS_ERR_HIP, "hipGetSymbolAddress returned NULL for the no-alloc scratch");
+        g_noalloc_ptr[dev] = static_cast<char *>(p);
+    }
+    base = g_noalloc_ptr[dev];
+    return OMNIGS_OK;
+}
 
 // The checks and stages of the backward on caller-provided scratch: `carve`
 // maps the accumulator and tile-order sizes to their buffers (or fails).
@@ -658,6 +687,31 @@ omnigs_status omnigs_backward(const omnigs_gaussians *g, const omnigs_camera *ca
         a.take<uint32_t>(ntiles);
         omnigs_status rc;
         if ((rc = alloc_arena(alloc, a.off, OMNIGS_MEM_SCRATCH, a, "gradient accumulators")) != OMNIGS_OK) return rc;
+        acc = a.take<float>(acc_words);
+        order = a.take<uint32_t>(ntiles);
+        return OMNIGS_OK;
+    };
+    return backward_impl(g, cam, s, state, fwd, dL_dimage, dL_ddepth, dL_dalpha, grads, stream, carve);
+}
+
+omnigs_status omnigs_backward_noalloc(const omnigs_gaussians *g, const omnigs_camera *cam,
+                                      const omnigs_settings *s, const omnigs_state *state,
+                                      const omnigs_image_out *fwd, const float *dL_dimage, const float *dL_ddepth,
+                                      const float *dL_dalpha, omnigs_grads *grads, void *stream) {
+    auto carve = [&](size_t acc_words, size_t ntiles, float *&acc, uint32_t *&order) -> omnigs_status {
+        Arena a;
+        a.take<float>(acc_words);
+        a.take<uint32_t>(ntiles);
+        if (a.off > kNoAllocScratchBytes)
+            return fail(OMNIGS_ERR_INVALID,
+                        "omnigs_backward_noalloc: %zu Gaussians and %zu tiles need %zu bytes of accumulators and "
+                        "tile order, more than its %zu-byte device scratch",
+                        (size_t)g->n, ntiles, a.off, kNoAllocScratchBytes);
+        char *base = nullptr;
+        omnigs_status rc;
+        if ((rc = noalloc_scratch(base)) != OMNIGS_OK) return rc;
+        a.base = base;
+        a.off = 0;
         acc = a.take<float>(acc_words);
         order = a.take<uint32_t>(ntiles);
         return OMNIGS_OK;

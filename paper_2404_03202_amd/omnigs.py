@@ -109,7 +109,7 @@ EXPORTS = ("omnigs_default_settings", "omnigs_forward", "omnigs_backward", "omni
            "omnigs_adam_step", "omnigs_accumulate_stats", "omnigs_densify", "omnigs_reset_opacity",
            "omnigs_last_error", "omnigs_profile_enable", "omnigs_profile_num_stages", "omnigs_profile_stage_name",
            "omnigs_profile_read", "omnigs_measure_ceilings",
-           "omnigs_selftest_lookback", "omnigs_forward_batch_bytes")
+           "omnigs_selftest_lookback", "omnigs_backward_noalloc", "omnigs_forward_batch_bytes")
 
 _lib = None
 _lib_lock = threading.Lock()
@@ -135,6 +135,9 @@ def load_library(path: str = LIB_PATH):
         lib.omnigs_backward.argtypes = [P(c_gaussians), P(c_camera), P(c_settings), P(c_state), P(c_image_out), vp,
                                         vp, vp, P(c_grads), c_allocator, vp]
         lib.omnigs_backward.restype = ctypes.c_int
+        lib.omnigs_backward_noalloc.argtypes = [P(c_gaussians), P(c_camera), P(c_settings), P(c_state),
+                                                P(c_image_out), vp, vp, vp, P(c_grads), vp]
+        lib.omnigs_backward_noalloc.restype = ctypes.c_int
         lib.omnigs_l1_loss.argtypes = [vp, vp, ctypes.c_int64, vp, vp, c_allocator, vp]
         lib.omnigs_l1_loss.restype = ctypes.c_int
         lib.omnigs_photometric_loss.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
@@ -436,6 +439,18 @@ def omnigs_backward(g: dict, camera: dict, settings: dict | None, fwd: ForwardRe
                            lambda *a: _check(lib.omnigs_backward(*a[:9], al.c, a[9])))
     al.scratch.clear()
     return grads
+
+
+def omnigs_backward_noalloc(g: dict, camera: dict, settings: dict | None, fwd: ForwardResult,
+                            dL_dimage: torch.Tensor, grads: dict, dL_ddepth: torch.Tensor | None = None,
+                            dL_dalpha: torch.Tensor | None = None) -> dict:
+    """omnigs_backward on the library's fixed device scratch: the caller
+    passes the gradient buffers, and the call allocates no device memory."""
+    if grads is None:
+        raise ValueError("omnigs_backward_noalloc writes into caller-provided gradient buffers")
+    lib = load_library()
+    return _backward_call(g, camera, settings, fwd, dL_dimage, grads, dL_ddepth, dL_dalpha,
+                          lambda *a: _check(lib.omnigs_backward_noalloc(*a)))
 
 
 def omnigs_l1_loss(image: torch.Tensor, target: torch.Tensor, grad: bool = True, allocator: Allocator | None = None):

@@ -1,0 +1,90 @@
+"""omnigs_backward_noalloc (the backward on the library's fixed device
+scratch, for callers that cannot allocate) against omnigs_backward, through
+the C ABI: two calls in a row, the second with a smaller input (fewer
+Gaussians, smaller image), each compared with the allocating entry point on
+the same forward and with the FP64 oracle by the gradient rule (relative
+1e-3 with the |contribution| floor).  The library's array keeps the previous
+call's contents, so the second call also shows that each call clears its
+accumulators.  A call larger than the array is refused before any work.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2404_03202_amd import omnigs as B
+from paper_2404_03202_amd import scenes
+
+import parity
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+NAMES = ("means", "scales", "quats", "opacities", "sh", "screen")
+
+
+def to_dev(g):
+    d = {k: torch.from_numpy(np.ascontiguousarray(v, dtype=np.float32)).to(DEV)
+         for k, v in g.items() if k != "sh_degree"}
+    d["sh_degree"] = g["sh_degree"]
+    return d
+
+
+def empty_grads(gd):
+    n = int(gd["means"].shape[0])
+    # poisoned: every entry must be overwritten
+    z = lambda *shape: torch.full(shape, float("nan"), dtype=torch.float32, device=DEV)
+    return dict(means=z(n, 3), scales=z(n, 3), quats=z(n, 4), opacities=z(n), sh=torch.full_like(gd["sh"], float("nan")),
+                screen=z(n, 2))
+
+
+def one_case(seed, n, width, height, yaw):
+    g = scenes.shell_scene(seed, n, r0=1.0, r1=6.0, scale_lo=0.02, scale_hi=0.3)
+    cam = scenes.camera(width, height, scenes.rot_y(yaw).T, [0.1, -0.2, 0.15])
+    sc = O.Scene(g, cam)
+    orc = O.render(sc)
+    target = O.render(O.Scene(scenes.perturbed(seed, g), cam), alt=False)["image"]
+    _, dl = O.l1(orc["image"], target)
+    dl[:, orc["n_grad_flags"] > 0] = 0.0
+    gd = to_dev(g)
+    dld = torch.from_numpy(dl.astype(np.float32)).to(DEV)
+    fwd = B.omnigs_forward(gd, cam)
+    ref = B.omnigs_backward(gd, cam, None, fwd, dld)
+    out = B.omnigs_backward_noalloc(gd, cam, None, fwd, dld, empty_grads(gd))
+    torch.cuda.synchronize()
+    ga = {k: v.cpu().numpy() for k, v in out.items()}
+    gr = {k: v.cpu().numpy() for k, v in ref.items()}
+    for k in NAMES:
+        assert np.isfinite(ga[k]).all(), f"{k}: entries left unwritten"
+    ob = O.backward(sc, dl)
+    flagged = np.nonzero(O.project(sc)[:, O.REC_FIELDS["flag"]] > 0)[0]
+    rep = parity.check_grads(ga, ob, NAMES, skip_rows=flagged)
+    # the two entry points against each other: the same rule, with the
+    # allocating entry point's gradients in the oracle's place
+    ref_as_orc = {k: gr[k].astype(np.float64) for k in NAMES}
+    ref_as_orc.update({"abs_" + k: ob["abs_" + k] for k in NAMES})
+    parity.check_grads(ga, ref_as_orc, NAMES, skip_rows=flagged)
+    return fwd.n_instances, rep
+
+
+def test_noalloc_matches_backward_twice_second_smaller():
+    m1, rep1 = one_case(410, 20000, 512, 256, 0.7)
+    m2, rep2 = one_case(411, 3000, 128, 64, -1.9)
+    assert m1 > m2 > 0
+    print("no-alloc backward", rep1, rep2)
+
+
+def test_noalloc_refuses_more_than_its_scratch():
+    # 2M Gaussians need 2M x 9 accumulator words (72 MB), beyond 64 MiB
+    n = 2_000_000
+    g = scenes.shell_scene(412, n, r0=1.0, r1=6.0, scale_lo=0.01, scale_hi=0.05, sh_degree=0)
+    cam = scenes.camera(64, 32)
+    gd = to_dev(g)
+    fwd = B.omnigs_forward(gd, cam)
+    dl = torch.zeros((3, 32, 64), dtype=torch.float32, device=DEV)
+    grads = empty_grads(gd)
+    with pytest.raises(B.OmnigsError, match="device scratch"):
+        B.omnigs_backward_noalloc(gd, cam, None, fwd, dl, grads)
+    torch.cuda.synchronize()
+    # nothing was enqueued: the gradient buffers are untouched
+    assert torch.isnan(grads["means"]).all()
