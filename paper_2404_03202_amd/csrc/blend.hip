@@ -16,6 +16,11 @@
 // image sets the period to infinity, so nothing wraps).  Pixels past the
 // image's right or bottom edge (partial last tiles) never blend.
 //
+// An instance whose centre is a turn away for part of the tile's columns
+// (seam split, below) is rare; a wave walks a batch with the per-column
+// centre select only when its list holds one (a uniform branch between two
+// instantiations of the walk).
+//
 // The lane that stages an instance also tests which quadrants its
 // alpha >= alpha_min ellipse can reach (the exact minimum of the quadratic
 // form over each quadrant's pixel-centre rectangle, with a safety margin).
@@ -33,10 +38,11 @@
 //
 // Backward reduction: a wave reduce-scatters an instance's nine gradient
 // terms across its lanes (gfx950 permlane swaps between wave halves and
-// between rows pair two fields per exchange, DPP finishes inside the rows: no
-// LDS traffic), and one lane per row adds up to three of the sums into the
-// instance's LDS slot; after the batch, the lane that staged the instance
-// converts the sums to screen-space gradients in place, and the workgroup
+// between rows, then DPP mirror and quad steps inside the rows, every
+// exchange carrying two fields: no LDS traffic), and the nine lanes holding
+// the sums add them into the instance's LDS slot in one instruction; after
+// the batch, the lane that staged the instance converts the sums to
+// screen-space gradients in place, and the workgroup
 // adds them to global memory with float atomics (one per nonzero field per
 // (tile, instance)), issued field-contiguous: consecutive lanes take
 // consecutive fields of the same few Gaussians.
@@ -54,6 +60,7 @@ namespace {
 
 constexpr float kLn2 = 0.69314718055994531f;
 constexpr int kQuads = 4;  // 8x8 quadrants per tile
+constexpr uint32_t kSplitBit = 1u << 31;  // staged quad mask: seam split inside the tile
 
 struct BlendFrame {
     int width, height, tiles_x, tiles_y;
@@ -193,33 +200,47 @@ __device__ inline void stage(const BlendRecord *rec, const float *rdepth, uint32
     S.b[slot] = make_float4(l11, rb4.w, rc4.x, rc4.y);
     S.c[slot] = make_float4(rc4.z, u0b, thr, kAux ? rdepth[gid] : 0.0f);
     if (kBwd) S.e[slot] = make_float4(xa, (float)xbd, y, 0.0f);
-    S.quad[slot] = quad;
+    // bit kSplitBit: the tile's columns take two centres (thr inside the tile)
+    S.quad[slot] = quad | (thr < 1e29f ? kSplitBit : 0u);
     S.gid[slot] = gid;
 }
 
 // Wave w lists, in order, the staged slots in [lo, nb) that reach one of its
-// quadrants; returns the count (uniform).
+// quadrants; returns the count (uniform) and sets `split` (uniform) when one
+// of them has its seam split inside the tile.
 template <int kW, bool kBwd>
-__device__ inline int compact(Stage<kW, kBwd> &S, int w, int lo, int nb) {
+__device__ inline int compact(Stage<kW, kBwd> &S, int w, int lo, int nb, bool &split, const int *qlo = nullptr) {
     constexpr int kPPL = kQuads / kW;
     const int lane = __lane_id();
     int n = 0;
+    bool sp = false;
     for (int c = 0; c < Stage<kW, kBwd>::kBatch; c += kWave) {
         const int slot = c + lane;
-        const uint32_t m = (slot >= lo && slot < nb) ? (S.quad[slot] >> (w * kPPL)) & ((1u << kPPL) - 1u) : 0u;
+        const uint32_t q = (slot >= lo && slot < nb) ? S.quad[slot] : 0u;
+        uint32_t m = (q >> (w * kPPL)) & ((1u << kPPL) - 1u);
+        if (qlo) {
+            // per-quadrant lower bounds: quadrant k of this wave drops slots below qlo[k]
+#pragma unroll
+            for (int k = 0; k < kPPL; ++k)
+                if (slot < qlo[k]) m &= ~(1u << k);
+        }
         const uint64_t hits = __ballot(m != 0u);
         if (m) S.list[w][n + __popcll(hits & ((1ull << lane) - 1ull))] = (uint16_t)(slot | (m << 8));
+        sp |= m != 0u && (q & kSplitBit);
         n += __popcll(hits);
     }
+    split = __ballot(sp) != 0ull;
     return n;
 }
 
 // alpha at the pixel (i, j) of the tile (integer coordinates as floats):
 // returns the unclamped alpha, writes the clamped one and
 // G = exp(-1/2 d^T Q d).
+template <bool kSplit>
 __device__ __forceinline__ float pixel_alpha(float i, float j, float4 a, float4 c, float l11, float o,
                                              float alpha_max, float &alpha, float &G) {
-    const float u0 = i >= c.z ? c.y : a.x;
+    // without a split every column takes u0a (thr lies past the tile)
+    const float u0 = (kSplit && i >= c.z) ? c.y : a.x;
     const float u = __builtin_fmaf(a.z, i, __builtin_fmaf(a.w, j, u0));  // L^T d
     const float v = __builtin_fmaf(l11, j, a.y);
     G = __builtin_amdgcn_exp2f(-__builtin_fmaf(u, u, v * v));
@@ -242,7 +263,6 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_forward(FrameTable FT, con
                                                                const uint2 *ranges, BlendSettings s,
                                                                const uint32_t *order, uint32_t *tile_work) {
     constexpr int kNT = kWave * kW, kPPL = kQuads / kW, kBatch = Stage<kW, false>::kBatch;
-    constexpr uint32_t kAll = (1u << kPPL) - 1u;
     __shared__ Stage<kW, false> S;
     __shared__ int s_wmax[kW];
     const uint32_t tile = order ? order[blockIdx.x] : blockIdx.x;
@@ -258,7 +278,8 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_forward(FrameTable FT, con
     const int count = (int)(range.y - range.x);
     float T[kPPL], C0[kPPL], C1[kPPL], C2[kPPL], Dp[kPPL];
     int last[kPPL], blended[kPPL];
-    uint32_t done = 0;
+    constexpr uint32_t kAll = (1u << kPPL) - 1u;
+    uint32_t done = 0;  // bit k: pixel k finished (stopped, or outside the image)
 #pragma unroll
     for (int k = 0; k < kPPL; ++k) {
         T[k] = 1.0f;
@@ -274,37 +295,47 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_forward(FrameTable FT, con
             stage<kDepth>(rec, rdepth, inst_gauss[range.x + base + threadIdx.x], X0, Y0, W, S, threadIdx.x);
         __syncthreads();
         if (__ballot(done != kAll) == 0ull) continue;  // this wave is finished: keep staging with the others
-        const int n = compact(S, w, 0, nb);
-        for (int t = 0; t < n; ++t) {
-            const uint32_t e = __builtin_amdgcn_readfirstlane(S.list[w][t]);
-            const int j = e & 0xff;
-            const uint32_t m = e >> 8;
-            const float4 a = S.a[j], b = S.b[j], c = S.c[j];
-            const float cb = c.x;
-            const float dj = c.w;
+        bool split;
+        const int n = compact(S, w, 0, nb, split);
+        // the walk, with the seam split of a centre handled only in batches
+        // that hold such an instance (uniform branch)
+        auto walk = [&](auto split_tag) {
+            constexpr bool kSplit = decltype(split_tag)::value;
+            for (int t = 0; t < n; ++t) {
+                const uint32_t e = __builtin_amdgcn_readfirstlane(S.list[w][t]);
+                const int j = e & 0xff;
+                const uint32_t m = e >> 8;
+                const float4 a = S.a[j], b = S.b[j], c = S.c[j];
+                const float cb = c.x;
+                const float dj = c.w;
 #pragma unroll
-            for (int k = 0; k < kPPL; ++k) {
-                if (!(m & (1u << k))) continue;  // uniform
-                float alpha, G;
-                pixel_alpha((float)slot_px<kW>(w, k, lx), (float)slot_py<kW>(w, k, ly), a, c, b.x, b.y, s.alpha_max,
-                            alpha, G);
-                const float aT = alpha * T[k];
-                const float Tn = T[k] - aT;  // T (1 - alpha)
-                const bool live = !(done & (1u << k)) && alpha >= s.alpha_min;
-                const bool keep = Tn >= s.T_min;  // T and alpha are finite
-                const bool take = live && keep;
-                done |= (live && !keep) ? (1u << k) : 0u;
-                const float wgt = take ? aT : 0.0f;
-                C0[k] = __builtin_fmaf(b.z, wgt, C0[k]);
-                C1[k] = __builtin_fmaf(b.w, wgt, C1[k]);
-                C2[k] = __builtin_fmaf(cb, wgt, C2[k]);
-                if (kDepth) Dp[k] = __builtin_fmaf(dj, wgt, Dp[k]);
-                T[k] = take ? Tn : T[k];
-                last[k] = take ? base + j + 1 : last[k];
-                if (kCount) blended[k] += take ? 1 : 0;
+                for (int k = 0; k < kPPL; ++k) {
+                    if (!(m & (1u << k))) continue;  // uniform
+                    float alpha, G;
+                    pixel_alpha<kSplit>((float)slot_px<kW>(w, k, lx), (float)slot_py<kW>(w, k, ly), a, c, b.x, b.y,
+                                        s.alpha_max, alpha, G);
+                    const float aT = alpha * T[k];
+                    const float Tn = T[k] - aT;  // T (1 - alpha)
+                    const bool live = !(done & (1u << k)) && alpha >= s.alpha_min;
+                    const bool keep = Tn >= s.T_min;  // T and alpha are finite
+                    const bool take = live && keep;
+                    done |= (live && !keep) ? (1u << k) : 0u;
+                    const float wgt = take ? aT : 0.0f;
+                    C0[k] = __builtin_fmaf(b.z, wgt, C0[k]);
+                    C1[k] = __builtin_fmaf(b.w, wgt, C1[k]);
+                    C2[k] = __builtin_fmaf(cb, wgt, C2[k]);
+                    if (kDepth) Dp[k] = __builtin_fmaf(dj, wgt, Dp[k]);
+                    T[k] = take ? Tn : T[k];
+                    last[k] = take ? base + j + 1 : last[k];
+                    if (kCount) blended[k] += take ? 1 : 0;
+                }
+                if ((t & 15) == 15 && __ballot(done != kAll) == 0ull) break;
             }
-            if ((t & 15) == 15 && __ballot(done != kAll) == 0ull) break;
-        }
+        };
+        if (split)
+            walk(std::true_type{});
+        else
+            walk(std::false_type{});
     }
     // the tile's backward walk length: its largest contributor count
     int wmax = 0;
@@ -341,43 +372,55 @@ __device__ __forceinline__ float dpp_add(float v) {
     return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kCtrl, kRowMask, 0xF, false));
 }
 
-// Reduce-scatter of ten per-lane values over the wave: permlane32_swap
-// pairs the wave halves (two fields per swap + add), permlane16_swap pairs
-// the rows, and four DPP steps (row rotations, quad permutes) finish the sums
-// inside each 16-lane row.  Afterwards every lane of row r holds, in o[k],
-// the wave-wide sum of field kFieldOf[k][r] (o[2] rows 1-3: padding).
+// Reduce-scatter of kNF <= 10 per-lane values over the wave, each exchange
+// carrying two fields: permlane32_swap pairs the wave halves (register p:
+// field 2p in lanes 0-31, 2p+1 in lanes 32-63), permlane16_swap pairs the
+// rows (register q, row r: field 4q + 2(r & 1) + (r >> 1)), then inside each
+// 16-lane row two pairing steps (row mirror, half-row mirror: a lane keeps
+// one field and sends the other to its partner) and two quad steps.  Lane l
+// ends with the wave-wide sum of field rs_field(l) (each field in the four
+// lanes l ^ {0, 1, 2, 3}).  Every lane must be active (DPP reads its
+// partner).
 __device__ __forceinline__ void swap_add(float &x, float &y, bool half32) {
     const auto r = half32 ? __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false)
                           : __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
     x = __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
-__device__ __forceinline__ float row_sum(float v) {
-    v = dpp_add<0x128, 0xF>(v);  // row_ror 8
-    v = dpp_add<0x124, 0xF>(v);  // row_ror 4
-    v = dpp_add<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
-    v = dpp_add<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
-    return v;
+template <int kCtrl>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kCtrl, 0xF, 0xF, false));
 }
-// field held by row r of output k: after the 32-lane step, register p holds
-// field 2p in lanes 0-31 and 2p+1 in lanes 32-63; the 16-lane step of
-// (p, q) leaves rows (2p, 2q, 2p+1, 2q+1)
-__device__ __forceinline__ int field_of(int k, int row) { return 4 * k + ((row & 1) << 1) + (row >> 1); }
-
-__device__ __forceinline__ void wave_reduce_scatter(const float (&v)[kAccAux], float (&o)[3]) {
-    float a0 = v[0], a1 = v[2], a2 = v[4], a3 = v[6], a4 = v[8];
-    float b0 = v[1], b1 = v[3], b2 = v[5], b3 = v[7], b4 = v[9];
-    swap_add(a0, b0, true);
-    swap_add(a1, b1, true);
-    swap_add(a2, b2, true);
-    swap_add(a3, b3, true);
-    swap_add(a4, b4, true);
-    float z = 0.0f;
-    swap_add(a0, a1, false);
-    swap_add(a2, a3, false);
-    swap_add(a4, z, false);
-    o[0] = row_sum(a0);
-    o[1] = row_sum(a2);
-    o[2] = row_sum(a4);
+template <int kCtrl>
+__device__ __forceinline__ float pair_step(float a, float b, bool hi) {
+    const float keep = hi ? b : a, send = hi ? a : b;
+    return keep + dpp_mov<kCtrl>(send);
+}
+__device__ __forceinline__ int rs_field(int lane) {
+    return 8 * ((lane >> 2) & 1) + 4 * ((lane >> 3) & 1) + 2 * ((lane >> 4) & 1) + (lane >> 5);
+}
+template <int kNF>
+__device__ __forceinline__ float wave_reduce_scatter(const float (&v)[kAccAux], int lane) {
+    float y[5];
+#pragma unroll
+    for (int p = 0; p < 5; ++p) {
+        float a = 2 * p < kNF ? v[2 * p] : 0.0f, b = 2 * p + 1 < kNF ? v[2 * p + 1] : 0.0f;
+        if (2 * p < kNF) swap_add(a, b, true);
+        y[p] = a;
+    }
+    float z0 = y[0], z1 = y[2], z2 = y[4], t1 = y[1], t3 = y[3], zero = 0.0f;
+    swap_add(z0, t1, false);
+    swap_add(z1, t3, false);
+    swap_add(z2, zero, false);
+    const bool h8 = lane & 8, h4 = lane & 4;
+    const float w0 = pair_step<0x140>(z0, z1, h8);  // row_mirror
+    // z2 pairs with an all-zero register: lanes 0-7 of a row sum its fields
+    // (8-11); lanes 8-15 would hold fields 12-15, which do not exist, so they
+    // take the same sums (no select: every lane takes part in each exchange)
+    const float w1 = z2 + dpp_mov<0x140>(z2);
+    float u = pair_step<0x141>(w0, w1, h4);  // row_half_mirror
+    u = dpp_add<0x4E, 0xF>(u);               // quad_perm [2,3,0,1]
+    u = dpp_add<0xB1, 0xF>(u);               // quad_perm [1,0,3,2]
+    return u;
 }
 
 // kAux: the depth and alpha cotangents too (colour channels with colour
@@ -432,6 +475,16 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, co
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) wmax = max(wmax, __shfl_xor(wmax, off, kWave));
     if (lane == 0) s_max[w] = wmax;
+    // per-quadrant largest contributor counts of this wave: a quadrant skips
+    // the positions past its own pixels' last contributors
+    int qmax[kPPL];
+#pragma unroll
+    for (int k = 0; k < kPPL; ++k) {
+        int m = last[k];
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) m = max(m, __shfl_xor(m, off, kWave));
+        qmax[k] = __builtin_amdgcn_readfirstlane(m);
+    }
     __syncthreads();
     int max_last = 0;
 #pragma unroll
@@ -447,74 +500,81 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, co
         }
         __syncthreads();
         // positions at or past this wave's largest contributor count (slots
-        // below hi - wmax) are never blended by its pixels
-        const int n = compact(S, w, hi - wmax, nb);
-        for (int t = 0; t < n; ++t) {
-            const uint32_t e = __builtin_amdgcn_readfirstlane(S.list[w][t]);
-            const int j = e & 0xff;
-            const uint32_t m = e >> 8;
-            const int pos = hi - 1 - j;
-            const float4 a = S.a[j], b = S.b[j], c = S.c[j];
-            const float4 ex = S.e[j];
-            const float cb = c.x;
-            const float dj = c.w;
-            float v[kAccAux];
+        // below hi - wmax) are never blended by its pixels, and positions past
+        // quadrant k's largest count (slots below hi - qmax[k]) by that
+        // quadrant's
+        bool split;
+        int qlo[kPPL];
 #pragma unroll
-            for (int f = 0; f < kAccAux; ++f) v[f] = 0.0f;
-            bool any = false;
+        for (int k = 0; k < kPPL; ++k) qlo[k] = hi - qmax[k];
+        const int n = compact(S, w, hi - wmax, nb, split, qlo);
+        auto walk = [&](auto split_tag) {
+            constexpr bool kSplit = decltype(split_tag)::value;
+            for (int t = 0; t < n; ++t) {
+                const uint32_t e = __builtin_amdgcn_readfirstlane(S.list[w][t]);
+                const int j = e & 0xff;
+                const uint32_t m = e >> 8;
+                const int pos = hi - 1 - j;
+                const float4 a = S.a[j], b = S.b[j], c = S.c[j];
+                const float4 ex = S.e[j];
+                const float cb = c.x;
+                const float dj = c.w;
+                float v[kAccAux];
 #pragma unroll
-            for (int k = 0; k < kPPL; ++k) {
-                if (!(m & (1u << k))) continue;  // uniform
-                const float fi = (float)slot_px<kW>(w, k, lx), fj = (float)slot_py<kW>(w, k, ly);
-                float alpha, G;
-                const float araw = pixel_alpha(fi, fj, a, c, b.x, b.y, s.alpha_max, alpha, G);
-                const bool valid = pos < last[k] && alpha >= s.alpha_min;
-                if (__ballot(valid) == 0ull) continue;  // uniform: nothing blended in this quadrant
-                // the pixel offset d (the centre a turn further for the columns past thr)
-                const float dx = (fi + 0.5f) - (fi >= c.z ? ex.y : ex.x), dy = (fj + 0.5f) - ex.z;
-                any |= valid;
-                const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
-                const float Tf = T[k] * inv;  // transmittance in front of this instance
-                T[k] = valid ? Tf : T[k];
-                const float wgt = valid ? alpha * Tf : 0.0f;
-                float dLc = __builtin_fmaf(dL0[k], b.z, __builtin_fmaf(dL1[k], b.w, dL2[k] * cb));
-                if (kAux) dLc += __builtin_fmaf(dLD[k], dj, dLA[k]);  // depth and alpha channels
-                const float dalpha = __builtin_fmaf(dLc, Tf, -(dLS[k] * inv));
-                dLS[k] = __builtin_fmaf(dLc, wgt, dLS[k]);
-                v[6] = __builtin_fmaf(dL0[k], wgt, v[6]);
-                v[7] = __builtin_fmaf(dL1[k], wgt, v[7]);
-                v[8] = __builtin_fmaf(dL2[k], wgt, v[8]);
-                if (kAux) v[9] = __builtin_fmaf(dLD[k], wgt, v[9]);
-                // dL/dalpha through an unclamped alpha only
-                const float da = (valid && araw < s.alpha_max) ? dalpha : 0.0f;
-                // moments of gp = dL/d(-1/2 d^T Q d) = alpha * dL/dalpha
-                const float gp = araw * da;
-                const float gx = dx * gp, gy = dy * gp;
-                v[0] += gx;
-                v[1] += gy;
-                v[2] = __builtin_fmaf(dx, gx, v[2]);
-                v[3] = __builtin_fmaf(dx, gy, v[3]);
-                v[4] = __builtin_fmaf(dy, gy, v[4]);
-                v[5] = __builtin_fmaf(G, da, v[5]);
-            }
-            if (__ballot(any) != 0ull) {
-                float o[3];
-                wave_reduce_scatter(v, o);
-                if ((lane & 15) == 15) {
-                    const int row = lane >> 4;
+                for (int f = 0; f < kAccAux; ++f) v[f] = 0.0f;
+                bool any = false;  // uniform: some lane blends this instance
 #pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        const int f = field_of(k, row);
-                        if (f >= kNF) continue;
-                        if (kW == 1) part[j][f] = o[k];
-                        else atomicAdd(&part[j][f], o[k]);  // the waves of this instance meet here
+                for (int k = 0; k < kPPL; ++k) {
+                    if (!(m & (1u << k))) continue;  // uniform
+                    const float fi = (float)slot_px<kW>(w, k, lx), fj = (float)slot_py<kW>(w, k, ly);
+                    float alpha, G;
+                    const float araw = pixel_alpha<kSplit>(fi, fj, a, c, b.x, b.y, s.alpha_max, alpha, G);
+                    const bool valid = pos < last[k] && alpha >= s.alpha_min;
+                    if (__ballot(valid) == 0ull) continue;  // uniform: nothing blended in this quadrant
+                    // the pixel offset d (the centre a turn further for the columns past thr)
+                    const float dx = (fi + 0.5f) - ((kSplit && fi >= c.z) ? ex.y : ex.x), dy = (fj + 0.5f) - ex.z;
+                    any = true;
+                    const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
+                    const float Tf = T[k] * inv;  // transmittance in front of this instance
+                    T[k] = valid ? Tf : T[k];
+                    const float wgt = valid ? alpha * Tf : 0.0f;
+                    float dLc = __builtin_fmaf(dL0[k], b.z, __builtin_fmaf(dL1[k], b.w, dL2[k] * cb));
+                    if (kAux) dLc += __builtin_fmaf(dLD[k], dj, dLA[k]);  // depth and alpha channels
+                    const float dalpha = __builtin_fmaf(dLc, Tf, -(dLS[k] * inv));
+                    dLS[k] = __builtin_fmaf(dLc, wgt, dLS[k]);
+                    v[6] = __builtin_fmaf(dL0[k], wgt, v[6]);
+                    v[7] = __builtin_fmaf(dL1[k], wgt, v[7]);
+                    v[8] = __builtin_fmaf(dL2[k], wgt, v[8]);
+                    if (kAux) v[9] = __builtin_fmaf(dLD[k], wgt, v[9]);
+                    // dL/dalpha through an unclamped alpha only
+                    const float da = (valid && araw < s.alpha_max) ? dalpha : 0.0f;
+                    // moments of gp = dL/d(-1/2 d^T Q d) = alpha * dL/dalpha
+                    const float gp = araw * da;
+                    const float gx = dx * gp, gy = dy * gp;
+                    v[0] += gx;
+                    v[1] += gy;
+                    v[2] = __builtin_fmaf(dx, gx, v[2]);
+                    v[3] = __builtin_fmaf(dx, gy, v[3]);
+                    v[4] = __builtin_fmaf(dy, gy, v[4]);
+                    v[5] = __builtin_fmaf(G, da, v[5]);
+                }
+                if (any) {
+                    const float u = wave_reduce_scatter<kNF>(v, lane);
+                    const int f = rs_field(lane);
+                    if ((lane & 3) == 0 && f < kNF) {
+                        if (kW == 1) part[j][f] = u;
+                        else atomicAdd(&part[j][f], u);  // the waves of this instance meet here
                     }
                 }
             }
-        }
+        };
+        if (split)
+            walk(std::true_type{});
+        else
+            walk(std::false_type{});
         __syncthreads();
         // moments -> screen-space gradients: the staging lane of each slot
-        if ((int)threadIdx.x < nb && S.quad[threadIdx.x]) {
+        if ((int)threadIdx.x < nb && (S.quad[threadIdx.x] & ~kSplitBit)) {
             const int j = threadIdx.x;
             float mo[kNF];
 #pragma unroll
