@@ -148,6 +148,17 @@ def cpu_baseline(g, poses, gt_images):
         t_one = sample()
     finally:
         O.set_num_threads(cores)
+
+    # serving: the oracle's forward of the first request of each resolution
+    # in the serving stream (the requests the serving accuracy test samples)
+    from paper_2404_03202_amd import scenes
+    stream = scenes.serve_cameras(4, 64)
+    serve_s = {}
+    for w, h in scenes.SERVE_RESOLUTIONS:
+        cam = next(c for c in stream if (c["width"], c["height"]) == (w, h))
+        t = time.perf_counter()
+        O.render(O.Scene(g, cam), alt=False)
+        serve_s[f"{w}x{h}"] = time.perf_counter() - t
     return dict(value=n / dt, unit="iters/s", cores=cores, kind="oracle",
                 sample=f"{n} of 200 poses (poses 0-{n - 1}), full 1M Gaussians at 2048x1024: forward + L1 + backward, "
                        f"{dt:.1f} s on {cores} threads",
@@ -157,6 +168,9 @@ def cpu_baseline(g, poses, gt_images):
                               seconds_1_thread=t_one, seconds_all_threads=t_all, threads=cores,
                               speedup=t_one / t_all,
                               implied_1core_iters_per_s=(n / dt) * t_all / t_one),
+                serving=dict(sample="forward of the first request of each serving resolution (resident 1M-Gaussian "
+                                    f"scene), {cores} threads", seconds=serve_s,
+                             renders_per_s=len(serve_s) / sum(serve_s.values())),
                 note="baseline only")
 
 

@@ -207,6 +207,34 @@ class Server:
                     batches=self.batches, overflows=self.overflows, makespan_s=makespan)
 
 
+SCENE_KEYS = ("means", "scales", "quats", "opacities", "sh")
+
+
+def save_scene(path: str, g: dict) -> None:
+    """Write a resident scene (activated parameters, as omnigs_forward takes
+    them) to an .npz file: float32 arrays and the SH degree, nothing pickled."""
+    arrays = {k: (g[k].detach().cpu().numpy() if isinstance(g[k], torch.Tensor) else np.asarray(g[k]))
+              .astype(np.float32) for k in SCENE_KEYS}
+    np.savez(path, sh_degree=np.int32(g["sh_degree"]), **arrays)
+
+
+def load_scene(path: str, device) -> dict:
+    """Read a scene written by save_scene onto `device` (contiguous float32
+    tensors), checking the array shapes against each other."""
+    with np.load(path, allow_pickle=False) as f:
+        g = {k: torch.from_numpy(np.ascontiguousarray(f[k], dtype=np.float32)).to(device) for k in SCENE_KEYS}
+        g["sh_degree"] = int(f["sh_degree"])
+    n = g["means"].shape[0]
+    shapes = dict(means=(n, 3), scales=(n, 3), quats=(n, 4), opacities=(n,))
+    for k, shp in shapes.items():
+        if tuple(g[k].shape) != shp:
+            raise ValueError(f"{path}: {k} has shape {tuple(g[k].shape)}, expected {shp}")
+    if g["sh"].dim() != 3 or g["sh"].shape[0] != n or g["sh"].shape[2] != 3 or \
+            not (g["sh_degree"] + 1) ** 2 <= g["sh"].shape[1] <= 16:
+        raise ValueError(f"{path}: sh has shape {tuple(g['sh'].shape)} for degree {g['sh_degree']}")
+    return g
+
+
 def make_requests(cameras: list, arrivals=None) -> list:
     """Requests for `cameras` in order, arriving at `arrivals` (seconds; None:
     all at 0)."""
