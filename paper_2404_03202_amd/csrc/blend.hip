@@ -257,8 +257,22 @@ __device__ __forceinline__ int slot_py(int w, int s, int ly) { return (((w * (kQ
 
 // kDepth: also the depth image sum_i d_i alpha_i T_i.  kCount: also the
 // number of instances blended per pixel (only when a frame asks for it).
+template <int kN>
+__device__ __forceinline__ bool all_stopped(const float (&amin)[kN]) {
+    bool a = true;
+#pragma unroll
+    for (int k = 0; k < kN; ++k) a = a && amin[k] == __builtin_huge_valf();
+    return a;
+}
+
+// Eight waves per SIMD (at most 64 VGPRs) for the four-wave colour-only
+// forward: it then fits without spills and hides more of its LDS latency;
+// the other instantiations need more registers.
+template <int kW, bool kDepth, bool kCount>
+constexpr int forward_min_waves() { return (kW == 4 && !kDepth && !kCount) ? 8 : 1; }
+
 template <int kW, bool kBatched, bool kDepth, bool kCount>
-__global__ __launch_bounds__(kWave * kW) void k_blend_forward(FrameTable FT, const BlendRecord *rec,
+__global__ __launch_bounds__(kWave * kW, (forward_min_waves<kW, kDepth, kCount>())) void k_blend_forward(FrameTable FT, const BlendRecord *rec,
                                                                const float *rdepth, const uint32_t *inst_gauss,
                                                                const uint2 *ranges, BlendSettings s,
                                                                const uint32_t *order, uint32_t *tile_work) {
@@ -278,34 +292,36 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_forward(FrameTable FT, con
     const int count = (int)(range.y - range.x);
     float T[kPPL], C0[kPPL], C1[kPPL], C2[kPPL], Dp[kPPL];
     int last[kPPL], blended[kPPL];
-    constexpr uint32_t kAll = (1u << kPPL) - 1u;
-    uint32_t done = 0;  // bit k: pixel k finished (stopped, or outside the image)
+    // per pixel, the alpha an instance needs to be blended: alpha_min, or
+    // +infinity once the pixel has stopped (or lies outside the image), so
+    // that one comparison tests both
+    float amin[kPPL];
 #pragma unroll
     for (int k = 0; k < kPPL; ++k) {
         T[k] = 1.0f;
         C0[k] = C1[k] = C2[k] = Dp[k] = 0.0f;
         last[k] = blended[k] = 0;
+        amin[k] = s.alpha_min;
         if (ty * kTile + slot_py<kW>(w, k, ly) >= F.height || tx * kTile + slot_px<kW>(w, k, lx) >= F.width)
-            done |= 1u << k;
+            amin[k] = __builtin_huge_valf();
     }
     for (int base = 0; base < count; base += kBatch) {
-        if (__syncthreads_count(done == kAll) == kNT) break;
+        if (__syncthreads_count(all_stopped(amin)) == kNT) break;
         const int nb = min(kBatch, count - base);
         if ((int)threadIdx.x < nb)
             stage<kDepth>(rec, rdepth, inst_gauss[range.x + base + threadIdx.x], X0, Y0, W, S, threadIdx.x);
         __syncthreads();
-        if (__ballot(done != kAll) == 0ull) continue;  // this wave is finished: keep staging with the others
+        if (__ballot(!all_stopped(amin)) == 0ull) continue;  // this wave is finished: keep staging with the others
         bool split;
         const int n = compact(S, w, 0, nb, split);
         // the walk, with the seam split of a centre handled only in batches
         // that hold such an instance (uniform branch)
         auto walk = [&](auto split_tag) {
             constexpr bool kSplit = decltype(split_tag)::value;
-            for (int t = 0; t < n; ++t) {
-                const uint32_t e = __builtin_amdgcn_readfirstlane(S.list[w][t]);
+            // blend instance t with its record in (a, b, c) (uniform entry e)
+            auto blend_one = [&](uint32_t e, const float4 &a, const float4 &b, const float4 &c) {
                 const int j = e & 0xff;
                 const uint32_t m = e >> 8;
-                const float4 a = S.a[j], b = S.b[j], c = S.c[j];
                 const float cb = c.x;
                 const float dj = c.w;
 #pragma unroll
@@ -316,10 +332,10 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_forward(FrameTable FT, con
                                         s.alpha_max, alpha, G);
                     const float aT = alpha * T[k];
                     const float Tn = T[k] - aT;  // T (1 - alpha)
-                    const bool live = !(done & (1u << k)) && alpha >= s.alpha_min;
+                    const bool live = alpha >= amin[k];
                     const bool keep = Tn >= s.T_min;  // T and alpha are finite
                     const bool take = live && keep;
-                    done |= (live && !keep) ? (1u << k) : 0u;
+                    amin[k] = (live && !keep) ? __builtin_huge_valf() : amin[k];
                     const float wgt = take ? aT : 0.0f;
                     C0[k] = __builtin_fmaf(b.z, wgt, C0[k]);
                     C1[k] = __builtin_fmaf(b.w, wgt, C1[k]);
@@ -329,7 +345,42 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_forward(FrameTable FT, con
                     last[k] = take ? base + j + 1 : last[k];
                     if (kCount) blended[k] += take ? 1 : 0;
                 }
-                if ((t & 15) == 15 && __ballot(done != kAll) == 0ull) break;
+            };
+            if constexpr (kW != 4) {
+                // two pixels per lane: the registers a second record set
+                // would take cost more waves than the latency it hides
+                for (int t = 0; t < n; ++t) {
+                    const uint32_t e = __builtin_amdgcn_readfirstlane(S.list[w][t]);
+                    // the record into registers once (a reference into LDS
+                    // would be read again by each quadrant)
+                    const float4 a = S.a[e & 0xff], b = S.b[e & 0xff], c = S.c[e & 0xff];
+                    blend_one(e, a, b, c);
+                    if ((t & 15) == 15 && __ballot(!all_stopped(amin)) == 0ull) break;
+                }
+                return;
+            }
+            if (n == 0) return;
+            // two register sets in turn: the record of the next instance is
+            // read from LDS while this one blends
+            uint32_t e0 = __builtin_amdgcn_readfirstlane(S.list[w][0]), e1 = 0;
+            float4 a0 = S.a[e0 & 0xff], b0 = S.b[e0 & 0xff], c0 = S.c[e0 & 0xff], a1, b1, c1;
+            for (int t = 0; t < n; t += 2) {
+                if (t + 1 < n) {
+                    e1 = __builtin_amdgcn_readfirstlane(S.list[w][t + 1]);
+                    a1 = S.a[e1 & 0xff];
+                    b1 = S.b[e1 & 0xff];
+                    c1 = S.c[e1 & 0xff];
+                }
+                blend_one(e0, a0, b0, c0);
+                if (t + 1 >= n) break;
+                if (t + 2 < n) {
+                    e0 = __builtin_amdgcn_readfirstlane(S.list[w][t + 2]);
+                    a0 = S.a[e0 & 0xff];
+                    b0 = S.b[e0 & 0xff];
+                    c0 = S.c[e0 & 0xff];
+                }
+                blend_one(e1, a1, b1, c1);
+                if ((t & 15) == 14 && __ballot(!all_stopped(amin)) == 0ull) break;
             }
         };
         if (split)
@@ -534,10 +585,14 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, co
                     // the pixel offset d (the centre a turn further for the columns past thr)
                     const float dx = (fi + 0.5f) - ((kSplit && fi >= c.z) ? ex.y : ex.x), dy = (fj + 0.5f) - ex.z;
                     any = true;
-                    const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
+                    // a lane that does not blend this instance takes alpha = 0:
+                    // 1 / (1 - 0) = 1 exactly, so its T stays as it is and its
+                    // weight and colour terms are zero
+                    const float ae = valid ? alpha : 0.0f;
+                    const float inv = __builtin_amdgcn_rcpf(1.0f - ae);
                     const float Tf = T[k] * inv;  // transmittance in front of this instance
-                    T[k] = valid ? Tf : T[k];
-                    const float wgt = valid ? alpha * Tf : 0.0f;
+                    T[k] = Tf;
+                    const float wgt = ae * Tf;
                     float dLc = __builtin_fmaf(dL0[k], b.z, __builtin_fmaf(dL1[k], b.w, dL2[k] * cb));
                     if (kAux) dLc += __builtin_fmaf(dLD[k], dj, dLA[k]);  // depth and alpha channels
                     const float dalpha = __builtin_fmaf(dLc, Tf, -(dLS[k] * inv));

@@ -38,7 +38,7 @@ def empty_grads(gd):
                 screen=z(n, 2))
 
 
-def one_case(seed, n, width, height, yaw):
+def one_case(seed, n, width, height, yaw, aux=False):
     g = scenes.shell_scene(seed, n, r0=1.0, r1=6.0, scale_lo=0.02, scale_hi=0.3)
     cam = scenes.camera(width, height, scenes.rot_y(yaw).T, [0.1, -0.2, 0.15])
     sc = O.Scene(g, cam)
@@ -48,15 +48,25 @@ def one_case(seed, n, width, height, yaw):
     dl[:, orc["n_grad_flags"] > 0] = 0.0
     gd = to_dev(g)
     dld = torch.from_numpy(dl.astype(np.float32)).to(DEV)
+    # with aux: seeded cotangents of the depth and alpha images too (ten
+    # accumulator fields per Gaussian instead of nine)
+    daux = {}
+    if aux:
+        rng = np.random.default_rng([seed, scenes.STREAM_FD])
+        for key in ("dL_ddepth", "dL_dalpha"):
+            a = rng.normal(size=(height, width)) / (height * width)
+            a[orc["n_grad_flags"] > 0] = 0.0
+            daux[key] = a
+    dauxd = {k: torch.from_numpy(v.astype(np.float32)).to(DEV) for k, v in daux.items()}
     fwd = B.omnigs_forward(gd, cam)
-    ref = B.omnigs_backward(gd, cam, None, fwd, dld)
-    out = B.omnigs_backward_noalloc(gd, cam, None, fwd, dld, empty_grads(gd))
+    ref = B.omnigs_backward(gd, cam, None, fwd, dld, **dauxd)
+    out = B.omnigs_backward_noalloc(gd, cam, None, fwd, dld, empty_grads(gd), **dauxd)
     torch.cuda.synchronize()
     ga = {k: v.cpu().numpy() for k, v in out.items()}
     gr = {k: v.cpu().numpy() for k, v in ref.items()}
     for k in NAMES:
         assert np.isfinite(ga[k]).all(), f"{k}: entries left unwritten"
-    ob = O.backward(sc, dl)
+    ob = O.backward(sc, dl, **{k: v.astype(np.float32).astype(np.float64) for k, v in daux.items()})
     flagged = np.nonzero(O.project(sc)[:, O.REC_FIELDS["flag"]] > 0)[0]
     rep = parity.check_grads(ga, ob, NAMES, skip_rows=flagged)
     # the two entry points against each other: the same rule, with the
@@ -72,6 +82,12 @@ def test_noalloc_matches_backward_twice_second_smaller():
     m2, rep2 = one_case(411, 3000, 128, 64, -1.9)
     assert m1 > m2 > 0
     print("no-alloc backward", rep1, rep2)
+
+
+def test_noalloc_with_depth_and_alpha_cotangents():
+    m, rep = one_case(413, 8000, 256, 128, 2.4, aux=True)
+    assert m > 0
+    print("no-alloc backward with depth and alpha cotangents", rep)
 
 
 def test_noalloc_refuses_more_than_its_scratch():
