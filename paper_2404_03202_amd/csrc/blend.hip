@@ -245,7 +245,10 @@ __device__ __forceinline__ float pixel_alpha(float i, float j, float4 a, float4 
     const float v = __builtin_fmaf(l11, j, a.y);
     G = __builtin_amdgcn_exp2f(-__builtin_fmaf(u, u, v * v));
     const float araw = o * G;
-    alpha = fminf(araw, alpha_max);  // alpha_max also for a NaN araw
+    // araw >= 0: non-negative floats order as their bit patterns, so the
+    // clamp is an integer min (no canonicalisation of alpha_max per pixel);
+    // a NaN araw gives alpha_max or a NaN alpha, which no pixel blends
+    alpha = __int_as_float(min(__float_as_int(araw), __float_as_int(alpha_max)));
     return araw;
 }
 
