@@ -90,7 +90,7 @@ __device__ inline int find_frame(const FrameTable &T, uint32_t tile) {
 
 // Staged instances (LDS):
 //   a = (u0a, v0, l00, l10), b = (l11, o, r, g), c = (b, u0b, thr, depth),
-//   e = (xa, xb, y) (backward only), quad = quadrant mask
+//   quad = quadrant mask
 // with L the record's scaled Cholesky factor of the conic:
 // -(l00 dx + l10 dy)^2 - (l11 dy)^2 = log2(e) * (-1/2 d^T Q d).  The pixel at
 // integer tile coordinates (i, j) has d = (i + 1/2 - x, j + 1/2 - y) with the
@@ -102,11 +102,10 @@ __device__ inline int find_frame(const FrameTable &T, uint32_t tile) {
 // precision: a pixel pays a compare, a select and three FMAs for L^T d.
 // list[w] holds, for wave w, the staged slots that reach one of its
 // quadrants, in order, as slot | (wave mask << 8).
-template <int kW, bool kBwd>
+template <int kW>
 struct Stage {
     static constexpr int kBatch = kWave * kW;
     float4 a[kBatch], b[kBatch], c[kBatch];
-    float4 e[kBwd ? kBatch : 1];
     uint32_t quad[kBatch];
     uint32_t gid[kBatch];
     uint16_t list[kW][kBatch];
@@ -141,9 +140,9 @@ __device__ inline float rect_min_quadratic(float l00, float l10, float l11, floa
 
 // Stage the record of Gaussian gid in slot `slot` (rdepth: per-record depth
 // values, read when kAux).
-template <bool kAux, int kW, bool kBwd>
+template <bool kAux, int kW>
 __device__ inline void stage(const BlendRecord *rec, const float *rdepth, uint32_t gid, float X0, float Y0, float W,
-                             Stage<kW, kBwd> &S, int slot) {
+                             Stage<kW> &S, int slot) {
     const float4 *p = reinterpret_cast<const float4 *>(rec + gid);
     const float4 ra4 = p[0], rb4 = p[1], rc4 = p[2];
     float x = (ra4.x - X0) + ra4.y;  // px_hi - X0 is exact near the tile
@@ -182,13 +181,12 @@ __device__ inline void stage(const BlendRecord *rec, const float *rdepth, uint32
     }
     // columns whose offset i + 1/2 - x leaves [-W/2, W/2) take the centre a
     // turn away: the right ones (offset >= W/2) or the left ones (< -W/2)
-    float xa = x, thr = 1e30f;
+    float thr = 1e30f;
     double xad = xd, xbd = xd;
     if (15.5f - x >= half) {
         xbd = xd + (double)W;
         thr = x + half - 0.5f;
     } else if (0.5f - x < -half) {
-        xa = x - W;
         xad = xd - (double)W;
         thr = x - half - 0.5f;
     }
@@ -199,7 +197,6 @@ __device__ inline void stage(const BlendRecord *rec, const float *rdepth, uint32
     S.a[slot] = make_float4(u0a, v0, l00, l10);
     S.b[slot] = make_float4(l11, rb4.w, rc4.x, rc4.y);
     S.c[slot] = make_float4(rc4.z, u0b, thr, kAux ? rdepth[gid] : 0.0f);
-    if (kBwd) S.e[slot] = make_float4(xa, (float)xbd, y, 0.0f);
     // bit kSplitBit: the tile's columns take two centres (thr inside the tile)
     S.quad[slot] = quad | (thr < 1e29f ? kSplitBit : 0u);
     S.gid[slot] = gid;
@@ -208,13 +205,13 @@ __device__ inline void stage(const BlendRecord *rec, const float *rdepth, uint32
 // Wave w lists, in order, the staged slots in [lo, nb) that reach one of its
 // quadrants; returns the count (uniform) and sets `split` (uniform) when one
 // of them has its seam split inside the tile.
-template <int kW, bool kBwd>
-__device__ inline int compact(Stage<kW, kBwd> &S, int w, int lo, int nb, bool &split, const int *qlo = nullptr) {
+template <int kW>
+__device__ inline int compact(Stage<kW> &S, int w, int lo, int nb, bool &split, const int *qlo = nullptr) {
     constexpr int kPPL = kQuads / kW;
     const int lane = __lane_id();
     int n = 0;
     bool sp = false;
-    for (int c = 0; c < Stage<kW, kBwd>::kBatch; c += kWave) {
+    for (int c = 0; c < Stage<kW>::kBatch; c += kWave) {
         const int slot = c + lane;
         const uint32_t q = (slot >= lo && slot < nb) ? S.quad[slot] : 0u;
         uint32_t m = (q >> (w * kPPL)) & ((1u << kPPL) - 1u);
@@ -234,15 +231,15 @@ __device__ inline int compact(Stage<kW, kBwd> &S, int w, int lo, int nb, bool &s
 }
 
 // alpha at the pixel (i, j) of the tile (integer coordinates as floats):
-// returns the unclamped alpha, writes the clamped one and
-// G = exp(-1/2 d^T Q d).
+// returns the unclamped alpha, writes the clamped one,
+// G = exp(-1/2 d^T Q d) and (u, v) = L^T d (L scaled as staged).
 template <bool kSplit>
 __device__ __forceinline__ float pixel_alpha(float i, float j, float4 a, float4 c, float l11, float o,
-                                             float alpha_max, float &alpha, float &G) {
+                                             float alpha_max, float &alpha, float &G, float &u, float &v) {
     // without a split every column takes u0a (thr lies past the tile)
     const float u0 = (kSplit && i >= c.z) ? c.y : a.x;
-    const float u = __builtin_fmaf(a.z, i, __builtin_fmaf(a.w, j, u0));  // L^T d
-    const float v = __builtin_fmaf(l11, j, a.y);
+    u = __builtin_fmaf(a.z, i, __builtin_fmaf(a.w, j, u0));
+    v = __builtin_fmaf(l11, j, a.y);
     G = __builtin_amdgcn_exp2f(-__builtin_fmaf(u, u, v * v));
     const float araw = o * G;
     // araw >= 0: non-negative floats order as their bit patterns, so the
@@ -279,8 +276,8 @@ __global__ __launch_bounds__(kWave * kW, (forward_min_waves<kW, kDepth, kCount>(
                                                                const float *rdepth, const uint32_t *inst_gauss,
                                                                const uint2 *ranges, BlendSettings s,
                                                                const uint32_t *order, uint32_t *tile_work) {
-    constexpr int kNT = kWave * kW, kPPL = kQuads / kW, kBatch = Stage<kW, false>::kBatch;
-    __shared__ Stage<kW, false> S;
+    constexpr int kNT = kWave * kW, kPPL = kQuads / kW, kBatch = Stage<kW>::kBatch;
+    __shared__ Stage<kW> S;
     __shared__ int s_wmax[kW];
     const uint32_t tile = order ? order[blockIdx.x] : blockIdx.x;
     const int fi = kBatched ? find_frame(FT, tile) : 0;
@@ -330,9 +327,9 @@ __global__ __launch_bounds__(kWave * kW, (forward_min_waves<kW, kDepth, kCount>(
 #pragma unroll
                 for (int k = 0; k < kPPL; ++k) {
                     if (!(m & (1u << k))) continue;  // uniform
-                    float alpha, G;
+                    float alpha, G, u, v;
                     pixel_alpha<kSplit>((float)slot_px<kW>(w, k, lx), (float)slot_py<kW>(w, k, ly), a, c, b.x, b.y,
-                                        s.alpha_max, alpha, G);
+                                        s.alpha_max, alpha, G, u, v);
                     const float aT = alpha * T[k];
                     const float Tn = T[k] - aT;  // T (1 - alpha)
                     const bool live = alpha >= amin[k];
@@ -484,9 +481,9 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, co
                                                                 const float *rdepth, const uint32_t *inst_gauss,
                                                                 const uint2 *ranges, BlendSettings s, float *acc,
                                                                 const uint32_t *order) {
-    constexpr int kPPL = kQuads / kW, kBatch = Stage<kW, true>::kBatch;
+    constexpr int kPPL = kQuads / kW, kBatch = Stage<kW>::kBatch;
     constexpr int kNF = kAux ? kAccAux : kAcc;  // accumulator fields per Gaussian
-    __shared__ Stage<kW, true> S;
+    __shared__ Stage<kW> S;
     __shared__ float part[kBatch][kNF];
     __shared__ int s_max[kW];
     const uint32_t tile = order ? order[blockIdx.x] : blockIdx.x;
@@ -570,7 +567,6 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, co
                 const uint32_t m = e >> 8;
                 const int pos = hi - 1 - j;
                 const float4 a = S.a[j], b = S.b[j], c = S.c[j];
-                const float4 ex = S.e[j];
                 const float cb = c.x;
                 const float dj = c.w;
                 float v[kAccAux];
@@ -581,12 +577,10 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, co
                 for (int k = 0; k < kPPL; ++k) {
                     if (!(m & (1u << k))) continue;  // uniform
                     const float fi = (float)slot_px<kW>(w, k, lx), fj = (float)slot_py<kW>(w, k, ly);
-                    float alpha, G;
-                    const float araw = pixel_alpha<kSplit>(fi, fj, a, c, b.x, b.y, s.alpha_max, alpha, G);
+                    float alpha, G, wu, wv;
+                    const float araw = pixel_alpha<kSplit>(fi, fj, a, c, b.x, b.y, s.alpha_max, alpha, G, wu, wv);
                     const bool valid = pos < last[k] && alpha >= s.alpha_min;
                     if (__ballot(valid) == 0ull) continue;  // uniform: nothing blended in this quadrant
-                    // the pixel offset d (the centre a turn further for the columns past thr)
-                    const float dx = (fi + 0.5f) - ((kSplit && fi >= c.z) ? ex.y : ex.x), dy = (fj + 0.5f) - ex.z;
                     any = true;
                     // a lane that does not blend this instance takes alpha = 0:
                     // 1 / (1 - 0) = 1 exactly, so its T stays as it is and its
@@ -606,14 +600,15 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, co
                     if (kAux) v[9] = __builtin_fmaf(dLD[k], wgt, v[9]);
                     // dL/dalpha through an unclamped alpha only
                     const float da = (valid && araw < s.alpha_max) ? dalpha : 0.0f;
-                    // moments of gp = dL/d(-1/2 d^T Q d) = alpha * dL/dalpha
+                    // moments of gp = dL/d(-1/2 d^T Q d) = alpha * dL/dalpha over
+                    // w = (wu, wv) = L^T d, which the exponent has formed already
                     const float gp = araw * da;
-                    const float gx = dx * gp, gy = dy * gp;
-                    v[0] += gx;
-                    v[1] += gy;
-                    v[2] = __builtin_fmaf(dx, gx, v[2]);
-                    v[3] = __builtin_fmaf(dx, gy, v[3]);
-                    v[4] = __builtin_fmaf(dy, gy, v[4]);
+                    const float gu = wu * gp, gv = wv * gp;
+                    v[0] += gu;
+                    v[1] += gv;
+                    v[2] = __builtin_fmaf(wu, gu, v[2]);
+                    v[3] = __builtin_fmaf(wu, gv, v[3]);
+                    v[4] = __builtin_fmaf(wv, gv, v[4]);
                     v[5] = __builtin_fmaf(G, da, v[5]);
                 }
                 if (any) {
@@ -637,18 +632,18 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, co
             float mo[kNF];
 #pragma unroll
             for (int f = 0; f < kNF; ++f) mo[f] = part[j][f];
-            // Q = 2 ln2 L L^T (L scaled by sqrt(log2(e) / 2))
+            // Q = 2 ln2 L L^T (L scaled by sqrt(log2(e) / 2)), so
+            // dL/dp = Q sum(d gp) = 2 ln2 L sum(w gp) with w = L^T d; the
+            // second moments sum(w w^T gp) go out as they are
             const float4 a = S.a[j], b = S.b[j];
             const float l00 = a.z, l10 = a.w, l11 = b.x;
-            const float q00 = 2.0f * kLn2 * l00 * l00, q01 = 2.0f * kLn2 * l00 * l10,
-                        q11 = 2.0f * kLn2 * __builtin_fmaf(l10, l10, l11 * l11);
             float out[kNF];
-            out[0] = q00 * mo[0] + q01 * mo[1];  // dL/dp_x
-            out[1] = q01 * mo[0] + q11 * mo[1];  // dL/dp_y
-            out[2] = -0.5f * mo[2];              // dL/dq00
-            out[3] = -mo[3];                     // dL/dq01
-            out[4] = -0.5f * mo[4];              // dL/dq11
-            out[5] = mo[5];                      // dL/do
+            out[0] = 2.0f * kLn2 * (l00 * mo[0]);                          // dL/dp_x
+            out[1] = 2.0f * kLn2 * __builtin_fmaf(l10, mo[0], l11 * mo[1]);  // dL/dp_y
+            out[2] = mo[2];  // sum(wu wu gp)
+            out[3] = mo[3];  // sum(wu wv gp)
+            out[4] = mo[4];  // sum(wv wv gp)
+            out[5] = mo[5];  // dL/do
             out[6] = mo[6];
             out[7] = mo[7];
             out[8] = mo[8];

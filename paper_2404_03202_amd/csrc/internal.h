@@ -30,8 +30,11 @@ struct alignas(16) BlendRecord {
 static_assert(sizeof(BlendRecord) == 48, "record layout");
 
 // Per-Gaussian screen-space gradient accumulators written by the backward
-// blend: dL/dp (2), dL/dQ (q00, q01, q11), dL/do, dL/drgb (3); with the
-// depth / alpha cotangents a tenth, dL/dd (the Gaussian's depth value).
+// blend: dL/dp (2); the second moments sum(w w^T gp) (uu, uv, vv) of the
+// exponent's cotangent gp = dL/d(-1/2 d^T Q d) over w = Ls^T d, Ls the
+// record's scaled factor of Q = Sigma2D^-1 (the projection backward turns
+// them into dL/dSigma2D); dL/do, dL/drgb (3); with the depth / alpha
+// cotangents a tenth, dL/dd (the Gaussian's depth value).
 constexpr int kAcc = 9;
 constexpr int kAccAux = 10;
 

@@ -26,7 +26,7 @@
 // image.
 //
 // Backward (Sec. 3.4, Eq. 18-20): from the per-Gaussian accumulators
-// dL/dp, dL/dQ (Q = Sigma2D^-1), dL/do, dL/drgb to dL/dm, dL/dS, dL/dq,
+// dL/dp, the exponent's second moments, dL/do, dL/drgb to dL/dm, dL/dS, dL/dq,
 // dL/do, dL/dSH and dL/ds, through the replaced omnidirectional terms
 // dSigma2D/dSigma, dJ/dt, dp/ds and ds/dt.
 #include "internal.h"
@@ -37,6 +37,7 @@ namespace omnigs {
 namespace {
 
 constexpr double kPi = 3.141592653589793238462643383279502884;
+constexpr double kLn2d = 0.693147180559945309417232121458176568;
 
 // Real SH basis constants (Condon-Shortley phase, index l*l + l + m,
 // z polar axis), from N_l^m = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!):
@@ -450,17 +451,18 @@ __global__ __launch_bounds__(256) void k_project_backward(ProjectArgs A, const u
 #pragma unroll
     for (int k = 0; k < kAcc; ++k) g[k] = acc[i * acc_stride + k];
     g[kAcc] = acc_stride > kAcc ? acc[i * acc_stride + kAcc] : 0.0;  // dL/dd of the depth image
-    // Q = Sigma2D^-1; the blend's dL/dQ treats q01 as one variable used in
-    // both off-diagonal entries: the symmetric gradient is [[g00, g01/2], ...].
-    const double id = 1.0 / P.det;
-    const double Q00 = P.c * id, Q01 = -P.b * id, Q11 = P.a * id;
-    const double G00 = g[2], G01 = 0.5 * g[3], G11 = g[4];
-    // dL/dSigma2D = -Q G Q (symmetric)
-    const double A00 = Q00 * G00 + Q01 * G01, A01 = Q00 * G01 + Q01 * G11;
-    const double A10 = Q01 * G00 + Q11 * G01, A11 = Q01 * G01 + Q11 * G11;
-    const double S00 = -(A00 * Q00 + A01 * Q01);
-    const double S01 = -(A00 * Q01 + A01 * Q11);
-    const double S11 = -(A10 * Q01 + A11 * Q11);
+    // dL/dSigma2D from the blend's moments M = sum(w w^T gp) of w = Ls^T d,
+    // Ls = sqrt(log2(e) / 2) L and Q = Sigma2D^-1 = L L^T: the exponent's
+    // gradient 1/2 Q d d^T Q summed with weights gp is
+    // 1/2 (2 ln2)^2 Ls M Ls^T = ln2 L M L^T, with
+    // L = [[sqrt(c / det), 0], [-b / sqrt(c det), 1 / sqrt(c)]]
+    const double sc = sqrt(P.c), sd = sqrt(P.det);
+    const double L0 = sc / sd, L1 = -P.b / (sc * sd), L2 = 1.0 / sc;
+    const double m00 = g[2], m01 = g[3], m11 = g[4];
+    const double r1 = L1 * m00 + L2 * m01;  // row 1 of L M, first column
+    const double S00 = kLn2d * (L0 * L0 * m00);
+    const double S01 = kLn2d * (L0 * r1);
+    const double S11 = kLn2d * (L1 * r1 + L2 * (L1 * m01 + L2 * m11));
     // a = V0.V0, b = V0.V1, c = V1.V1 (b used twice in the symmetric matrix)
     const double ga = S00, gb = 2.0 * S01, gc = S11;
     double dV[6];
