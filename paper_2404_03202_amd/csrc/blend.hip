@@ -100,15 +100,23 @@ __device__ inline int find_frame(const FrameTable &T, uint32_t tile) {
 // tile); there xb = xa + W and thr splits the columns.  So L^T d = (l00 i + l10 j + u0, l11 j +
 // v0) with u0 = u0a or u0b, formed once per (tile, instance) in double
 // precision: a pixel pays a compare, a select and three FMAs for L^T d.
-// list[w] holds, for wave w, the staged slots that reach one of its
-// quadrants, in order, as slot | (wave mask << 8).
+// The quadrant mask sits in c.w (its bits) when no depth is staged (kAux
+// false), else in quad[].  list[w] holds, for wave w, the staged slots that
+// reach one of its quadrants, in order, as slot | (wave mask << 8).
 template <int kW>
-struct Stage {
+struct StageCore {
     static constexpr int kBatch = kWave * kW;
     float4 a[kBatch], b[kBatch], c[kBatch];
-    uint32_t quad[kBatch];
-    uint32_t gid[kBatch];
     uint16_t list[kW][kBatch];
+};
+template <int kW, bool kAux>
+struct Stage : StageCore<kW> {
+    uint32_t quad[StageCore<kW>::kBatch];
+    __device__ uint32_t quad_of(int slot) const { return quad[slot]; }
+};
+template <int kW>
+struct Stage<kW, false> : StageCore<kW> {
+    __device__ uint32_t quad_of(int slot) const { return __float_as_uint(this->c[slot].w); }
 };
 
 // Minimum of q(u, v) = (l00 u + l10 v)^2 + (l11 v)^2 (positive definite)
@@ -142,7 +150,7 @@ __device__ inline float rect_min_quadratic(float l00, float l10, float l11, floa
 // values, read when kAux).
 template <bool kAux, int kW>
 __device__ inline void stage(const BlendRecord *rec, const float *rdepth, uint32_t gid, float X0, float Y0, float W,
-                             Stage<kW> &S, int slot) {
+                             Stage<kW, kAux> &S, int slot) {
     const float4 *p = reinterpret_cast<const float4 *>(rec + gid);
     const float4 ra4 = p[0], rb4 = p[1], rc4 = p[2];
     float x = (ra4.x - X0) + ra4.y;  // px_hi - X0 is exact near the tile
@@ -196,24 +204,24 @@ __device__ inline void stage(const BlendRecord *rec, const float *rdepth, uint32
     const float v0 = (float)((double)l11 * dy0);
     S.a[slot] = make_float4(u0a, v0, l00, l10);
     S.b[slot] = make_float4(l11, rb4.w, rc4.x, rc4.y);
-    S.c[slot] = make_float4(rc4.z, u0b, thr, kAux ? rdepth[gid] : 0.0f);
     // bit kSplitBit: the tile's columns take two centres (thr inside the tile)
-    S.quad[slot] = quad | (thr < 1e29f ? kSplitBit : 0u);
-    S.gid[slot] = gid;
+    const uint32_t qm = quad | (thr < 1e29f ? kSplitBit : 0u);
+    S.c[slot] = make_float4(rc4.z, u0b, thr, kAux ? rdepth[gid] : __uint_as_float(qm));
+    if constexpr (kAux) S.quad[slot] = qm;
 }
 
 // Wave w lists, in order, the staged slots in [lo, nb) that reach one of its
 // quadrants; returns the count (uniform) and sets `split` (uniform) when one
 // of them has its seam split inside the tile.
-template <int kW>
-__device__ inline int compact(Stage<kW> &S, int w, int lo, int nb, bool &split, const int *qlo = nullptr) {
+template <int kW, bool kAux>
+__device__ inline int compact(Stage<kW, kAux> &S, int w, int lo, int nb, bool &split, const int *qlo = nullptr) {
     constexpr int kPPL = kQuads / kW;
     const int lane = __lane_id();
     int n = 0;
     bool sp = false;
-    for (int c = 0; c < Stage<kW>::kBatch; c += kWave) {
+    for (int c = 0; c < Stage<kW, kAux>::kBatch; c += kWave) {
         const int slot = c + lane;
-        const uint32_t q = (slot >= lo && slot < nb) ? S.quad[slot] : 0u;
+        const uint32_t q = (slot >= lo && slot < nb) ? S.quad_of(slot) : 0u;
         uint32_t m = (q >> (w * kPPL)) & ((1u << kPPL) - 1u);
         if (qlo) {
             // per-quadrant lower bounds: quadrant k of this wave drops slots below qlo[k]
@@ -258,10 +266,10 @@ __device__ __forceinline__ int slot_py(int w, int s, int ly) { return (((w * (kQ
 // kDepth: also the depth image sum_i d_i alpha_i T_i.  kCount: also the
 // number of instances blended per pixel (only when a frame asks for it).
 template <int kN>
-__device__ __forceinline__ bool all_stopped(const float (&amin)[kN]) {
+__device__ __forceinline__ bool all_stopped(const float (&T)[kN]) {
     bool a = true;
 #pragma unroll
-    for (int k = 0; k < kN; ++k) a = a && amin[k] == __builtin_huge_valf();
+    for (int k = 0; k < kN; ++k) a = a && !(T[k] > 0.0f);
     return a;
 }
 
@@ -276,8 +284,8 @@ __global__ __launch_bounds__(kWave * kW, (forward_min_waves<kW, kDepth, kCount>(
                                                                const float *rdepth, const uint32_t *inst_gauss,
                                                                const uint2 *ranges, BlendSettings s,
                                                                const uint32_t *order, uint32_t *tile_work) {
-    constexpr int kNT = kWave * kW, kPPL = kQuads / kW, kBatch = Stage<kW>::kBatch;
-    __shared__ Stage<kW> S;
+    constexpr int kNT = kWave * kW, kPPL = kQuads / kW, kBatch = Stage<kW, kDepth>::kBatch;
+    __shared__ Stage<kW, kDepth> S;
     __shared__ int s_wmax[kW];
     const uint32_t tile = order ? order[blockIdx.x] : blockIdx.x;
     const int fi = kBatched ? find_frame(FT, tile) : 0;
@@ -292,26 +300,24 @@ __global__ __launch_bounds__(kWave * kW, (forward_min_waves<kW, kDepth, kCount>(
     const int count = (int)(range.y - range.x);
     float T[kPPL], C0[kPPL], C1[kPPL], C2[kPPL], Dp[kPPL];
     int last[kPPL], blended[kPPL];
-    // per pixel, the alpha an instance needs to be blended: alpha_min, or
-    // +infinity once the pixel has stopped (or lies outside the image), so
-    // that one comparison tests both
-    float amin[kPPL];
+    // a pixel that has stopped (or lies outside the image) holds -T: with
+    // T <= 0, T (1 - alpha) never passes T_min > 0, so the test that stops a
+    // pixel also keeps it stopped, and |T| is its transmittance
 #pragma unroll
     for (int k = 0; k < kPPL; ++k) {
         T[k] = 1.0f;
         C0[k] = C1[k] = C2[k] = Dp[k] = 0.0f;
         last[k] = blended[k] = 0;
-        amin[k] = s.alpha_min;
         if (ty * kTile + slot_py<kW>(w, k, ly) >= F.height || tx * kTile + slot_px<kW>(w, k, lx) >= F.width)
-            amin[k] = __builtin_huge_valf();
+            T[k] = -1.0f;
     }
     for (int base = 0; base < count; base += kBatch) {
-        if (__syncthreads_count(all_stopped(amin)) == kNT) break;
+        if (__syncthreads_count(all_stopped(T)) == kNT) break;
         const int nb = min(kBatch, count - base);
         if ((int)threadIdx.x < nb)
             stage<kDepth>(rec, rdepth, inst_gauss[range.x + base + threadIdx.x], X0, Y0, W, S, threadIdx.x);
         __syncthreads();
-        if (__ballot(!all_stopped(amin)) == 0ull) continue;  // this wave is finished: keep staging with the others
+        if (__ballot(!all_stopped(T)) == 0ull) continue;  // this wave is finished: keep staging with the others
         bool split;
         const int n = compact(S, w, 0, nb, split);
         // the walk, with the seam split of a centre handled only in batches
@@ -332,16 +338,16 @@ __global__ __launch_bounds__(kWave * kW, (forward_min_waves<kW, kDepth, kCount>(
                                         s.alpha_max, alpha, G, u, v);
                     const float aT = alpha * T[k];
                     const float Tn = T[k] - aT;  // T (1 - alpha)
-                    const bool live = alpha >= amin[k];
-                    const bool keep = Tn >= s.T_min;  // T and alpha are finite
+                    const bool live = alpha >= s.alpha_min;
+                    const bool keep = Tn >= s.T_min;  // false for a stopped pixel (T <= 0)
                     const bool take = live && keep;
-                    amin[k] = (live && !keep) ? __builtin_huge_valf() : amin[k];
                     const float wgt = take ? aT : 0.0f;
                     C0[k] = __builtin_fmaf(b.z, wgt, C0[k]);
                     C1[k] = __builtin_fmaf(b.w, wgt, C1[k]);
                     C2[k] = __builtin_fmaf(cb, wgt, C2[k]);
                     if (kDepth) Dp[k] = __builtin_fmaf(dj, wgt, Dp[k]);
-                    T[k] = take ? Tn : T[k];
+                    // stopping: T keeps its magnitude with the sign flipped
+                    T[k] = live ? (keep ? Tn : -fabsf(T[k])) : T[k];
                     last[k] = take ? base + j + 1 : last[k];
                     if (kCount) blended[k] += take ? 1 : 0;
                 }
@@ -355,7 +361,7 @@ __global__ __launch_bounds__(kWave * kW, (forward_min_waves<kW, kDepth, kCount>(
                     // would be read again by each quadrant)
                     const float4 a = S.a[e & 0xff], b = S.b[e & 0xff], c = S.c[e & 0xff];
                     blend_one(e, a, b, c);
-                    if ((t & 15) == 15 && __ballot(!all_stopped(amin)) == 0ull) break;
+                    if ((t & 15) == 15 && __ballot(!all_stopped(T)) == 0ull) break;
                 }
                 return;
             }
@@ -380,7 +386,7 @@ __global__ __launch_bounds__(kWave * kW, (forward_min_waves<kW, kDepth, kCount>(
                     c0 = S.c[e0 & 0xff];
                 }
                 blend_one(e1, a1, b1, c1);
-                if ((t & 15) == 14 && __ballot(!all_stopped(amin)) == 0ull) break;
+                if ((t & 15) == 14 && __ballot(!all_stopped(T)) == 0ull) break;
             }
         };
         if (split)
@@ -408,6 +414,7 @@ __global__ __launch_bounds__(kWave * kW, (forward_min_waves<kW, kDepth, kCount>(
         const int y = ty * kTile + slot_py<kW>(w, k, ly), x = tx * kTile + slot_px<kW>(w, k, lx);
         if (y >= F.height || x >= F.width) continue;
         const int64_t p = (int64_t)y * F.width + x;
+        T[k] = fabsf(T[k]);  // a stopped pixel holds -T
         F.image[p] = __builtin_fmaf(T[k], s.bg[0], C0[k]);
         F.image[HW + p] = __builtin_fmaf(T[k], s.bg[1], C1[k]);
         F.image[2 * HW + p] = __builtin_fmaf(T[k], s.bg[2], C2[k]);
@@ -481,11 +488,12 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, co
                                                                 const float *rdepth, const uint32_t *inst_gauss,
                                                                 const uint2 *ranges, BlendSettings s, float *acc,
                                                                 const uint32_t *order) {
-    constexpr int kPPL = kQuads / kW, kBatch = Stage<kW>::kBatch;
+    constexpr int kPPL = kQuads / kW, kBatch = Stage<kW, kAux>::kBatch;
     constexpr int kNF = kAux ? kAccAux : kAcc;  // accumulator fields per Gaussian
-    __shared__ Stage<kW> S;
+    __shared__ Stage<kW, kAux> S;
     __shared__ float part[kBatch][kNF];
-    __shared__ int s_max[kW];
+    // per-wave contributor maxima, read before the first batch clears part
+    int *s_max = reinterpret_cast<int *>(&part[0][0]);
     const uint32_t tile = order ? order[blockIdx.x] : blockIdx.x;
     const int fi = kBatched ? find_frame(FT, tile) : 0;
     const BlendFrame &F = FT.f[fi];
@@ -543,9 +551,11 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, co
     for (int hi = max_last; hi > 0; hi -= kBatch) {
         const int nb = min(kBatch, hi);
         __syncthreads();
+        uint32_t my_gid = 0;  // the Gaussian this thread stages (slot threadIdx.x)
         if ((int)threadIdx.x < nb) {
             // slot i holds list position hi-1-i
-            stage<kAux>(rec, rdepth, inst_gauss[range.x + hi - 1 - threadIdx.x], X0, Y0, W, S, threadIdx.x);
+            my_gid = inst_gauss[range.x + hi - 1 - threadIdx.x];
+            stage<kAux>(rec, rdepth, my_gid, X0, Y0, W, S, threadIdx.x);
 #pragma unroll
             for (int f = 0; f < kNF; ++f) part[threadIdx.x][f] = 0.0f;
         }
@@ -627,7 +637,7 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, co
             walk(std::false_type{});
         __syncthreads();
         // moments -> screen-space gradients: the staging lane of each slot
-        if ((int)threadIdx.x < nb && (S.quad[threadIdx.x] & ~kSplitBit)) {
+        if ((int)threadIdx.x < nb && (S.quad_of(threadIdx.x) & ~kSplitBit)) {
             const int j = threadIdx.x;
             float mo[kNF];
 #pragma unroll
@@ -652,15 +662,20 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, co
             for (int f = 0; f < kNF; ++f) part[j][f] = out[f];
         }
         __syncthreads();
-        // the workgroup's threads walk the slots' fields in order, so the
+        // each wave walks the fields of the slots it staged in order, so the
         // lanes of one atomic instruction cover whole records of a few
         // Gaussians (a handful of cache lines) rather than one field of 64
-        // scattered Gaussians (64 lines): L2 takes far fewer atomic requests
-        const float *flat = &part[0][0];
-        for (int q = threadIdx.x; q < nb * kNF; q += kWave * kW) {
-            const int j = q / kNF, f = q - j * kNF;
-            const float val = flat[q];
-            if (val != 0.0f) atomicAdd(acc + (int64_t)S.gid[j] * kNF + f, val);
+        // scattered Gaussians (64 lines): L2 takes far fewer atomic requests;
+        // a slot's Gaussian id comes from the lane that staged it
+        const int j0 = w * kWave;
+        const int nq = max(0, min(kWave, nb - j0)) * kNF;
+        const float *flat = &part[j0][0];
+#pragma unroll 1
+        for (int i = 0; i < kNF; ++i) {
+            const int q = lane + i * kWave, jl = q / kNF, f = q - jl * kNF;
+            const uint32_t g = (uint32_t)__shfl((int)my_gid, jl, kWave);
+            const float val = q < nq ? flat[q] : 0.0f;
+            if (val != 0.0f) atomicAdd(acc + (int64_t)g * kNF + f, val);
         }
     }
 }

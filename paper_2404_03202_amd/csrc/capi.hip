@@ -177,7 +177,8 @@ omnigs_status check_settings(const omnigs_settings *s) {
     if (!(s->alpha_min > 0.0 && s->alpha_min < 1.0)) return fail(OMNIGS_ERR_INVALID, "alpha_min must be in (0, 1)");
     if (!(s->alpha_max >= s->alpha_min && s->alpha_max < 1.0))
         return fail(OMNIGS_ERR_INVALID, "alpha_max must be in [alpha_min, 1)");
-    if (!(s->T_min > 0.0 && s->T_min < 1.0)) return fail(OMNIGS_ERR_INVALID, "T_min must be in (0, 1)");
+    if (!(s->T_min > 0.0 && s->T_min < 1.0) || !((float)s->T_min > 0.0f))
+        return fail(OMNIGS_ERR_INVALID, "T_min must be in (0, 1) and positive as a float");
     if (!(s->dilation >= 0.0) || !std::isfinite(s->dilation)) return fail(OMNIGS_ERR_INVALID, "bad dilation");
     if (!(s->near_plane >= 0.0) || !std::isfinite(s->near_plane)) return fail(OMNIGS_ERR_INVALID, "bad near_plane");
     for (int k = 0; k < 3; ++k)

@@ -86,6 +86,7 @@ def _forward(lib, g, c, s, out, alloc, cap=None):
     (lambda g, c, s, o: c.R_cw.__setitem__(3, float("nan")), "non-finite"),
     (lambda g, c, s, o: setattr(s, "alpha_min", 0.0), "alpha_min"),
     (lambda g, c, s, o: setattr(s, "T_min", 1.5), "T_min"),
+    (lambda g, c, s, o: setattr(s, "T_min", 1e-50), "T_min"),  # zero as a float
     (lambda g, c, s, o: setattr(o, "image", None), "NULL"),
     (lambda g, c, s, o: setattr(c, "model", 7), "unknown camera model"),
     (lambda g, c, s, o: setattr(c, "rows", 33), "rows"),
