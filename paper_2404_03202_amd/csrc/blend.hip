@@ -89,7 +89,7 @@ __device__ inline int find_frame(const FrameTable &T, uint32_t tile) {
 }
 
 // Staged instances (LDS):
-//   a = (u0a, v0, l00, l10), b = (l11, o, r, g), c = (b, u0b, thr, depth),
+//   a = (u0a, v0, l00, l10), b = (l11, log2 o, r, g), c = (b, u0b, thr, depth),
 //   quad = quadrant mask
 // with L the record's scaled Cholesky factor of the conic:
 // -(l00 dx + l10 dy)^2 - (l11 dy)^2 = log2(e) * (-1/2 d^T Q d).  The pixel at
@@ -239,17 +239,16 @@ __device__ inline int compact(Stage<kW, kAux> &S, int w, int lo, int nb, bool &s
 }
 
 // alpha at the pixel (i, j) of the tile (integer coordinates as floats):
-// returns the unclamped alpha, writes the clamped one,
-// G = exp(-1/2 d^T Q d) and (u, v) = L^T d (L scaled as staged).
+// returns the unclamped alpha o exp(-1/2 d^T Q d) = 2^(log2 o - |w|^2),
+// writes the clamped one and w = (u, v) = L^T d (L scaled as staged).
 template <bool kSplit>
-__device__ __forceinline__ float pixel_alpha(float i, float j, float4 a, float4 c, float l11, float o,
-                                             float alpha_max, float &alpha, float &G, float &u, float &v) {
+__device__ __forceinline__ float pixel_alpha(float i, float j, float4 a, float4 c, float l11, float log2o,
+                                             float alpha_max, float &alpha, float &u, float &v) {
     // without a split every column takes u0a (thr lies past the tile)
     const float u0 = (kSplit && i >= c.z) ? c.y : a.x;
     u = __builtin_fmaf(a.z, i, __builtin_fmaf(a.w, j, u0));
     v = __builtin_fmaf(l11, j, a.y);
-    G = __builtin_amdgcn_exp2f(-__builtin_fmaf(u, u, v * v));
-    const float araw = o * G;
+    const float araw = __builtin_amdgcn_exp2f(__builtin_fmaf(-u, u, __builtin_fmaf(-v, v, log2o)));
     // araw >= 0: non-negative floats order as their bit patterns, so the
     // clamp is an integer min (no canonicalisation of alpha_max per pixel);
     // a NaN araw gives alpha_max or a NaN alpha, which no pixel blends
@@ -333,9 +332,9 @@ __global__ __launch_bounds__(kWave * kW, (forward_min_waves<kW, kDepth, kCount>(
 #pragma unroll
                 for (int k = 0; k < kPPL; ++k) {
                     if (!(m & (1u << k))) continue;  // uniform
-                    float alpha, G, u, v;
+                    float alpha, u, v;
                     pixel_alpha<kSplit>((float)slot_px<kW>(w, k, lx), (float)slot_py<kW>(w, k, ly), a, c, b.x, b.y,
-                                        s.alpha_max, alpha, G, u, v);
+                                        s.alpha_max, alpha, u, v);
                     const float aT = alpha * T[k];
                     const float Tn = T[k] - aT;  // T (1 - alpha)
                     const bool live = alpha >= s.alpha_min;
@@ -587,8 +586,8 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, co
                 for (int k = 0; k < kPPL; ++k) {
                     if (!(m & (1u << k))) continue;  // uniform
                     const float fi = (float)slot_px<kW>(w, k, lx), fj = (float)slot_py<kW>(w, k, ly);
-                    float alpha, G, wu, wv;
-                    const float araw = pixel_alpha<kSplit>(fi, fj, a, c, b.x, b.y, s.alpha_max, alpha, G, wu, wv);
+                    float alpha, wu, wv;
+                    const float araw = pixel_alpha<kSplit>(fi, fj, a, c, b.x, b.y, s.alpha_max, alpha, wu, wv);
                     const bool valid = pos < last[k] && alpha >= s.alpha_min;
                     if (__ballot(valid) == 0ull) continue;  // uniform: nothing blended in this quadrant
                     any = true;
@@ -619,7 +618,7 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, co
                     v[2] = __builtin_fmaf(wu, gu, v[2]);
                     v[3] = __builtin_fmaf(wu, gv, v[3]);
                     v[4] = __builtin_fmaf(wv, gv, v[4]);
-                    v[5] = __builtin_fmaf(G, da, v[5]);
+                    v[5] += gp;  // o dL/do
                 }
                 if (any) {
                     const float u = wave_reduce_scatter<kNF>(v, lane);
@@ -653,7 +652,7 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, co
             out[2] = mo[2];  // sum(wu wu gp)
             out[3] = mo[3];  // sum(wu wv gp)
             out[4] = mo[4];  // sum(wv wv gp)
-            out[5] = mo[5];  // dL/do
+            out[5] = mo[5] * __builtin_amdgcn_exp2f(-b.y);  // dL/do: sum(gp) / o
             out[6] = mo[6];
             out[7] = mo[7];
             out[8] = mo[8];

@@ -21,8 +21,9 @@ constexpr int kMaxBatch = OMNIGS_MAX_BATCH;  // cameras per batched launch
 // next to a tile keep full precision at 4K widths.
 struct alignas(16) BlendRecord {
     float px_hi, px_lo, py_hi, py_lo;  // pixel position of the centre (Eq. 5 or Eq. 2)
-    float l00, l10, l11, opacity;      // Cholesky factor L of Q = Sigma2D^-1 (Eq. 8), scaled by
-                                       // sqrt(log2(e) / 2), and the opacity
+    float l00, l10, l11, log2o;        // Cholesky factor L of Q = Sigma2D^-1 (Eq. 8), scaled by
+                                       // sqrt(log2(e) / 2), and log2 of the opacity: the blends
+                                       // take alpha = 2^(log2o - |L^T d|^2)
     float r, g, b;                     // SH colour, clamped at 0
     float reach;                       // log2(opacity / alpha_min): alpha >= alpha_min
                                        // iff |L^T d|^2 <= reach (L scaled as above)

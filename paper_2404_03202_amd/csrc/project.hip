@@ -306,14 +306,14 @@ __device__ inline uint32_t project_one(const ProjectArgs &A, int64_t i, int64_t 
     r.l00 = (float)(ls * sqrt(P.c / P.det));
     r.l10 = (float)(ls * (-P.b / (sc * sqrt(P.det))));
     r.l11 = (float)(ls / sc);
-    r.opacity = (float)o;
+    r.log2o = (float)log2(o);
     r.r = rgb[0];
     r.g = rgb[1];
     r.b = rgb[2];
     r.reach = (float)(log2(o / A.alpha_min));
     float4 *dst = reinterpret_cast<float4 *>(rec + slot);
     dst[0] = make_float4(r.px_hi, r.px_lo, r.py_hi, r.py_lo);
-    dst[1] = make_float4(r.l00, r.l10, r.l11, r.opacity);
+    dst[1] = make_float4(r.l00, r.l10, r.l11, r.log2o);
     dst[2] = make_float4(r.r, r.g, r.b, r.reach);
     depth_key[slot] = __float_as_uint((float)P.depth);
     if (depth) depth[slot] = (float)P.depth;
