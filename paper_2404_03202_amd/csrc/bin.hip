@@ -27,6 +27,7 @@ constexpr int kChunk = 256;  // super-list entries per chunk (one per thread)
 constexpr int kThreads = kChunk;
 constexpr int kWaves = kThreads / kWave;
 constexpr int kTilesPer = kSuper * kSuper;  // 64 tiles per super-tile
+constexpr uint32_t kXcds = 8;  // XCDs of the device, each with its own L2
 
 __device__ inline int find_super_frame(const SuperTable &T, uint32_t s) {
     int f = 0;
@@ -160,8 +161,13 @@ __global__ __launch_bounds__(kThreads) void k_bin_expand(SuperTable T, const uin
                                                          uint32_t *inst_gauss, int32_t *overflow) {
     __shared__ uint64_t rc[kWaves][2 * kSuper];
     __shared__ uint32_t wpre[kWaves][kTilesPer];
-    const uint32_t k = blockIdx.x;
-    if (k >= choff[n_super]) return;
+    // workgroups go to the XCDs in turn (workgroup b to XCD b mod 8): XCD x
+    // takes the chunks [x per, (x + 1) per) in order, so the chunks that write
+    // adjacent pieces of a tile's list run on one XCD and their partial cache
+    // lines meet in its L2 (the grid is a multiple of 8 and covers 8 per)
+    const uint32_t total = choff[n_super], per = (total + kXcds - 1) / kXcds;
+    const uint32_t k = (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+    if (blockIdx.x / kXcds >= per || k >= total) return;
     const int w = threadIdx.x / kWave, lane = __lane_id();
     const uint32_t s = desc[k], o = choff[s], n = nch[s], c = k - o;
     const SuperFrame &F = T.f[find_super_frame(T, s)];
@@ -277,7 +283,7 @@ hipError_t launch_binning(const SuperTable &T, uint32_t n_super_total, const uin
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_bin_ranges, dim3((unsigned)blocks_for((int64_t)n_super_total * kTilesPer, 256)), dim3(256), 0,
                        st, T, n_super_total, B.choff, B.nch, B.scanned, inst_cap, ranges);
-    hipLaunchKernelGGL(k_bin_expand, dim3((unsigned)K), dim3(kThreads), 0, st, T, rect, sinst_gauss, sranges, B.choff,
+    hipLaunchKernelGGL(k_bin_expand, dim3((unsigned)((K + kXcds - 1) / kXcds * kXcds)), dim3(kThreads), 0, st, T, rect, sinst_gauss, sranges, B.choff,
                        B.nch, B.desc, n_super_total, B.scanned, inst_cap, inst_gauss, overflow);
     return hipGetLastError();
 }
