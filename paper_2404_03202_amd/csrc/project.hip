@@ -38,6 +38,7 @@ namespace {
 
 constexpr double kPi = 3.141592653589793238462643383279502884;
 constexpr double kLn2d = 0.693147180559945309417232121458176568;
+constexpr double kInvPi = 0.318309886183790671537767526745028724;
 
 // Real SH basis constants (Condon-Shortley phase, index l*l + l + m,
 // z polar axis), from N_l^m = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!):
@@ -169,17 +170,20 @@ __device__ inline bool project_core(const ProjectArgs &A, int64_t i, double o, P
         P.depth = P.tr;
         double lon = atan2(tx, tz);
         if (lon >= kPi) lon = -kPi;
-        const double lat = asin(ty / P.tr);
-        P.px = (lon / kPi + 1.0) * (0.5 * A.width);
-        P.py = (2.0 * lat / kPi + 1.0) * (0.5 * A.height);
-        const double kx = A.width / (2.0 * kPi), ky = A.height / kPi;
-        const double r2 = P.tr * P.tr;
-        P.J[0] = kx * tz / rho2;
+        // one reciprocal per denominator, multiplied in (a double division is
+        // a long dependent sequence; the product differs in the last bit)
+        const double itr = 1.0 / P.tr;
+        const double lat = asin(ty * itr);
+        P.px = (lon * kInvPi + 1.0) * (0.5 * A.width);
+        P.py = (2.0 * lat * kInvPi + 1.0) * (0.5 * A.height);
+        const double kx = A.width * (0.5 * kInvPi), ky = A.height * kInvPi;
+        const double irho2 = 1.0 / rho2, ir2 = itr * itr, ir2rho = ir2 / P.rho;
+        P.J[0] = kx * tz * irho2;
         P.J[1] = 0.0;
-        P.J[2] = -kx * tx / rho2;
-        P.J[3] = -ky * tx * ty / (r2 * P.rho);
-        P.J[4] = ky * P.rho / r2;
-        P.J[5] = -ky * tz * ty / (r2 * P.rho);
+        P.J[2] = -kx * tx * irho2;
+        P.J[3] = -ky * tx * ty * ir2rho;
+        P.J[4] = ky * P.rho * ir2;
+        P.J[5] = -ky * tz * ty * ir2rho;
         for (int k = 0; k < 6; ++k) P.Jp[k] = P.J[k];
     }
     for (int a = 0; a < 2; ++a)
@@ -188,7 +192,8 @@ __device__ inline bool project_core(const ProjectArgs &A, int64_t i, double o, P
     const float4 q = reinterpret_cast<const float4 *>(A.quats)[i];
     P.qnorm = sqrt((double)q.x * q.x + (double)q.y * q.y + (double)q.z * q.z + (double)q.w * q.w);
     if (!(P.qnorm > 0.0)) return false;
-    const double w = q.x / P.qnorm, x = q.y / P.qnorm, y = q.z / P.qnorm, z = q.w / P.qnorm;
+    const double iqn = 1.0 / P.qnorm;
+    const double w = q.x * iqn, x = q.y * iqn, y = q.z * iqn, z = q.w * iqn;
     P.qn[0] = w; P.qn[1] = x; P.qn[2] = y; P.qn[3] = z;
     double *R = P.Rq;
     R[0] = 1.0 - 2.0 * (y * y + z * z); R[1] = 2.0 * (x * y - w * z);       R[2] = 2.0 * (x * z + w * y);
@@ -206,9 +211,10 @@ __device__ inline bool project_core(const ProjectArgs &A, int64_t i, double o, P
     if (!(P.det > 0.0)) return false;
     const double v0 = m0 - A.campos[0], v1 = m1 - A.campos[1], v2 = m2 - A.campos[2];
     P.vnorm = sqrt(v0 * v0 + v1 * v1 + v2 * v2);
-    P.dir[0] = v0 / P.vnorm;
-    P.dir[1] = v1 / P.vnorm;
-    P.dir[2] = v2 / P.vnorm;
+    const double ivn = 1.0 / P.vnorm;
+    P.dir[0] = v0 * ivn;
+    P.dir[1] = v1 * ivn;
+    P.dir[2] = v2 * ivn;
     return true;
 }
 
@@ -408,24 +414,26 @@ __device__ inline void jacobian_grad(const Proj &P, double kx, double ky, double
     const double r2 = P.tr * P.tr, r4 = r2 * r2;
     const double rho3 = rho2 * rho;
     const double txx_tzz = tx * tx - tz * tz;
-    dJ[0][0] = -2.0 * kx * tx * tz / rho4;
+    // the denominators' reciprocals, multiplied in
+    const double irho4 = 1.0 / rho4, ir4 = 1.0 / r4, ir4rho = ir4 / rho, ir4rho3 = ir4rho / rho2;
+    dJ[0][0] = -2.0 * kx * tx * tz * irho4;
     dJ[0][1] = 0.0;
-    dJ[0][2] = kx * txx_tzz / rho4;
+    dJ[0][2] = kx * txx_tzz * irho4;
     dJ[1][0] = dJ[1][1] = dJ[1][2] = 0.0;
-    dJ[2][0] = kx * txx_tzz / rho4;
+    dJ[2][0] = kx * txx_tzz * irho4;
     dJ[2][1] = 0.0;
-    dJ[2][2] = 2.0 * kx * tx * tz / rho4;
+    dJ[2][2] = 2.0 * kx * tx * tz * irho4;
     const double q = 2.0 * rho2 + r2;
     const double u = ty * ty - rho2;
-    dJ[3][0] = -ky * ty * (r2 * rho2 - tx * tx * q) / (r4 * rho3);
-    dJ[3][1] = ky * tx * u / (r4 * rho);
-    dJ[3][2] = ky * tx * ty * tz * q / (r4 * rho3);
-    dJ[4][0] = ky * tx * u / (rho * r4);
-    dJ[4][1] = -2.0 * ky * rho * ty / r4;
-    dJ[4][2] = ky * tz * u / (rho * r4);
-    dJ[5][0] = ky * tx * ty * tz * q / (r4 * rho3);
-    dJ[5][1] = ky * tz * u / (r4 * rho);
-    dJ[5][2] = -ky * ty * (r2 * rho2 - tz * tz * q) / (r4 * rho3);
+    dJ[3][0] = -ky * ty * (r2 * rho2 - tx * tx * q) * ir4rho3;
+    dJ[3][1] = ky * tx * u * ir4rho;
+    dJ[3][2] = ky * tx * ty * tz * q * ir4rho3;
+    dJ[4][0] = ky * tx * u * ir4rho;
+    dJ[4][1] = -2.0 * ky * rho * ty * ir4;
+    dJ[4][2] = ky * tz * u * ir4rho;
+    dJ[5][0] = ky * tx * ty * tz * q * ir4rho3;
+    dJ[5][1] = ky * tz * u * ir4rho;
+    dJ[5][2] = -ky * ty * (r2 * rho2 - tz * tz * q) * ir4rho3;
 }
 
 template <int D>
@@ -457,7 +465,8 @@ __global__ __launch_bounds__(256) void k_project_backward(ProjectArgs A, const u
     // 1/2 (2 ln2)^2 Ls M Ls^T = ln2 L M L^T, with
     // L = [[sqrt(c / det), 0], [-b / sqrt(c det), 1 / sqrt(c)]]
     const double sc = sqrt(P.c), sd = sqrt(P.det);
-    const double L0 = sc / sd, L1 = -P.b / (sc * sd), L2 = 1.0 / sc;
+    const double isc = 1.0 / sc, isd = 1.0 / sd;
+    const double L0 = sc * isd, L1 = -P.b * (isc * isd), L2 = isc;
     const double m00 = g[2], m01 = g[3], m11 = g[4];
     const double r1 = L1 * m00 + L2 * m01;  // row 1 of L M, first column
     const double S00 = kLn2d * (L0 * L0 * m00);
@@ -497,10 +506,11 @@ __global__ __launch_bounds__(256) void k_project_backward(ProjectArgs A, const u
                     x * dR[6] + y * dR[7]);
     const double qd = w * dqn[0] + x * dqn[1] + y * dqn[2] + z * dqn[3];
     float4 dq;
-    dq.x = (float)((dqn[0] - w * qd) / P.qnorm);
-    dq.y = (float)((dqn[1] - x * qd) / P.qnorm);
-    dq.z = (float)((dqn[2] - y * qd) / P.qnorm);
-    dq.w = (float)((dqn[3] - z * qd) / P.qnorm);
+    const double iqn = 1.0 / P.qnorm;
+    dq.x = (float)((dqn[0] - w * qd) * iqn);
+    dq.y = (float)((dqn[1] - x * qd) * iqn);
+    dq.z = (float)((dqn[2] - y * qd) * iqn);
+    dq.w = (float)((dqn[3] - z * qd) * iqn);
     // M = J W: dJ = dM W^T
     double dJ[6];
     for (int a = 0; a < 2; ++a)
@@ -510,17 +520,25 @@ __global__ __launch_bounds__(256) void k_project_backward(ProjectArgs A, const u
     if (A.model == OMNIGS_CAMERA_PINHOLE)
         jacobian_grad_pinhole(P, A.fx, A.fy, dJdt);
     else
-        jacobian_grad(P, A.width / (2.0 * kPi), A.height / kPi, dJdt);
+        jacobian_grad(P, A.width * (0.5 * kInvPi), A.height * kInvPi, dJdt);
     double dt[3];
+    const double itr = 1.0 / P.tr;
     for (int nn = 0; nn < 3; ++nn) {
         double v = P.Jp[nn] * g[0] + P.Jp[3 + nn] * g[1];
         for (int e = 0; e < 6; ++e) v += dJ[e] * dJdt[e][nn];
         // the depth value d: t_r (d t_r / dt = t / t_r) or t_z
-        v += A.model == OMNIGS_CAMERA_PINHOLE ? (nn == 2 ? g[kAcc] : 0.0) : g[kAcc] * P.t[nn] / P.tr;
+        v += A.model == OMNIGS_CAMERA_PINHOLE ? (nn == 2 ? g[kAcc] : 0.0) : g[kAcc] * P.t[nn] * itr;
         dt[nn] = v;
     }
     double dm[3];
     for (int k = 0; k < 3; ++k) dm[k] = A.R[k] * dt[0] + A.R[3 + k] * dt[1] + A.R[6 + k] * dt[2];
+    // the geometric gradients out before the SH term, so that their values
+    // are not held through it
+    for (int k = 0; k < 3; ++k) G.dscales[3 * i + k] = (float)dS[k];
+    reinterpret_cast<float4 *>(G.dquats)[i] = dq;
+    G.dopacities[i] = (float)g[5];
+    G.dscreen[2 * i] = (float)(g[0] * (0.5 * A.width));
+    G.dscreen[2 * i + 1] = (float)(g[1] * (0.5 * A.height));
     // SH colour: the coefficients loaded once as floats (all loads ahead of
     // the dsh stores, which may alias them), the basis gradient accumulated
     // term by term
@@ -557,15 +575,9 @@ __global__ __launch_bounds__(256) void k_project_backward(ProjectArgs A, const u
         dsh[3 * k + 2] = (float)(Y[k] * grgb[2]);
     }
     const double pd = P.dir[0] * gdir[0] + P.dir[1] * gdir[1] + P.dir[2] * gdir[2];
-    for (int k = 0; k < 3; ++k) dm[k] += (gdir[k] - P.dir[k] * pd) / P.vnorm;
-    for (int k = 0; k < 3; ++k) {
-        G.dmeans[3 * i + k] = (float)dm[k];
-        G.dscales[3 * i + k] = (float)dS[k];
-    }
-    reinterpret_cast<float4 *>(G.dquats)[i] = dq;
-    G.dopacities[i] = (float)g[5];
-    G.dscreen[2 * i] = (float)(g[0] * (0.5 * A.width));
-    G.dscreen[2 * i + 1] = (float)(g[1] * (0.5 * A.height));
+    const double ivn = 1.0 / P.vnorm;
+    for (int k = 0; k < 3; ++k) dm[k] += (gdir[k] - P.dir[k] * pd) * ivn;
+    for (int k = 0; k < 3; ++k) G.dmeans[3 * i + k] = (float)dm[k];
 }
 
 }  // namespace
