@@ -35,11 +35,6 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / kWave;
-#ifndef OMNIGS_SORT_ITEMS
-#define OMNIGS_SORT_ITEMS 16
-#endif
-constexpr int kItems = OMNIGS_SORT_ITEMS;   // keys per thread per pass
-constexpr int kTileKeys = kThreads * kItems;  // keys per block
 constexpr int kRadixBits = 8;
 constexpr int kBins = 1 << kRadixBits;
 constexpr int kScanItems = 16;
@@ -84,6 +79,45 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *wave_tot, 
     __syncthreads();
     return base + x - v;
 }
+
+// The same over the NT threads of a block (NT / 64 waves).
+template <int NT>
+__device__ inline uint32_t block_exclusive_scan_n(uint32_t v, uint32_t *wave_tot, uint32_t *total) {
+    constexpr int NW = NT / kWave;
+    const int lane = __lane_id(), w = threadIdx.x / kWave;
+    uint32_t x = v;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off, kWave);
+        if (lane >= off) x += y;
+    }
+    if (lane == kWave - 1) wave_tot[w] = x;
+    __syncthreads();
+    uint32_t base = 0, all = 0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+        const uint32_t t = wave_tot[k];
+        base += (k < w) ? t : 0u;
+        all += t;
+    }
+    if (threadIdx.x == 0) *total = all;
+    __syncthreads();
+    return base + x - v;
+}
+
+// A pass runs 512 threads (eight waves, kPI keys each) per block: more waves
+// per compute unit hide more of the ranking's and the loads' latency; the
+// first kBins threads own a digit each.  Blocks hold 4096 keys, or 6144 once
+// that still gives every compute unit a block (fewer blocks, shorter
+// lookback chains).
+constexpr int kPassThreads = 512;
+constexpr int kPassWaves = kPassThreads / kWave;
+constexpr int kSmallItems = 8, kLargeItems = 12;
+static_assert(kPassThreads >= kBins, "pass layout");
+constexpr int64_t kLargeFrom = (int64_t)256 * kPassThreads * kLargeItems;
+
+// Keys per block of a sort of n keys.
+int64_t pass_tile_keys(int64_t n) { return (int64_t)kPassThreads * (n >= kLargeFrom ? kLargeItems : kSmallItems); }
 
 // ---------------------------------------------------------------- radix pass
 // Element count of a sort: n, or min(n, *n_dev) when counted on the device.
@@ -152,7 +186,7 @@ __global__ __launch_bounds__(kThreads) void k_sort_hist(const uint32_t *keys, in
     }
 }
 
-// One pass: the block at ticket position b ranks its kTileKeys keys by digit
+// One pass: the block at ticket position b ranks its kTK keys by digit
 // (ballot matches per wave), publishes its digit counts, looks back over the
 // earlier blocks' words for the count of each digit before it (decoupled
 // lookback), and writes its keys as contiguous per-digit runs at
@@ -160,50 +194,53 @@ __global__ __launch_bounds__(kThreads) void k_sort_hist(const uint32_t *keys, in
 // (rank in the block).  vals_in == nullptr: the values are the input
 // positions.  key_ranges (one-pass sorts, may be null): workgroup 0 writes
 // [start, end) of every key value below n_ranges from the digit totals.
-__global__ __launch_bounds__(kThreads) void k_radix_pass(const uint32_t *keys_in, const uint32_t *vals_in,
+template <int kPI>
+__global__ __launch_bounds__(kPassThreads) void k_radix_pass(const uint32_t *keys_in, const uint32_t *vals_in,
                                                           uint32_t *keys_out, uint32_t *vals_out, int64_t n_max,
                                                           const uint32_t *n_dev, int shift, int bits,
                                                           const uint32_t *ghist, uint32_t *status,
                                                           uint32_t *ticket, uint2 *key_ranges, int n_ranges,
                                                           uint32_t *fault, uint32_t max_polls) {
-    __shared__ uint32_t s_keys[kTileKeys];
-    __shared__ uint32_t s_vals[kTileKeys];
-    __shared__ uint32_t cnt[kWaves][kBins];
+    constexpr int kTK = kPassThreads * kPI;  // keys per block
+    __shared__ uint32_t s_keys[kTK];
+    __shared__ uint32_t s_vals[kTK];
+    __shared__ uint32_t cnt[kPassWaves][kBins];
     __shared__ uint32_t gbase[kBins];
-    __shared__ uint32_t wave_tot[kWaves];
+    __shared__ uint32_t wave_tot[kPassWaves];
     __shared__ uint32_t total;
     __shared__ uint32_t s_pos;
     const int64_t n = sort_count(n_max, n_dev);
     if (key_ranges && blockIdx.x == 0) {
-        const uint32_t c = ghist[threadIdx.x];
-        const uint32_t start = block_exclusive_scan(c, wave_tot, &total);
+        const uint32_t c = threadIdx.x < kBins ? ghist[threadIdx.x] : 0u;
+        const uint32_t start = block_exclusive_scan_n<kPassThreads>(c, wave_tot, &total);
         if ((int)threadIdx.x < n_ranges) key_ranges[threadIdx.x] = make_uint2(start, start + c);
     }
-    // the first ceil(n / kTileKeys) workgroups take the tickets 0, 1, ... in
+    // the first ceil(n / kTK) workgroups take the tickets 0, 1, ... in
     // the order they start; the others (a grid sized for a capacity) have no
     // keys and leave at once
-    if ((int64_t)blockIdx.x * kTileKeys >= n) return;
+    if ((int64_t)blockIdx.x * kTK >= n) return;
     if (threadIdx.x == 0) s_pos = atomicAdd(ticket, 1u);
-    const uint32_t gcount = ghist[threadIdx.x];  // keys of digit threadIdx.x (0 past the pass's digits)
-    for (int k = threadIdx.x; k < kWaves * kBins; k += kThreads) (&cnt[0][0])[k] = 0;
+    // keys of digit threadIdx.x (0 past the pass's digits)
+    const uint32_t gcount = threadIdx.x < kBins ? ghist[threadIdx.x] : 0u;
+    for (int k = threadIdx.x; k < kPassWaves * kBins; k += kPassThreads) (&cnt[0][0])[k] = 0;
     __syncthreads();
     const uint32_t b = s_pos;
-    const int64_t block0 = (int64_t)b * kTileKeys;
+    const int64_t block0 = (int64_t)b * kTK;
     const int w = threadIdx.x / kWave, lane = __lane_id();
     const uint32_t mask = (1u << bits) - 1u;
-    const int64_t base = block0 + (int64_t)w * (kItems * kWave);
-    uint32_t key[kItems], val[kItems], rank[kItems];
+    const int64_t base = block0 + (int64_t)w * (kPI * kWave);
+    uint32_t key[kPI], val[kPI], rank[kPI];
     // keys past n get the largest digit: they sort last in the block and are
     // never written out
 #pragma unroll
-    for (int it = 0; it < kItems; ++it) {
+    for (int it = 0; it < kPI; ++it) {
         const int64_t idx = base + it * kWave + lane;
         const bool valid = idx < n;
         key[it] = valid ? keys_in[idx] : 0xffffffffu;
         val[it] = valid ? (vals_in ? vals_in[idx] : (uint32_t)idx) : 0u;
     }
 #pragma unroll
-    for (int it = 0; it < kItems; ++it) {
+    for (int it = 0; it < kPI; ++it) {
         const int64_t idx = base + it * kWave + lane;
         const uint32_t d = (idx < n) ? (key[it] >> shift) & mask : mask;
         const uint64_t peers = match_digit(d, bits, true);
@@ -212,16 +249,16 @@ __global__ __launch_bounds__(kThreads) void k_radix_pass(const uint32_t *keys_in
         if ((peers & lanemask_lt()) == 0) cnt[w][d] = before + (uint32_t)__popcll(peers);
     }
     __syncthreads();
-    const int d = threadIdx.x;  // kThreads == kBins
-    uint32_t per[kWaves], tot = 0;
+    const int d = threadIdx.x;  // the digit of the first kBins threads
+    uint32_t per[kPassWaves], tot = 0;
 #pragma unroll
-    for (int k = 0; k < kWaves; ++k) {
-        per[k] = cnt[k][d];
+    for (int k = 0; k < kPassWaves; ++k) {
+        per[k] = d < kBins ? cnt[k][d] : 0u;
         tot += per[k];
     }
     // padding keys (digit `mask`) are not counted
-    const int64_t nvalid64 = n - block0 < kTileKeys ? n - block0 : kTileKeys;
-    const uint32_t pad = (uint32_t)(kTileKeys - nvalid64);
+    const int64_t nvalid64 = n - block0 < kTK ? n - block0 : kTK;
+    const uint32_t pad = (uint32_t)(kTK - nvalid64);
     const uint32_t mine = d == (int)mask ? tot - pad : tot;
     uint32_t before = 0;  // keys of digit d in the earlier blocks
     if (d <= (int)mask) {
@@ -268,21 +305,21 @@ __global__ __launch_bounds__(kThreads) void k_radix_pass(const uint32_t *keys_in
     }
     // block layout: digit runs in order, each wave's keys after the earlier
     // waves' keys of the same digit
-    const uint32_t start = block_exclusive_scan(tot, wave_tot, &total);
-    {
+    const uint32_t start = block_exclusive_scan_n<kPassThreads>(tot, wave_tot, &total);
+    if (d < kBins) {
         uint32_t run = start;
 #pragma unroll
-        for (int k = 0; k < kWaves; ++k) {
+        for (int k = 0; k < kPassWaves; ++k) {
             cnt[k][d] = run;
             run += per[k];
         }
     }
     // first output position of digit d: the keys of all smaller digits
-    const uint32_t gstart = block_exclusive_scan(gcount, wave_tot, &total);
+    const uint32_t gstart = block_exclusive_scan_n<kPassThreads>(gcount, wave_tot, &total);
     if (d <= (int)mask) gbase[d] = gstart + before - start;
     __syncthreads();
 #pragma unroll
-    for (int it = 0; it < kItems; ++it) {
+    for (int it = 0; it < kPI; ++it) {
         const int64_t idx = base + it * kWave + lane;
         const uint32_t dg = (idx < n) ? (key[it] >> shift) & mask : mask;
         const uint32_t pos = cnt[w][dg] + rank[it];
@@ -291,7 +328,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_pass(const uint32_t *keys_in
     }
     __syncthreads();
     const int nvalid = (int)nvalid64;
-    for (int q = threadIdx.x; q < nvalid; q += kThreads) {
+    for (int q = threadIdx.x; q < nvalid; q += kPassThreads) {
         const uint32_t k = s_keys[q];
         const uint32_t dg = (k >> shift) & mask;
         const uint32_t dst = gbase[dg] + (uint32_t)q;
@@ -638,7 +675,7 @@ hipError_t scan_exclusive(const uint32_t *in, uint32_t *out, int64_t n, uint32_t
 }
 
 size_t sort_scratch_bytes(int64_t n) {
-    const int64_t nb = blocks_for(n > 0 ? n : 1, kTileKeys);
+    const int64_t nb = blocks_for(n > 0 ? n : 1, pass_tile_keys(n));
     return ((size_t)kHeadWords + (size_t)kMaxPasses * nb * kBins) * 4 + 256;
 }
 
@@ -646,7 +683,7 @@ int64_t sort_clear_words(int64_t n, int bits) {
     if (n <= 0) return 0;
     bits = std::min(std::max(bits, 1), 32);
     const int passes = (bits + kRadixBits - 1) / kRadixBits;
-    return kHeadWords + (int64_t)passes * blocks_for(n, kTileKeys) * kBins;
+    return kHeadWords + (int64_t)passes * blocks_for(n, pass_tile_keys(n)) * kBins;
 }
 
 hipError_t radix_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_tmp,
@@ -662,7 +699,8 @@ hipError_t radix_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in, ui
     if (bits < 1) bits = 1;
     if (bits > 32) bits = 32;
     const int passes = (bits + kRadixBits - 1) / kRadixBits;
-    const int64_t nb = blocks_for(n, kTileKeys);
+    const int64_t nb = blocks_for(n, pass_tile_keys(n));
+    const bool large = n >= kLargeFrom;
     // [digit totals per pass | tickets | lookback words per pass], cleared at once
     uint32_t *head = static_cast<uint32_t *>(scratch);
     uint32_t *ghist = head, *tickets = head + kMaxPasses * kBins;
@@ -683,9 +721,16 @@ hipError_t radix_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in, ui
         const bool to_out = ((passes - 1 - p) % 2) == 0;
         uint32_t *dk = to_out ? keys_out : keys_tmp;
         uint32_t *dv = to_out ? vals_out : vals_tmp;
-        hipLaunchKernelGGL(k_radix_pass, dim3((unsigned)nb), dim3(kThreads), 0, st, src_k, src_v, dk, dv, n, n_dev,
-                           shift, pbits, (const uint32_t *)(ghist + p * kBins), status + (int64_t)p * nb * kBins,
-                           tickets + p, key_ranges, n_ranges, fault, g_max_polls);
+        const uint32_t *gh = ghist + p * kBins;
+        uint32_t *stp = status + (int64_t)p * nb * kBins;
+        if (large)
+            hipLaunchKernelGGL(k_radix_pass<kLargeItems>, dim3((unsigned)nb), dim3(kPassThreads), 0, st, src_k, src_v,
+                               dk, dv, n, n_dev, shift, pbits, gh, stp, tickets + p, key_ranges, n_ranges, fault,
+                               g_max_polls);
+        else
+            hipLaunchKernelGGL(k_radix_pass<kSmallItems>, dim3((unsigned)nb), dim3(kPassThreads), 0, st, src_k, src_v,
+                               dk, dv, n, n_dev, shift, pbits, gh, stp, tickets + p, key_ranges, n_ranges, fault,
+                               g_max_polls);
         src_k = dk;
         src_v = dv;
     }
