@@ -39,6 +39,7 @@ constexpr int kRadixBits = 8;
 constexpr int kBins = 1 << kRadixBits;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kThreads * kScanItems;
+constexpr int kScanThreads = 512;  // threads of a lookback scan block (kScanTile / 512 items each)
 constexpr int kEmitItems = 8;
 constexpr int kEmitSpan = kThreads * kEmitItems;  // outputs per emit block
 static_assert(kEmitItems == 8, "k_emit stores a thread's outputs as two uint4");
@@ -356,11 +357,12 @@ __device__ inline uint32_t scan_input(const uint32_t *in, const uint32_t *gather
 // status: one 64-bit word per tile, zero until published, then value + 1
 // with the top bit set when the value is inclusive.
 constexpr uint64_t kInc64 = 1ull << 63;
-__global__ __launch_bounds__(kThreads) void k_scan_lookback(const uint32_t *in, const uint32_t *gather, uint32_t *out,
+__global__ __launch_bounds__(kScanThreads) void k_scan_lookback(const uint32_t *in, const uint32_t *gather, uint32_t *out,
                                                              int64_t n, uint64_t *status, uint32_t *ticket,
                                                              uint32_t *grand_total, uint32_t *fault,
                                                              uint32_t max_polls) {
-    __shared__ uint32_t wave_tot[kWaves];
+    constexpr int kSI = kScanTile / kScanThreads;  // items per thread
+    __shared__ uint32_t wave_tot[kScanThreads / kWave];
     __shared__ uint32_t total;
     __shared__ uint32_t s_data[kScanTile];
     __shared__ uint32_t s_pos;
@@ -369,23 +371,23 @@ __global__ __launch_bounds__(kThreads) void k_scan_lookback(const uint32_t *in, 
     __syncthreads();
     const uint32_t b = s_pos;
     const int64_t block0 = (int64_t)b * kScanTile;
-    uint32_t v[kScanItems];
+    uint32_t v[kSI];
 #pragma unroll
-    for (int it = 0; it < kScanItems; ++it) {
-        const int64_t idx = block0 + it * kThreads + threadIdx.x;
+    for (int it = 0; it < kSI; ++it) {
+        const int64_t idx = block0 + it * kScanThreads + threadIdx.x;
         v[it] = idx < n ? scan_input(in, gather, idx, n) : 0u;
     }
 #pragma unroll
-    for (int it = 0; it < kScanItems; ++it) s_data[it * kThreads + threadIdx.x] = v[it];
+    for (int it = 0; it < kSI; ++it) s_data[it * kScanThreads + threadIdx.x] = v[it];
     __syncthreads();
-    // blocked arrangement: thread t owns items [t*kScanItems, (t+1)*kScanItems)
+    // blocked arrangement: thread t owns items [t*kSI, (t+1)*kSI)
     uint32_t s = 0;
 #pragma unroll
-    for (int it = 0; it < kScanItems; ++it) {
-        v[it] = s_data[threadIdx.x * kScanItems + it];
+    for (int it = 0; it < kSI; ++it) {
+        v[it] = s_data[threadIdx.x * kSI + it];
         s += v[it];
     }
-    uint32_t run = block_exclusive_scan(s, wave_tot, &total);
+    uint32_t run = block_exclusive_scan_n<kScanThreads>(s, wave_tot, &total);
     if (threadIdx.x < kWave) {
         const int lane = __lane_id();
         const uint64_t agg = total;
@@ -428,16 +430,16 @@ __global__ __launch_bounds__(kThreads) void k_scan_lookback(const uint32_t *in, 
     __syncthreads();
     run += (uint32_t)s_before;
 #pragma unroll
-    for (int it = 0; it < kScanItems; ++it) {
-        s_data[threadIdx.x * kScanItems + it] = run;
+    for (int it = 0; it < kSI; ++it) {
+        s_data[threadIdx.x * kSI + it] = run;
         run += v[it];
     }
-    if (grand_total && block0 + kScanTile >= n && threadIdx.x == kThreads - 1) *grand_total = run;
+    if (grand_total && block0 + kScanTile >= n && threadIdx.x == kScanThreads - 1) *grand_total = run;
     __syncthreads();
 #pragma unroll
-    for (int it = 0; it < kScanItems; ++it) {
-        const int64_t idx = block0 + it * kThreads + threadIdx.x;
-        if (idx < n) out[idx] = s_data[it * kThreads + threadIdx.x];
+    for (int it = 0; it < kSI; ++it) {
+        const int64_t idx = block0 + it * kScanThreads + threadIdx.x;
+        if (idx < n) out[idx] = s_data[it * kScanThreads + threadIdx.x];
     }
 }
 
@@ -669,7 +671,7 @@ hipError_t scan_exclusive(const uint32_t *in, uint32_t *out, int64_t n, uint32_t
         const hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(status), 0u, words, st);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_scan_lookback, dim3((unsigned)nb), dim3(kThreads), 0, st, in, gather, out, n, status, ticket,
+    hipLaunchKernelGGL(k_scan_lookback, dim3((unsigned)nb), dim3(kScanThreads), 0, st, in, gather, out, n, status, ticket,
                        total, fault, g_max_polls);
     return hipGetLastError();
 }
