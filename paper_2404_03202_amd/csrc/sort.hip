@@ -152,13 +152,16 @@ constexpr int kLook = OMNIGS_SORT_LOOK;  // lookback words loaded at once
 // ghist is zero on entry.  Each block takes chunks of kHistChunk keys (all
 // loads of a chunk issued before its counts), counts them in per-wave LDS
 // histograms and adds its nonzero totals to ghist once.
-constexpr int kHistItems = 16;
-constexpr int kHistChunk = kThreads * kHistItems;
+constexpr int kHistThreads = 512;  // eight waves: more loads in flight per compute unit
+constexpr int kHistWaves = kHistThreads / kWave;
+constexpr int kHistItems = 8;
+constexpr int kHistChunk = kHistThreads * kHistItems;
 constexpr int kHistMaxBlocks = 256;  // bounds the global atomics per digit
-__global__ __launch_bounds__(kThreads) void k_sort_hist(const uint32_t *keys, int64_t n_max, const uint32_t *n_dev,
-                                                         int passes, int bits, uint32_t *ghist) {
-    __shared__ uint32_t h[kWaves][kMaxPasses * kBins];
-    for (int k = threadIdx.x; k < kWaves * kMaxPasses * kBins; k += kThreads) (&h[0][0])[k] = 0;
+__global__ __launch_bounds__(kHistThreads) void k_sort_hist(const uint32_t *keys, int64_t n_max,
+                                                             const uint32_t *n_dev, int passes, int bits,
+                                                             uint32_t *ghist) {
+    __shared__ uint32_t h[kHistWaves][kMaxPasses * kBins];
+    for (int k = threadIdx.x; k < kHistWaves * kMaxPasses * kBins; k += kHistThreads) (&h[0][0])[k] = 0;
     __syncthreads();
     const int64_t n = sort_count(n_max, n_dev);
     const int w = threadIdx.x / kWave;
@@ -166,12 +169,12 @@ __global__ __launch_bounds__(kThreads) void k_sort_hist(const uint32_t *keys, in
         uint32_t key[kHistItems];
 #pragma unroll
         for (int it = 0; it < kHistItems; ++it) {
-            const int64_t idx = c0 + it * kThreads + threadIdx.x;
+            const int64_t idx = c0 + it * kHistThreads + threadIdx.x;
             key[it] = idx < n ? keys[idx] : 0u;
         }
 #pragma unroll
         for (int it = 0; it < kHistItems; ++it) {
-            if (c0 + it * kThreads + threadIdx.x >= n) continue;
+            if (c0 + it * kHistThreads + threadIdx.x >= n) continue;
             for (int p = 0; p < passes; ++p) {
                 const int pb = min(kRadixBits, bits - p * kRadixBits);
                 atomicAdd(&h[w][p * kBins + ((key[it] >> (p * kRadixBits)) & ((1u << pb) - 1u))], 1u);
@@ -179,10 +182,10 @@ __global__ __launch_bounds__(kThreads) void k_sort_hist(const uint32_t *keys, in
         }
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < passes * kBins; k += kThreads) {
+    for (int k = threadIdx.x; k < passes * kBins; k += kHistThreads) {
         uint32_t t = 0;
 #pragma unroll
-        for (int q = 0; q < kWaves; ++q) t += h[q][k];
+        for (int q = 0; q < kHistWaves; ++q) t += h[q][k];
         if (t) atomicAdd(&ghist[k], t);
     }
 }
@@ -713,7 +716,7 @@ hipError_t radix_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in, ui
         if (e != hipSuccess) return e;
     }
     const int64_t hist_blocks = std::min<int64_t>(blocks_for(n, kHistChunk), kHistMaxBlocks);
-    hipLaunchKernelGGL(k_sort_hist, dim3((unsigned)hist_blocks), dim3(kThreads), 0, st, keys_in, n, n_dev, passes,
+    hipLaunchKernelGGL(k_sort_hist, dim3((unsigned)hist_blocks), dim3(kHistThreads), 0, st, keys_in, n, n_dev, passes,
                        bits, ghist);
     // ping-pong so that the last pass lands in keys_out / vals_out
     const uint32_t *src_k = keys_in, *src_v = vals_in;
