@@ -433,6 +433,16 @@ omnigs_status omnigs_reset_opacity(omnigs_params *p, omnigs_params *m1, omnigs_p
 omnigs_status omnigs_selftest_lookback(int32_t primitive, int64_t n, uint32_t max_polls, omnigs_allocator alloc,
                                        uint32_t *fault, int32_t *correct, void *stream);
 
+/* Binning path selection, for tests.  The tile binning (Sec. 3.3) takes each
+ * (Gaussian, 8x8-tile block) entry's covered tiles from the upper 16 bits of
+ * its sort key while a call's images hold at most `blocks` blocks (default
+ * and maximum 65536, which keeps the block ids within the lower 16 bits),
+ * and from the Gaussians' tile rectangles otherwise; both give the same
+ * tile lists.  blocks = 0 restores the default, larger values are clamped
+ * to it.  Process-wide, like omnigs_selftest_lookback's bound: not to be
+ * called while other threads launch library work.  Always OMNIGS_OK. */
+omnigs_status omnigs_set_cover_key_blocks(uint32_t blocks);
+
 /* Measured ceilings of the device that `stream` runs on, against which the
  * stages are quoted: the blends are bound by FP32 issue (Sec. 3.3-3.4 do a
  * few dozen scalar operations and one exp per pixel-instance pair), the

@@ -36,27 +36,6 @@ __device__ inline int find_super_frame(const SuperTable &T, uint32_t s) {
     return f;
 }
 
-// Rows and columns of super-tile (sx, sy) covered by the tile rectangle r
-// (columns wrapping across the seam): the covered tiles are their product,
-// tile (row k, column c) being tile 8k + c of the super-tile.
-struct Cover {
-    uint32_t rows, cols;
-};
-__device__ inline Cover cover_of(uint2 r, int tiles_x, int sx, int sy) {
-    const int ntx = (int)(r.x >> 16), tx0 = (int)(r.x & 0xffffu), nty = (int)(r.y >> 16), ty0 = (int)(r.y & 0xffffu);
-    const int y_lo = max(ty0, sy * kSuper) - sy * kSuper, y_hi = min(ty0 + nty, sy * kSuper + kSuper) - sy * kSuper;
-    if (ntx == 0 || y_hi <= y_lo) return Cover{0u, 0u};
-    uint32_t cols = 0;
-#pragma unroll
-    for (int c = 0; c < kSuper; ++c) {
-        const int tx = sx * kSuper + c;
-        int d = tx - tx0;
-        d += d < 0 ? tiles_x : 0;  // offset from the rectangle's first column, modulo tiles_x
-        cols |= (tx < tiles_x && d < ntx) ? (1u << c) : 0u;
-    }
-    return Cover{((1u << y_hi) - 1u) & ~((1u << y_lo) - 1u), cols};
-}
-
 // The wave's ballots of covered rows and columns: lane q < 8 receives the
 // ballot of row q, lane 8 + q that of column q.  The lanes covering tile
 // (k, c) are then rowball(k) & colball(c): a product of rectangles is the
@@ -100,7 +79,8 @@ __global__ __launch_bounds__(256) void k_bin_desc(const uint32_t *choff, uint32_
     desc[k] = lo;
 }
 
-__global__ __launch_bounds__(kThreads) void k_bin_count(SuperTable T, const uint2 *rect, const uint32_t *sinst_gauss,
+__global__ __launch_bounds__(kThreads) void k_bin_count(SuperTable T, const uint2 *rect, const uint32_t *skeys,
+                                                        const uint32_t *sinst_gauss,
                                                         const uint2 *sranges, const uint32_t *choff,
                                                         const uint32_t *nch, const uint32_t *desc, uint32_t n_super,
                                                         uint32_t *counts) {
@@ -120,7 +100,7 @@ __global__ __launch_bounds__(kThreads) void k_bin_count(SuperTable T, const uint
     const int sx = (int)(ls % (uint32_t)F.super_x), sy = (int)(ls / (uint32_t)F.super_x);
     const uint32_t e = sranges[s].x + c * kChunk + threadIdx.x;
     Cover cv{0u, 0u};
-    if (e < sranges[s].y) cv = cover_of(rect[sinst_gauss[e]], F.tiles_x, sx, sy);
+    if (e < sranges[s].y) cv = skeys ? cover_from_key(skeys[e]) : cover_of(rect[sinst_gauss[e]], F.tiles_x, sx, sy);
     const uint64_t b = row_col_ballots(cv, lane);
     if (lane < 2 * kSuper) rc[w][lane] = b;
     __syncthreads();
@@ -154,7 +134,8 @@ __global__ __launch_bounds__(256) void k_bin_ranges(SuperTable T, uint32_t n_sup
 }
 
 // Every instance of the chunk to its final position.
-__global__ __launch_bounds__(kThreads) void k_bin_expand(SuperTable T, const uint2 *rect, const uint32_t *sinst_gauss,
+__global__ __launch_bounds__(kThreads) void k_bin_expand(SuperTable T, const uint2 *rect, const uint32_t *skeys,
+                                                         const uint32_t *sinst_gauss,
                                                          const uint2 *sranges, const uint32_t *choff,
                                                          const uint32_t *nch, const uint32_t *desc, uint32_t n_super,
                                                          const uint32_t *scanned, uint64_t inst_cap,
@@ -178,7 +159,7 @@ __global__ __launch_bounds__(kThreads) void k_bin_expand(SuperTable T, const uin
     uint32_t g = 0;
     if (e < sranges[s].y) {
         g = sinst_gauss[e];
-        cv = cover_of(rect[g], F.tiles_x, sx, sy);
+        cv = skeys ? cover_from_key(skeys[e]) : cover_of(rect[g], F.tiles_x, sx, sy);
     }
     const uint64_t b = row_col_ballots(cv, lane);
     if (lane < 2 * kSuper) rc[w][lane] = b;
@@ -261,8 +242,9 @@ void binning_clear(void *scratch, uint64_t super_cap, uint32_t n_super_total, Cl
     L.add(B.scan_counts, scan_clear_words((int64_t)cells));
 }
 
-hipError_t launch_binning(const SuperTable &T, uint32_t n_super_total, const uint2 *rect, const uint32_t *sinst_gauss,
-                          const uint2 *sranges, uint64_t super_cap, uint64_t inst_cap, void *scratch, uint2 *ranges,
+hipError_t launch_binning(const SuperTable &T, uint32_t n_super_total, const uint2 *rect, const uint32_t *skeys,
+                          const uint32_t *sinst_gauss, const uint2 *sranges, uint64_t super_cap, uint64_t inst_cap,
+                          void *scratch, uint2 *ranges,
                           uint32_t *inst_gauss, int32_t *overflow, hipStream_t st, bool cleared,
                           uint32_t *fault) {
     if (n_super_total == 0) return hipSuccess;
@@ -276,15 +258,16 @@ hipError_t launch_binning(const SuperTable &T, uint32_t n_super_total, const uin
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_bin_desc, dim3((unsigned)blocks_for((int64_t)K, 256)), dim3(256), 0, st, B.choff,
                        n_super_total, K, B.desc);
-    hipLaunchKernelGGL(k_bin_count, dim3((unsigned)K), dim3(kThreads), 0, st, T, rect, sinst_gauss, sranges, B.choff,
-                       B.nch, B.desc, n_super_total, B.counts);
+    hipLaunchKernelGGL(k_bin_count, dim3((unsigned)K), dim3(kThreads), 0, st, T, rect, skeys, sinst_gauss, sranges,
+                       B.choff, B.nch, B.desc, n_super_total, B.counts);
     e = scan_exclusive(B.counts, B.scanned, (int64_t)cells, B.scanned + cells, B.scan_counts, st, nullptr, cleared,
                        fault);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_bin_ranges, dim3((unsigned)blocks_for((int64_t)n_super_total * kTilesPer, 256)), dim3(256), 0,
                        st, T, n_super_total, B.choff, B.nch, B.scanned, inst_cap, ranges);
-    hipLaunchKernelGGL(k_bin_expand, dim3((unsigned)((K + kXcds - 1) / kXcds * kXcds)), dim3(kThreads), 0, st, T, rect, sinst_gauss, sranges, B.choff,
-                       B.nch, B.desc, n_super_total, B.scanned, inst_cap, inst_gauss, overflow);
+    hipLaunchKernelGGL(k_bin_expand, dim3((unsigned)((K + kXcds - 1) / kXcds * kXcds)), dim3(kThreads), 0, st, T,
+                       rect, skeys, sinst_gauss, sranges, B.choff, B.nch, B.desc, n_super_total, B.scanned, inst_cap,
+                       inst_gauss, overflow);
     return hipGetLastError();
 }
 

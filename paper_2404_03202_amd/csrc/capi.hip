@@ -296,6 +296,10 @@ void geom_clear(int64_t n, GeomState &gst, GeomScratch &gs, ClearList &L) {
     L.add(gst.totals, 3);
 }
 
+// Largest block count of a launch whose block-entry keys carry the covers
+// (omnigs_set_cover_key_blocks lowers it to test the other path).
+uint32_t g_cover_key_blocks = kMaxCoverKeyBlocks;
+
 // Grids of the images of a launch.
 struct Grids {
     EmitFrames ef{};   // super-tile emission
@@ -309,6 +313,7 @@ struct Grids {
         sup.f[b] = SuperFrame{n_super, n_tiles, sx, sy, tiles_x, tiles_y};
         n_super += (uint32_t)(sx * sy);
         n_tiles += (uint32_t)(tiles_x * tiles_y);
+        ef.cover_key = n_super <= g_cover_key_blocks;
     }
 };
 
@@ -357,12 +362,14 @@ omnigs_status run_binning(int64_t nrec, const GeomState &gst, const GeomScratch 
                                  one_pass ? (int)G.n_super : 0, cleared, gst.totals + 2));
         if (!one_pass) {
             HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(bs.sranges), 0u, 2 * (int64_t)G.n_super, st));
-            HIP_TRY(launch_tile_ranges(bs.stile, gst.totals, super_cap, bs.sranges, G.n_super, st));
+            HIP_TRY(launch_tile_ranges(bs.stile, gst.totals, super_cap, bs.sranges, G.n_super,
+                                       G.ef.cover_key ? kMaxCoverKeyBlocks - 1u : ~0u, st));
         }
     }
     {
         StageTimer t(st, kStTileBin);
-        HIP_TRY(launch_binning(G.sup, G.n_super, gst.rect, bs.sgauss, bs.sranges, super_cap, inst_cap, bs.bin_tmp,
+        HIP_TRY(launch_binning(G.sup, G.n_super, gst.rect, G.ef.cover_key ? bs.stile : nullptr, bs.sgauss, bs.sranges,
+                               super_cap, inst_cap, bs.bin_tmp,
                                ranges, inst_gauss, overflow, st, cleared, gst.totals + 2));
     }
     if (overflow) {
@@ -732,6 +739,11 @@ omnigs_status omnigs_l1_loss(const float *image, const float *target, int64_t co
     hipStream_t st = static_cast<hipStream_t>(stream);
     StageTimer t(st, kStL1);
     HIP_TRY(launch_l1(image, target, count, dL_dimage, loss, a.base, st));
+    return OMNIGS_OK;
+}
+
+omnigs_status omnigs_set_cover_key_blocks(uint32_t blocks) {
+    g_cover_key_blocks = blocks == 0 || blocks > kMaxCoverKeyBlocks ? kMaxCoverKeyBlocks : blocks;
     return OMNIGS_OK;
 }
 

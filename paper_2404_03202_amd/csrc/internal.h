@@ -109,6 +109,46 @@ __host__ __device__ inline uint2 super_rect(uint2 r, int tiles_x) {
     return make_uint2(sx0 | (nsx << 16), sy0 | ((sy1 - sy0 + 1) << 16));
 }
 
+// Rows and columns of super-tile (sx, sy) covered by the tile rectangle r
+// (columns wrapping across the seam): the covered tiles are their product,
+// tile (row k, column c) being tile 8k + c of the super-tile.
+struct Cover {
+    uint32_t rows, cols;
+};
+// Bits [lo, hi) of the super-tile starting at column (or row) `base` that
+// the tile interval [a, b) covers.
+__device__ inline uint32_t cover_span(int a, int b, int base) {
+    const int lo = max(a, base) - base, hi = min(b, base + kSuper) - base;
+    return hi > lo ? ((1u << hi) - 1u) & ~((1u << lo) - 1u) : 0u;
+}
+__device__ inline Cover cover_of(uint2 r, int tiles_x, int sx, int sy) {
+    const int ntx = (int)(r.x >> 16), tx0 = (int)(r.x & 0xffffu), nty = (int)(r.y >> 16), ty0 = (int)(r.y & 0xffffu);
+    const uint32_t rows = cover_span(ty0, ty0 + nty, sy * kSuper);
+    if (ntx == 0 || rows == 0u) return Cover{0u, 0u};
+    // columns [tx0, tx0 + ntx) modulo tiles_x: the whole row of tiles, one
+    // interval, or two when the rectangle wraps across the seam
+    const int base = sx * kSuper;
+    uint32_t cols;
+    if (ntx >= tiles_x)
+        cols = cover_span(0, tiles_x, base);
+    else if (tx0 + ntx <= tiles_x)
+        cols = cover_span(tx0, tx0 + ntx, base);
+    else
+        cols = cover_span(tx0, tiles_x, base) | cover_span(0, tx0 + ntx - tiles_x, base);
+    return Cover{rows, cols};
+}
+
+// Block entries' sort keys: the super-tile id, and above it, when every id
+// of the launch fits in the 16 bits below (at most kMaxCoverKeyBlocks
+// super-tiles), the entry's covered rows | columns << 8, which the radix
+// sort (on the id bits only) carries to the binning for free.
+constexpr int kCoverShift = 16;
+constexpr uint32_t kMaxCoverKeyBlocks = 1u << kCoverShift;
+__device__ inline uint32_t cover_bits(Cover c) { return (c.rows | (c.cols << kSuper)) << kCoverShift; }
+__device__ inline Cover cover_from_key(uint32_t key) {
+    return Cover{(key >> kCoverShift) & ((1u << kSuper) - 1u), key >> (kCoverShift + kSuper)};
+}
+
 // Grid geometry of the cameras behind record index g = b * n_per + i, for
 // emission into tiles (super == 0: cols = tiles_x, base = first tile id) or
 // super-tiles (super == 1: cols = ceil(tiles_x / 8), base = first super id).
@@ -116,6 +156,7 @@ struct EmitFrames {
     int64_t n_per;  // records per camera
     int count;
     int super;
+    int cover_key;  // super: keys carry the covered rows and columns (kCoverShift)
     int tiles_x[kMaxBatch];
     int cols[kMaxBatch];
     uint32_t base[kMaxBatch];
@@ -216,8 +257,9 @@ uint64_t emit_blocks(uint64_t capacity);
 hipError_t launch_emit(const uint32_t *order, const uint2 *rect, const uint32_t *offs, int64_t n, uint32_t *part,
                        const uint32_t *m_dev, const EmitFrames &frames, uint64_t capacity, uint32_t *inst_tile,
                        uint32_t *inst_gauss, int32_t *overflow, hipStream_t st);
+// key_mask: the id bits of the sorted keys.
 hipError_t launch_tile_ranges(const uint32_t *inst_tile, const uint32_t *m_dev, uint64_t capacity,
-                              uint2 *ranges, uint32_t n_tiles_total, hipStream_t st);
+                              uint2 *ranges, uint32_t n_tiles_total, uint32_t key_mask, hipStream_t st);
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);
 
@@ -233,8 +275,11 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);
 // cleared == true expects zero.
 size_t binning_scratch_bytes(uint64_t super_cap, uint32_t n_super_total);
 void binning_clear(void *scratch, uint64_t super_cap, uint32_t n_super_total, ClearList &L);
-hipError_t launch_binning(const SuperTable &T, uint32_t n_super_total, const uint2 *rect, const uint32_t *sinst_gauss,
-                          const uint2 *sranges, uint64_t super_cap, uint64_t inst_cap, void *scratch, uint2 *ranges,
+// skeys: the sorted block-entry keys when they carry the covers (else null:
+// the covers come from the Gaussians' rectangles).
+hipError_t launch_binning(const SuperTable &T, uint32_t n_super_total, const uint2 *rect, const uint32_t *skeys,
+                          const uint32_t *sinst_gauss, const uint2 *sranges, uint64_t super_cap, uint64_t inst_cap,
+                          void *scratch, uint2 *ranges,
                           uint32_t *inst_gauss, int32_t *overflow, hipStream_t st, bool cleared = false,
                           uint32_t *fault = nullptr);
 // *overflow |= 2 when *fault is nonzero (one thread).

@@ -509,6 +509,7 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *order, const 
     __shared__ uint32_t s_off[kEmitSpan + 1];
     __shared__ uint32_t s_gid[kEmitSpan + 1];
     __shared__ uint2 s_rect[kEmitSpan + 1];
+    __shared__ uint2 s_trect[kEmitSpan + 1];  // the tile rectangle (covers in the keys)
     __shared__ uint8_t s_cam[kEmitSpan + 1];
     const uint64_t M = *m_dev;
     if (blockIdx.x == 0 && threadIdx.x == 0 && M > capacity && overflow) *overflow = 1;
@@ -552,6 +553,7 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *order, const 
         s_off[i] = ov[it];
         s_gid[i] = g;
         s_rect[i] = rc;
+        s_trect[i] = rv[it];
         s_cam[i] = (uint8_t)cam;
     }
     __syncthreads();
@@ -588,6 +590,7 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *order, const 
         uint32_t tx = tx0 + k % ntx;
         if (tx >= cols) tx -= cols;
         tile[i] = F.base[cam] + ty * cols + tx;
+        if (F.super && F.cover_key) tile[i] |= cover_bits(cover_of(s_trect[lo], F.tiles_x[cam], (int)tx, (int)ty));
         gid[i] = s_gid[lo];
     }
     if (jt + kEmitItems <= jend) {
@@ -610,15 +613,16 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *order, const 
 // [start, end) of every tile from adjacent sorted instances.  Ranges must be
 // zeroed beforehand (empty tiles keep [0, 0)).
 __global__ __launch_bounds__(kThreads) void k_tile_ranges(const uint32_t *inst_tile, const uint32_t *m_dev,
-                                                           uint64_t capacity, uint2 *ranges, uint32_t n_tiles_total) {
+                                                           uint64_t capacity, uint2 *ranges, uint32_t n_tiles_total,
+                                                           uint32_t key_mask) {
     const uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
     uint64_t m = *m_dev;
     if (m > capacity) m = capacity;
     if (i >= m) return;
-    const uint32_t t = inst_tile[i];
+    const uint32_t t = inst_tile[i] & key_mask;
     if (t >= n_tiles_total) return;
-    if (i == 0 || inst_tile[i - 1] != t) ranges[t].x = (uint32_t)i;
-    if (i + 1 == m || inst_tile[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
+    if (i == 0 || (inst_tile[i - 1] & key_mask) != t) ranges[t].x = (uint32_t)i;
+    if (i + 1 == m || (inst_tile[i + 1] & key_mask) != t) ranges[t].y = (uint32_t)(i + 1);
 }
 
 // Region blockIdx.y of the list, grid-strided in x.
@@ -787,10 +791,10 @@ hipError_t launch_emit(const uint32_t *order, const uint2 *rect, const uint32_t 
 }
 
 hipError_t launch_tile_ranges(const uint32_t *inst_tile, const uint32_t *m_dev, uint64_t capacity, uint2 *ranges,
-                              uint32_t n_tiles_total, hipStream_t st) {
+                              uint32_t n_tiles_total, uint32_t key_mask, hipStream_t st) {
     if (capacity == 0) return hipSuccess;
     hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)blocks_for((int64_t)capacity, kThreads)), dim3(kThreads), 0,
-                       st, inst_tile, m_dev, capacity, ranges, n_tiles_total);
+                       st, inst_tile, m_dev, capacity, ranges, n_tiles_total, key_mask);
     return hipGetLastError();
 }
 

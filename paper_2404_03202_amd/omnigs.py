@@ -109,7 +109,8 @@ EXPORTS = ("omnigs_default_settings", "omnigs_forward", "omnigs_backward", "omni
            "omnigs_adam_step", "omnigs_accumulate_stats", "omnigs_densify", "omnigs_reset_opacity",
            "omnigs_last_error", "omnigs_profile_enable", "omnigs_profile_num_stages", "omnigs_profile_stage_name",
            "omnigs_profile_read", "omnigs_measure_ceilings",
-           "omnigs_selftest_lookback", "omnigs_backward_noalloc", "omnigs_forward_batch_bytes")
+           "omnigs_selftest_lookback", "omnigs_backward_noalloc", "omnigs_forward_batch_bytes",
+           "omnigs_set_cover_key_blocks")
 
 _lib = None
 _lib_lock = threading.Lock()
@@ -166,6 +167,8 @@ def load_library(path: str = LIB_PATH):
         lib.omnigs_selftest_lookback.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, c_allocator,
                                                  P(ctypes.c_uint32), P(ctypes.c_int32), vp]
         lib.omnigs_selftest_lookback.restype = ctypes.c_int
+        lib.omnigs_set_cover_key_blocks.argtypes = [ctypes.c_uint32]
+        lib.omnigs_set_cover_key_blocks.restype = ctypes.c_int
         lib.omnigs_last_error.argtypes = []
         lib.omnigs_last_error.restype = ctypes.c_char_p
         lib.omnigs_profile_enable.argtypes = [ctypes.c_uint32]
@@ -707,6 +710,13 @@ def omnigs_measure_ceilings(atomic_words: int = 10 << 20, copy_bytes: int = 256 
                                            ctypes.c_void_p(_stream_ptr(dev))))
     A.scratch.clear()
     return {k: getattr(out, k) for k, _ in c_ceilings._fields_}
+
+
+def omnigs_set_cover_key_blocks(blocks: int = 0) -> None:
+    """Binning path for tests: covers from the sort keys while a call has at
+    most `blocks` 8x8-tile blocks (0: the default, 65536), else from the
+    Gaussians' rectangles; both give the same tile lists."""
+    _check(load_library().omnigs_set_cover_key_blocks(int(blocks)))
 
 
 def omnigs_selftest_lookback(primitive: str, n: int, max_polls: int = 0, device: str = "cuda:0") -> tuple:
