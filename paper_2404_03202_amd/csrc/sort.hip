@@ -508,8 +508,7 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *order, const 
                                                     uint32_t *inst_tile, uint32_t *inst_gauss, int32_t *overflow) {
     __shared__ uint32_t s_off[kEmitSpan + 1];
     __shared__ uint32_t s_gid[kEmitSpan + 1];
-    __shared__ uint2 s_rect[kEmitSpan + 1];
-    __shared__ uint2 s_trect[kEmitSpan + 1];  // the tile rectangle (covers in the keys)
+    __shared__ uint2 s_rect[kEmitSpan + 1];  // the tile rectangle
     __shared__ uint8_t s_cam[kEmitSpan + 1];
     const uint64_t M = *m_dev;
     if (blockIdx.x == 0 && threadIdx.x == 0 && M > capacity && overflow) *overflow = 1;
@@ -548,12 +547,9 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *order, const 
         const uint32_t g = gv[it];
         // camera of record g = b * n_per + i
         const int cam = F.count > 1 && g < (uint64_t)n ? (int)min((int64_t)g / F.n_per, (int64_t)F.count - 1) : 0;
-        uint2 rc = rv[it];
-        if (F.super) rc = super_rect(rc, F.tiles_x[cam]);
         s_off[i] = ov[it];
         s_gid[i] = g;
-        s_rect[i] = rc;
-        s_trect[i] = rv[it];
+        s_rect[i] = rv[it];
         s_cam[i] = (uint8_t)cam;
     }
     __syncthreads();
@@ -574,23 +570,31 @@ __global__ __launch_bounds__(kThreads) void k_emit(const uint32_t *order, const 
         }
     }
     uint32_t tile[kEmitItems], gid[kEmitItems];
+    // the owner's rectangle (in super-tiles when emitting super entries),
+    // formed again only when the owner changes
+    int cur = -1, cam = 0;
+    uint2 tr = make_uint2(0u, 0u), rc = tr;
 #pragma unroll
     for (int i = 0; i < kEmitItems; ++i) {
         const uint64_t j = jt + i;
         tile[i] = gid[i] = 0u;
         if (j >= jend) continue;
         while (lo + 1 < cnt && s_off[lo + 1] <= j) ++lo;
+        if (lo != cur) {
+            cur = lo;
+            tr = s_rect[lo];
+            cam = s_cam[lo];
+            rc = F.super ? super_rect(tr, F.tiles_x[cam]) : tr;
+        }
         const uint32_t k = (uint32_t)(j - s_off[lo]);
-        const uint2 rc = s_rect[lo];
         const uint32_t ntx = rc.x >> 16, tx0 = rc.x & 0xffffu, ty0 = rc.y & 0xffffu;
         if (ntx == 0) continue;
-        const int cam = s_cam[lo];
         const uint32_t cols = (uint32_t)F.cols[cam];
         const uint32_t ty = ty0 + k / ntx;
         uint32_t tx = tx0 + k % ntx;
         if (tx >= cols) tx -= cols;
         tile[i] = F.base[cam] + ty * cols + tx;
-        if (F.super && F.cover_key) tile[i] |= cover_bits(cover_of(s_trect[lo], F.tiles_x[cam], (int)tx, (int)ty));
+        if (F.super && F.cover_key) tile[i] |= cover_bits(cover_of(tr, F.tiles_x[cam], (int)tx, (int)ty));
         gid[i] = s_gid[lo];
     }
     if (jt + kEmitItems <= jend) {
