@@ -139,8 +139,13 @@ __global__ __launch_bounds__(kThreads) void k_bin_expand(SuperTable T, const uin
                                                          const uint2 *sranges, const uint32_t *choff,
                                                          const uint32_t *nch, const uint32_t *desc, uint32_t n_super,
                                                          const uint32_t *scanned, uint64_t inst_cap,
-                                                         uint32_t *inst_gauss, int32_t *overflow) {
+                                                         uint32_t *inst_gauss, int32_t *overflow,
+                                                         const uint32_t *fault) {
     __shared__ uint64_t rc[kWaves][2 * kSuper];
+    // a lookback wait of the sorts or scans before this kernel that gave up
+    // marks the overflow word too (bit 1), so that a caller who reads nothing
+    // back but that word still sees it
+    if (fault && overflow && blockIdx.x == 0 && threadIdx.x == 0 && *fault) atomicOr(overflow, 2);
     __shared__ uint32_t wpre[kWaves][kTilesPer];
     // workgroups go to the XCDs in turn (workgroup b to XCD b mod 8): XCD x
     // takes the chunks [x per, (x + 1) per) in order, so the chunks that write
@@ -193,7 +198,7 @@ __global__ __launch_bounds__(kThreads) void k_bin_expand(SuperTable T, const uin
             }
         }
     }
-    if (dropped && overflow) *overflow = 1;
+    if (dropped && overflow) atomicOr(overflow, 1);
 }
 
 int64_t blocks_for(int64_t n, int64_t per) { return (n + per - 1) / per; }
@@ -247,7 +252,7 @@ hipError_t launch_binning(const SuperTable &T, uint32_t n_super_total, const uin
                           void *scratch, uint2 *ranges,
                           uint32_t *inst_gauss, int32_t *overflow, hipStream_t st, bool cleared,
                           uint32_t *fault) {
-    if (n_super_total == 0) return hipSuccess;
+    if (n_super_total == 0) return overflow && fault ? launch_merge_fault(fault, overflow, st) : hipSuccess;
     const uint64_t K = max_chunks(super_cap, n_super_total);
     const uint64_t cells = (uint64_t)kTilesPer * K;
     const BinLayout B(scratch, super_cap, n_super_total);
@@ -267,7 +272,7 @@ hipError_t launch_binning(const SuperTable &T, uint32_t n_super_total, const uin
                        st, T, n_super_total, B.choff, B.nch, B.scanned, inst_cap, ranges);
     hipLaunchKernelGGL(k_bin_expand, dim3((unsigned)((K + kXcds - 1) / kXcds * kXcds)), dim3(kThreads), 0, st, T,
                        rect, skeys, sinst_gauss, sranges, B.choff, B.nch, B.desc, n_super_total, B.scanned, inst_cap,
-                       inst_gauss, overflow);
+                       inst_gauss, overflow, fault);
     return hipGetLastError();
 }
 

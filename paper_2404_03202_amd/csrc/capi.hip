@@ -372,11 +372,6 @@ omnigs_status run_binning(int64_t nrec, const GeomState &gst, const GeomScratch 
                                super_cap, inst_cap, bs.bin_tmp,
                                ranges, inst_gauss, overflow, st, cleared, gst.totals + 2));
     }
-    if (overflow) {
-        // with capacities nothing is read back: a lookback wait that gave up
-        // also marks the call's overflow word
-        HIP_TRY(launch_merge_fault(gst.totals + 2, overflow, st));
-    }
     return OMNIGS_OK;
 }
 

@@ -276,13 +276,16 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);
 size_t binning_scratch_bytes(uint64_t super_cap, uint32_t n_super_total);
 void binning_clear(void *scratch, uint64_t super_cap, uint32_t n_super_total, ClearList &L);
 // skeys: the sorted block-entry keys when they carry the covers (else null:
-// the covers come from the Gaussians' rectangles).
+// the covers come from the Gaussians' rectangles).  fault: the call's
+// lookback fault word; with overflow given, a nonzero word sets bit 1 of
+// *overflow (bit 0: an instance beyond inst_cap was dropped).
 hipError_t launch_binning(const SuperTable &T, uint32_t n_super_total, const uint2 *rect, const uint32_t *skeys,
                           const uint32_t *sinst_gauss, const uint2 *sranges, uint64_t super_cap, uint64_t inst_cap,
                           void *scratch, uint2 *ranges,
                           uint32_t *inst_gauss, int32_t *overflow, hipStream_t st, bool cleared = false,
                           uint32_t *fault = nullptr);
-// *overflow |= 2 when *fault is nonzero (one thread).
+// *overflow |= 2 when *fault is nonzero (one thread; launch_binning's path
+// when there are no blocks).
 hipError_t launch_merge_fault(const uint32_t *fault, int32_t *overflow, hipStream_t st);
 
 // Blend kernels.

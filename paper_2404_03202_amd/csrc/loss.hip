@@ -11,14 +11,23 @@ namespace {
 constexpr int kL1Blocks = 1024;
 constexpr int kL1Threads = 256;
 
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
 // Grid-stride pass with a fixed grid: every element lands in the same
 // thread's partial on every run, so the reduction order is fixed.
 // kVec: image, target and grad are 16-byte aligned and the grid strides over
-// float4 groups (the last count % 4 elements by the first threads).
+// float4 groups (the last count % 4 elements by the first threads); each
+// thread issues the loads of kL1Unroll strided groups before it uses them
+// (and adds them in the same order as one group at a time).
+constexpr int kL1Unroll = 4;
 template <bool kVec>
 __global__ __launch_bounds__(kL1Threads) void k_l1_partial(const float *image, const float *target, int64_t count,
                                                             float *grad, double *partial) {
-    __shared__ double red[kL1Threads];
+    __shared__ double red[kL1Threads / kWave];
     const float inv = (float)(1.0 / (double)count);
     auto sgn = [inv](float r) { return r > 0.0f ? inv : (r < 0.0f ? -inv : 0.0f); };
     double s = 0.0;
@@ -26,12 +35,28 @@ __global__ __launch_bounds__(kL1Threads) void k_l1_partial(const float *image, c
     int64_t i = tid;
     if (kVec) {
         const int64_t n4 = count / 4;
-        for (int64_t q = tid; q < n4; q += stride) {
-            const float4 x = reinterpret_cast<const float4 *>(image)[q];
-            const float4 y = reinterpret_cast<const float4 *>(target)[q];
+        const float4 *x4 = reinterpret_cast<const float4 *>(image), *y4 = reinterpret_cast<const float4 *>(target);
+        float4 *g4 = reinterpret_cast<float4 *>(grad);
+        int64_t q = tid;
+        for (; q + (kL1Unroll - 1) * stride < n4; q += kL1Unroll * stride) {
+            float4 x[kL1Unroll], y[kL1Unroll];
+#pragma unroll
+            for (int u = 0; u < kL1Unroll; ++u) {
+                x[u] = x4[q + u * stride];
+                y[u] = y4[q + u * stride];
+            }
+#pragma unroll
+            for (int u = 0; u < kL1Unroll; ++u) {
+                const float r0 = x[u].x - y[u].x, r1 = x[u].y - y[u].y, r2 = x[u].z - y[u].z, r3 = x[u].w - y[u].w;
+                s += (double)fabsf(r0) + (double)fabsf(r1) + (double)fabsf(r2) + (double)fabsf(r3);
+                if (grad) g4[q + u * stride] = make_float4(sgn(r0), sgn(r1), sgn(r2), sgn(r3));
+            }
+        }
+        for (; q < n4; q += stride) {
+            const float4 x = x4[q], y = y4[q];
             const float r0 = x.x - y.x, r1 = x.y - y.y, r2 = x.z - y.z, r3 = x.w - y.w;
             s += (double)fabsf(r0) + (double)fabsf(r1) + (double)fabsf(r2) + (double)fabsf(r3);
-            if (grad) reinterpret_cast<float4 *>(grad)[q] = make_float4(sgn(r0), sgn(r1), sgn(r2), sgn(r3));
+            if (grad) g4[q] = make_float4(sgn(r0), sgn(r1), sgn(r2), sgn(r3));
         }
         i = 4 * n4 + tid;
     }
@@ -40,13 +65,14 @@ __global__ __launch_bounds__(kL1Threads) void k_l1_partial(const float *image, c
         s += (double)fabsf(r);
         if (grad) grad[i] = sgn(r);
     }
-    red[threadIdx.x] = s;
+    s = wave_sum(s);
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = s;
     __syncthreads();
-    for (int off = kL1Threads / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-        __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kL1Threads / kWave; ++w) t += red[w];
+        partial[blockIdx.x] = t;
     }
-    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
 __global__ __launch_bounds__(kL1Threads) void k_l1_final(const double *partial, int64_t count, float *loss) {
@@ -187,12 +213,6 @@ __device__ inline void horizontal(const float *lds, int r, int g, const float *w
         for (int f = 0; f < NV; ++f) v[f] = lds[(f * kSsimTH + r) * kVPitch + g * kRun + t];
         add_row<NV>(m, v, t, w);
     }
-}
-
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
 }
 
 constexpr int kLdsStats = 5 * kSsimTH * kVPitch > 2 * kSsimIH * kSsimIW ? 5 * kSsimTH * kVPitch : 2 * kSsimIH * kSsimIW;

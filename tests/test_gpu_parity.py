@@ -143,10 +143,13 @@ def test_seam_roll_symmetry_gpu():
         assert np.abs(img - np.roll(base, k, axis=2)).max() <= 1e-4
 
 
-@pytest.mark.parametrize("shape,offset", [((3, 100, 64), 0), ((3, 37, 41), 0), ((3, 37, 41), 1)])
+@pytest.mark.parametrize("shape,offset", [((3, 100, 64), 0), ((3, 37, 41), 0), ((3, 37, 41), 1),
+                                          ((3, 2048, 1024), 0), ((3, 1031, 1029), 0), ((3, 1031, 1029), 1)])
 def test_l1_loss_kernel(shape, offset):
-    """16-byte groups with a ragged tail (count not a multiple of 4), and
-    inputs at an odd float offset (the word-by-word path)."""
+    """16-byte groups with a ragged tail (count not a multiple of 4), inputs
+    at an odd float offset (the word-by-word path), and images large enough
+    that threads take the groups four strides at a time (the benchmark's
+    2048x1024, and a size whose groups end inside that loop's reach)."""
     rng = np.random.default_rng(3)
     n = int(np.prod(shape))
     af = rng.normal(size=n + offset).astype(np.float32)
