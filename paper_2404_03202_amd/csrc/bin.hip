@@ -140,20 +140,38 @@ __global__ __launch_bounds__(kThreads) void k_bin_expand(SuperTable T, const uin
                                                          const uint32_t *nch, const uint32_t *desc, uint32_t n_super,
                                                          const uint32_t *scanned, uint64_t inst_cap,
                                                          uint32_t *inst_gauss, int32_t *overflow,
-                                                         const uint32_t *fault) {
-    __shared__ uint64_t rc[kWaves][2 * kSuper];
-    // a lookback wait of the sorts or scans before this kernel that gave up
+                                                         const uint32_t *fault, const uint2 *ranges,
+                                                         uint32_t order_tiles, uint32_t *order) {
+    __shared__ union {
+        struct {
+            uint64_t rc[kWaves][2 * kSuper];
+            uint32_t wpre[kWaves][kTilesPer];
+        } e;
+        TileOrderShared o;
+    } sh;
+    auto &rc = sh.e.rc;
+    auto &wpre = sh.e.wpre;
+    // the first kXcds workgroups take no chunk: workgroup 0 (dispatched
+    // first, so it runs beside the expansion) writes the blend's launch order
+    // from the tile ranges when asked; workgroup 1 merges the fault word: a
+    // lookback wait of the sorts or scans before this kernel that gave up
     // marks the overflow word too (bit 1), so that a caller who reads nothing
     // back but that word still sees it
-    if (fault && overflow && blockIdx.x == 0 && threadIdx.x == 0 && *fault) atomicOr(overflow, 2);
-    __shared__ uint32_t wpre[kWaves][kTilesPer];
+    if (blockIdx.x < kXcds) {
+        if (blockIdx.x == 0 && order && order_tiles > 0)
+            tile_order_block<kThreads>(ranges, nullptr, order_tiles, order, sh.o);
+        if (blockIdx.x == 1 && threadIdx.x == 0 && fault && overflow && *fault) atomicOr(overflow, 2);
+        return;
+    }
     // workgroups go to the XCDs in turn (workgroup b to XCD b mod 8): XCD x
     // takes the chunks [x per, (x + 1) per) in order, so the chunks that write
     // adjacent pieces of a tile's list run on one XCD and their partial cache
-    // lines meet in its L2 (the grid is a multiple of 8 and covers 8 per)
+    // lines meet in its L2 (after the kXcds leading workgroups, the grid is a
+    // multiple of 8 and covers 8 per)
+    const uint32_t wg = blockIdx.x - kXcds;
     const uint32_t total = choff[n_super], per = (total + kXcds - 1) / kXcds;
-    const uint32_t k = (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
-    if (blockIdx.x / kXcds >= per || k >= total) return;
+    const uint32_t k = (wg % kXcds) * per + wg / kXcds;
+    if (wg / kXcds >= per || k >= total) return;
     const int w = threadIdx.x / kWave, lane = __lane_id();
     const uint32_t s = desc[k], o = choff[s], n = nch[s], c = k - o;
     const SuperFrame &F = T.f[find_super_frame(T, s)];
@@ -251,8 +269,15 @@ hipError_t launch_binning(const SuperTable &T, uint32_t n_super_total, const uin
                           const uint32_t *sinst_gauss, const uint2 *sranges, uint64_t super_cap, uint64_t inst_cap,
                           void *scratch, uint2 *ranges,
                           uint32_t *inst_gauss, int32_t *overflow, hipStream_t st, bool cleared,
-                          uint32_t *fault) {
-    if (n_super_total == 0) return overflow && fault ? launch_merge_fault(fault, overflow, st) : hipSuccess;
+                          uint32_t *fault, uint32_t *order, uint32_t order_tiles) {
+    if (n_super_total == 0) {
+        // no lists: every tile's range is empty and any order is longest first
+        if (order && order_tiles > 0) {
+            hipError_t e = launch_tile_order(ranges, nullptr, order_tiles, order, st);
+            if (e != hipSuccess) return e;
+        }
+        return overflow && fault ? launch_merge_fault(fault, overflow, st) : hipSuccess;
+    }
     const uint64_t K = max_chunks(super_cap, n_super_total);
     const uint64_t cells = (uint64_t)kTilesPer * K;
     const BinLayout B(scratch, super_cap, n_super_total);
@@ -270,9 +295,9 @@ hipError_t launch_binning(const SuperTable &T, uint32_t n_super_total, const uin
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_bin_ranges, dim3((unsigned)blocks_for((int64_t)n_super_total * kTilesPer, 256)), dim3(256), 0,
                        st, T, n_super_total, B.choff, B.nch, B.scanned, inst_cap, ranges);
-    hipLaunchKernelGGL(k_bin_expand, dim3((unsigned)((K + kXcds - 1) / kXcds * kXcds)), dim3(kThreads), 0, st, T,
-                       rect, skeys, sinst_gauss, sranges, B.choff, B.nch, B.desc, n_super_total, B.scanned, inst_cap,
-                       inst_gauss, overflow, fault);
+    hipLaunchKernelGGL(k_bin_expand, dim3((unsigned)(kXcds + (K + kXcds - 1) / kXcds * kXcds)), dim3(kThreads), 0, st,
+                       T, rect, skeys, sinst_gauss, sranges, B.choff, B.nch, B.desc, n_super_total, B.scanned, inst_cap,
+                       inst_gauss, overflow, fault, ranges, order_tiles, order);
     return hipGetLastError();
 }
 

@@ -679,83 +679,28 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, co
     }
 }
 
-// Launch order, longest first: tiles bucketed by descending work (work
-// clamped to kOrderBuckets - 1) in one workgroup (LDS counting sort), so the
-// longest walks start first and do not trail the kernel.  Work is the list
-// length (ranges, forward) or the walk length recorded by the forward
-// (work, backward).
-constexpr int kOrderBuckets = 4096;
 constexpr int kOrderThreads = 1024;
-constexpr int kOrderChunk = 8;  // tiles whose work one thread loads at once
-
-// Buckets of the tiles t0 + c * kOrderThreads, c < kOrderChunk: the loads go
-// out together (indices clamped to the last tile, so none is predicated
-// away), then tiles past ntiles are marked with kOrderBuckets.
-__device__ __forceinline__ void order_buckets(const uint2 *ranges, const uint32_t *work, uint32_t ntiles,
-                                              uint32_t t0, uint32_t bk[kOrderChunk]) {
-    uint32_t wk[kOrderChunk];
-    if (work) {
-#pragma unroll
-        for (int c = 0; c < kOrderChunk; ++c) wk[c] = work[min(t0 + (uint32_t)(c * kOrderThreads), ntiles - 1u)];
-    } else {
-        uint2 r[kOrderChunk];
-#pragma unroll
-        for (int c = 0; c < kOrderChunk; ++c) r[c] = ranges[min(t0 + (uint32_t)(c * kOrderThreads), ntiles - 1u)];
-#pragma unroll
-        for (int c = 0; c < kOrderChunk; ++c) wk[c] = r[c].y - r[c].x;
-    }
-#pragma unroll
-    for (int c = 0; c < kOrderChunk; ++c)
-        bk[c] = t0 + (uint32_t)(c * kOrderThreads) < ntiles
-                    ? (uint32_t)(kOrderBuckets - 1) - min(wk[c], (uint32_t)(kOrderBuckets - 1))
-                    : (uint32_t)kOrderBuckets;
-}
 
 __global__ __launch_bounds__(kOrderThreads) void k_tile_order(const uint2 *ranges, const uint32_t *work,
                                                               uint32_t ntiles, uint32_t *order) {
-    __shared__ uint32_t cnt[kOrderBuckets];
-    __shared__ uint32_t wave_tot[kOrderThreads / kWave];
-    for (int b = threadIdx.x; b < kOrderBuckets; b += kOrderThreads) cnt[b] = 0;
-    __syncthreads();
-    for (uint32_t t0 = threadIdx.x; t0 < ntiles; t0 += kOrderThreads * kOrderChunk) {
-        uint32_t bk[kOrderChunk];
-        order_buckets(ranges, work, ntiles, t0, bk);
-#pragma unroll
-        for (int c = 0; c < kOrderChunk; ++c)
-            if (bk[c] < kOrderBuckets) atomicAdd(&cnt[bk[c]], 1u);
+    __shared__ TileOrderShared sh;
+    tile_order_block<kOrderThreads>(ranges, work, ntiles, order, sh);
+}
+
+// Workgroup 0 writes the tile order (it starts first, and its loads and LDS
+// passes run beside the clearing); the others clear four words per thread.
+__global__ __launch_bounds__(kOrderThreads) void k_clear_and_order(uint32_t *acc, int64_t n, const uint32_t *work,
+                                                                   uint32_t ntiles, uint32_t *order) {
+    __shared__ TileOrderShared sh;
+    if (blockIdx.x == 0) {
+        if (ntiles > 0) tile_order_block<kOrderThreads>(nullptr, work, ntiles, order, sh);
+        return;
     }
-    __syncthreads();
-    // exclusive scan of the bucket counts: 4 per thread, then across waves
-    constexpr int kPer = kOrderBuckets / kOrderThreads;
-    uint32_t v[kPer], sum = 0;
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-        v[k] = cnt[threadIdx.x * kPer + k];
-        sum += v[k];
-    }
-    const int lane = __lane_id(), wv = threadIdx.x / kWave;
-    uint32_t x = sum;
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        const uint32_t y = __shfl_up(x, off, kWave);
-        if (lane >= off) x += y;
-    }
-    if (lane == kWave - 1) wave_tot[wv] = x;
-    __syncthreads();
-    uint32_t run = x - sum;
-    for (int k = 0; k < wv; ++k) run += wave_tot[k];
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-        cnt[threadIdx.x * kPer + k] = run;
-        run += v[k];
-    }
-    __syncthreads();
-    for (uint32_t t0 = threadIdx.x; t0 < ntiles; t0 += kOrderThreads * kOrderChunk) {
-        uint32_t bk[kOrderChunk];
-        order_buckets(ranges, work, ntiles, t0, bk);
-#pragma unroll
-        for (int c = 0; c < kOrderChunk; ++c)
-            if (bk[c] < kOrderBuckets) order[atomicAdd(&cnt[bk[c]], 1u)] = t0 + (uint32_t)(c * kOrderThreads);
+    const int64_t i = ((int64_t)(blockIdx.x - 1) * kOrderThreads + threadIdx.x) * 4;
+    if (i + 4 <= n && (reinterpret_cast<uintptr_t>(acc + i) & 15u) == 0) {
+        *reinterpret_cast<uint4 *>(acc + i) = make_uint4(0u, 0u, 0u, 0u);
+    } else {
+        for (int64_t k = i; k < i + 4 && k < n; ++k) acc[k] = 0u;
     }
 }
 
@@ -767,6 +712,15 @@ hipError_t launch_tile_order(const uint2 *ranges, const uint32_t *work, uint32_t
                              hipStream_t st) {
     if (ntiles == 0) return hipSuccess;
     hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, st, ranges, work, ntiles, order);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_and_order(uint32_t *acc, int64_t n, const uint32_t *work, uint32_t ntiles, uint32_t *order,
+                                  hipStream_t st) {
+    if (n < 0 || (ntiles > 0 && !work)) return hipErrorInvalidValue;
+    const int64_t fill_blocks = (n + 4 * kOrderThreads - 1) / (4 * kOrderThreads);
+    hipLaunchKernelGGL(k_clear_and_order, dim3((unsigned)(1 + fill_blocks)), dim3(kOrderThreads), 0, st, acc, n, work,
+                       ntiles, order);
     return hipGetLastError();
 }
 

@@ -341,7 +341,8 @@ struct BinScratch {
 // true the entry count is read on the device (min(S, super_cap)).
 omnigs_status run_binning(int64_t nrec, const GeomState &gst, const GeomScratch &gs, const Grids &G,
                           uint64_t super_cap, uint64_t inst_cap, bool counted, BinScratch &bs, uint2 *ranges,
-                          uint32_t *inst_gauss, int32_t *overflow, hipStream_t st, bool cleared = false) {
+                          uint32_t *inst_gauss, int32_t *overflow, hipStream_t st, bool cleared = false,
+                          uint32_t *order = nullptr, uint32_t order_tiles = 0) {
     const int bits = bits_for(G.n_super);
     const bool odd = ((bits + 7) / 8) % 2;
     uint32_t *et = odd ? bs.stile_tmp : bs.stile, *eg = odd ? bs.sgauss_tmp : bs.sgauss;
@@ -370,7 +371,7 @@ omnigs_status run_binning(int64_t nrec, const GeomState &gst, const GeomScratch 
         StageTimer t(st, kStTileBin);
         HIP_TRY(launch_binning(G.sup, G.n_super, gst.rect, G.ef.cover_key ? bs.stile : nullptr, bs.sgauss, bs.sranges,
                                super_cap, inst_cap, bs.bin_tmp,
-                               ranges, inst_gauss, overflow, st, cleared, gst.totals + 2));
+                               ranges, inst_gauss, overflow, st, cleared, gst.totals + 2, order, order_tiles));
     }
     return OMNIGS_OK;
 }
@@ -452,14 +453,13 @@ omnigs_status backward_impl(const omnigs_gaussians *g, const omnigs_camera *cam,
     const auto *rec = static_cast<const BlendRecord *>(state->records);
     const auto *ranges = reinterpret_cast<const uint2 *>(state->tile_range);
     {
+        // the accumulators cleared and the tile order (longest recorded walk
+        // first) in one launch
         StageTimer t(st, kStBwdClear);
-        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(acc), 0u, n * nacc, st));
+        HIP_TRY(launch_clear_and_order(reinterpret_cast<uint32_t *>(acc), n * nacc, state->tile_work, ntiles, order,
+                                       st));
     }
     const FrameGeom f{cam->width, pa.rows, pa.tiles_x, pa.tiles_y, 0u, pa.model == OMNIGS_CAMERA_ERP};
-    {
-        StageTimer t(st, kStTileOrder);
-        HIP_TRY(launch_tile_order(ranges, state->tile_work, ntiles, order, st));
-    }
     {
         StageTimer t(st, kStBlendBwd);
         HIP_TRY(launch_blend_backward(f, rec, state->depth, state->inst_gauss, ranges, make_blend_settings(s),
@@ -644,15 +644,12 @@ omnigs_status omnigs_forward(const omnigs_gaussians *g, const omnigs_camera *cam
         HIP_TRY(launch_clear(L, st));
     }
 
+    // the launch order (longest list first) comes out of the binning's last
+    // kernel when the forward uses one
+    if (!forward_uses_order(inst_cap, ntiles)) order = nullptr;
     if ((rc = run_binning(n, gst, gs, G, super_cap, inst_cap, counted, bs, ranges, inst_gauss,
-                          counted ? cap->overflow : nullptr, st, true)) != OMNIGS_OK)
+                          counted ? cap->overflow : nullptr, st, true, order, ntiles)) != OMNIGS_OK)
         return rc;
-    if (forward_uses_order(inst_cap, ntiles)) {
-        StageTimer t(st, kStTileOrder);
-        HIP_TRY(launch_tile_order(ranges, nullptr, ntiles, order, st));
-    } else {
-        order = nullptr;
-    }
     {
         StageTimer t(st, kStBlendFwd);
         FrameGeom f{cam->width, pa.rows, pa.tiles_x, pa.tiles_y, 0u, pa.model == OMNIGS_CAMERA_ERP};
@@ -972,12 +969,8 @@ omnigs_status omnigs_forward_batch(const omnigs_gaussians *g, const omnigs_camer
     if ((rc = alloc_arena(alloc, ia.off, OMNIGS_MEM_SCRATCH, ia, "instance lists")) != OMNIGS_OK) return rc;
     bb.carve_instances(ia, inst_cap, super_cap, ntiles, G);
     if ((rc = run_binning(nrec, gst, gs, G, super_cap, inst_cap, counted, bb.bs, bb.ranges, bb.inst_gauss, overflow,
-                          st)) != OMNIGS_OK)
+                          st, false, bb.order, ntiles)) != OMNIGS_OK)
         return rc;
-    {
-        StageTimer t(st, kStTileOrder);
-        HIP_TRY(launch_tile_order(bb.ranges, nullptr, ntiles, bb.order, st));
-    }
     {
         StageTimer t(st, kStBlendFwd);
         HIP_TRY(launch_blend_forward_frames(frames, outs, batch, gst.rec, gst.depth, bb.inst_gauss, bb.ranges,

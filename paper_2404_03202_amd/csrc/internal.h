@@ -278,12 +278,14 @@ void binning_clear(void *scratch, uint64_t super_cap, uint32_t n_super_total, Cl
 // skeys: the sorted block-entry keys when they carry the covers (else null:
 // the covers come from the Gaussians' rectangles).  fault: the call's
 // lookback fault word; with overflow given, a nonzero word sets bit 1 of
-// *overflow (bit 0: an instance beyond inst_cap was dropped).
+// *overflow (bit 0: an instance beyond inst_cap was dropped).  order: when
+// given, also the blend's longest-first launch order of the order_tiles
+// tiles from the ranges (one workgroup of the expansion).
 hipError_t launch_binning(const SuperTable &T, uint32_t n_super_total, const uint2 *rect, const uint32_t *skeys,
                           const uint32_t *sinst_gauss, const uint2 *sranges, uint64_t super_cap, uint64_t inst_cap,
                           void *scratch, uint2 *ranges,
                           uint32_t *inst_gauss, int32_t *overflow, hipStream_t st, bool cleared = false,
-                          uint32_t *fault = nullptr);
+                          uint32_t *fault = nullptr, uint32_t *order = nullptr, uint32_t order_tiles = 0);
 // *overflow |= 2 when *fault is nonzero (one thread; launch_binning's path
 // when there are no blocks).
 hipError_t launch_merge_fault(const uint32_t *fault, int32_t *overflow, hipStream_t st);
@@ -321,6 +323,96 @@ hipError_t launch_blend_backward(const FrameGeom &f, const BlendRecord *rec, con
 // per-tile work array.  One workgroup; ntiles unbounded.
 hipError_t launch_tile_order(const uint2 *ranges, const uint32_t *work, uint32_t ntiles, uint32_t *order,
                              hipStream_t st);
+// The backward's set-up in one launch: the gradient accumulators acc[0, n)
+// cleared, and the tile order from the recorded walk lengths `work`.
+hipError_t launch_clear_and_order(uint32_t *acc, int64_t n, const uint32_t *work, uint32_t ntiles, uint32_t *order,
+                                  hipStream_t st);
+
+// Launch order, longest first: tiles bucketed by descending work (work
+// clamped to kOrderBuckets - 1) by one workgroup of NT threads (a counting
+// sort in LDS), so that the longest walks start first and do not trail the
+// blend.  Work is the list length (ranges, work null) or a recorded walk
+// length per tile (work).  Tiles of one bucket come in no fixed order.
+constexpr int kOrderBuckets = 4096;
+constexpr int kOrderChunk = 8;  // tiles whose work one thread loads at once
+struct TileOrderShared {
+    uint32_t cnt[kOrderBuckets];
+    uint32_t wave_tot[16];
+};
+
+// Buckets of the tiles t0 + c NT, c < kOrderChunk: the loads go out
+// together (indices clamped to the last tile, so none is predicated away),
+// then tiles past ntiles are marked with kOrderBuckets.
+template <int NT>
+__device__ __forceinline__ void order_buckets(const uint2 *ranges, const uint32_t *work, uint32_t ntiles,
+                                              uint32_t t0, uint32_t bk[kOrderChunk]) {
+    uint32_t wk[kOrderChunk];
+    if (work) {
+#pragma unroll
+        for (int c = 0; c < kOrderChunk; ++c) wk[c] = work[min(t0 + (uint32_t)(c * NT), ntiles - 1u)];
+    } else {
+        uint2 r[kOrderChunk];
+#pragma unroll
+        for (int c = 0; c < kOrderChunk; ++c) r[c] = ranges[min(t0 + (uint32_t)(c * NT), ntiles - 1u)];
+#pragma unroll
+        for (int c = 0; c < kOrderChunk; ++c) wk[c] = r[c].y - r[c].x;
+    }
+#pragma unroll
+    for (int c = 0; c < kOrderChunk; ++c)
+        bk[c] = t0 + (uint32_t)(c * NT) < ntiles
+                    ? (uint32_t)(kOrderBuckets - 1) - min(wk[c], (uint32_t)(kOrderBuckets - 1))
+                    : (uint32_t)kOrderBuckets;
+}
+
+// The order, written by the NT threads of the calling workgroup (all of
+// them call it; ntiles > 0).
+template <int NT>
+__device__ inline void tile_order_block(const uint2 *ranges, const uint32_t *work, uint32_t ntiles, uint32_t *order,
+                                        TileOrderShared &sh) {
+    static_assert(NT % kWave == 0 && NT / kWave <= 16 && kOrderBuckets % NT == 0, "workgroup shape");
+    for (int b = threadIdx.x; b < kOrderBuckets; b += NT) sh.cnt[b] = 0;
+    __syncthreads();
+    for (uint32_t t0 = threadIdx.x; t0 < ntiles; t0 += NT * kOrderChunk) {
+        uint32_t bk[kOrderChunk];
+        order_buckets<NT>(ranges, work, ntiles, t0, bk);
+#pragma unroll
+        for (int c = 0; c < kOrderChunk; ++c)
+            if (bk[c] < kOrderBuckets) atomicAdd(&sh.cnt[bk[c]], 1u);
+    }
+    __syncthreads();
+    // exclusive scan of the bucket counts: kPer per thread, then across waves
+    constexpr int kPer = kOrderBuckets / NT;
+    uint32_t v[kPer], sum = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        v[k] = sh.cnt[threadIdx.x * kPer + k];
+        sum += v[k];
+    }
+    const int lane = __lane_id(), wv = threadIdx.x / kWave;
+    uint32_t x = sum;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off, kWave);
+        if (lane >= off) x += y;
+    }
+    if (lane == kWave - 1) sh.wave_tot[wv] = x;
+    __syncthreads();
+    uint32_t run = x - sum;
+    for (int k = 0; k < wv; ++k) run += sh.wave_tot[k];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        sh.cnt[threadIdx.x * kPer + k] = run;
+        run += v[k];
+    }
+    __syncthreads();
+    for (uint32_t t0 = threadIdx.x; t0 < ntiles; t0 += NT * kOrderChunk) {
+        uint32_t bk[kOrderChunk];
+        order_buckets<NT>(ranges, work, ntiles, t0, bk);
+#pragma unroll
+        for (int c = 0; c < kOrderChunk; ++c)
+            if (bk[c] < kOrderBuckets) order[atomicAdd(&sh.cnt[bk[c]], 1u)] = t0 + (uint32_t)(c * NT);
+    }
+}
 
 // Optimisation (optim.hip).  Parameter arrays as five segments.
 constexpr int kSegments = 5;
