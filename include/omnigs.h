@@ -438,7 +438,10 @@ omnigs_status omnigs_selftest_lookback(int32_t primitive, int64_t n, uint32_t ma
  * its sort key while a call's images hold at most `blocks` blocks (default
  * and maximum 65536, which keeps the block ids within the lower 16 bits),
  * and from the Gaussians' tile rectangles otherwise; both give the same
- * tile lists.  blocks = 0 restores the default, larger values are clamped
+ * tile lists.  The same bound (and fewer than 8192 blocks) selects the
+ * one-workgroup split of the block lists into chunks over the three-kernel
+ * one, again with the same result.  blocks = 0 restores the default, larger
+ * values are clamped
  * to it.  Process-wide, like omnigs_selftest_lookback's bound: not to be
  * called while other threads launch library work.  Always OMNIGS_OK. */
 omnigs_status omnigs_set_cover_key_blocks(uint32_t blocks);

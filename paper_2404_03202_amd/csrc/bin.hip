@@ -113,6 +113,65 @@ __global__ __launch_bounds__(kThreads) void k_bin_count(SuperTable T, const uint
     }
 }
 
+// Chunks, chunk offsets and chunk owners in one workgroup, for fewer than
+// kPlanMax super-tiles: nch[s], choff[s] (exclusive scan, choff[n_super]
+// the total) and desc[k] for every chunk k < min(total, max_chunks), as
+// k_bin_chunks, the scan and k_bin_desc give them.
+constexpr int kPlanThreads = 1024;
+constexpr int kPlanPer = 8;  // super-tiles per thread
+constexpr uint32_t kPlanMax = kPlanThreads * kPlanPer;
+__global__ __launch_bounds__(kPlanThreads) void k_bin_plan(const uint2 *sranges, uint32_t n_super,
+                                                          uint64_t max_chunks, uint32_t *nch, uint32_t *choff,
+                                                          uint32_t *desc) {
+    __shared__ uint32_t s_off[kPlanMax];
+    __shared__ uint32_t wave_tot[kPlanThreads / kWave];
+    uint32_t v[kPlanPer], sum = 0;
+#pragma unroll
+    for (int q = 0; q < kPlanPer; ++q) {
+        const uint32_t sidx = threadIdx.x * kPlanPer + q;
+        v[q] = 0;
+        if (sidx < n_super) {
+            const uint2 r = sranges[sidx];
+            v[q] = (r.y - r.x + kChunk - 1) / kChunk;
+            nch[sidx] = v[q];
+        }
+        sum += v[q];
+    }
+    const int lane = __lane_id(), wv = threadIdx.x / kWave;
+    uint32_t x = sum;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off, kWave);
+        if (lane >= off) x += y;
+    }
+    if (lane == kWave - 1) wave_tot[wv] = x;
+    __syncthreads();
+    uint32_t run = x - sum;
+    for (int k = 0; k < wv; ++k) run += wave_tot[k];
+    // n_super < kPlanMax: the slot n_super (the total) lies in some thread's
+    // range, and every v past n_super is zero
+#pragma unroll
+    for (int q = 0; q < kPlanPer; ++q) {
+        const uint32_t sidx = threadIdx.x * kPlanPer + q;
+        if (sidx <= n_super) {
+            s_off[sidx] = run;
+            choff[sidx] = run;
+        }
+        run += v[q];
+    }
+    __syncthreads();
+    const uint32_t total = s_off[n_super];
+    const uint64_t kend = max_chunks < total ? max_chunks : total;
+    for (uint64_t k = threadIdx.x; k < kend; k += kPlanThreads) {
+        uint32_t lo = 0, hi = n_super;  // s_off[lo] <= k < s_off[hi]
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (s_off[mid] <= k) lo = mid; else hi = mid;
+        }
+        desc[k] = lo;
+    }
+}
+
 // [start, end) of every tile, from the scanned counts.
 __global__ __launch_bounds__(256) void k_bin_ranges(SuperTable T, uint32_t n_super, const uint32_t *choff,
                                                     const uint32_t *nch, const uint32_t *scanned, uint64_t inst_cap,
@@ -282,12 +341,20 @@ hipError_t launch_binning(const SuperTable &T, uint32_t n_super_total, const uin
     const uint64_t cells = (uint64_t)kTilesPer * K;
     const BinLayout B(scratch, super_cap, n_super_total);
     const unsigned sb = (unsigned)blocks_for(n_super_total, 256);
-    hipLaunchKernelGGL(k_bin_chunks, dim3(sb), dim3(256), 0, st, sranges, n_super_total, B.nch);
-    hipError_t e = scan_exclusive(B.nch, B.choff, n_super_total, B.choff + n_super_total, B.scan_chunks, st, nullptr,
-                                  false, fault);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_bin_desc, dim3((unsigned)blocks_for((int64_t)K, 256)), dim3(256), 0, st, B.choff,
-                       n_super_total, K, B.desc);
+    hipError_t e;
+    // the one-workgroup plan goes with the cover keys, so that the knob that
+    // turns those off (for tests) exercises the three-kernel path as well
+    if (skeys && n_super_total < kPlanMax) {
+        hipLaunchKernelGGL(k_bin_plan, dim3(1), dim3(kPlanThreads), 0, st, sranges, n_super_total, K, B.nch, B.choff,
+                           B.desc);
+    } else {
+        hipLaunchKernelGGL(k_bin_chunks, dim3(sb), dim3(256), 0, st, sranges, n_super_total, B.nch);
+        e = scan_exclusive(B.nch, B.choff, n_super_total, B.choff + n_super_total, B.scan_chunks, st, nullptr, false,
+                           fault);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_bin_desc, dim3((unsigned)blocks_for((int64_t)K, 256)), dim3(256), 0, st, B.choff,
+                           n_super_total, K, B.desc);
+    }
     hipLaunchKernelGGL(k_bin_count, dim3((unsigned)K), dim3(kThreads), 0, st, T, rect, skeys, sinst_gauss, sranges,
                        B.choff, B.nch, B.desc, n_super_total, B.counts);
     e = scan_exclusive(B.counts, B.scanned, (int64_t)cells, B.scanned + cells, B.scan_counts, st, nullptr, cleared,

@@ -2,8 +2,10 @@
 covers carried in the upper bits of the block-entry sort keys (the default)
 and the covers recomputed from the Gaussians' tile rectangles (taken when a
 call has more 8x8-tile blocks than the keys' id bits hold, forced here with
-omnigs_set_cover_key_blocks).  Tile lists, ranges and images must be equal
-bit for bit; the default path's lists are checked against the oracle's in
+omnigs_set_cover_key_blocks).  The same switch moves the split of the block
+lists into chunks from one workgroup to three kernels (chunk counts, their
+scan, chunk owners).  Tile lists, ranges and images must be equal bit for
+bit; the default path's lists are checked against the oracle's in
 test_gpu_parity.py and test_gpu_fullsize.py."""
 import numpy as np
 import pytest
