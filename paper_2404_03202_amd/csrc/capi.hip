@@ -273,7 +273,9 @@ struct GeomScratch {
 // and S at gst.totals[0].
 // cleared: the sort's and the scan's lookback words are already zero
 // (geom_clear).
-omnigs_status sort_and_count(int64_t n, GeomState &gst, GeomScratch &gs, hipStream_t st, bool cleared = false) {
+// part: when given, the scan also writes the emission's partition.
+omnigs_status sort_and_count(int64_t n, GeomState &gst, GeomScratch &gs, hipStream_t st, bool cleared = false,
+                             ScanPartition part = {}) {
     {
         StageTimer t(st, kStDepthSort);
         HIP_TRY(radix_sort_pairs(gs.depth_key, nullptr, gs.keys_tmp, gs.vals_tmp, gs.keys_sorted, gst.order, n, 32,
@@ -282,7 +284,7 @@ omnigs_status sort_and_count(int64_t n, GeomState &gst, GeomScratch &gs, hipStre
     {
         StageTimer t(st, kStEmitCount);
         HIP_TRY(scan_exclusive(gs.n_super, gs.offs, n, gst.totals, gs.scan_tmp, st, gst.order, cleared,
-                               gst.totals + 2));
+                               gst.totals + 2, part));
     }
     return OMNIGS_OK;
 }
@@ -342,7 +344,7 @@ struct BinScratch {
 omnigs_status run_binning(int64_t nrec, const GeomState &gst, const GeomScratch &gs, const Grids &G,
                           uint64_t super_cap, uint64_t inst_cap, bool counted, BinScratch &bs, uint2 *ranges,
                           uint32_t *inst_gauss, int32_t *overflow, hipStream_t st, bool cleared = false,
-                          uint32_t *order = nullptr, uint32_t order_tiles = 0) {
+                          uint32_t *order = nullptr, uint32_t order_tiles = 0, bool partitioned = false) {
     const int bits = bits_for(G.n_super);
     const bool odd = ((bits + 7) / 8) % 2;
     uint32_t *et = odd ? bs.stile_tmp : bs.stile, *eg = odd ? bs.sgauss_tmp : bs.sgauss;
@@ -351,7 +353,7 @@ omnigs_status run_binning(int64_t nrec, const GeomState &gst, const GeomScratch 
         // emit where the sort's ping-pong starts, so that the last pass lands
         // in stile / sgauss
         HIP_TRY(launch_emit(gst.order, gst.rect, gs.offs, nrec, bs.part, gst.totals, G.ef, super_cap, et, eg, overflow,
-                            st));
+                            st, partitioned));
     }
     {
         StageTimer t(st, kStSuperSort);
@@ -619,7 +621,11 @@ omnigs_status omnigs_forward(const omnigs_gaussians *g, const omnigs_camera *cam
         HIP_TRY(launch_project(pa, gst.rec, gs.depth_key, gst.depth, gst.n_tiles, gst.rect, gs.n_super, gst.radii,
                                gst.totals + 1, st, true));
     }
-    if ((rc = sort_and_count(n, gst, gs, st, true)) != OMNIGS_OK) return rc;
+    // with capacities the binning scratch exists already: the scan of the
+    // block-entry counts also partitions the emission
+    ScanPartition part;
+    if (counted) part = ScanPartition{bs.part, emit_blocks(super_cap)};
+    if ((rc = sort_and_count(n, gst, gs, st, true, part)) != OMNIGS_OK) return rc;
 
     int64_t S = -1, M = -1;
     if (!counted) {
@@ -648,7 +654,7 @@ omnigs_status omnigs_forward(const omnigs_gaussians *g, const omnigs_camera *cam
     // kernel when the forward uses one
     if (!forward_uses_order(inst_cap, ntiles)) order = nullptr;
     if ((rc = run_binning(n, gst, gs, G, super_cap, inst_cap, counted, bs, ranges, inst_gauss,
-                          counted ? cap->overflow : nullptr, st, true, order, ntiles)) != OMNIGS_OK)
+                          counted ? cap->overflow : nullptr, st, true, order, ntiles, counted)) != OMNIGS_OK)
         return rc;
     {
         StageTimer t(st, kStBlendFwd);

@@ -213,8 +213,17 @@ hipError_t radix_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in, ui
 // first scan_clear_words(n) words are already zero.
 size_t scan_scratch_bytes(int64_t n);
 int64_t scan_clear_words(int64_t n);
+// The emission's partition, written by the scan of the block-entry counts
+// when `part` is given: part[b] = the rank whose output range holds output
+// b * (outputs per emit block), for every b < blocks whose output lies below
+// the total (as launch_emit's own partition kernel writes it).
+struct ScanPartition {
+    uint32_t *part = nullptr;
+    uint64_t blocks = 0;
+};
 hipError_t scan_exclusive(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *total, void *scratch,
-                          hipStream_t st, const uint32_t *gather, bool cleared = false, uint32_t *fault = nullptr);
+                          hipStream_t st, const uint32_t *gather, bool cleared = false, uint32_t *fault = nullptr,
+                          ScanPartition P = {});
 
 // Lookback self-test: the poll bound of every later lookback wait (the
 // default is restored by passing 0).  Only the self-test entry point lowers
@@ -256,7 +265,7 @@ hipError_t launch_clear(const ClearList &L, hipStream_t st);
 uint64_t emit_blocks(uint64_t capacity);
 hipError_t launch_emit(const uint32_t *order, const uint2 *rect, const uint32_t *offs, int64_t n, uint32_t *part,
                        const uint32_t *m_dev, const EmitFrames &frames, uint64_t capacity, uint32_t *inst_tile,
-                       uint32_t *inst_gauss, int32_t *overflow, hipStream_t st);
+                       uint32_t *inst_gauss, int32_t *overflow, hipStream_t st, bool partitioned = false);
 // key_mask: the id bits of the sorted keys.
 hipError_t launch_tile_ranges(const uint32_t *inst_tile, const uint32_t *m_dev, uint64_t capacity,
                               uint2 *ranges, uint32_t n_tiles_total, uint32_t key_mask, hipStream_t st);

@@ -352,6 +352,14 @@ __device__ inline uint32_t scan_input(const uint32_t *in, const uint32_t *gather
     return g < (uint64_t)n ? in[g] : 0u;
 }
 
+// Item idx of a scan with exclusive value o and count c: the emit blocks
+// whose first output lies in [o, o + c) start in rank idx.
+__device__ inline void mark_partition(const ScanPartition &P, int64_t idx, uint32_t o, uint32_t c) {
+    if (c == 0) return;
+    const uint64_t b1 = ((uint64_t)o + c - 1) / kEmitSpan;
+    for (uint64_t b = ((uint64_t)o + kEmitSpan - 1) / kEmitSpan; b <= b1 && b < P.blocks; ++b) P.part[b] = (uint32_t)idx;
+}
+
 // Single-pass exclusive scan of kScanTile-element tiles: the workgroup at
 // ticket position b loads its tile (all loads issued before use), publishes
 // the tile sum, and its first wave takes the sum of all earlier tiles by
@@ -363,7 +371,7 @@ constexpr uint64_t kInc64 = 1ull << 63;
 __global__ __launch_bounds__(kScanThreads) void k_scan_lookback(const uint32_t *in, const uint32_t *gather, uint32_t *out,
                                                              int64_t n, uint64_t *status, uint32_t *ticket,
                                                              uint32_t *grand_total, uint32_t *fault,
-                                                             uint32_t max_polls) {
+                                                             uint32_t max_polls, ScanPartition P) {
     constexpr int kSI = kScanTile / kScanThreads;  // items per thread
     __shared__ uint32_t wave_tot[kScanThreads / kWave];
     __shared__ uint32_t total;
@@ -435,6 +443,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_lookback(const uint32_t *
 #pragma unroll
     for (int it = 0; it < kSI; ++it) {
         s_data[threadIdx.x * kSI + it] = run;
+        if (P.part) mark_partition(P, block0 + threadIdx.x * kSI + it, run, v[it]);
         run += v[it];
     }
     if (grand_total && block0 + kScanTile >= n && threadIdx.x == kScanThreads - 1) *grand_total = run;
@@ -449,7 +458,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_lookback(const uint32_t *
 // Exclusive scan of at most kScanTile elements in one workgroup (blocked
 // arrangement: thread t owns items [t*kScanItems, (t+1)*kScanItems)).
 __global__ __launch_bounds__(kThreads) void k_scan_tile(const uint32_t *in, const uint32_t *gather, uint32_t *out,
-                                                         int64_t n, uint32_t *grand_total) {
+                                                         int64_t n, uint32_t *grand_total, ScanPartition P) {
     __shared__ uint32_t wave_tot[kWaves];
     __shared__ uint32_t total;
     __shared__ uint32_t s_data[kScanTile];
@@ -472,6 +481,7 @@ __global__ __launch_bounds__(kThreads) void k_scan_tile(const uint32_t *in, cons
 #pragma unroll
     for (int it = 0; it < kScanItems; ++it) {
         s_data[threadIdx.x * kScanItems + it] = run;
+        if (P.part) mark_partition(P, threadIdx.x * kScanItems + it, run, v[it]);
         run += v[it];
     }
     if (grand_total && threadIdx.x == kThreads - 1) *grand_total = run;
@@ -668,11 +678,11 @@ int64_t scan_clear_words(int64_t n) {
 }
 
 hipError_t scan_exclusive(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *total, void *scratch,
-                          hipStream_t st, const uint32_t *gather, bool cleared, uint32_t *fault) {
+                          hipStream_t st, const uint32_t *gather, bool cleared, uint32_t *fault, ScanPartition P) {
     if (n <= 0) return total ? launch_fill_u32(total, 0u, 1, st) : hipSuccess;
     const int64_t nb = blocks_for(n, kScanTile);
     if (nb == 1) {
-        hipLaunchKernelGGL(k_scan_tile, dim3(1), dim3(kThreads), 0, st, in, gather, out, n, total);
+        hipLaunchKernelGGL(k_scan_tile, dim3(1), dim3(kThreads), 0, st, in, gather, out, n, total, P);
         return hipGetLastError();
     }
     uint64_t *status = static_cast<uint64_t *>(scratch);
@@ -683,7 +693,7 @@ hipError_t scan_exclusive(const uint32_t *in, uint32_t *out, int64_t n, uint32_t
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_scan_lookback, dim3((unsigned)nb), dim3(kScanThreads), 0, st, in, gather, out, n, status, ticket,
-                       total, fault, g_max_polls);
+                       total, fault, g_max_polls, P);
     return hipGetLastError();
 }
 
@@ -784,11 +794,12 @@ uint64_t emit_blocks(uint64_t capacity) { return (capacity + kEmitSpan - 1) / kE
 
 hipError_t launch_emit(const uint32_t *order, const uint2 *rect, const uint32_t *offs, int64_t n, uint32_t *part,
                        const uint32_t *m_dev, const EmitFrames &frames, uint64_t capacity, uint32_t *inst_tile,
-                       uint32_t *inst_gauss, int32_t *overflow, hipStream_t st) {
+                       uint32_t *inst_gauss, int32_t *overflow, hipStream_t st, bool partitioned) {
     if (n <= 0 || capacity == 0) return hipSuccess;
     const uint64_t nb = emit_blocks(capacity);
-    hipLaunchKernelGGL(k_emit_partition, dim3((unsigned)blocks_for(n, kThreads)), dim3(kThreads), 0, st, offs, m_dev,
-                       n, nb, part);
+    if (!partitioned)
+        hipLaunchKernelGGL(k_emit_partition, dim3((unsigned)blocks_for(n, kThreads)), dim3(kThreads), 0, st, offs,
+                           m_dev, n, nb, part);
     hipLaunchKernelGGL(k_emit, dim3((unsigned)nb), dim3(kThreads), 0, st, order, rect, offs, n,
                        (const uint32_t *)part, m_dev, frames, capacity, inst_tile, inst_gauss, overflow);
     return hipGetLastError();
