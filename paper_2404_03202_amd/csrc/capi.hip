@@ -45,7 +45,9 @@ enum Stage {
     kStSuperEmit,
     kStSuperSort,
     kStTileBin,
-    kStTileOrder,
+    kStTileOrder,  // records nothing: the forward's tile order is written inside the
+                   // tile binning, the backward's with the accumulator clear (the
+                   // stage keeps its index so that callers' stage masks stay valid)
     kStBlendFwd,
     kStL1,
     kStBwdClear,
