@@ -252,8 +252,8 @@ def hbm_stages(ms, n, S, M, W, H, ceilings=None):
 
 
 def blend_rates(walked, blended, ms_fwd, ms_bwd, ceilings=None):
-    """The two blends against the FP32 vector peak: work in the survey unit
-    (ops per walked pair) and in the refined FLOP count."""
+    """The two blends against the FP32 vector peak: work counted as a fixed
+    number of ops per walked pair, and as the refined FLOP count."""
     out = {}
     for name, ms, ops, flops in (("blend_fwd", ms_fwd, OPS_FWD_PAIR * walked, FLOP_ALPHA * walked),
                                  ("blend_bwd", ms_bwd, OPS_BWD_PAIR * walked, FLOP_ALPHA * walked + FLOP_GRAD * blended)):
