@@ -154,6 +154,13 @@ typedef struct {
                                     or scan gave up; the lists are then invalid)
                                     (device words; n_entries and n_instances are
                                     -1 when the call read nothing back)             */
+    const uint8_t *inst_quad;    /* [M] per instance, the 8x8 quadrants of its tile
+                                    that its alpha >= alpha_min region can reach
+                                    (bits 0-3, quadrant 2*row + column), written
+                                    by the forward's blend for each instance it
+                                    walked; the backward reads them instead of
+                                    testing again.  NULL (a state built by hand):
+                                    the backward tests                             */
 } omnigs_state;
 
 /* Capacities of a forward call that reads nothing back (host struct).  With

@@ -74,6 +74,10 @@ struct BlendFrame {
     float *depth;        // forward only: the depth image (with kAux)
     const float *dLD;    // backward only: dL/ddepth, may be null
     const float *dLA;    // backward only: dL/dalpha, may be null
+    // per tile instance (indexed as the instance lists), the reach mask of its
+    // quadrants: written by the forward for every instance it stages, read by
+    // the backward in place of the quadrant tests (null: computed)
+    uint8_t *quad;
 };
 
 struct FrameTable {
@@ -148,9 +152,11 @@ __device__ inline float rect_min_quadratic(float l00, float l10, float l11, floa
 
 // Stage the record of Gaussian gid in slot `slot` (rdepth: per-record depth
 // values, read when kAux).
+// qin >= 0: the quadrant mask as an earlier staging of the same instance
+// found it (the tests are skipped).  Returns the mask.
 template <bool kAux, int kW>
-__device__ inline void stage(const BlendRecord *rec, const float *rdepth, uint32_t gid, float X0, float Y0, float W,
-                             Stage<kW, kAux> &S, int slot) {
+__device__ inline uint32_t stage(const BlendRecord *rec, const float *rdepth, uint32_t gid, float X0, float Y0,
+                                 float W, Stage<kW, kAux> &S, int slot, int qin = -1) {
     const float4 *p = reinterpret_cast<const float4 *>(rec + gid);
     const float4 ra4 = p[0], rb4 = p[1], rc4 = p[2];
     float x = (ra4.x - X0) + ra4.y;  // px_hi - X0 is exact near the tile
@@ -174,10 +180,12 @@ __device__ inline void stage(const BlendRecord *rec, const float *rdepth, uint32
     // minima only need to be near-exact: a slightly wrong clamp point still
     // bounds the minimum over an edge from above, and the margin absorbs the
     // rounding
+    uint32_t quad = (uint32_t)qin;
+    if (qin < 0) {
     const float reach = rc4.w + 1e-3f * (1.0f + fabsf(rc4.w));
     const float qa = l00 * l00, qb = l00 * l10, qc = __builtin_fmaf(l10, l10, l11 * l11);
     const float ra = __builtin_amdgcn_rcpf(qa), rc = __builtin_amdgcn_rcpf(qc);
-    uint32_t quad = 0;
+    quad = 0;
 #pragma unroll
     for (int k = 0; k < kQuads; ++k) {
         const float qx = (float)((k & 1) * 8), qy = (float)((k >> 1) * 8);
@@ -186,6 +194,7 @@ __device__ inline void stage(const BlendRecord *rec, const float *rdepth, uint32
         // offsets that the seam wrap may shift: keep the quadrant
         const bool wraps = u0 < -half || u1 >= half;
         if (wraps || rect_min_quadratic(l00, l10, l11, qb, ra, rc, u0, u1, v0, v1) <= reach) quad |= 1u << k;
+    }
     }
     // columns whose offset i + 1/2 - x leaves [-W/2, W/2) take the centre a
     // turn away: the right ones (offset >= W/2) or the left ones (< -W/2)
@@ -208,6 +217,7 @@ __device__ inline void stage(const BlendRecord *rec, const float *rdepth, uint32
     const uint32_t qm = quad | (thr < 1e29f ? kSplitBit : 0u);
     S.c[slot] = make_float4(rc4.z, u0b, thr, kAux ? rdepth[gid] : __uint_as_float(qm));
     if constexpr (kAux) S.quad[slot] = qm;
+    return quad;
 }
 
 // Wave w lists, in order, the staged slots in [lo, nb) that reach one of its
@@ -313,8 +323,11 @@ __global__ __launch_bounds__(kWave * kW, (forward_min_waves<kW, kDepth, kCount>(
     for (int base = 0; base < count; base += kBatch) {
         if (__syncthreads_count(all_stopped(T)) == kNT) break;
         const int nb = min(kBatch, count - base);
-        if ((int)threadIdx.x < nb)
-            stage<kDepth>(rec, rdepth, inst_gauss[range.x + base + threadIdx.x], X0, Y0, W, S, threadIdx.x);
+        if ((int)threadIdx.x < nb) {
+            const uint32_t at = range.x + base + threadIdx.x;
+            const uint32_t q = stage<kDepth>(rec, rdepth, inst_gauss[at], X0, Y0, W, S, threadIdx.x);
+            if (F.quad) F.quad[at] = (uint8_t)q;
+        }
         __syncthreads();
         if (__ballot(!all_stopped(T)) == 0ull) continue;  // this wave is finished: keep staging with the others
         bool split;
@@ -552,9 +565,11 @@ __global__ __launch_bounds__(kWave * kW) void k_blend_backward(FrameTable FT, co
         __syncthreads();
         uint32_t my_gid = 0;  // the Gaussian this thread stages (slot threadIdx.x)
         if ((int)threadIdx.x < nb) {
-            // slot i holds list position hi-1-i
-            my_gid = inst_gauss[range.x + hi - 1 - threadIdx.x];
-            stage<kAux>(rec, rdepth, my_gid, X0, Y0, W, S, threadIdx.x);
+            // slot i holds list position hi-1-i (staged by the forward, which
+            // left the quadrant mask of every position it staged)
+            const uint32_t at = range.x + hi - 1 - threadIdx.x;
+            my_gid = inst_gauss[at];
+            stage<kAux>(rec, rdepth, my_gid, X0, Y0, W, S, threadIdx.x, F.quad ? (int)F.quad[at] : -1);
 #pragma unroll
             for (int f = 0; f < kNF; ++f) part[threadIdx.x][f] = 0.0f;
         }
@@ -758,11 +773,12 @@ bool forward_uses_order(uint64_t instances, uint32_t tiles) { return instances <
 hipError_t launch_blend_forward(const FrameGeom &f, const BlendRecord *rec, const float *rdepth,
                                 const uint32_t *inst_gauss, const uint2 *ranges, const BlendSettings &s, float *image,
                                 float *final_T, int32_t *n_contrib, int32_t *n_blended, float *depth_out,
-                                const uint32_t *order, uint32_t *tile_work, uint64_t instances, hipStream_t st) {
+                                const uint32_t *order, uint32_t *tile_work, uint64_t instances, hipStream_t st,
+                                uint8_t *inst_quad) {
     FrameTable T{};
     T.n = 1;
     T.f[0] = BlendFrame{f.width, f.height, f.tiles_x, f.tiles_y, 0u, period_of(f), image, final_T, n_contrib,
-                        n_blended, nullptr, depth_out, nullptr, nullptr};
+                        n_blended, nullptr, depth_out, nullptr, nullptr, inst_quad};
     const unsigned tiles = (unsigned)(f.tiles_x * f.tiles_y);
     if (tiles == 0) return hipSuccess;
     if (instances > kLongLists * tiles)
@@ -816,12 +832,12 @@ hipError_t launch_blend_backward(const FrameGeom &f, const BlendRecord *rec, con
                                  const uint32_t *inst_gauss, const uint2 *ranges, const BlendSettings &s,
                                  const float *final_T, const int32_t *n_contrib, const float *dL_dimage,
                                  const float *dL_ddepth, const float *dL_dalpha, float *acc, const uint32_t *order,
-                                 hipStream_t st) {
+                                 hipStream_t st, const uint8_t *inst_quad) {
     FrameTable T{};
     T.n = 1;
     T.f[0] = BlendFrame{f.width, f.height, f.tiles_x, f.tiles_y, 0u, period_of(f), nullptr,
                         const_cast<float *>(final_T), const_cast<int32_t *>(n_contrib), nullptr, dL_dimage, nullptr,
-                        dL_ddepth, dL_dalpha};
+                        dL_ddepth, dL_dalpha, const_cast<uint8_t *>(inst_quad)};
     const unsigned tiles = (unsigned)(f.tiles_x * f.tiles_y);
     if (tiles == 0) return hipSuccess;
     constexpr int kW = OMNIGS_BWD_WAVES;

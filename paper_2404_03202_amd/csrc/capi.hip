@@ -467,7 +467,7 @@ omnigs_status backward_impl(const omnigs_gaussians *g, const omnigs_camera *cam,
     {
         StageTimer t(st, kStBlendBwd);
         HIP_TRY(launch_blend_backward(f, rec, state->depth, state->inst_gauss, ranges, make_blend_settings(s),
-                                      fwd->final_T, fwd->n_contrib, dL_dimage, dL_ddepth, dL_dalpha, acc, order, st));
+                                      fwd->final_T, fwd->n_contrib, dL_dimage, dL_ddepth, dL_dalpha, acc, order, st, state->inst_quad));
     }
     {
         StageTimer t(st, kStProjectBwd);
@@ -576,10 +576,12 @@ omnigs_status omnigs_forward(const omnigs_gaussians *g, const omnigs_camera *cam
     GeomScratch gs;
     uint64_t super_cap = 0, inst_cap = 0;
     uint32_t *inst_gauss = nullptr, *tile_work = nullptr, *order = nullptr;
+    uint8_t *inst_quad = nullptr;
     uint2 *ranges = nullptr;
     BinScratch bs;
     auto carve_inst_state = [&](Arena &a) {
         inst_gauss = a.take<uint32_t>((size_t)(inst_cap > 0 ? inst_cap : 1));
+        inst_quad = a.take<uint8_t>((size_t)(inst_cap > 0 ? inst_cap : 1));
         ranges = a.take<uint2>(ntiles);
         tile_work = a.take<uint32_t>(ntiles);
     };
@@ -663,7 +665,7 @@ omnigs_status omnigs_forward(const omnigs_gaussians *g, const omnigs_camera *cam
         FrameGeom f{cam->width, pa.rows, pa.tiles_x, pa.tiles_y, 0u, pa.model == OMNIGS_CAMERA_ERP};
         HIP_TRY(launch_blend_forward(f, gst.rec, gst.depth, inst_gauss, ranges, make_blend_settings(s), out->image,
                                      out->final_T, out->n_contrib, out->n_blended, out->depth, order, tile_work,
-                                     inst_cap, st));
+                                     inst_cap, st, inst_quad));
     }
     state->n = n;
     state->n_instances = M;
@@ -676,6 +678,7 @@ omnigs_status omnigs_forward(const omnigs_gaussians *g, const omnigs_camera *cam
     state->n_tiles = gst.n_tiles;
     state->depth_order = gst.order;
     state->inst_gauss = inst_gauss;
+    state->inst_quad = inst_quad;
     state->tile_range = reinterpret_cast<const uint32_t *>(ranges);
     state->tile_work = tile_work;
     state->radii = gst.radii;

@@ -314,20 +314,24 @@ bool forward_uses_order(uint64_t instances, uint32_t tiles);
 hipError_t launch_blend_forward(const FrameGeom &f, const BlendRecord *rec, const float *rdepth,
                                 const uint32_t *inst_gauss, const uint2 *ranges, const BlendSettings &s, float *image,
                                 float *final_T, int32_t *n_contrib, int32_t *n_blended, float *depth_out,
-                                const uint32_t *order, uint32_t *tile_work, uint64_t instances, hipStream_t st);
+                                const uint32_t *order, uint32_t *tile_work, uint64_t instances, hipStream_t st,
+                                uint8_t *inst_quad = nullptr);
 // Forward blend of several images in one launch over their concatenated
 // tile space (frames[k].tile_base ascending, total_tiles in all).
 hipError_t launch_blend_forward_frames(const FrameGeom *frames, const omnigs_image_out *outs, int count,
                                        const BlendRecord *rec, const float *rdepth, const uint32_t *inst_gauss,
                                        const uint2 *ranges, const BlendSettings &s, const uint32_t *order,
                                        uint32_t total_tiles, hipStream_t st);
+// inst_quad (may be null): one byte per tile instance, the reach mask of
+// its tile's four 8x8 quadrants, written by the forward for every instance
+// it stages and read by the backward (which stages only such instances).
 // With dL_ddepth or dL_dalpha (either may be null) the accumulators have
 // kAccAux fields per Gaussian, else kAcc; rdepth is read only then.
 hipError_t launch_blend_backward(const FrameGeom &f, const BlendRecord *rec, const float *rdepth,
                                  const uint32_t *inst_gauss, const uint2 *ranges, const BlendSettings &s,
                                  const float *final_T, const int32_t *n_contrib, const float *dL_dimage,
                                  const float *dL_ddepth, const float *dL_dalpha, float *acc, const uint32_t *order,
-                                 hipStream_t st);
+                                 hipStream_t st, const uint8_t *inst_quad = nullptr);
 // Longest-first tile order from the list lengths (work == null) or from a
 // per-tile work array.  One workgroup; ntiles unbounded.
 hipError_t launch_tile_order(const uint2 *ranges, const uint32_t *work, uint32_t ntiles, uint32_t *order,

@@ -72,7 +72,8 @@ class c_state(ctypes.Structure):
                 ("height", ctypes.c_int32), ("tiles_x", ctypes.c_int32), ("tiles_y", ctypes.c_int32),
                 ("records", ctypes.c_void_p), ("n_tiles", ctypes.c_void_p), ("depth_order", ctypes.c_void_p),
                 ("inst_gauss", ctypes.c_void_p), ("tile_range", ctypes.c_void_p), ("tile_work", ctypes.c_void_p),
-                ("radii", ctypes.c_void_p), ("depth", ctypes.c_void_p), ("counts", ctypes.c_void_p)]
+                ("radii", ctypes.c_void_p), ("depth", ctypes.c_void_p), ("counts", ctypes.c_void_p),
+                ("inst_quad", ctypes.c_void_p)]
 
 
 class c_capacity(ctypes.Structure):
